@@ -1,0 +1,373 @@
+"""Seeded tensor-network constructions (inputs only; no expansion arithmetic).
+
+Conventions shared by every consumer:
+
+* A network is a list of site tensors plus a bond list.  Site ``s`` holds an
+  FP64 array in C order over its *leg slots*.
+* On lattices, sites are numbered row-major with x fastest
+  (``s = x + Lx*y`` in 2D, ``s = x + L*(y + L*z)`` in 3D).  A site's bond legs
+  come in the canonical order (-x, +x, -y, +y, -z, +z), keeping only the
+  directions that exist under open boundaries; open (physical) legs follow.
+* ``bonds[b] = (u, leg_u, v, leg_v)`` joins leg slot ``leg_u`` of site ``u``
+  to leg slot ``leg_v`` of site ``v``.  Lattice bonds are listed site by site
+  in the order +x, +y, +z.
+* ``open_legs[k] = (site, leg)`` lists legs that stay uncontracted.
+
+The physical constructions follow the paper's Appendix A: the Ising partition
+function in the usual symmetric-square-root encoding, the AKLT PEPS norm
+(physical dimension 5, virtual dimension 2, merged bond dimension 4) and
+random tensors with i.i.d. entries.
+"""
+
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+from functools import reduce
+
+import numpy as np
+
+
+@dataclass
+class Network:
+    tensors: list
+    bonds: np.ndarray  # (M, 4) int32: u, leg_u, v, leg_v
+    open_legs: np.ndarray = field(default_factory=lambda: np.zeros((0, 2), np.int32))
+    name: str = ""
+    info: dict = field(default_factory=dict)
+
+    @property
+    def n_sites(self) -> int:
+        return len(self.tensors)
+
+    @property
+    def n_bonds(self) -> int:
+        return int(self.bonds.shape[0])
+
+    @property
+    def n_open(self) -> int:
+        return int(self.open_legs.shape[0])
+
+    def bond_dim(self, b: int) -> int:
+        u, lu, _, _ = self.bonds[b]
+        return int(self.tensors[u].shape[lu])
+
+    def nbytes(self) -> int:
+        return int(sum(t.nbytes for t in self.tensors))
+
+
+# ----------------------------------------------------------------------------
+# lattice geometry
+
+
+_DIRS = ("-x", "+x", "-y", "+y", "-z", "+z")
+
+
+def _lattice(shape):
+    """Return (site_dirs, bonds) for an open-boundary hypercubic lattice.
+
+    ``site_dirs[s]`` maps a direction name to the site's leg slot.
+    """
+    nd = len(shape)
+    dims = list(shape)
+    n = int(np.prod(dims))
+    strides = [int(np.prod(dims[:k])) for k in range(nd)]
+    coords = []
+    for s in range(n):
+        c = []
+        r = s
+        for k in range(nd):
+            c.append(r % dims[k])
+            r //= dims[k]
+        coords.append(c)
+    site_dirs = []
+    for s in range(n):
+        c = coords[s]
+        slots = {}
+        for k in range(nd):
+            if c[k] > 0:
+                slots[_DIRS[2 * k]] = len(slots)
+            if c[k] < dims[k] - 1:
+                slots[_DIRS[2 * k + 1]] = len(slots)
+        site_dirs.append(slots)
+    bonds = []
+    for s in range(n):
+        c = coords[s]
+        for k in range(nd):
+            if c[k] < dims[k] - 1:
+                t = s + strides[k]
+                bonds.append((s, site_dirs[s][_DIRS[2 * k + 1]], t, site_dirs[t][_DIRS[2 * k]]))
+    return site_dirs, np.asarray(bonds, dtype=np.int32).reshape(-1, 4)
+
+
+def lattice_2d(Lx: int, Ly: int):
+    return _lattice((Lx, Ly))
+
+
+def lattice_3d(L: int):
+    return _lattice((L, L, L))
+
+
+def _site_index(shape, coord):
+    s = 0
+    mul = 1
+    for k, c in enumerate(coord):
+        s += c * mul
+        mul *= shape[k]
+    return s
+
+
+def _build(shape, make_tensor, open_sites=None, name=""):
+    """Assemble a lattice network; ``make_tensor(s, bond_rank, open_dims)``."""
+    site_dirs, bonds = _lattice(shape)
+    open_sites = dict(open_sites or {})
+    tensors = []
+    open_legs = []
+    for s, slots in enumerate(site_dirs):
+        odims = open_sites.get(s, ())
+        if isinstance(odims, int):
+            odims = (odims,)
+        t = make_tensor(s, len(slots), tuple(odims))
+        for k in range(len(odims)):
+            open_legs.append((s, len(slots) + k))
+        tensors.append(np.ascontiguousarray(t, dtype=np.float64))
+    ol = np.asarray(open_legs, dtype=np.int32).reshape(-1, 2)
+    return Network(tensors, bonds, ol, name=name, info={"shape": tuple(shape)})
+
+
+# ----------------------------------------------------------------------------
+# Ising (Appendix A.1)
+
+
+def _ising_w(beta: float, J: float = 1.0) -> np.ndarray:
+    """Symmetric square root W of the bond Boltzmann matrix B = W W.
+
+    B[s, s'] = exp(beta*J*s*s') for spins s, s' in {+1, -1}; its eigenvalues
+    are 2 cosh(beta J) and 2 sinh(beta J) with eigenvectors (1, 1)/sqrt2 and
+    (1, -1)/sqrt2.
+    """
+    l0 = 2.0 * math.cosh(beta * J)
+    l1 = 2.0 * math.sinh(beta * J)
+    if l1 < 0:
+        raise ValueError("antiferromagnetic coupling needs a complex square root")
+    a, b = math.sqrt(l0), math.sqrt(l1)
+    return 0.5 * np.array([[a + b, a - b], [a - b, a + b]], dtype=np.float64)
+
+
+def _ising_site(W: np.ndarray, rank: int) -> np.ndarray:
+    """T[a_1..a_r] = sum_s prod_l W[s, a_l] (spin s summed at the site)."""
+    if rank == 0:
+        return np.array(2.0)
+    out = np.zeros((2,) * rank)
+    for s in range(2):
+        out += reduce(np.multiply.outer, [W[s]] * rank)
+    return out
+
+
+def ising_2d(Lx: int, Ly: int, beta: float, J: float = 1.0) -> Network:
+    W = _ising_w(beta, J)
+    net = _build((Lx, Ly), lambda s, r, o: _ising_site(W, r), name=f"ising2d_{Lx}x{Ly}_b{beta}")
+    net.info.update(model="ising", beta=beta, J=J)
+    return net
+
+
+def ising_3d(L: int, beta: float, J: float = 1.0) -> Network:
+    W = _ising_w(beta, J)
+    net = _build((L, L, L), lambda s, r, o: _ising_site(W, r), name=f"ising3d_{L}_b{beta}")
+    net.info.update(model="ising", beta=beta, J=J)
+    return net
+
+
+# ----------------------------------------------------------------------------
+# random tensors (Appendix A.3)
+
+
+def _draw(rng, shape, dist):
+    if dist in ("uniform01", "uniform"):
+        return rng.random(shape)
+    if dist == "normal":  # mean 1, sd 0.3
+        return rng.normal(1.0, 0.3, shape)
+    if isinstance(dist, tuple) and dist[0] == "uniform":
+        return rng.uniform(dist[1], dist[2], shape)
+    if isinstance(dist, tuple) and dist[0] == "normal":
+        return rng.normal(dist[1], dist[2], shape)
+    raise ValueError(f"unknown distribution {dist!r}")
+
+
+def random_2d(Lx, Ly, D, dist="uniform01", seed=0, open_sites=None) -> Network:
+    """i.i.d. entries, sites drawn in site order from one PCG64 stream.
+
+    ``open_sites`` maps a site index to its open-leg dimension(s).
+    """
+    rng = np.random.default_rng(seed)
+    net = _build((Lx, Ly), lambda s, r, o: _draw(rng, (D,) * r + o, dist),
+                 open_sites=open_sites, name=f"rand2d_{Lx}x{Ly}_D{D}_s{seed}")
+    net.info.update(model="random", D=D, dist=dist, seed=seed)
+    return net
+
+
+def random_3d(L, D, dist="uniform01", seed=0, open_sites=None) -> Network:
+    rng = np.random.default_rng(seed)
+    net = _build((L, L, L), lambda s, r, o: _draw(rng, (D,) * r + o, dist),
+                 open_sites=open_sites, name=f"rand3d_{L}_D{D}_s{seed}")
+    net.info.update(model="random", D=D, dist=dist, seed=seed)
+    return net
+
+
+# ----------------------------------------------------------------------------
+# AKLT norm network (Appendix A.2)
+
+
+def _aklt_projector() -> np.ndarray:
+    """Spin-2 PEPS tensor A[p; l, r, u, d] with virtual spin-1/2 legs.
+
+    The physical state p (0..4) is the normalised symmetric combination of the
+    four virtual spins with p of them down; a singlet matrix is absorbed on the
+    +x and +y legs so every bond carries exactly one singlet.
+    """
+    A = np.zeros((5, 2, 2, 2, 2))
+    for a in np.ndindex(2, 2, 2, 2):
+        p = sum(a)
+        A[(p,) + a] = 1.0 / math.sqrt(math.comb(4, p))
+    eps = np.array([[0.0, 1.0], [-1.0, 0.0]])
+    # leg order (-x, +x, -y, +y): absorb eps on +x (axis 2) and +y (axis 4)
+    A = np.einsum("pabcd,bB->paBcd", A, eps)
+    A = np.einsum("pabcd,dD->pabcD", A, eps)
+    return A
+
+
+def aklt_2d(Lx: int, Ly: int) -> Network:
+    """<psi|psi> for the square-lattice AKLT PEPS, ket/bra legs merged (D=4).
+
+    Merged index = 2*ket + bra.  Boundary directions that have no neighbour are
+    capped by the SU(2)-invariant vector vec(I2)/sqrt(2).
+    """
+    A = _aklt_projector()
+    E = np.einsum("pabcd,pABCD->aAbBcCdD", A, A).reshape(4, 4, 4, 4)
+    cap = np.array([1.0, 0.0, 0.0, 1.0]) / math.sqrt(2.0)
+    site_dirs, _ = _lattice((Lx, Ly))
+
+    def make(s, r, o):
+        slots = site_dirs[s]
+        T = E
+        # contract missing directions from the last axis down to keep order
+        for k in range(3, -1, -1):
+            if _DIRS[k] not in slots:
+                T = np.tensordot(T, cap, axes=([k], [0]))
+        return T
+
+    net = _build((Lx, Ly), make, name=f"aklt2d_{Lx}x{Ly}")
+    net.info.update(model="aklt")
+    return net
+
+
+# ----------------------------------------------------------------------------
+# small non-lattice networks used by tests
+
+
+def ring_network(mats) -> Network:
+    """Closed ring: site i holds M_i[left, right]; Z = Tr(M_0 M_1 ... M_{L-1})."""
+    L = len(mats)
+    tensors = [np.ascontiguousarray(m, dtype=np.float64) for m in mats]
+    bonds = [(i, 1, (i + 1) % L, 0) for i in range(L)]
+    return Network(tensors, np.asarray(bonds, np.int32), name=f"ring{L}")
+
+
+def chain_network(tensors) -> Network:
+    """Open chain: first/last tensors are vectors, middle ones matrices."""
+    L = len(tensors)
+    bonds = []
+    for i in range(L - 1):
+        bonds.append((i, 0 if i == 0 else 1, i + 1, 0))
+    return Network([np.ascontiguousarray(t, np.float64) for t in tensors],
+                   np.asarray(bonds, np.int32).reshape(-1, 4), name=f"chain{L}")
+
+
+def grid_from_tensors(shape, tensor_fn, open_sites=None, name="grid") -> Network:
+    """Generic lattice builder: ``tensor_fn(site, bond_rank, open_dims)``."""
+    return _build(tuple(shape), tensor_fn, open_sites=open_sites, name=name)
+
+
+def apply_random_gauge(net: Network, seed: int, scale: float = 0.3) -> Network:
+    """Insert G G^-1 on every bond with a random well-conditioned G.
+
+    The contraction value is unchanged; the site tensors (and so the BP
+    messages) change, which is what the gauge-invariance checks rely on.
+    """
+    rng = np.random.default_rng(seed)
+    tensors = [t.copy() for t in net.tensors]
+    for (u, lu, v, lv) in net.bonds:
+        D = tensors[u].shape[lu]
+        G = np.eye(D) + scale * rng.standard_normal((D, D))
+        Gi = np.linalg.inv(G)
+        tu = np.tensordot(tensors[u], G, axes=([lu], [0]))
+        tensors[u] = np.ascontiguousarray(np.moveaxis(tu, -1, lu))
+        tv = np.tensordot(tensors[v], Gi, axes=([lv], [1]))
+        tensors[v] = np.ascontiguousarray(np.moveaxis(tv, -1, lv))
+    out = Network(tensors, net.bonds.copy(), net.open_legs.copy(),
+                  name=net.name + f"_g{seed}", info=dict(net.info, gauge_seed=seed))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# the five benchmark workloads
+
+
+def config1_network(beta: float = 0.44) -> Network:
+    """4x4 open-boundary 2D Ising, J=1, zero field."""
+    return ising_2d(4, 4, beta)
+
+
+def config1_betas(n: int, seed: int = 1) -> np.ndarray:
+    """Throughput batch: beta_i = 0.44 (1 + 0.01 u_i), u_i ~ U[-1, 1]."""
+    u = np.random.default_rng(seed).uniform(-1.0, 1.0, n)
+    return 0.44 * (1.0 + 0.01 * u)
+
+
+def config2_network(D: int = 4, seed: int = 2000) -> Network:
+    """16x16 open-boundary random network, i.i.d. U[0,1] entries."""
+    return random_2d(16, 16, D, "uniform01", seed)
+
+
+def config3_ising_network(beta: float) -> Network:
+    """6x6x6 open-boundary 3D Ising."""
+    return ising_3d(6, beta)
+
+
+def config3_aklt_network(gauge_seed=None) -> Network:
+    """12x12 AKLT norm network; optional random bond gauge (seed 3000+i)."""
+    net = aklt_2d(12, 12)
+    if gauge_seed is not None:
+        net = apply_random_gauge(net, gauge_seed)
+    return net
+
+
+def config4_request(i: int) -> Network:
+    """Serving request i (seed 40000+i): 2D L~U{4..32} or 3D L~U{4..8},
+    D~U{2,3,4}, entries U[0,1] or N(1, 0.3^2), each choice with p=1/2."""
+    rng = np.random.default_rng(40000 + i)
+    is3d = bool(rng.random() < 0.5)
+    L = int(rng.integers(4, 9)) if is3d else int(rng.integers(4, 33))
+    D = int(rng.integers(2, 5))
+    dist = "normal" if rng.random() < 0.5 else "uniform01"
+    shape = (L, L, L) if is3d else (L, L)
+    net = _build(shape, lambda s, r, o: _draw(rng, (D,) * r, dist),
+                 name=f"req{i}_{'3d' if is3d else '2d'}_L{L}_D{D}_{dist}")
+    net.info.update(model="random", D=D, dist=dist, L=L, dim=3 if is3d else 2, request=i)
+    return net
+
+
+def config4_arrivals(n: int, rate: float, seed: int = 4) -> np.ndarray:
+    """Poisson arrival times (seconds) at ``rate`` requests per second."""
+    gaps = np.random.default_rng(seed).exponential(1.0 / rate, n)
+    return np.cumsum(gaps)
+
+
+def config5_network(d: int, L: int = 32, D: int = 6, phys: int = 2) -> Network:
+    """32x32 D=6 U[0,1] network with open physical legs (dim 2) at
+    A = (x=12, y=15) and B = (x=12+d, y=15); seed 5000+d."""
+    a = _site_index((L, L), (12, 15))
+    b = _site_index((L, L), (12 + d, 15))
+    net = random_2d(L, L, D, "uniform01", 5000 + d, open_sites={a: phys, b: phys})
+    net.info.update(open_sites=(a, b), separation=d)
+    return net
