@@ -1,0 +1,206 @@
+"""Benchmark: PNE networks/s (and terms/s) on one MI355X.
+
+Workload (one step): the 16x16 open-boundary random-tensor networks with
+i.i.d. U[0,1] entries, 256 networks at bond dimension D=4 (seeds 2000-2255)
+plus the same 256 seeds at D=3, expanded to clusters of up to K=6 excited
+bonds.  Term contractions in FP32 (default) with FP64 BP, gauge, vacuum
+log-norms and cross-term sum; every network runs the whole path (BP from
+uniform messages, gauge, slices, clusters, sum) every step.  Tensors are
+resident in device memory before timing; the batch's geometry plan and
+device tables are prepared once (they depend only on the lattice).
+
+Prints one JSON line.  Kernel durations come from HIP events the library
+records on its own stream around each launch during the timed steps.
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PNE terms/s and networks/s at <=1e-5 rel err vs FP64 oracle; p50/p99 latency"
+HBM_PEAK_GBS = 8000.0
+
+
+def sweep_bytes(net) -> int:
+    """Algorithmic bytes of one BP sweep of one network: every site tensor
+    read once (FP64), every incoming message read twice (contraction and
+    residual) and every outgoing message written once."""
+    b = 0
+    for t in net.tensors:
+        b += 8 * t.size + 3 * 8 * sum(t.shape)
+    return b
+
+
+def regauge_bytes(net, slice_bytes: int) -> int:
+    """Site tensors read once (FP64), slices written once, gauge matrices read."""
+    b = 0
+    for t in net.tensors:
+        b += 8 * t.size + slice_bytes * t.size + 8 * sum(d * d for d in t.shape)
+    return b
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--precision", default="fp32", choices=["fp64", "fp32", "bf16"])
+    ap.add_argument("--nets", type=int, default=256, help="networks per bond dimension")
+    ap.add_argument("--K", type=int, default=6)
+    ap.add_argument("--check", type=int, default=2, help="networks per D checked against the oracle")
+    ap.add_argument("--cpu-sample", type=int, default=6, help="networks timed on the CPU oracle (0: skip)")
+    ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
+    args = ap.parse_args()
+
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+              "multi-GPU sharding is a design note, not an implemented path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    import pne_inputs as P
+    import paper_2512_10910_amd as pne
+
+    if not torch.cuda.is_available():
+        print("bench.py: no GPU visible", file=sys.stderr)
+        sys.exit(1)
+
+    t_setup = time.time()
+    nets_in = []
+    for D in (4, 3):
+        for i in range(args.nets):
+            nets_in.append(P.config2_network(D, 2000 + i))
+    print(f"bench: built {len(nets_in)} networks in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    ctx = pne.Context(0)
+    nets = [ctx.network(n) for n in nets_in]
+    batch = ctx.batch(nets, K=args.K, precision=args.precision, profile=True)
+    print(f"bench: prepared batch in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
+
+    for _ in range(args.warmup):
+        batch.run(raise_on_error=True)
+    batch.kernel_times(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = None
+    for _ in range(args.steps):
+        results = batch.run(raise_on_error=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = batch.kernel_times(reset=True)
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    n_nets = len(nets)
+    terms = sum(r.n_cluster_terms for r in results)
+    nets_per_s = n_nets / (ms_step * 1e-3)
+    print(f"bench: {ms_step:.3f} ms/step, {nets_per_s:.1f} networks/s", file=sys.stderr, flush=True)
+
+    # roofline of the dominant kernel (by device time)
+    slice_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    sweeps = [r.bp_iters for r in results]
+    bytes_sweep = sum(s * sweep_bytes(n) for s, n in zip(sweeps, nets_in))
+    bytes_regauge = sum(regauge_bytes(n, slice_bytes) for n in nets_in)
+    dom = max(("bp_sweep", "regauge", "clusters", "combine", "gauge"), key=lambda k: kt[k][0])
+    per_step_ms = {k: v[0] / args.steps for k, v in kt.items()}
+    if dom == "bp_sweep":
+        alg_bytes = bytes_sweep
+    elif dom == "regauge":
+        alg_bytes = bytes_regauge
+    else:
+        alg_bytes = None
+    achieved = None
+    if alg_bytes is not None and kt[dom][0] > 0:
+        # bytes per launch / average launch duration == bytes per step / time per step
+        achieved = alg_bytes / (per_step_ms[dom] * 1e-3) / 1e9
+    roofline = {
+        "kernel": dom,
+        "bound": "hbm",
+        "achieved": round(achieved, 1) if achieved else None,
+        "peak": HBM_PEAK_GBS,
+        "unit": "GB/s",
+        "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
+        "traffic": None,
+        "launches_per_step": kt[dom][1] / args.steps,
+        "avg_launch_us": round(kt[dom][0] / max(1, kt[dom][1]) * 1e3, 2),
+        "alg_bytes_per_step": alg_bytes,
+    }
+
+    out = {
+        "metric": METRIC,
+        "value": round(nets_per_s, 1),
+        "unit": "networks/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": {"fp64": "f64", "fp32": "f64 (BP, gauge, sums) + f32 (terms)",
+                  "bf16": "f64 (BP, gauge, sums) + bf16/f32 (terms)"}[args.precision],
+        "data": "synthetic",
+        "config": {
+            "workload": f"16x16 open-boundary U[0,1] random networks, D=4 and D=3, {args.nets} seeds each "
+                        f"(2000+), K={args.K}, {args.precision} terms",
+            "networks_per_step": n_nets,
+            "K": args.K,
+            "precision": args.precision,
+        },
+        "terms_per_s": round(terms / (ms_step * 1e-3), 1),
+        "terms_per_step": terms,
+        "bp_sweeps_mean": float(np.mean(sweeps)),
+        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step_ms.items()},
+        "roofline": roofline,
+    }
+
+    if not args.profile_run:
+        import oracle as O
+
+        # accuracy against the FP64 oracle on sampled networks of this batch
+        errs = []
+        idx = list(range(min(args.check, args.nets))) + [args.nets + i for i in range(min(args.check, args.nets))]
+        for i in idx:
+            ref = O.pne_contract(nets_in[i], args.K)
+            d = abs(results[i].log_abs - ref.log_abs)
+            errs.append(d / max(1.0, abs(ref.log_abs)))
+            if results[i].sign != ref.sign:
+                errs.append(math.inf)
+        out["max_rel_err_log_vs_oracle"] = float(max(errs)) if errs else None
+        out["accuracy_ok"] = bool(errs and max(errs) <= 1e-5)
+
+        if args.cpu_sample > 0:
+            try:
+                from threadpoolctl import threadpool_limits
+            except Exception:  # pragma: no cover
+                threadpool_limits = None
+            sample = [nets_in[i] for i in range(args.cpu_sample // 2)] + \
+                     [nets_in[args.nets + i] for i in range(args.cpu_sample - args.cpu_sample // 2)]
+            ctxm = threadpool_limits(1) if threadpool_limits else None
+            tc0 = time.perf_counter()
+            for n in sample:
+                O.pne_contract(n, args.K)
+            tc1 = time.perf_counter()
+            if ctxm is not None:
+                ctxm.unregister() if hasattr(ctxm, "unregister") else None
+            out["cpu_baseline"] = {
+                "value": round(len(sample) / (tc1 - tc0), 4),
+                "unit": "networks/s",
+                "cores": 1,
+                "kind": "oracle",
+                "sample": f"{len(sample)} networks of this workload (half D=4, half D=3), FP64 oracle, "
+                          f"one thread, {tc1 - tc0:.1f}s; host nproc={os.cpu_count()}",
+            }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

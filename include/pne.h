@@ -1,0 +1,185 @@
+/*
+ * pne.h — C ABI of the MI355X (gfx950) partitioned-network-expansion library.
+ *
+ * What the library computes (Evenbly, Gray, Chan, "Partitioned Expansions for
+ * Approximate Tensor Network Contractions"):
+ *
+ *   Input  : a tensor network — site tensors T_r joined by indices (Sec. II.A,
+ *            Eq. A1) — optionally with open indices (Sec. III.D).
+ *   Method : every bond is a single-index partition P_b + Q_b = I (Eq. A2);
+ *            P_b is the rank-1 projector made from the two fixed-point belief
+ *            propagation messages on the bond (Eq. A7), symmetrised by the
+ *            gauge of Appendix B; the complete P/Q expansion (Eq. A4) is
+ *            truncated to configurations of at most K excited (Q) bonds that
+ *            have no dangling excitation (Sec. III.A-B, "degree").
+ *   Output : the approximate contraction value as (sign, ln|Z|), or, for a
+ *            network with open legs, the open-index tensor with an FP64
+ *            log-scale.
+ *
+ * Conventions for every call:
+ *   - Integers describing the graph are int32; tensor values are FP64 at the
+ *     boundary in every precision mode.
+ *   - Site tensors are dense, C order over the site's leg slots 0..rank-1.
+ *   - Ownership: the caller owns every descriptor array and every host or
+ *     device buffer it passes.  The library copies host data, borrows device
+ *     data (see pne_network_create), and never frees caller memory.
+ *   - Errors: a negative pne_status is a failure (no result), a positive one
+ *     is a warning with a result.  pne_last_error() gives a message.
+ *   - Threading: a context is used by one thread at a time, except for the
+ *     server calls, which are thread safe.
+ *   - Streams: all device work is enqueued on the context's HIP stream.
+ */
+#ifndef PNE_H
+#define PNE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    PNE_OK = 0,
+    PNE_WARN_BP_NOT_CONVERGED = 1, /* result computed from the last BP sweep */
+    PNE_ERR_INVALID_ARG = -1,      /* malformed network, options or pointer */
+    PNE_ERR_UNSUPPORTED = -2,      /* outside the implemented envelope */
+    PNE_ERR_OUT_OF_MEMORY = -3,    /* device allocation failed or budget exceeded */
+    PNE_ERR_SINGULAR = -4,         /* a bond overlap a.c ~ 0 or a vacuum factor == 0 */
+    PNE_ERR_DEVICE = -5,           /* HIP runtime error or no usable device */
+    PNE_ERR_NOT_READY = -6         /* pne_poll: request still running */
+} pne_status;
+
+/* pne_options.flags bits */
+#define PNE_FLAG_PROFILE 1u /* time every kernel launch with HIP events on the context stream */
+
+/* Precision of the excited slices and the cluster (term) contractions.  BP,
+ * the bond gauge, vacuum log-norms and the cross-term sum are FP64 always. */
+typedef enum {
+    PNE_FP64 = 0, /* FP64 slices, FP64 arithmetic */
+    PNE_FP32 = 1, /* FP32 slices, FP32 arithmetic with FP32 accumulation */
+    PNE_BF16 = 2  /* BF16 slices, FP32 arithmetic with FP32 accumulation */
+} pne_precision;
+
+/* A tensor network (Sec. II.A).  Every leg slot of every site is either
+ * joined by exactly one bond or listed exactly once as an open leg. */
+typedef struct {
+    int32_t n_sites;
+    int32_t n_bonds;
+    int32_t n_open;
+    const int32_t *site_rank;     /* [n_sites] number of leg slots (>= 1)        */
+    const int32_t *leg_dim;       /* [sum site_rank] dims of the slots, site-major */
+    const int32_t *bond_site;     /* [2*n_bonds] (u, v) per bond, u != v           */
+    const int32_t *bond_leg;      /* [2*n_bonds] (slot at u, slot at v)            */
+    const int32_t *open_leg;      /* [2*n_open] (site, slot); may be NULL if 0     */
+    const double *const *site_data; /* [n_sites] FP64 tensors, host or device      */
+} pne_network_desc;
+
+typedef struct {
+    int32_t max_excited;  /* K: largest retained configuration degree (>= 0)   */
+    int32_t precision;    /* pne_precision                                       */
+    double bp_tol;        /* stop when the largest sign-insensitive inf-norm
+                             message change of a sweep is <= bp_tol (1e-13)      */
+    int32_t bp_max_iter;  /* sweep cap (500)                                     */
+    int32_t bp_check_every; /* sweeps between host convergence checks (0: auto) */
+    uint32_t flags;       /* reserved, 0                                         */
+    int32_t reserved;
+} pne_options;
+
+/* One network's result.  Closed network: Z = sign * exp(log_abs).  Open
+ * network: Out[i_0, i_1, ...] = open_values[...] * exp(log_abs), axes in the
+ * order of the descriptor's open legs, C order. */
+typedef struct {
+    int32_t status;          /* pne_status of this network                     */
+    int32_t sign;            /* +1, -1 (0 if Z == 0)                            */
+    double log_abs;          /* ln|Z| (closed) or the log-scale (open)          */
+    double log_abs_bp;       /* ln|Z_BP| (closed) or the vacuum log-scale       */
+    int32_t bp_iters;        /* sweeps performed                                 */
+    int32_t n_open_values;   /* number of entries written to open_values        */
+    double bp_residual;      /* last sweep's residual                            */
+    int64_t n_cluster_terms; /* connected dangling-free clusters contracted      */
+    int64_t n_config_terms;  /* retained configurations (collections), excl. 0  */
+    double *open_values;     /* caller buffer for open networks, or NULL        */
+    int64_t open_capacity;   /* entries available in open_values                */
+} pne_result;
+
+typedef struct pne_ctx pne_ctx;
+typedef struct pne_network pne_network;
+typedef struct pne_batch pne_batch;
+typedef struct pne_server pne_server;
+
+/* Fill *opt with defaults: K=4, FP64, tol 1e-13, 500 sweeps. */
+pne_status pne_options_default(pne_options *opt);
+
+/* Create a context on HIP device `device`.  mem_budget_bytes bounds the
+ * device memory the context may hold (0: no bound).  hip_stream is a
+ * hipStream_t to enqueue on (NULL: the context creates its own stream).
+ * Returns PNE_ERR_DEVICE if no device is usable. */
+pne_status pne_ctx_create(int device, size_t mem_budget_bytes, void *hip_stream, pne_ctx **out);
+pne_status pne_ctx_destroy(pne_ctx *ctx);
+/* Message of the last failing call on ctx (never NULL; valid until the next call). */
+const char *pne_last_error(const pne_ctx *ctx);
+
+/* Validate desc and make a network object (Sec. II.A network definition).
+ * data_on_device = 0: site_data are host pointers; the tensors are copied to
+ * device memory owned by the network.  data_on_device = 1: site_data are
+ * device pointers that the library borrows; the caller keeps them alive and
+ * unchanged until pne_network_destroy.  Descriptor arrays are copied. */
+pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int data_on_device,
+                              pne_network **out);
+pne_status pne_network_destroy(pne_network *net);
+
+/* Prepare a batch: enumerate (or fetch cached) retained clusters per network
+ * geometry, build contraction plans and device tables, allocate the batch's
+ * device working memory.  The networks must stay alive while the batch does. */
+pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n,
+                            const pne_options *opt, pne_batch **out);
+/* Enqueue the whole expansion for every network of the batch on the context
+ * stream (BP sweeps, gauge, slices, cluster contractions, FP64 sum). */
+pne_status pne_batch_launch(pne_batch *batch);
+/* Wait for a launched batch and fill results[0..n-1]. */
+pne_status pne_batch_wait(pne_batch *batch, pne_result *results);
+/* pne_batch_launch followed by pne_batch_wait. */
+pne_status pne_batch_run(pne_batch *batch, pne_result *results);
+pne_status pne_batch_destroy(pne_batch *batch);
+
+/* One-shot forms: batch of one / batch of n, created, run and destroyed. */
+pne_status pne_contract(pne_ctx *ctx, pne_network *net, const pne_options *opt, pne_result *res);
+pne_status pne_contract_batch(pne_ctx *ctx, pne_network *const *nets, int32_t n,
+                              const pne_options *opt, pne_result *results);
+
+/* --- introspection (parity tests and tooling) -------------------------- */
+
+/* Host-only: list the retained clusters (connected bond sets of size <= K in
+ * which every site has degree >= 2, sites with open legs >= 1) of a network
+ * geometry.  With bonds == NULL only counts: *n_clusters and *n_entries.
+ * Otherwise writes sizes[n_clusters] and bonds[n_entries] (each cluster's
+ * bond ids ascending, clusters in the library's order). */
+pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64_t *n_clusters,
+                                  int64_t *n_entries, int32_t *sizes, int32_t *bonds);
+
+/* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
+ * measured with HIP events recorded on the context stream around each launch.
+ * Index k: 0 init, 1 BP sweep, 2 sweep bookkeeping, 3 bond gauge, 4 regauge /
+ * slices, 5 cluster contraction, 6 combine.  Writes n entries; reset != 0
+ * clears the accumulators afterwards. */
+pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *launches, int32_t n,
+                                  int32_t reset);
+
+/* After pne_batch_wait: copy network i's final BP messages to host.  For
+ * every bond b, out holds the message arriving at the bond's first site
+ * (dim d_b) followed by the message arriving at its second site; bonds in
+ * order.  Capacity in doubles; returns INVALID_ARG if too small. */
+pne_status pne_batch_messages(pne_batch *batch, int32_t i, double *out, int64_t capacity);
+/* After pne_batch_wait: copy network i's cluster weights w_c (cluster order
+ * of pne_enumerate_clusters; open clusters contribute their full tensors, so
+ * *n_values may exceed the cluster count).  offsets[c] gives each cluster's
+ * first value when offsets != NULL. */
+pne_status pne_batch_cluster_weights(pne_batch *batch, int32_t i, double *out, int64_t capacity,
+                                     int64_t *n_values, int64_t *offsets);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PNE_H */

@@ -1,0 +1,20 @@
+"""MI355X (gfx950) partitioned network expansion: C-ABI library + thin binding.
+
+The hot path (BP sweeps, bond gauge, excited slices, cluster contractions and
+the FP64 cross-term sum) runs in hand-written HIP kernels inside libpne.so;
+this package only marshals arguments.  Importing it does not load the
+library; the first Context (or enumerate_clusters) call does, and fails
+loudly if libpne.so has not been built.
+"""
+
+from .pne import (  # noqa: F401
+    Batch,
+    Context,
+    Network,
+    PNEError,
+    Result,
+    enumerate_clusters,
+    load_library,
+    LIB_PATH,
+    PRECISIONS,
+)

@@ -1,0 +1,72 @@
+// Host-side geometry: validation, cluster enumeration, contraction plans and
+// combine tables.  Everything here depends only on the network's graph and
+// leg dimensions (never on tensor values), so results are cached per
+// (geometry, K) by the runtime.
+#pragma once
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "pne.h"
+#include "pne_internal.h"
+
+namespace pne {
+
+struct Geometry {
+    int n_sites = 0, n_bonds = 0, n_open = 0;
+    std::vector<int> rank;       // per site
+    std::vector<int> slot_base;  // per site: first global slot
+    std::vector<int> dim;        // per global slot
+    std::vector<int> bu, bul, bv, bvl;
+    std::vector<int> open_site, open_slot;
+    std::vector<int> partner;    // per global slot: slot receiving its outgoing message
+    std::vector<int> is_open;    // per global slot
+    std::vector<int> open_sites; // distinct sites with open legs, by first open leg
+    uint64_t hash = 0;
+
+    int slot(int s, int l) const { return slot_base[s] + l; }
+    bool same_as(const Geometry &o) const;
+};
+
+// Validate a descriptor and fill *g.  Returns an empty string or the reason.
+std::string build_geometry(const pne_network_desc *desc, Geometry *g);
+
+struct ClusterList {
+    std::vector<int> off{0};  // cluster c: bonds[off[c] .. off[c+1])
+    std::vector<int> bonds;
+    int count() const { return (int)off.size() - 1; }
+};
+
+// Every connected bond set of size <= K whose sites all have degree >= 2
+// inside the set (sites with open legs: >= 1).  Bonds of a cluster ascending.
+void enumerate_clusters(const Geometry &g, int K, ClusterList *out);
+
+struct GeoPlan {
+    int K = 0;
+    ClusterList clusters;             // ordered by (type, size, discovery)
+    std::vector<int> ctype, csize;    // per cluster
+    std::vector<int64_t> w_off;       // per cluster: offset of its weight values
+    int64_t w_total = 0;
+    std::vector<int> cls_of, inst_of; // per cluster: class and instance index
+
+    std::vector<ClassDesc> classes;
+    std::vector<StepDesc> steps;
+    std::vector<std::vector<int>> inst_cluster;    // per class
+    std::vector<std::vector<int>> inst_site;       // per class: n_inst * n_verts (local site ids)
+    std::vector<std::vector<uint32_t>> inst_slots; // per class: n_inst * n_verts packed slots
+
+    std::vector<Bucket> buckets;
+    std::vector<int> pair_a, pair_b;  // overlapping cluster pairs (|a|+|b| <= K)
+    std::vector<PairCat> pair_cats;
+    int open_a = -1, open_b = -1, pa = 1, pb = 1;
+    int64_t n_configs = 0;
+    size_t max_f = 1;
+};
+
+// Build the plan; returns nullptr and sets *err (prefixed "unsupported:" when
+// the geometry is valid but outside the implemented envelope).
+std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err);
+
+}  // namespace pne

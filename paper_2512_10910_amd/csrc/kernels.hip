@@ -1,0 +1,834 @@
+// gfx950 kernels of the partitioned network expansion hot path.
+//
+//   k_init      uniform start messages (1/sqrt(d) on every directed message)
+//   k_bp_sweep  one Jacobi BP sweep over LDS-staged tiles of same-shape sites
+//               (Sec. II.B: fixed-point messages; Sec. III.D: open legs reflect)
+//   k_bp_finish per-network sweep bookkeeping and convergence test
+//   k_gauge     per bond: rank-1 projector from the two messages in the
+//               symmetrising gauge of Appendix B (P = e0 e0^T, Q = the rest)
+//   k_regauge   per site: apply the bond gauges, split off the vacuum factor,
+//               store the excited slices in the term precision
+//   k_clusters  per cluster instance: contract the excited slices (the loop
+//               terms of Sec. III.A-B; every term keeps the original geometry
+//               with modified tensors, Sec. VI)
+//   k_combine   per network: FP64 sum of the retained configurations
+//               (Eq. A4 truncated to degree <= K, vertex-disjoint products)
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "kernels.h"
+
+namespace pne {
+
+namespace {
+
+constexpr int kBpThreads = 256;
+constexpr int kRgThreads = 128;
+constexpr int kClThreads = 256;
+constexpr int kCbThreads = 256;
+
+__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// Round an FP64 value to bfloat16 once (round to nearest even).  The FP32
+// intermediate is truncated and carries a sticky bit, so the single rounding
+// step happens at bfloat16 precision.
+__device__ inline uint16_t f64_to_bf16(double x) {
+    float f = __double2float_rz(x);
+    uint32_t u = __float_as_uint(f);
+    if ((double)f != x) u |= 1u;  // sticky
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf/nan
+    uint32_t lsb = (u >> 16) & 1u;
+    u += 0x7fffu + lsb;
+    return (uint16_t)(u >> 16);
+}
+
+template <typename S>
+struct SliceIO;
+template <>
+struct SliceIO<double> {
+    using acc = double;
+    __device__ static double load(const double *p, int64_t i) { return p[i]; }
+    __device__ static void store(double *p, int64_t i, double v) { p[i] = v; }
+};
+template <>
+struct SliceIO<float> {
+    using acc = float;
+    __device__ static float load(const float *p, int64_t i) { return p[i]; }
+    __device__ static void store(float *p, int64_t i, double v) { p[i] = (float)v; }
+};
+template <>
+struct SliceIO<uint16_t> {
+    using acc = float;
+    __device__ static float load(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
+    __device__ static void store(uint16_t *p, int64_t i, double v) { p[i] = f64_to_bf16(v); }
+};
+
+__device__ inline double warp_max(double v) {
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+// ---------------------------------------------------------------------------
+
+__global__ void k_init(const SiteRec *__restrict__ sites, int n_sites, double *__restrict__ msg0,
+                       NetState *__restrict__ st, int n_nets) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n_nets) {
+        NetState s;
+        s.active = 1;
+        s.iters = 0;
+        s.parity = 0;
+        s.status = 0;
+        s.res_bits = 0ull;
+        s.residual = 0.0;
+        s.log_bp = 0.0;
+        s.sign_bp = 1;
+        s.converged = 0;
+        st[i] = s;
+    }
+    if (i < n_sites) {
+        const SiteRec &r = sites[i];
+        for (int l = 0; l < r.rank; ++l) {
+            double v = 1.0 / sqrt((double)r.dim[l]);
+            double *m = msg0 + r.msg_off + r.moff[l];
+            for (int k = 0; k < r.dim[l]; ++k) m[k] = v;
+        }
+    }
+}
+
+// Outgoing (unnormalised) message on leg `l`, entry `i`: the site tensor
+// contracted with the incoming messages of every other leg.  The innermost
+// other leg is summed as a dot product; the remaining legs run an odometer.
+// Shape arrays live in LDS (uniform per tile).
+template <int R>
+__device__ double bp_out(const double *__restrict__ T, const double *__restrict__ M, const int *s_dim,
+                         const int *s_moff, const int *s_stride, int l, int i) {
+    if constexpr (R == 1) {
+        return T[i];
+    } else {
+        const int q = (l == R - 1) ? R - 2 : R - 1;
+        int dim[R], str[R], mo[R], dig[R];
+        int nouter = 1;
+#pragma unroll
+        for (int k = 0; k < R; ++k) {
+            dim[k] = s_dim[k];
+            str[k] = s_stride[k];
+            mo[k] = s_moff[k];
+            dig[k] = 0;
+            if (k != l && k != q) nouter *= dim[k];
+        }
+        const int dq = s_dim[q], sq = s_stride[q];
+        const double *Mq = M + s_moff[q];
+        int base = i * s_stride[l];
+        double acc = 0.0;
+        for (int it = 0; it < nouter; ++it) {
+            double pp = 1.0;
+#pragma unroll
+            for (int k = 0; k < R; ++k)
+                if (k != l && k != q) pp *= M[mo[k] + dig[k]];
+            double s = 0.0;
+            for (int d = 0; d < dq; ++d) s = fma(T[base + d * sq], Mq[d], s);
+            acc = fma(pp, s, acc);
+#pragma unroll
+            for (int k = R - 1; k >= 0; --k) {
+                if (k == l || k == q) continue;
+                if (++dig[k] < dim[k]) {
+                    base += str[k];
+                    break;
+                }
+                base -= (dim[k] - 1) * str[k];
+                dig[k] = 0;
+            }
+        }
+        return acc;
+    }
+}
+
+__device__ double bp_out_dispatch(int R, const double *T, const double *M, const int *dim, const int *moff,
+                                  const int *stride, int l, int i) {
+    switch (R) {
+        case 1: return bp_out<1>(T, M, dim, moff, stride, l, i);
+        case 2: return bp_out<2>(T, M, dim, moff, stride, l, i);
+        case 3: return bp_out<3>(T, M, dim, moff, stride, l, i);
+        case 4: return bp_out<4>(T, M, dim, moff, stride, l, i);
+        case 5: return bp_out<5>(T, M, dim, moff, stride, l, i);
+        case 6: return bp_out<6>(T, M, dim, moff, stride, l, i);
+        case 7: return bp_out<7>(T, M, dim, moff, stride, l, i);
+        default: return bp_out<8>(T, M, dim, moff, stride, l, i);
+    }
+}
+
+// One Jacobi sweep.  Block = one tile: up to 64 sites of one network with
+// identical leg dims.  Tensors and incoming messages are staged in LDS with
+// coalesced loads; each thread produces one outgoing message entry; then one
+// thread per (site, leg) normalises (unit 2-norm, non-negative sum), writes
+// the message to the partner slot and folds its residual into the network's
+// running maximum.
+__global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restrict__ sites,
+                                                         const BpTile *__restrict__ tiles,
+                                                         const int *__restrict__ tile_sites,
+                                                         double *msg0, double *msg1, NetState *st) {
+    const BpTile tl = tiles[blockIdx.x];
+    NetState *ns = st + tl.net;
+    if (!ns->active) return;
+    const double *__restrict__ min = ns->parity ? msg1 : msg0;
+    double *__restrict__ mout = ns->parity ? msg0 : msg1;
+
+    extern __shared__ double lds[];
+    __shared__ const double *s_t[64];
+    __shared__ int s_msg[64];
+    __shared__ int s_dst[64 * kMaxRank];
+    __shared__ int s_dim[kMaxRank], s_moff[kMaxRank], s_stride[kMaxRank];
+    __shared__ double s_red[kBpThreads / 64];
+    __shared__ int s_bad;
+
+    const int tid = threadIdx.x;
+    const int R = tl.rank, size = tl.size, nos = tl.n_os, ns_ = tl.n_sites;
+    if (tid < ns_) {
+        const SiteRec &r = sites[tile_sites[tl.site_begin + tid]];
+        s_t[tid] = r.t;
+        s_msg[tid] = r.msg_off;
+        for (int l = 0; l < R; ++l) s_dst[tid * kMaxRank + l] = r.dst[l];
+        if (tid == 0) {
+            for (int l = 0; l < R; ++l) {
+                s_dim[l] = r.dim[l];
+                s_moff[l] = r.moff[l];
+                s_stride[l] = r.stride[l];
+            }
+            s_bad = 0;
+        }
+    }
+    __syncthreads();
+    double *lt = lds;
+    double *lm = lt + ns_ * size;
+    double *lo = lm + ns_ * nos;
+    for (int j = 0; j < ns_; ++j) {
+        const double *src = s_t[j];
+        for (int e = tid; e < size; e += kBpThreads) lt[j * size + e] = src[e];
+        for (int e = tid; e < nos; e += kBpThreads) lm[j * nos + e] = min[s_msg[j] + e];
+    }
+    __syncthreads();
+
+    const int nout = ns_ * nos;
+    for (int o = tid; o < nout; o += kBpThreads) {
+        int j = o / nos;
+        int r = o - j * nos;
+        int l = 0;
+        while (l + 1 < R && r >= s_moff[l + 1]) ++l;
+        lo[o] = bp_out_dispatch(R, lt + j * size, lm + j * nos, s_dim, s_moff, s_stride, l, r - s_moff[l]);
+    }
+    __syncthreads();
+
+    double res = 0.0;
+    for (int m = tid; m < ns_ * R; m += kBpThreads) {
+        int j = m / R;
+        int l = m - j * R;
+        const double *raw = lo + j * nos + s_moff[l];
+        const int d = s_dim[l];
+        double n2 = 0.0, sum = 0.0;
+        for (int k = 0; k < d; ++k) {
+            n2 = fma(raw[k], raw[k], n2);
+            sum += raw[k];
+        }
+        double nrm = sqrt(n2);
+        if (!(nrm > 0.0) || !isfinite(nrm)) {
+            s_bad = 1;
+            continue;
+        }
+        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        const int dst = s_dst[j * kMaxRank + l];
+        double d1 = 0.0, d2 = 0.0;
+        for (int k = 0; k < d; ++k) {
+            double v = sg * (raw[k] / nrm);
+            double old = min[dst + k];
+            d1 = fmax(d1, fabs(v - old));
+            d2 = fmax(d2, fabs(v + old));
+            mout[dst + k] = v;
+        }
+        res = fmax(res, fmin(d1, d2));
+    }
+    res = warp_max(res);
+    if ((tid & 63) == 0) s_red[tid >> 6] = res;
+    __syncthreads();
+    if (tid == 0) {
+        double r = s_red[0];
+        for (int w = 1; w < kBpThreads / 64; ++w) r = fmax(r, s_red[w]);
+        atomicMax(&ns->res_bits, (unsigned long long)__double_as_longlong(r));
+        if (s_bad) atomicMin(&ns->status, -4);
+    }
+}
+
+// Sweep bookkeeping: flip buffers, record the residual, stop converged or
+// exhausted networks, count the still-active ones (single block).
+__global__ void k_bp_finish(NetState *st, int n_nets, double tol, int max_iter, int *n_active) {
+    __shared__ int s_cnt[1024 / 64];
+    int cnt = 0;
+    for (int i = threadIdx.x; i < n_nets; i += blockDim.x) {
+        NetState &s = st[i];
+        if (!s.active) continue;
+        s.iters += 1;
+        s.parity ^= 1;
+        double r = __longlong_as_double((long long)s.res_bits);
+        s.residual = r;
+        s.res_bits = 0ull;
+        if (s.status < 0) {
+            s.active = 0;
+        } else if (r <= tol) {
+            s.active = 0;
+            s.converged = 1;
+        } else if (s.iters >= max_iter) {
+            s.active = 0;
+        } else {
+            ++cnt;
+        }
+    }
+    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
+    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int t = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_cnt[w];
+        *n_active = t;
+    }
+}
+
+// Per bond: with a = message arriving at the first site, c = message
+// arriving at the second site and n = a.c, the gauge G = [a/n | R] (R an
+// orthonormal basis of the complement of c, from one Householder reflection)
+// has inverse [c^T ; R^T (I - a c^T / n)].  Inserting G G^-1 on the bond makes
+// the rank-1 projector a c^T / n equal to e0 e0^T, so Q = I - P keeps exactly
+// the indices 1..d-1.  The first site's slot is multiplied by G, the second
+// site's slot by G^-1 (stored transposed so both use T'[.k.] = sum_i T[.i.] X[i,k]).
+__global__ void k_gauge(const BondRec *__restrict__ bonds, int n_bonds, const double *msg0,
+                        const double *msg1, NetState *st, double *__restrict__ xg) {
+    int b = blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= n_bonds) return;
+    const BondRec br = bonds[b];
+    NetState *ns = st + br.net;
+    const double *m = ns->parity ? msg1 : msg0;
+    const double *a = m + br.a_off;
+    const double *c = m + br.c_off;
+    const int D = br.dim;
+    double n = 0.0, na = 0.0, nc = 0.0;
+    for (int i = 0; i < D; ++i) {
+        n = fma(a[i], c[i], n);
+        na = fma(a[i], a[i], na);
+        nc = fma(c[i], c[i], nc);
+    }
+    na = sqrt(na);
+    nc = sqrt(nc);
+    double *Xu = xg + br.xu_off;
+    double *Xv = xg + br.xv_off;
+    if (!(fabs(n) >= 1e-12 * na * nc) || !isfinite(n)) {
+        atomicMin(&ns->status, -4);
+        for (int i = 0; i < D * D; ++i) {
+            Xu[i] = (i % (D + 1) == 0) ? 1.0 : 0.0;
+            Xv[i] = Xu[i];
+        }
+        return;
+    }
+    // Householder vector u = c/|c| - alpha e0 with alpha = -sign(c0)
+    const double v0 = c[0] / nc;
+    const double alpha = v0 > 0.0 ? -1.0 : 1.0;
+    const double u0 = v0 - alpha;
+    double uu = u0 * u0;
+    for (int i = 1; i < D; ++i) uu = fma(c[i] / nc, c[i] / nc, uu);
+    const double inv_n = 1.0 / n;
+    for (int i = 0; i < D; ++i) {
+        Xu[i * D] = a[i] * inv_n;
+        Xv[i * D] = c[i];
+    }
+    for (int k = 1; k < D; ++k) {
+        const double uk = c[k] / nc;
+        // column k of the reflection: r_i = delta_ik - 2 u_i u_k / uu
+        double ra = 0.0;
+        for (int i = 0; i < D; ++i) {
+            const double ui = (i == 0) ? u0 : c[i] / nc;
+            const double r = (i == k ? 1.0 : 0.0) - 2.0 * ui * uk / uu;
+            Xu[i * D + k] = r;
+            ra = fma(r, a[i], ra);
+        }
+        const double f = ra * inv_n;
+        for (int j = 0; j < D; ++j) {
+            const double uj = (j == 0) ? u0 : c[j] / nc;
+            const double r = (j == k ? 1.0 : 0.0) - 2.0 * uj * uk / uu;
+            Xv[j * D + k] = r - f * c[j];
+        }
+    }
+}
+
+// Per site (one block): apply the gauge of every bond slot (mode products in
+// LDS), then divide by the vacuum factor z'_v = T'[0,...,0] (closed sites) or
+// by the largest magnitude of the vacuum vector (sites with open legs), and
+// store the result in the slice precision.  ln|z'| and its sign are kept in
+// FP64; their sum over sites is ln|Z_BP|.
+template <typename S>
+__global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restrict__ sites,
+                                                        const double *__restrict__ xg, S *__restrict__ slices,
+                                                        double *__restrict__ site_log, int *__restrict__ site_sign,
+                                                        double *__restrict__ vac, NetState *st) {
+    const SiteRec r = sites[blockIdx.x];
+    extern __shared__ double lds[];
+    __shared__ double s_x[kMaxDim * kMaxDim];
+    __shared__ double s_norm;
+    __shared__ int s_ok;
+    const int tid = threadIdx.x;
+    const int size = r.size;
+    double *b0 = lds;
+    double *b1 = lds + size;
+    for (int e = tid; e < size; e += kRgThreads) b0[e] = r.t[e];
+    int xoff = 0;
+    for (int l = 0; l < r.rank; ++l) {
+        const int d = r.dim[l];
+        if (!((r.open_mask >> l) & 1)) {
+            __syncthreads();
+            for (int e = tid; e < d * d; e += kRgThreads) s_x[e] = xg[r.xg_off + xoff + e];
+            __syncthreads();
+            const int sl = r.stride[l];
+            for (int e = tid; e < size; e += kRgThreads) {
+                const int k = (e / sl) % d;
+                const int base = e - k * sl;
+                double acc = 0.0;
+                for (int i = 0; i < d; ++i) acc = fma(b0[base + i * sl], s_x[i * d + k], acc);
+                b1[e] = acc;
+            }
+            double *t = b0;
+            b0 = b1;
+            b1 = t;
+        }
+        xoff += d * d;
+    }
+    __syncthreads();
+    if (tid == 0) {
+        double nv;
+        int sg = 1;
+        if (r.open_mask == 0) {
+            nv = b0[0];
+            sg = nv < 0.0 ? -1 : 1;
+        } else {
+            // vacuum vector over the open legs (bond indices 0)
+            int n_open = 1;
+            for (int l = 0; l < r.rank; ++l)
+                if ((r.open_mask >> l) & 1) n_open *= r.dim[l];
+            nv = 0.0;
+            for (int p = 0; p < n_open; ++p) {
+                int rem = p, off = 0;
+                for (int l = r.rank - 1; l >= 0; --l) {
+                    if (!((r.open_mask >> l) & 1)) continue;
+                    off += (rem % r.dim[l]) * r.stride[l];
+                    rem /= r.dim[l];
+                }
+                nv = fmax(nv, fabs(b0[off]));
+            }
+        }
+        s_ok = (fabs(nv) > 0.0) && isfinite(nv);
+        s_norm = nv;
+        site_log[blockIdx.x] = s_ok ? log(fabs(nv)) : 0.0;
+        site_sign[blockIdx.x] = sg;
+        if (!s_ok) atomicMin(&st[r.net].status, -4);
+    }
+    __syncthreads();
+    if (!s_ok) return;
+    const double nv = s_norm;
+    for (int e = tid; e < size; e += kRgThreads) SliceIO<S>::store(slices, r.slice_off + e, b0[e] / nv);
+    if (r.open_mask != 0) {
+        int n_open = 1;
+        for (int l = 0; l < r.rank; ++l)
+            if ((r.open_mask >> l) & 1) n_open *= r.dim[l];
+        for (int p = tid; p < n_open; p += kRgThreads) {
+            int rem = p, off = 0;
+            for (int l = r.rank - 1; l >= 0; --l) {
+                if (!((r.open_mask >> l) & 1)) continue;
+                off += (rem % r.dim[l]) * r.stride[l];
+                rem /= r.dim[l];
+            }
+            vac[r.vac_off + p] = b0[off] / nv;
+        }
+    }
+}
+
+// Cluster contraction by a per-class plan: the frontier tensor F absorbs one
+// excited slice per step (F_next[out] = sum_shared F[.] X[.]).  A class runs
+// `group` lanes per instance; every step is uniform across the block.
+template <typename S>
+__global__ void __launch_bounds__(kClThreads) k_clusters(
+    const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps,
+    const ClusterBlock *__restrict__ blocks, const int *__restrict__ inst_site,
+    const uint32_t *__restrict__ inst_slots, const int64_t *__restrict__ inst_rec,
+    const int64_t *__restrict__ inst_wout, const SiteRec *__restrict__ sites, const S *__restrict__ slices,
+    double *__restrict__ w) {
+    using A = typename SliceIO<S>::acc;
+    const ClusterBlock blk = blocks[blockIdx.x];
+    const ClassDesc cd = classes[blk.cls];
+    extern __shared__ double lds_raw[];
+    __shared__ StepDesc s_steps[kMaxVerts];
+    const int tid = threadIdx.x;
+    for (int i = tid; i < cd.n_steps * (int)(sizeof(StepDesc) / 4); i += kClThreads)
+        reinterpret_cast<int32_t *>(s_steps)[i] =
+            reinterpret_cast<const int32_t *>(steps + cd.step_begin)[i];
+    const int g = cd.group;
+    const int lane = tid & (g - 1);
+    const int slot = tid / g;
+    const bool valid = slot < blk.count;
+    const int64_t inst = blk.inst_begin + slot;
+    A *F = reinterpret_cast<A *>(lds_raw) + (size_t)slot * 2 * cd.max_f;
+    A *G = F + cd.max_f;
+    if (lane == 0) F[0] = A(1);
+    const int64_t rec = valid ? inst_rec[inst] : 0;
+    __syncthreads();
+    for (int st = 0; st < cd.n_steps; ++st) {
+        const StepDesc &sd = s_steps[st];
+        if (valid) {
+            const int site = inst_site[rec + sd.vert];
+            const uint32_t slots = inst_slots[rec + sd.vert];
+            const SiteRec &sr = sites[site];
+            int xs[kMaxLab];
+            int64_t xbase = sr.slice_off;
+#pragma unroll
+            for (int m = 0; m < kMaxLab; ++m) {
+                xs[m] = 0;
+                if (m < sd.n_xl) {
+                    xs[m] = sr.stride[(slots >> (4 * m)) & 15u];
+                    if (sd.x_excited[m]) xbase += xs[m];  // excited indices start at 1
+                }
+            }
+            for (int o = lane; o < sd.n_out; o += g) {
+                int rem = o, fb = 0, xb = 0;
+                for (int k = sd.n_ol - 1; k >= 0; --k) {
+                    const int dd = sd.out_dim[k];
+                    const int dg = rem % dd;
+                    rem /= dd;
+                    fb += dg * sd.out_fs[k];
+                    const int xl = sd.out_xl[k];
+                    if (xl >= 0) {
+#pragma unroll
+                        for (int m = 0; m < kMaxLab; ++m)
+                            if (m == xl) xb += dg * xs[m];
+                    }
+                }
+                int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
+#pragma unroll
+                for (int k = 0; k < kMaxLab; ++k) {
+                    sdg[k] = 0;
+                    sfs[k] = 0;
+                    sxs[k] = 0;
+                    if (k < sd.n_sl) {
+                        sfs[k] = sd.sum_fs[k];
+#pragma unroll
+                        for (int m = 0; m < kMaxLab; ++m)
+                            if (m == sd.sum_xl[k]) sxs[k] = xs[m];
+                    }
+                }
+                A acc = A(0);
+                int fo = fb;
+                int64_t xo = xbase + xb;
+                for (int t = 0; t < sd.n_sum; ++t) {
+                    acc += F[fo] * SliceIO<S>::load(slices, xo);
+#pragma unroll
+                    for (int k = kMaxLab - 1; k >= 0; --k) {
+                        if (k >= sd.n_sl) continue;
+                        if (++sdg[k] < sd.sum_dim[k]) {
+                            fo += sfs[k];
+                            xo += sxs[k];
+                            break;
+                        }
+                        fo -= (sd.sum_dim[k] - 1) * sfs[k];
+                        xo -= (int64_t)(sd.sum_dim[k] - 1) * sxs[k];
+                        sdg[k] = 0;
+                    }
+                }
+                G[o] = acc;
+            }
+        }
+        __syncthreads();
+        A *t = F;
+        F = G;
+        G = t;
+    }
+    if (valid) {
+        const int64_t wo = inst_wout[inst];
+        for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
+    }
+}
+
+// Block sum of one value per thread in a fixed order (deterministic).
+__device__ double block_sum(double v, double *red) {
+    const int tid = threadIdx.x;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < kCbThreads / 64; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// Per network: FP64 sum of the retained configurations.  Clusters come in
+// contiguous (type, size) buckets; with W_s the bucket sums, configurations of
+// one or two vertex-disjoint clusters with total degree <= K are
+//   sum_s W_s + sum_{s<s'} W_s W_s' + sum_s (W_s^2 - sum w^2)/2 - overlaps,
+// the overlaps being the explicitly listed pairs of clusters that share a
+// site.  Open networks combine vacuum vectors and open-cluster tensors the
+// same way, one tensor product per configuration.
+__global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__restrict__ recs,
+                                                        const GeoRec *__restrict__ geos,
+                                                        const Bucket *__restrict__ buckets,
+                                                        const int *__restrict__ pair_a, const int *__restrict__ pair_b,
+                                                        const PairCat *__restrict__ cats, const double *__restrict__ w,
+                                                        const double *__restrict__ site_log,
+                                                        const int *__restrict__ site_sign, const double *__restrict__ vac,
+                                                        const NetState *__restrict__ st, NetResult *__restrict__ out) {
+    const int net = blockIdx.x;
+    const CombineRec cr = recs[net];
+    const GeoRec gr = geos[cr.geo];
+    __shared__ double red[kCbThreads / 64];
+    __shared__ double bsum[64][kMaxOpenOut];
+    __shared__ double bsq[64];
+    __shared__ double psum[8][kMaxOpenOut];
+    __shared__ int bidx[4][33];
+    const int tid = threadIdx.x;
+    const double *wn = w + cr.w_base;
+
+    double lg = 0.0, neg = 0.0;
+    for (int s = tid; s < cr.n_sites; s += kCbThreads) {
+        lg += site_log[cr.site_begin + s];
+        neg += site_sign[cr.site_begin + s] < 0 ? 1.0 : 0.0;
+    }
+    lg = block_sum(lg, red);
+    neg = block_sum(neg, red);
+
+    for (int i = tid; i < 4 * 33; i += kCbThreads) bidx[i / 33][i % 33] = -1;
+    __syncthreads();
+    const int nb = gr.n_buckets < 64 ? gr.n_buckets : 64;
+    for (int b = 0; b < nb; ++b) {
+        const Bucket bk = buckets[gr.bucket_begin + b];
+        if (tid == 0 && bk.size <= 32) bidx[bk.type][bk.size] = b;
+        for (int e = 0; e < bk.osz; ++e) {
+            double v = 0.0;
+            for (int c = bk.begin + tid; c < bk.end; c += kCbThreads) v += wn[bk.w_begin + (int64_t)(c - bk.begin) * bk.osz + e];
+            v = block_sum(v, red);
+            if (tid == 0) bsum[b][e] = v;
+        }
+        if (bk.type == 0) {
+            double v = 0.0;
+            for (int c = bk.begin + tid; c < bk.end; c += kCbThreads) {
+                double x = wn[bk.w_begin + (c - bk.begin)];
+                v = fma(x, x, v);
+            }
+            v = block_sum(v, red);
+            if (tid == 0) bsq[b] = v;
+        }
+    }
+    // overlap pair sums per category (index: 0 closed-closed, 1 A-closed,
+    // 2 B-closed, 3 AB-closed, 4 B-with-A)
+    const int pa = cr.pa, pb = cr.pb;
+    for (int k = 0; k < 5; ++k)
+        for (int e = tid; e < kMaxOpenOut; e += kCbThreads) psum[k][e] = 0.0;
+    __syncthreads();
+    for (int ci = 0; ci < gr.n_pair_cats; ++ci) {
+        const PairCat pc = cats[gr.pair_cat_begin + ci];
+        int slot, osz;
+        if (pc.t2 == 0) {
+            slot = pc.t1;
+            osz = pc.t1 == 0 ? 1 : pc.t1 == 1 ? pa : pc.t1 == 2 ? pb : pa * pb;
+        } else {
+            slot = 4;
+            osz = pa * pb;
+        }
+        // weight offsets: clusters within a type are contiguous, so locate by bucket
+        for (int e = 0; e < osz; ++e) {
+            double v = 0.0;
+            for (int p = pc.begin + tid; p < pc.end; p += kCbThreads) {
+                const int ca = pair_a[gr.pair_begin + p], cb = pair_b[gr.pair_begin + p];
+                // offsets through the bucket tables (type-ordered clusters)
+                int64_t oa = -1, ob = -1;
+                int sa = 1, sb = 1;
+                for (int b = 0; b < nb; ++b) {
+                    const Bucket bk = buckets[gr.bucket_begin + b];
+                    if (ca >= bk.begin && ca < bk.end) {
+                        oa = bk.w_begin + (int64_t)(ca - bk.begin) * bk.osz;
+                        sa = bk.osz;
+                    }
+                    if (cb >= bk.begin && cb < bk.end) {
+                        ob = bk.w_begin + (int64_t)(cb - bk.begin) * bk.osz;
+                        sb = bk.osz;
+                    }
+                }
+                if (slot == 4) {
+                    // B-cluster (ca) with A-cluster (cb): entry e = (ia, ib)
+                    const int ia = e / pb, ib = e % pb;
+                    v = fma(wn[ob + ia], wn[oa + ib], v);
+                } else {
+                    (void)sa;
+                    (void)sb;
+                    v = fma(wn[oa + e], wn[ob], v);
+                }
+            }
+            v = block_sum(v, red);
+            if (tid == 0) psum[slot][e] = v;
+        }
+    }
+    __syncthreads();
+    if (tid != 0) return;
+
+    NetResult res;
+    const NetState ns = st[net];
+    res.status = ns.status;
+    res.log_bp = lg;
+    const int sign_bp = ((int)neg & 1) ? -1 : 1;
+    const int K = gr.K < 32 ? gr.K : 32;
+    auto B = [&](int t, int s) { return (s >= 0 && s <= 32) ? bidx[t][s] : -1; };
+    double SC = 0.0;
+    for (int s = 1; s <= K; ++s) {
+        int b = B(0, s);
+        if (b >= 0) SC += bsum[b][0];
+    }
+    for (int s = 1; s <= K; ++s) {
+        int b = B(0, s);
+        if (b < 0) continue;
+        for (int s2 = s + 1; s + s2 <= K; ++s2) {
+            int b2 = B(0, s2);
+            if (b2 >= 0) SC += bsum[b][0] * bsum[b2][0];
+        }
+        if (2 * s <= K) SC += 0.5 * (bsum[b][0] * bsum[b][0] - bsq[b]);
+    }
+    SC -= psum[0][0];
+    res.sum = SC;
+    if (cr.vac_a < 0) {
+        const double tot = 1.0 + SC;
+        res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
+        res.log_abs = lg + log(fabs(tot));
+        for (int e = 0; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
+    } else {
+        // Wc(<= budget) helper: sum of closed bucket sums with size <= budget
+        auto wc_upto = [&](int budget) {
+            double v = 0.0;
+            for (int s = 1; s <= budget && s <= K; ++s) {
+                int b = B(0, s);
+                if (b >= 0) v += bsum[b][0];
+            }
+            return v;
+        };
+        double xa[kMaxOpenOut], xb[kMaxOpenOut];
+        for (int i = 0; i < pa; ++i) xa[i] = vac[cr.vac_a + i];
+        for (int j = 0; j < pb; ++j) xb[j] = cr.vac_b >= 0 ? vac[cr.vac_b + j] : 1.0;
+        double VA[kMaxOpenOut], VB[kMaxOpenOut];
+        for (int i = 0; i < pa; ++i) {
+            double v = 0.0;
+            for (int s = 1; s <= K; ++s) {
+                int b = B(1, s);
+                if (b >= 0) v += bsum[b][i] * (1.0 + wc_upto(K - s));
+            }
+            VA[i] = v - psum[1][i];
+        }
+        for (int j = 0; j < pb; ++j) {
+            double v = 0.0;
+            for (int s = 1; s <= K; ++s) {
+                int b = B(2, s);
+                if (b >= 0) v += bsum[b][j] * (1.0 + wc_upto(K - s));
+            }
+            VB[j] = v - psum[2][j];
+        }
+        for (int i = 0; i < pa; ++i)
+            for (int j = 0; j < pb; ++j) {
+                const int e = i * pb + j;
+                double v = xa[i] * xb[j] * (1.0 + SC) + VA[i] * xb[j] + xa[i] * VB[j];
+                for (int s = 1; s <= K; ++s) {
+                    int b = B(3, s);
+                    if (b >= 0) v += bsum[b][e] * (1.0 + wc_upto(K - s));
+                }
+                v -= psum[3][e];
+                for (int s = 1; s <= K; ++s) {
+                    int b = B(1, s);
+                    if (b < 0) continue;
+                    for (int s2 = 1; s + s2 <= K; ++s2) {
+                        int b2 = B(2, s2);
+                        if (b2 >= 0) v += bsum[b][i] * bsum[b2][j];
+                    }
+                }
+                v -= psum[4][e];
+                res.open[e] = sign_bp * v;
+            }
+        for (int e = pa * pb; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
+        res.sign = sign_bp;
+        res.log_abs = lg;
+    }
+    out[net] = res;
+}
+
+}  // namespace
+
+hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
+    int n = b.n_sites > b.n_nets ? b.n_sites : b.n_nets;
+    hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, b.sites, b.n_sites, b.msg0, b.state,
+                       b.n_nets);
+    return hipGetLastError();
+}
+
+hipError_t launch_sweep(const DeviceBatch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_bp_sweep, dim3(b.n_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites, b.tiles,
+                       b.tile_sites, b.msg0, b.msg1, b.state);
+    return hipGetLastError();
+}
+
+hipError_t launch_finish(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
+    hipLaunchKernelGGL(k_bp_finish, dim3(1), dim3(1024), 0, s, b.state, b.n_nets, tol, max_iter, b.n_active);
+    return hipGetLastError();
+}
+
+hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s) {
+    if (b.n_bonds > 0)
+        hipLaunchKernelGGL(k_gauge, dim3((b.n_bonds + 127) / 128), dim3(128), 0, s, b.bonds, b.n_bonds, b.msg0,
+                           b.msg1, b.state, b.xg);
+    return hipGetLastError();
+}
+
+hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s) {
+    switch (b.precision) {
+        case 0:
+            hipLaunchKernelGGL(k_regauge<double>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
+                               b.xg, (double *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_regauge<float>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
+                               b.xg, (float *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+            break;
+        default:
+            hipLaunchKernelGGL(k_regauge<uint16_t>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
+                               b.xg, (uint16_t *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
+    if (!b.n_cblocks) return hipSuccess;
+    switch (b.precision) {
+        case 0:
+            hipLaunchKernelGGL(k_clusters<double>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
+                               b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout, b.sites,
+                               (const double *)b.slices, b.w);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_clusters<float>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
+                               b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout, b.sites,
+                               (const float *)b.slices, b.w);
+            break;
+        default:
+            hipLaunchKernelGGL(k_clusters<uint16_t>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s,
+                               b.classes, b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout,
+                               b.sites, (const uint16_t *)b.slices, b.w);
+            break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine, dim3(b.n_nets), dim3(kCbThreads), 0, s, b.crec, b.geos, b.buckets, b.pair_a,
+                       b.pair_b, b.pair_cats, b.w, b.site_log, b.site_sign, b.vac, b.state, b.results);
+    return hipGetLastError();
+}
+
+}  // namespace pne

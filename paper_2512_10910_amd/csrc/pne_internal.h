@@ -1,0 +1,153 @@
+// Internal types shared by the host runtime and the gfx950 kernels.
+#pragma once
+
+#include <cstdint>
+
+namespace pne {
+
+constexpr int kMaxRank = 8;    // leg slots per site
+constexpr int kMaxDim = 16;    // largest leg dimension
+constexpr int kMaxLab = 8;     // index labels touched by one contraction step
+constexpr int kMaxVerts = 16;  // sites in one cluster
+constexpr int kMaxOpenOut = 64;  // entries of an open-index output tensor
+
+// One site of one network in a batch (device table).
+struct SiteRec {
+    const double *t;      // input tensor, FP64, C order over slots
+    int64_t slice_off;    // element offset of the regauged slices in the slice arena
+    int32_t msg_off;      // offset of the site's incoming messages (slot-major)
+    int32_t xg_off;       // offset of the site's leg transforms (d*d per bond slot)
+    int32_t rank;
+    int32_t size;         // product of dims
+    int32_t net;          // network index in the batch
+    int32_t open_mask;    // bit l set when slot l is an open leg
+    int32_t vac_off;      // open sites: offset in the FP64 vacuum buffer, else -1
+    int32_t pad;
+    int32_t dim[kMaxRank];
+    int32_t stride[kMaxRank];
+    int32_t moff[kMaxRank];  // offset of slot l's incoming message relative to msg_off
+    int32_t dst[kMaxRank];   // absolute offset of the incoming message that slot l's
+                             // outgoing message becomes (partner slot, or itself if open)
+};
+
+// A BP tile: sites of one network sharing rank and leg dims.
+struct BpTile {
+    int32_t site_begin;   // index into the tile-site list
+    int32_t n_sites;
+    int32_t net;
+    int32_t rank;
+    int32_t size;         // tensor entries per site
+    int32_t n_os;         // outputs (sum of dims) per site
+    int32_t pad0, pad1;
+};
+
+// One bond of one network (device table for the gauge kernel).
+struct BondRec {
+    int32_t net;
+    int32_t dim;
+    int32_t a_off;   // incoming message at the bond's first site (absolute)
+    int32_t c_off;   // incoming message at the bond's second site (absolute)
+    int32_t xu_off;  // transform applied to the first site's slot
+    int32_t xv_off;  // transform applied to the second site's slot
+};
+
+// Per-network BP state.
+struct NetState {
+    int32_t active;
+    int32_t iters;
+    int32_t parity;     // buffer holding the latest messages
+    int32_t status;     // 0 ok, else a negative pne_status
+    unsigned long long res_bits;  // running max of the sweep residual (bits of a double >= 0)
+    double residual;
+    double log_bp;      // sum of vacuum log-magnitudes (+ open scales)
+    int32_t sign_bp;
+    int32_t converged;
+};
+
+// A contraction step of a cluster plan: absorb one site's slice into the
+// running frontier tensor F.  Output labels come first in F_next's C order.
+struct StepDesc {
+    int32_t vert;        // position of the absorbed site in the instance record
+    int32_t n_out;       // entries of F_next
+    int32_t n_sum;       // entries of the summed (shared) index space
+    int32_t n_ol;        // output labels
+    int32_t n_sl;        // summed labels
+    int32_t n_xl;        // legs of the absorbed slice
+    int32_t out_dim[kMaxLab];
+    int32_t out_fs[kMaxLab];   // stride in F of each output label (0 if new)
+    int32_t out_xl[kMaxLab];   // slice leg of each output label (-1 if from F)
+    int32_t sum_dim[kMaxLab];
+    int32_t sum_fs[kMaxLab];
+    int32_t sum_xl[kMaxLab];
+    int32_t x_excited[kMaxLab];  // 1 when the slice leg is an excited bond leg
+};
+
+// A class of clusters with the same contraction plan.
+struct ClassDesc {
+    int32_t step_begin;  // index into the step table
+    int32_t n_steps;
+    int32_t n_verts;
+    int32_t max_f;       // largest frontier (entries)
+    int32_t group;       // lanes per instance (power of two, <= 64)
+    int32_t out_size;    // entries of the result tensor (1 for closed clusters)
+    int32_t pad0, pad1;
+};
+
+// A block of cluster work: `count` consecutive instances of one class.
+struct ClusterBlock {
+    int32_t cls;
+    int32_t inst_begin;
+    int32_t count;
+    int32_t pad;
+};
+
+// Per-network combine description (geometry tables are shared).
+struct CombineRec {
+    int64_t w_base;        // start of the network's weights in the weight buffer
+    int32_t n_clusters;
+    int32_t pad0;
+    int32_t geo;           // geometry table index
+    int32_t site_begin;    // first global site of the network
+    int32_t n_sites;
+    int32_t vac_a, vac_b;  // vacuum offsets of the open sites (-1 if none)
+    int32_t pa, pb;        // open dims of A and B (1 if absent)
+    int32_t pad1, pad2;
+};
+
+// Per-network device result.
+struct NetResult {
+    double log_abs;
+    double log_bp;
+    double sum;            // closed networks: the retained-term sum S (Z = Z_BP (1+S))
+    int32_t sign;
+    int32_t status;
+    double open[kMaxOpenOut];
+};
+
+// Geometry-level combine tables.
+struct GeoRec {
+    int32_t K;
+    int32_t n_buckets;     // buckets of (type, size), contiguous cluster ranges
+    int32_t bucket_begin;  // index into the bucket table
+    int32_t pair_begin;    // index into the overlap-pair tables
+    int32_t n_pairs;
+    int32_t pair_cat_begin;  // categories of pairs (contiguous ranges)
+    int32_t n_pair_cats;
+    int32_t pad;
+};
+
+struct Bucket {
+    int32_t type;    // 0 closed, 1 touches A only, 2 touches B only, 3 touches both
+    int32_t size;    // cluster size (bonds)
+    int32_t begin;   // cluster range [begin, end) within the network
+    int32_t end;
+    int32_t w_begin; // weight offset of the first cluster (weights are contiguous)
+    int32_t osz;     // weight entries per cluster
+};
+
+struct PairCat {
+    int32_t t1, t2;  // types of the two clusters (t1 >= t2 after ordering)
+    int32_t begin, end;  // range in the pair table
+};
+
+}  // namespace pne

@@ -1,0 +1,824 @@
+// Host runtime behind the C ABI (pne.h): contexts, networks, batches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "geometry.h"
+#include "kernels.h"
+#include "pne.h"
+
+using namespace pne;
+
+struct PlanEntry {
+    std::shared_ptr<Geometry> geo;
+    std::map<int, std::shared_ptr<GeoPlan>> plans;  // by K
+};
+
+struct pne_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    size_t budget = 0;
+    size_t used = 0;
+    std::string err;
+    std::multimap<uint64_t, PlanEntry> cache;
+    std::mutex mu;
+};
+
+struct pne_network {
+    pne_ctx *ctx = nullptr;
+    std::shared_ptr<Geometry> geo;
+    std::vector<const double *> dptr;  // per site, device
+    double *owned = nullptr;
+    size_t owned_bytes = 0;
+};
+
+struct pne_batch {
+    pne_ctx *ctx = nullptr;
+    std::vector<pne_network *> nets;
+    pne_options opt{};
+    std::vector<std::shared_ptr<GeoPlan>> plans;  // per net
+    std::vector<int> site_base;                   // per net
+    std::vector<int64_t> w_base;                  // per net
+    std::vector<void *> allocs;
+    size_t bytes = 0;
+    DeviceBatch db;
+    int *h_active = nullptr;  // pinned
+    bool launched = false;
+    bool waited = false;
+    // per-kernel HIP-event timing (PNE_FLAG_PROFILE)
+    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    std::vector<hipEvent_t> ev_pool;
+    double kt_ms[KID_COUNT] = {0};
+    int64_t kt_n[KID_COUNT] = {0};
+    std::vector<NetResult> h_results;
+    std::vector<NetState> h_state;
+    int64_t msg_total = 0;
+    std::vector<int> msg_off;  // per global site
+    std::vector<int> moff;     // per global slot, relative
+};
+
+namespace {
+
+thread_local std::string g_tls_err;
+
+pne_status fail(pne_ctx *ctx, pne_status st, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    g_tls_err = msg;
+    return st;
+}
+
+pne_status hip_fail(pne_ctx *ctx, hipError_t e, const char *what) {
+    return fail(ctx, PNE_ERR_DEVICE, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+#define HIP_TRY(ctx, expr)                                   \
+    do {                                                     \
+        hipError_t e_ = (expr);                              \
+        if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
+    } while (0)
+
+std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> &g, int K, std::string *err,
+                                  std::shared_ptr<Geometry> *canon) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto range = ctx->cache.equal_range(g->hash);
+    PlanEntry *pe = nullptr;
+    for (auto it = range.first; it != range.second; ++it)
+        if (it->second.geo->same_as(*g)) {
+            pe = &it->second;
+            break;
+        }
+    if (!pe) {
+        auto it = ctx->cache.emplace(g->hash, PlanEntry{g, {}});
+        pe = &it->second;
+    }
+    if (canon) *canon = pe->geo;
+    auto f = pe->plans.find(K);
+    if (f != pe->plans.end()) return f->second;
+    auto p = build_plan(*pe->geo, K, err);
+    if (p) pe->plans[K] = p;
+    return p;
+}
+
+template <class T>
+pne_status upload(pne_batch *b, const std::vector<T> &v, const T **dst) {
+    if (v.empty()) {
+        *dst = nullptr;
+        return PNE_OK;
+    }
+    void *p = nullptr;
+    size_t n = v.size() * sizeof(T);
+    hipError_t e = hipMalloc(&p, n);
+    if (e != hipSuccess) return fail(b->ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    b->allocs.push_back(p);
+    b->bytes += n;
+    e = hipMemcpyAsync(p, v.data(), n, hipMemcpyHostToDevice, b->ctx->stream);
+    if (e != hipSuccess) return hip_fail(b->ctx, e, "hipMemcpyAsync");
+    *dst = (const T *)p;
+    return PNE_OK;
+}
+
+pne_status alloc(pne_batch *b, size_t n, void **p) {
+    *p = nullptr;
+    if (n == 0) n = 8;
+    hipError_t e = hipMalloc(p, n);
+    if (e != hipSuccess) return fail(b->ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    b->allocs.push_back(*p);
+    b->bytes += n;
+    return PNE_OK;
+}
+
+hipEvent_t take_event(pne_batch *b) {
+    if (!b->ev_pool.empty()) {
+        hipEvent_t e = b->ev_pool.back();
+        b->ev_pool.pop_back();
+        return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+}
+
+// Launch `fn` on the batch stream, bracketed by events when profiling.
+template <class F>
+hipError_t timed(pne_batch *b, int kid, F &&fn) {
+    const bool prof = (b->opt.flags & PNE_FLAG_PROFILE) != 0;
+    hipStream_t s = b->ctx->stream;
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (prof) {
+        e0 = take_event(b);
+        e1 = take_event(b);
+        hipError_t e = hipEventRecord(e0, s);
+        if (e != hipSuccess) return e;
+    }
+    hipError_t err = fn(s);
+    if (err != hipSuccess) return err;
+    if (prof) {
+        err = hipEventRecord(e1, s);
+        b->ev_used.push_back({kid, {e0, e1}});
+    }
+    return err;
+}
+
+void collect_times(pne_batch *b) {
+    for (auto &u : b->ev_used) {
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, u.second.first, u.second.second) == hipSuccess) {
+            b->kt_ms[u.first] += ms;
+            b->kt_n[u.first] += 1;
+        }
+        b->ev_pool.push_back(u.second.first);
+        b->ev_pool.push_back(u.second.second);
+    }
+    b->ev_used.clear();
+}
+
+void free_batch(pne_batch *b) {
+    for (auto &u : b->ev_used) {
+        (void)hipEventDestroy(u.second.first);
+        (void)hipEventDestroy(u.second.second);
+    }
+    b->ev_used.clear();
+    for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
+    b->ev_pool.clear();
+    for (void *p : b->allocs) (void)hipFree(p);
+    b->allocs.clear();
+    if (b->h_active) (void)hipHostFree(b->h_active);
+    b->h_active = nullptr;
+    if (b->ctx) b->ctx->used -= std::min(b->ctx->used, b->bytes);
+}
+
+}  // namespace
+
+extern "C" {
+
+pne_status pne_options_default(pne_options *opt) {
+    if (!opt) return PNE_ERR_INVALID_ARG;
+    std::memset(opt, 0, sizeof *opt);
+    opt->max_excited = 4;
+    opt->precision = PNE_FP64;
+    opt->bp_tol = 1e-13;
+    opt->bp_max_iter = 500;
+    opt->bp_check_every = 0;
+    return PNE_OK;
+}
+
+const char *pne_last_error(const pne_ctx *ctx) {
+    if (ctx) return ctx->err.c_str();
+    return g_tls_err.c_str();
+}
+
+pne_status pne_ctx_create(int device, size_t budget, void *stream, pne_ctx **out) {
+    if (!out) return fail(nullptr, PNE_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    hipError_t e = hipGetDeviceCount(&n);
+    if (e != hipSuccess || n <= 0) return fail(nullptr, PNE_ERR_DEVICE, "no HIP device available");
+    if (device < 0 || device >= n) return fail(nullptr, PNE_ERR_INVALID_ARG, "device index out of range");
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return fail(nullptr, PNE_ERR_DEVICE, "hipSetDevice failed");
+    auto *c = new pne_ctx();
+    c->device = device;
+    c->budget = budget;
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            delete c;
+            return fail(nullptr, PNE_ERR_DEVICE, "hipStreamCreate failed");
+        }
+        c->own_stream = true;
+    }
+    *out = c;
+    return PNE_OK;
+}
+
+pne_status pne_ctx_destroy(pne_ctx *ctx) {
+    if (!ctx) return PNE_ERR_INVALID_ARG;
+    if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    delete ctx;
+    return PNE_OK;
+}
+
+pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on_device, pne_network **out) {
+    if (!ctx || !desc || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "null argument");
+    *out = nullptr;
+    auto g = std::make_shared<Geometry>();
+    std::string why = build_geometry(desc, g.get());
+    if (!why.empty()) return fail(ctx, PNE_ERR_INVALID_ARG, why);
+    if (!desc->site_data) return fail(ctx, PNE_ERR_INVALID_ARG, "site_data is NULL");
+    for (int s = 0; s < g->n_sites; ++s)
+        if (!desc->site_data[s]) return fail(ctx, PNE_ERR_INVALID_ARG, "site tensor pointer is NULL");
+    auto *net = new pne_network();
+    net->ctx = ctx;
+    net->geo = g;
+    net->dptr.resize(g->n_sites);
+    std::vector<size_t> sz(g->n_sites);
+    size_t total = 0;
+    for (int s = 0; s < g->n_sites; ++s) {
+        size_t n = 1;
+        for (int l = 0; l < g->rank[s]; ++l) n *= (size_t)g->dim[g->slot(s, l)];
+        sz[s] = n;
+        total += n;
+    }
+    if (on_device) {
+        for (int s = 0; s < g->n_sites; ++s) net->dptr[s] = desc->site_data[s];
+    } else {
+        // reject non-finite inputs before they reach the device
+        for (int s = 0; s < g->n_sites; ++s)
+            for (size_t i = 0; i < sz[s]; ++i)
+                if (!std::isfinite(desc->site_data[s][i])) {
+                    delete net;
+                    return fail(ctx, PNE_ERR_INVALID_ARG, "non-finite tensor entry");
+                }
+        size_t bytes = total * sizeof(double);
+        if (ctx->budget && ctx->used + bytes > ctx->budget) {
+            delete net;
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
+        }
+        void *p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) {
+            delete net;
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
+        }
+        net->owned = (double *)p;
+        net->owned_bytes = bytes;
+        ctx->used += bytes;
+        std::vector<double> host(total);
+        size_t off = 0;
+        for (int s = 0; s < g->n_sites; ++s) {
+            std::memcpy(host.data() + off, desc->site_data[s], sz[s] * sizeof(double));
+            net->dptr[s] = net->owned + off;
+            off += sz[s];
+        }
+        hipError_t e = hipMemcpyAsync(p, host.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            ctx->used -= bytes;
+            delete net;
+            return hip_fail(ctx, e, "tensor upload");
+        }
+    }
+    *out = net;
+    return PNE_OK;
+}
+
+pne_status pne_network_destroy(pne_network *net) {
+    if (!net) return PNE_ERR_INVALID_ARG;
+    if (net->owned) {
+        (void)hipFree(net->owned);
+        net->ctx->used -= std::min(net->ctx->used, net->owned_bytes);
+    }
+    delete net;
+    return PNE_OK;
+}
+
+pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
+                            pne_batch **out) {
+    if (!ctx || !nets || n <= 0 || !opt || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "bad batch arguments");
+    *out = nullptr;
+    if (opt->max_excited < 0 || opt->max_excited > 32) return fail(ctx, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
+    if (opt->precision < 0 || opt->precision > 2) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown precision");
+    if (!(opt->bp_tol >= 0.0) || opt->bp_max_iter < 1) return fail(ctx, PNE_ERR_INVALID_ARG, "bad BP options");
+    for (int i = 0; i < n; ++i)
+        if (!nets[i] || nets[i]->ctx != ctx) return fail(ctx, PNE_ERR_INVALID_ARG, "network from another context");
+
+    auto b = std::make_unique<pne_batch>();
+    b->ctx = ctx;
+    b->nets.assign(nets, nets + n);
+    b->opt = *opt;
+    const int K = opt->max_excited;
+    const int prec = opt->precision;
+    const size_t esz = prec == PNE_FP64 ? 8 : prec == PNE_FP32 ? 4 : 2;
+
+    // plans
+    for (int i = 0; i < n; ++i) {
+        std::string err;
+        std::shared_ptr<Geometry> canon;
+        auto p = get_plan(ctx, nets[i]->geo, K, &err, &canon);
+        if (!p) {
+            bool unsup = err.rfind("unsupported", 0) == 0;
+            return fail(ctx, unsup ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
+        }
+        if ((int)p->buckets.size() > 64) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: too many term buckets");
+        b->plans.push_back(p);
+    }
+
+    // sites, messages, transforms, slices
+    std::vector<SiteRec> sites;
+    std::vector<BondRec> bonds;
+    std::vector<int> net_of_site;
+    int64_t msg = 0, xg = 0, sl = 0, vac = 0;
+    size_t max_size = 1;
+    b->site_base.resize(n);
+    for (int i = 0; i < n; ++i) {
+        const Geometry &g = *nets[i]->geo;
+        b->site_base[i] = (int)sites.size();
+        for (int s = 0; s < g.n_sites; ++s) {
+            SiteRec r;
+            std::memset(&r, 0, sizeof r);
+            r.t = nets[i]->dptr[s];
+            r.net = i;
+            r.rank = g.rank[s];
+            r.msg_off = (int)msg;
+            r.xg_off = (int)xg;
+            r.slice_off = sl;
+            r.vac_off = -1;
+            int size = 1, mo = 0, xo = 0, omask = 0, nopen = 1;
+            for (int l = r.rank - 1; l >= 0; --l) {
+                r.stride[l] = size;
+                size *= g.dim[g.slot(s, l)];
+            }
+            for (int l = 0; l < r.rank; ++l) {
+                int d = g.dim[g.slot(s, l)];
+                r.dim[l] = d;
+                r.moff[l] = mo;
+                mo += d;
+                xo += d * d;
+                if (g.is_open[g.slot(s, l)]) {
+                    omask |= 1 << l;
+                    nopen *= d;
+                }
+            }
+            r.size = size;
+            r.open_mask = omask;
+            if (omask) {
+                r.vac_off = (int)vac;
+                vac += nopen;
+            }
+            max_size = std::max(max_size, (size_t)size);
+            msg += mo;
+            xg += xo;
+            sl += size;
+            sites.push_back(r);
+            net_of_site.push_back(i);
+        }
+    }
+    if (msg > INT32_MAX || xg > INT32_MAX) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: batch too large");
+    // partner destinations
+    for (int i = 0; i < n; ++i) {
+        const Geometry &g = *nets[i]->geo;
+        int base = b->site_base[i];
+        for (int s = 0; s < g.n_sites; ++s) {
+            SiteRec &r = sites[base + s];
+            for (int l = 0; l < r.rank; ++l) {
+                int p = g.partner[g.slot(s, l)];
+                int ps = (int)(std::upper_bound(g.slot_base.begin(), g.slot_base.end(), p) - g.slot_base.begin()) - 1;
+                int pl = p - g.slot_base[ps];
+                r.dst[l] = sites[base + ps].msg_off + sites[base + ps].moff[pl];
+            }
+        }
+        for (int bb = 0; bb < g.n_bonds; ++bb) {
+            const SiteRec &ru = sites[base + g.bu[bb]];
+            const SiteRec &rv = sites[base + g.bv[bb]];
+            BondRec br;
+            br.net = i;
+            br.dim = ru.dim[g.bul[bb]];
+            br.a_off = ru.msg_off + ru.moff[g.bul[bb]];
+            br.c_off = rv.msg_off + rv.moff[g.bvl[bb]];
+            int xu = 0, xv = 0;
+            for (int l = 0; l < g.bul[bb]; ++l) xu += ru.dim[l] * ru.dim[l];
+            for (int l = 0; l < g.bvl[bb]; ++l) xv += rv.dim[l] * rv.dim[l];
+            br.xu_off = ru.xg_off + xu;
+            br.xv_off = rv.xg_off + xv;
+            bonds.push_back(br);
+        }
+    }
+    b->msg_total = msg;
+
+    // BP tiles: per network, runs of sites with identical leg dims
+    std::vector<BpTile> tiles;
+    std::vector<int> tile_sites;
+    const size_t bp_budget = 48 * 1024 / 8;  // doubles of dynamic LDS per tile
+    size_t bp_lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const Geometry &g = *nets[i]->geo;
+        int base = b->site_base[i];
+        std::map<std::vector<int>, std::vector<int>> groups;
+        for (int s = 0; s < g.n_sites; ++s) {
+            std::vector<int> key(g.dim.begin() + g.slot_base[s], g.dim.begin() + g.slot_base[s + 1]);
+            groups[key].push_back(base + s);
+        }
+        for (auto &kv : groups) {
+            const SiteRec &r0 = sites[kv.second[0]];
+            int nos = 0;
+            for (int l = 0; l < r0.rank; ++l) nos += r0.dim[l];
+            size_t per = (size_t)r0.size + 2 * (size_t)nos;
+            int cap = (int)std::max<size_t>(1, std::min<size_t>(64, bp_budget / per));
+            cap = std::min(cap, std::max(1, 256 / nos));
+            if (per > 160 * 1024 / 8 - 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
+            for (size_t k = 0; k < kv.second.size(); k += cap) {
+                BpTile t;
+                std::memset(&t, 0, sizeof t);
+                t.site_begin = (int)tile_sites.size();
+                t.n_sites = (int)std::min<size_t>(cap, kv.second.size() - k);
+                t.net = i;
+                t.rank = r0.rank;
+                t.size = r0.size;
+                t.n_os = nos;
+                for (int j = 0; j < t.n_sites; ++j) tile_sites.push_back(kv.second[k + j]);
+                bp_lds = std::max(bp_lds, (size_t)t.n_sites * per * 8);
+                tiles.push_back(t);
+            }
+        }
+    }
+
+    // cluster tables: classes shared per distinct plan, instances per class
+    std::vector<ClassDesc> classes;
+    std::vector<StepDesc> steps;
+    std::vector<ClusterBlock> cblocks;
+    std::vector<int> inst_site;
+    std::vector<uint32_t> inst_slots;
+    std::vector<int64_t> inst_rec, inst_wout;
+    std::vector<CombineRec> crec(n);
+    std::vector<GeoRec> geos;
+    std::vector<Bucket> buckets;
+    std::vector<int> pair_a, pair_b;
+    std::vector<PairCat> pair_cats;
+    std::map<const GeoPlan *, int> plan_index;  // -> first class id
+    std::map<const GeoPlan *, int> geo_index;
+    int64_t wtot = 0;
+    b->w_base.resize(n);
+    size_t cl_lds = 0;
+    for (int i = 0; i < n; ++i) {
+        const GeoPlan *p = b->plans[i].get();
+        b->w_base[i] = wtot;
+        wtot += p->w_total;
+        if (!plan_index.count(p)) {
+            plan_index[p] = (int)classes.size();
+            for (const ClassDesc &cd0 : p->classes) {
+                ClassDesc cd = cd0;
+                cd.step_begin += (int)steps.size();
+                classes.push_back(cd);
+                const size_t asz = prec == PNE_FP64 ? 8 : 4;
+                cl_lds = std::max(cl_lds, (size_t)(256 / cd.group) * 2 * (size_t)cd.max_f * asz);
+            }
+            steps.insert(steps.end(), p->steps.begin(), p->steps.end());
+            GeoRec gr;
+            std::memset(&gr, 0, sizeof gr);
+            gr.K = K;
+            gr.n_buckets = (int)p->buckets.size();
+            gr.bucket_begin = (int)buckets.size();
+            buckets.insert(buckets.end(), p->buckets.begin(), p->buckets.end());
+            gr.pair_begin = (int)pair_a.size();
+            gr.n_pairs = (int)p->pair_a.size();
+            pair_a.insert(pair_a.end(), p->pair_a.begin(), p->pair_a.end());
+            pair_b.insert(pair_b.end(), p->pair_b.begin(), p->pair_b.end());
+            gr.pair_cat_begin = (int)pair_cats.size();
+            gr.n_pair_cats = (int)p->pair_cats.size();
+            pair_cats.insert(pair_cats.end(), p->pair_cats.begin(), p->pair_cats.end());
+            geo_index[p] = (int)geos.size();
+            geos.push_back(gr);
+        }
+        CombineRec &cr = crec[i];
+        std::memset(&cr, 0, sizeof cr);
+        cr.w_base = b->w_base[i];
+        cr.n_clusters = p->clusters.count();
+        cr.geo = geo_index[p];
+        cr.site_begin = b->site_base[i];
+        cr.n_sites = nets[i]->geo->n_sites;
+        cr.vac_a = p->open_a >= 0 ? sites[b->site_base[i] + p->open_a].vac_off : -1;
+        cr.vac_b = p->open_b >= 0 ? sites[b->site_base[i] + p->open_b].vac_off : -1;
+        cr.pa = p->pa;
+        cr.pb = p->pb;
+    }
+    if (cl_lds > 64 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: cluster frontier too large for LDS");
+    // instances grouped by batch class across networks
+    std::vector<std::vector<std::pair<int, int>>> per_class(classes.size());  // (net, local instance)
+    for (int i = 0; i < n; ++i) {
+        const GeoPlan *p = b->plans[i].get();
+        int c0 = plan_index[p];
+        for (size_t c = 0; c < p->classes.size(); ++c)
+            for (size_t k = 0; k < p->inst_cluster[c].size(); ++k) per_class[c0 + c].push_back({i, (int)k});
+    }
+    for (size_t cid = 0; cid < classes.size(); ++cid) {
+        const ClassDesc &cd = classes[cid];
+        const int ipb = 256 / cd.group;
+        int64_t first = (int64_t)inst_wout.size();
+        for (auto &pr : per_class[cid]) {
+            int i = pr.first, k = pr.second;
+            const GeoPlan *p = b->plans[i].get();
+            int lc = (int)cid - plan_index[p];
+            int cluster = p->inst_cluster[lc][k];
+            inst_rec.push_back((int64_t)inst_site.size());
+            for (int v = 0; v < cd.n_verts; ++v) {
+                inst_site.push_back(b->site_base[i] + p->inst_site[lc][(size_t)k * cd.n_verts + v]);
+                inst_slots.push_back(p->inst_slots[lc][(size_t)k * cd.n_verts + v]);
+            }
+            inst_wout.push_back(b->w_base[i] + p->w_off[cluster]);
+        }
+        int64_t cnt = (int64_t)inst_wout.size() - first;
+        for (int64_t k = 0; k < cnt; k += ipb) {
+            ClusterBlock cb;
+            cb.cls = (int)cid;
+            cb.inst_begin = (int)(first + k);
+            cb.count = (int)std::min<int64_t>(ipb, cnt - k);
+            cb.pad = 0;
+            cblocks.push_back(cb);
+        }
+    }
+
+    // device allocation
+    size_t regauge_lds = 2 * max_size * 8;
+    if (regauge_lds > 150 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
+    pne_status st;
+    DeviceBatch &db = b->db;
+#define UP(vec, field)                                   \
+    st = upload(b.get(), vec, &db.field);                \
+    if (st != PNE_OK) { free_batch(b.get()); return st; }
+    UP(sites, sites);
+    UP(tiles, tiles);
+    UP(tile_sites, tile_sites);
+    UP(bonds, bonds);
+    UP(classes, classes);
+    UP(steps, steps);
+    UP(cblocks, cblocks);
+    UP(inst_site, inst_site);
+    UP(inst_slots, inst_slots);
+    UP(inst_rec, inst_rec);
+    UP(inst_wout, inst_wout);
+    UP(crec, crec);
+    UP(geos, geos);
+    UP(buckets, buckets);
+    UP(pair_a, pair_a);
+    UP(pair_b, pair_b);
+    UP(pair_cats, pair_cats);
+#undef UP
+    db.n_sites = (int)sites.size();
+    db.n_tiles = (int)tiles.size();
+    db.n_bonds = (int)bonds.size();
+    db.n_nets = n;
+    db.n_cblocks = (int)cblocks.size();
+    db.bp_lds = bp_lds;
+    db.regauge_lds = regauge_lds;
+    db.cluster_lds = cl_lds;
+    db.precision = prec;
+    void *p;
+#define AL(bytes, field, type)                                             \
+    st = alloc(b.get(), (bytes), &p);                                      \
+    if (st != PNE_OK) { free_batch(b.get()); return st; }                  \
+    db.field = (type)p;
+    AL(sizeof(NetState) * n, state, NetState *);
+    AL(sizeof(int), n_active, int *);
+    AL(sizeof(double) * msg, msg0, double *);
+    AL(sizeof(double) * msg, msg1, double *);
+    AL(sizeof(double) * std::max<int64_t>(xg, 1), xg, double *);
+    AL(esz * std::max<int64_t>(sl, 1), slices, void *);
+    AL(sizeof(double) * sites.size(), site_log, double *);
+    AL(sizeof(int) * sites.size(), site_sign, int *);
+    AL(sizeof(double) * std::max<int64_t>(vac, 1), vac, double *);
+    AL(sizeof(double) * std::max<int64_t>(wtot, 1), w, double *);
+    AL(sizeof(NetResult) * n, results, NetResult *);
+#undef AL
+    if (ctx->budget && ctx->used + b->bytes > ctx->budget) {
+        free_batch(b.get());
+        return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
+    }
+    ctx->used += b->bytes;
+    if (hipHostMalloc((void **)&b->h_active, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+        free_batch(b.get());
+        return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+    }
+    hipError_t e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) {
+        free_batch(b.get());
+        return hip_fail(ctx, e, "batch upload");
+    }
+    b->msg_off.resize(sites.size());
+    for (size_t s = 0; s < sites.size(); ++s) b->msg_off[s] = sites[s].msg_off;
+    *out = b.release();
+    return PNE_OK;
+}
+
+pne_status pne_batch_launch(pne_batch *b) {
+    if (!b) return PNE_ERR_INVALID_ARG;
+    pne_ctx *ctx = b->ctx;
+    hipStream_t s = ctx->stream;
+    const DeviceBatch &db = b->db;
+    HIP_TRY(ctx, timed(b, KID_INIT, [&](hipStream_t st) { return launch_init(db, st); }));
+    const int max_iter = b->opt.bp_max_iter;
+    const double tol = b->opt.bp_tol;
+    int done = 0;
+    int chunk = b->opt.bp_check_every > 0 ? b->opt.bp_check_every : 4;
+    while (done < max_iter) {
+        int k = std::min(chunk, max_iter - done);
+        for (int j = 0; j < k; ++j) {
+            HIP_TRY(ctx, timed(b, KID_SWEEP, [&](hipStream_t st) { return launch_sweep(db, st); }));
+            HIP_TRY(ctx, timed(b, KID_FINISH, [&](hipStream_t st) { return launch_finish(db, tol, max_iter, st); }));
+        }
+        done += k;
+        HIP_TRY(ctx, hipMemcpyAsync(b->h_active, b->db.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+        HIP_TRY(ctx, hipStreamSynchronize(s));
+        if (*b->h_active == 0) break;
+        if (b->opt.bp_check_every <= 0) chunk = std::min(chunk * 2, 16);
+    }
+    HIP_TRY(ctx, timed(b, KID_GAUGE, [&](hipStream_t st) { return launch_gauge(db, st); }));
+    HIP_TRY(ctx, timed(b, KID_REGAUGE, [&](hipStream_t st) { return launch_regauge(db, st); }));
+    HIP_TRY(ctx, timed(b, KID_CLUSTERS, [&](hipStream_t st) { return launch_clusters(db, st); }));
+    HIP_TRY(ctx, timed(b, KID_COMBINE, [&](hipStream_t st) { return launch_combine(db, st); }));
+    b->launched = true;
+    b->waited = false;
+    return PNE_OK;
+}
+
+pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
+    if (!b || !b->launched) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "batch not launched");
+    pne_ctx *ctx = b->ctx;
+    const int n = (int)b->nets.size();
+    b->h_results.resize(n);
+    b->h_state.resize(n);
+    HIP_TRY(ctx, hipMemcpyAsync(b->h_results.data(), b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipMemcpyAsync(b->h_state.data(), b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost,
+                                ctx->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    collect_times(b);
+    b->waited = true;
+    if (!results) return PNE_OK;
+    pne_status worst = PNE_OK;
+    for (int i = 0; i < n; ++i) {
+        const NetResult &r = b->h_results[i];
+        const NetState &s = b->h_state[i];
+        const GeoPlan &p = *b->plans[i];
+        pne_result &o = results[i];
+        double *ov = o.open_values;
+        int64_t cap = o.open_capacity;
+        o.bp_iters = s.iters;
+        o.bp_residual = s.residual;
+        o.n_cluster_terms = p.clusters.count();
+        o.n_config_terms = p.n_configs;
+        o.log_abs = r.log_abs;
+        o.log_abs_bp = r.log_bp;
+        o.sign = r.sign;
+        o.n_open_values = 0;
+        int st = s.status < 0 ? s.status : (s.converged ? PNE_OK : PNE_WARN_BP_NOT_CONVERGED);
+        if (st >= 0 && !std::isfinite(r.log_abs)) st = PNE_ERR_SINGULAR;
+        if (st >= 0 && p.open_a >= 0) {
+            int m = p.pa * p.pb;
+            if (!ov || cap < m) {
+                st = PNE_ERR_INVALID_ARG;
+            } else {
+                for (int e = 0; e < m; ++e) ov[e] = r.open[e];
+                o.n_open_values = m;
+            }
+        }
+        o.status = st;
+        if (st < 0 && (worst >= 0 || st < worst)) worst = (pne_status)st;
+        else if (st > 0 && worst == PNE_OK) worst = (pne_status)st;
+    }
+    if (worst < 0) fail(ctx, worst, "one or more networks failed (see per-result status)");
+    return worst;
+}
+
+pne_status pne_batch_run(pne_batch *b, pne_result *results) {
+    pne_status s = pne_batch_launch(b);
+    if (s != PNE_OK) return s;
+    return pne_batch_wait(b, results);
+}
+
+pne_status pne_batch_destroy(pne_batch *b) {
+    if (!b) return PNE_ERR_INVALID_ARG;
+    if (b->ctx) (void)hipStreamSynchronize(b->ctx->stream);
+    free_batch(b);
+    delete b;
+    return PNE_OK;
+}
+
+pne_status pne_contract_batch(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
+                              pne_result *results) {
+    pne_batch *b = nullptr;
+    pne_status s = pne_batch_create(ctx, nets, n, opt, &b);
+    if (s != PNE_OK) return s;
+    s = pne_batch_run(b, results);
+    pne_batch_destroy(b);
+    return s;
+}
+
+pne_status pne_contract(pne_ctx *ctx, pne_network *net, const pne_options *opt, pne_result *res) {
+    return pne_contract_batch(ctx, &net, 1, opt, res);
+}
+
+pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64_t *n_clusters, int64_t *n_entries,
+                                  int32_t *sizes, int32_t *bonds) {
+    if (!desc || !n_clusters || !n_entries) return fail(nullptr, PNE_ERR_INVALID_ARG, "null argument");
+    Geometry g;
+    std::string why = build_geometry(desc, &g);
+    if (!why.empty()) return fail(nullptr, PNE_ERR_INVALID_ARG, why);
+    std::string err;
+    auto p = build_plan(g, K, &err);
+    if (!p) return fail(nullptr, err.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
+    const ClusterList &cl = p->clusters;
+    if (bonds) {
+        if (*n_clusters < cl.count() || *n_entries < (int64_t)cl.bonds.size())
+            return fail(nullptr, PNE_ERR_INVALID_ARG, "output buffers too small");
+        for (int c = 0; c < cl.count(); ++c) sizes[c] = cl.off[c + 1] - cl.off[c];
+        std::memcpy(bonds, cl.bonds.data(), cl.bonds.size() * sizeof(int32_t));
+    }
+    *n_clusters = cl.count();
+    *n_entries = (int64_t)cl.bonds.size();
+    return PNE_OK;
+}
+
+pne_status pne_batch_kernel_times(pne_batch *b, double *ms_total, int64_t *launches, int32_t n, int32_t reset) {
+    if (!b || !ms_total || !launches || n < 0) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
+    for (int k = 0; k < n; ++k) {
+        ms_total[k] = k < KID_COUNT ? b->kt_ms[k] : 0.0;
+        launches[k] = k < KID_COUNT ? b->kt_n[k] : 0;
+    }
+    if (reset)
+        for (int k = 0; k < KID_COUNT; ++k) {
+            b->kt_ms[k] = 0.0;
+            b->kt_n[k] = 0;
+        }
+    return PNE_OK;
+}
+
+pne_status pne_batch_messages(pne_batch *b, int32_t i, double *out, int64_t capacity) {
+    if (!b || !b->waited || i < 0 || i >= (int)b->nets.size() || !out)
+        return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
+    const Geometry &g = *b->nets[i]->geo;
+    int64_t need = 0;
+    for (int bb = 0; bb < g.n_bonds; ++bb) need += 2 * g.dim[g.slot(g.bu[bb], g.bul[bb])];
+    if (capacity < need) return fail(b->ctx, PNE_ERR_INVALID_ARG, "capacity too small");
+    const double *src = b->h_state[i].parity ? b->db.msg1 : b->db.msg0;
+    std::vector<double> host(b->msg_total);
+    HIP_TRY(b->ctx, hipMemcpy(host.data(), src, sizeof(double) * b->msg_total, hipMemcpyDeviceToHost));
+    int base = b->site_base[i];
+    int64_t o = 0;
+    for (int bb = 0; bb < g.n_bonds; ++bb) {
+        int d = g.dim[g.slot(g.bu[bb], g.bul[bb])];
+        int au = b->msg_off[base + g.bu[bb]];
+        for (int l = 0; l < g.bul[bb]; ++l) au += g.dim[g.slot(g.bu[bb], l)];
+        int cv = b->msg_off[base + g.bv[bb]];
+        for (int l = 0; l < g.bvl[bb]; ++l) cv += g.dim[g.slot(g.bv[bb], l)];
+        for (int k = 0; k < d; ++k) out[o++] = host[au + k];
+        for (int k = 0; k < d; ++k) out[o++] = host[cv + k];
+    }
+    return PNE_OK;
+}
+
+pne_status pne_batch_cluster_weights(pne_batch *b, int32_t i, double *out, int64_t capacity, int64_t *n_values,
+                                     int64_t *offsets) {
+    if (!b || !b->waited || i < 0 || i >= (int)b->nets.size() || !n_values)
+        return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
+    const GeoPlan &p = *b->plans[i];
+    *n_values = p.w_total;
+    if (!out) return PNE_OK;
+    if (capacity < p.w_total) return fail(b->ctx, PNE_ERR_INVALID_ARG, "capacity too small");
+    if (p.w_total)
+        HIP_TRY(b->ctx, hipMemcpy(out, b->db.w + b->w_base[i], sizeof(double) * p.w_total, hipMemcpyDeviceToHost));
+    if (offsets)
+        for (int c = 0; c < p.clusters.count(); ++c) offsets[c] = p.w_off[c];
+    return PNE_OK;
+}
+
+}  // extern "C"

