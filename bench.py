@@ -60,6 +60,7 @@ def main():
     ap.add_argument("--check", type=int, default=2, help="networks per D checked against the oracle")
     ap.add_argument("--cpu-sample", type=int, default=6, help="networks timed on the CPU oracle (0: skip)")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
+    ap.add_argument("--no-events", action="store_true", help="time without per-kernel HIP events")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -84,7 +85,7 @@ def main():
     print(f"bench: built {len(nets_in)} networks in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
     ctx = pne.Context(0)
     nets = [ctx.network(n) for n in nets_in]
-    batch = ctx.batch(nets, K=args.K, precision=args.precision, profile=True)
+    batch = ctx.batch(nets, K=args.K, precision=args.precision, profile=not args.no_events)
     print(f"bench: prepared batch in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):

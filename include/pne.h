@@ -52,6 +52,7 @@ typedef enum {
 
 /* pne_options.flags bits */
 #define PNE_FLAG_PROFILE 1u /* time every kernel launch with HIP events on the context stream */
+#define PNE_FLAG_NO_PERSISTENT 2u /* sweep every network launch by launch (no persistent BP kernel) */
 
 /* Precision of the excited slices and the cluster (term) contractions.  BP,
  * the bond gauge, vacuum log-norms and the cross-term sum are FP64 always. */
@@ -160,8 +161,8 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
 
 /* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
  * measured with HIP events recorded on the context stream around each launch.
- * Index k: 0 init, 1 BP sweep, 2 sweep bookkeeping, 3 bond gauge, 4 regauge /
- * slices, 5 cluster contraction, 6 combine.  Writes n entries; reset != 0
+ * Index k: 0 init, 1 BP sweep (per-launch), 2 BP close, 3 persistent BP,
+ * 4 bond gauge, 5 regauge / slices, 6 cluster contraction, 7 combine.  Writes n entries; reset != 0
  * clears the accumulators afterwards. */
 pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *launches, int32_t n,
                                   int32_t reset);

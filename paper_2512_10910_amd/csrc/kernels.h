@@ -12,15 +12,18 @@ struct DeviceBatch {
     // tables
     const SiteRec *sites = nullptr;
     int n_sites = 0;
-    const BpTile *tiles = nullptr;
+    const BpTile *tiles = nullptr;      // tiles swept by the per-sweep kernel
     int n_tiles = 0;
+    const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
+    const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel
+    int n_fused = 0;
+    size_t fused_lds = 0;
     const int *tile_sites = nullptr;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
     const BondRec *bonds = nullptr;
     int n_bonds = 0;
     NetState *state = nullptr;
     int n_nets = 0;
-    int *n_active = nullptr;
     // buffers
     double *msg0 = nullptr, *msg1 = nullptr;
     double *xg = nullptr;
@@ -51,11 +54,20 @@ struct DeviceBatch {
 };
 
 // kernel identifiers for per-kernel timing
-enum KernelId { KID_INIT = 0, KID_SWEEP, KID_FINISH, KID_GAUGE, KID_REGAUGE, KID_CLUSTERS, KID_COMBINE, KID_COUNT };
+enum KernelId { KID_INIT = 0, KID_SWEEP, KID_CLOSE, KID_FUSED, KID_GAUGE, KID_REGAUGE, KID_CLUSTERS, KID_COMBINE, KID_COUNT };
+
+// threads per BP tile and dynamic LDS (doubles) of one BP tile
+int bp_tile_threads();
+// sites per tile on the register path for uniform leg dimension D and rank R (0: LDS path)
+int bp_reg_sites_per_tile(int D, int R);
+size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int max_dim);
 
 hipError_t launch_init(const DeviceBatch &b, hipStream_t s);
-hipError_t launch_sweep(const DeviceBatch &b, hipStream_t s);
-hipError_t launch_finish(const DeviceBatch &b, double tol, int max_iter, hipStream_t s);
+hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s);
+hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s);
+hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s);
+// largest tile (sites) the persistent kernel accepts
+int bp_fused_tile_sites();
 hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s);

@@ -1,9 +1,6 @@
 // gfx950 kernels of the partitioned network expansion hot path.
 //
-//   k_init      uniform start messages (1/sqrt(d) on every directed message)
-//   k_bp_sweep  one Jacobi BP sweep over LDS-staged tiles of same-shape sites
-//               (Sec. II.B: fixed-point messages; Sec. III.D: open legs reflect)
-//   k_bp_finish per-network sweep bookkeeping and convergence test
+//   (BP sweeps live in bp.hip)
 //   k_gauge     per bond: rank-1 projector from the two messages in the
 //               symmetrising gauge of Appendix B (P = e0 e0^T, Q = the rest)
 //   k_regauge   per site: apply the bond gauges, split off the vacuum factor,
@@ -23,7 +20,6 @@ namespace pne {
 
 namespace {
 
-constexpr int kBpThreads = 256;
 constexpr int kRgThreads = 128;
 constexpr int kClThreads = 256;
 constexpr int kCbThreads = 256;
@@ -64,234 +60,7 @@ struct SliceIO<uint16_t> {
     __device__ static void store(uint16_t *p, int64_t i, double v) { p[i] = f64_to_bf16(v); }
 };
 
-__device__ inline double warp_max(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
-    return v;
-}
-
 // ---------------------------------------------------------------------------
-
-__global__ void k_init(const SiteRec *__restrict__ sites, int n_sites, double *__restrict__ msg0,
-                       NetState *__restrict__ st, int n_nets) {
-    int i = blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n_nets) {
-        NetState s;
-        s.active = 1;
-        s.iters = 0;
-        s.parity = 0;
-        s.status = 0;
-        s.res_bits = 0ull;
-        s.residual = 0.0;
-        s.log_bp = 0.0;
-        s.sign_bp = 1;
-        s.converged = 0;
-        st[i] = s;
-    }
-    if (i < n_sites) {
-        const SiteRec &r = sites[i];
-        for (int l = 0; l < r.rank; ++l) {
-            double v = 1.0 / sqrt((double)r.dim[l]);
-            double *m = msg0 + r.msg_off + r.moff[l];
-            for (int k = 0; k < r.dim[l]; ++k) m[k] = v;
-        }
-    }
-}
-
-// Outgoing (unnormalised) message on leg `l`, entry `i`: the site tensor
-// contracted with the incoming messages of every other leg.  The innermost
-// other leg is summed as a dot product; the remaining legs run an odometer.
-// Shape arrays live in LDS (uniform per tile).
-template <int R>
-__device__ double bp_out(const double *__restrict__ T, const double *__restrict__ M, const int *s_dim,
-                         const int *s_moff, const int *s_stride, int l, int i) {
-    if constexpr (R == 1) {
-        return T[i];
-    } else {
-        const int q = (l == R - 1) ? R - 2 : R - 1;
-        int dim[R], str[R], mo[R], dig[R];
-        int nouter = 1;
-#pragma unroll
-        for (int k = 0; k < R; ++k) {
-            dim[k] = s_dim[k];
-            str[k] = s_stride[k];
-            mo[k] = s_moff[k];
-            dig[k] = 0;
-            if (k != l && k != q) nouter *= dim[k];
-        }
-        const int dq = s_dim[q], sq = s_stride[q];
-        const double *Mq = M + s_moff[q];
-        int base = i * s_stride[l];
-        double acc = 0.0;
-        for (int it = 0; it < nouter; ++it) {
-            double pp = 1.0;
-#pragma unroll
-            for (int k = 0; k < R; ++k)
-                if (k != l && k != q) pp *= M[mo[k] + dig[k]];
-            double s = 0.0;
-            for (int d = 0; d < dq; ++d) s = fma(T[base + d * sq], Mq[d], s);
-            acc = fma(pp, s, acc);
-#pragma unroll
-            for (int k = R - 1; k >= 0; --k) {
-                if (k == l || k == q) continue;
-                if (++dig[k] < dim[k]) {
-                    base += str[k];
-                    break;
-                }
-                base -= (dim[k] - 1) * str[k];
-                dig[k] = 0;
-            }
-        }
-        return acc;
-    }
-}
-
-__device__ double bp_out_dispatch(int R, const double *T, const double *M, const int *dim, const int *moff,
-                                  const int *stride, int l, int i) {
-    switch (R) {
-        case 1: return bp_out<1>(T, M, dim, moff, stride, l, i);
-        case 2: return bp_out<2>(T, M, dim, moff, stride, l, i);
-        case 3: return bp_out<3>(T, M, dim, moff, stride, l, i);
-        case 4: return bp_out<4>(T, M, dim, moff, stride, l, i);
-        case 5: return bp_out<5>(T, M, dim, moff, stride, l, i);
-        case 6: return bp_out<6>(T, M, dim, moff, stride, l, i);
-        case 7: return bp_out<7>(T, M, dim, moff, stride, l, i);
-        default: return bp_out<8>(T, M, dim, moff, stride, l, i);
-    }
-}
-
-// One Jacobi sweep.  Block = one tile: up to 64 sites of one network with
-// identical leg dims.  Tensors and incoming messages are staged in LDS with
-// coalesced loads; each thread produces one outgoing message entry; then one
-// thread per (site, leg) normalises (unit 2-norm, non-negative sum), writes
-// the message to the partner slot and folds its residual into the network's
-// running maximum.
-__global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restrict__ sites,
-                                                         const BpTile *__restrict__ tiles,
-                                                         const int *__restrict__ tile_sites,
-                                                         double *msg0, double *msg1, NetState *st) {
-    const BpTile tl = tiles[blockIdx.x];
-    NetState *ns = st + tl.net;
-    if (!ns->active) return;
-    const double *__restrict__ min = ns->parity ? msg1 : msg0;
-    double *__restrict__ mout = ns->parity ? msg0 : msg1;
-
-    extern __shared__ double lds[];
-    __shared__ const double *s_t[64];
-    __shared__ int s_msg[64];
-    __shared__ int s_dst[64 * kMaxRank];
-    __shared__ int s_dim[kMaxRank], s_moff[kMaxRank], s_stride[kMaxRank];
-    __shared__ double s_red[kBpThreads / 64];
-    __shared__ int s_bad;
-
-    const int tid = threadIdx.x;
-    const int R = tl.rank, size = tl.size, nos = tl.n_os, ns_ = tl.n_sites;
-    if (tid < ns_) {
-        const SiteRec &r = sites[tile_sites[tl.site_begin + tid]];
-        s_t[tid] = r.t;
-        s_msg[tid] = r.msg_off;
-        for (int l = 0; l < R; ++l) s_dst[tid * kMaxRank + l] = r.dst[l];
-        if (tid == 0) {
-            for (int l = 0; l < R; ++l) {
-                s_dim[l] = r.dim[l];
-                s_moff[l] = r.moff[l];
-                s_stride[l] = r.stride[l];
-            }
-            s_bad = 0;
-        }
-    }
-    __syncthreads();
-    double *lt = lds;
-    double *lm = lt + ns_ * size;
-    double *lo = lm + ns_ * nos;
-    for (int j = 0; j < ns_; ++j) {
-        const double *src = s_t[j];
-        for (int e = tid; e < size; e += kBpThreads) lt[j * size + e] = src[e];
-        for (int e = tid; e < nos; e += kBpThreads) lm[j * nos + e] = min[s_msg[j] + e];
-    }
-    __syncthreads();
-
-    const int nout = ns_ * nos;
-    for (int o = tid; o < nout; o += kBpThreads) {
-        int j = o / nos;
-        int r = o - j * nos;
-        int l = 0;
-        while (l + 1 < R && r >= s_moff[l + 1]) ++l;
-        lo[o] = bp_out_dispatch(R, lt + j * size, lm + j * nos, s_dim, s_moff, s_stride, l, r - s_moff[l]);
-    }
-    __syncthreads();
-
-    double res = 0.0;
-    for (int m = tid; m < ns_ * R; m += kBpThreads) {
-        int j = m / R;
-        int l = m - j * R;
-        const double *raw = lo + j * nos + s_moff[l];
-        const int d = s_dim[l];
-        double n2 = 0.0, sum = 0.0;
-        for (int k = 0; k < d; ++k) {
-            n2 = fma(raw[k], raw[k], n2);
-            sum += raw[k];
-        }
-        double nrm = sqrt(n2);
-        if (!(nrm > 0.0) || !isfinite(nrm)) {
-            s_bad = 1;
-            continue;
-        }
-        const double sg = sum < 0.0 ? -1.0 : 1.0;
-        const int dst = s_dst[j * kMaxRank + l];
-        double d1 = 0.0, d2 = 0.0;
-        for (int k = 0; k < d; ++k) {
-            double v = sg * (raw[k] / nrm);
-            double old = min[dst + k];
-            d1 = fmax(d1, fabs(v - old));
-            d2 = fmax(d2, fabs(v + old));
-            mout[dst + k] = v;
-        }
-        res = fmax(res, fmin(d1, d2));
-    }
-    res = warp_max(res);
-    if ((tid & 63) == 0) s_red[tid >> 6] = res;
-    __syncthreads();
-    if (tid == 0) {
-        double r = s_red[0];
-        for (int w = 1; w < kBpThreads / 64; ++w) r = fmax(r, s_red[w]);
-        atomicMax(&ns->res_bits, (unsigned long long)__double_as_longlong(r));
-        if (s_bad) atomicMin(&ns->status, -4);
-    }
-}
-
-// Sweep bookkeeping: flip buffers, record the residual, stop converged or
-// exhausted networks, count the still-active ones (single block).
-__global__ void k_bp_finish(NetState *st, int n_nets, double tol, int max_iter, int *n_active) {
-    __shared__ int s_cnt[1024 / 64];
-    int cnt = 0;
-    for (int i = threadIdx.x; i < n_nets; i += blockDim.x) {
-        NetState &s = st[i];
-        if (!s.active) continue;
-        s.iters += 1;
-        s.parity ^= 1;
-        double r = __longlong_as_double((long long)s.res_bits);
-        s.residual = r;
-        s.res_bits = 0ull;
-        if (s.status < 0) {
-            s.active = 0;
-        } else if (r <= tol) {
-            s.active = 0;
-            s.converged = 1;
-        } else if (s.iters >= max_iter) {
-            s.active = 0;
-        } else {
-            ++cnt;
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) cnt += __shfl_xor(cnt, o, 64);
-    if ((threadIdx.x & 63) == 0) s_cnt[threadIdx.x >> 6] = cnt;
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        int t = 0;
-        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) t += s_cnt[w];
-        *n_active = t;
-    }
-}
 
 // Per bond: with a = message arriving at the first site, c = message
 // arriving at the second site and n = a.c, the gauge G = [a/n | R] (R an
@@ -759,24 +528,6 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__rest
 }
 
 }  // namespace
-
-hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
-    int n = b.n_sites > b.n_nets ? b.n_sites : b.n_nets;
-    hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, b.sites, b.n_sites, b.msg0, b.state,
-                       b.n_nets);
-    return hipGetLastError();
-}
-
-hipError_t launch_sweep(const DeviceBatch &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_bp_sweep, dim3(b.n_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites, b.tiles,
-                       b.tile_sites, b.msg0, b.msg1, b.state);
-    return hipGetLastError();
-}
-
-hipError_t launch_finish(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_bp_finish, dim3(1), dim3(1024), 0, s, b.state, b.n_nets, tol, max_iter, b.n_active);
-    return hipGetLastError();
-}
 
 hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s) {
     if (b.n_bonds > 0)

@@ -38,7 +38,20 @@ struct BpTile {
     int32_t rank;
     int32_t size;         // tensor entries per site
     int32_t n_os;         // outputs (sum of dims) per site
-    int32_t pad0, pad1;
+    int32_t first;        // 1 for the network's first tile (writes its bookkeeping)
+    int32_t dc;           // common leg dimension (2..6) for specialised code, else 0
+    int32_t reg;          // 1: register path (all legs of dimension dc)
+    int32_t pad;
+};
+
+// A network run by the persistent per-network BP kernel.
+struct FusedNet {
+    int32_t net;         // network index in the batch
+    int32_t tile_begin;  // first tile (in the full tile table)
+    int32_t n_tiles;
+    int32_t msg_base;    // absolute offset of the network's first message
+    int32_t msg_size;    // doubles of messages
+    int32_t scratch;     // doubles of per-wavefront scratch
 };
 
 // One bond of one network (device table for the gauge kernel).
@@ -51,15 +64,17 @@ struct BondRec {
     int32_t xv_off;  // transform applied to the second site's slot
 };
 
-// Per-network BP state.
+// Per-network BP state.  Sweep k reads message buffer k&1, writes buffer
+// (k+1)&1 and folds its residual into res_acc[k%3]; a network stopped at
+// sweep s keeps its final messages in buffer (s+1)&1.
 struct NetState {
-    int32_t active;
-    int32_t iters;
-    int32_t parity;     // buffer holding the latest messages
+    int32_t stop;       // sweep at which BP stopped, -1 while running
+    int32_t iters;      // sweeps performed (stop + 1)
+    int32_t parity;     // buffer holding the final messages
     int32_t status;     // 0 ok, else a negative pne_status
-    unsigned long long res_bits;  // running max of the sweep residual (bits of a double >= 0)
-    double residual;
-    double log_bp;      // sum of vacuum log-magnitudes (+ open scales)
+    unsigned long long res_acc[3];  // per-sweep residual maxima (bits of doubles >= 0)
+    double residual;    // residual of the last sweep
+    double log_bp;
     int32_t sign_bp;
     int32_t converged;
 };

@@ -50,7 +50,8 @@ struct pne_batch {
     std::vector<void *> allocs;
     size_t bytes = 0;
     DeviceBatch db;
-    int *h_active = nullptr;  // pinned
+    NetState *h_state_pinned = nullptr;  // pinned copy of the per-network state
+    int first_chunk = 4;                 // sweeps before the first convergence check
     bool launched = false;
     bool waited = false;
     // per-kernel HIP-event timing (PNE_FLAG_PROFILE)
@@ -190,8 +191,8 @@ void free_batch(pne_batch *b) {
     b->ev_pool.clear();
     for (void *p : b->allocs) (void)hipFree(p);
     b->allocs.clear();
-    if (b->h_active) (void)hipHostFree(b->h_active);
-    b->h_active = nullptr;
+    if (b->h_state_pinned) (void)hipHostFree(b->h_state_pinned);
+    b->h_state_pinned = nullptr;
     if (b->ctx) b->ctx->used -= std::min(b->ctx->used, b->bytes);
 }
 
@@ -435,27 +436,49 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     }
     b->msg_total = msg;
 
-    // BP tiles: per network, runs of sites with identical leg dims
+    // BP tiles: per network, runs of sites with identical leg dims.  A network
+    // whose tiles all take the register path and whose messages fit in LDS is
+    // run by the persistent BP kernel; the others are swept launch by launch.
     std::vector<BpTile> tiles;
     std::vector<int> tile_sites;
-    const size_t bp_budget = 48 * 1024 / 8;  // doubles of dynamic LDS per tile
-    size_t bp_lds = 0;
+    std::vector<FusedNet> fused;
+    std::vector<BpTile> loop_tiles;
+    const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
+    const size_t fused_budget = 76 * 1024 / 8;  // doubles of dynamic LDS per persistent block
+    size_t bp_lds = 0, fused_lds = 0;
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
         int base = b->site_base[i];
         std::map<std::vector<int>, std::vector<int>> groups;
+        bool first_tile_of_net = true;
         for (int s = 0; s < g.n_sites; ++s) {
             std::vector<int> key(g.dim.begin() + g.slot_base[s], g.dim.begin() + g.slot_base[s + 1]);
             groups[key].push_back(base + s);
         }
+        const int tile_begin = (int)tiles.size();
+        bool all_reg = true;
+        size_t scratch = 0, net_lds = 0;
         for (auto &kv : groups) {
             const SiteRec &r0 = sites[kv.second[0]];
             int nos = 0;
             for (int l = 0; l < r0.rank; ++l) nos += r0.dim[l];
-            size_t per = (size_t)r0.size + 2 * (size_t)nos;
+            const int last = r0.dim[r0.rank - 1];
+            int maxd = 1;
+            for (int l = 0; l < r0.rank; ++l) maxd = std::max(maxd, r0.dim[l]);
+            // per-site share of the tile's LDS (the reduction scratch is shared)
+            const size_t per = 3 * (size_t)nos + (size_t)r0.size + 2 * (size_t)(r0.size / last);
+            const int rows0 = r0.size / last;
             int cap = (int)std::max<size_t>(1, std::min<size_t>(64, bp_budget / per));
-            cap = std::min(cap, std::max(1, 256 / nos));
-            if (per > 160 * 1024 / 8 - 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
+            cap = std::min(cap, std::max(1, bp_tile_threads() / std::max(rows0, nos)));
+            int dc = maxd;
+            for (int l = 0; l < r0.rank; ++l)
+                if (r0.dim[l] != maxd) dc = 0;
+            if (dc < 2 || dc > 6) dc = 0;
+            const int reg_spt = dc ? bp_reg_sites_per_tile(dc, r0.rank) : 0;
+            if (reg_spt > 0) cap = std::min(reg_spt, bp_fused_tile_sites());
+            else all_reg = false;
+            if (!reg_spt && per > 150 * 1024 / 8)
+                return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
             for (size_t k = 0; k < kv.second.size(); k += cap) {
                 BpTile t;
                 std::memset(&t, 0, sizeof t);
@@ -465,10 +488,40 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 t.rank = r0.rank;
                 t.size = r0.size;
                 t.n_os = nos;
+                t.first = first_tile_of_net ? 1 : 0;
+                t.dc = dc;
+                t.reg = reg_spt > 0 ? 1 : 0;
+                first_tile_of_net = false;
                 for (int j = 0; j < t.n_sites; ++j) tile_sites.push_back(kv.second[k + j]);
-                bp_lds = std::max(bp_lds, (size_t)t.n_sites * per * 8);
+                const size_t need = t.reg ? (size_t)t.n_sites * nos * 8
+                                          : bp_tile_lds_doubles(t.n_sites, r0.size, nos, last, maxd) * 8;
+                net_lds = std::max(net_lds, need);
+                scratch = std::max(scratch, (size_t)t.n_sites * nos);
                 tiles.push_back(t);
             }
+        }
+        const int n_tiles_net = (int)tiles.size() - tile_begin;
+        int64_t msg_lo = sites[base].msg_off;
+        int64_t msg_hi = sites[base + g.n_sites - 1].msg_off;
+        {
+            const SiteRec &rl = sites[base + g.n_sites - 1];
+            for (int l = 0; l < rl.rank; ++l) msg_hi += rl.dim[l];
+        }
+        const size_t msg_size = (size_t)(msg_hi - msg_lo);
+        const size_t fneed = 2 * msg_size + 8 * scratch;
+        if (all_reg && fneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
+            FusedNet f;
+            f.net = i;
+            f.tile_begin = tile_begin;
+            f.n_tiles = n_tiles_net;
+            f.msg_base = (int)msg_lo;
+            f.msg_size = (int)msg_size;
+            f.scratch = (int)scratch;
+            fused.push_back(f);
+            fused_lds = std::max(fused_lds, fneed * 8);
+        } else {
+            loop_tiles.insert(loop_tiles.end(), tiles.begin() + tile_begin, tiles.end());
+            bp_lds = std::max(bp_lds, net_lds);
         }
     }
 
@@ -576,7 +629,9 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     st = upload(b.get(), vec, &db.field);                \
     if (st != PNE_OK) { free_batch(b.get()); return st; }
     UP(sites, sites);
-    UP(tiles, tiles);
+    UP(loop_tiles, tiles);
+    UP(tiles, all_tiles);
+    UP(fused, fused);
     UP(tile_sites, tile_sites);
     UP(bonds, bonds);
     UP(classes, classes);
@@ -594,7 +649,9 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     UP(pair_cats, pair_cats);
 #undef UP
     db.n_sites = (int)sites.size();
-    db.n_tiles = (int)tiles.size();
+    db.n_tiles = (int)loop_tiles.size();
+    db.n_fused = (int)fused.size();
+    db.fused_lds = fused_lds;
     db.n_bonds = (int)bonds.size();
     db.n_nets = n;
     db.n_cblocks = (int)cblocks.size();
@@ -608,7 +665,6 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     if (st != PNE_OK) { free_batch(b.get()); return st; }                  \
     db.field = (type)p;
     AL(sizeof(NetState) * n, state, NetState *);
-    AL(sizeof(int), n_active, int *);
     AL(sizeof(double) * msg, msg0, double *);
     AL(sizeof(double) * msg, msg1, double *);
     AL(sizeof(double) * std::max<int64_t>(xg, 1), xg, double *);
@@ -624,7 +680,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
     }
     ctx->used += b->bytes;
-    if (hipHostMalloc((void **)&b->h_active, sizeof(int), hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&b->h_state_pinned, sizeof(NetState) * n, hipHostMallocDefault) != hipSuccess) {
         free_batch(b.get());
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
     }
@@ -647,20 +703,37 @@ pne_status pne_batch_launch(pne_batch *b) {
     HIP_TRY(ctx, timed(b, KID_INIT, [&](hipStream_t st) { return launch_init(db, st); }));
     const int max_iter = b->opt.bp_max_iter;
     const double tol = b->opt.bp_tol;
-    int done = 0;
-    int chunk = b->opt.bp_check_every > 0 ? b->opt.bp_check_every : 4;
-    while (done < max_iter) {
-        int k = std::min(chunk, max_iter - done);
-        for (int j = 0; j < k; ++j) {
-            HIP_TRY(ctx, timed(b, KID_SWEEP, [&](hipStream_t st) { return launch_sweep(db, st); }));
-            HIP_TRY(ctx, timed(b, KID_FINISH, [&](hipStream_t st) { return launch_finish(db, tol, max_iter, st); }));
-        }
-        done += k;
-        HIP_TRY(ctx, hipMemcpyAsync(b->h_active, b->db.n_active, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIP_TRY(ctx, timed(b, KID_FUSED, [&](hipStream_t st) { return launch_fused(db, tol, max_iter, st); }));
+    // Networks not run by the persistent kernel are swept one launch per
+    // sweep, in chunks; after each chunk the host reads the per-network state
+    // and stops once every network has stopped, failed, or reached the
+    // tolerance on the chunk's last sweep.
+    const int n = db.n_nets;
+    int sweep = 0;
+    int chunk = b->opt.bp_check_every > 0 ? b->opt.bp_check_every : b->first_chunk;
+    while (db.n_tiles > 0 && sweep < max_iter) {
+        const int kk = std::min(chunk, max_iter - sweep);
+        for (int j = 0; j < kk; ++j, ++sweep)
+            HIP_TRY(ctx, timed(b, KID_SWEEP, [&](hipStream_t st) { return launch_sweep(db, sweep, tol, max_iter, st); }));
+        HIP_TRY(ctx, hipMemcpyAsync(b->h_state_pinned, db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost, s));
         HIP_TRY(ctx, hipStreamSynchronize(s));
-        if (*b->h_active == 0) break;
+        const int last = sweep - 1;
+        bool all_done = true;
+        for (int i = 0; i < n && all_done; ++i) {
+            const NetState &st = b->h_state_pinned[i];
+            if (st.stop >= 0 || st.status < 0) continue;
+            const double r = [&] {
+                double d;
+                std::memcpy(&d, &st.res_acc[last % 3], sizeof d);
+                return d;
+            }();
+            if (!(r <= tol)) all_done = false;
+        }
+        if (all_done) break;
         if (b->opt.bp_check_every <= 0) chunk = std::min(chunk * 2, 16);
     }
+    if (sweep == 0) sweep = 1;  // only persistent networks: close is a no-op for them
+    HIP_TRY(ctx, timed(b, KID_CLOSE, [&](hipStream_t st) { return launch_close(db, sweep - 1, tol, st); }));
     HIP_TRY(ctx, timed(b, KID_GAUGE, [&](hipStream_t st) { return launch_gauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_REGAUGE, [&](hipStream_t st) { return launch_regauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_CLUSTERS, [&](hipStream_t st) { return launch_clusters(db, st); }));

@@ -220,11 +220,12 @@ class Result:
         return self.status >= 0
 
 
-KERNEL_NAMES = ["init", "bp_sweep", "bp_finish", "gauge", "regauge", "clusters", "combine"]
+KERNEL_NAMES = ["init", "bp_sweep", "bp_close", "bp_persistent", "gauge", "regauge", "clusters", "combine"]
 PNE_FLAG_PROFILE = 1
+PNE_FLAG_NO_PERSISTENT = 2
 
 
-def _options(K, precision, tol, max_iter, check_every, profile=False):
+def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True):
     lib = load_library()
     o = Options()
     lib.pne_options_default(ctypes.byref(o))
@@ -233,7 +234,7 @@ def _options(K, precision, tol, max_iter, check_every, profile=False):
     o.bp_tol = float(tol)
     o.bp_max_iter = int(max_iter)
     o.bp_check_every = int(check_every)
-    o.flags = PNE_FLAG_PROFILE if profile else 0
+    o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT)
     return o
 
 
@@ -268,8 +269,8 @@ class Context:
         return Network(self, obj, on_device)
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
-              profile=False) -> "Batch":
-        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile)
+              profile=False, persistent=True) -> "Batch":
+        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent)
 
     def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
         b = self.batch([net], K, precision, tol, max_iter)
@@ -321,10 +322,11 @@ class Network:
 class Batch:
     """Prepared batch: plans and device tables built once, run many times."""
 
-    def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False):
+    def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
+                 persistent=True):
         self.ctx = ctx
         self.nets = list(nets)
-        self.opt = _options(K, precision, tol, max_iter, check_every, profile)
+        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),

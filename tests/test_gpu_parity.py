@@ -40,6 +40,24 @@ def _run(ctx, net_in, K, precision="fp64", **kw):
     return r, b, net
 
 
+@pytest.mark.parametrize("name,make,K", [
+    ("rand2d_4x4_D3", lambda: P.random_2d(4, 4, 3, "uniform01", seed=7), 6),
+    ("rand3d_3_D3", lambda: P.random_3d(3, 3, "normal", seed=11), 6),
+    ("aklt_4x4", lambda: P.aklt_2d(4, 4), 8),
+    ("open_4x4", lambda: P.random_2d(4, 4, 3, "uniform01", seed=32, open_sites={5: 2, 6: 2}), 6),
+])
+def test_per_launch_sweeps_match_persistent(ctx, name, make, K):
+    """The launch-per-sweep BP path and the persistent per-network path agree."""
+    net = make()
+    a, _, _ = _run(ctx, net, K, persistent=True)
+    b, _, _ = _run(ctx, net, K, persistent=False)
+    assert a.bp_iters == b.bp_iters
+    assert abs(a.log_abs - b.log_abs) < 1e-12
+    ref = O.pne_contract(net, K)
+    if net.n_open == 0:
+        _check_closed(b, ref, 1e-10)
+
+
 def _check_closed(r, ref, tol):
     assert r.status >= 0, r.status
     assert r.sign == ref.sign
