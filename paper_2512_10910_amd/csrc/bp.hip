@@ -555,108 +555,6 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
 }
 
 
-// Persistent BP for one network per block (512 threads): both message
-// buffers live in LDS for all sweeps, each wavefront takes register tiles
-// round-robin, and the block-wide residual decides convergence after every
-// sweep.  Used for networks whose sites all have a uniform leg dimension and
-// whose messages fit in LDS.  On exit the final messages are copied to the
-// network's region of global buffer 0 and the state records the stop.
-constexpr int kFusedThreads = 512;
-
-// One register tile inside the persistent kernel, kept out of line so each
-// shape gets its own register allocation (inlining all shapes into one
-// switch would size the kernel for their union).
-template <int D, int R>
-__device__ __attribute__((noinline)) double fused_tile(const BpTile &tl, const SiteRec *__restrict__ sites,
-                                                       const int *__restrict__ tile_sites, const double *mi,
-                                                       double *mo, int msg_base, double *scr,
-                                                       TileSharedN<kFusedTileSites> &sh, int *bad) {
-    return sweep_reg<D, R, true, TileSharedN<kFusedTileSites>, 1>(tl, sites, tile_sites, mi, mo, msg_base, scr, sh,
-                                                                   bad);
-}
-
-__global__ void __launch_bounds__(kFusedThreads) __attribute__((amdgpu_waves_per_eu(4, 8))) k_bp_fused(const FusedNet *__restrict__ fnets,
-                                                           const BpTile *__restrict__ tiles,
-                                                           const int *__restrict__ tile_sites,
-                                                           const SiteRec *__restrict__ sites, double *msg0,
-                                                           NetState *st, double tol, int max_iter) {
-    const FusedNet fn = fnets[blockIdx.x];
-    NetState *ns = st + fn.net;
-    extern __shared__ double lds[];
-    __shared__ TileSharedN<kFusedTileSites> shw[kFusedThreads / 64];
-    __shared__ double s_res[kFusedThreads / 64];
-    __shared__ int s_bad;
-    const int tid = threadIdx.x;
-    const int wave = tid >> 6;
-    constexpr int nwaves = kFusedThreads / 64;
-    double *b0 = lds;
-    double *b1 = b0 + fn.msg_size;
-    double *wscr = b1 + fn.msg_size + wave * fn.scratch;
-    for (int e = tid; e < fn.msg_size; e += kFusedThreads) b0[e] = msg0[fn.msg_base + e];
-    if (tid == 0) s_bad = 0;
-    __syncthreads();
-    int sweep = 0;
-    double r = 0.0;
-    bool conv = false;
-    for (sweep = 0; sweep < max_iter; ++sweep) {
-        const double *mi = (sweep & 1) ? b1 : b0;
-        double *mo = (sweep & 1) ? b0 : b1;
-        double wres = 0.0;
-        for (int t = wave; t < fn.n_tiles; t += nwaves) {
-            const BpTile tl = tiles[fn.tile_begin + t];
-            double tr = 0.0;
-            switch (tl.dc * 8 + tl.rank) {
-                case 17: tr = fused_tile<2, 1>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 18: tr = fused_tile<2, 2>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 19: tr = fused_tile<2, 3>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 20: tr = fused_tile<2, 4>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 21: tr = fused_tile<2, 5>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 22: tr = fused_tile<2, 6>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 25: tr = fused_tile<3, 1>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 26: tr = fused_tile<3, 2>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 27: tr = fused_tile<3, 3>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 28: tr = fused_tile<3, 4>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 29: tr = fused_tile<3, 5>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 33: tr = fused_tile<4, 1>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 34: tr = fused_tile<4, 2>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 35: tr = fused_tile<4, 3>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 36: tr = fused_tile<4, 4>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 37: tr = fused_tile<4, 5>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 41: tr = fused_tile<5, 1>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 42: tr = fused_tile<5, 2>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 43: tr = fused_tile<5, 3>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 49: tr = fused_tile<6, 1>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 50: tr = fused_tile<6, 2>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                case 51: tr = fused_tile<6, 3>(tl, sites, tile_sites, mi, mo, fn.msg_base, wscr, shw[wave], &s_bad); break;
-                default: break;
-            }
-            wres = fmax(wres, tr);
-        }
-        if ((tid & 63) == 0) s_res[wave] = wres;
-        __syncthreads();
-        r = s_res[0];
-        for (int w = 1; w < nwaves; ++w) r = fmax(r, s_res[w]);
-        const int bad = s_bad;
-        __syncthreads();
-        if (bad) break;
-        if (r <= tol) {
-            conv = true;
-            break;
-        }
-    }
-    const int last = sweep < max_iter ? sweep : max_iter - 1;
-    const double *fin = (last & 1) ? b0 : b1;
-    for (int e = tid; e < fn.msg_size; e += kFusedThreads) msg0[fn.msg_base + e] = fin[e];
-    if (tid == 0) {
-        ns->stop = last;
-        ns->iters = last + 1;
-        ns->parity = 0;
-        ns->residual = r;
-        ns->converged = conv ? 1 : 0;
-        if (s_bad) ns->status = -4;
-    }
-}
-
 // After the last launched sweep k_last: record networks that are still running.
 __global__ void k_bp_close(NetState *st, int n_nets, int k_last, double tol) {
     const int i = blockIdx.x * blockDim.x + threadIdx.x;
@@ -695,15 +593,6 @@ hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, h
                        b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter);
     return hipGetLastError();
 }
-
-hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
-    if (!b.n_fused) return hipSuccess;
-    hipLaunchKernelGGL(k_bp_fused, dim3(b.n_fused), dim3(kFusedThreads), b.fused_lds, s, b.fused, b.all_tiles,
-                       b.tile_sites, b.sites, b.msg0, b.state, tol, max_iter);
-    return hipGetLastError();
-}
-
-int bp_fused_tile_sites() { return kFusedTileSites; }
 
 hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s) {
     hipLaunchKernelGGL(k_bp_close, dim3((b.n_nets + 255) / 256), dim3(256), 0, s, b.state, b.n_nets, k_last, tol);

@@ -17,6 +17,8 @@ struct DeviceBatch {
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel
     int n_fused = 0;
+    const FusedGroup *fgroups = nullptr;
+    const int *fsite_list = nullptr;
     size_t fused_lds = 0;
     const int *tile_sites = nullptr;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
@@ -33,6 +35,10 @@ struct DeviceBatch {
     int *site_sign = nullptr;
     double *vac = nullptr;
     size_t regauge_lds = 0;
+    const int *rg_tiles = nullptr;  // register-path tiles (indices into all_tiles) for the regauge
+    int n_rg_tiles = 0;
+    const int *rg_sites = nullptr;  // sites regauged one per block (open or mixed-dimension sites)
+    int n_rg_sites = 0;
     // clusters
     const ClassDesc *classes = nullptr;
     const StepDesc *steps = nullptr;
@@ -66,10 +72,14 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s);
 hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s);
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s);
-// largest tile (sites) the persistent kernel accepts
-int bp_fused_tile_sites();
+// doubles of dynamic LDS of a persistent block and its per-wave scratch
+size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave);
+int bp_persistent_scratch(int spw, int rank, int dim);
+int bp_persistent_tiles_in_flight(int dim, int rank);
 hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
+// shapes the register-path regauge handles (all legs of dimension dim)
+bool regauge_reg_supported(int dim, int rank);
 hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s);
 

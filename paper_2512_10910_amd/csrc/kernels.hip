@@ -134,10 +134,12 @@ __global__ void k_gauge(const BondRec *__restrict__ bonds, int n_bonds, const do
 // FP64; their sum over sites is ln|Z_BP|.
 template <typename S>
 __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restrict__ sites,
+                                                        const int *__restrict__ rg_sites,
                                                         const double *__restrict__ xg, S *__restrict__ slices,
                                                         double *__restrict__ site_log, int *__restrict__ site_sign,
                                                         double *__restrict__ vac, NetState *st) {
-    const SiteRec r = sites[blockIdx.x];
+    const int gsite = rg_sites[blockIdx.x];
+    const SiteRec r = sites[gsite];
     extern __shared__ double lds[];
     __shared__ double s_x[kMaxDim * kMaxDim];
     __shared__ double s_norm;
@@ -193,8 +195,8 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
         }
         s_ok = (fabs(nv) > 0.0) && isfinite(nv);
         s_norm = nv;
-        site_log[blockIdx.x] = s_ok ? log(fabs(nv)) : 0.0;
-        site_sign[blockIdx.x] = sg;
+        site_log[gsite] = s_ok ? log(fabs(nv)) : 0.0;
+        site_sign[gsite] = sg;
         if (!s_ok) atomicMin(&st[r.net].status, -4);
     }
     __syncthreads();
@@ -214,6 +216,126 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
             }
             vac[r.vac_off + p] = b0[off] / nv;
         }
+    }
+}
+
+constexpr int rg_ipow(int b, int e) { return e <= 0 ? 1 : b * rg_ipow(b, e - 1); }
+
+// Register-path regauge for a tile of same-shape sites (all R legs of
+// dimension D, no open legs), laid out as in the BP register path: the last
+// T legs index lanes through power-of-two bit-fields, the first R-T legs
+// index NL values per lane.  A gauge on a register leg is an in-lane mode
+// product; a gauge on a lane leg gathers the D values of the leg with
+// shuffles.  The vacuum factor T'[0,...,0] sits in the segment's first lane.
+template <int D, int R, typename S>
+__device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
+                            const double *__restrict__ xg, S *__restrict__ slices, double *__restrict__ site_log,
+                            int *__restrict__ site_sign, NetState *st) {
+    constexpr int P = D <= 2 ? 2 : (D <= 4 ? 4 : 8);
+    constexpr int B = P == 2 ? 1 : (P == 4 ? 2 : 3);
+    constexpr int T = (6 / B) < R ? (6 / B) : R;
+    constexpr int NLEG = R - T;
+    constexpr int LS = 1 << (B * T);
+    constexpr int NL = rg_ipow(D, NLEG);
+    constexpr int DT = rg_ipow(D, T);
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LS;
+    const int tb = lane - slot * LS;
+    bool act = slot < tl.n_sites;
+    int dig[T];
+    int toff = 0;
+#pragma unroll
+    for (int m = 0; m < T; ++m) {
+        dig[m] = (tb >> (B * (T - 1 - m))) & (P - 1);
+        act = act && dig[m] < D;
+        toff = toff * D + (dig[m] < D ? dig[m] : 0);
+    }
+    const int gsite = tile_sites[tl.site_begin + (slot < tl.n_sites ? slot : 0)];
+    const SiteRec &sr = sites[gsite];
+    const double *tp = sr.t;
+    const double *X0 = xg + sr.xg_off;
+    double v[NL];
+#pragma unroll
+    for (int q = 0; q < NL; ++q) v[q] = act ? tp[q * DT + toff] : 0.0;
+    // register (lead) legs
+#pragma unroll
+    for (int k = 0; k < NLEG; ++k) {
+        const double *X = X0 + k * D * D;
+        constexpr int dummy = 0;
+        (void)dummy;
+        double w[NL];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            const int stride = rg_ipow(D, NLEG - 1 - k);
+            const int dk = (q / stride) % D;
+            const int q0 = q - dk * stride;
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) acc = fma(v[q0 + i * stride], X[i * D + dk], acc);
+            w[q] = acc;
+        }
+#pragma unroll
+        for (int q = 0; q < NL; ++q) v[q] = w[q];
+    }
+    // lane (trailing) legs
+#pragma unroll
+    for (int m = 0; m < T; ++m) {
+        const double *X = X0 + (NLEG + m) * D * D;
+        const int shift = B * (T - 1 - m);
+        const int field_clear = lane & ~((P - 1) << shift);
+        double xc[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) xc[i] = X[i * D + (dig[m] < D ? dig[m] : 0)];
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < D; ++i) acc = fma(__shfl(v[q], field_clear | (i << shift), 64), xc[i], acc);
+            v[q] = acc;
+        }
+    }
+    // vacuum factor of each site: element 0 in the segment's first lane
+    const double z = __shfl(v[0], slot * LS, 64);
+    const bool ok = (fabs(z) > 0.0) && isfinite(z);
+    if (act) {
+        const int64_t so = sr.slice_off;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) SliceIO<S>::store(slices, so + q * DT + toff, ok ? v[q] / z : 0.0);
+    }
+    if (tb == 0 && slot < tl.n_sites) {
+        site_log[gsite] = ok ? log(fabs(z)) : 0.0;
+        site_sign[gsite] = z < 0.0 ? -1 : 1;
+        if (!ok) atomicMin(&st[tl.net].status, -4);
+    }
+}
+
+template <typename S>
+__global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__ tiles, const int *__restrict__ rg_tiles,
+                                                      const SiteRec *__restrict__ sites,
+                                                      const int *__restrict__ tile_sites, const double *__restrict__ xg,
+                                                      S *__restrict__ slices, double *__restrict__ site_log,
+                                                      int *__restrict__ site_sign, NetState *st) {
+    const BpTile tl = tiles[rg_tiles[blockIdx.x]];
+    switch (tl.dc * 8 + tl.rank) {
+        case 17: regauge_reg<2, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 18: regauge_reg<2, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 19: regauge_reg<2, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 20: regauge_reg<2, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 21: regauge_reg<2, 5, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 22: regauge_reg<2, 6, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 25: regauge_reg<3, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 26: regauge_reg<3, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 27: regauge_reg<3, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 28: regauge_reg<3, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 33: regauge_reg<4, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 34: regauge_reg<4, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 35: regauge_reg<4, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 36: regauge_reg<4, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 41: regauge_reg<5, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 42: regauge_reg<5, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 49: regauge_reg<6, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 50: regauge_reg<6, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        default: break;
     }
 }
 
@@ -536,20 +658,28 @@ hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+bool regauge_reg_supported(int dim, int rank) {
+    if (dim < 2 || dim > 6 || rank < 1 || rank > 6) return false;
+    const int B = dim <= 2 ? 1 : (dim <= 4 ? 2 : 3);
+    const int T = (6 / B) < rank ? (6 / B) : rank;
+    return rg_ipow(dim, rank - T) <= 4;
+}
+
+template <typename S>
+static void launch_regauge_t(const DeviceBatch &b, hipStream_t s) {
+    if (b.n_rg_tiles)
+        hipLaunchKernelGGL(k_regauge_tiles<S>, dim3(b.n_rg_tiles), dim3(64), 0, s, b.all_tiles, b.rg_tiles, b.sites,
+                           b.tile_sites, b.xg, (S *)b.slices, b.site_log, b.site_sign, b.state);
+    if (b.n_rg_sites)
+        hipLaunchKernelGGL(k_regauge<S>, dim3(b.n_rg_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites, b.rg_sites,
+                           b.xg, (S *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+}
+
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s) {
     switch (b.precision) {
-        case 0:
-            hipLaunchKernelGGL(k_regauge<double>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
-                               b.xg, (double *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
-            break;
-        case 1:
-            hipLaunchKernelGGL(k_regauge<float>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
-                               b.xg, (float *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
-            break;
-        default:
-            hipLaunchKernelGGL(k_regauge<uint16_t>, dim3(b.n_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites,
-                               b.xg, (uint16_t *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
-            break;
+        case 0: launch_regauge_t<double>(b, s); break;
+        case 1: launch_regauge_t<float>(b, s); break;
+        default: launch_regauge_t<uint16_t>(b, s); break;
     }
     return hipGetLastError();
 }

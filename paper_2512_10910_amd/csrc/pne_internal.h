@@ -46,12 +46,26 @@ struct BpTile {
 
 // A network run by the persistent per-network BP kernel.
 struct FusedNet {
-    int32_t net;         // network index in the batch
-    int32_t tile_begin;  // first tile (in the full tile table)
-    int32_t n_tiles;
-    int32_t msg_base;    // absolute offset of the network's first message
-    int32_t msg_size;    // doubles of messages
-    int32_t scratch;     // doubles of per-wavefront scratch
+    int32_t net;          // network index in the batch
+    int32_t msg_base;     // absolute offset of the network's first message
+    int32_t msg_size;     // doubles of messages
+    int32_t site_base;    // global index of the network's first site
+    int32_t n_sites;
+    int32_t group_begin;  // shape groups of the network
+    int32_t n_groups;
+    int32_t list_begin;   // site list (local site ids, group after group)
+    int32_t scratch;      // doubles of per-wavefront scratch
+    int32_t pad;
+};
+
+// Sites of one network with all legs of dimension dc and rank `rank`.
+struct FusedGroup {
+    int32_t dc, rank;
+    int32_t spw;          // sites per tile
+    int32_t list_off;     // first entry in the network's site list
+    int32_t n_sites;
+    int32_t nt;           // tiles per wavefront step
+    int32_t pad1, pad2;
 };
 
 // One bond of one network (device table for the gauge kernel).

@@ -442,6 +442,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     std::vector<BpTile> tiles;
     std::vector<int> tile_sites;
     std::vector<FusedNet> fused;
+    std::vector<FusedGroup> fgroups;
+    std::vector<int> fsite_list;
     std::vector<BpTile> loop_tiles;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     const size_t fused_budget = 76 * 1024 / 8;  // doubles of dynamic LDS per persistent block
@@ -456,8 +458,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             groups[key].push_back(base + s);
         }
         const int tile_begin = (int)tiles.size();
-        bool all_reg = true;
-        size_t scratch = 0, net_lds = 0;
+        bool all_reg = g.n_open == 0;
+        size_t net_lds = 0;
         for (auto &kv : groups) {
             const SiteRec &r0 = sites[kv.second[0]];
             int nos = 0;
@@ -475,7 +477,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 if (r0.dim[l] != maxd) dc = 0;
             if (dc < 2 || dc > 6) dc = 0;
             const int reg_spt = dc ? bp_reg_sites_per_tile(dc, r0.rank) : 0;
-            if (reg_spt > 0) cap = std::min(reg_spt, bp_fused_tile_sites());
+            if (reg_spt > 0) cap = reg_spt;
             else all_reg = false;
             if (!reg_spt && per > 150 * 1024 / 8)
                 return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
@@ -496,29 +498,51 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 const size_t need = t.reg ? (size_t)t.n_sites * nos * 8
                                           : bp_tile_lds_doubles(t.n_sites, r0.size, nos, last, maxd) * 8;
                 net_lds = std::max(net_lds, need);
-                scratch = std::max(scratch, (size_t)t.n_sites * nos);
                 tiles.push_back(t);
             }
         }
-        const int n_tiles_net = (int)tiles.size() - tile_begin;
+        // persistent path: every shape group on the register path, LDS fits
         int64_t msg_lo = sites[base].msg_off;
         int64_t msg_hi = sites[base + g.n_sites - 1].msg_off;
         {
             const SiteRec &rl = sites[base + g.n_sites - 1];
             for (int l = 0; l < rl.rank; ++l) msg_hi += rl.dim[l];
         }
-        const size_t msg_size = (size_t)(msg_hi - msg_lo);
-        const size_t fneed = 2 * msg_size + 8 * scratch;
-        if (all_reg && fneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
+        const int msg_size = (int)(msg_hi - msg_lo);
+        int pscratch = 0;
+        for (auto &kv : groups) {
+            const SiteRec &r0 = sites[kv.second[0]];
+            const int spw = bp_reg_sites_per_tile(r0.dim[0], r0.rank);
+            if (spw > 0) pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0]));
+        }
+        const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch);
+        if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
             FusedNet f;
+            std::memset(&f, 0, sizeof f);
             f.net = i;
-            f.tile_begin = tile_begin;
-            f.n_tiles = n_tiles_net;
             f.msg_base = (int)msg_lo;
-            f.msg_size = (int)msg_size;
-            f.scratch = (int)scratch;
+            f.msg_size = msg_size;
+            f.site_base = base;
+            f.n_sites = g.n_sites;
+            f.group_begin = (int)fgroups.size();
+            f.list_begin = (int)fsite_list.size();
+            f.scratch = pscratch;
+            for (auto &kv : groups) {
+                const SiteRec &r0 = sites[kv.second[0]];
+                FusedGroup fg;
+                std::memset(&fg, 0, sizeof fg);
+                fg.dc = r0.dim[0];
+                fg.rank = r0.rank;
+                fg.spw = bp_reg_sites_per_tile(fg.dc, fg.rank);
+                fg.nt = bp_persistent_tiles_in_flight(fg.dc, fg.rank);
+                fg.list_off = (int)fsite_list.size() - f.list_begin;
+                fg.n_sites = (int)kv.second.size();
+                for (int gs : kv.second) fsite_list.push_back(gs - base);
+                fgroups.push_back(fg);
+            }
+            f.n_groups = (int)fgroups.size() - f.group_begin;
             fused.push_back(f);
-            fused_lds = std::max(fused_lds, fneed * 8);
+            fused_lds = std::max(fused_lds, pneed * 8);
         } else {
             loop_tiles.insert(loop_tiles.end(), tiles.begin() + tile_begin, tiles.end());
             bp_lds = std::max(bp_lds, net_lds);
@@ -632,6 +656,23 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
     UP(fused, fused);
+    UP(fgroups, fgroups);
+    UP(fsite_list, fsite_list);
+    // regauge work: register tiles without open legs, other sites one per block
+    std::vector<int> rg_tiles, rg_sites;
+    for (size_t t = 0; t < tiles.size(); ++t) {
+        bool open = false;
+        for (int j = 0; j < tiles[t].n_sites; ++j) open = open || sites[tile_sites[tiles[t].site_begin + j]].open_mask;
+        if (tiles[t].reg && !open && regauge_reg_supported(tiles[t].dc, tiles[t].rank)) {
+            rg_tiles.push_back((int)t);
+        } else {
+            for (int j = 0; j < tiles[t].n_sites; ++j) rg_sites.push_back(tile_sites[tiles[t].site_begin + j]);
+        }
+    }
+    UP(rg_tiles, rg_tiles);
+    UP(rg_sites, rg_sites);
+    db.n_rg_tiles = (int)rg_tiles.size();
+    db.n_rg_sites = (int)rg_sites.size();
     UP(tile_sites, tile_sites);
     UP(bonds, bonds);
     UP(classes, classes);
