@@ -61,6 +61,8 @@ def main():
     ap.add_argument("--cpu-sample", type=int, default=6, help="networks timed on the CPU oracle (0: skip)")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel HIP events")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="before the workload, run plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1:
@@ -76,6 +78,16 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+
+    if args.copy_calibration:
+        # a plain copy kernel of known size: reads and writes exactly MIB MiB
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     t_setup = time.time()
     nets_in = []

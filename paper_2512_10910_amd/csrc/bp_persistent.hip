@@ -106,21 +106,6 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
             for (int i = 0; i < D; ++i) ml[k][j][i] = p_lds[mb + j * D + i];
     }
     // normalisation item of this lane: (tile k, site j in the tile, leg l)
-    const int items = kNT * SPW * R;
-    const int ik = lane / (SPW * R);
-    const int irem = lane - ik * (SPW * R);
-    const int ij = irem / R;
-    const int il = irem - ij * R;
-    const int ipos = base_pos + ik * SPW + ij;
-    const bool iact = lane < items && ipos < n_in_group;
-    int idst = 0;
-    double oldv[D];
-    if (iact) {
-        const int site = int_at(L.list, gl_off + ipos);
-        idst = int_at(L.dst, site * kMaxRank + il);
-#pragma unroll
-        for (int i = 0; i < D; ++i) oldv[i] = p_lds[mi + idst + i];
-    }
 
     double *out = p_lds + scr;  // [tile][site][R*D]
 #pragma unroll
@@ -179,8 +164,17 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
         }
     }
     wave_sync();
+    // normalisation items: (tile k, site j in the tile, leg l)
     double res = 0.0;
-    if (iact) {
+    for (int n = lane; n < kNT * SPW * R; n += 64) {
+        const int ik = n / (SPW * R);
+        const int irem = n - ik * (SPW * R);
+        const int ij = irem / R;
+        const int il = irem - ij * R;
+        const int ipos = base_pos + ik * SPW + ij;
+        if (ipos >= n_in_group) continue;
+        const int site = int_at(L.list, gl_off + ipos);
+        const int idst = int_at(L.dst, site * kMaxRank + il);
         const double *raw = out + (ik * SPW + ij) * ND + il * D;
         double n2 = 0.0, sum = 0.0;
 #pragma unroll
@@ -191,18 +185,196 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
         const double nrm = sqrt(n2);
         if (!(nrm > 0.0) || !isfinite(nrm)) {
             *bad = 1;
-        } else {
-            const double sg = sum < 0.0 ? -1.0 : 1.0;
-            double d1 = 0.0, d2 = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) {
-                const double v = sg * (raw[i] / nrm);
-                d1 = fmax(d1, fabs(v - oldv[i]));
-                d2 = fmax(d2, fabs(v + oldv[i]));
-                p_lds[mo + idst + i] = v;
-            }
-            res = fmin(d1, d2);
+            continue;
         }
+        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double v = sg * (raw[i] / nrm);
+            const double old = p_lds[mi + idst + i];
+            d1 = fmax(d1, fabs(v - old));
+            d2 = fmax(d2, fabs(v + old));
+            p_lds[mo + idst + i] = v;
+        }
+        res = fmax(res, fmin(d1, d2));
+    }
+    res = wave_max_p(res);
+    wave_sync();
+    return res;
+}
+
+// ---------------------------------------------------------------------------
+// DPP variant for D <= 4: only the last T = min(R, 2) legs index lanes, so a
+// site's lane segment (P^T <= 16 lanes) lies inside one DPP row and every
+// reduction is a data-parallel-primitive move on the VALU: the low field
+// (last leg) with quad permutations, the high field (second-to-last leg,
+// P = 4) with row rotations by 4 and 8, which keep the low bits.  The first
+// R-T legs index NL = D^(R-T) values per lane.
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    return __hiloint2double(hi, lo);
+}
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppRor4 = 0x124;   // row_ror:4
+constexpr int kDppRor8 = 0x128;   // row_ror:8
+
+template <int P>
+__device__ inline double sum_low(double v) {  // over the last leg's digit
+    v += dpp_f64<kDppXor1>(v);
+    if (P == 4) v += dpp_f64<kDppXor2>(v);
+    return v;
+}
+template <int P>
+__device__ inline double sum_high(double v) {  // over the second-to-last leg's digit
+    if (P == 2) {
+        v += dpp_f64<kDppXor2>(v);
+    } else {
+        v += dpp_f64<kDppRor4>(v);
+        v += dpp_f64<kDppRor8>(v);
+    }
+    return v;
+}
+
+__host__ __device__ constexpr bool dpp_shape(int D, int R) {
+    return D >= 2 && D <= 4 && R >= 1 && R <= 6 && ipw(D, R - (R < 2 ? R : 2)) <= 16;
+}
+// tiles per wavefront step: two for small register sets, fewer when the
+// tiles' (site, leg) items would exceed one wavefront
+__host__ __device__ constexpr int dpp_tiles_in_flight(int D, int R) {
+    return (tiles_in_flight(ipw(D, R - (R < 2 ? R : 2))) == 2 &&
+            2 * (64 >> ((D <= 2 ? 1 : 2) * (R < 2 ? R : 2))) * R <= 64)
+               ? 2
+               : 1;
+}
+
+template <int D, int R>
+__device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_off, int n_in_group, int chunk,
+                                                       int mi, int mo, int scr, int *bad) {
+    constexpr int P = D <= 2 ? 2 : 4;
+    constexpr int B = P == 2 ? 1 : 2;
+    constexpr int T = R < 2 ? R : 2;
+    constexpr int NLEG = R - T;
+    constexpr int LS = 1 << (B * T);
+    constexpr int SPW = 64 / LS;
+    constexpr int NL = ipw(D, NLEG);
+    constexpr int DT = ipw(D, T);
+    constexpr int ND = R * D;
+    constexpr int kNT = dpp_tiles_in_flight(D, R);
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LS;
+    const int tb = lane - slot * LS;
+    const int dlo = tb & (P - 1);                 // digit of leg R-1
+    const int dhi = T == 2 ? (tb >> B) : 0;       // digit of leg R-2 (T == 2)
+    const bool inseg = dlo < D && dhi < D;
+    const int toff = T == 2 ? (dhi % D) * D + dlo % D : dlo % D;
+    const int base_pos = chunk * kNT * SPW;
+    double tv[kNT][NL];
+    double mlo[kNT], mhi[kNT];
+    double ml[kNT][NLEG > 0 ? NLEG : 1][D];
+    bool act[kNT];
+#pragma unroll
+    for (int k = 0; k < kNT; ++k) {
+        const int pos = base_pos + k * SPW + slot;
+        act[k] = inseg && pos < n_in_group;
+        const int site = int_at(L.list, gl_off + (pos < n_in_group ? pos : 0));
+        const double *tp = tptr_at(L, site);
+        const int mb = mi + int_at(L.moff, site);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) tv[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+        mlo[k] = p_lds[mb + (R - 1) * D + dlo % D];
+        mhi[k] = T == 2 ? p_lds[mb + (R - 2) * D + dhi % D] : 1.0;
+#pragma unroll
+        for (int j = 0; j < NLEG; ++j)
+#pragma unroll
+            for (int i = 0; i < D; ++i) ml[k][j][i] = p_lds[mb + j * D + i];
+    }
+    double *out = p_lds + scr;  // [tile][site][R*D]
+#pragma unroll
+    for (int k = 0; k < kNT; ++k) {
+        const int oslot = (k * SPW + slot) * ND;
+        const bool valid = act[k];
+        double A = 0.0;
+#pragma unroll
+        for (int q = 0; q < NL; ++q) {
+            double w = 1.0;
+#pragma unroll
+            for (int j = 0; j < NLEG; ++j) w *= ml[k][j][(q / ipw(D, NLEG - 1 - j)) % D];
+            A = fma(tv[k][q], w, A);
+        }
+        // leg R-1: lanes of one low digit, summed over the high field
+        {
+            double pm = A * mhi[k];
+            if (T == 2) pm = sum_high<P>(pm);
+            if (valid && dhi == 0) out[oslot + (R - 1) * D + dlo] = pm;
+        }
+        // leg R-2: summed over the low field
+        if (T == 2) {
+            double pm = sum_low<P>(A * mlo[k]);
+            if (valid && dlo == 0) out[oslot + (R - 2) * D + dhi] = pm;
+        }
+        // lead legs: summed over the whole segment
+        if (NLEG > 0) {
+            const double qt = valid ? mlo[k] * mhi[k] : 0.0;
+#pragma unroll
+            for (int j = 0; j < NLEG; ++j) {
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    double sv = 0.0;
+#pragma unroll
+                    for (int q = 0; q < NL; ++q) {
+                        if ((q / ipw(D, NLEG - 1 - j)) % D != i) continue;
+                        double w = 1.0;
+#pragma unroll
+                        for (int j2 = 0; j2 < NLEG; ++j2)
+                            if (j2 != j) w *= ml[k][j2][(q / ipw(D, NLEG - 1 - j2)) % D];
+                        sv = fma(tv[k][q], w, sv);
+                    }
+                    sv = sum_low<P>(sv * qt);
+                    if (T == 2) sv = sum_high<P>(sv);
+                    if (tb == 0 && base_pos + k * SPW + slot < n_in_group) out[oslot + j * D + i] = sv;
+                }
+            }
+        }
+    }
+    wave_sync();
+    // normalisation items: (tile k, site j in the tile, leg l)
+    double res = 0.0;
+    for (int n = lane; n < kNT * SPW * R; n += 64) {
+        const int ik = n / (SPW * R);
+        const int irem = n - ik * (SPW * R);
+        const int ij = irem / R;
+        const int il = irem - ij * R;
+        const int ipos = base_pos + ik * SPW + ij;
+        if (ipos >= n_in_group) continue;
+        const int site = int_at(L.list, gl_off + ipos);
+        const int idst = int_at(L.dst, site * kMaxRank + il);
+        const double *raw = out + (ik * SPW + ij) * ND + il * D;
+        double n2 = 0.0, sum = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            n2 = fma(raw[i], raw[i], n2);
+            sum += raw[i];
+        }
+        const double nrm = sqrt(n2);
+        if (!(nrm > 0.0) || !isfinite(nrm)) {
+            *bad = 1;
+            continue;
+        }
+        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        double d1 = 0.0, d2 = 0.0;
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double v = sg * (raw[i] / nrm);
+            const double old = p_lds[mi + idst + i];
+            d1 = fmax(d1, fabs(v - old));
+            d2 = fmax(d2, fabs(v + old));
+            p_lds[mo + idst + i] = v;
+        }
+        res = fmax(res, fmin(d1, d2));
     }
     res = wave_max_p(res);
     wave_sync();
@@ -254,21 +426,21 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
             for (int c = wave; c < nchunks; c += kPWaves) {
                 double tr = 0.0;
                 switch (gr.dc * 8 + gr.rank) {
-                    case 17: tr = ptiles<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 18: tr = ptiles<2, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 19: tr = ptiles<2, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 20: tr = ptiles<2, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 21: tr = ptiles<2, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 22: tr = ptiles<2, 6>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 25: tr = ptiles<3, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 26: tr = ptiles<3, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 27: tr = ptiles<3, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 28: tr = ptiles<3, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 18: tr = ptiles_dpp<2, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 19: tr = ptiles_dpp<2, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 20: tr = ptiles_dpp<2, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 21: tr = ptiles_dpp<2, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 22: tr = ptiles_dpp<2, 6>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 25: tr = ptiles_dpp<3, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 26: tr = ptiles_dpp<3, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 27: tr = ptiles_dpp<3, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 28: tr = ptiles_dpp<3, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
                     case 29: tr = ptiles<3, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 33: tr = ptiles<4, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 34: tr = ptiles<4, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 35: tr = ptiles<4, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 36: tr = ptiles<4, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 33: tr = ptiles_dpp<4, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 34: tr = ptiles_dpp<4, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 35: tr = ptiles_dpp<4, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 36: tr = ptiles_dpp<4, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
                     case 37: tr = ptiles<4, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
                     case 41: tr = ptiles<5, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
                     case 42: tr = ptiles<5, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
@@ -315,9 +487,19 @@ size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave
 }
 
 int bp_persistent_tiles_in_flight(int dim, int rank) {
+    if (dpp_shape(dim, rank)) return dpp_tiles_in_flight(dim, rank);
     const int B = dim <= 2 ? 1 : (dim <= 4 ? 2 : 3);
     const int T = (6 / B) < rank ? (6 / B) : rank;
     return tiles_in_flight(ipw(dim, rank - T));
+}
+
+int bp_persistent_sites_per_tile(int dim, int rank) {
+    if (dpp_shape(dim, rank)) {
+        const int B = dim <= 2 ? 1 : 2;
+        const int T = rank < 2 ? rank : 2;
+        return 64 >> (B * T);
+    }
+    return bp_reg_sites_per_tile(dim, rank);
 }
 
 int bp_persistent_scratch(int spw, int rank, int dim) {

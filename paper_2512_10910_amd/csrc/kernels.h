@@ -76,6 +76,7 @@ hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStrea
 size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave);
 int bp_persistent_scratch(int spw, int rank, int dim);
 int bp_persistent_tiles_in_flight(int dim, int rank);
+int bp_persistent_sites_per_tile(int dim, int rank);
 hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 // shapes the register-path regauge handles (all legs of dimension dim)

@@ -446,7 +446,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     std::vector<int> fsite_list;
     std::vector<BpTile> loop_tiles;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
-    const size_t fused_budget = 76 * 1024 / 8;  // doubles of dynamic LDS per persistent block
+    const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
     size_t bp_lds = 0, fused_lds = 0;
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
@@ -512,7 +512,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
         int pscratch = 0;
         for (auto &kv : groups) {
             const SiteRec &r0 = sites[kv.second[0]];
-            const int spw = bp_reg_sites_per_tile(r0.dim[0], r0.rank);
+            const int spw = bp_persistent_sites_per_tile(r0.dim[0], r0.rank);
             if (spw > 0) pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0]));
         }
         const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch);
@@ -533,7 +533,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 std::memset(&fg, 0, sizeof fg);
                 fg.dc = r0.dim[0];
                 fg.rank = r0.rank;
-                fg.spw = bp_reg_sites_per_tile(fg.dc, fg.rank);
+                fg.spw = bp_persistent_sites_per_tile(fg.dc, fg.rank);
                 fg.nt = bp_persistent_tiles_in_flight(fg.dc, fg.rank);
                 fg.list_off = (int)fsite_list.size() - f.list_begin;
                 fg.n_sites = (int)kv.second.size();
