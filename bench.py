@@ -11,6 +11,8 @@ device tables are prepared once (they depend only on the lattice).
 
 Prints one JSON line.  Kernel durations come from HIP events the library
 records on its own stream around each launch during the timed steps.
+Results come back as one numpy structured array per step (no Python object
+per network).
 """
 
 from __future__ import annotations
@@ -42,10 +44,11 @@ def sweep_bytes(net) -> int:
 
 
 def regauge_bytes(net, slice_bytes: int) -> int:
-    """Site tensors read once (FP64), slices written once, gauge matrices read."""
+    """Site tensors read once (FP64), slices written once, and the two FP64
+    messages of every bond slot read (the gauge is built from them)."""
     b = 0
     for t in net.tensors:
-        b += 8 * t.size + slice_bytes * t.size + 8 * sum(d * d for d in t.shape)
+        b += 8 * t.size + slice_bytes * t.size + 2 * 8 * sum(t.shape)
     return b
 
 
@@ -101,28 +104,28 @@ def main():
     print(f"bench: prepared batch in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
-        batch.run(raise_on_error=True)
+        batch.run_arrays(raise_on_error=True)
     batch.kernel_times(reset=True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = None
     for _ in range(args.steps):
-        results = batch.run(raise_on_error=True)
+        results = batch.run_arrays(raise_on_error=True)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     kt = batch.kernel_times(reset=True)
     ms_step = (t1 - t0) * 1e3 / args.steps
     n_nets = len(nets)
-    terms = sum(r.n_cluster_terms for r in results)
+    terms = int(results["n_cluster_terms"].sum())
     nets_per_s = n_nets / (ms_step * 1e-3)
     print(f"bench: {ms_step:.3f} ms/step, {nets_per_s:.1f} networks/s", file=sys.stderr, flush=True)
 
     # roofline of the dominant kernel (by device time)
     slice_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
-    sweeps = [r.bp_iters for r in results]
+    sweeps = [int(x) for x in results["bp_iters"]]
     bytes_sweep = sum(s * sweep_bytes(n) for s, n in zip(sweeps, nets_in))
     bytes_regauge = sum(regauge_bytes(n, slice_bytes) for n in nets_in)
-    dom = max(("bp_persistent", "bp_sweep", "regauge", "clusters", "combine", "gauge"), key=lambda k: kt[k][0])
+    dom = max(("bp_persistent", "bp_sweep", "regauge", "clusters", "combine"), key=lambda k: kt[k][0])
     per_step_ms = {k: v[0] / args.steps for k, v in kt.items()}
     if dom in ("bp_sweep", "bp_persistent"):
         # every BP kernel of the step together performs all network-sweeps
@@ -186,9 +189,9 @@ def main():
         idx = list(range(min(args.check, args.nets))) + [args.nets + i for i in range(min(args.check, args.nets))]
         for i in idx:
             ref = O.pne_contract(nets_in[i], args.K)
-            d = abs(results[i].log_abs - ref.log_abs)
+            d = abs(float(results["log_abs"][i]) - ref.log_abs)
             errs.append(d / max(1.0, abs(ref.log_abs)))
-            if results[i].sign != ref.sign:
+            if int(results["sign"][i]) != ref.sign:
                 errs.append(math.inf)
         out["max_rel_err_log_vs_oracle"] = float(max(errs)) if errs else None
         out["accuracy_ok"] = bool(errs and max(errs) <= 1e-5)

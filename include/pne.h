@@ -162,7 +162,8 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
 /* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
  * measured with HIP events recorded on the context stream around each launch.
  * Index k: 0 init, 1 BP sweep (per-launch), 2 BP close, 3 persistent BP,
- * 4 bond gauge, 5 regauge / slices, 6 cluster contraction, 7 combine.  Writes n entries; reset != 0
+ * 4 bond gauge (no launches of its own: built inside the regauge kernels),
+ * 5 gauge + regauge / slices, 6 cluster contraction, 7 combine.  Writes n entries; reset != 0
  * clears the accumulators afterwards. */
 pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *launches, int32_t n,
                                   int32_t reset);

@@ -22,13 +22,10 @@ struct DeviceBatch {
     size_t fused_lds = 0;
     const int *tile_sites = nullptr;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
-    const BondRec *bonds = nullptr;
-    int n_bonds = 0;
     NetState *state = nullptr;
     int n_nets = 0;
     // buffers
     double *msg0 = nullptr, *msg1 = nullptr;
-    double *xg = nullptr;
     void *slices = nullptr;
     int precision = 0;
     double *site_log = nullptr;
@@ -59,7 +56,8 @@ struct DeviceBatch {
     NetResult *results = nullptr;
 };
 
-// kernel identifiers for per-kernel timing
+// kernel identifiers for per-kernel timing (KID_GAUGE stays as a slot: the
+// gauge is built inside the regauge kernels and has no launch of its own)
 enum KernelId { KID_INIT = 0, KID_SWEEP, KID_CLOSE, KID_FUSED, KID_GAUGE, KID_REGAUGE, KID_CLUSTERS, KID_COMBINE, KID_COUNT };
 
 // threads per BP tile and dynamic LDS (doubles) of one BP tile
@@ -77,7 +75,6 @@ size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave
 int bp_persistent_scratch(int spw, int rank, int dim);
 int bp_persistent_tiles_in_flight(int dim, int rank);
 int bp_persistent_sites_per_tile(int dim, int rank);
-hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 // shapes the register-path regauge handles (all legs of dimension dim)
 bool regauge_reg_supported(int dim, int rank);

@@ -1,10 +1,10 @@
 // gfx950 kernels of the partitioned network expansion hot path.
 //
 //   (BP sweeps live in bp.hip)
-//   k_gauge     per bond: rank-1 projector from the two messages in the
-//               symmetrising gauge of Appendix B (P = e0 e0^T, Q = the rest)
-//   k_regauge   per site: apply the bond gauges, split off the vacuum factor,
-//               store the excited slices in the term precision
+//   k_regauge   per site: build each bond's rank-1 projector from its two
+//               messages in the symmetrising gauge of Appendix B (P = e0 e0^T,
+//               Q = the rest), apply it, split off the vacuum factor and store
+//               the excited slices in the term precision
 //   k_clusters  per cluster instance: contract the excited slices (the loop
 //               terms of Sec. III.A-B; every term keeps the original geometry
 //               with modified tensors, Sec. VI)
@@ -62,23 +62,22 @@ struct SliceIO<uint16_t> {
 
 // ---------------------------------------------------------------------------
 
-// Per bond: with a = message arriving at the first site, c = message
-// arriving at the second site and n = a.c, the gauge G = [a/n | R] (R an
-// orthonormal basis of the complement of c, from one Householder reflection)
-// has inverse [c^T ; R^T (I - a c^T / n)].  Inserting G G^-1 on the bond makes
-// the rank-1 projector a c^T / n equal to e0 e0^T, so Q = I - P keeps exactly
-// the indices 1..d-1.  The first site's slot is multiplied by G, the second
-// site's slot by G^-1 (stored transposed so both use T'[.k.] = sum_i T[.i.] X[i,k]).
-__global__ void k_gauge(const BondRec *__restrict__ bonds, int n_bonds, const double *msg0,
-                        const double *msg1, NetState *st, double *__restrict__ xg) {
-    int b = blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= n_bonds) return;
-    const BondRec br = bonds[b];
-    NetState *ns = st + br.net;
-    const double *m = ns->parity ? msg1 : msg0;
-    const double *a = m + br.a_off;
-    const double *c = m + br.c_off;
-    const int D = br.dim;
+// Gauge of Appendix B for one bond slot, built from the bond's two messages.
+// With a = message arriving at the bond's first site, c = message arriving at
+// its second site and n = a.c, G = [a/n | R] (R = columns 1..d-1 of the
+// Householder reflection that maps c/|c| onto the e0 axis, an orthonormal
+// basis of c's complement) has inverse [c^T ; R^T (I - a c^T / n)].  Inserting
+// G G^-1 on the bond turns P = a c^T / n into e0 e0^T, so Q keeps exactly the
+// indices 1..d-1.  The first site's slot is multiplied by G, the second
+// site's by the transpose of G^-1, both as T'[.k.] = sum_i T[.i.] X[i,k].
+// Each endpoint site builds the transform itself (no per-bond table).
+struct LegGauge {
+    double inv_n, inv_nc, u0, t, ua;  // t = 2/|u|^2 with u = c/|c| - alpha e0; ua = u.a
+    bool ok;                          // false: |n| ~ 0 relative to |a||c| (SINGULAR)
+};
+
+__device__ inline LegGauge leg_gauge_setup(const double *a, const double *c, int D) {
+    LegGauge g;
     double n = 0.0, na = 0.0, nc = 0.0;
     for (int i = 0; i < D; ++i) {
         n = fma(a[i], c[i], n);
@@ -87,44 +86,33 @@ __global__ void k_gauge(const BondRec *__restrict__ bonds, int n_bonds, const do
     }
     na = sqrt(na);
     nc = sqrt(nc);
-    double *Xu = xg + br.xu_off;
-    double *Xv = xg + br.xv_off;
-    if (!(fabs(n) >= 1e-12 * na * nc) || !isfinite(n)) {
-        atomicMin(&ns->status, -4);
-        for (int i = 0; i < D * D; ++i) {
-            Xu[i] = (i % (D + 1) == 0) ? 1.0 : 0.0;
-            Xv[i] = Xu[i];
-        }
-        return;
-    }
-    // Householder vector u = c/|c| - alpha e0 with alpha = -sign(c0)
-    const double v0 = c[0] / nc;
+    g.ok = (fabs(n) >= 1e-12 * na * nc) && isfinite(n) && nc > 0.0;
+    g.inv_n = 1.0 / n;
+    g.inv_nc = 1.0 / nc;
+    const double v0 = c[0] * g.inv_nc;
     const double alpha = v0 > 0.0 ? -1.0 : 1.0;
-    const double u0 = v0 - alpha;
-    double uu = u0 * u0;
-    for (int i = 1; i < D; ++i) uu = fma(c[i] / nc, c[i] / nc, uu);
-    const double inv_n = 1.0 / n;
-    for (int i = 0; i < D; ++i) {
-        Xu[i * D] = a[i] * inv_n;
-        Xv[i * D] = c[i];
+    g.u0 = v0 - alpha;
+    double uu = g.u0 * g.u0, ua = g.u0 * a[0];
+    for (int i = 1; i < D; ++i) {
+        const double ui = c[i] * g.inv_nc;
+        uu = fma(ui, ui, uu);
+        ua = fma(ui, a[i], ua);
     }
-    for (int k = 1; k < D; ++k) {
-        const double uk = c[k] / nc;
-        // column k of the reflection: r_i = delta_ik - 2 u_i u_k / uu
-        double ra = 0.0;
-        for (int i = 0; i < D; ++i) {
-            const double ui = (i == 0) ? u0 : c[i] / nc;
-            const double r = (i == k ? 1.0 : 0.0) - 2.0 * ui * uk / uu;
-            Xu[i * D + k] = r;
-            ra = fma(r, a[i], ra);
-        }
-        const double f = ra * inv_n;
-        for (int j = 0; j < D; ++j) {
-            const double uj = (j == 0) ? u0 : c[j] / nc;
-            const double r = (j == k ? 1.0 : 0.0) - 2.0 * uj * uk / uu;
-            Xv[j * D + k] = r - f * c[j];
-        }
-    }
+    g.t = 2.0 / uu;
+    g.ua = ua;
+    return g;
+}
+
+// X[i,k] of the slot transform; ak = a[k], ck = c[k], ai = a[i], ci = c[i].
+__device__ inline double leg_gauge_x(const LegGauge &g, bool vside, int i, int k, double ai, double ci, double ak,
+                                     double ck) {
+    if (!g.ok) return i == k ? 1.0 : 0.0;
+    if (k == 0) return vside ? ci : ai * g.inv_n;
+    const double ui = i == 0 ? g.u0 : ci * g.inv_nc;
+    const double uk = ck * g.inv_nc;
+    double r = (i == k ? 1.0 : 0.0) - g.t * ui * uk;
+    if (vside) r -= (ak - g.t * uk * g.ua) * g.inv_n * ci;
+    return r;
 }
 
 // Per site (one block): apply the gauge of every bond slot (mode products in
@@ -135,7 +123,8 @@ __global__ void k_gauge(const BondRec *__restrict__ bonds, int n_bonds, const do
 template <typename S>
 __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restrict__ sites,
                                                         const int *__restrict__ rg_sites,
-                                                        const double *__restrict__ xg, S *__restrict__ slices,
+                                                        const double *msg0, const double *msg1,
+                                                        S *__restrict__ slices,
                                                         double *__restrict__ site_log, int *__restrict__ site_sign,
                                                         double *__restrict__ vac, NetState *st) {
     const int gsite = rg_sites[blockIdx.x];
@@ -149,12 +138,21 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
     double *b0 = lds;
     double *b1 = lds + size;
     for (int e = tid; e < size; e += kRgThreads) b0[e] = r.t[e];
-    int xoff = 0;
+    const double *mb = st[r.net].parity ? msg1 : msg0;
     for (int l = 0; l < r.rank; ++l) {
         const int d = r.dim[l];
         if (!((r.open_mask >> l) & 1)) {
+            const bool vs = (r.vside_mask >> l) & 1;
+            const double *pin = mb + r.msg_off + r.moff[l];
+            const double *pout = mb + r.dst[l];
+            const double *pa = vs ? pout : pin;
+            const double *pc = vs ? pin : pout;
             __syncthreads();
-            for (int e = tid; e < d * d; e += kRgThreads) s_x[e] = xg[r.xg_off + xoff + e];
+            for (int k = tid; k < d; k += kRgThreads) {  // one column of X per thread
+                const LegGauge g = leg_gauge_setup(pa, pc, d);
+                if (k == 0 && !g.ok) atomicMin(&st[r.net].status, -4);
+                for (int i = 0; i < d; ++i) s_x[i * d + k] = leg_gauge_x(g, vs, i, k, pa[i], pc[i], pa[k], pc[k]);
+            }
             __syncthreads();
             const int sl = r.stride[l];
             for (int e = tid; e < size; e += kRgThreads) {
@@ -168,7 +166,6 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
             b0 = b1;
             b1 = t;
         }
-        xoff += d * d;
     }
     __syncthreads();
     if (tid == 0) {
@@ -227,10 +224,15 @@ constexpr int rg_ipow(int b, int e) { return e <= 0 ? 1 : b * rg_ipow(b, e - 1);
 // index NL values per lane.  A gauge on a register leg is an in-lane mode
 // product; a gauge on a lane leg gathers the D values of the leg with
 // shuffles.  The vacuum factor T'[0,...,0] sits in the segment's first lane.
+// LDS doubles for the slot transforms of one register-path regauge tile:
+// (sites per tile) * rank * D^2, largest for D=6 rank 1 (8 sites * 36).
+constexpr int kRgXgMax = 288;
+
 template <int D, int R, typename S>
 __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
-                            const double *__restrict__ xg, S *__restrict__ slices, double *__restrict__ site_log,
-                            int *__restrict__ site_sign, NetState *st) {
+                            const double *msg0, const double *msg1, S *__restrict__ slices,
+                            double *__restrict__ site_log, int *__restrict__ site_sign, NetState *st,
+                            double *__restrict__ xs) {
     constexpr int P = D <= 2 ? 2 : (D <= 4 ? 4 : 8);
     constexpr int B = P == 2 ? 1 : (P == 4 ? 2 : 3);
     constexpr int T = (6 / B) < R ? (6 / B) : R;
@@ -238,7 +240,42 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
     constexpr int LS = 1 << (B * T);
     constexpr int NL = rg_ipow(D, NLEG);
     constexpr int DT = rg_ipow(D, T);
+    static_assert((64 / LS) * R * D * D <= kRgXgMax, "slot transforms exceed the LDS table");
     const int lane = threadIdx.x & 63;
+    const double *mb = st[tl.net].parity ? msg1 : msg0;
+    // Phase 1: the tile's slot transforms X (site, slot, D x D) into LDS, one
+    // column per lane: each (site, slot) runs the gauge set-up once per column
+    // instead of once per lane of the site.
+    for (int j = lane; j < tl.n_sites * R * D; j += 64) {
+        const int s = j / (R * D);
+        const int l = (j / D) % R;
+        const int k = j % D;
+        const SiteRec &q = sites[tile_sites[tl.site_begin + s]];
+        const bool vs = (q.vside_mask >> l) & 1;
+        const double *pin = mb + q.msg_off + q.moff[l];
+        const double *pout = mb + q.dst[l];
+        double a[D], c[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double x = pin[i], y = pout[i];
+            a[i] = vs ? y : x;
+            c[i] = vs ? x : y;
+        }
+        const LegGauge g = leg_gauge_setup(a, c, D);
+        if (k == 0 && !g.ok) atomicMin(&st[tl.net].status, -4);
+        double ak = a[0], ck = c[0];
+#pragma unroll
+        for (int i = 1; i < D; ++i)
+            if (k == i) {
+                ak = a[i];
+                ck = c[i];
+            }
+        double *X = xs + (s * R + l) * D * D;
+#pragma unroll
+        for (int i = 0; i < D; ++i) X[i * D + k] = leg_gauge_x(g, vs, i, k, a[i], c[i], ak, ck);
+    }
+    __syncthreads();
+    // Phase 2: apply the transforms to the site tensors held across lanes.
     const int slot = lane / LS;
     const int tb = lane - slot * LS;
     bool act = slot < tl.n_sites;
@@ -250,10 +287,11 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
         act = act && dig[m] < D;
         toff = toff * D + (dig[m] < D ? dig[m] : 0);
     }
-    const int gsite = tile_sites[tl.site_begin + (slot < tl.n_sites ? slot : 0)];
+    const int sl = slot < tl.n_sites ? slot : 0;
+    const int gsite = tile_sites[tl.site_begin + sl];
     const SiteRec &sr = sites[gsite];
     const double *tp = sr.t;
-    const double *X0 = xg + sr.xg_off;
+    const double *X0 = xs + sl * R * D * D;
     double v[NL];
 #pragma unroll
     for (int q = 0; q < NL; ++q) v[q] = act ? tp[q * DT + toff] : 0.0;
@@ -261,8 +299,6 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
 #pragma unroll
     for (int k = 0; k < NLEG; ++k) {
         const double *X = X0 + k * D * D;
-        constexpr int dummy = 0;
-        (void)dummy;
         double w[NL];
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
@@ -280,12 +316,13 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
     // lane (trailing) legs
 #pragma unroll
     for (int m = 0; m < T; ++m) {
-        const double *X = X0 + (NLEG + m) * D * D;
         const int shift = B * (T - 1 - m);
         const int field_clear = lane & ~((P - 1) << shift);
+        const double *X = X0 + (NLEG + m) * D * D;
+        const int kk = dig[m] < D ? dig[m] : 0;
         double xc[D];
 #pragma unroll
-        for (int i = 0; i < D; ++i) xc[i] = X[i * D + (dig[m] < D ? dig[m] : 0)];
+        for (int i = 0; i < D; ++i) xc[i] = X[i * D + kk];
 #pragma unroll
         for (int q = 0; q < NL; ++q) {
             double acc = 0.0;
@@ -299,8 +336,9 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
     const bool ok = (fabs(z) > 0.0) && isfinite(z);
     if (act) {
         const int64_t so = sr.slice_off;
+        const double iz = ok ? 1.0 / z : 0.0;
 #pragma unroll
-        for (int q = 0; q < NL; ++q) SliceIO<S>::store(slices, so + q * DT + toff, ok ? v[q] / z : 0.0);
+        for (int q = 0; q < NL; ++q) SliceIO<S>::store(slices, so + q * DT + toff, v[q] * iz);
     }
     if (tb == 0 && slot < tl.n_sites) {
         site_log[gsite] = ok ? log(fabs(z)) : 0.0;
@@ -312,29 +350,31 @@ __device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
 template <typename S>
 __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__ tiles, const int *__restrict__ rg_tiles,
                                                       const SiteRec *__restrict__ sites,
-                                                      const int *__restrict__ tile_sites, const double *__restrict__ xg,
-                                                      S *__restrict__ slices, double *__restrict__ site_log,
+                                                      const int *__restrict__ tile_sites, const double *msg0,
+                                                      const double *msg1, S *__restrict__ slices,
+                                                      double *__restrict__ site_log,
                                                       int *__restrict__ site_sign, NetState *st) {
     const BpTile tl = tiles[rg_tiles[blockIdx.x]];
+    __shared__ double s_xg[kRgXgMax];
     switch (tl.dc * 8 + tl.rank) {
-        case 17: regauge_reg<2, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 18: regauge_reg<2, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 19: regauge_reg<2, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 20: regauge_reg<2, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 21: regauge_reg<2, 5, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 22: regauge_reg<2, 6, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 25: regauge_reg<3, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 26: regauge_reg<3, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 27: regauge_reg<3, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 28: regauge_reg<3, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 33: regauge_reg<4, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 34: regauge_reg<4, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 35: regauge_reg<4, 3, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 36: regauge_reg<4, 4, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 41: regauge_reg<5, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 42: regauge_reg<5, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 49: regauge_reg<6, 1, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
-        case 50: regauge_reg<6, 2, S>(tl, sites, tile_sites, xg, slices, site_log, site_sign, st); break;
+        case 17: regauge_reg<2, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 18: regauge_reg<2, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 19: regauge_reg<2, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 20: regauge_reg<2, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 21: regauge_reg<2, 5, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 22: regauge_reg<2, 6, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 25: regauge_reg<3, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 26: regauge_reg<3, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 27: regauge_reg<3, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 28: regauge_reg<3, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 33: regauge_reg<4, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 34: regauge_reg<4, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 35: regauge_reg<4, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 36: regauge_reg<4, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 41: regauge_reg<5, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 42: regauge_reg<5, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 49: regauge_reg<6, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
+        case 50: regauge_reg<6, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
         default: break;
     }
 }
@@ -651,13 +691,6 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__rest
 
 }  // namespace
 
-hipError_t launch_gauge(const DeviceBatch &b, hipStream_t s) {
-    if (b.n_bonds > 0)
-        hipLaunchKernelGGL(k_gauge, dim3((b.n_bonds + 127) / 128), dim3(128), 0, s, b.bonds, b.n_bonds, b.msg0,
-                           b.msg1, b.state, b.xg);
-    return hipGetLastError();
-}
-
 bool regauge_reg_supported(int dim, int rank) {
     if (dim < 2 || dim > 6 || rank < 1 || rank > 6) return false;
     const int B = dim <= 2 ? 1 : (dim <= 4 ? 2 : 3);
@@ -669,10 +702,10 @@ template <typename S>
 static void launch_regauge_t(const DeviceBatch &b, hipStream_t s) {
     if (b.n_rg_tiles)
         hipLaunchKernelGGL(k_regauge_tiles<S>, dim3(b.n_rg_tiles), dim3(64), 0, s, b.all_tiles, b.rg_tiles, b.sites,
-                           b.tile_sites, b.xg, (S *)b.slices, b.site_log, b.site_sign, b.state);
+                           b.tile_sites, b.msg0, b.msg1, (S *)b.slices, b.site_log, b.site_sign, b.state);
     if (b.n_rg_sites)
         hipLaunchKernelGGL(k_regauge<S>, dim3(b.n_rg_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites, b.rg_sites,
-                           b.xg, (S *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+                           b.msg0, b.msg1, (S *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
 }
 
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s) {

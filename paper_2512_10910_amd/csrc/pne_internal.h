@@ -16,7 +16,7 @@ struct SiteRec {
     const double *t;      // input tensor, FP64, C order over slots
     int64_t slice_off;    // element offset of the regauged slices in the slice arena
     int32_t msg_off;      // offset of the site's incoming messages (slot-major)
-    int32_t xg_off;       // offset of the site's leg transforms (d*d per bond slot)
+    int32_t vside_mask;   // bit l set when this site is the second site of slot l's bond
     int32_t rank;
     int32_t size;         // product of dims
     int32_t net;          // network index in the batch
@@ -66,16 +66,6 @@ struct FusedGroup {
     int32_t n_sites;
     int32_t nt;           // tiles per wavefront step
     int32_t pad1, pad2;
-};
-
-// One bond of one network (device table for the gauge kernel).
-struct BondRec {
-    int32_t net;
-    int32_t dim;
-    int32_t a_off;   // incoming message at the bond's first site (absolute)
-    int32_t c_off;   // incoming message at the bond's second site (absolute)
-    int32_t xu_off;  // transform applied to the first site's slot
-    int32_t xv_off;  // transform applied to the second site's slot
 };
 
 // Per-network BP state.  Sweep k reads message buffer k&1, writes buffer

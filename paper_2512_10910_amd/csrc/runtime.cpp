@@ -51,6 +51,7 @@ struct pne_batch {
     size_t bytes = 0;
     DeviceBatch db;
     NetState *h_state_pinned = nullptr;  // pinned copy of the per-network state
+    NetResult *h_results_pinned = nullptr;  // pinned copy of the per-network results
     int first_chunk = 4;                 // sweeps before the first convergence check
     bool launched = false;
     bool waited = false;
@@ -59,7 +60,6 @@ struct pne_batch {
     std::vector<hipEvent_t> ev_pool;
     double kt_ms[KID_COUNT] = {0};
     int64_t kt_n[KID_COUNT] = {0};
-    std::vector<NetResult> h_results;
     std::vector<NetState> h_state;
     int64_t msg_total = 0;
     std::vector<int> msg_off;  // per global site
@@ -193,6 +193,8 @@ void free_batch(pne_batch *b) {
     b->allocs.clear();
     if (b->h_state_pinned) (void)hipHostFree(b->h_state_pinned);
     b->h_state_pinned = nullptr;
+    if (b->h_results_pinned) (void)hipHostFree(b->h_results_pinned);
+    b->h_results_pinned = nullptr;
     if (b->ctx) b->ctx->used -= std::min(b->ctx->used, b->bytes);
 }
 
@@ -356,9 +358,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
 
     // sites, messages, transforms, slices
     std::vector<SiteRec> sites;
-    std::vector<BondRec> bonds;
     std::vector<int> net_of_site;
-    int64_t msg = 0, xg = 0, sl = 0, vac = 0;
+    int64_t msg = 0, sl = 0, vac = 0;
     size_t max_size = 1;
     b->site_base.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -371,10 +372,9 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             r.net = i;
             r.rank = g.rank[s];
             r.msg_off = (int)msg;
-            r.xg_off = (int)xg;
             r.slice_off = sl;
             r.vac_off = -1;
-            int size = 1, mo = 0, xo = 0, omask = 0, nopen = 1;
+            int size = 1, mo = 0, omask = 0, nopen = 1;
             for (int l = r.rank - 1; l >= 0; --l) {
                 r.stride[l] = size;
                 size *= g.dim[g.slot(s, l)];
@@ -384,7 +384,6 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 r.dim[l] = d;
                 r.moff[l] = mo;
                 mo += d;
-                xo += d * d;
                 if (g.is_open[g.slot(s, l)]) {
                     omask |= 1 << l;
                     nopen *= d;
@@ -398,13 +397,12 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             }
             max_size = std::max(max_size, (size_t)size);
             msg += mo;
-            xg += xo;
             sl += size;
             sites.push_back(r);
             net_of_site.push_back(i);
         }
     }
-    if (msg > INT32_MAX || xg > INT32_MAX) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: batch too large");
+    if (msg > INT32_MAX) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: batch too large");
     // partner destinations
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
@@ -418,21 +416,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 r.dst[l] = sites[base + ps].msg_off + sites[base + ps].moff[pl];
             }
         }
-        for (int bb = 0; bb < g.n_bonds; ++bb) {
-            const SiteRec &ru = sites[base + g.bu[bb]];
-            const SiteRec &rv = sites[base + g.bv[bb]];
-            BondRec br;
-            br.net = i;
-            br.dim = ru.dim[g.bul[bb]];
-            br.a_off = ru.msg_off + ru.moff[g.bul[bb]];
-            br.c_off = rv.msg_off + rv.moff[g.bvl[bb]];
-            int xu = 0, xv = 0;
-            for (int l = 0; l < g.bul[bb]; ++l) xu += ru.dim[l] * ru.dim[l];
-            for (int l = 0; l < g.bvl[bb]; ++l) xv += rv.dim[l] * rv.dim[l];
-            br.xu_off = ru.xg_off + xu;
-            br.xv_off = rv.xg_off + xv;
-            bonds.push_back(br);
-        }
+        for (int bb = 0; bb < g.n_bonds; ++bb) sites[base + g.bv[bb]].vside_mask |= 1 << g.bvl[bb];
     }
     b->msg_total = msg;
 
@@ -674,7 +658,6 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     db.n_rg_tiles = (int)rg_tiles.size();
     db.n_rg_sites = (int)rg_sites.size();
     UP(tile_sites, tile_sites);
-    UP(bonds, bonds);
     UP(classes, classes);
     UP(steps, steps);
     UP(cblocks, cblocks);
@@ -693,7 +676,6 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     db.n_tiles = (int)loop_tiles.size();
     db.n_fused = (int)fused.size();
     db.fused_lds = fused_lds;
-    db.n_bonds = (int)bonds.size();
     db.n_nets = n;
     db.n_cblocks = (int)cblocks.size();
     db.bp_lds = bp_lds;
@@ -708,7 +690,6 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     AL(sizeof(NetState) * n, state, NetState *);
     AL(sizeof(double) * msg, msg0, double *);
     AL(sizeof(double) * msg, msg1, double *);
-    AL(sizeof(double) * std::max<int64_t>(xg, 1), xg, double *);
     AL(esz * std::max<int64_t>(sl, 1), slices, void *);
     AL(sizeof(double) * sites.size(), site_log, double *);
     AL(sizeof(int) * sites.size(), site_sign, int *);
@@ -721,7 +702,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
     }
     ctx->used += b->bytes;
-    if (hipHostMalloc((void **)&b->h_state_pinned, sizeof(NetState) * n, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&b->h_state_pinned, sizeof(NetState) * n, hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void **)&b->h_results_pinned, sizeof(NetResult) * n, hipHostMallocDefault) != hipSuccess) {
         free_batch(b.get());
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
     }
@@ -775,7 +757,6 @@ pne_status pne_batch_launch(pne_batch *b) {
     }
     if (sweep == 0) sweep = 1;  // only persistent networks: close is a no-op for them
     HIP_TRY(ctx, timed(b, KID_CLOSE, [&](hipStream_t st) { return launch_close(db, sweep - 1, tol, st); }));
-    HIP_TRY(ctx, timed(b, KID_GAUGE, [&](hipStream_t st) { return launch_gauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_REGAUGE, [&](hipStream_t st) { return launch_regauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_CLUSTERS, [&](hipStream_t st) { return launch_clusters(db, st); }));
     HIP_TRY(ctx, timed(b, KID_COMBINE, [&](hipStream_t st) { return launch_combine(db, st); }));
@@ -788,19 +769,18 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
     if (!b || !b->launched) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "batch not launched");
     pne_ctx *ctx = b->ctx;
     const int n = (int)b->nets.size();
-    b->h_results.resize(n);
-    b->h_state.resize(n);
-    HIP_TRY(ctx, hipMemcpyAsync(b->h_results.data(), b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
+    HIP_TRY(ctx, hipMemcpyAsync(b->h_results_pinned, b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
                                 ctx->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(b->h_state.data(), b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost,
+    HIP_TRY(ctx, hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost,
                                 ctx->stream));
     HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+    b->h_state.assign(b->h_state_pinned, b->h_state_pinned + n);
     collect_times(b);
     b->waited = true;
     if (!results) return PNE_OK;
     pne_status worst = PNE_OK;
     for (int i = 0; i < n; ++i) {
-        const NetResult &r = b->h_results[i];
+        const NetResult &r = b->h_results_pinned[i];
         const NetState &s = b->h_state[i];
         const GeoPlan &p = *b->plans[i];
         pne_result &o = results[i];

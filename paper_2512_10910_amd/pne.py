@@ -74,6 +74,19 @@ class ResultStruct(ctypes.Structure):
     ]
 
 
+# numpy view of pne_result (same field offsets as the C struct)
+RESULT_DTYPE = np.dtype({
+    "names": ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
+              "n_cluster_terms", "n_config_terms", "open_values", "open_capacity"],
+    "formats": [np.int32, np.int32, np.float64, np.float64, np.int32, np.int32, np.float64, np.int64, np.int64,
+                np.uint64, np.int64],
+    "offsets": [getattr(ResultStruct, f).offset for f in
+                ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
+                 "n_cluster_terms", "n_config_terms", "open_values", "open_capacity"]],
+    "itemsize": ctypes.sizeof(ResultStruct),
+})
+
+
 # exported C symbols and their prototypes: (restype, argtypes)
 _PROTOS = {
     "pne_options_default": (ctypes.c_int, [ctypes.POINTER(Options)]),
@@ -376,6 +389,27 @@ class Batch:
     def run(self, raise_on_error: bool = False):
         self.launch()
         return self.wait(raise_on_error)
+
+    def wait_arrays(self, raise_on_error: bool = False) -> np.ndarray:
+        """Like wait(), but returns the per-network results as one numpy
+        structured array (fields of RESULT_DTYPE), without building a Python
+        object per network.  Open-index values stay in open_values(i)."""
+        st = self.ctx.lib.pne_batch_wait(self.handle, self._res)
+        arr = np.frombuffer(self._res, dtype=RESULT_DTYPE, count=len(self.nets)).copy()
+        if raise_on_error or (st < 0 and not (arr["status"] < 0).any()):
+            _check(self.ctx.lib, st, self.ctx.handle)
+        return arr
+
+    def run_arrays(self, raise_on_error: bool = False) -> np.ndarray:
+        self.launch()
+        return self.wait_arrays(raise_on_error)
+
+    def open_values(self, i: int) -> np.ndarray | None:
+        """Open-index output of network i from the last wait (rescaled: the
+        contraction is open_values * exp(log_abs))."""
+        net = self.nets[i]
+        m = int(self._res[i].n_open_values)
+        return self._open[i][:m].copy().reshape(net.open_shape) if net.n_open and m else None
 
     def kernel_times(self, reset: bool = False):
         """{kernel: (total ms, launches)} from HIP events (profile=True batches)."""

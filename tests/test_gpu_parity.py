@@ -267,3 +267,62 @@ def test_config3_aklt_12x12(ctx):
     g = P.config3_aklt_network(gauge_seed=3000)
     r, _, _ = _run(ctx, g, 8)
     assert abs(r.log_abs - ref.log_abs) < 1e-9
+
+
+def test_run_arrays_matches_run(ctx):
+    nets = [ctx.network(P.random_2d(4, 4, 3, "uniform01", seed=50 + i)) for i in range(3)]
+    nets.append(ctx.network(P.random_2d(4, 4, 3, "uniform01", seed=53, open_sites={5: 2, 6: 2})))
+    b = ctx.batch(nets, K=6)
+    objs = b.run()
+    arr = b.run_arrays()
+    for i, r in enumerate(objs):
+        assert arr["log_abs"][i] == r.log_abs and arr["sign"][i] == r.sign
+        assert arr["status"][i] == r.status and arr["bp_iters"][i] == r.bp_iters
+        assert arr["n_cluster_terms"][i] == r.n_cluster_terms and arr["n_config_terms"][i] == r.n_config_terms
+    np.testing.assert_array_equal(b.open_values(3), objs[3].open_values)
+    assert b.open_values(0) is None
+
+
+def _config5_ref():
+    import json
+    import os
+
+    path = os.path.join(os.path.dirname(__file__), "golden", "config5_oracle.json")
+    with open(path) as f:
+        return json.load(f)["results"]
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 6, 7, 8])
+def test_config5_open_32x32_fp64(ctx, d):
+    """32x32 D=6 with two open legs at separation d, K=8, against the stored
+    oracle outputs (written by tests/golden/make_config5.py)."""
+    ref = _config5_ref()[str(d)]
+    net = P.config5_network(d)
+    r, _, _ = _run(ctx, net, 8)
+    assert r.status >= 0, r.status
+    assert r.n_cluster_terms == ref["n_clusters"]
+    assert r.n_config_terms == ref["n_configs"]
+    assert abs(r.bp_iters - ref["bp_iters"]) <= 1
+    o = np.asarray(ref["values"])
+    g = r.open_values * math.exp(r.log_abs - ref["log_scale"])
+    err = np.linalg.norm(g - o) / np.linalg.norm(o)
+    assert err <= 1e-10, f"eps2={err:.3e}"
+
+
+@pytest.mark.parametrize("precision", ["fp32", "bf16"])
+def test_config5_open_32x32_reduced(ctx, precision):
+    ref = _config5_ref()["3"]
+    net = P.config5_network(3)
+    r, _, _ = _run(ctx, net, 8, precision)
+    assert r.status >= 0, r.status
+    o = np.asarray(ref["values"])
+    g = r.open_values * math.exp(r.log_abs - ref["log_scale"])
+    err = np.linalg.norm(g - o) / np.linalg.norm(o)
+    # log-contraction bound on the entries' common scale
+    rel_log = abs(math.log(np.linalg.norm(g)) - math.log(np.linalg.norm(o))) / max(1.0, abs(ref["log_scale"]))
+    print(f"config5 d=3 {precision}: eps2={err:.3e} rel_log={rel_log:.3e}")
+    assert rel_log <= 1e-5
+    # slices rounded once to the term precision (unit roundoff 2^-24 / 2^-9);
+    # the loop corrections are ~1e-3 of the output here, so the bound on
+    # eps2 is a few roundoffs times that fraction
+    assert err <= {"fp32": 1e-8, "bf16": 1e-5}[precision], f"eps2={err:.3e}"
