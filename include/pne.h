@@ -53,6 +53,18 @@ typedef enum {
 /* pne_options.flags bits */
 #define PNE_FLAG_PROFILE 1u /* time every kernel launch with HIP events on the context stream */
 #define PNE_FLAG_NO_PERSISTENT 2u /* sweep every network launch by launch (no persistent BP kernel) */
+#define PNE_FLAG_BP_JACOBI 4u /* persistent BP: Jacobi sweeps even on bipartite networks (see below) */
+
+/* BP schedule.  Jacobi: every sweep updates every message from the previous
+ * sweep's messages.  On a bipartite network (two site colours, every bond
+ * joining different colours) the persistent kernel by default runs the
+ * red-black schedule instead: step t updates only the messages leaving sites
+ * of colour t mod 2, in place.  Its messages after step t equal Jacobi's on
+ * one of the two independent message chains Jacobi carries on such a graph,
+ * so it reaches the same fixed point in about as many steps while reading
+ * half the site tensors per step.  It stops once two consecutive steps (both
+ * colours) change no message by more than bp_tol; bp_iters then counts
+ * steps.  The per-launch path always runs Jacobi sweeps. */
 
 /* Precision of the excited slices and the cluster (term) contractions.  BP,
  * the bond gauge, vacuum log-norms and the cross-term sum are FP64 always. */
@@ -95,7 +107,7 @@ typedef struct {
     int32_t sign;            /* +1, -1 (0 if Z == 0)                            */
     double log_abs;          /* ln|Z| (closed) or the log-scale (open)          */
     double log_abs_bp;       /* ln|Z_BP| (closed) or the vacuum log-scale       */
-    int32_t bp_iters;        /* sweeps performed                                 */
+    int32_t bp_iters;        /* sweeps (red-black schedule: steps) performed    */
     int32_t n_open_values;   /* number of entries written to open_values        */
     double bp_residual;      /* last sweep's residual                            */
     int64_t n_cluster_terms; /* connected dangling-free clusters contracted      */

@@ -1,5 +1,7 @@
 // Persistent belief propagation: one block runs every sweep of one network
-// (Sec. II.B fixed-point messages; open legs are not handled here).
+// (Sec. II.B fixed-point messages; open legs are not handled here).  A
+// bipartite network runs the red-black schedule in one message buffer (see
+// the kernel), any other network Jacobi sweeps in two.
 //
 // The network's two message buffers, its site table (tensor pointer, local
 // message offsets) and the site order of its tiles are staged in LDS once.
@@ -392,10 +394,11 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int ns_ = fn.n_sites;
+    const bool rb = fn.colors == 2;  // red-black schedule: one buffer, updated in place
     PLayout L;
     L.b0 = 0;
-    L.b1 = fn.msg_size;
-    L.tptr = 2 * fn.msg_size;
+    L.b1 = rb ? 0 : fn.msg_size;
+    L.tptr = (rb ? 1 : 2) * fn.msg_size;
     L.moff = L.tptr + ns_;
     L.dst = L.moff + (ns_ + 1) / 2;
     L.list = L.dst + (ns_ * kMaxRank + 1) / 2;
@@ -413,17 +416,26 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     if (tid == 0) s_bad = 0;
     __syncthreads();
     int sweep = 0;
-    double r = 0.0;
+    double r = 0.0, r_prev = 0.0;
     bool conv = false;
     for (sweep = 0; sweep < max_iter; ++sweep) {
+        // Jacobi: read buffer sweep&1, write the other.  Red-black: sites of
+        // colour sweep&1 read their incoming messages and overwrite their
+        // outgoing ones (the incoming messages of the other colour), so no
+        // message is read and written in the same step.
         const int mi = (sweep & 1) ? L.b1 : L.b0;
         const int mo = (sweep & 1) ? L.b0 : L.b1;
         double wres = 0.0;
+        // chunks of all groups in one sequence, dealt round-robin to the waves
+        int cbase = 0;
         for (int g = 0; g < fn.n_groups; ++g) {
             const FusedGroup gr = groups[fn.group_begin + g];
+            if (rb && gr.color != (sweep & 1)) continue;
             const int per_chunk = gr.nt * gr.spw;
             const int nchunks = (gr.n_sites + per_chunk - 1) / per_chunk;
-            for (int c = wave; c < nchunks; c += kPWaves) {
+            const int c0 = ((wave - cbase) % kPWaves + kPWaves) % kPWaves;
+            cbase += nchunks;
+            for (int c = c0; c < nchunks; c += kPWaves) {
                 double tr = 0.0;
                 switch (gr.dc * 8 + gr.rank) {
                     case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
@@ -460,19 +472,21 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         const int bad = s_bad;
         __syncthreads();
         if (bad) break;
-        if (r <= tol) {
+        // red-black: both colours' latest updates must be within tol
+        if (r <= tol && (!rb || (sweep > 0 && r_prev <= tol))) {
             conv = true;
             break;
         }
+        r_prev = r;
     }
     const int last = sweep < max_iter ? sweep : max_iter - 1;
-    const int fin = (last & 1) ? L.b0 : L.b1;
+    const int fin = rb ? L.b0 : ((last & 1) ? L.b0 : L.b1);
     for (int e = tid; e < fn.msg_size; e += kPThreads) msg0[fn.msg_base + e] = p_lds[fin + e];
     if (tid == 0) {
         ns->stop = last;
         ns->iters = last + 1;
         ns->parity = 0;
-        ns->residual = r;
+        ns->residual = rb ? fmax(r, r_prev) : r;
         ns->converged = conv ? 1 : 0;
         if (s_bad) ns->status = -4;
     }
@@ -481,8 +495,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
 }  // namespace
 
 // doubles of dynamic LDS for a persistent block (see PLayout)
-size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave) {
-    return 2 * (size_t)msg_size + (size_t)n_sites + (size_t)(n_sites + 1) / 2 +
+size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers) {
+    return (size_t)n_buffers * msg_size + (size_t)n_sites + (size_t)(n_sites + 1) / 2 +
            (size_t)(n_sites * kMaxRank + 1) / 2 + (size_t)(n_sites + 1) / 2 + (size_t)kPWaves * scratch_per_wave;
 }
 

@@ -71,7 +71,7 @@ hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, h
 hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s);
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s);
 // doubles of dynamic LDS of a persistent block and its per-wave scratch
-size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave);
+size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers);
 int bp_persistent_scratch(int spw, int rank, int dim);
 int bp_persistent_tiles_in_flight(int dim, int rank);
 int bp_persistent_sites_per_tile(int dim, int rank);

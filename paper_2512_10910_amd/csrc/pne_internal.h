@@ -55,7 +55,7 @@ struct FusedNet {
     int32_t n_groups;
     int32_t list_begin;   // site list (local site ids, group after group)
     int32_t scratch;      // doubles of per-wavefront scratch
-    int32_t pad;
+    int32_t colors;       // 2: bipartite, red-black schedule in one buffer; 1: Jacobi, two buffers
 };
 
 // Sites of one network with all legs of dimension dc and rank `rank`.
@@ -65,7 +65,8 @@ struct FusedGroup {
     int32_t list_off;     // first entry in the network's site list
     int32_t n_sites;
     int32_t nt;           // tiles per wavefront step
-    int32_t pad1, pad2;
+    int32_t color;        // site colour (0/1) under the red-black schedule, else 0
+    int32_t pad;
 };
 
 // Per-network BP state.  Sweep k reads message buffer k&1, writes buffer

@@ -499,7 +499,35 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             const int spw = bp_persistent_sites_per_tile(r0.dim[0], r0.rank);
             if (spw > 0) pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0]));
         }
-        const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch);
+        // two-colouring of the site graph for the red-black schedule
+        std::vector<int> colour(g.n_sites, -1);
+        bool bip = !(opt->flags & PNE_FLAG_BP_JACOBI) && g.n_sites > 1;
+        if (bip) {
+            std::vector<std::vector<int>> adj(g.n_sites);
+            for (int bb = 0; bb < g.n_bonds; ++bb) {
+                adj[g.bu[bb]].push_back(g.bv[bb]);
+                adj[g.bv[bb]].push_back(g.bu[bb]);
+            }
+            std::vector<int> queue;
+            for (int s0 = 0; s0 < g.n_sites && bip; ++s0) {
+                if (colour[s0] >= 0) continue;
+                colour[s0] = 0;
+                queue.assign(1, s0);
+                for (size_t h = 0; h < queue.size() && bip; ++h) {
+                    const int u = queue[h];
+                    for (int v : adj[u]) {
+                        if (colour[v] < 0) {
+                            colour[v] = 1 - colour[u];
+                            queue.push_back(v);
+                        } else if (colour[v] == colour[u]) {
+                            bip = false;
+                            break;
+                        }
+                    }
+                }
+            }
+        }
+        const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2);
         if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
             FusedNet f;
             std::memset(&f, 0, sizeof f);
@@ -511,19 +539,23 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             f.group_begin = (int)fgroups.size();
             f.list_begin = (int)fsite_list.size();
             f.scratch = pscratch;
-            for (auto &kv : groups) {
-                const SiteRec &r0 = sites[kv.second[0]];
-                FusedGroup fg;
-                std::memset(&fg, 0, sizeof fg);
-                fg.dc = r0.dim[0];
-                fg.rank = r0.rank;
-                fg.spw = bp_persistent_sites_per_tile(fg.dc, fg.rank);
-                fg.nt = bp_persistent_tiles_in_flight(fg.dc, fg.rank);
-                fg.list_off = (int)fsite_list.size() - f.list_begin;
-                fg.n_sites = (int)kv.second.size();
-                for (int gs : kv.second) fsite_list.push_back(gs - base);
-                fgroups.push_back(fg);
-            }
+            f.colors = bip ? 2 : 1;
+            for (int c = 0; c < f.colors; ++c)
+                for (auto &kv : groups) {
+                    const SiteRec &r0 = sites[kv.second[0]];
+                    FusedGroup fg;
+                    std::memset(&fg, 0, sizeof fg);
+                    fg.dc = r0.dim[0];
+                    fg.rank = r0.rank;
+                    fg.spw = bp_persistent_sites_per_tile(fg.dc, fg.rank);
+                    fg.nt = bp_persistent_tiles_in_flight(fg.dc, fg.rank);
+                    fg.color = c;
+                    fg.list_off = (int)fsite_list.size() - f.list_begin;
+                    for (int gs : kv.second)
+                        if (!bip || colour[gs - base] == c) fsite_list.push_back(gs - base);
+                    fg.n_sites = (int)fsite_list.size() - f.list_begin - fg.list_off;
+                    if (fg.n_sites > 0) fgroups.push_back(fg);
+                }
             f.n_groups = (int)fgroups.size() - f.group_begin;
             fused.push_back(f);
             fused_lds = std::max(fused_lds, pneed * 8);

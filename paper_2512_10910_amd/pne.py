@@ -236,9 +236,10 @@ class Result:
 KERNEL_NAMES = ["init", "bp_sweep", "bp_close", "bp_persistent", "gauge", "regauge", "clusters", "combine"]
 PNE_FLAG_PROFILE = 1
 PNE_FLAG_NO_PERSISTENT = 2
+PNE_FLAG_BP_JACOBI = 4
 
 
-def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True):
+def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False):
     lib = load_library()
     o = Options()
     lib.pne_options_default(ctypes.byref(o))
@@ -247,7 +248,8 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.bp_tol = float(tol)
     o.bp_max_iter = int(max_iter)
     o.bp_check_every = int(check_every)
-    o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT)
+    o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT) | \
+        (PNE_FLAG_BP_JACOBI if jacobi else 0)
     return o
 
 
@@ -282,8 +284,10 @@ class Context:
         return Network(self, obj, on_device)
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
-              profile=False, persistent=True) -> "Batch":
-        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent)
+              profile=False, persistent=True, jacobi=False) -> "Batch":
+        """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
+        in the persistent kernel even on bipartite networks."""
+        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi)
 
     def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
         b = self.batch([net], K, precision, tol, max_iter)
@@ -336,10 +340,10 @@ class Batch:
     """Prepared batch: plans and device tables built once, run many times."""
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
-                 persistent=True):
+                 persistent=True, jacobi=False):
         self.ctx = ctx
         self.nets = list(nets)
-        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent)
+        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),
