@@ -169,6 +169,9 @@ def main():
         alg_bytes = bytes_sweep
         if dom == "bp_persistent":
             per_step_ms[dom] = per_step_ms["bp_persistent"] + per_step_ms["bp_sweep"]
+            if kt["regauge"][1] == 0:
+                # no regauge launches: the persistent blocks built the gauge and slices
+                alg_bytes += bytes_regauge
     elif dom == "regauge":
         alg_bytes = bytes_regauge
     else:

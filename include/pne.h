@@ -54,6 +54,7 @@ typedef enum {
 #define PNE_FLAG_PROFILE 1u /* time every kernel launch with HIP events on the context stream */
 #define PNE_FLAG_NO_PERSISTENT 2u /* sweep every network launch by launch (no persistent BP kernel) */
 #define PNE_FLAG_BP_JACOBI 4u /* persistent BP: Jacobi sweeps even on bipartite networks (see below) */
+#define PNE_FLAG_SEPARATE_REGAUGE 8u /* gauge + slices in their own launch, not in the persistent BP block */
 
 /* BP schedule.  Jacobi: every sweep updates every message from the previous
  * sweep's messages.  On a bipartite network (two site colours, every bond
@@ -179,6 +180,14 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
  * clears the accumulators afterwards. */
 pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *launches, int32_t n,
                                   int32_t reset);
+
+/* After pne_batch_wait: phase durations of the persistent BP blocks of the
+ * last run, from the device wall clock (microseconds): out[0] mean BP time per
+ * block, out[1] mean in-block gauge + slice time, out[2] / out[3] their
+ * maxima, out[4] span from the first block's start to the last BP end,
+ * out[5] span to the last block's end.  Writes n entries (zeros when the
+ * batch has no persistent networks). */
+pne_status pne_batch_phase_times(pne_batch *batch, double *out, int32_t n);
 
 /* After pne_batch_wait: copy network i's final BP messages to host.  For
  * every bond b, out holds the message arriving at the bond's first site

@@ -18,6 +18,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "regauge.h"
 
 namespace pne {
 
@@ -51,6 +52,8 @@ struct PLayout {
     int moff;        // n_sites ints: local message offsets
     int dst;         // n_sites * kMaxRank ints: local destination offsets
     int list;        // n_sites ints: local site ids in group order
+    int vside;       // n_sites ints: mask of slots where the site is the bond's second site
+    int soff;        // n_sites int64: slice offsets
     int scr;         // per-wave scratch
 };
 
@@ -383,12 +386,215 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
     return res;
 }
 
+// Messages of the block's network in LDS, addressed by absolute offset.
+struct LdsMsg {
+    int base;  // LDS index of absolute offset 0
+    __device__ double operator()(int o) const { return p_lds[base + o]; }
+};
+
+// Register regauge of one tile of a persistent block (kept out of line so
+// each shape gets its own register allocation).
+template <int D, int R, typename S>
+__device__ __attribute__((noinline)) void p_regauge(int cnt, int net, int site_base, int list_off, int first,
+                                                    int msg_lds, const SiteRec *__restrict__ sites,
+                                                    S *__restrict__ slices, double *__restrict__ site_log,
+                                                    int *__restrict__ site_sign, NetState *st, int scr) {
+    const LdsMsg msg{msg_lds};
+    auto site_of = [site_base, list_off, first](int j) { return site_base + int_at(list_off, first + j); };
+    dev::regauge_reg<D, R, S, dev::rg_passes(D, R)>(cnt, net, site_of, sites, msg, slices, site_log, site_sign, st,
+                                                     p_lds + scr);
+}
+
+// Regauge on the DPP layout (all legs of dimension D <= 4, same lanes and
+// registers as ptiles_dpp).  With a, c the bond's messages, n = a.c and the
+// Householder vector u (t = 2/|u|^2) of c, the Appendix-B transform of a slot
+// has column 0 equal to g0 (a/n on the bond's first site, c on its second)
+// and columns k >= 1 equal to e_k - t u_k u - f_k c, where f = 0 on the first
+// site and f_k = (a_k - t u_k (u.a))/n on the second.  Along that slot,
+//   T'[0] = W0,  T'[k] = T[k] - t u_k Wu - f_k W0   (k >= 1),
+// with W0 = T.g0 and Wu = T.u contracted over the slot: two sums over the
+// slot's lane field (DPP all-reduces) or fiber (registers), then an in-lane
+// update.  Per (site, slot) one lane builds the record g0[D], u[D], f[D], t
+// in the wave's LDS scratch.  NP passes of SPW sites load their tensors
+// before any record is built.
+template <int D, int R>
+__host__ __device__ constexpr int rgd_passes() {
+    constexpr int T = R < 2 ? R : 2;
+    constexpr int SPW = 64 >> ((D <= 2 ? 1 : 2) * T);
+    constexpr int NL = ipw(D, R - T);
+    constexpr int a = 16 / NL < 1 ? 1 : (16 / NL > 4 ? 4 : 16 / NL);
+    constexpr int b = 512 / (SPW * R * (3 * D + 1));
+    return a < b ? a : (b < 1 ? 1 : b);
+}
+template <int D, int R>
+__host__ __device__ constexpr int rgd_sites_per_call() {
+    return rgd_passes<D, R>() * (64 >> ((D <= 2 ? 1 : 2) * (R < 2 ? R : 2)));
+}
+
+// sites per regauge call of a persistent block for shape (dim, rank)
+__host__ __device__ inline int regauge_call_sites(int dim, int rank) {
+    switch (dim * 8 + rank) {
+#define PNE_SPC(D_, R_) \
+    case D_ * 8 + R_: return rgd_sites_per_call<D_, R_>();
+        PNE_SPC(2, 1) PNE_SPC(2, 2) PNE_SPC(2, 3) PNE_SPC(2, 4) PNE_SPC(2, 5) PNE_SPC(2, 6) PNE_SPC(3, 1)
+        PNE_SPC(3, 2) PNE_SPC(3, 3) PNE_SPC(3, 4) PNE_SPC(4, 1) PNE_SPC(4, 2) PNE_SPC(4, 3) PNE_SPC(4, 4)
+#undef PNE_SPC
+        default: return dev::regauge_sites_per_call(dim, rank);
+    }
+}
+
+template <int D, int R, typename S>
+__device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt, int net, int site_base, int first,
+                                                        int fin, S *__restrict__ slices,
+                                                        double *__restrict__ site_log, int *__restrict__ site_sign,
+                                                        NetState *st, int scr) {
+    constexpr int P = D <= 2 ? 2 : 4;
+    constexpr int B = P == 2 ? 1 : 2;
+    constexpr int T = R < 2 ? R : 2;
+    constexpr int NLEG = R - T;
+    constexpr int LS = 1 << (B * T);
+    constexpr int SPW = 64 / LS;
+    constexpr int NL = ipw(D, NLEG);
+    constexpr int DT = ipw(D, T);
+    constexpr int GR = 3 * D + 1;
+    constexpr int NP = rgd_passes<D, R>();
+    const int lane = threadIdx.x & 63;
+    const int slot = lane / LS;
+    const int tb = lane - slot * LS;
+    const int dlo = tb & (P - 1);
+    const int dhi = T == 2 ? (tb >> B) : 0;
+    const bool inseg = dlo < D && dhi < D;
+    const int toff = T == 2 ? (dhi % D) * D + dlo % D : dlo % D;
+    // every pass's tensor values first: the call's only global loads
+    double v[NP][NL];
+    int ls[NP];
+    bool act[NP];
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        const int j = k * SPW + slot;
+        act[k] = inseg && j < cnt;
+        ls[k] = int_at(L.list, first + (j < cnt ? j : 0));
+        const double *tp = tptr_at(L, ls[k]);
+#pragma unroll
+        for (int q = 0; q < NL; ++q) v[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+    }
+    double *G = p_lds + scr;  // [site][slot][GR]
+    wave_sync();              // the wave's previous call has finished reading G
+    for (int j = lane; j < cnt * R; j += 64) {
+        const int s = j / R;
+        const int l = j - s * R;
+        const int loc = int_at(L.list, first + s);
+        const bool vs = (int_at(L.vside, loc) >> l) & 1;
+        const int pin = fin + int_at(L.moff, loc) + l * D;
+        const int pout = fin + int_at(L.dst, loc * kMaxRank + l);
+        double a[D], c[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double x = p_lds[pin + i], y = p_lds[pout + i];
+            a[i] = vs ? y : x;
+            c[i] = vs ? x : y;
+        }
+        const dev::LegGauge g = dev::leg_gauge_setup(a, c, D);
+        double *rec = G + j * GR;
+        if (!g.ok) {
+            atomicMin(&st[net].status, -4);
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                rec[i] = i == 0 ? 1.0 : 0.0;
+                rec[D + i] = 0.0;
+                rec[2 * D + i] = 0.0;
+            }
+            rec[3 * D] = 0.0;
+            continue;
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            const double ui = i == 0 ? g.u0 : c[i] * g.inv_nc;
+            rec[i] = vs ? c[i] : a[i] * g.inv_n;
+            rec[D + i] = ui;
+            rec[2 * D + i] = (vs && i > 0) ? (a[i] - g.t * ui * g.ua) * g.inv_n : 0.0;
+        }
+        rec[3 * D] = g.t;
+    }
+    wave_sync();
+#pragma unroll
+    for (int k = 0; k < NP; ++k) {
+        if (k * SPW >= cnt) break;
+        const int j = k * SPW + slot;
+        const double *Gs = G + (j < cnt ? j : 0) * R * GR;
+        // register (lead) legs: contractions along each fiber
+#pragma unroll
+        for (int jl = 0; jl < NLEG; ++jl) {
+            const double *g = Gs + jl * GR;
+            const double t = g[3 * D];
+            constexpr int dummy = 0;
+            (void)dummy;
+#pragma unroll
+            for (int q0 = 0; q0 < NL; ++q0) {
+                const int stride = ipw(D, NLEG - 1 - jl);
+                if ((q0 / stride) % D != 0) continue;
+                double w0 = 0.0, wu = 0.0;
+#pragma unroll
+                for (int i = 0; i < D; ++i) {
+                    w0 = fma(v[k][q0 + i * stride], g[i], w0);
+                    wu = fma(v[k][q0 + i * stride], g[D + i], wu);
+                }
+                v[k][q0] = w0;
+#pragma unroll
+                for (int kk = 1; kk < D; ++kk)
+                    v[k][q0 + kk * stride] = v[k][q0 + kk * stride] - t * g[D + kk] * wu - g[2 * D + kk] * w0;
+            }
+        }
+        // lane legs: leg R-1 on the low field, leg R-2 on the high field
+#pragma unroll
+        for (int m = 0; m < T; ++m) {
+            const double *g = Gs + (R - 1 - m) * GR;
+            const int d = m == 0 ? dlo : dhi;
+            const bool dv = d < D;
+            const int dd = dv ? d : 0;
+            const double g0 = dv ? g[dd] : 0.0;
+            const double gu = dv ? g[D + dd] : 0.0;
+            const double cu = dv ? g[3 * D] * g[D + dd] : 0.0;
+            const double cf = dv ? g[2 * D + dd] : 0.0;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) {
+                double w0 = v[k][q] * g0, wu = v[k][q] * gu;
+                if (m == 0) {
+                    w0 = sum_low<P>(w0);
+                    wu = sum_low<P>(wu);
+                } else {
+                    w0 = sum_high<P>(w0);
+                    wu = sum_high<P>(wu);
+                }
+                v[k][q] = d == 0 ? w0 : v[k][q] - cu * wu - cf * w0;
+            }
+        }
+        // vacuum factor: element 0 in the segment's first lane
+        const double z = __shfl(v[k][0], slot * LS, 64);
+        const bool ok = (fabs(z) > 0.0) && isfinite(z);
+        if (act[k]) {
+            const int64_t so = reinterpret_cast<const int64_t *>(p_lds + L.soff)[ls[k]];
+            const double iz = ok ? 1.0 / z : 0.0;
+#pragma unroll
+            for (int q = 0; q < NL; ++q) dev::SliceIO<S>::store(slices, so + q * DT + toff, v[k][q] * iz);
+        }
+        if (tb == 0 && j < cnt) {
+            site_log[site_base + ls[k]] = ok ? log(fabs(z)) : 0.0;
+            site_sign[site_base + ls[k]] = z < 0.0 ? -1 : 1;
+            if (!ok) atomicMin(&st[net].status, -4);
+        }
+    }
+}
+
+template <typename S>
 __global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict__ groups,
                 const int *__restrict__ site_list, const SiteRec *__restrict__ sites, double *msg0, NetState *st,
-                double tol, int max_iter) {
+                double tol, int max_iter, S *__restrict__ slices, double *__restrict__ site_log,
+                int *__restrict__ site_sign, int rg_enabled) {
     const FusedNet fn = fnets[blockIdx.x];
     NetState *ns = st + fn.net;
+    const unsigned long long t_start = wall_clock64();
     __shared__ double s_res[kPWaves];
     __shared__ int s_bad;
     const int tid = threadIdx.x;
@@ -402,7 +608,9 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     L.moff = L.tptr + ns_;
     L.dst = L.moff + (ns_ + 1) / 2;
     L.list = L.dst + (ns_ * kMaxRank + 1) / 2;
-    L.scr = L.list + (ns_ + 1) / 2;
+    L.vside = L.list + (ns_ + 1) / 2;
+    L.soff = L.vside + (ns_ + 1) / 2;
+    L.scr = L.soff + ns_;
     const int scr = L.scr + wave * fn.scratch;
     for (int e = tid; e < fn.msg_size; e += kPThreads) p_lds[e] = msg0[fn.msg_base + e];
     for (int s = tid; s < ns_; s += kPThreads) {
@@ -412,6 +620,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         for (int l = 0; l < kMaxRank; ++l)
             reinterpret_cast<int *>(p_lds + L.dst)[s * kMaxRank + l] = l < r.rank ? r.dst[l] - fn.msg_base : 0;
         reinterpret_cast<int *>(p_lds + L.list)[s] = site_list[fn.list_begin + s];
+        reinterpret_cast<int *>(p_lds + L.vside)[s] = r.vside_mask;
+        reinterpret_cast<int64_t *>(p_lds + L.soff)[s] = r.slice_off;
     }
     if (tid == 0) s_bad = 0;
     __syncthreads();
@@ -489,7 +699,49 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         ns->residual = rb ? fmax(r, r_prev) : r;
         ns->converged = conv ? 1 : 0;
         if (s_bad) ns->status = -4;
+        ns->t_start = t_start;
+        ns->t_bp = wall_clock64();
+        ns->t_rg = ns->t_bp;
     }
+    if (!fn.rg_inline || !rg_enabled) return;
+    // Gauge and slices (Appendix B; Sec. VI) straight from the final
+    // messages in LDS: register-path tiles of each shape group dealt to the
+    // waves, each wave's transform table in its BP scratch (free after the
+    // last sweep's barrier).
+    const int msg_lds = fin - fn.msg_base;
+    int tbase = 0;
+    for (int g = 0; g < fn.n_groups; ++g) {
+        const FusedGroup gr = groups[fn.group_begin + g];
+        const int spt = regauge_call_sites(gr.dc, gr.rank);
+        const int ntl = (gr.n_sites + spt - 1) / spt;
+        const int t0 = ((wave - tbase) % kPWaves + kPWaves) % kPWaves;
+        tbase += ntl;
+        for (int t = t0; t < ntl; t += kPWaves) {
+            const int first = gr.list_off + t * spt;
+            const int cnt = min(spt, gr.n_sites - t * spt);
+#define PNE_PRG(D_, R_)                                                                                    \
+    case D_ * 8 + R_:                                                                                     \
+        p_regauge<D_, R_, S>(cnt, fn.net, fn.site_base, L.list, first, msg_lds, sites, slices, site_log, \
+                             site_sign, st, scr);                                                         \
+        break;
+#define PNE_PRGD(D_, R_)                                                                                    \
+    case D_ * 8 + R_:                                                                                      \
+        p_regauge_dpp<D_, R_, S>(L, cnt, fn.net, fn.site_base, first, fin, slices, site_log, site_sign, st,  \
+                                 scr);                                                                     \
+        break;
+            switch (gr.dc * 8 + gr.rank) {
+                PNE_PRGD(2, 1) PNE_PRGD(2, 2) PNE_PRGD(2, 3) PNE_PRGD(2, 4) PNE_PRGD(2, 5) PNE_PRGD(2, 6)
+                PNE_PRGD(3, 1) PNE_PRGD(3, 2) PNE_PRGD(3, 3) PNE_PRGD(3, 4) PNE_PRGD(4, 1) PNE_PRGD(4, 2)
+                PNE_PRGD(4, 3) PNE_PRGD(4, 4)
+                PNE_PRG(5, 1) PNE_PRG(5, 2) PNE_PRG(6, 1) PNE_PRG(6, 2)
+                default: break;
+            }
+#undef PNE_PRG
+#undef PNE_PRGD
+        }
+    }
+    __syncthreads();
+    if (tid == 0) ns->t_rg = wall_clock64();
 }
 
 }  // namespace
@@ -497,7 +749,19 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
 // doubles of dynamic LDS for a persistent block (see PLayout)
 size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers) {
     return (size_t)n_buffers * msg_size + (size_t)n_sites + (size_t)(n_sites + 1) / 2 +
-           (size_t)(n_sites * kMaxRank + 1) / 2 + (size_t)(n_sites + 1) / 2 + (size_t)kPWaves * scratch_per_wave;
+           (size_t)(n_sites * kMaxRank + 1) / 2 + 2 * (size_t)((n_sites + 1) / 2) + (size_t)n_sites +
+           (size_t)kPWaves * scratch_per_wave;
+}
+
+// Shapes whose gauge and slices the persistent block builds itself: the DPP
+// layout (D <= 4, up to 16 register values) or the shuffle register path.
+bool bp_persistent_regauge_supported(int dim, int rank) {
+    return dpp_shape(dim, rank) || regauge_reg_supported(dim, rank);
+}
+
+int bp_persistent_regauge_table(int dim, int rank) {
+    if (dpp_shape(dim, rank)) return regauge_call_sites(dim, rank) * rank * (3 * dim + 1);
+    return dev::regauge_call_table(dim, rank);
 }
 
 int bp_persistent_tiles_in_flight(int dim, int rank) {
@@ -522,8 +786,23 @@ int bp_persistent_scratch(int spw, int rank, int dim) {
 
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
     if (!b.n_fused) return hipSuccess;
-    hipLaunchKernelGGL(k_bp_persistent, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused, b.fgroups,
-                       b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter);
+    switch (b.precision) {
+        case 0:
+            hipLaunchKernelGGL(k_bp_persistent<double>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
+                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
+                               b.site_log, b.site_sign, b.fused_regauge);
+            break;
+        case 1:
+            hipLaunchKernelGGL(k_bp_persistent<float>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
+                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
+                               b.site_log, b.site_sign, b.fused_regauge);
+            break;
+        default:
+            hipLaunchKernelGGL(k_bp_persistent<uint16_t>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
+                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter,
+                               (uint16_t *)b.slices, b.site_log, b.site_sign, b.fused_regauge);
+            break;
+    }
     return hipGetLastError();
 }
 

@@ -20,6 +20,7 @@ struct DeviceBatch {
     const FusedGroup *fgroups = nullptr;
     const int *fsite_list = nullptr;
     size_t fused_lds = 0;
+    int fused_regauge = 1;              // persistent blocks also build gauge + slices
     const int *tile_sites = nullptr;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
     NetState *state = nullptr;
@@ -74,10 +75,16 @@ hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStrea
 size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers);
 int bp_persistent_scratch(int spw, int rank, int dim);
 int bp_persistent_tiles_in_flight(int dim, int rank);
+// shapes whose gauge and slices the persistent block builds, and the doubles
+// of per-wavefront scratch that needs
+bool bp_persistent_regauge_supported(int dim, int rank);
+int bp_persistent_regauge_table(int dim, int rank);
 int bp_persistent_sites_per_tile(int dim, int rank);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 // shapes the register-path regauge handles (all legs of dimension dim)
 bool regauge_reg_supported(int dim, int rank);
+// doubles of the per-wavefront LDS transform table of a register regauge tile
+int regauge_table_doubles(int dim, int rank);
 hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s);
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s);
 

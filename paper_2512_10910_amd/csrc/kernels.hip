@@ -15,105 +15,18 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "regauge.h"
 
 namespace pne {
 
 namespace {
 
+using namespace dev;
+
 constexpr int kRgThreads = 128;
 constexpr int kClThreads = 256;
 constexpr int kCbThreads = 256;
 
-__device__ inline float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
-
-// Round an FP64 value to bfloat16 once (round to nearest even).  The FP32
-// intermediate is truncated and carries a sticky bit, so the single rounding
-// step happens at bfloat16 precision.
-__device__ inline uint16_t f64_to_bf16(double x) {
-    float f = __double2float_rz(x);
-    uint32_t u = __float_as_uint(f);
-    if ((double)f != x) u |= 1u;  // sticky
-    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16);  // inf/nan
-    uint32_t lsb = (u >> 16) & 1u;
-    u += 0x7fffu + lsb;
-    return (uint16_t)(u >> 16);
-}
-
-template <typename S>
-struct SliceIO;
-template <>
-struct SliceIO<double> {
-    using acc = double;
-    __device__ static double load(const double *p, int64_t i) { return p[i]; }
-    __device__ static void store(double *p, int64_t i, double v) { p[i] = v; }
-};
-template <>
-struct SliceIO<float> {
-    using acc = float;
-    __device__ static float load(const float *p, int64_t i) { return p[i]; }
-    __device__ static void store(float *p, int64_t i, double v) { p[i] = (float)v; }
-};
-template <>
-struct SliceIO<uint16_t> {
-    using acc = float;
-    __device__ static float load(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
-    __device__ static void store(uint16_t *p, int64_t i, double v) { p[i] = f64_to_bf16(v); }
-};
-
-// ---------------------------------------------------------------------------
-
-// Gauge of Appendix B for one bond slot, built from the bond's two messages.
-// With a = message arriving at the bond's first site, c = message arriving at
-// its second site and n = a.c, G = [a/n | R] (R = columns 1..d-1 of the
-// Householder reflection that maps c/|c| onto the e0 axis, an orthonormal
-// basis of c's complement) has inverse [c^T ; R^T (I - a c^T / n)].  Inserting
-// G G^-1 on the bond turns P = a c^T / n into e0 e0^T, so Q keeps exactly the
-// indices 1..d-1.  The first site's slot is multiplied by G, the second
-// site's by the transpose of G^-1, both as T'[.k.] = sum_i T[.i.] X[i,k].
-// Each endpoint site builds the transform itself (no per-bond table).
-struct LegGauge {
-    double inv_n, inv_nc, u0, t, ua;  // t = 2/|u|^2 with u = c/|c| - alpha e0; ua = u.a
-    bool ok;                          // false: |n| ~ 0 relative to |a||c| (SINGULAR)
-};
-
-__device__ inline LegGauge leg_gauge_setup(const double *a, const double *c, int D) {
-    LegGauge g;
-    double n = 0.0, na = 0.0, nc = 0.0;
-    for (int i = 0; i < D; ++i) {
-        n = fma(a[i], c[i], n);
-        na = fma(a[i], a[i], na);
-        nc = fma(c[i], c[i], nc);
-    }
-    na = sqrt(na);
-    nc = sqrt(nc);
-    g.ok = (fabs(n) >= 1e-12 * na * nc) && isfinite(n) && nc > 0.0;
-    g.inv_n = 1.0 / n;
-    g.inv_nc = 1.0 / nc;
-    const double v0 = c[0] * g.inv_nc;
-    const double alpha = v0 > 0.0 ? -1.0 : 1.0;
-    g.u0 = v0 - alpha;
-    double uu = g.u0 * g.u0, ua = g.u0 * a[0];
-    for (int i = 1; i < D; ++i) {
-        const double ui = c[i] * g.inv_nc;
-        uu = fma(ui, ui, uu);
-        ua = fma(ui, a[i], ua);
-    }
-    g.t = 2.0 / uu;
-    g.ua = ua;
-    return g;
-}
-
-// X[i,k] of the slot transform; ak = a[k], ck = c[k], ai = a[i], ci = c[i].
-__device__ inline double leg_gauge_x(const LegGauge &g, bool vside, int i, int k, double ai, double ci, double ak,
-                                     double ck) {
-    if (!g.ok) return i == k ? 1.0 : 0.0;
-    if (k == 0) return vside ? ci : ai * g.inv_n;
-    const double ui = i == 0 ? g.u0 : ci * g.inv_nc;
-    const double uk = ck * g.inv_nc;
-    double r = (i == k ? 1.0 : 0.0) - g.t * ui * uk;
-    if (vside) r -= (ak - g.t * uk * g.ua) * g.inv_n * ci;
-    return r;
-}
 
 // Per site (one block): apply the gauge of every bond slot (mode products in
 // LDS), then divide by the vacuum factor z'_v = T'[0,...,0] (closed sites) or
@@ -216,136 +129,10 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
     }
 }
 
-constexpr int rg_ipow(int b, int e) { return e <= 0 ? 1 : b * rg_ipow(b, e - 1); }
-
-// Register-path regauge for a tile of same-shape sites (all R legs of
-// dimension D, no open legs), laid out as in the BP register path: the last
-// T legs index lanes through power-of-two bit-fields, the first R-T legs
-// index NL values per lane.  A gauge on a register leg is an in-lane mode
-// product; a gauge on a lane leg gathers the D values of the leg with
-// shuffles.  The vacuum factor T'[0,...,0] sits in the segment's first lane.
-// LDS doubles for the slot transforms of one register-path regauge tile:
-// (sites per tile) * rank * D^2, largest for D=6 rank 1 (8 sites * 36).
-constexpr int kRgXgMax = 288;
-
-template <int D, int R, typename S>
-__device__ void regauge_reg(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
-                            const double *msg0, const double *msg1, S *__restrict__ slices,
-                            double *__restrict__ site_log, int *__restrict__ site_sign, NetState *st,
-                            double *__restrict__ xs) {
-    constexpr int P = D <= 2 ? 2 : (D <= 4 ? 4 : 8);
-    constexpr int B = P == 2 ? 1 : (P == 4 ? 2 : 3);
-    constexpr int T = (6 / B) < R ? (6 / B) : R;
-    constexpr int NLEG = R - T;
-    constexpr int LS = 1 << (B * T);
-    constexpr int NL = rg_ipow(D, NLEG);
-    constexpr int DT = rg_ipow(D, T);
-    static_assert((64 / LS) * R * D * D <= kRgXgMax, "slot transforms exceed the LDS table");
-    const int lane = threadIdx.x & 63;
-    const double *mb = st[tl.net].parity ? msg1 : msg0;
-    // Phase 1: the tile's slot transforms X (site, slot, D x D) into LDS, one
-    // column per lane: each (site, slot) runs the gauge set-up once per column
-    // instead of once per lane of the site.
-    for (int j = lane; j < tl.n_sites * R * D; j += 64) {
-        const int s = j / (R * D);
-        const int l = (j / D) % R;
-        const int k = j % D;
-        const SiteRec &q = sites[tile_sites[tl.site_begin + s]];
-        const bool vs = (q.vside_mask >> l) & 1;
-        const double *pin = mb + q.msg_off + q.moff[l];
-        const double *pout = mb + q.dst[l];
-        double a[D], c[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const double x = pin[i], y = pout[i];
-            a[i] = vs ? y : x;
-            c[i] = vs ? x : y;
-        }
-        const LegGauge g = leg_gauge_setup(a, c, D);
-        if (k == 0 && !g.ok) atomicMin(&st[tl.net].status, -4);
-        double ak = a[0], ck = c[0];
-#pragma unroll
-        for (int i = 1; i < D; ++i)
-            if (k == i) {
-                ak = a[i];
-                ck = c[i];
-            }
-        double *X = xs + (s * R + l) * D * D;
-#pragma unroll
-        for (int i = 0; i < D; ++i) X[i * D + k] = leg_gauge_x(g, vs, i, k, a[i], c[i], ak, ck);
-    }
-    __syncthreads();
-    // Phase 2: apply the transforms to the site tensors held across lanes.
-    const int slot = lane / LS;
-    const int tb = lane - slot * LS;
-    bool act = slot < tl.n_sites;
-    int dig[T];
-    int toff = 0;
-#pragma unroll
-    for (int m = 0; m < T; ++m) {
-        dig[m] = (tb >> (B * (T - 1 - m))) & (P - 1);
-        act = act && dig[m] < D;
-        toff = toff * D + (dig[m] < D ? dig[m] : 0);
-    }
-    const int sl = slot < tl.n_sites ? slot : 0;
-    const int gsite = tile_sites[tl.site_begin + sl];
-    const SiteRec &sr = sites[gsite];
-    const double *tp = sr.t;
-    const double *X0 = xs + sl * R * D * D;
-    double v[NL];
-#pragma unroll
-    for (int q = 0; q < NL; ++q) v[q] = act ? tp[q * DT + toff] : 0.0;
-    // register (lead) legs
-#pragma unroll
-    for (int k = 0; k < NLEG; ++k) {
-        const double *X = X0 + k * D * D;
-        double w[NL];
-#pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            const int stride = rg_ipow(D, NLEG - 1 - k);
-            const int dk = (q / stride) % D;
-            const int q0 = q - dk * stride;
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) acc = fma(v[q0 + i * stride], X[i * D + dk], acc);
-            w[q] = acc;
-        }
-#pragma unroll
-        for (int q = 0; q < NL; ++q) v[q] = w[q];
-    }
-    // lane (trailing) legs
-#pragma unroll
-    for (int m = 0; m < T; ++m) {
-        const int shift = B * (T - 1 - m);
-        const int field_clear = lane & ~((P - 1) << shift);
-        const double *X = X0 + (NLEG + m) * D * D;
-        const int kk = dig[m] < D ? dig[m] : 0;
-        double xc[D];
-#pragma unroll
-        for (int i = 0; i < D; ++i) xc[i] = X[i * D + kk];
-#pragma unroll
-        for (int q = 0; q < NL; ++q) {
-            double acc = 0.0;
-#pragma unroll
-            for (int i = 0; i < D; ++i) acc = fma(__shfl(v[q], field_clear | (i << shift), 64), xc[i], acc);
-            v[q] = acc;
-        }
-    }
-    // vacuum factor of each site: element 0 in the segment's first lane
-    const double z = __shfl(v[0], slot * LS, 64);
-    const bool ok = (fabs(z) > 0.0) && isfinite(z);
-    if (act) {
-        const int64_t so = sr.slice_off;
-        const double iz = ok ? 1.0 / z : 0.0;
-#pragma unroll
-        for (int q = 0; q < NL; ++q) SliceIO<S>::store(slices, so + q * DT + toff, v[q] * iz);
-    }
-    if (tb == 0 && slot < tl.n_sites) {
-        site_log[gsite] = ok ? log(fabs(z)) : 0.0;
-        site_sign[gsite] = z < 0.0 ? -1 : 1;
-        if (!ok) atomicMin(&st[tl.net].status, -4);
-    }
-}
+struct GlobalMsg {
+    const double *mb;
+    __device__ double operator()(int o) const { return mb[o]; }
+};
 
 template <typename S>
 __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__ tiles, const int *__restrict__ rg_tiles,
@@ -356,27 +143,11 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
                                                       int *__restrict__ site_sign, NetState *st) {
     const BpTile tl = tiles[rg_tiles[blockIdx.x]];
     __shared__ double s_xg[kRgXgMax];
-    switch (tl.dc * 8 + tl.rank) {
-        case 17: regauge_reg<2, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 18: regauge_reg<2, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 19: regauge_reg<2, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 20: regauge_reg<2, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 21: regauge_reg<2, 5, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 22: regauge_reg<2, 6, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 25: regauge_reg<3, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 26: regauge_reg<3, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 27: regauge_reg<3, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 28: regauge_reg<3, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 33: regauge_reg<4, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 34: regauge_reg<4, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 35: regauge_reg<4, 3, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 36: regauge_reg<4, 4, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 41: regauge_reg<5, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 42: regauge_reg<5, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 49: regauge_reg<6, 1, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        case 50: regauge_reg<6, 2, S>(tl, sites, tile_sites, msg0, msg1, slices, site_log, site_sign, st, s_xg); break;
-        default: break;
-    }
+    const GlobalMsg msg{st[tl.net].parity ? msg1 : msg0};
+    const int *ts = tile_sites + tl.site_begin;
+    auto site_of = [ts](int j) { return ts[j]; };
+    regauge_reg_any<S, false>(tl.dc, tl.rank, tl.n_sites, tl.net, site_of, sites, msg, slices, site_log, site_sign,
+                              st, s_xg);
 }
 
 // Cluster contraction by a per-class plan: the frontier tensor F absorbs one
@@ -690,6 +461,8 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__rest
 }
 
 }  // namespace
+
+int regauge_table_doubles(int dim, int rank) { return regauge_call_table(dim, rank); }
 
 bool regauge_reg_supported(int dim, int rank) {
     if (dim < 2 || dim > 6 || rank < 1 || rank > 6) return false;

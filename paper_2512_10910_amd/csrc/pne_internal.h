@@ -56,6 +56,8 @@ struct FusedNet {
     int32_t list_begin;   // site list (local site ids, group after group)
     int32_t scratch;      // doubles of per-wavefront scratch
     int32_t colors;       // 2: bipartite, red-black schedule in one buffer; 1: Jacobi, two buffers
+    int32_t rg_inline;    // 1: the block also builds the gauge and slices of every site
+    int32_t pad;
 };
 
 // Sites of one network with all legs of dimension dc and rank `rank`.
@@ -82,6 +84,9 @@ struct NetState {
     double log_bp;
     int32_t sign_bp;
     int32_t converged;
+    // persistent block phase timestamps (device wall clock ticks): start,
+    // end of BP, end of the in-block gauge + slices
+    unsigned long long t_start, t_bp, t_rg;
 };
 
 // A contraction step of a cluster plan: absorb one site's slice into the

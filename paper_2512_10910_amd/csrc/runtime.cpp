@@ -30,6 +30,7 @@ struct pne_ctx {
     std::string err;
     std::multimap<uint64_t, PlanEntry> cache;
     std::mutex mu;
+    double wall_khz = 100000.0;  // device wall clock rate (ticks per ms)
 };
 
 struct pne_network {
@@ -61,6 +62,7 @@ struct pne_batch {
     double kt_ms[KID_COUNT] = {0};
     int64_t kt_n[KID_COUNT] = {0};
     std::vector<NetState> h_state;
+    std::vector<FusedNet> h_fused;  // host copy of the persistent-block table
     int64_t msg_total = 0;
     std::vector<int> msg_off;  // per global site
     std::vector<int> moff;     // per global slot, relative
@@ -230,6 +232,9 @@ pne_status pne_ctx_create(int device, size_t budget, void *stream, pne_ctx **out
     auto *c = new pne_ctx();
     c->device = device;
     c->budget = budget;
+    int khz = 0;
+    if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && khz > 0)
+        c->wall_khz = khz;
     if (stream) {
         c->stream = (hipStream_t)stream;
     } else {
@@ -432,6 +437,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
     size_t bp_lds = 0, fused_lds = 0;
+    std::vector<char> net_rg_inline(n, 0);  // gauge + slices built by the persistent block
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
         int base = b->site_base[i];
@@ -527,6 +533,23 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
                 }
             }
         }
+        // gauge + slices inside the persistent block when every shape has a
+        // register-path regauge; its per-wave transform table shares the scratch
+        // (dropped again when the larger scratch would not fit the LDS budget)
+        bool rg_inline = !(opt->flags & PNE_FLAG_SEPARATE_REGAUGE);
+        int rg_scratch = pscratch;
+        for (auto &kv : groups) {
+            const SiteRec &r0 = sites[kv.second[0]];
+            if (!bp_persistent_regauge_supported(r0.dim[0], r0.rank)) {
+                rg_inline = false;
+                break;
+            }
+            rg_scratch = std::max(rg_scratch, bp_persistent_regauge_table(r0.dim[0], r0.rank));
+        }
+        if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2) <= fused_budget)
+            pscratch = rg_scratch;
+        else
+            rg_inline = false;
         const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2);
         if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
             FusedNet f;
@@ -540,6 +563,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
             f.list_begin = (int)fsite_list.size();
             f.scratch = pscratch;
             f.colors = bip ? 2 : 1;
+            f.rg_inline = rg_inline ? 1 : 0;
+            net_rg_inline[i] = rg_inline ? 1 : 0;
             for (int c = 0; c < f.colors; ++c)
                 for (auto &kv : groups) {
                     const SiteRec &r0 = sites[kv.second[0]];
@@ -672,11 +697,13 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
     UP(fused, fused);
+    b->h_fused = fused;
     UP(fgroups, fgroups);
     UP(fsite_list, fsite_list);
     // regauge work: register tiles without open legs, other sites one per block
     std::vector<int> rg_tiles, rg_sites;
     for (size_t t = 0; t < tiles.size(); ++t) {
+        if (net_rg_inline[tiles[t].net]) continue;
         bool open = false;
         for (int j = 0; j < tiles[t].n_sites; ++j) open = open || sites[tile_sites[tiles[t].site_begin + j]].open_mask;
         if (tiles[t].reg && !open && regauge_reg_supported(tiles[t].dc, tiles[t].rank)) {
@@ -905,6 +932,35 @@ pne_status pne_batch_kernel_times(pne_batch *b, double *ms_total, int64_t *launc
             b->kt_ms[k] = 0.0;
             b->kt_n[k] = 0;
         }
+    return PNE_OK;
+}
+
+pne_status pne_batch_phase_times(pne_batch *b, double *out, int32_t n) {
+    if (!b || !b->waited || !out || n < 0) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
+    double v[6] = {0, 0, 0, 0, 0, 0};
+    unsigned long long t0 = ~0ull, t1 = 0, t2 = 0;
+    int cnt = 0;
+    const double tick_us = 1000.0 / b->ctx->wall_khz;
+    for (const FusedNet &f : b->h_fused) {
+        const NetState &s = b->h_state[f.net];
+        if (s.t_bp < s.t_start || s.t_rg < s.t_bp) continue;
+        const double bp = (double)(s.t_bp - s.t_start) * tick_us, rg = (double)(s.t_rg - s.t_bp) * tick_us;
+        v[0] += bp;
+        v[1] += rg;
+        v[2] = std::max(v[2], bp);
+        v[3] = std::max(v[3], rg);
+        t0 = std::min(t0, s.t_start);
+        t1 = std::max(t1, s.t_bp);
+        t2 = std::max(t2, s.t_rg);
+        ++cnt;
+    }
+    if (cnt) {
+        v[0] /= cnt;
+        v[1] /= cnt;
+        v[4] = (double)(t1 - t0) * tick_us;
+        v[5] = (double)(t2 - t0) * tick_us;
+    }
+    for (int k = 0; k < n; ++k) out[k] = k < 6 ? v[k] : 0.0;
     return PNE_OK;
 }
 

@@ -110,6 +110,7 @@ _PROTOS = {
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                               _i32p, _i32p]),
     "pne_batch_messages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64]),
+    "pne_batch_phase_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32]),
     "pne_batch_kernel_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
                                               ctypes.c_int32]),
     "pne_batch_cluster_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64,
@@ -237,9 +238,11 @@ KERNEL_NAMES = ["init", "bp_sweep", "bp_close", "bp_persistent", "gauge", "regau
 PNE_FLAG_PROFILE = 1
 PNE_FLAG_NO_PERSISTENT = 2
 PNE_FLAG_BP_JACOBI = 4
+PNE_FLAG_SEPARATE_REGAUGE = 8
 
 
-def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False):
+def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
+             fused_regauge=True):
     lib = load_library()
     o = Options()
     lib.pne_options_default(ctypes.byref(o))
@@ -249,7 +252,7 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.bp_max_iter = int(max_iter)
     o.bp_check_every = int(check_every)
     o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT) | \
-        (PNE_FLAG_BP_JACOBI if jacobi else 0)
+        (PNE_FLAG_BP_JACOBI if jacobi else 0) | (0 if fused_regauge else PNE_FLAG_SEPARATE_REGAUGE)
     return o
 
 
@@ -284,10 +287,12 @@ class Context:
         return Network(self, obj, on_device)
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
-              profile=False, persistent=True, jacobi=False) -> "Batch":
+              profile=False, persistent=True, jacobi=False, fused_regauge=True) -> "Batch":
         """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
-        in the persistent kernel even on bipartite networks."""
-        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi)
+        in the persistent kernel even on bipartite networks; fused_regauge=
+        False: gauge + slices in their own launch."""
+        return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi,
+                     fused_regauge)
 
     def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
         b = self.batch([net], K, precision, tol, max_iter)
@@ -340,10 +345,10 @@ class Batch:
     """Prepared batch: plans and device tables built once, run many times."""
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
-                 persistent=True, jacobi=False):
+                 persistent=True, jacobi=False, fused_regauge=True):
         self.ctx = ctx
         self.nets = list(nets)
-        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi)
+        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),
@@ -424,6 +429,14 @@ class Batch:
             self.handle, ms.ctypes.data_as(_f64p), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n,
             1 if reset else 0), self.ctx.handle)
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def phase_times(self) -> dict:
+        """Persistent-block phase durations of the last run (microseconds)."""
+        out = np.zeros(6, np.float64)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_phase_times(self.handle, out.ctypes.data_as(_f64p), 6),
+               self.ctx.handle)
+        keys = ["bp_mean", "regauge_mean", "bp_max", "regauge_max", "bp_span", "total_span"]
+        return {k: float(v) for k, v in zip(keys, out)}
 
     def messages(self, i: int) -> np.ndarray:
         """Final BP messages of network i: per bond, [a_b, c_b] concatenated."""
