@@ -201,6 +201,64 @@ pne_status pne_batch_messages(pne_batch *batch, int32_t i, double *out, int64_t 
 pne_status pne_batch_cluster_weights(pne_batch *batch, int32_t i, double *out, int64_t capacity,
                                      int64_t *n_values, int64_t *offsets);
 
+/* ------------------------------------------------------------------------
+ * Request server (continuous batching of independent networks).
+ *
+ * Networks are independent work (terms of different networks never mix), so
+ * a stream of requests is served by batching whatever has arrived: a worker
+ * thread admits pending requests in arrival order while their estimated
+ * device bytes fit mem_budget, runs requests with identical options as one
+ * batch (the same kernels as pne_batch_*), and keeps up to pipeline_depth
+ * batches in flight on their own streams so that preparing the next batch
+ * overlaps the device work of the current one.  A request's tensors and
+ * messages stay in device memory from admission to completion.  Its result
+ * is the same as when it is contracted alone (same kernels, same per-network
+ * reduction order).
+ *
+ * Ownership: pne_submit copies the descriptor arrays and the host tensors
+ * (site_data must point to host memory); the caller may free them on return.
+ * While a server exists, its worker thread is the only user of the context:
+ * the caller must not use that context (or its networks and batches)
+ * concurrently.  pne_submit, pne_poll and pne_server_get_stats may be called
+ * from any thread.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    size_t mem_budget;       /* device bytes admitted requests may hold (estimate); 0: no limit */
+    int32_t max_batch;       /* networks per launch (default 1024) */
+    int32_t pipeline_depth;  /* batches in flight, 1 or 2 (default 2) */
+    int32_t reserved[4];
+} pne_server_options;
+
+typedef struct {
+    int64_t submitted, completed, failed, batches, pending;
+    int64_t device_bytes_admitted;  /* estimate held by admitted requests now */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms; /* submit -> result ready */
+    double networks_per_s;          /* completed / (last completion - first submission) */
+    double busy_s;                  /* wall time with at least one batch in flight */
+    double prep_s;                  /* worker time creating networks / batches and launching */
+    double wait_s;                  /* worker time blocked on batch completion */
+} pne_server_stats;
+
+pne_status pne_server_options_default(pne_server_options *opt);
+/* opt may be NULL (defaults).  Starts the worker thread on the calling
+ * thread's current device. */
+pne_status pne_server_create(pne_ctx *ctx, const pne_server_options *opt, pne_server **out);
+/* Finishes every submitted request, then stops the worker. */
+pne_status pne_server_destroy(pne_server *server);
+/* Queue one network.  *ticket identifies it for pne_poll.  INVALID_ARG for
+ * a malformed descriptor (further checks happen at admission and are
+ * reported by pne_poll), OUT_OF_MEMORY if the request alone exceeds
+ * mem_budget. */
+pne_status pne_submit(pne_server *server, const pne_network_desc *desc, const pne_options *opt,
+                      uint64_t *ticket);
+/* PNE_ERR_NOT_READY while the request is pending or running.  Otherwise
+ * fills *result (open values into result->open_values, capacity
+ * result->open_capacity), returns the request's status and forgets the
+ * ticket; with too small an open buffer it returns INVALID_ARG and keeps the
+ * result for another poll. */
+pne_status pne_poll(pne_server *server, uint64_t ticket, pne_result *result);
+pne_status pne_server_get_stats(pne_server *server, pne_server_stats *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -11,6 +11,7 @@
 #include <vector>
 
 #include "geometry.h"
+#include "runtime.h"
 #include "kernels.h"
 #include "pne.h"
 
@@ -31,6 +32,8 @@ struct pne_ctx {
     std::multimap<uint64_t, PlanEntry> cache;
     std::mutex mu;
     double wall_khz = 100000.0;  // device wall clock rate (ticks per ms)
+    void *staging = nullptr;     // pinned upload staging, reused by every batch creation
+    size_t staging_bytes = 0;
 };
 
 struct pne_network {
@@ -43,6 +46,7 @@ struct pne_network {
 
 struct pne_batch {
     pne_ctx *ctx = nullptr;
+    hipStream_t stream = nullptr;  // stream every launch and copy of the batch is enqueued on
     std::vector<pne_network *> nets;
     pne_options opt{};
     std::vector<std::shared_ptr<GeoPlan>> plans;  // per net
@@ -53,6 +57,7 @@ struct pne_batch {
     DeviceBatch db;
     NetState *h_state_pinned = nullptr;  // pinned copy of the per-network state
     NetResult *h_results_pinned = nullptr;  // pinned copy of the per-network results
+    void *h_pinned = nullptr;               // the one pinned block holding both
     int first_chunk = 4;                 // sweeps before the first convergence check
     bool launched = false;
     bool waited = false;
@@ -110,31 +115,69 @@ std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> 
     return p;
 }
 
-template <class T>
-pne_status upload(pne_batch *b, const std::vector<T> &v, const T **dst) {
-    if (v.empty()) {
-        *dst = nullptr;
-        return PNE_OK;
+// Device memory of a batch: every table and buffer is a 256-byte aligned
+// piece of one allocation.  Tables with host contents come first, so one
+// copy from the context's pinned staging buffer uploads all of them.
+struct ArenaPlan {
+    struct Piece {
+        const void *src;  // host contents, or nullptr for a device-only buffer
+        size_t bytes;
+        void **dst;
+        size_t off;
+    };
+    std::vector<Piece> up, buf;
+    template <class T>
+    void upload(const std::vector<T> &v, const T **dst) {
+        if (v.empty()) {
+            *dst = nullptr;
+            return;
+        }
+        up.push_back({v.data(), v.size() * sizeof(T), (void **)dst, 0});
     }
-    void *p = nullptr;
-    size_t n = v.size() * sizeof(T);
-    hipError_t e = hipMalloc(&p, n);
-    if (e != hipSuccess) return fail(b->ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
-    b->allocs.push_back(p);
-    b->bytes += n;
-    e = hipMemcpyAsync(p, v.data(), n, hipMemcpyHostToDevice, b->ctx->stream);
-    if (e != hipSuccess) return hip_fail(b->ctx, e, "hipMemcpyAsync");
-    *dst = (const T *)p;
-    return PNE_OK;
-}
+    template <class T>
+    void buffer(size_t bytes, T **dst) {
+        buf.push_back({nullptr, bytes ? bytes : 8, (void **)dst, 0});
+    }
+};
 
-pne_status alloc(pne_batch *b, size_t n, void **p) {
-    *p = nullptr;
-    if (n == 0) n = 8;
-    hipError_t e = hipMalloc(p, n);
-    if (e != hipSuccess) return fail(b->ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
-    b->allocs.push_back(*p);
-    b->bytes += n;
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
+    pne_ctx *ctx = b->ctx;
+    size_t off = 0;
+    for (auto &pc : ap.up) {
+        pc.off = off;
+        off += align256(pc.bytes);
+    }
+    const size_t up_bytes = off;
+    for (auto &pc : ap.buf) {
+        pc.off = off;
+        off += align256(pc.bytes);
+    }
+    const size_t total = off;
+    if (ctx->budget && ctx->used + total > ctx->budget) return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
+    void *p = nullptr;
+    if (hipMalloc(&p, total) != hipSuccess) return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
+    b->allocs.push_back(p);
+    b->bytes += total;
+    ctx->used += total;
+    if (up_bytes) {
+        if (ctx->staging_bytes < up_bytes) {
+            if (ctx->staging) (void)hipHostFree(ctx->staging);
+            ctx->staging = nullptr;
+            ctx->staging_bytes = 0;
+            const size_t want = std::max(up_bytes + up_bytes / 2, (size_t)1 << 20);
+            if (hipHostMalloc(&ctx->staging, want, hipHostMallocDefault) != hipSuccess)
+                return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+            ctx->staging_bytes = want;
+        }
+        char *st = (char *)ctx->staging;
+        for (auto &pc : ap.up) std::memcpy(st + pc.off, pc.src, pc.bytes);
+        hipError_t e = hipMemcpyAsync(p, st, up_bytes, hipMemcpyHostToDevice, b->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
+    }
+    for (auto &pc : ap.up) *pc.dst = (char *)p + pc.off;
+    for (auto &pc : ap.buf) *pc.dst = (char *)p + pc.off;
     return PNE_OK;
 }
 
@@ -153,7 +196,7 @@ hipEvent_t take_event(pne_batch *b) {
 template <class F>
 hipError_t timed(pne_batch *b, int kid, F &&fn) {
     const bool prof = (b->opt.flags & PNE_FLAG_PROFILE) != 0;
-    hipStream_t s = b->ctx->stream;
+    hipStream_t s = b->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
         e0 = take_event(b);
@@ -193,9 +236,9 @@ void free_batch(pne_batch *b) {
     b->ev_pool.clear();
     for (void *p : b->allocs) (void)hipFree(p);
     b->allocs.clear();
-    if (b->h_state_pinned) (void)hipHostFree(b->h_state_pinned);
+    if (b->h_pinned) (void)hipHostFree(b->h_pinned);
+    b->h_pinned = nullptr;
     b->h_state_pinned = nullptr;
-    if (b->h_results_pinned) (void)hipHostFree(b->h_results_pinned);
     b->h_results_pinned = nullptr;
     if (b->ctx) b->ctx->used -= std::min(b->ctx->used, b->bytes);
 }
@@ -252,11 +295,19 @@ pne_status pne_ctx_create(int device, size_t budget, void *stream, pne_ctx **out
 pne_status pne_ctx_destroy(pne_ctx *ctx) {
     if (!ctx) return PNE_ERR_INVALID_ARG;
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->staging) (void)hipHostFree(ctx->staging);
     delete ctx;
     return PNE_OK;
 }
 
 pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on_device, pne_network **out) {
+    return ctx ? pne::network_create_on(ctx, desc, on_device, ctx->stream, out) : PNE_ERR_INVALID_ARG;
+}
+
+}  // extern "C"
+
+pne_status pne::network_create_on(pne_ctx *ctx, const pne_network_desc *desc, int on_device, hipStream_t stream,
+                                  pne_network **out) {
     if (!ctx || !desc || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "null argument");
     *out = nullptr;
     auto g = std::make_shared<Geometry>();
@@ -307,8 +358,8 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on
             net->dptr[s] = net->owned + off;
             off += sz[s];
         }
-        hipError_t e = hipMemcpyAsync(p, host.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
-        if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+        hipError_t e = hipMemcpyAsync(p, host.data(), bytes, hipMemcpyHostToDevice, stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(stream);
         if (e != hipSuccess) {
             (void)hipFree(p);
             ctx->used -= bytes;
@@ -319,6 +370,9 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on
     *out = net;
     return PNE_OK;
 }
+
+extern "C" {
+
 
 pne_status pne_network_destroy(pne_network *net) {
     if (!net) return PNE_ERR_INVALID_ARG;
@@ -332,6 +386,13 @@ pne_status pne_network_destroy(pne_network *net) {
 
 pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
                             pne_batch **out) {
+    return ctx ? pne::batch_create_on(ctx, nets, n, opt, ctx->stream, out) : PNE_ERR_INVALID_ARG;
+}
+
+}  // extern "C"
+
+pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
+                                hipStream_t stream, pne_batch **out) {
     if (!ctx || !nets || n <= 0 || !opt || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "bad batch arguments");
     *out = nullptr;
     if (opt->max_excited < 0 || opt->max_excited > 32) return fail(ctx, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
@@ -342,6 +403,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
 
     auto b = std::make_unique<pne_batch>();
     b->ctx = ctx;
+    b->stream = stream;
     b->nets.assign(nets, nets + n);
     b->opt = *opt;
     const int K = opt->max_excited;
@@ -690,9 +752,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     if (regauge_lds > 150 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
     pne_status st;
     DeviceBatch &db = b->db;
-#define UP(vec, field)                                   \
-    st = upload(b.get(), vec, &db.field);                \
-    if (st != PNE_OK) { free_batch(b.get()); return st; }
+    ArenaPlan ap;
+#define UP(vec, field) ap.upload(vec, &db.field)
     UP(sites, sites);
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
@@ -741,11 +802,7 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     db.regauge_lds = regauge_lds;
     db.cluster_lds = cl_lds;
     db.precision = prec;
-    void *p;
-#define AL(bytes, field, type)                                             \
-    st = alloc(b.get(), (bytes), &p);                                      \
-    if (st != PNE_OK) { free_batch(b.get()); return st; }                  \
-    db.field = (type)p;
+#define AL(bytes, field, type) ap.buffer((bytes), &db.field)
     AL(sizeof(NetState) * n, state, NetState *);
     AL(sizeof(double) * msg, msg0, double *);
     AL(sizeof(double) * msg, msg1, double *);
@@ -756,17 +813,20 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     AL(sizeof(double) * std::max<int64_t>(wtot, 1), w, double *);
     AL(sizeof(NetResult) * n, results, NetResult *);
 #undef AL
-    if (ctx->budget && ctx->used + b->bytes > ctx->budget) {
+    st = commit_arena(b.get(), ap);
+    if (st != PNE_OK) {
         free_batch(b.get());
-        return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
+        return st;
     }
-    ctx->used += b->bytes;
-    if (hipHostMalloc((void **)&b->h_state_pinned, sizeof(NetState) * n, hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc((void **)&b->h_results_pinned, sizeof(NetResult) * n, hipHostMallocDefault) != hipSuccess) {
+    // one pinned block for the per-network state and results read back by every wait
+    const size_t st_bytes = align256(sizeof(NetState) * n);
+    if (hipHostMalloc(&b->h_pinned, st_bytes + sizeof(NetResult) * n, hipHostMallocDefault) != hipSuccess) {
         free_batch(b.get());
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
     }
-    hipError_t e = hipStreamSynchronize(ctx->stream);
+    b->h_state_pinned = (NetState *)b->h_pinned;
+    b->h_results_pinned = (NetResult *)((char *)b->h_pinned + st_bytes);
+    hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         free_batch(b.get());
         return hip_fail(ctx, e, "batch upload");
@@ -777,10 +837,13 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
     return PNE_OK;
 }
 
+extern "C" {
+
+
 pne_status pne_batch_launch(pne_batch *b) {
     if (!b) return PNE_ERR_INVALID_ARG;
     pne_ctx *ctx = b->ctx;
-    hipStream_t s = ctx->stream;
+    hipStream_t s = b->stream;
     const DeviceBatch &db = b->db;
     HIP_TRY(ctx, timed(b, KID_INIT, [&](hipStream_t st) { return launch_init(db, st); }));
     const int max_iter = b->opt.bp_max_iter;
@@ -829,10 +892,10 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
     pne_ctx *ctx = b->ctx;
     const int n = (int)b->nets.size();
     HIP_TRY(ctx, hipMemcpyAsync(b->h_results_pinned, b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
-                                ctx->stream));
+                                b->stream));
     HIP_TRY(ctx, hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost,
-                                ctx->stream));
-    HIP_TRY(ctx, hipStreamSynchronize(ctx->stream));
+                                b->stream));
+    HIP_TRY(ctx, hipStreamSynchronize(b->stream));
     b->h_state.assign(b->h_state_pinned, b->h_state_pinned + n);
     collect_times(b);
     b->waited = true;
@@ -880,7 +943,7 @@ pne_status pne_batch_run(pne_batch *b, pne_result *results) {
 
 pne_status pne_batch_destroy(pne_batch *b) {
     if (!b) return PNE_ERR_INVALID_ARG;
-    if (b->ctx) (void)hipStreamSynchronize(b->ctx->stream);
+    if (b->ctx) (void)hipStreamSynchronize(b->stream);
     free_batch(b);
     delete b;
     return PNE_OK;

@@ -74,6 +74,34 @@ class ResultStruct(ctypes.Structure):
     ]
 
 
+class ServerOptions(ctypes.Structure):
+    _fields_ = [
+        ("mem_budget", ctypes.c_size_t),
+        ("max_batch", ctypes.c_int32),
+        ("pipeline_depth", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class ServerStats(ctypes.Structure):
+    _fields_ = [
+        ("submitted", ctypes.c_int64),
+        ("completed", ctypes.c_int64),
+        ("failed", ctypes.c_int64),
+        ("batches", ctypes.c_int64),
+        ("pending", ctypes.c_int64),
+        ("device_bytes_admitted", ctypes.c_int64),
+        ("latency_p50_ms", ctypes.c_double),
+        ("latency_p99_ms", ctypes.c_double),
+        ("latency_mean_ms", ctypes.c_double),
+        ("latency_max_ms", ctypes.c_double),
+        ("networks_per_s", ctypes.c_double),
+        ("busy_s", ctypes.c_double),
+        ("prep_s", ctypes.c_double),
+        ("wait_s", ctypes.c_double),
+    ]
+
+
 # numpy view of pne_result (same field offsets as the C struct)
 RESULT_DTYPE = np.dtype({
     "names": ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
@@ -111,6 +139,14 @@ _PROTOS = {
                                               _i32p, _i32p]),
     "pne_batch_messages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64]),
     "pne_batch_phase_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32]),
+    "pne_server_options_default": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
+    "pne_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
+                                         ctypes.POINTER(ctypes.c_void_p)]),
+    "pne_server_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(NetworkDesc), ctypes.POINTER(Options),
+                                  ctypes.POINTER(ctypes.c_uint64)]),
+    "pne_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ResultStruct)]),
+    "pne_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "pne_batch_kernel_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
                                               ctypes.c_int32]),
     "pne_batch_cluster_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64,
@@ -465,3 +501,70 @@ class Batch:
             self.handle, i, vals.ctypes.data_as(_f64p), n.value, ctypes.byref(n),
             offs.ctypes.data_as(ctypes.POINTER(ctypes.c_int64))), self.ctx.handle)
         return vals[: n.value], offs
+
+
+PNE_ERR_NOT_READY = -6
+
+
+class Server:
+    """Continuous-batching request server on a context (see pne_server_* in
+    pne.h).  While it exists, its worker thread is the context's only user."""
+
+    def __init__(self, ctx: Context, mem_budget: int = 0, max_batch: int = 1024, pipeline_depth: int = 2):
+        self.ctx = ctx
+        self.lib = ctx.lib
+        so = ServerOptions()
+        self.lib.pne_server_options_default(ctypes.byref(so))
+        so.mem_budget = int(mem_budget)
+        so.max_batch = int(max_batch)
+        so.pipeline_depth = int(pipeline_depth)
+        h = ctypes.c_void_p()
+        _check(self.lib, self.lib.pne_server_create(ctx.handle, ctypes.byref(so), ctypes.byref(h)))
+        self.handle = h
+        self._alive = True
+        self._open_shape = {}
+
+    def submit(self, obj, K=6, precision="fp64", tol=1e-13, max_iter=500, persistent=True) -> int:
+        tensors, bonds, open_legs = _net_parts(obj)
+        da = _DescArrays(tensors, bonds, open_legs)
+        o = _options(K, precision, tol, max_iter, 0, False, persistent)
+        t = ctypes.c_uint64(0)
+        _check(self.lib, self.lib.pne_submit(self.handle, ctypes.byref(da.desc), ctypes.byref(o), ctypes.byref(t)))
+        if da.n_open:
+            self._open_shape[t.value] = tuple(int(tensors[a].shape[b]) for a, b in
+                                              np.asarray(open_legs).reshape(-1, 2))
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        """Result for `ticket`, or None while it is pending or running."""
+        shape = self._open_shape.get(ticket)
+        m = int(np.prod(shape)) if shape else 0
+        buf = np.zeros(max(1, m), np.float64)
+        r = ResultStruct()
+        r.open_values = buf.ctypes.data_as(_f64p) if m else None
+        r.open_capacity = m
+        st = self.lib.pne_poll(self.handle, ctypes.c_uint64(ticket), ctypes.byref(r))
+        if st == PNE_ERR_NOT_READY:
+            return None
+        if st == -1 and r.status >= 0:
+            raise PNEError(st, "unknown ticket or open buffer too small")
+        self._open_shape.pop(ticket, None)
+        ov = buf[: r.n_open_values].copy().reshape(shape) if (m and r.n_open_values) else None
+        return Result(r.status, r.sign, r.log_abs, r.log_abs_bp, r.bp_iters, r.bp_residual, r.n_cluster_terms,
+                      r.n_config_terms, ov)
+
+    def stats(self) -> dict:
+        st = ServerStats()
+        _check(self.lib, self.lib.pne_server_get_stats(self.handle, ctypes.byref(st)))
+        return {name: getattr(st, name) for name, _ in ServerStats._fields_}
+
+    def close(self):
+        if self._alive:
+            self.lib.pne_server_destroy(self.handle)
+            self._alive = False
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

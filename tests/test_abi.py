@@ -59,6 +59,9 @@ int main(void) {
   P(pne_options, bp_tol) P(pne_options, bp_max_iter) P(pne_options, flags)
   P(pne_result, log_abs) P(pne_result, bp_iters) P(pne_result, bp_residual)
   P(pne_result, n_config_terms) P(pne_result, open_values) P(pne_result, open_capacity)
+  printf("sopt %zu\nsstat %zu\n", sizeof(pne_server_options), sizeof(pne_server_stats));
+  P(pne_server_options, max_batch) P(pne_server_options, pipeline_depth)
+  P(pne_server_stats, device_bytes_admitted) P(pne_server_stats, latency_p50_ms) P(pne_server_stats, busy_s)
   return 0;
 }
 ''')
@@ -68,10 +71,13 @@ int main(void) {
     assert int(out["desc"]) == ctypes.sizeof(B.NetworkDesc)
     assert int(out["opt"]) == ctypes.sizeof(B.Options)
     assert int(out["res"]) == ctypes.sizeof(B.ResultStruct)
+    assert int(out["sopt"]) == ctypes.sizeof(B.ServerOptions)
+    assert int(out["sstat"]) == ctypes.sizeof(B.ServerStats)
     for key, val in out.items():
         if "." in key:
             T, f = key.split(".")
-            cls = {"pne_network_desc": B.NetworkDesc, "pne_options": B.Options, "pne_result": B.ResultStruct}[T]
+            cls = {"pne_network_desc": B.NetworkDesc, "pne_options": B.Options, "pne_result": B.ResultStruct,
+                   "pne_server_options": B.ServerOptions, "pne_server_stats": B.ServerStats}[T]
             assert getattr(cls, f).offset == int(val), key
 
 
@@ -79,6 +85,16 @@ def test_options_default(lib):
     o = B.Options()
     assert lib.pne_options_default(ctypes.byref(o)) == 0
     assert o.max_excited == 4 and o.precision == 0 and o.bp_tol == 1e-13 and o.bp_max_iter == 500
+
+
+def test_server_options_default_and_null_context(lib):
+    so = B.ServerOptions()
+    assert lib.pne_server_options_default(ctypes.byref(so)) == 0
+    assert so.mem_budget == 0 and so.max_batch == 1024 and so.pipeline_depth == 2
+    h = ctypes.c_void_p()
+    assert lib.pne_server_create(None, ctypes.byref(so), ctypes.byref(h)) == B.PNE_ERR_INVALID_ARG
+    assert lib.pne_submit(None, None, None, None) == B.PNE_ERR_INVALID_ARG
+    assert lib.pne_poll(None, ctypes.c_uint64(1), None) == B.PNE_ERR_INVALID_ARG
 
 
 def test_context_without_gpu_reports_device_error(lib):
