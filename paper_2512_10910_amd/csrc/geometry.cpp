@@ -297,6 +297,45 @@ LocalCluster localise(const Geometry &g, const int *bonds, int k) {
     return lc;
 }
 
+// A cluster that is one simple cycle (every vertex with exactly two legs,
+// all bond labels of one dimension, no open legs): the cycle walked from
+// local vertex 0, as (vertex, leg towards the previous vertex, leg towards
+// the next vertex) per position.  Empty for any other cluster.
+std::vector<int> simple_cycle(const LocalCluster &lc) {
+    const int nv = (int)lc.verts.size();
+    if (nv < 2) return {};
+    for (int v = 0; v < nv; ++v)
+        if (lc.vlegs[v].size() != 2) return {};
+    for (size_t l = 0; l < lc.label_dim.size(); ++l)
+        if (lc.label_open_index[l] >= 0 || lc.label_dim[l] != lc.label_dim[0]) return {};
+    std::vector<int> out;
+    int v = 0, m_in = 1;  // enter vertex 0 through its leg 1, leave through leg 0
+    std::vector<char> seen(nv, 0);
+    for (int j = 0; j < nv; ++j) {
+        if (seen[v]) return {};
+        seen[v] = 1;
+        const int m_out = 1 - m_in;
+        out.push_back(v);
+        out.push_back(m_in);
+        out.push_back(m_out);
+        const int lab = lc.vlegs[v][m_out];
+        int nxt = -1, nm = -1;
+        for (int u = 0; u < nv && nxt < 0; ++u) {
+            if (u == v) continue;
+            for (int m = 0; m < 2; ++m)
+                if (lc.vlegs[u][m] == lab) {
+                    nxt = u;
+                    nm = m;
+                }
+        }
+        if (nxt < 0) return {};
+        v = nxt;
+        m_in = nm;
+    }
+    if (v != 0 || m_in != 1) return {};  // must close on vertex 0's leg 1
+    return out;
+}
+
 // Class key: structure of the cluster up to the labelling induced by sorted
 // site and bond ids (translates on a lattice share it).
 std::vector<int> class_key(const LocalCluster &lc, const Geometry &g) {
@@ -624,6 +663,8 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
             plan->inst_cluster.emplace_back();
             plan->inst_site.emplace_back();
             plan->inst_slots.emplace_back();
+            plan->loop_order.push_back(simple_cycle(lc));
+            plan->loop_e.push_back(plan->loop_order.back().empty() ? 0 : lc.label_dim[0]);
         } else {
             cid = it->second;
         }

@@ -56,6 +56,12 @@ struct GeoPlan {
     std::vector<std::vector<int>> inst_cluster;    // per class
     std::vector<std::vector<int>> inst_site;       // per class: n_inst * n_verts (local site ids)
     std::vector<std::vector<uint32_t>> inst_slots; // per class: n_inst * n_verts packed slots
+    // per class, when the cluster is one simple cycle of legs of a single
+    // dimension e (every site with exactly two cluster legs, no open leg):
+    // for each cycle position, (local vertex, leg to the previous vertex,
+    // leg to the next vertex); empty otherwise
+    std::vector<std::vector<int>> loop_order;
+    std::vector<int> loop_e;
 
     std::vector<Bucket> buckets;
     std::vector<int> pair_a, pair_b;  // overlapping cluster pairs (|a|+|b| <= K)

@@ -42,10 +42,9 @@ struct DeviceBatch {
     const StepDesc *steps = nullptr;
     const ClusterBlock *cblocks = nullptr;
     int n_cblocks = 0;
-    const int *inst_site = nullptr;       // global site ids, n_verts per instance
-    const uint32_t *inst_slots = nullptr;
-    const int64_t *inst_wout = nullptr;   // per instance: weight offset
-    const int64_t *inst_rec = nullptr;    // per instance: offset into inst_site/inst_slots
+    const InstStep *inst_tab = nullptr;   // per plan class: n_inst * n_steps records
+    const int *inst_w = nullptr;          // per plan class: weight offset of each instance
+    const PlanNet *pnets = nullptr;       // per plan: its networks' slice and weight bases
     size_t cluster_lds = 0;
     double *w = nullptr;
     // combine

@@ -150,22 +150,104 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
                               st, s_xg);
 }
 
+// Logical block of a physical one so that consecutive logical blocks run on
+// the same XCD (workgroups are dealt to the eight XCDs round robin): blocks
+// of one network, which read the same slices, then share that XCD's L2.
+__device__ inline int xcd_block(int p, int nb) {
+    const int x = p & 7, q = nb >> 3, r = nb & 7;
+    return x * q + min(x, r) + (p >> 3);
+}
+
+// A cycle of L sites whose cluster legs all have dimension E: the term is
+// Tr(M_0 M_1 ... M_{L-1}) with M_j[a][b] the excited block of site j's slice
+// (a on the leg towards site j-1, b towards site j+1).  One thread holds the
+// running product (E x E) in registers.
+template <int E, typename S>
+__device__ inline typename SliceIO<S>::acc loop_trace(const InstStep *__restrict__ rec, int L,
+                                                      const S *__restrict__ slices, int64_t base) {
+    using A = typename SliceIO<S>::acc;
+    A F[E][E], M[E][E];
+    InstStep r = rec[0];
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) F[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+    for (int j = 1; j < L; ++j) {
+        r = rec[j];
+#pragma unroll
+        for (int a = 0; a < E; ++a)
+#pragma unroll
+            for (int b = 0; b < E; ++b) M[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+        if (j == L - 1) break;
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+            A row[E];
+#pragma unroll
+            for (int b = 0; b < E; ++b) {
+                A acc = A(0);
+#pragma unroll
+                for (int c = 0; c < E; ++c) acc += F[a][c] * M[c][b];
+                row[b] = acc;
+            }
+#pragma unroll
+            for (int b = 0; b < E; ++b) F[a][b] = row[b];
+        }
+    }
+    A tr = A(0);
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) tr += F[a][b] * M[b][a];
+    return tr;
+}
+
 // Cluster contraction by a per-class plan: the frontier tensor F absorbs one
 // excited slice per step (F_next[out] = sum_shared F[.] X[.]).  A class runs
-// `group` lanes per instance; every step is uniform across the block.
+// `group` lanes per instance; every step is uniform across the block.  An
+// instance's step records (slice offset from its network's slice base, leg
+// strides) come from the plan's instance table; classes whose frontier has
+// one entry throughout are a plain product of one slice element per vertex,
+// one instance per thread.
 template <typename S>
 __global__ void __launch_bounds__(kClThreads) k_clusters(
     const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps,
-    const ClusterBlock *__restrict__ blocks, const int *__restrict__ inst_site,
-    const uint32_t *__restrict__ inst_slots, const int64_t *__restrict__ inst_rec,
-    const int64_t *__restrict__ inst_wout, const SiteRec *__restrict__ sites, const S *__restrict__ slices,
-    double *__restrict__ w) {
+    const ClusterBlock *__restrict__ blocks, const InstStep *__restrict__ tab, const int *__restrict__ inst_w,
+    const PlanNet *__restrict__ pnets, const S *__restrict__ slices, double *__restrict__ w) {
     using A = typename SliceIO<S>::acc;
-    const ClusterBlock blk = blocks[blockIdx.x];
+    const ClusterBlock blk = blocks[xcd_block(blockIdx.x, gridDim.x)];
     const ClassDesc cd = classes[blk.cls];
+    const int tid = threadIdx.x;
+    if (cd.loop_e) {
+        if (tid >= blk.count) return;
+        const int f = blk.flat_begin + tid;
+        const int net = f / cd.n_inst;
+        const int k = f - net * cd.n_inst;
+        const PlanNet pn = pnets[cd.pnet_begin + net];
+        const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_verts;
+        A v = A(0);
+        switch (cd.loop_e) {
+            case 2: v = loop_trace<2, S>(rec, cd.n_verts, slices, pn.slice_base); break;
+            case 3: v = loop_trace<3, S>(rec, cd.n_verts, slices, pn.slice_base); break;
+            case 4: v = loop_trace<4, S>(rec, cd.n_verts, slices, pn.slice_base); break;
+            default: v = loop_trace<5, S>(rec, cd.n_verts, slices, pn.slice_base); break;
+        }
+        w[pn.w_base + inst_w[cd.w_begin + k]] = (double)v;
+        return;
+    }
+    if (cd.scalar) {
+        if (tid >= blk.count) return;
+        const int f = blk.flat_begin + tid;
+        const int net = f / cd.n_inst;
+        const int k = f - net * cd.n_inst;
+        const PlanNet pn = pnets[cd.pnet_begin + net];
+        const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_steps;
+        A prod = A(1);
+        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, pn.slice_base + rec[st].xoff);
+        w[pn.w_base + inst_w[cd.w_begin + k]] = (double)prod;
+        return;
+    }
     extern __shared__ double lds_raw[];
     __shared__ StepDesc s_steps[kMaxVerts];
-    const int tid = threadIdx.x;
     for (int i = tid; i < cd.n_steps * (int)(sizeof(StepDesc) / 4); i += kClThreads)
         reinterpret_cast<int32_t *>(s_steps)[i] =
             reinterpret_cast<const int32_t *>(steps + cd.step_begin)[i];
@@ -173,36 +255,31 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
     const int lane = tid & (g - 1);
     const int slot = tid / g;
     const bool valid = slot < blk.count;
-    const int64_t inst = blk.inst_begin + slot;
+    const int f = blk.flat_begin + (valid ? slot : 0);
+    const int net = f / cd.n_inst;
+    const int k = f - net * cd.n_inst;
+    const PlanNet pn = pnets[cd.pnet_begin + net];
+    const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_steps;
     A *F = reinterpret_cast<A *>(lds_raw) + (size_t)slot * 2 * cd.max_f;
     A *G = F + cd.max_f;
     if (lane == 0) F[0] = A(1);
-    const int64_t rec = valid ? inst_rec[inst] : 0;
     __syncthreads();
     for (int st = 0; st < cd.n_steps; ++st) {
         const StepDesc &sd = s_steps[st];
         if (valid) {
-            const int site = inst_site[rec + sd.vert];
-            const uint32_t slots = inst_slots[rec + sd.vert];
-            const SiteRec &sr = sites[site];
+            const InstStep r = rec[st];
+            const int64_t xbase = pn.slice_base + r.xoff;
             int xs[kMaxLab];
-            int64_t xbase = sr.slice_off;
 #pragma unroll
-            for (int m = 0; m < kMaxLab; ++m) {
-                xs[m] = 0;
-                if (m < sd.n_xl) {
-                    xs[m] = sr.stride[(slots >> (4 * m)) & 15u];
-                    if (sd.x_excited[m]) xbase += xs[m];  // excited indices start at 1
-                }
-            }
+            for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? r.xs[m] : 0;
             for (int o = lane; o < sd.n_out; o += g) {
                 int rem = o, fb = 0, xb = 0;
-                for (int k = sd.n_ol - 1; k >= 0; --k) {
-                    const int dd = sd.out_dim[k];
+                for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
+                    const int dd = sd.out_dim[kk];
                     const int dg = rem % dd;
                     rem /= dd;
-                    fb += dg * sd.out_fs[k];
-                    const int xl = sd.out_xl[k];
+                    fb += dg * sd.out_fs[kk];
+                    const int xl = sd.out_xl[kk];
                     if (xl >= 0) {
 #pragma unroll
                         for (int m = 0; m < kMaxLab; ++m)
@@ -211,15 +288,15 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                 }
                 int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
 #pragma unroll
-                for (int k = 0; k < kMaxLab; ++k) {
-                    sdg[k] = 0;
-                    sfs[k] = 0;
-                    sxs[k] = 0;
-                    if (k < sd.n_sl) {
-                        sfs[k] = sd.sum_fs[k];
+                for (int kk = 0; kk < kMaxLab; ++kk) {
+                    sdg[kk] = 0;
+                    sfs[kk] = 0;
+                    sxs[kk] = 0;
+                    if (kk < sd.n_sl) {
+                        sfs[kk] = sd.sum_fs[kk];
 #pragma unroll
                         for (int m = 0; m < kMaxLab; ++m)
-                            if (m == sd.sum_xl[k]) sxs[k] = xs[m];
+                            if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
                     }
                 }
                 A acc = A(0);
@@ -228,16 +305,16 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                 for (int t = 0; t < sd.n_sum; ++t) {
                     acc += F[fo] * SliceIO<S>::load(slices, xo);
 #pragma unroll
-                    for (int k = kMaxLab - 1; k >= 0; --k) {
-                        if (k >= sd.n_sl) continue;
-                        if (++sdg[k] < sd.sum_dim[k]) {
-                            fo += sfs[k];
-                            xo += sxs[k];
+                    for (int kk = kMaxLab - 1; kk >= 0; --kk) {
+                        if (kk >= sd.n_sl) continue;
+                        if (++sdg[kk] < sd.sum_dim[kk]) {
+                            fo += sfs[kk];
+                            xo += sxs[kk];
                             break;
                         }
-                        fo -= (sd.sum_dim[k] - 1) * sfs[k];
-                        xo -= (int64_t)(sd.sum_dim[k] - 1) * sxs[k];
-                        sdg[k] = 0;
+                        fo -= (sd.sum_dim[kk] - 1) * sfs[kk];
+                        xo -= (int64_t)(sd.sum_dim[kk] - 1) * sxs[kk];
+                        sdg[kk] = 0;
                     }
                 }
                 G[o] = acc;
@@ -249,7 +326,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         G = t;
     }
     if (valid) {
-        const int64_t wo = inst_wout[inst];
+        const int64_t wo = pn.w_base + inst_w[cd.w_begin + k];
         for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
     }
 }
@@ -495,18 +572,18 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
     switch (b.precision) {
         case 0:
             hipLaunchKernelGGL(k_clusters<double>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout, b.sites,
+                               b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
                                (const double *)b.slices, b.w);
             break;
         case 1:
             hipLaunchKernelGGL(k_clusters<float>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout, b.sites,
+                               b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
                                (const float *)b.slices, b.w);
             break;
         default:
             hipLaunchKernelGGL(k_clusters<uint16_t>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s,
-                               b.classes, b.steps, b.cblocks, b.inst_site, b.inst_slots, b.inst_rec, b.inst_wout,
-                               b.sites, (const uint16_t *)b.slices, b.w);
+                               b.classes, b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
+                               (const uint16_t *)b.slices, b.w);
             break;
     }
     return hipGetLastError();

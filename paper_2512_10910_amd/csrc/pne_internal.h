@@ -115,13 +115,39 @@ struct ClassDesc {
     int32_t max_f;       // largest frontier (entries)
     int32_t group;       // lanes per instance (power of two, <= 64)
     int32_t out_size;    // entries of the result tensor (1 for closed clusters)
-    int32_t pad0, pad1;
+    // batch tables (filled per batch; the plan's own copy leaves them 0)
+    int32_t tab_off;     // first InstStep record of the class (instance-major, n_steps per instance)
+    int32_t w_begin;     // first entry of the class in the per-instance weight-offset table
+    int32_t n_inst;      // instances per network
+    int32_t pnet_begin;  // first PlanNet of the networks sharing the class's plan
+    int32_t n_pnets;
+    int32_t scalar;      // 1: frontier of one entry throughout (every leg of dimension 1)
+    int32_t loop_e;      // > 0: a simple cycle of legs of dimension loop_e, evaluated as the
+                         // trace of a matrix product (records in cycle order)
+    int32_t pad;
+};
+
+// One step of one instance: where the absorbed slice's block starts (element
+// offset from the network's slice base, excited legs already at index 1)
+// and the strides of the slice legs the step uses.  For a cycle class the
+// records follow the cycle, xs[0] being the leg towards the previous site
+// and xs[1] the leg towards the next.
+struct InstStep {
+    int32_t xoff;
+    int32_t xs[kMaxLab];
+    int32_t pad[3];
+};
+
+// A network in the batch that uses a given plan.
+struct PlanNet {
+    int64_t slice_base;  // element offset of the network's first slice
+    int64_t w_base;      // offset of the network's first cluster weight
 };
 
 // A block of cluster work: `count` consecutive instances of one class.
 struct ClusterBlock {
     int32_t cls;
-    int32_t inst_begin;
+    int32_t flat_begin;  // first (network, instance) pair, network-major: net * n_inst + instance
     int32_t count;
     int32_t pad;
 };

@@ -656,9 +656,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<ClassDesc> classes;
     std::vector<StepDesc> steps;
     std::vector<ClusterBlock> cblocks;
-    std::vector<int> inst_site;
-    std::vector<uint32_t> inst_slots;
-    std::vector<int64_t> inst_rec, inst_wout;
+    std::vector<InstStep> inst_tab;
+    std::vector<int> inst_w;
+    std::vector<PlanNet> pnets;
     std::vector<CombineRec> crec(n);
     std::vector<GeoRec> geos;
     std::vector<Bucket> buckets;
@@ -712,39 +712,116 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         cr.pb = p->pb;
     }
     if (cl_lds > 64 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: cluster frontier too large for LDS");
-    // instances grouped by batch class across networks
-    std::vector<std::vector<std::pair<int, int>>> per_class(classes.size());  // (net, local instance)
-    for (int i = 0; i < n; ++i) {
-        const GeoPlan *p = b->plans[i].get();
-        int c0 = plan_index[p];
-        for (size_t c = 0; c < p->classes.size(); ++c)
-            for (size_t k = 0; k < p->inst_cluster[c].size(); ++k) per_class[c0 + c].push_back({i, (int)k});
-    }
-    for (size_t cid = 0; cid < classes.size(); ++cid) {
-        const ClassDesc &cd = classes[cid];
-        const int ipb = 256 / cd.group;
-        int64_t first = (int64_t)inst_wout.size();
-        for (auto &pr : per_class[cid]) {
-            int i = pr.first, k = pr.second;
+    // Instance tables per plan (shared by every network using the plan):
+    // for each instance and contraction step, the absorbed slice's element
+    // offset from the network's slice base (excited legs at index 1) and its
+    // leg strides; a network only adds its slice and weight bases.  Blocks
+    // walk the plan's networks in order, each block covering up to 256/group
+    // consecutive (network, instance) pairs of one class.
+    {
+        std::map<const GeoPlan *, std::vector<int>> nets_of_plan;
+        std::vector<const GeoPlan *> plan_order;
+        for (int i = 0; i < n; ++i) {
             const GeoPlan *p = b->plans[i].get();
-            int lc = (int)cid - plan_index[p];
-            int cluster = p->inst_cluster[lc][k];
-            inst_rec.push_back((int64_t)inst_site.size());
-            for (int v = 0; v < cd.n_verts; ++v) {
-                inst_site.push_back(b->site_base[i] + p->inst_site[lc][(size_t)k * cd.n_verts + v]);
-                inst_slots.push_back(p->inst_slots[lc][(size_t)k * cd.n_verts + v]);
+            if (!nets_of_plan.count(p)) plan_order.push_back(p);
+            nets_of_plan[p].push_back(i);
+        }
+        for (const GeoPlan *p : plan_order) {
+            const std::vector<int> &pn = nets_of_plan[p];
+            const Geometry &g = *nets[pn[0]]->geo;
+            const int pnet_begin = (int)pnets.size();
+            for (int i : pn) pnets.push_back(PlanNet{sites[b->site_base[i]].slice_off, b->w_base[i]});
+            // slice offsets and strides of the plan's geometry
+            std::vector<int64_t> soff(g.n_sites + 1, 0);
+            for (int s2 = 0; s2 < g.n_sites; ++s2) {
+                int64_t sz = 1;
+                for (int l = 0; l < g.rank[s2]; ++l) sz *= g.dim[g.slot(s2, l)];
+                soff[s2 + 1] = soff[s2] + sz;
             }
-            inst_wout.push_back(b->w_base[i] + p->w_off[cluster]);
+            auto stride_of = [&](int site, int slot) {
+                int64_t st2 = 1;
+                for (int l = g.rank[site] - 1; l > slot; --l) st2 *= g.dim[g.slot(site, l)];
+                return st2;
+            };
+            const int c0 = plan_index[p];
+            const int ncls = (int)p->classes.size();
+            for (int c = 0; c < ncls; ++c) {
+                ClassDesc &cd = classes[c0 + c];
+                cd.tab_off = (int)inst_tab.size();
+                cd.w_begin = (int)inst_w.size();
+                cd.n_inst = (int)p->inst_cluster[c].size();
+                cd.pnet_begin = pnet_begin;
+                cd.n_pnets = (int)pn.size();
+                cd.scalar = (cd.max_f == 1 && cd.out_size == 1) ? 1 : 0;
+                const std::vector<int> &cyc = p->loop_order[c];
+                cd.loop_e = 0;
+                if (!cd.scalar && !cyc.empty() && p->loop_e[c] >= 2 && p->loop_e[c] <= 5 &&
+                    (int)cyc.size() == 3 * cd.n_verts)
+                    cd.loop_e = p->loop_e[c];
+                for (int k = 0; k < cd.n_inst; ++k) {
+                    inst_w.push_back((int)p->w_off[p->inst_cluster[c][k]]);
+                    if (cd.loop_e) {
+                        for (int j = 0; j < cd.n_verts; ++j) {
+                            const int v = cyc[3 * j];
+                            const int site = p->inst_site[c][(size_t)k * cd.n_verts + v];
+                            const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + v];
+                            InstStep r;
+                            std::memset(&r, 0, sizeof r);
+                            const int64_t s_in = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 1])) & 15u));
+                            const int64_t s_out = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 2])) & 15u));
+                            r.xs[0] = (int32_t)s_in;
+                            r.xs[1] = (int32_t)s_out;
+                            r.xoff = (int32_t)(soff[site] + s_in + s_out);  // excited indices start at 1
+                            inst_tab.push_back(r);
+                        }
+                        continue;
+                    }
+                    for (int st2 = 0; st2 < cd.n_steps; ++st2) {
+                        const StepDesc &sd = steps[cd.step_begin + st2];
+                        const int site = p->inst_site[c][(size_t)k * cd.n_verts + sd.vert];
+                        const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + sd.vert];
+                        InstStep r;
+                        std::memset(&r, 0, sizeof r);
+                        int64_t xo = soff[site];
+                        for (int m = 0; m < sd.n_xl; ++m) {
+                            const int64_t sm = stride_of(site, (int)((slots >> (4 * m)) & 15u));
+                            r.xs[m] = (int32_t)sm;
+                            if (sd.x_excited[m]) xo += sm;  // excited indices start at 1
+                        }
+                        r.xoff = (int32_t)xo;
+                        inst_tab.push_back(r);
+                    }
+                }
+            }
+            // blocks: networks in order, classes interleaved
+            std::vector<int> pend_begin(ncls, 0), pend_count(ncls, 0);
+            auto emit = [&](int c) {
+                ClusterBlock cb;
+                cb.cls = c0 + c;
+                cb.flat_begin = pend_begin[c];
+                cb.count = pend_count[c];
+                cb.pad = 0;
+                cblocks.push_back(cb);
+                pend_count[c] = 0;
+            };
+            for (size_t j = 0; j < pn.size(); ++j)
+                for (int c = 0; c < ncls; ++c) {
+                    const ClassDesc &cd = classes[c0 + c];
+                    const int ipb = (cd.scalar || cd.loop_e) ? 256 : 256 / cd.group;
+                    int64_t f0 = (int64_t)j * cd.n_inst, f1 = f0 + cd.n_inst;
+                    while (f0 < f1) {
+                        if (pend_count[c] == 0) pend_begin[c] = (int)f0;
+                        const int64_t take = std::min<int64_t>(ipb - pend_count[c], f1 - f0);
+                        pend_count[c] += (int)take;
+                        f0 += take;
+                        if (pend_count[c] == ipb) emit(c);
+                    }
+                }
+            for (int c = 0; c < ncls; ++c)
+                if (pend_count[c] > 0) emit(c);
         }
-        int64_t cnt = (int64_t)inst_wout.size() - first;
-        for (int64_t k = 0; k < cnt; k += ipb) {
-            ClusterBlock cb;
-            cb.cls = (int)cid;
-            cb.inst_begin = (int)(first + k);
-            cb.count = (int)std::min<int64_t>(ipb, cnt - k);
-            cb.pad = 0;
-            cblocks.push_back(cb);
-        }
+        if (inst_tab.size() > (size_t)INT32_MAX || pnets.size() > (size_t)INT32_MAX)
+            return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: batch too large");
     }
 
     // device allocation
@@ -781,10 +858,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(classes, classes);
     UP(steps, steps);
     UP(cblocks, cblocks);
-    UP(inst_site, inst_site);
-    UP(inst_slots, inst_slots);
-    UP(inst_rec, inst_rec);
-    UP(inst_wout, inst_wout);
+    UP(inst_tab, inst_tab);
+    UP(inst_w, inst_w);
+    UP(pnets, pnets);
     UP(crec, crec);
     UP(geos, geos);
     UP(buckets, buckets);
