@@ -93,6 +93,42 @@ def regauge_bytes(net, slice_bytes: int) -> int:
     return b
 
 
+# sources compiled into the persistent BP kernel; a committed HBM-traffic
+# profile counts only while their hash matches the one it records
+KERNEL_SOURCES = ["paper_2512_10910_amd/csrc/bp_persistent.hip", "paper_2512_10910_amd/csrc/regauge.h",
+                  "paper_2512_10910_amd/csrc/kernels.h", "paper_2512_10910_amd/csrc/pne_internal.h"]
+TRAFFIC_PROFILE = "profiles/hbm_traffic_16x16_D4D3_K6_fp32.md"
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by the copy calibration), or
+    None when the summary is missing or was taken on other kernel sources."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    vals = {}
+    with open(path) as fh:
+        for line in fh:
+            if line.startswith("<!-- ") and "=" in line:
+                k, v = line[5:].split("-->")[0].strip().split("=", 1)
+                vals[k.strip()] = v.strip()
+    if vals.get("source_hash") != kernel_source_hash():
+        return None
+    v = vals.get(f"traffic_bytes_per_launch.{kernel}")
+    return int(float(v)) if v else None
+
+
 def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int):
     """Serving requests i = 0..n_req-1 (seed 40000+i): saturated capacity
     (all submitted at once), then Poisson arrivals (seed 4) at 0.7 x capacity;
@@ -211,8 +247,32 @@ def main():
     print(f"bench: built {len(nets_in)} networks in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
     ctx = pne.Context(0)
     nets = [ctx.network(n) for n in nets_in]
-    batch = ctx.batch(nets, K=args.K, precision=args.precision, profile=not args.no_events)
-    print(f"bench: prepared batch in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
+    slice_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    bp_kernels = ("bp_persistent", "bp_sweep")
+
+    # Breakdown pass (outside the timed region): every kernel bracketed by HIP
+    # events, to name the dominant kernel and report the per-kernel split.
+    pb = ctx.batch(nets, K=args.K, precision=args.precision, profile=True)
+    for _ in range(max(1, args.warmup)):
+        pb.run_arrays(raise_on_error=True)
+    pb.kernel_times(reset=True)
+    bd_steps = max(3, min(args.steps, 10))
+    for _ in range(bd_steps):
+        pb.run_arrays(raise_on_error=True)
+    kt_all = pb.kernel_times(reset=True)
+    phases = pb.phase_times()
+    pb.close()
+    breakdown = {k: round(v[0] / bd_steps, 4) for k, v in kt_all.items()}
+    dom = max(("bp_persistent", "bp_sweep", "regauge", "clusters", "combine"), key=lambda k: kt_all[k][0])
+    if dom == "bp_sweep" and kt_all["bp_persistent"][0] > 0:
+        dom = "bp_persistent"
+    timed_kernels = list(bp_kernels) if dom in bp_kernels else [dom]
+
+    # Timed region: HIP events only around the dominant kernel(s) on the
+    # library's stream (events around every launch would add gaps).
+    batch = ctx.batch(nets, K=args.K, precision=args.precision,
+                      profile=False if args.no_events else timed_kernels)
+    print(f"bench: prepared batches in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):
         batch.run_arrays(raise_on_error=True)
@@ -231,29 +291,26 @@ def main():
     nets_per_s = n_nets / (ms_step * 1e-3)
     print(f"bench: {ms_step:.3f} ms/step, {nets_per_s:.1f} networks/s", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel (by device time)
-    slice_bytes = {"fp64": 8, "fp32": 4, "bf16": 2}[args.precision]
+    # roofline of the dominant kernel
     sweeps = [int(x) for x in results["bp_iters"]]
     bytes_sweep = sum(bp_bytes(n, s) for s, n in zip(sweeps, nets_in))
     bytes_regauge = sum(regauge_bytes(n, slice_bytes) for n in nets_in)
-    dom = max(("bp_persistent", "bp_sweep", "regauge", "clusters", "combine"), key=lambda k: kt[k][0])
-    per_step_ms = {k: v[0] / args.steps for k, v in kt.items()}
-    if dom in ("bp_sweep", "bp_persistent"):
+    dom_ms = sum(kt[k][0] for k in timed_kernels) / args.steps
+    dom_launches = sum(kt[k][1] for k in timed_kernels)
+    if dom in bp_kernels:
         # every BP kernel of the step together performs all network-sweeps
         alg_bytes = bytes_sweep
-        if dom == "bp_persistent":
-            per_step_ms[dom] = per_step_ms["bp_persistent"] + per_step_ms["bp_sweep"]
-            if kt["regauge"][1] == 0:
-                # no regauge launches: the persistent blocks built the gauge and slices
-                alg_bytes += bytes_regauge
+        if phases["regauge_mean"] > 0 and kt_all["regauge"][0] < 0.02 * kt_all["bp_persistent"][0]:
+            # the persistent blocks also built the gauge and slices
+            alg_bytes += bytes_regauge
     elif dom == "regauge":
         alg_bytes = bytes_regauge
     else:
         alg_bytes = None
     achieved = None
-    if alg_bytes is not None and kt[dom][0] > 0:
+    if alg_bytes is not None and dom_ms > 0:
         # bytes per launch / average launch duration == bytes per step / time per step
-        achieved = alg_bytes / (per_step_ms[dom] * 1e-3) / 1e9
+        achieved = alg_bytes / (dom_ms * 1e-3) / 1e9
     roofline = {
         "kernel": dom,
         "bound": "hbm",
@@ -261,9 +318,9 @@ def main():
         "peak": HBM_PEAK_GBS,
         "unit": "GB/s",
         "frac": round(achieved / HBM_PEAK_GBS, 4) if achieved else None,
-        "traffic": None,
-        "launches_per_step": kt[dom][1] / args.steps,
-        "avg_launch_us": round(kt[dom][0] / max(1, kt[dom][1]) * 1e3, 2),
+        "traffic": measured_traffic(dom),
+        "launches_per_step": dom_launches / args.steps,
+        "avg_launch_us": round(dom_ms * args.steps / max(1, dom_launches) * 1e3, 2),
         "alg_bytes_per_step": alg_bytes,
     }
 
@@ -291,7 +348,8 @@ def main():
         "terms_per_s": round(terms / (ms_step * 1e-3), 1),
         "terms_per_step": terms,
         "bp_sweeps_mean": float(np.mean(sweeps)),
-        "kernel_ms_per_step": {k: round(v, 4) for k, v in per_step_ms.items()},
+        "kernel_ms_per_step_breakdown_pass": breakdown,
+        "persistent_block_phases_us": {k: round(v, 1) for k, v in phases.items()},
         "roofline": roofline,
     }
 

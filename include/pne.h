@@ -55,6 +55,11 @@ typedef enum {
 #define PNE_FLAG_NO_PERSISTENT 2u /* sweep every network launch by launch (no persistent BP kernel) */
 #define PNE_FLAG_BP_JACOBI 4u /* persistent BP: Jacobi sweeps even on bipartite networks (see below) */
 #define PNE_FLAG_SEPARATE_REGAUGE 8u /* gauge + slices in their own launch, not in the persistent BP block */
+#define PNE_FLAG_GRAPH 16u /* capture a batch's launch sequence (and result copies) into a HIP graph on its
+                              first launch and replay it; applies when every network's BP runs in the
+                              persistent kernel, profiling is off and the stream is not the null stream */
+#define PNE_FLAG_AUTOTUNE 32u /* pne_batch_create: pick PNE_FLAG_GRAPH / PNE_FLAG_SEPARATE_REGAUGE by
+                                 measurement (pne_autotune), cached per batch signature in the context */
 
 /* BP schedule.  Jacobi: every sweep updates every message from the previous
  * sweep's messages.  On a bipartite network (two site colours, every bond
@@ -96,8 +101,9 @@ typedef struct {
                              message change of a sweep is <= bp_tol (1e-13)      */
     int32_t bp_max_iter;  /* sweep cap (500)                                     */
     int32_t bp_check_every; /* sweeps between host convergence checks (0: auto) */
-    uint32_t flags;       /* reserved, 0                                         */
-    int32_t reserved;
+    uint32_t flags;       /* PNE_FLAG_* bits (0: defaults)                       */
+    int32_t profile_kernels; /* with PNE_FLAG_PROFILE: bit k times kernel index k of
+                                pne_batch_kernel_times only; 0 times every kernel  */
 } pne_options;
 
 /* One network's result.  Closed network: Z = sign * exp(log_abs).  Open
@@ -171,6 +177,19 @@ pne_status pne_contract_batch(pne_ctx *ctx, pne_network *const *nets, int32_t n,
  * bond ids ascending, clusters in the library's order). */
 pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64_t *n_clusters,
                                   int64_t *n_entries, int32_t *sizes, int32_t *bonds);
+
+/* Autotune: for the batch these networks and options would form, time the
+ * execution variants (gauge + slices inside the persistent BP block or in
+ * their own launch; eager launches or graph replay), `trials` runs each after
+ * one warm-up run, and return in *best the options with the fastest variant's
+ * flags.  The choice is cached in the context per batch signature (multiset
+ * of lattices, K, precision, BP flags): later calls and batches created with
+ * PNE_FLAG_AUTOTUNE reuse it without running anything.  The variants agree
+ * to rounding (the two regauge forms order their sums differently; graph
+ * replay is bitwise the eager sequence).  The runs use the context stream
+ * and block. */
+pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt, int32_t trials,
+                        pne_options *best);
 
 /* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
  * measured with HIP events recorded on the context stream around each launch.

@@ -2,6 +2,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -34,6 +35,7 @@ struct pne_ctx {
     double wall_khz = 100000.0;  // device wall clock rate (ticks per ms)
     void *staging = nullptr;     // pinned upload staging, reused by every batch creation
     size_t staging_bytes = 0;
+    std::map<uint64_t, uint32_t> tuned;  // batch signature -> chosen flags (PNE_FLAG_AUTOTUNE)
 };
 
 struct pne_network {
@@ -58,6 +60,9 @@ struct pne_batch {
     NetState *h_state_pinned = nullptr;  // pinned copy of the per-network state
     NetResult *h_results_pinned = nullptr;  // pinned copy of the per-network results
     void *h_pinned = nullptr;               // the one pinned block holding both
+    hipGraph_t graph = nullptr;             // captured launch sequence (PNE_FLAG_GRAPH)
+    hipGraphExec_t graph_exec = nullptr;
+    bool copies_enqueued = false;           // result copies already part of the launch
     int first_chunk = 4;                 // sweeps before the first convergence check
     bool launched = false;
     bool waited = false;
@@ -181,6 +186,29 @@ pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
     return PNE_OK;
 }
 
+hipError_t enqueue_result_copies(pne_batch *b) {
+    const int n = (int)b->nets.size();
+    hipError_t e = hipMemcpyAsync(b->h_results_pinned, b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
+                                  b->stream);
+    if (e != hipSuccess) return e;
+    return hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost, b->stream);
+}
+
+// The launch sequence of a batch without per-launch BP networks, followed by
+// the result copies (what a graph capture records).
+hipError_t enqueue_all(pne_batch *b) {
+    const DeviceBatch &db = b->db;
+    hipStream_t s = b->stream;
+    hipError_t e;
+    if ((e = launch_init(db, s)) != hipSuccess) return e;
+    if ((e = launch_fused(db, b->opt.bp_tol, b->opt.bp_max_iter, s)) != hipSuccess) return e;
+    if ((e = launch_close(db, 0, b->opt.bp_tol, s)) != hipSuccess) return e;
+    if ((e = launch_regauge(db, s)) != hipSuccess) return e;
+    if ((e = launch_clusters(db, s)) != hipSuccess) return e;
+    if ((e = launch_combine(db, s)) != hipSuccess) return e;
+    return enqueue_result_copies(b);
+}
+
 hipEvent_t take_event(pne_batch *b) {
     if (!b->ev_pool.empty()) {
         hipEvent_t e = b->ev_pool.back();
@@ -195,7 +223,8 @@ hipEvent_t take_event(pne_batch *b) {
 // Launch `fn` on the batch stream, bracketed by events when profiling.
 template <class F>
 hipError_t timed(pne_batch *b, int kid, F &&fn) {
-    const bool prof = (b->opt.flags & PNE_FLAG_PROFILE) != 0;
+    const bool prof = (b->opt.flags & PNE_FLAG_PROFILE) != 0 &&
+                      (b->opt.profile_kernels == 0 || ((b->opt.profile_kernels >> kid) & 1));
     hipStream_t s = b->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (prof) {
@@ -236,6 +265,10 @@ void free_batch(pne_batch *b) {
     b->ev_pool.clear();
     for (void *p : b->allocs) (void)hipFree(p);
     b->allocs.clear();
+    if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
+    b->graph_exec = nullptr;
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->graph = nullptr;
     if (b->h_pinned) (void)hipHostFree(b->h_pinned);
     b->h_pinned = nullptr;
     b->h_state_pinned = nullptr;
@@ -386,7 +419,72 @@ pne_status pne_network_destroy(pne_network *net) {
 
 pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
                             pne_batch **out) {
-    return ctx ? pne::batch_create_on(ctx, nets, n, opt, ctx->stream, out) : PNE_ERR_INVALID_ARG;
+    if (!ctx || !opt) return PNE_ERR_INVALID_ARG;
+    if (opt->flags & PNE_FLAG_AUTOTUNE) {
+        pne_options tuned;
+        pne_status st = pne_autotune(ctx, nets, n, opt, 3, &tuned);
+        if (st != PNE_OK) return st;
+        return pne::batch_create_on(ctx, nets, n, &tuned, ctx->stream, out);
+    }
+    return pne::batch_create_on(ctx, nets, n, opt, ctx->stream, out);
+}
+
+// Signature of a batch for the tuning cache: the multiset of network
+// geometries, K, the precision and the flags that change results.
+static uint64_t batch_signature(pne_network *const *nets, int32_t n, const pne_options *opt) {
+    std::vector<uint64_t> h(n);
+    for (int i = 0; i < n; ++i) h[i] = nets[i]->geo->hash;
+    std::sort(h.begin(), h.end());
+    uint64_t x = 0x9e3779b97f4a7c15ull ^ (uint64_t)n;
+    auto mix = [&](uint64_t v) {
+        x ^= v + 0x9e3779b97f4a7c15ull + (x << 6) + (x >> 2);
+    };
+    for (uint64_t v : h) mix(v);
+    mix((uint64_t)opt->max_excited);
+    mix((uint64_t)opt->precision);
+    mix((uint64_t)(opt->flags & (PNE_FLAG_NO_PERSISTENT | PNE_FLAG_BP_JACOBI)));
+    return x;
+}
+
+pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt, int32_t trials,
+                        pne_options *best) {
+    if (!ctx || !nets || n <= 0 || !opt || !best) return fail(ctx, PNE_ERR_INVALID_ARG, "bad autotune arguments");
+    const uint32_t keep = opt->flags & ~(PNE_FLAG_AUTOTUNE | PNE_FLAG_GRAPH | PNE_FLAG_SEPARATE_REGAUGE);
+    const uint64_t sig = batch_signature(nets, n, opt);
+    *best = *opt;
+    auto it = ctx->tuned.find(sig);
+    if (it != ctx->tuned.end()) {
+        best->flags = keep | it->second;
+        return PNE_OK;
+    }
+    if (trials < 1) trials = 1;
+    const uint32_t cands[4] = {0u, PNE_FLAG_SEPARATE_REGAUGE, PNE_FLAG_GRAPH,
+                               PNE_FLAG_GRAPH | PNE_FLAG_SEPARATE_REGAUGE};
+    double best_ms = 1e300;
+    uint32_t best_flags = 0;
+    for (uint32_t c : cands) {
+        pne_options o = *opt;
+        o.flags = (keep & ~PNE_FLAG_PROFILE) | c;
+        pne_batch *b = nullptr;
+        pne_status st = pne::batch_create_on(ctx, nets, n, &o, ctx->stream, &b);
+        if (st != PNE_OK) return st;
+        double ms = 1e300;
+        for (int t = 0; t <= trials && st >= 0; ++t) {  // the first run warms up
+            const auto t0 = std::chrono::steady_clock::now();
+            st = pne_batch_run(b, nullptr);
+            const double dt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+            if (t > 0) ms = std::min(ms, dt);
+        }
+        pne_batch_destroy(b);
+        if (st < 0) return st;
+        if (ms < best_ms) {
+            best_ms = ms;
+            best_flags = c;
+        }
+    }
+    ctx->tuned[sig] = best_flags;
+    best->flags = keep | best_flags;
+    return PNE_OK;
 }
 
 }  // extern "C"
@@ -921,6 +1019,29 @@ pne_status pne_batch_launch(pne_batch *b) {
     pne_ctx *ctx = b->ctx;
     hipStream_t s = b->stream;
     const DeviceBatch &db = b->db;
+    // Graph replay: a batch whose BP runs entirely in persistent blocks has
+    // no host decision inside a run, so its whole sequence (kernels and the
+    // result copies) is captured once and replayed.
+    if ((b->opt.flags & PNE_FLAG_GRAPH) && !(b->opt.flags & PNE_FLAG_PROFILE) && db.n_tiles == 0 && s != nullptr) {
+        if (!b->graph_exec) {
+            HIP_TRY(ctx, hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+            hipError_t e = enqueue_all(b);
+            hipGraph_t g = nullptr;
+            hipError_t e2 = hipStreamEndCapture(s, &g);
+            if (e != hipSuccess || e2 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return hip_fail(ctx, e != hipSuccess ? e : e2, "graph capture");
+            }
+            b->graph = g;
+            HIP_TRY(ctx, hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
+        }
+        HIP_TRY(ctx, hipGraphLaunch(b->graph_exec, s));
+        b->launched = true;
+        b->waited = false;
+        b->copies_enqueued = true;
+        return PNE_OK;
+    }
+    b->copies_enqueued = false;
     HIP_TRY(ctx, timed(b, KID_INIT, [&](hipStream_t st) { return launch_init(db, st); }));
     const int max_iter = b->opt.bp_max_iter;
     const double tol = b->opt.bp_tol;
@@ -967,10 +1088,7 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
     if (!b || !b->launched) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "batch not launched");
     pne_ctx *ctx = b->ctx;
     const int n = (int)b->nets.size();
-    HIP_TRY(ctx, hipMemcpyAsync(b->h_results_pinned, b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
-                                b->stream));
-    HIP_TRY(ctx, hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost,
-                                b->stream));
+    if (!b->copies_enqueued) HIP_TRY(ctx, enqueue_result_copies(b));
     HIP_TRY(ctx, hipStreamSynchronize(b->stream));
     b->h_state.assign(b->h_state_pinned, b->h_state_pinned + n);
     collect_times(b);

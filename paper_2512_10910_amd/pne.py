@@ -54,7 +54,7 @@ class Options(ctypes.Structure):
         ("bp_max_iter", ctypes.c_int32),
         ("bp_check_every", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
-        ("reserved", ctypes.c_int32),
+        ("profile_kernels", ctypes.c_int32),
     ]
 
 
@@ -139,6 +139,8 @@ _PROTOS = {
                                               _i32p, _i32p]),
     "pne_batch_messages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64]),
     "pne_batch_phase_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32]),
+    "pne_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                    ctypes.POINTER(Options), ctypes.c_int32, ctypes.POINTER(Options)]),
     "pne_server_options_default": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "pne_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
                                          ctypes.POINTER(ctypes.c_void_p)]),
@@ -275,10 +277,13 @@ PNE_FLAG_PROFILE = 1
 PNE_FLAG_NO_PERSISTENT = 2
 PNE_FLAG_BP_JACOBI = 4
 PNE_FLAG_SEPARATE_REGAUGE = 8
+PNE_FLAG_GRAPH = 16
+PNE_FLAG_AUTOTUNE = 32
 
 
 def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
-             fused_regauge=True):
+             fused_regauge=True, graph=False, autotune=False):
+    """profile: False, True (every kernel) or a list of KERNEL_NAMES to time."""
     lib = load_library()
     o = Options()
     lib.pne_options_default(ctypes.byref(o))
@@ -287,8 +292,11 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.bp_tol = float(tol)
     o.bp_max_iter = int(max_iter)
     o.bp_check_every = int(check_every)
+    if profile and not isinstance(profile, bool):
+        o.profile_kernels = sum(1 << KERNEL_NAMES.index(k) for k in profile)
     o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT) | \
-        (PNE_FLAG_BP_JACOBI if jacobi else 0) | (0 if fused_regauge else PNE_FLAG_SEPARATE_REGAUGE)
+        (PNE_FLAG_BP_JACOBI if jacobi else 0) | (0 if fused_regauge else PNE_FLAG_SEPARATE_REGAUGE) | \
+        (PNE_FLAG_GRAPH if graph else 0) | (PNE_FLAG_AUTOTUNE if autotune else 0)
     return o
 
 
@@ -323,12 +331,25 @@ class Context:
         return Network(self, obj, on_device)
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
-              profile=False, persistent=True, jacobi=False, fused_regauge=True) -> "Batch":
+              profile=False, persistent=True, jacobi=False, fused_regauge=True, graph=False,
+              autotune=False) -> "Batch":
         """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
         in the persistent kernel even on bipartite networks; fused_regauge=
-        False: gauge + slices in their own launch."""
+        False: gauge + slices in their own launch; graph=True: replay a
+        captured HIP graph; autotune=True: pick the variant by measurement
+        (cached per batch signature in the context)."""
         return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi,
-                     fused_regauge)
+                     fused_regauge, graph, autotune)
+
+    def autotune(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, trials=3) -> dict:
+        """Time the execution variants for this batch; returns the chosen flags."""
+        o = _options(K, precision, tol, max_iter, 0)
+        best = Options()
+        arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+        _check(self.lib, self.lib.pne_autotune(self.handle, arr, len(nets), ctypes.byref(o), int(trials),
+                                               ctypes.byref(best)), self.handle)
+        return {"graph": bool(best.flags & PNE_FLAG_GRAPH),
+                "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags)}
 
     def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
         b = self.batch([net], K, precision, tol, max_iter)
@@ -381,10 +402,11 @@ class Batch:
     """Prepared batch: plans and device tables built once, run many times."""
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
-                 persistent=True, jacobi=False, fused_regauge=True):
+                 persistent=True, jacobi=False, fused_regauge=True, graph=False, autotune=False):
         self.ctx = ctx
         self.nets = list(nets)
-        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge)
+        self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge,
+                            graph, autotune)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),

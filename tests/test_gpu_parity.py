@@ -380,3 +380,41 @@ def test_config5_open_32x32_reduced(ctx, precision):
     # the loop corrections are ~1e-3 of the output here, so the bound on
     # eps2 is a few roundoffs times that fraction
     assert err <= {"fp32": 1e-8, "bf16": 1e-5}[precision], f"eps2={err:.3e}"
+
+
+def test_graph_replays_equal_eager(ctx):
+    """Graph replay of the whole launch sequence gives the eager results on
+    every replay, with eager work in between; a batch with a network that
+    needs per-launch sweeps falls back to eager launches under the flag."""
+    nets = [ctx.network(P.random_2d(6, 6, 3, "uniform01", seed=70 + i)) for i in range(6)]
+    eager = ctx.batch(nets, K=6, precision="fp32")
+    graph = ctx.batch(nets, K=6, precision="fp32", graph=True)
+    ref = eager.run_arrays()
+    for _ in range(4):
+        g = graph.run_arrays()
+        for f in ("log_abs", "sign", "bp_iters", "status"):
+            np.testing.assert_array_equal(g[f], ref[f])
+        e = eager.run_arrays()
+        np.testing.assert_array_equal(e["log_abs"], ref["log_abs"])
+    mixed = nets[:2] + [ctx.network(P.random_2d(4, 4, 3, "uniform01", seed=32, open_sites={5: 2, 6: 2}))]
+    a = ctx.batch(mixed, K=6).run()
+    bgr = ctx.batch(mixed, K=6, graph=True)
+    for _ in range(2):
+        b = bgr.run()
+        for x, y in zip(a, b):
+            assert x.log_abs == y.log_abs
+        np.testing.assert_array_equal(a[2].open_values, b[2].open_values)
+
+
+def test_autotune_picks_a_variant_and_keeps_results(ctx):
+    nets = [ctx.network(P.random_2d(8, 8, 4, "uniform01", seed=80 + i)) for i in range(8)]
+    choice = ctx.autotune(nets, K=6, precision="fp64", trials=2)
+    assert set(choice) == {"graph", "fused_regauge", "flags"}
+    again = ctx.autotune(nets, K=6, precision="fp64", trials=2)  # cached
+    assert again == choice
+    tuned = ctx.batch(nets, K=6, precision="fp64", autotune=True).run_arrays()
+    plain = ctx.batch(nets, K=6, precision="fp64").run_arrays()
+    assert np.max(np.abs(tuned["log_abs"] - plain["log_abs"])) < 1e-12
+    for i, n in enumerate([P.random_2d(8, 8, 4, "uniform01", seed=80 + i) for i in range(2)]):
+        ref = O.pne_contract(n, 6)
+        assert abs(tuned["log_abs"][i] - ref.log_abs) < 1e-10
