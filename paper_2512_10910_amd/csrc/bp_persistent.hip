@@ -545,20 +545,33 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
                     v[k][q0 + kk * stride] = v[k][q0 + kk * stride] - t * g[D + kk] * wu - g[2 * D + kk] * w0;
             }
         }
-        // lane legs: leg R-1 on the low field, leg R-2 on the high field
+        // lane legs (leg R-1 on the low field, leg R-2 on the high field),
+        // one register value at a time, each stored as soon as it is final;
+        // value 0 carries the vacuum factor T'[0,...,0] in the segment's
+        // first lane
+        double g0m[T], gum[T], cum[T], cfm[T];
+        bool zero_digit[T];
 #pragma unroll
         for (int m = 0; m < T; ++m) {
             const double *g = Gs + (R - 1 - m) * GR;
             const int d = m == 0 ? dlo : dhi;
             const bool dv = d < D;
             const int dd = dv ? d : 0;
-            const double g0 = dv ? g[dd] : 0.0;
-            const double gu = dv ? g[D + dd] : 0.0;
-            const double cu = dv ? g[3 * D] * g[D + dd] : 0.0;
-            const double cf = dv ? g[2 * D + dd] : 0.0;
+            g0m[m] = dv ? g[dd] : 0.0;
+            gum[m] = dv ? g[D + dd] : 0.0;
+            cum[m] = dv ? g[3 * D] * g[D + dd] : 0.0;
+            cfm[m] = dv ? g[2 * D + dd] : 0.0;
+            zero_digit[m] = d == 0;
+        }
+        const int64_t so = reinterpret_cast<const int64_t *>(p_lds + L.soff)[ls[k]];
+        double z = 0.0, iz = 0.0;
+        bool ok = false;
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                double w0 = v[k][q] * g0, wu = v[k][q] * gu;
+        for (int q = 0; q < NL; ++q) {
+            double x = v[k][q];
+#pragma unroll
+            for (int m = 0; m < T; ++m) {
+                double w0 = x * g0m[m], wu = x * gum[m];
                 if (m == 0) {
                     w0 = sum_low<P>(w0);
                     wu = sum_low<P>(wu);
@@ -566,17 +579,14 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
                     w0 = sum_high<P>(w0);
                     wu = sum_high<P>(wu);
                 }
-                v[k][q] = d == 0 ? w0 : v[k][q] - cu * wu - cf * w0;
+                x = zero_digit[m] ? w0 : x - cum[m] * wu - cfm[m] * w0;
             }
-        }
-        // vacuum factor: element 0 in the segment's first lane
-        const double z = __shfl(v[k][0], slot * LS, 64);
-        const bool ok = (fabs(z) > 0.0) && isfinite(z);
-        if (act[k]) {
-            const int64_t so = reinterpret_cast<const int64_t *>(p_lds + L.soff)[ls[k]];
-            const double iz = ok ? 1.0 / z : 0.0;
-#pragma unroll
-            for (int q = 0; q < NL; ++q) dev::SliceIO<S>::store(slices, so + q * DT + toff, v[k][q] * iz);
+            if (q == 0) {
+                z = __shfl(x, slot * LS, 64);
+                ok = (fabs(z) > 0.0) && isfinite(z);
+                iz = ok ? 1.0 / z : 0.0;
+            }
+            if (act[k]) dev::SliceIO<S>::store(slices, so + q * DT + toff, x * iz);
         }
         if (tb == 0 && j < cnt) {
             site_log[site_base + ls[k]] = ok ? log(fabs(z)) : 0.0;
