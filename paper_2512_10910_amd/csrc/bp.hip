@@ -27,8 +27,11 @@ __device__ inline double wave_max(double v) {
 // FP32: (a + 0.5) / b stays within 0.5/b of the true quotient's floor + 0.5.
 __device__ inline int fdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
-__global__ void k_init(const SiteRec *__restrict__ sites, int n_sites, double *__restrict__ msg0,
-                       NetState *__restrict__ st, int n_nets) {
+// Per-network state reset, and uniform initial messages 1/sqrt(d) for the
+// sites listed in init_sites (networks swept launch by launch; a persistent
+// block initialises its network's messages in LDS itself).
+__global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict__ init_sites, int n_sites,
+                       double *__restrict__ msg0, NetState *__restrict__ st, int n_nets) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_nets) {
         NetState s;
@@ -44,7 +47,7 @@ __global__ void k_init(const SiteRec *__restrict__ sites, int n_sites, double *_
         st[i] = s;
     }
     if (i < n_sites) {
-        const SiteRec &r = sites[i];
+        const SiteRec &r = sites[init_sites[i]];
         for (int l = 0; l < r.rank; ++l) {
             double v = 1.0 / sqrt((double)r.dim[l]);
             double *m = msg0 + r.msg_off + r.moff[l];
@@ -582,9 +585,9 @@ size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int ma
 }
 
 hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
-    int n = b.n_sites > b.n_nets ? b.n_sites : b.n_nets;
-    hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, b.sites, b.n_sites, b.msg0, b.state,
-                       b.n_nets);
+    int n = b.n_init_sites > b.n_nets ? b.n_init_sites : b.n_nets;
+    hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, b.sites, b.init_sites, b.n_init_sites,
+                       b.msg0, b.state, b.n_nets);
     return hipGetLastError();
 }
 

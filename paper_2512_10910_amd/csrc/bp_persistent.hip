@@ -622,9 +622,14 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     L.soff = L.vside + (ns_ + 1) / 2;
     L.scr = L.soff + ns_;
     const int scr = L.scr + wave * fn.scratch;
-    for (int e = tid; e < fn.msg_size; e += kPThreads) p_lds[e] = msg0[fn.msg_base + e];
+    // uniform initial messages 1/sqrt(d): each site fills its incoming slots
     for (int s = tid; s < ns_; s += kPThreads) {
         const SiteRec &r = sites[fn.site_base + s];
+        for (int l = 0; l < r.rank; ++l) {
+            const double v = 1.0 / sqrt((double)r.dim[l]);
+            double *m = p_lds + (r.msg_off - fn.msg_base) + r.moff[l];
+            for (int k = 0; k < r.dim[l]; ++k) m[k] = v;
+        }
         reinterpret_cast<const double **>(p_lds + L.tptr)[s] = r.t;
         reinterpret_cast<int *>(p_lds + L.moff)[s] = r.msg_off - fn.msg_base;
         for (int l = 0; l < kMaxRank; ++l)

@@ -22,6 +22,8 @@ struct DeviceBatch {
     size_t fused_lds = 0;
     int fused_regauge = 1;              // persistent blocks also build gauge + slices
     const int *tile_sites = nullptr;
+    const int *init_sites = nullptr;    // sites whose messages k_init resets (non-persistent networks)
+    int n_init_sites = 0;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
     NetState *state = nullptr;
     int n_nets = 0;

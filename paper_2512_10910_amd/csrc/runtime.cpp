@@ -202,7 +202,6 @@ hipError_t enqueue_all(pne_batch *b) {
     hipError_t e;
     if ((e = launch_init(db, s)) != hipSuccess) return e;
     if ((e = launch_fused(db, b->opt.bp_tol, b->opt.bp_max_iter, s)) != hipSuccess) return e;
-    if ((e = launch_close(db, 0, b->opt.bp_tol, s)) != hipSuccess) return e;
     if ((e = launch_regauge(db, s)) != hipSuccess) return e;
     if ((e = launch_clusters(db, s)) != hipSuccess) return e;
     if ((e = launch_combine(db, s)) != hipSuccess) return e;
@@ -598,6 +597,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
     size_t bp_lds = 0, fused_lds = 0;
     std::vector<char> net_rg_inline(n, 0);  // gauge + slices built by the persistent block
+    std::vector<char> net_fused(n, 0);      // BP in a persistent block
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
         int base = b->site_base[i];
@@ -743,6 +743,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 }
             f.n_groups = (int)fgroups.size() - f.group_begin;
             fused.push_back(f);
+            net_fused[i] = 1;
             fused_lds = std::max(fused_lds, pneed * 8);
         } else {
             loop_tiles.insert(loop_tiles.end(), tiles.begin() + tile_begin, tiles.end());
@@ -953,6 +954,13 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_rg_tiles = (int)rg_tiles.size();
     db.n_rg_sites = (int)rg_sites.size();
     UP(tile_sites, tile_sites);
+    // k_init resets the messages of networks swept launch by launch only
+    std::vector<int> init_sites;
+    for (int i = 0; i < n; ++i)
+        if (!net_fused[i])
+            for (int s2 = 0; s2 < nets[i]->geo->n_sites; ++s2) init_sites.push_back(b->site_base[i] + s2);
+    UP(init_sites, init_sites);
+    db.n_init_sites = (int)init_sites.size();
     UP(classes, classes);
     UP(steps, steps);
     UP(cblocks, cblocks);
@@ -1074,8 +1082,10 @@ pne_status pne_batch_launch(pne_batch *b) {
         if (all_done) break;
         if (b->opt.bp_check_every <= 0) chunk = std::min(chunk * 2, 16);
     }
-    if (sweep == 0) sweep = 1;  // only persistent networks: close is a no-op for them
-    HIP_TRY(ctx, timed(b, KID_CLOSE, [&](hipStream_t st) { return launch_close(db, sweep - 1, tol, st); }));
+    // the close kernel finishes per-launch networks only (persistent blocks
+    // record their own final state)
+    if (db.n_tiles > 0)
+        HIP_TRY(ctx, timed(b, KID_CLOSE, [&](hipStream_t st) { return launch_close(db, sweep - 1, tol, st); }));
     HIP_TRY(ctx, timed(b, KID_REGAUGE, [&](hipStream_t st) { return launch_regauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_CLUSTERS, [&](hipStream_t st) { return launch_clusters(db, st); }));
     HIP_TRY(ctx, timed(b, KID_COMBINE, [&](hipStream_t st) { return launch_combine(db, st); }));
