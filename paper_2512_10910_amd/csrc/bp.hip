@@ -253,11 +253,11 @@ __device__ void sweep_tile(const BpTile &tl, const SiteRec *__restrict__ sites, 
             s_bad = 1;
             continue;
         }
-        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
         const int dst = s_dst[j * kMaxRank + l];
         double d1 = 0.0, d2 = 0.0;
         for (int k = 0; k < d; ++k) {
-            const double v = sg * (raw[k] / nrm);
+            const double v = raw[k] * inv;
             d1 = fmax(d1, fabs(v - old[k]));
             d2 = fmax(d2, fabs(v + old[k]));
             mout[dst + k] = v;
@@ -464,12 +464,12 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
             *bad = 1;
             continue;
         }
-        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
         const int dst = sh.dst[j * kMaxRank + l];
         double d1 = 0.0, d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double v = sg * (raw[k] / nrm);
+            const double v = raw[k] * inv;
             d1 = fmax(d1, fabs(v - oldv[k]));
             d2 = fmax(d2, fabs(v + oldv[k]));
             mout[dst + k] = v;

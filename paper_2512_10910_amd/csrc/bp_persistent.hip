@@ -192,11 +192,11 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
             *bad = 1;
             continue;
         }
-        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
         double d1 = 0.0, d2 = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double v = sg * (raw[i] / nrm);
+            const double v = raw[i] * inv;
             const double old = p_lds[mi + idst + i];
             d1 = fmax(d1, fabs(v - old));
             d2 = fmax(d2, fabs(v + old));
@@ -216,16 +216,97 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
 // (last leg) with quad permutations, the high field (second-to-last leg,
 // P = 4) with row rotations by 4 and 8, which keep the low bits.  The first
 // R-T legs index NL = D^(R-T) values per lane.
+// Every control used here is a full permutation of a row, so no lane reads
+// outside it and the DPP "old" operand is never needed.
 template <int CTRL>
 __device__ inline double dpp_f64(double v) {
-    const int lo = __builtin_amdgcn_update_dpp(0, __double2loint(v), CTRL, 0xF, 0xF, false);
-    const int hi = __builtin_amdgcn_update_dpp(0, __double2hiint(v), CTRL, 0xF, 0xF, false);
+    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), CTRL, 0xF, 0xF, true);
+    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), CTRL, 0xF, 0xF, true);
     return __hiloint2double(hi, lo);
 }
-constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]
-constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]
+constexpr int kDppXor1 = 0xB1;    // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int kDppXor2 = 0x4E;    // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int kDppXor3 = 0x1B;    // quad_perm [3,2,1,0]: lane ^ 3
 constexpr int kDppRor4 = 0x124;   // row_ror:4
 constexpr int kDppRor8 = 0x128;   // row_ror:8
+constexpr int kDppMirror = 0x140;      // row_mirror: lane ^ 15 within the row
+constexpr int kDppHalfMirror = 0x141;  // row_half_mirror: lane ^ 7 within each half row
+
+// Partner lane (lane ^ MASK inside a 16-lane row) for the masks 15, 7, 3, 1,
+// which span the four lane bits of a row.
+template <int MASK>
+__device__ inline double dpp_xor(double v) {
+    if constexpr (MASK == 15) return dpp_f64<kDppMirror>(v);
+    else if constexpr (MASK == 7) return dpp_f64<kDppHalfMirror>(v);
+    else if constexpr (MASK == 3) return dpp_f64<kDppXor3>(v);
+    else return dpp_f64<kDppXor1>(v);
+}
+
+template <int S, int STAGE>
+__device__ inline double seg_partner(double x) {
+    if constexpr (S == 4) return STAGE == 0 ? dpp_xor<15>(x) : (STAGE == 1 ? dpp_xor<7>(x) : (STAGE == 2 ? dpp_xor<3>(x) : dpp_xor<1>(x)));
+    else if constexpr (S == 2) return STAGE == 0 ? dpp_xor<3>(x) : dpp_xor<1>(x);
+    else return dpp_xor<1>(x);
+}
+
+// Stages STAGE.. of a segment reduction (see seg_reduce_stream) on the first
+// NC entries of v; compile-time sizes keep every index static.
+template <int S, int STAGE, int NC, int N>
+__device__ inline void seg_stages(double (&v)[N], int tb, int &elem, bool &writer) {
+    if constexpr (STAGE < S) {
+        const bool hi = (tb >> (S - 1 - STAGE)) & 1;
+        if constexpr (NC > 1) {
+            constexpr int h = NC / 2;
+#pragma unroll
+            for (int k = 0; k < h; ++k) {
+                const double send = hi ? v[k] : v[k + h];
+                const double keep = hi ? v[k + h] : v[k];
+                v[k] = keep + seg_partner<S, STAGE>(send);
+            }
+            elem = elem * 2 + (hi ? 1 : 0);
+            seg_stages<S, STAGE + 1, h, N>(v, tb, elem, writer);
+        } else {
+            v[0] += seg_partner<S, STAGE>(v[0]);
+            writer = writer && !hi;
+            seg_stages<S, STAGE + 1, 1, N>(v, tb, elem, writer);
+        }
+    }
+}
+
+// Sum N per-lane values (N a power of two) over a segment of LS lanes (2, 4
+// or 16, inside one DPP row) by recursive halving.  At stage s a lane and its
+// partner lane ^ mask (masks 15/7/3/1 from the segment's top bit down) keep
+// complementary halves of their vectors and add the partner's copy of the
+// half they keep; once one value is left, later stages add it to the
+// partner's.  part(e) produces element e's per-lane value on the fly and the
+// first stage consumes the pairs (e, e + N/2) as they are made, so at most
+// N/2 values stay live.  Afterwards v[0..m-1] (m = N / LS when N > LS,
+// else 1) hold the segment totals of elements elem*m .. elem*m+m-1, the same
+// in every lane sharing the kept bits; `writer` marks one of them.
+template <int LS, int N, typename Part>
+__device__ inline void seg_reduce_stream(const Part &part, double (&v)[N], int tb, int &elem, bool &writer) {
+    constexpr int S = LS == 16 ? 4 : (LS == 4 ? 2 : 1);
+    elem = 0;
+    writer = true;
+    const bool hi = (tb >> (S - 1)) & 1;
+    if constexpr (N > 1) {
+        constexpr int h = N / 2;
+#pragma unroll
+        for (int k = 0; k < h; ++k) {
+            const double a = part(k), b = part(k + h);
+            const double send = hi ? a : b;
+            const double keep = hi ? b : a;
+            v[k] = keep + seg_partner<S, 0>(send);
+        }
+        elem = hi ? 1 : 0;
+        seg_stages<S, 1, h, N>(v, tb, elem, writer);
+    } else {
+        v[0] = part(0);
+        v[0] += seg_partner<S, 0>(v[0]);
+        writer = !hi;
+        seg_stages<S, 1, 1, N>(v, tb, elem, writer);
+    }
+}
 
 template <int P>
 __device__ inline double sum_low(double v) {  // over the last leg's digit
@@ -321,27 +402,37 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
             double pm = sum_low<P>(A * mlo[k]);
             if (valid && dlo == 0) out[oslot + (R - 2) * D + dhi] = pm;
         }
-        // lead legs: summed over the whole segment
+        // lead legs: the NLEG*D outputs of a site are per-lane partial sums,
+        // reduced jointly over the segment (recursive halving)
         if (NLEG > 0) {
+            constexpr int NO = NLEG * D;
+            constexpr int NP2 = NO <= 1 ? 1 : (NO <= 2 ? 2 : (NO <= 4 ? 4 : (NO <= 8 ? 8 : 16)));
             const double qt = valid ? mlo[k] * mhi[k] : 0.0;
+            // element e = j*D + i: the lane's part of slot j's outgoing entry i
+            auto part = [&](int e) {
+                if (e >= NO) return 0.0;
+                const int j = e / D, i = e % D;
+                double sv = 0.0;
 #pragma unroll
-            for (int j = 0; j < NLEG; ++j) {
+                for (int q = 0; q < NL; ++q) {
+                    if ((q / ipw(D, NLEG - 1 - j)) % D != i) continue;
+                    double w = 1.0;
 #pragma unroll
-                for (int i = 0; i < D; ++i) {
-                    double sv = 0.0;
-#pragma unroll
-                    for (int q = 0; q < NL; ++q) {
-                        if ((q / ipw(D, NLEG - 1 - j)) % D != i) continue;
-                        double w = 1.0;
-#pragma unroll
-                        for (int j2 = 0; j2 < NLEG; ++j2)
-                            if (j2 != j) w *= ml[k][j2][(q / ipw(D, NLEG - 1 - j2)) % D];
-                        sv = fma(tv[k][q], w, sv);
-                    }
-                    sv = sum_low<P>(sv * qt);
-                    if (T == 2) sv = sum_high<P>(sv);
-                    if (tb == 0 && base_pos + k * SPW + slot < n_in_group) out[oslot + j * D + i] = sv;
+                    for (int j2 = 0; j2 < NLEG; ++j2)
+                        if (j2 != j) w *= ml[k][j2][(q / ipw(D, NLEG - 1 - j2)) % D];
+                    sv = fma(tv[k][q], w, sv);
                 }
+                return sv * qt;
+            };
+            double pv[NP2];
+            constexpr int M = NP2 > LS ? NP2 / LS : 1;  // totals per lane
+            int e;
+            bool wr;
+            seg_reduce_stream<LS, NP2>(part, pv, tb, e, wr);
+            if (wr && base_pos + k * SPW + slot < n_in_group) {
+#pragma unroll
+                for (int m = 0; m < M; ++m)
+                    if (e * M + m < NO) out[oslot + e * M + m] = pv[m];
             }
         }
     }
@@ -369,11 +460,11 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
             *bad = 1;
             continue;
         }
-        const double sg = sum < 0.0 ? -1.0 : 1.0;
+        const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
         double d1 = 0.0, d2 = 0.0;
 #pragma unroll
         for (int i = 0; i < D; ++i) {
-            const double v = sg * (raw[i] / nrm);
+            const double v = raw[i] * inv;
             const double old = p_lds[mi + idst + i];
             d1 = fmax(d1, fabs(v - old));
             d2 = fmax(d2, fabs(v + old));

