@@ -270,8 +270,8 @@ def main():
 
     # Timed region: HIP events only around the dominant kernel(s) on the
     # library's stream (events around every launch would add gaps).
-    batch = ctx.batch(nets, K=args.K, precision=args.precision,
-                      profile=False if args.no_events else timed_kernels)
+    prof = False if args.no_events else timed_kernels
+    batch = ctx.batch(nets, K=args.K, precision=args.precision, profile=prof)
     print(f"bench: prepared batches in {time.time() - t_setup:.1f}s", file=sys.stderr, flush=True)
 
     for _ in range(args.warmup):

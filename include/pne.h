@@ -155,9 +155,16 @@ pne_status pne_network_destroy(pne_network *net);
 pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n,
                             const pne_options *opt, pne_batch **out);
 /* Enqueue the whole expansion for every network of the batch on the context
- * stream (BP sweeps, gauge, slices, cluster contractions, FP64 sum). */
+ * stream (BP sweeps, gauge, slices, cluster contractions, FP64 sum), followed
+ * by the copy of its results to pinned host memory.  Up to two launches may
+ * be outstanding (INVALID_ARG beyond that): the second is enqueued behind the
+ * first and reuses the device buffers in stream order, so the host can
+ * collect one launch's results while the next runs.  A batch with networks
+ * swept launch by launch synchronises inside launch (convergence checks). */
 pne_status pne_batch_launch(pne_batch *batch);
-/* Wait for a launched batch and fill results[0..n-1]. */
+/* Wait for the oldest outstanding launch and fill results[0..n-1] (results
+ * may be NULL).  The diagnostics below describe the launch last waited for
+ * and are meaningful only when no other launch is outstanding. */
 pne_status pne_batch_wait(pne_batch *batch, pne_result *results);
 /* pne_batch_launch followed by pne_batch_wait. */
 pne_status pne_batch_run(pne_batch *batch, pne_result *results);

@@ -57,17 +57,28 @@ struct pne_batch {
     std::vector<void *> allocs;
     size_t bytes = 0;
     DeviceBatch db;
-    NetState *h_state_pinned = nullptr;  // pinned copy of the per-network state
-    NetResult *h_results_pinned = nullptr;  // pinned copy of the per-network results
-    void *h_pinned = nullptr;               // the one pinned block holding both
+    // Two pinned result slots: a batch may have two launches outstanding;
+    // launch k copies its per-network state and results into slot k % 2 and
+    // records done[k % 2]; waits take the launches in order.
+    NetState *h_state_pinned = nullptr;     // slot of the current launch / wait
+    NetResult *h_results_pinned = nullptr;
+    NetState *h_state_slot[2] = {nullptr, nullptr};
+    NetResult *h_results_slot[2] = {nullptr, nullptr};
+    void *h_pinned = nullptr;               // the one pinned block holding both slots
+    hipEvent_t done_slot[2] = {nullptr, nullptr};
+    int64_t n_launched = 0, n_waited = 0;
     hipGraph_t graph = nullptr;             // captured launch sequence (PNE_FLAG_GRAPH)
     hipGraphExec_t graph_exec = nullptr;
-    bool copies_enqueued = false;           // result copies already part of the launch
     int first_chunk = 4;                 // sweeps before the first convergence check
     bool launched = false;
     bool waited = false;
     // per-kernel HIP-event timing (PNE_FLAG_PROFILE)
-    std::vector<std::pair<int, std::pair<hipEvent_t, hipEvent_t>>> ev_used;
+    struct TimedLaunch {
+        int64_t launch;  // index of the batch launch the kernel belongs to
+        int kid;
+        hipEvent_t e0, e1;
+    };
+    std::vector<TimedLaunch> ev_used;
     std::vector<hipEvent_t> ev_pool;
     double kt_ms[KID_COUNT] = {0};
     int64_t kt_n[KID_COUNT] = {0};
@@ -194,8 +205,9 @@ hipError_t enqueue_result_copies(pne_batch *b) {
     return hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost, b->stream);
 }
 
-// The launch sequence of a batch without per-launch BP networks, followed by
-// the result copies (what a graph capture records).
+// The launch sequence of a batch without per-launch BP networks (what a
+// graph capture records; the result copies follow it outside the graph,
+// into the launch's pinned slot).
 hipError_t enqueue_all(pne_batch *b) {
     const DeviceBatch &db = b->db;
     hipStream_t s = b->stream;
@@ -204,8 +216,7 @@ hipError_t enqueue_all(pne_batch *b) {
     if ((e = launch_fused(db, b->opt.bp_tol, b->opt.bp_max_iter, s)) != hipSuccess) return e;
     if ((e = launch_regauge(db, s)) != hipSuccess) return e;
     if ((e = launch_clusters(db, s)) != hipSuccess) return e;
-    if ((e = launch_combine(db, s)) != hipSuccess) return e;
-    return enqueue_result_copies(b);
+    return launch_combine(db, s);
 }
 
 hipEvent_t take_event(pne_batch *b) {
@@ -236,34 +247,45 @@ hipError_t timed(pne_batch *b, int kid, F &&fn) {
     if (err != hipSuccess) return err;
     if (prof) {
         err = hipEventRecord(e1, s);
-        b->ev_used.push_back({kid, {e0, e1}});
+        b->ev_used.push_back({b->n_launched, kid, e0, e1});
     }
     return err;
 }
 
-void collect_times(pne_batch *b) {
+// Fold in the kernel times of launches up to `upto` (exclusive), which have
+// completed; events of a still outstanding launch stay for its own wait.
+void collect_times(pne_batch *b, int64_t upto) {
+    std::vector<pne_batch::TimedLaunch> keep;
     for (auto &u : b->ev_used) {
-        float ms = 0.f;
-        if (hipEventElapsedTime(&ms, u.second.first, u.second.second) == hipSuccess) {
-            b->kt_ms[u.first] += ms;
-            b->kt_n[u.first] += 1;
+        if (u.launch >= upto) {
+            keep.push_back(u);
+            continue;
         }
-        b->ev_pool.push_back(u.second.first);
-        b->ev_pool.push_back(u.second.second);
+        float ms = 0.f;
+        if (hipEventElapsedTime(&ms, u.e0, u.e1) == hipSuccess) {
+            b->kt_ms[u.kid] += ms;
+            b->kt_n[u.kid] += 1;
+        }
+        b->ev_pool.push_back(u.e0);
+        b->ev_pool.push_back(u.e1);
     }
-    b->ev_used.clear();
+    b->ev_used.swap(keep);
 }
 
 void free_batch(pne_batch *b) {
     for (auto &u : b->ev_used) {
-        (void)hipEventDestroy(u.second.first);
-        (void)hipEventDestroy(u.second.second);
+        (void)hipEventDestroy(u.e0);
+        (void)hipEventDestroy(u.e1);
     }
     b->ev_used.clear();
     for (hipEvent_t e : b->ev_pool) (void)hipEventDestroy(e);
     b->ev_pool.clear();
     for (void *p : b->allocs) (void)hipFree(p);
     b->allocs.clear();
+    for (hipEvent_t &e : b->done_slot) {
+        if (e) (void)hipEventDestroy(e);
+        e = nullptr;
+    }
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     b->graph_exec = nullptr;
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -1002,12 +1024,21 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     }
     // one pinned block for the per-network state and results read back by every wait
     const size_t st_bytes = align256(sizeof(NetState) * n);
-    if (hipHostMalloc(&b->h_pinned, st_bytes + sizeof(NetResult) * n, hipHostMallocDefault) != hipSuccess) {
+    const size_t slot_bytes = st_bytes + align256(sizeof(NetResult) * n);
+    if (hipHostMalloc(&b->h_pinned, 2 * slot_bytes, hipHostMallocDefault) != hipSuccess) {
         free_batch(b.get());
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
     }
-    b->h_state_pinned = (NetState *)b->h_pinned;
-    b->h_results_pinned = (NetResult *)((char *)b->h_pinned + st_bytes);
+    for (int k = 0; k < 2; ++k) {
+        b->h_state_slot[k] = (NetState *)((char *)b->h_pinned + k * slot_bytes);
+        b->h_results_slot[k] = (NetResult *)((char *)b->h_pinned + k * slot_bytes + st_bytes);
+        if (hipEventCreateWithFlags(&b->done_slot[k], hipEventDisableTiming) != hipSuccess) {
+            free_batch(b.get());
+            return fail(ctx, PNE_ERR_DEVICE, "event creation failed");
+        }
+    }
+    b->h_state_pinned = b->h_state_slot[0];
+    b->h_results_pinned = b->h_results_slot[0];
     hipError_t e = hipStreamSynchronize(b->stream);
     if (e != hipSuccess) {
         free_batch(b.get());
@@ -1027,6 +1058,10 @@ pne_status pne_batch_launch(pne_batch *b) {
     pne_ctx *ctx = b->ctx;
     hipStream_t s = b->stream;
     const DeviceBatch &db = b->db;
+    if (b->n_launched - b->n_waited >= 2) return fail(ctx, PNE_ERR_INVALID_ARG, "two launches already outstanding");
+    const int slot = (int)(b->n_launched & 1);
+    b->h_state_pinned = b->h_state_slot[slot];
+    b->h_results_pinned = b->h_results_slot[slot];
     // Graph replay: a batch whose BP runs entirely in persistent blocks has
     // no host decision inside a run, so its whole sequence (kernels and the
     // result copies) is captured once and replayed.
@@ -1044,12 +1079,13 @@ pne_status pne_batch_launch(pne_batch *b) {
             HIP_TRY(ctx, hipGraphInstantiate(&b->graph_exec, g, nullptr, nullptr, 0));
         }
         HIP_TRY(ctx, hipGraphLaunch(b->graph_exec, s));
+        HIP_TRY(ctx, enqueue_result_copies(b));
+        HIP_TRY(ctx, hipEventRecord(b->done_slot[slot], s));
+        ++b->n_launched;
         b->launched = true;
         b->waited = false;
-        b->copies_enqueued = true;
         return PNE_OK;
     }
-    b->copies_enqueued = false;
     HIP_TRY(ctx, timed(b, KID_INIT, [&](hipStream_t st) { return launch_init(db, st); }));
     const int max_iter = b->opt.bp_max_iter;
     const double tol = b->opt.bp_tol;
@@ -1089,19 +1125,28 @@ pne_status pne_batch_launch(pne_batch *b) {
     HIP_TRY(ctx, timed(b, KID_REGAUGE, [&](hipStream_t st) { return launch_regauge(db, st); }));
     HIP_TRY(ctx, timed(b, KID_CLUSTERS, [&](hipStream_t st) { return launch_clusters(db, st); }));
     HIP_TRY(ctx, timed(b, KID_COMBINE, [&](hipStream_t st) { return launch_combine(db, st); }));
+    // results and state go to pinned memory in the same stream order, so the
+    // host can enqueue further work (another batch) before waiting on this one
+    HIP_TRY(ctx, enqueue_result_copies(b));
+    HIP_TRY(ctx, hipEventRecord(b->done_slot[slot], s));
+    ++b->n_launched;
     b->launched = true;
     b->waited = false;
     return PNE_OK;
 }
 
 pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
-    if (!b || !b->launched) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "batch not launched");
+    if (!b || b->n_waited >= b->n_launched)
+        return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "batch not launched");
     pne_ctx *ctx = b->ctx;
     const int n = (int)b->nets.size();
-    if (!b->copies_enqueued) HIP_TRY(ctx, enqueue_result_copies(b));
-    HIP_TRY(ctx, hipStreamSynchronize(b->stream));
+    const int slot = (int)(b->n_waited & 1);
+    HIP_TRY(ctx, hipEventSynchronize(b->done_slot[slot]));
+    ++b->n_waited;
+    b->h_state_pinned = b->h_state_slot[slot];
+    b->h_results_pinned = b->h_results_slot[slot];
     b->h_state.assign(b->h_state_pinned, b->h_state_pinned + n);
-    collect_times(b);
+    collect_times(b, b->n_waited);
     b->waited = true;
     if (!results) return PNE_OK;
     pne_status worst = PNE_OK;

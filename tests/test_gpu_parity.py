@@ -420,3 +420,31 @@ def test_autotune_picks_a_variant_and_keeps_results(ctx):
     for i, n in enumerate([P.random_2d(8, 8, 4, "uniform01", seed=80 + i) for i in range(2)]):
         ref = O.pne_contract(n, 6)
         assert abs(tuned["log_abs"][i] - ref.log_abs) < 1e-10
+
+
+def test_two_outstanding_launches(ctx):
+    """A batch may be launched twice before waiting: each wait returns its
+    launch's results (same values), a third launch is refused."""
+    import paper_2512_10910_amd as pne
+
+    nets = [ctx.network(P.random_2d(5, 5, 3, "uniform01", seed=90 + i)) for i in range(4)]
+    b = ctx.batch(nets, K=6)
+    ref = b.run_arrays()
+    b.launch()
+    b.launch()
+    with pytest.raises(pne.PNEError):
+        b.launch()
+    r1 = b.wait_arrays()
+    r2 = b.wait_arrays()
+    np.testing.assert_array_equal(r1["log_abs"], ref["log_abs"])
+    np.testing.assert_array_equal(r2["log_abs"], ref["log_abs"])
+    with pytest.raises(pne.PNEError):
+        b.wait_arrays(raise_on_error=True)
+    # kernel events of an outstanding launch are kept for its own wait
+    pb = ctx.batch(nets, K=6, profile=True)
+    pb.launch()
+    pb.launch()
+    pb.wait_arrays()
+    assert pb.kernel_times()["combine"][1] == 1
+    pb.wait_arrays()
+    assert pb.kernel_times()["combine"][1] == 2
