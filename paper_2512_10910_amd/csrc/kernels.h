@@ -51,6 +51,8 @@ struct DeviceBatch {
     double *w = nullptr;
     // combine
     const CombineRec *crec = nullptr;
+    const int *combine_nets = nullptr;   // networks summed by the combine launch
+    int n_combine = 0;
     const GeoRec *geos = nullptr;
     const Bucket *buckets = nullptr;
     const int *pair_a = nullptr, *pair_b = nullptr;

@@ -16,6 +16,7 @@
 
 #include "kernels.h"
 #include "regauge.h"
+#include "terms.h"
 
 namespace pne {
 
@@ -156,49 +157,6 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
 __device__ inline int xcd_block(int p, int nb) {
     const int x = p & 7, q = nb >> 3, r = nb & 7;
     return x * q + min(x, r) + (p >> 3);
-}
-
-// A cycle of L sites whose cluster legs all have dimension E: the term is
-// Tr(M_0 M_1 ... M_{L-1}) with M_j[a][b] the excited block of site j's slice
-// (a on the leg towards site j-1, b towards site j+1).  One thread holds the
-// running product (E x E) in registers.
-template <int E, typename S>
-__device__ inline typename SliceIO<S>::acc loop_trace(const InstStep *__restrict__ rec, int L,
-                                                      const S *__restrict__ slices, int64_t base) {
-    using A = typename SliceIO<S>::acc;
-    A F[E][E], M[E][E];
-    InstStep r = rec[0];
-#pragma unroll
-    for (int a = 0; a < E; ++a)
-#pragma unroll
-        for (int b = 0; b < E; ++b) F[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
-    for (int j = 1; j < L; ++j) {
-        r = rec[j];
-#pragma unroll
-        for (int a = 0; a < E; ++a)
-#pragma unroll
-            for (int b = 0; b < E; ++b) M[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
-        if (j == L - 1) break;
-#pragma unroll
-        for (int a = 0; a < E; ++a) {
-            A row[E];
-#pragma unroll
-            for (int b = 0; b < E; ++b) {
-                A acc = A(0);
-#pragma unroll
-                for (int c = 0; c < E; ++c) acc += F[a][c] * M[c][b];
-                row[b] = acc;
-            }
-#pragma unroll
-            for (int b = 0; b < E; ++b) F[a][b] = row[b];
-        }
-    }
-    A tr = A(0);
-#pragma unroll
-    for (int a = 0; a < E; ++a)
-#pragma unroll
-        for (int b = 0; b < E; ++b) tr += F[a][b] * M[b][a];
-    return tr;
 }
 
 // Cluster contraction by a per-class plan: the frontier tensor F absorbs one
@@ -351,7 +309,8 @@ __device__ double block_sum(double v, double *red) {
 // the overlaps being the explicitly listed pairs of clusters that share a
 // site.  Open networks combine vacuum vectors and open-cluster tensors the
 // same way, one tensor product per configuration.
-__global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__restrict__ recs,
+__global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ combine_nets,
+                                                        const CombineRec *__restrict__ recs,
                                                         const GeoRec *__restrict__ geos,
                                                         const Bucket *__restrict__ buckets,
                                                         const int *__restrict__ pair_a, const int *__restrict__ pair_b,
@@ -359,7 +318,7 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const CombineRec *__rest
                                                         const double *__restrict__ site_log,
                                                         const int *__restrict__ site_sign, const double *__restrict__ vac,
                                                         const NetState *__restrict__ st, NetResult *__restrict__ out) {
-    const int net = blockIdx.x;
+    const int net = combine_nets[blockIdx.x];
     const CombineRec cr = recs[net];
     const GeoRec gr = geos[cr.geo];
     __shared__ double red[kCbThreads / 64];
@@ -590,8 +549,10 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
 }
 
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
-    hipLaunchKernelGGL(k_combine, dim3(b.n_nets), dim3(kCbThreads), 0, s, b.crec, b.geos, b.buckets, b.pair_a,
-                       b.pair_b, b.pair_cats, b.w, b.site_log, b.site_sign, b.vac, b.state, b.results);
+    if (!b.n_combine) return hipSuccess;
+    hipLaunchKernelGGL(k_combine, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
+                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.w, b.site_log, b.site_sign, b.vac, b.state,
+                       b.results);
     return hipGetLastError();
 }
 

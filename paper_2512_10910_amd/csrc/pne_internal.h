@@ -57,7 +57,11 @@ struct FusedNet {
     int32_t scratch;      // doubles of per-wavefront scratch
     int32_t colors;       // 2: bipartite, red-black schedule in one buffer; 1: Jacobi, two buffers
     int32_t rg_inline;    // 1: the block also builds the gauge and slices of every site
+    int32_t cl_fused;     // 1: ... and contracts its clusters and sums its terms (closed network)
+    int32_t class_begin;  // the network's plan classes (cl_fused)
+    int32_t n_classes;
     int32_t pad;
+    int64_t w_base;       // the network's first cluster weight (cl_fused)
 };
 
 // Sites of one network with all legs of dimension dc and rank `rank`.

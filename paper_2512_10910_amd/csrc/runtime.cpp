@@ -620,6 +620,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     size_t bp_lds = 0, fused_lds = 0;
     std::vector<char> net_rg_inline(n, 0);  // gauge + slices built by the persistent block
     std::vector<char> net_fused(n, 0);      // BP in a persistent block
+    std::vector<int> fused_of_net(n, -1);   // index of the network's persistent block
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
         int base = b->site_base[i];
@@ -728,6 +729,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             }
             rg_scratch = std::max(rg_scratch, bp_persistent_regauge_table(r0.dim[0], r0.rank));
         }
+        rg_scratch = std::max(rg_scratch, 32);  // the in-block term sum's LDS (8 waves x 32)
         if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2) <= fused_budget)
             pscratch = rg_scratch;
         else
@@ -764,6 +766,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                     if (fg.n_sites > 0) fgroups.push_back(fg);
                 }
             f.n_groups = (int)fgroups.size() - f.group_begin;
+            fused_of_net[i] = (int)fused.size();
             fused.push_back(f);
             net_fused[i] = 1;
             fused_lds = std::max(fused_lds, pneed * 8);
@@ -839,6 +842,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     // leg strides; a network only adds its slice and weight bases.  Blocks
     // walk the plan's networks in order, each block covering up to 256/group
     // consecutive (network, instance) pairs of one class.
+    std::vector<char> net_cl_fused(n, 0);
+    const bool cl_separate = (opt->flags & PNE_FLAG_SEPARATE_REGAUGE) != 0;
     {
         std::map<const GeoPlan *, std::vector<int>> nets_of_plan;
         std::vector<const GeoPlan *> plan_order;
@@ -848,8 +853,33 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             nets_of_plan[p].push_back(i);
         }
         for (const GeoPlan *p : plan_order) {
-            const std::vector<int> &pn = nets_of_plan[p];
-            const Geometry &g = *nets[pn[0]]->geo;
+            const std::vector<int> &pn_all = nets_of_plan[p];
+            const Geometry &g = *nets[pn_all[0]]->geo;
+            const int c0 = plan_index[p];
+            const int ncls = (int)p->classes.size();
+            // A closed network whose BP, gauge and slices run in a persistent
+            // block, and whose plan has only scalar and cycle classes, also
+            // gets its clusters and term sum from that block.
+            bool plan_fast = g.n_open == 0 && !cl_separate;
+            for (int c = 0; c < ncls && plan_fast; ++c) {
+                const ClassDesc &cd = classes[c0 + c];
+                const bool sc = cd.max_f == 1 && cd.out_size == 1;
+                const bool lp = !p->loop_order[c].empty() && p->loop_e[c] >= 2 && p->loop_e[c] <= 5;
+                plan_fast = sc || lp;
+            }
+            std::vector<int> pn;  // networks left to the cluster and combine launches
+            for (int i : pn_all) {
+                if (plan_fast && net_fused[i] && net_rg_inline[i]) {
+                    FusedNet &f = fused[fused_of_net[i]];
+                    f.cl_fused = 1;
+                    f.class_begin = c0;
+                    f.n_classes = ncls;
+                    f.w_base = b->w_base[i];
+                    net_cl_fused[i] = 1;
+                } else {
+                    pn.push_back(i);
+                }
+            }
             const int pnet_begin = (int)pnets.size();
             for (int i : pn) pnets.push_back(PlanNet{sites[b->site_base[i]].slice_off, b->w_base[i]});
             // slice offsets and strides of the plan's geometry
@@ -864,8 +894,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 for (int l = g.rank[site] - 1; l > slot; --l) st2 *= g.dim[g.slot(site, l)];
                 return st2;
             };
-            const int c0 = plan_index[p];
-            const int ncls = (int)p->classes.size();
             for (int c = 0; c < ncls; ++c) {
                 ClassDesc &cd = classes[c0 + c];
                 cd.tab_off = (int)inst_tab.size();
@@ -990,6 +1018,11 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(inst_w, inst_w);
     UP(pnets, pnets);
     UP(crec, crec);
+    std::vector<int> combine_nets;  // networks whose terms the combine launch sums
+    for (int i = 0; i < n; ++i)
+        if (!net_cl_fused[i]) combine_nets.push_back(i);
+    UP(combine_nets, combine_nets);
+    db.n_combine = (int)combine_nets.size();
     UP(geos, geos);
     UP(buckets, buckets);
     UP(pair_a, pair_a);

@@ -1,0 +1,184 @@
+// Device code shared by the cluster kernel and the persistent block: the
+// one-thread term paths (scalar products and cycle traces) and the FP64 sum
+// of a closed network's retained configurations.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+#include "pne_internal.h"
+#include "regauge.h"
+
+namespace pne {
+namespace dev {
+
+// A cycle of L sites whose cluster legs all have dimension E: the term is
+// Tr(M_0 M_1 ... M_{L-1}) with M_j[a][b] the excited block of site j's slice
+// (a on the leg towards site j-1, b towards site j+1).  One thread holds the
+// running product (E x E) in registers.
+template <int E, typename S>
+__device__ inline typename SliceIO<S>::acc loop_trace(const InstStep *__restrict__ rec, int L,
+                                                      const S *__restrict__ slices, int64_t base) {
+    using A = typename SliceIO<S>::acc;
+    A F[E][E], M[E][E];
+    InstStep r = rec[0];
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) F[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+    for (int j = 1; j < L; ++j) {
+        r = rec[j];
+#pragma unroll
+        for (int a = 0; a < E; ++a)
+#pragma unroll
+            for (int b = 0; b < E; ++b) M[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+        if (j == L - 1) break;
+#pragma unroll
+        for (int a = 0; a < E; ++a) {
+            A row[E];
+#pragma unroll
+            for (int b = 0; b < E; ++b) {
+                A acc = A(0);
+#pragma unroll
+                for (int c = 0; c < E; ++c) acc += F[a][c] * M[c][b];
+                row[b] = acc;
+            }
+#pragma unroll
+            for (int b = 0; b < E; ++b) F[a][b] = row[b];
+        }
+    }
+    A tr = A(0);
+#pragma unroll
+    for (int a = 0; a < E; ++a)
+#pragma unroll
+        for (int b = 0; b < E; ++b) tr += F[a][b] * M[b][a];
+    return tr;
+}
+
+// Value of one scalar or cycle instance (cd.scalar or cd.loop_e); rec are its
+// step records, base the network's slice base.
+template <typename S>
+__device__ inline typename SliceIO<S>::acc fast_term(const ClassDesc &cd, const InstStep *__restrict__ rec,
+                                                     const S *__restrict__ slices, int64_t base) {
+    using A = typename SliceIO<S>::acc;
+    if (cd.scalar) {
+        A prod = A(1);
+        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, base + rec[st].xoff);
+        return prod;
+    }
+    switch (cd.loop_e) {
+        case 2: return loop_trace<2, S>(rec, cd.n_verts, slices, base);
+        case 3: return loop_trace<3, S>(rec, cd.n_verts, slices, base);
+        case 4: return loop_trace<4, S>(rec, cd.n_verts, slices, base);
+        default: return loop_trace<5, S>(rec, cd.n_verts, slices, base);
+    }
+}
+
+// Sum of one value per thread over a block of NT threads, in a fixed order.
+template <int NT>
+__device__ inline double block_sum_nt(double v, double *red) {
+    const int tid = threadIdx.x;
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NT / 64; ++k) t += red[k];
+    __syncthreads();
+    return t;
+}
+
+// FP64 sum of a closed network's retained configurations by a block of NT
+// threads (the closed case of the combine kernel): with W_s the sum of the
+// weights of clusters of size s and Q_s the sum of their squares,
+//   S = sum_s W_s + sum_{s<s', s+s'<=K} W_s W_s' + sum_{2s<=K} (W_s^2 - Q_s)/2
+//       - (sum over listed overlapping pairs of w_a w_b),
+// ln|Z| = sum_v ln|z'_v| + ln|1 + S|.  lds: 8 + 2*64 + 33 doubles.
+template <int NT>
+__device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, const Bucket *__restrict__ buckets,
+                               const int *__restrict__ pair_a, const int *__restrict__ pair_b,
+                               const PairCat *__restrict__ cats, const double *__restrict__ w,
+                               const double *__restrict__ site_log, const int *__restrict__ site_sign,
+                               const NetState *__restrict__ st, NetResult *__restrict__ out, double *lds) {
+    const int tid = threadIdx.x;
+    double *red = lds;
+    double *bw = lds + 8;
+    double *bq = bw + 64;
+    int *bidx = reinterpret_cast<int *>(bq + 64);
+    const double *wn = w + cr.w_base;
+    double lg = 0.0, neg = 0.0;
+    for (int s = tid; s < cr.n_sites; s += NT) {
+        lg += site_log[cr.site_begin + s];
+        neg += site_sign[cr.site_begin + s] < 0 ? 1.0 : 0.0;
+    }
+    lg = block_sum_nt<NT>(lg, red);
+    neg = block_sum_nt<NT>(neg, red);
+    for (int i = tid; i < 33; i += NT) bidx[i] = -1;
+    __syncthreads();
+    const int nb = gr.n_buckets < 64 ? gr.n_buckets : 64;
+    for (int b = 0; b < nb; ++b) {
+        const Bucket bk = buckets[gr.bucket_begin + b];
+        if (tid == 0 && bk.type == 0 && bk.size <= 32) bidx[bk.size] = b;
+        double v = 0.0, q = 0.0;
+        for (int c = bk.begin + tid; c < bk.end; c += NT) {
+            const double x = wn[bk.w_begin + (c - bk.begin)];
+            v += x;
+            q = fma(x, x, q);
+        }
+        v = block_sum_nt<NT>(v, red);
+        q = block_sum_nt<NT>(q, red);
+        if (tid == 0) {
+            bw[b] = v;
+            bq[b] = q;
+        }
+    }
+    double pv = 0.0;
+    for (int ci = 0; ci < gr.n_pair_cats; ++ci) {
+        const PairCat pc = cats[gr.pair_cat_begin + ci];
+        if (pc.t1 != 0 || pc.t2 != 0) continue;
+        for (int p = pc.begin + tid; p < pc.end; p += NT) {
+            const int ca = pair_a[gr.pair_begin + p], cb = pair_b[gr.pair_begin + p];
+            int64_t oa = -1, ob = -1;
+            for (int b = 0; b < nb; ++b) {
+                const Bucket bk = buckets[gr.bucket_begin + b];
+                if (ca >= bk.begin && ca < bk.end) oa = bk.w_begin + (int64_t)(ca - bk.begin) * bk.osz;
+                if (cb >= bk.begin && cb < bk.end) ob = bk.w_begin + (int64_t)(cb - bk.begin) * bk.osz;
+            }
+            pv = fma(wn[oa], wn[ob], pv);
+        }
+    }
+    pv = block_sum_nt<NT>(pv, red);
+    if (tid != 0) return;
+    const int K = gr.K < 32 ? gr.K : 32;
+    auto B = [&](int s) { return (s >= 0 && s <= 32) ? bidx[s] : -1; };
+    double SC = 0.0;
+    for (int s = 1; s <= K; ++s) {
+        const int b = B(s);
+        if (b >= 0) SC += bw[b];
+    }
+    for (int s = 1; s <= K; ++s) {
+        const int b = B(s);
+        if (b < 0) continue;
+        for (int s2 = s + 1; s + s2 <= K; ++s2) {
+            const int b2 = B(s2);
+            if (b2 >= 0) SC += bw[b] * bw[b2];
+        }
+        if (2 * s <= K) SC += 0.5 * (bw[b] * bw[b] - bq[b]);
+    }
+    SC -= pv;
+    NetResult res;
+    const NetState ns = st[net];
+    res.status = ns.status;
+    res.log_bp = lg;
+    res.sum = SC;
+    const int sign_bp = ((int)neg & 1) ? -1 : 1;
+    const double tot = 1.0 + SC;
+    res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
+    res.log_abs = lg + log(fabs(tot));
+    for (int e = 0; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
+    out[net] = res;
+}
+
+}  // namespace dev
+}  // namespace pne
