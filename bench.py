@@ -84,6 +84,32 @@ def bp_bytes(net, steps: int) -> int:
     return ((steps + 1) // 2) * cb[0] + (steps // 2) * cb[1]
 
 
+_CLUSTER_BYTES = {}
+
+
+def cluster_bytes(pne, net, K: int, slice_bytes: int) -> int:
+    """Algorithmic bytes of the cluster contractions and term sum of one
+    network: every cluster reads, at each of its sites, the excited block of
+    that site's slice (e^(cluster legs at the site) entries) and writes one
+    FP64 weight, which the sum reads back.  Depends only on the lattice."""
+    key = (tuple(t.shape for t in net.tensors), K, slice_bytes)
+    if key not in _CLUSTER_BYTES:
+        bonds = np.asarray(net.bonds).reshape(-1, 4)
+        total = 0
+        for cl in pne.enumerate_clusters(net, K):
+            deg = {}
+            for b in cl:
+                u, lu, v, _ = (int(x) for x in bonds[b])
+                e = net.tensors[u].shape[lu] - 1
+                deg.setdefault(u, []).append(e)
+                deg.setdefault(v, []).append(e)
+            for es in deg.values():
+                total += slice_bytes * int(np.prod(es))
+            total += 16
+        _CLUSTER_BYTES[key] = total
+    return _CLUSTER_BYTES[key]
+
+
 def regauge_bytes(net, slice_bytes: int) -> int:
     """Site tensors read once (FP64), slices written once, and the two FP64
     messages of every bond slot read (the gauge is built from them)."""
@@ -303,6 +329,9 @@ def main():
         if phases["regauge_mean"] > 0 and kt_all["regauge"][0] < 0.02 * kt_all["bp_persistent"][0]:
             # the persistent blocks also built the gauge and slices
             alg_bytes += bytes_regauge
+        if kt_all["clusters"][0] < 0.02 * kt_all["bp_persistent"][0]:
+            # ... and contracted the clusters and summed the terms
+            alg_bytes += sum(cluster_bytes(pne, n, args.K, slice_bytes) for n in nets_in)
     elif dom == "regauge":
         alg_bytes = bytes_regauge
     else:
