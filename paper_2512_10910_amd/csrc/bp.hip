@@ -27,11 +27,13 @@ __device__ inline double wave_max(double v) {
 // FP32: (a + 0.5) / b stays within 0.5/b of the true quotient's floor + 0.5.
 __device__ inline int fdiv(int a, float inv_b) { return (int)(((float)a + 0.5f) * inv_b); }
 
-// Per-network state reset, and uniform initial messages 1/sqrt(d) for the
-// sites listed in init_sites (networks swept launch by launch; a persistent
-// block initialises its network's messages in LDS itself).
+// State reset of the networks listed in init_nets and uniform initial
+// messages 1/sqrt(d) for the sites listed in init_sites (networks swept launch
+// by launch; a persistent block resets its network's state and initialises
+// its messages in LDS itself).
 __global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict__ init_sites, int n_sites,
-                       double *__restrict__ msg0, NetState *__restrict__ st, int n_nets) {
+                       double *__restrict__ msg0, NetState *__restrict__ st, const int *__restrict__ init_nets,
+                       int n_nets) {
     int i = blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n_nets) {
         NetState s;
@@ -44,7 +46,8 @@ __global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict_
         s.log_bp = 0.0;
         s.sign_bp = 1;
         s.converged = 0;
-        st[i] = s;
+        s.t_start = s.t_bp = s.t_rg = 0ull;
+        st[init_nets[i]] = s;
     }
     if (i < n_sites) {
         const SiteRec &r = sites[init_sites[i]];
@@ -585,9 +588,10 @@ size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int ma
 }
 
 hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
-    int n = b.n_init_sites > b.n_nets ? b.n_init_sites : b.n_nets;
+    int n = b.n_init_sites > b.n_init_nets ? b.n_init_sites : b.n_init_nets;
+    if (n == 0) return hipSuccess;
     hipLaunchKernelGGL(k_init, dim3((n + 255) / 256), dim3(256), 0, s, b.sites, b.init_sites, b.n_init_sites,
-                       b.msg0, b.state, b.n_nets);
+                       b.msg0, b.state, b.init_nets, b.n_init_nets);
     return hipGetLastError();
 }
 

@@ -490,11 +490,11 @@ template <int D, int R, typename S>
 __device__ __attribute__((noinline)) void p_regauge(int cnt, int net, int site_base, int list_off, int first,
                                                     int msg_lds, const SiteRec *__restrict__ sites,
                                                     S *__restrict__ slices, double *__restrict__ site_log,
-                                                    int *__restrict__ site_sign, NetState *st, int scr) {
+                                                    int *__restrict__ site_sign, int *status, int scr) {
     const LdsMsg msg{msg_lds};
     auto site_of = [site_base, list_off, first](int j) { return site_base + int_at(list_off, first + j); };
-    dev::regauge_reg<D, R, S, dev::rg_passes(D, R)>(cnt, net, site_of, sites, msg, slices, site_log, site_sign, st,
-                                                     p_lds + scr);
+    dev::regauge_reg<D, R, S, dev::rg_passes(D, R)>(cnt, net, site_of, sites, msg, slices, site_log, site_sign,
+                                                     status, p_lds + scr);
 }
 
 // Regauge on the DPP layout (all legs of dimension D <= 4, same lanes and
@@ -539,7 +539,7 @@ template <int D, int R, typename S>
 __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt, int net, int site_base, int first,
                                                         int fin, S *__restrict__ slices,
                                                         double *__restrict__ site_log, int *__restrict__ site_sign,
-                                                        NetState *st, int scr) {
+                                                        int *status, int scr) {
     constexpr int P = D <= 2 ? 2 : 4;
     constexpr int B = P == 2 ? 1 : 2;
     constexpr int T = R < 2 ? R : 2;
@@ -589,7 +589,7 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
         const dev::LegGauge g = dev::leg_gauge_setup(a, c, D);
         double *rec = G + j * GR;
         if (!g.ok) {
-            atomicMin(&st[net].status, -4);
+            atomicMin(status, -4);
 #pragma unroll
             for (int i = 0; i < D; ++i) {
                 rec[i] = i == 0 ? 1.0 : 0.0;
@@ -683,7 +683,7 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
         if (tb == 0 && j < cnt) {
             site_log[site_base + ls[k]] = ok ? log(fabs(z)) : 0.0;
             site_sign[site_base + ls[k]] = z < 0.0 ? -1 : 1;
-            if (!ok) atomicMin(&st[net].status, -4);
+            if (!ok) atomicMin(status, -4);
         }
     }
 }
@@ -720,6 +720,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     const unsigned long long t_start = wall_clock64();
     __shared__ double s_res[kPWaves];
     __shared__ int s_bad;
+    __shared__ int s_status;  // the network's status this run (lowered with LDS atomics)
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
     const int ns_ = fn.n_sites;
@@ -751,7 +752,10 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         reinterpret_cast<int *>(p_lds + L.vside)[s] = r.vside_mask;
         reinterpret_cast<int64_t *>(p_lds + L.soff)[s] = r.slice_off;
     }
-    if (tid == 0) s_bad = 0;
+    if (tid == 0) {
+        s_bad = 0;
+        s_status = 0;
+    }
     __syncthreads();
     int sweep = 0;
     double r = 0.0, r_prev = 0.0;
@@ -826,7 +830,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         ns->parity = 0;
         ns->residual = rb ? fmax(r, r_prev) : r;
         ns->converged = conv ? 1 : 0;
-        if (s_bad) ns->status = -4;
+        if (s_bad) s_status = -4;
+        ns->status = s_status;
         ns->t_start = t_start;
         ns->t_bp = wall_clock64();
         ns->t_rg = ns->t_bp;
@@ -850,12 +855,12 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
 #define PNE_PRG(D_, R_)                                                                                    \
     case D_ * 8 + R_:                                                                                     \
         p_regauge<D_, R_, S>(cnt, fn.net, fn.site_base, L.list, first, msg_lds, sites, slices, site_log, \
-                             site_sign, st, scr);                                                         \
+                             site_sign, &s_status, scr);                                                         \
         break;
 #define PNE_PRGD(D_, R_)                                                                                    \
     case D_ * 8 + R_:                                                                                      \
-        p_regauge_dpp<D_, R_, S>(L, cnt, fn.net, fn.site_base, first, fin, slices, site_log, site_sign, st,  \
-                                 scr);                                                                     \
+        p_regauge_dpp<D_, R_, S>(L, cnt, fn.net, fn.site_base, first, fin, slices, site_log, site_sign,      \
+                                 &s_status, scr);                                                                     \
         break;
             switch (gr.dc * 8 + gr.rank) {
                 PNE_PRGD(2, 1) PNE_PRGD(2, 2) PNE_PRGD(2, 3) PNE_PRGD(2, 4) PNE_PRGD(2, 5) PNE_PRGD(2, 6)
@@ -869,7 +874,10 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         }
     }
     __syncthreads();  // the network's slices and vacuum factors are written
-    if (tid == 0) ns->t_rg = wall_clock64();
+    if (tid == 0) {
+        ns->t_rg = wall_clock64();
+        ns->status = s_status;  // lowered by the gauge on a singular bond or vacuum factor
+    }
     if (!fn.cl_fused) return;
     // Clusters of the network (scalar and cycle classes: one instance per
     // thread, slices just written by this block) and its FP64 term sum.
@@ -878,7 +886,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     __syncthreads();
     const CombineRec cr = crecs[fn.net];
     dev::combine_closed<kPThreads>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
-                                   st, results, p_lds + L.scr);
+                                   s_status, results, p_lds + L.scr);
 }
 
 }  // namespace

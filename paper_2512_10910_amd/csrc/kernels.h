@@ -24,6 +24,8 @@ struct DeviceBatch {
     const int *tile_sites = nullptr;
     const int *init_sites = nullptr;    // sites whose messages k_init resets (non-persistent networks)
     int n_init_sites = 0;
+    const int *init_nets = nullptr;     // networks whose state k_init resets (non-persistent networks)
+    int n_init_nets = 0;
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
     NetState *state = nullptr;
     int n_nets = 0;

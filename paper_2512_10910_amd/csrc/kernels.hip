@@ -148,7 +148,7 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
     const int *ts = tile_sites + tl.site_begin;
     auto site_of = [ts](int j) { return ts[j]; };
     regauge_reg_any<S, false>(tl.dc, tl.rank, tl.n_sites, tl.net, site_of, sites, msg, slices, site_log, site_sign,
-                              st, s_xg);
+                              &st[tl.net].status, s_xg);
 }
 
 // Logical block of a physical one so that consecutive logical blocks run on

@@ -147,7 +147,7 @@ constexpr int kRgXgMax = 512;
 template <int D, int R, typename S, int NP, typename SiteOf, typename Msg>
 __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, const SiteRec *__restrict__ sites,
                                    const Msg &msg, S *__restrict__ slices, double *__restrict__ site_log,
-                                   int *__restrict__ site_sign, NetState *st, double *__restrict__ xs) {
+                                   int *__restrict__ site_sign, int *status, double *__restrict__ xs) {
     constexpr int B = rg_bits(D);
     constexpr int P = 1 << B;
     constexpr int T = rg_lane_legs(D, R);
@@ -200,7 +200,7 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
             c[i] = vs ? x : y;
         }
         const LegGauge g = leg_gauge_setup(a, c, D);
-        if (k == 0 && !g.ok) atomicMin(&st[net].status, -4);
+        if (k == 0 && !g.ok) atomicMin(status, -4);
         double ak = a[0], ck = c[0];
 #pragma unroll
         for (int i = 1; i < D; ++i)
@@ -267,7 +267,7 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
         if (tb == 0 && j < n_sites) {
             site_log[gs[k]] = ok ? log(fabs(z)) : 0.0;
             site_sign[gs[k]] = z < 0.0 ? -1 : 1;
-            if (!ok) atomicMin(&st[net].status, -4);
+            if (!ok) atomicMin(status, -4);
         }
     }
 }
@@ -278,12 +278,12 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
 template <typename S, bool MULTI, typename SiteOf, typename Msg>
 __device__ inline void regauge_reg_any(int dc, int rank, int n_sites, int net, const SiteOf &site_of,
                                        const SiteRec *__restrict__ sites, const Msg &msg, S *__restrict__ slices,
-                                       double *__restrict__ site_log, int *__restrict__ site_sign, NetState *st,
+                                       double *__restrict__ site_log, int *__restrict__ site_sign, int *status,
                                        double *__restrict__ xs) {
 #define PNE_RG_CASE(D_, R_)                                                                                  \
     case D_ * 8 + R_:                                                                                       \
         regauge_reg<D_, R_, S, MULTI ? rg_passes(D_, R_) : 1>(n_sites, net, site_of, sites, msg, slices,    \
-                                                               site_log, site_sign, st, xs);               \
+                                                               site_log, site_sign, status, xs);               \
         break;
     switch (dc * 8 + rank) {
         PNE_RG_CASE(2, 1) PNE_RG_CASE(2, 2) PNE_RG_CASE(2, 3) PNE_RG_CASE(2, 4) PNE_RG_CASE(2, 5)

@@ -1011,6 +1011,11 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             for (int s2 = 0; s2 < nets[i]->geo->n_sites; ++s2) init_sites.push_back(b->site_base[i] + s2);
     UP(init_sites, init_sites);
     db.n_init_sites = (int)init_sites.size();
+    std::vector<int> init_nets;
+    for (int i = 0; i < n; ++i)
+        if (!net_fused[i]) init_nets.push_back(i);
+    UP(init_nets, init_nets);
+    db.n_init_nets = (int)init_nets.size();
     UP(classes, classes);
     UP(steps, steps);
     UP(cblocks, cblocks);

@@ -94,13 +94,14 @@ __device__ inline double block_sum_nt(double v, double *red) {
 // weights of clusters of size s and Q_s the sum of their squares,
 //   S = sum_s W_s + sum_{s<s', s+s'<=K} W_s W_s' + sum_{2s<=K} (W_s^2 - Q_s)/2
 //       - (sum over listed overlapping pairs of w_a w_b),
-// ln|Z| = sum_v ln|z'_v| + ln|1 + S|.  lds: 8 + 2*64 + 33 doubles.
+// ln|Z| = sum_v ln|z'_v| + ln|1 + S|; `status` is the network's status this
+// run.  lds: 8 + 2*64 + 33 doubles.
 template <int NT>
 __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, const Bucket *__restrict__ buckets,
                                const int *__restrict__ pair_a, const int *__restrict__ pair_b,
                                const PairCat *__restrict__ cats, const double *__restrict__ w,
                                const double *__restrict__ site_log, const int *__restrict__ site_sign,
-                               const NetState *__restrict__ st, NetResult *__restrict__ out, double *lds) {
+                               int status, NetResult *__restrict__ out, double *lds) {
     const int tid = threadIdx.x;
     double *red = lds;
     double *bw = lds + 8;
@@ -168,8 +169,7 @@ __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, 
     }
     SC -= pv;
     NetResult res;
-    const NetState ns = st[net];
-    res.status = ns.status;
+    res.status = status;
     res.log_bp = lg;
     res.sum = SC;
     const int sign_bp = ((int)neg & 1) ? -1 : 1;
