@@ -22,6 +22,7 @@ per network).
 from __future__ import annotations
 
 import argparse
+import contextlib
 import json
 import math
 import os
@@ -37,20 +38,9 @@ METRIC = "PNE terms/s and networks/s at <=1e-5 rel err vs FP64 oracle; p50/p99 l
 HBM_PEAK_GBS = 8000.0
 
 
-def sweep_bytes(net) -> int:
-    """Algorithmic bytes of one BP sweep of one network: every site tensor
-    read once (FP64), every incoming message read twice (contraction and
-    residual) and every outgoing message written once."""
-    b = 0
-    for t in net.tensors:
-        b += 8 * t.size + 3 * 8 * sum(t.shape)
-    return b
-
-
-def colour_sweep_bytes(net):
-    """sweep_bytes split by the two site colours of a bipartite network
-    (colour 0 holds site 0), or None when the site graph is not bipartite.
-    Under the red-black schedule, step k updates the sites of colour k mod 2."""
+def site_colours(net):
+    """Two-colouring of the site graph (site 0 has colour 0), or None when the
+    graph is not bipartite."""
     import collections
 
     adj = collections.defaultdict(list)
@@ -70,18 +60,30 @@ def colour_sweep_bytes(net):
                     q.append(y)
                 elif col[y] == col[x]:
                     return None
-    out = [0, 0]
-    for i, t in enumerate(net.tensors):
-        out[col[i]] += 8 * t.size + 3 * 8 * sum(t.shape)
-    return out
+    return col
 
 
-def bp_bytes(net, steps: int) -> int:
-    """Algorithmic bytes of the persistent kernel's BP on one network."""
-    cb = colour_sweep_bytes(net) if len(net.tensors) > 1 else None
-    if cb is None:
-        return steps * sweep_bytes(net)
-    return ((steps + 1) // 2) * cb[0] + (steps // 2) * cb[1]
+def bp_bytes(net, steps: int, messages_in_lds: bool = False) -> int:
+    """Algorithmic bytes of the BP of one network over `steps` steps: network
+    sweeps under Jacobi; under red-black, step k updates the sites of colour
+    k mod 2 only.  Per updated site: the FP64 tensor read once, and, when the
+    messages live in memory, every incoming message read twice (contraction
+    and residual) and every outgoing message written once.  With
+    messages_in_lds (the persistent block keeps its network's messages in
+    LDS) only the tensors stream, plus one write of the final messages."""
+    msg = 0 if messages_in_lds else 3 * 8
+    per = [8 * t.size + msg * sum(t.shape) for t in net.tensors]
+    col = site_colours(net) if len(net.tensors) > 1 else None
+    if col is None:
+        b = steps * sum(per)
+    else:
+        cb = [0, 0]
+        for i, x in enumerate(per):
+            cb[col[i]] += x
+        b = ((steps + 1) // 2) * cb[0] + (steps // 2) * cb[1]
+    if messages_in_lds:
+        b += sum(8 * sum(t.shape) for t in net.tensors)
+    return b
 
 
 _CLUSTER_BYTES = {}
@@ -110,18 +112,21 @@ def cluster_bytes(pne, net, K: int, slice_bytes: int) -> int:
     return _CLUSTER_BYTES[key]
 
 
-def regauge_bytes(net, slice_bytes: int) -> int:
-    """Site tensors read once (FP64), slices written once, and the two FP64
-    messages of every bond slot read (the gauge is built from them)."""
+def regauge_bytes(net, slice_bytes: int, messages_in_lds: bool = False) -> int:
+    """Site tensors read once (FP64), slices written once, one FP64 vacuum
+    log-factor written per site and, unless they are already in LDS, the two
+    FP64 messages of every bond slot read (the gauge is built from them)."""
+    msg = 0 if messages_in_lds else 2 * 8
     b = 0
     for t in net.tensors:
-        b += 8 * t.size + slice_bytes * t.size + 2 * 8 * sum(t.shape)
+        b += 8 * t.size + slice_bytes * t.size + msg * sum(t.shape) + 12
     return b
 
 
 # sources compiled into the persistent BP kernel; a committed HBM-traffic
 # profile counts only while their hash matches the one it records
 KERNEL_SOURCES = ["paper_2512_10910_amd/csrc/bp_persistent.hip", "paper_2512_10910_amd/csrc/regauge.h",
+                  "paper_2512_10910_amd/csrc/terms.h", "paper_2512_10910_amd/csrc/gmem.h",
                   "paper_2512_10910_amd/csrc/kernels.h", "paper_2512_10910_amd/csrc/pne_internal.h"]
 TRAFFIC_PROFILE = "profiles/hbm_traffic_16x16_D4D3_K6_fp32.md"
 
@@ -231,7 +236,8 @@ def main():
     ap.add_argument("--nets", type=int, default=256, help="networks per bond dimension")
     ap.add_argument("--K", type=int, default=6)
     ap.add_argument("--check", type=int, default=2, help="networks per D checked against the oracle")
-    ap.add_argument("--cpu-sample", type=int, default=6, help="networks timed on the CPU oracle (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=24, help="networks timed on the CPU oracle (0: skip)")
+    ap.add_argument("--fp64-steps", type=int, default=10, help="steps timed with FP64 terms (0: skip)")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel HIP events")
     ap.add_argument("--serving", type=int, default=1024, metavar="N",
@@ -319,23 +325,25 @@ def main():
 
     # roofline of the dominant kernel
     sweeps = [int(x) for x in results["bp_iters"]]
-    bytes_sweep = sum(bp_bytes(n, s) for s, n in zip(sweeps, nets_in))
-    bytes_regauge = sum(regauge_bytes(n, slice_bytes) for n in nets_in)
+    # every network's BP ran in a persistent block, messages in LDS
+    in_lds = kt_all["bp_persistent"][0] > 0 and kt_all["bp_sweep"][0] == 0
+    bytes_sweep = sum(bp_bytes(n, s, in_lds) for s, n in zip(sweeps, nets_in))
+    bytes_regauge = sum(regauge_bytes(n, slice_bytes, in_lds) for n in nets_in)
     dom_ms = sum(kt[k][0] for k in timed_kernels) / args.steps
     dom_launches = sum(kt[k][1] for k in timed_kernels)
+    alg_split = {}
     if dom in bp_kernels:
         # every BP kernel of the step together performs all network-sweeps
-        alg_bytes = bytes_sweep
+        alg_split["bp"] = bytes_sweep
         if phases["regauge_mean"] > 0 and kt_all["regauge"][0] < 0.02 * kt_all["bp_persistent"][0]:
             # the persistent blocks also built the gauge and slices
-            alg_bytes += bytes_regauge
+            alg_split["gauge_slices"] = bytes_regauge
         if kt_all["clusters"][0] < 0.02 * kt_all["bp_persistent"][0]:
             # ... and contracted the clusters and summed the terms
-            alg_bytes += sum(cluster_bytes(pne, n, args.K, slice_bytes) for n in nets_in)
+            alg_split["clusters_sum"] = sum(cluster_bytes(pne, n, args.K, slice_bytes) for n in nets_in)
     elif dom == "regauge":
-        alg_bytes = bytes_regauge
-    else:
-        alg_bytes = None
+        alg_split["gauge_slices"] = bytes_regauge
+    alg_bytes = sum(alg_split.values()) if alg_split else None
     achieved = None
     if alg_bytes is not None and dom_ms > 0:
         # bytes per launch / average launch duration == bytes per step / time per step
@@ -351,6 +359,8 @@ def main():
         "launches_per_step": dom_launches / args.steps,
         "avg_launch_us": round(dom_ms * args.steps / max(1, dom_launches) * 1e3, 2),
         "alg_bytes_per_step": alg_bytes,
+        "alg_bytes_split": alg_split,
+        "messages_in_lds": in_lds,
     }
 
     out = {
@@ -382,6 +392,30 @@ def main():
         "roofline": roofline,
     }
 
+    if args.fp64_steps > 0 and not args.profile_run and args.precision != "fp64":
+        # the same batch with FP64 term contractions (slices, clusters and
+        # sums all FP64), timed the same way: the plain FP64 form
+        fb = ctx.batch(nets, K=args.K, precision="fp64")
+        for _ in range(args.warmup):
+            fb.run_arrays(raise_on_error=True)
+        torch.cuda.synchronize()
+        f0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            r64 = fb.run_arrays(raise_on_error=True)
+        torch.cuda.synchronize()
+        f1 = time.perf_counter()
+        fb.close()
+        fms = (f1 - f0) * 1e3 / args.fp64_steps
+        d = np.abs(results["log_abs"] - r64["log_abs"]) / np.maximum(1.0, np.abs(r64["log_abs"]))
+        out["fp64_form"] = {
+            "networks_per_s": round(n_nets / (fms * 1e-3), 1),
+            "ms_per_step": round(fms, 4),
+            "steps": args.fp64_steps,
+            "speedup_of_reduced_precision": round(fms / ms_step, 3),
+            "max_rel_err_log_vs_fp64_form": float(d.max()),
+            "signs_equal": bool((results["sign"] == r64["sign"]).all()),
+        }
+
     if not args.profile_run:
         import oracle as O
 
@@ -404,13 +438,11 @@ def main():
                 threadpool_limits = None
             sample = [nets_in[i] for i in range(args.cpu_sample // 2)] + \
                      [nets_in[args.nets + i] for i in range(args.cpu_sample - args.cpu_sample // 2)]
-            ctxm = threadpool_limits(1) if threadpool_limits else None
-            tc0 = time.perf_counter()
-            for n in sample:
-                O.pne_contract(n, args.K)
-            tc1 = time.perf_counter()
-            if ctxm is not None:
-                ctxm.unregister() if hasattr(ctxm, "unregister") else None
+            with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
+                tc0 = time.perf_counter()
+                for n in sample:
+                    O.pne_contract(n, args.K)
+                tc1 = time.perf_counter()
             out["cpu_baseline"] = {
                 "value": round(len(sample) / (tc1 - tc0), 4),
                 "unit": "networks/s",

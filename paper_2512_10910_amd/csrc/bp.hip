@@ -10,6 +10,7 @@
 
 #include <cstdint>
 
+#include "gmem.h"
 #include "kernels.h"
 
 namespace pne {
@@ -144,7 +145,7 @@ __device__ void sweep_tile(const BpTile &tl, const SiteRec *__restrict__ sites, 
     const float inv_nos = 1.0f / (float)nos;
     for (int e = tid; e < nsit * size; e += kBpThreads) {
         const int j = fdiv(e, inv_size);
-        part[e] = s_t[j][e - j * size];
+        part[e] = dev::gld(s_t[j] + (e - j * size));
     }
     for (int e = tid; e < nsit * nos; e += kBpThreads) {
         const int j = fdiv(e, inv_nos);
@@ -367,7 +368,10 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
         const double *tp = sh.t[s];
         const double *mi = min + sh.msg[s];
 #pragma unroll
-        for (int L = 0; L < NL; ++L) tv[row][L] = act[row] ? tp[L * DT + toff] : 0.0;
+        for (int L = 0; L < NL; ++L) {
+            const double x = dev::gld(tp + L * DT + toff);  // in bounds on every lane
+            tv[row][L] = act[row] ? x : 0.0;
+        }
 #pragma unroll
         for (int m = 0; m < T; ++m) mt[row][m] = mi[(NLEG + m) * D + dig[m] % D];
 #pragma unroll

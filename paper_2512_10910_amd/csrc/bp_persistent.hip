@@ -103,7 +103,7 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
         const double *tp = tptr_at(L, site);
         const int mb = mi + int_at(L.moff, site);
 #pragma unroll
-        for (int q = 0; q < NL; ++q) tv[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+        for (int q = 0; q < NL; ++q) tv[k][q] = dev::gld(tp + q * DT + toff);  // in bounds on every lane
 #pragma unroll
         for (int m = 0; m < T; ++m) mt[k][m] = p_lds[mb + (NLEG + m) * D + dig[m] % D];
 #pragma unroll
@@ -125,6 +125,7 @@ __device__ __attribute__((noinline)) double ptiles(const PLayout L, int gl_off, 
             for (int j = 0; j < NLEG; ++j) w *= ml[k][j][(q / ipw(D, NLEG - 1 - j)) % D];
             A = fma(tv[k][q], w, A);
         }
+        if (!inseg) A = 0.0;  // lanes past the last digit add nothing to the segment sums
 #pragma unroll
         for (int m = 0; m < T; ++m) {
             double pm = A;
@@ -371,7 +372,7 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
         const double *tp = tptr_at(L, site);
         const int mb = mi + int_at(L.moff, site);
 #pragma unroll
-        for (int q = 0; q < NL; ++q) tv[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+        for (int q = 0; q < NL; ++q) tv[k][q] = dev::gld(tp + q * DT + toff);  // in bounds on every lane
         mlo[k] = p_lds[mb + (R - 1) * D + dlo % D];
         mhi[k] = T == 2 ? p_lds[mb + (R - 2) * D + dhi % D] : 1.0;
 #pragma unroll
@@ -392,6 +393,7 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
             for (int j = 0; j < NLEG; ++j) w *= ml[k][j][(q / ipw(D, NLEG - 1 - j)) % D];
             A = fma(tv[k][q], w, A);
         }
+        if (!inseg) A = 0.0;  // lanes past the last digit add nothing to the segment sums
         // leg R-1: lanes of one low digit, summed over the high field
         {
             double pm = A * mhi[k];
@@ -568,7 +570,10 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
         ls[k] = int_at(L.list, first + (j < cnt ? j : 0));
         const double *tp = tptr_at(L, ls[k]);
 #pragma unroll
-        for (int q = 0; q < NL; ++q) v[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+        for (int q = 0; q < NL; ++q) {
+            const double x = dev::gld(tp + q * DT + toff);  // in bounds on every lane
+            v[k][q] = act[k] ? x : 0.0;
+        }
     }
     double *G = p_lds + scr;  // [site][slot][GR]
     wave_sync();              // the wave's previous call has finished reading G
@@ -681,8 +686,8 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
             if (act[k]) dev::SliceIO<S>::store(slices, so + q * DT + toff, x * iz);
         }
         if (tb == 0 && j < cnt) {
-            site_log[site_base + ls[k]] = ok ? log(fabs(z)) : 0.0;
-            site_sign[site_base + ls[k]] = z < 0.0 ? -1 : 1;
+            dev::gst(site_log + site_base + ls[k], ok ? log(fabs(z)) : 0.0);
+            dev::gst(site_sign + site_base + ls[k], z < 0.0 ? -1 : 1);
             if (!ok) atomicMin(status, -4);
         }
     }
@@ -700,7 +705,8 @@ __device__ __attribute__((noinline)) void p_clusters(int class_begin, int n_clas
         const int per = cd.loop_e ? cd.n_verts : cd.n_steps;
         for (int k = threadIdx.x; k < cd.n_inst; k += kPThreads) {
             const InstStep *rec = tab + cd.tab_off + (int64_t)k * per;
-            w[w_base + inst_w[cd.w_begin + k]] = (double)dev::fast_term<S>(cd, rec, slices, slice_base);
+            dev::gst(w + w_base + dev::gld(inst_w + cd.w_begin + k),
+                     (double)dev::fast_term<S>(cd, rec, slices, slice_base));
         }
     }
 }

@@ -7,6 +7,7 @@
 
 #include <cstdint>
 
+#include "gmem.h"
 #include "pne_internal.h"
 
 namespace pne {
@@ -32,20 +33,20 @@ struct SliceIO;
 template <>
 struct SliceIO<double> {
     using acc = double;
-    __device__ static double load(const double *p, int64_t i) { return p[i]; }
-    __device__ static void store(double *p, int64_t i, double v) { p[i] = v; }
+    __device__ static double load(const double *p, int64_t i) { return gld(p + i); }
+    __device__ static void store(double *p, int64_t i, double v) { gst(p + i, v); }
 };
 template <>
 struct SliceIO<float> {
     using acc = float;
-    __device__ static float load(const float *p, int64_t i) { return p[i]; }
-    __device__ static void store(float *p, int64_t i, double v) { p[i] = (float)v; }
+    __device__ static float load(const float *p, int64_t i) { return gld(p + i); }
+    __device__ static void store(float *p, int64_t i, double v) { gst(p + i, (float)v); }
 };
 template <>
 struct SliceIO<uint16_t> {
     using acc = float;
-    __device__ static float load(const uint16_t *p, int64_t i) { return bf16_to_f32(p[i]); }
-    __device__ static void store(uint16_t *p, int64_t i, double v) { p[i] = f64_to_bf16(v); }
+    __device__ static float load(const uint16_t *p, int64_t i) { return bf16_to_f32(gld(p + i)); }
+    __device__ static void store(uint16_t *p, int64_t i, double v) { gst(p + i, f64_to_bf16(v)); }
 };
 
 
@@ -178,9 +179,12 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
         const int j = k * SPT + slot;
         act[k] = inseg && j < n_sites;
         gs[k] = site_of(j < n_sites ? j : 0);
-        const double *tp = sites[gs[k]].t;
+        const double *tp = gld(&sites[gs[k]].t);
 #pragma unroll
-        for (int q = 0; q < NL; ++q) v[k][q] = act[k] ? tp[q * DT + toff] : 0.0;
+        for (int q = 0; q < NL; ++q) {
+            const double x = gld(tp + q * DT + toff);  // in bounds on every lane
+            v[k][q] = act[k] ? x : 0.0;
+        }
     }
     rg_wave_sync();  // the wave's previous call has finished reading xs
     // 1. slot transforms, one column per item
@@ -188,10 +192,10 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
         const int s = j / (R * D);
         const int l = (j / D) % R;
         const int k = j % D;
-        const SiteRec &q = sites[site_of(s)];
-        const bool vs = (q.vside_mask >> l) & 1;
-        const int pin = q.msg_off + q.moff[l];
-        const int pout = q.dst[l];
+        const SiteRec *q = sites + site_of(s);
+        const bool vs = (gld(&q->vside_mask) >> l) & 1;
+        const int pin = gld(&q->msg_off) + gld(&q->moff[l]);
+        const int pout = gld(&q->dst[l]);
         double a[D], c[D];
 #pragma unroll
         for (int i = 0; i < D; ++i) {
@@ -259,14 +263,14 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
         const double z = __shfl(v[k][0], slot * LS, 64);
         const bool ok = (fabs(z) > 0.0) && isfinite(z);
         if (act[k]) {
-            const int64_t so = sites[gs[k]].slice_off;
+            const int64_t so = gld(&sites[gs[k]].slice_off);
             const double iz = ok ? 1.0 / z : 0.0;
 #pragma unroll
             for (int q = 0; q < NL; ++q) SliceIO<S>::store(slices, so + q * DT + toff, v[k][q] * iz);
         }
         if (tb == 0 && j < n_sites) {
-            site_log[gs[k]] = ok ? log(fabs(z)) : 0.0;
-            site_sign[gs[k]] = z < 0.0 ? -1 : 1;
+            gst(site_log + gs[k], ok ? log(fabs(z)) : 0.0);
+            gst(site_sign + gs[k], z < 0.0 ? -1 : 1);
             if (!ok) atomicMin(status, -4);
         }
     }

@@ -22,17 +22,19 @@ __device__ inline typename SliceIO<S>::acc loop_trace(const InstStep *__restrict
                                                       const S *__restrict__ slices, int64_t base) {
     using A = typename SliceIO<S>::acc;
     A F[E][E], M[E][E];
-    InstStep r = rec[0];
+    int xo = gld(&rec[0].xoff), x0 = gld(&rec[0].xs[0]), x1 = gld(&rec[0].xs[1]);
 #pragma unroll
     for (int a = 0; a < E; ++a)
 #pragma unroll
-        for (int b = 0; b < E; ++b) F[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+        for (int b = 0; b < E; ++b) F[a][b] = SliceIO<S>::load(slices, base + xo + a * x0 + b * x1);
     for (int j = 1; j < L; ++j) {
-        r = rec[j];
+        xo = gld(&rec[j].xoff);
+        x0 = gld(&rec[j].xs[0]);
+        x1 = gld(&rec[j].xs[1]);
 #pragma unroll
         for (int a = 0; a < E; ++a)
 #pragma unroll
-            for (int b = 0; b < E; ++b) M[a][b] = SliceIO<S>::load(slices, base + r.xoff + a * r.xs[0] + b * r.xs[1]);
+            for (int b = 0; b < E; ++b) M[a][b] = SliceIO<S>::load(slices, base + xo + a * x0 + b * x1);
         if (j == L - 1) break;
 #pragma unroll
         for (int a = 0; a < E; ++a) {
@@ -64,7 +66,7 @@ __device__ inline typename SliceIO<S>::acc fast_term(const ClassDesc &cd, const 
     using A = typename SliceIO<S>::acc;
     if (cd.scalar) {
         A prod = A(1);
-        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, base + rec[st].xoff);
+        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, base + gld(&rec[st].xoff));
         return prod;
     }
     switch (cd.loop_e) {
