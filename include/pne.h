@@ -252,7 +252,8 @@ typedef struct {
     size_t mem_budget;       /* device bytes admitted requests may hold (estimate); 0: no limit */
     int32_t max_batch;       /* networks per launch (default 1024) */
     int32_t pipeline_depth;  /* batches in flight, 1 or 2 (default 2) */
-    int32_t reserved[4];
+    int32_t completion_queue; /* 1: finished tickets are queued for pne_server_completed (default 0) */
+    int32_t reserved[3];
 } pne_server_options;
 
 typedef struct {
@@ -263,6 +264,10 @@ typedef struct {
     double busy_s;                  /* wall time with at least one batch in flight */
     double prep_s;                  /* worker time creating networks / batches and launching */
     double wait_s;                  /* worker time blocked on batch completion */
+    /* prep_s split: tensor staging and upload, network creation, batch
+     * creation (tables, device arena), launch (which waits on the device
+     * where a network's BP is swept launch by launch) */
+    double upload_s, networks_s, batch_s, launch_s;
 } pne_server_stats;
 
 pne_status pne_server_options_default(pne_server_options *opt);
@@ -284,6 +289,11 @@ pne_status pne_submit(pne_server *server, const pne_network_desc *desc, const pn
  * result for another poll. */
 pne_status pne_poll(pne_server *server, uint64_t ticket, pne_result *result);
 pne_status pne_server_get_stats(pne_server *server, pne_server_stats *out);
+/* With completion_queue set: moves up to `capacity` tickets of finished
+ * requests (success or failure), oldest first, into tickets[] and sets *n to
+ * their count; a client then polls only those.  INVALID_ARG without the
+ * option or with a NULL argument. */
+pne_status pne_server_completed(pne_server *server, uint64_t *tickets, int32_t capacity, int32_t *n);
 
 #ifdef __cplusplus
 }

@@ -13,6 +13,7 @@ from .pne import (  # noqa: F401
     Network,
     PNEError,
     Result,
+    Prepared,
     Server,
     enumerate_clusters,
     load_library,

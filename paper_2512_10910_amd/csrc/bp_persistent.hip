@@ -698,15 +698,13 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
 template <typename S>
 __device__ __attribute__((noinline)) void p_clusters(int class_begin, int n_classes, int64_t w_base,
                                                      int64_t slice_base, const ClassDesc *__restrict__ classes,
-                                                     const InstStep *__restrict__ tab, const int *__restrict__ inst_w,
                                                      const S *__restrict__ slices, double *__restrict__ w) {
     for (int c = class_begin; c < class_begin + n_classes; ++c) {
         const ClassDesc cd = classes[c];
         const int per = cd.loop_e ? cd.n_verts : cd.n_steps;
         for (int k = threadIdx.x; k < cd.n_inst; k += kPThreads) {
-            const InstStep *rec = tab + cd.tab_off + (int64_t)k * per;
-            dev::gst(w + w_base + dev::gld(inst_w + cd.w_begin + k),
-                     (double)dev::fast_term<S>(cd, rec, slices, slice_base));
+            const InstStep *rec = cd.tab + (int64_t)k * per;
+            dev::gst(w + w_base + dev::gld(cd.iw + k), (double)dev::fast_term<S>(cd, rec, slices, slice_base));
         }
     }
 }
@@ -717,7 +715,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
                 const int *__restrict__ site_list, const SiteRec *__restrict__ sites, double *msg0, NetState *st,
                 double tol, int max_iter, S *__restrict__ slices, double *__restrict__ site_log,
                 int *__restrict__ site_sign, int rg_enabled, const ClassDesc *__restrict__ classes,
-                const InstStep *__restrict__ tab, const int *__restrict__ inst_w, double *__restrict__ w,
+                double *__restrict__ w,
                 const CombineRec *__restrict__ crecs, const GeoRec *__restrict__ geos,
                 const Bucket *__restrict__ buckets, const int *__restrict__ pair_a, const int *__restrict__ pair_b,
                 const PairCat *__restrict__ cats, NetResult *__restrict__ results) {
@@ -888,7 +886,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     // Clusters of the network (scalar and cycle classes: one instance per
     // thread, slices just written by this block) and its FP64 term sum.
     p_clusters<S>(fn.class_begin, fn.n_classes, fn.w_base, reinterpret_cast<const int64_t *>(p_lds + L.soff)[0],
-                  classes, tab, inst_w, slices, w);
+                  classes, slices, w);
     __syncthreads();
     const CombineRec cr = crecs[fn.net];
     dev::combine_closed<kPThreads>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
@@ -941,20 +939,20 @@ hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStrea
         case 0:
             hipLaunchKernelGGL(k_bp_persistent<double>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
                                b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
-                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.inst_tab, b.inst_w, b.w,
+                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w,
                                b.crec, b.geos, b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         case 1:
             hipLaunchKernelGGL(k_bp_persistent<float>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
                                b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
-                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.inst_tab, b.inst_w, b.w,
+                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w,
                                b.crec, b.geos, b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         default:
             hipLaunchKernelGGL(k_bp_persistent<uint16_t>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
                                b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter,
                                (uint16_t *)b.slices, b.site_log, b.site_sign, b.fused_regauge, b.classes,
-                               b.inst_tab, b.inst_w, b.w, b.crec, b.geos, b.buckets, b.pair_a, b.pair_b,
+                               b.w, b.crec, b.geos, b.buckets, b.pair_a, b.pair_b,
                                b.pair_cats, b.results);
             break;
     }

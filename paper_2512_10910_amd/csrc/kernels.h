@@ -46,8 +46,6 @@ struct DeviceBatch {
     const StepDesc *steps = nullptr;
     const ClusterBlock *cblocks = nullptr;
     int n_cblocks = 0;
-    const InstStep *inst_tab = nullptr;   // per plan class: n_inst * n_steps records
-    const int *inst_w = nullptr;          // per plan class: weight offset of each instance
     const PlanNet *pnets = nullptr;       // per plan: its networks' slice and weight bases
     size_t cluster_lds = 0;
     double *w = nullptr;

@@ -169,8 +169,8 @@ __device__ inline int xcd_block(int p, int nb) {
 template <typename S>
 __global__ void __launch_bounds__(kClThreads) k_clusters(
     const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps,
-    const ClusterBlock *__restrict__ blocks, const InstStep *__restrict__ tab, const int *__restrict__ inst_w,
-    const PlanNet *__restrict__ pnets, const S *__restrict__ slices, double *__restrict__ w) {
+    const ClusterBlock *__restrict__ blocks, const PlanNet *__restrict__ pnets, const S *__restrict__ slices,
+    double *__restrict__ w) {
     using A = typename SliceIO<S>::acc;
     const ClusterBlock blk = blocks[xcd_block(blockIdx.x, gridDim.x)];
     const ClassDesc cd = classes[blk.cls];
@@ -181,7 +181,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         const int net = f / cd.n_inst;
         const int k = f - net * cd.n_inst;
         const PlanNet pn = pnets[cd.pnet_begin + net];
-        const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_verts;
+        const InstStep *rec = cd.tab + (int64_t)k * cd.n_verts;
         A v = A(0);
         switch (cd.loop_e) {
             case 2: v = loop_trace<2, S>(rec, cd.n_verts, slices, pn.slice_base); break;
@@ -189,7 +189,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
             case 4: v = loop_trace<4, S>(rec, cd.n_verts, slices, pn.slice_base); break;
             default: v = loop_trace<5, S>(rec, cd.n_verts, slices, pn.slice_base); break;
         }
-        w[pn.w_base + inst_w[cd.w_begin + k]] = (double)v;
+        w[pn.w_base + gld(cd.iw + k)] = (double)v;
         return;
     }
     if (cd.scalar) {
@@ -198,10 +198,10 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         const int net = f / cd.n_inst;
         const int k = f - net * cd.n_inst;
         const PlanNet pn = pnets[cd.pnet_begin + net];
-        const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_steps;
+        const InstStep *rec = cd.tab + (int64_t)k * cd.n_steps;
         A prod = A(1);
-        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, pn.slice_base + rec[st].xoff);
-        w[pn.w_base + inst_w[cd.w_begin + k]] = (double)prod;
+        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, pn.slice_base + gld(&rec[st].xoff));
+        w[pn.w_base + gld(cd.iw + k)] = (double)prod;
         return;
     }
     extern __shared__ double lds_raw[];
@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
     const int net = f / cd.n_inst;
     const int k = f - net * cd.n_inst;
     const PlanNet pn = pnets[cd.pnet_begin + net];
-    const InstStep *rec = tab + cd.tab_off + (int64_t)k * cd.n_steps;
+    const InstStep *rec = cd.tab + (int64_t)k * cd.n_steps;
     A *F = reinterpret_cast<A *>(lds_raw) + (size_t)slot * 2 * cd.max_f;
     A *G = F + cd.max_f;
     if (lane == 0) F[0] = A(1);
@@ -225,11 +225,10 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
     for (int st = 0; st < cd.n_steps; ++st) {
         const StepDesc &sd = s_steps[st];
         if (valid) {
-            const InstStep r = rec[st];
-            const int64_t xbase = pn.slice_base + r.xoff;
+            const int64_t xbase = pn.slice_base + gld(&rec[st].xoff);
             int xs[kMaxLab];
 #pragma unroll
-            for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? r.xs[m] : 0;
+            for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
             for (int o = lane; o < sd.n_out; o += g) {
                 int rem = o, fb = 0, xb = 0;
                 for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
@@ -284,7 +283,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         G = t;
     }
     if (valid) {
-        const int64_t wo = pn.w_base + inst_w[cd.w_begin + k];
+        const int64_t wo = pn.w_base + gld(cd.iw + k);
         for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
     }
 }
@@ -531,17 +530,17 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
     switch (b.precision) {
         case 0:
             hipLaunchKernelGGL(k_clusters<double>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
+                               b.steps, b.cblocks, b.pnets,
                                (const double *)b.slices, b.w);
             break;
         case 1:
             hipLaunchKernelGGL(k_clusters<float>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
+                               b.steps, b.cblocks, b.pnets,
                                (const float *)b.slices, b.w);
             break;
         default:
             hipLaunchKernelGGL(k_clusters<uint16_t>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s,
-                               b.classes, b.steps, b.cblocks, b.inst_tab, b.inst_w, b.pnets,
+                               b.classes, b.steps, b.cblocks, b.pnets,
                                (const uint16_t *)b.slices, b.w);
             break;
     }

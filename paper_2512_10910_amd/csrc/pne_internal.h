@@ -113,15 +113,17 @@ struct StepDesc {
 
 // A class of clusters with the same contraction plan.
 struct ClassDesc {
+    // device tables of the class, kept by the context once per plan (null in
+    // the plan's own copy)
+    const struct InstStep *tab;  // InstStep records, instance-major (n_steps, or n_verts for a cycle, each)
+    const int32_t *iw;           // weight offset of each instance from its network's weight base
     int32_t step_begin;  // index into the step table
     int32_t n_steps;
     int32_t n_verts;
     int32_t max_f;       // largest frontier (entries)
     int32_t group;       // lanes per instance (power of two, <= 64)
     int32_t out_size;    // entries of the result tensor (1 for closed clusters)
-    // batch tables (filled per batch; the plan's own copy leaves them 0)
-    int32_t tab_off;     // first InstStep record of the class (instance-major, n_steps per instance)
-    int32_t w_begin;     // first entry of the class in the per-instance weight-offset table
+    // filled per batch
     int32_t n_inst;      // instances per network
     int32_t pnet_begin;  // first PlanNet of the networks sharing the class's plan
     int32_t n_pnets;

@@ -9,6 +9,7 @@
 #include <memory>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "geometry.h"
@@ -23,6 +24,22 @@ struct PlanEntry {
     std::map<int, std::shared_ptr<GeoPlan>> plans;  // by K
 };
 
+// Device instance tables of one plan, built and uploaded once per context:
+// for every class instance and contraction step the absorbed slice's element
+// offset from the network's slice base (excited legs at index 1) and its leg
+// strides, and every instance's weight offset.  A batch only adds per-network
+// slice and weight bases.
+struct PlanTables {
+    void *dev = nullptr;  // one allocation: records, then weight offsets
+    size_t bytes = 0;
+    struct Cls {
+        const InstStep *tab;
+        const int32_t *iw;
+        int32_t n_inst, scalar, loop_e;
+    };
+    std::vector<Cls> cls;  // per class of the plan
+};
+
 struct pne_ctx {
     int device = 0;
     hipStream_t stream = nullptr;
@@ -30,12 +47,21 @@ struct pne_ctx {
     size_t budget = 0;
     size_t used = 0;
     std::string err;
+    std::mutex err_mu;  // a server's two threads may both report errors on the context
     std::multimap<uint64_t, PlanEntry> cache;
     std::mutex mu;
     double wall_khz = 100000.0;  // device wall clock rate (ticks per ms)
     void *staging = nullptr;     // pinned upload staging, reused by every batch creation
     size_t staging_bytes = 0;
+    // Table uploads run on their own stream, so they never wait behind
+    // kernels already queued on a batch's stream; the batch stream waits on
+    // up_done instead, and the staging buffer is rewritten only once the
+    // previous upload has completed.
+    hipStream_t up_stream = nullptr;
+    hipEvent_t up_done = nullptr;
+    bool up_pending = false;
     std::map<uint64_t, uint32_t> tuned;  // batch signature -> chosen flags (PNE_FLAG_AUTOTUNE)
+    std::unordered_map<const GeoPlan *, PlanTables> plan_tables;  // plans live as long as the context
 };
 
 struct pne_network {
@@ -94,7 +120,10 @@ namespace {
 thread_local std::string g_tls_err;
 
 pne_status fail(pne_ctx *ctx, pne_status st, const std::string &msg) {
-    if (ctx) ctx->err = msg;
+    if (ctx) {
+        std::lock_guard<std::mutex> lk(ctx->err_mu);
+        ctx->err = msg;
+    }
     g_tls_err = msg;
     return st;
 }
@@ -129,6 +158,108 @@ std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> 
     auto p = build_plan(*pe->geo, K, err);
     if (p) pe->plans[K] = p;
     return p;
+}
+
+size_t align256(size_t x);
+
+// The plan's device instance tables (see PlanTables), built on its first use
+// with g its geometry; the upload is complete on return.
+// nullptr (with *st set) when the device memory cannot be had.
+const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g, pne_status *st) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->plan_tables.find(p);
+    if (it != ctx->plan_tables.end()) return &it->second;
+    std::vector<int64_t> soff(g.n_sites + 1, 0);
+    for (int s2 = 0; s2 < g.n_sites; ++s2) {
+        int64_t sz = 1;
+        for (int l = 0; l < g.rank[s2]; ++l) sz *= g.dim[g.slot(s2, l)];
+        soff[s2 + 1] = soff[s2] + sz;
+    }
+    auto stride_of = [&](int site, int slot) {
+        int64_t st2 = 1;
+        for (int l = g.rank[site] - 1; l > slot; --l) st2 *= g.dim[g.slot(site, l)];
+        return st2;
+    };
+    const int ncls = (int)p->classes.size();
+    std::vector<InstStep> tab;
+    std::vector<int32_t> iw;
+    std::vector<size_t> tab_off(ncls), iw_off(ncls);
+    PlanTables pt;
+    pt.cls.resize(ncls);
+    for (int c = 0; c < ncls; ++c) {
+        const ClassDesc &cd = p->classes[c];
+        PlanTables::Cls &pc = pt.cls[c];
+        tab_off[c] = tab.size();
+        iw_off[c] = iw.size();
+        pc.n_inst = (int)p->inst_cluster[c].size();
+        pc.scalar = (cd.max_f == 1 && cd.out_size == 1) ? 1 : 0;
+        const std::vector<int> &cyc = p->loop_order[c];
+        pc.loop_e = 0;
+        if (!pc.scalar && !cyc.empty() && p->loop_e[c] >= 2 && p->loop_e[c] <= 5 && (int)cyc.size() == 3 * cd.n_verts)
+            pc.loop_e = p->loop_e[c];
+        for (int k = 0; k < pc.n_inst; ++k) {
+            iw.push_back((int32_t)p->w_off[p->inst_cluster[c][k]]);
+            if (pc.loop_e) {
+                for (int j = 0; j < cd.n_verts; ++j) {
+                    const int v = cyc[3 * j];
+                    const int site = p->inst_site[c][(size_t)k * cd.n_verts + v];
+                    const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + v];
+                    InstStep r;
+                    std::memset(&r, 0, sizeof r);
+                    const int64_t s_in = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 1])) & 15u));
+                    const int64_t s_out = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 2])) & 15u));
+                    r.xs[0] = (int32_t)s_in;
+                    r.xs[1] = (int32_t)s_out;
+                    r.xoff = (int32_t)(soff[site] + s_in + s_out);  // excited indices start at 1
+                    tab.push_back(r);
+                }
+                continue;
+            }
+            for (int st2 = 0; st2 < cd.n_steps; ++st2) {
+                const StepDesc &sd = p->steps[cd.step_begin + st2];
+                const int site = p->inst_site[c][(size_t)k * cd.n_verts + sd.vert];
+                const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + sd.vert];
+                InstStep r;
+                std::memset(&r, 0, sizeof r);
+                int64_t xo = soff[site];
+                for (int m = 0; m < sd.n_xl; ++m) {
+                    const int64_t sm = stride_of(site, (int)((slots >> (4 * m)) & 15u));
+                    r.xs[m] = (int32_t)sm;
+                    if (sd.x_excited[m]) xo += sm;  // excited indices start at 1
+                }
+                r.xoff = (int32_t)xo;
+                tab.push_back(r);
+            }
+        }
+    }
+    const size_t tab_bytes = align256(std::max<size_t>(1, tab.size()) * sizeof(InstStep));
+    pt.bytes = tab_bytes + align256(std::max<size_t>(1, iw.size()) * sizeof(int32_t));
+    if (ctx->budget && ctx->used + pt.bytes > ctx->budget) {
+        *st = fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded (cluster tables)");
+        return nullptr;
+    }
+    if (hipMalloc(&pt.dev, pt.bytes) != hipSuccess) {
+        *st = fail(ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed (cluster tables)");
+        return nullptr;
+    }
+    hipError_t e = hipSuccess;
+    if (!tab.empty())
+        e = hipMemcpyAsync(pt.dev, tab.data(), tab.size() * sizeof(InstStep), hipMemcpyHostToDevice, ctx->up_stream);
+    if (e == hipSuccess && !iw.empty())
+        e = hipMemcpyAsync((char *)pt.dev + tab_bytes, iw.data(), iw.size() * sizeof(int32_t), hipMemcpyHostToDevice,
+                           ctx->up_stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->up_stream);  // any stream may use the tables next
+    if (e != hipSuccess) {
+        (void)hipFree(pt.dev);
+        *st = hip_fail(ctx, e, "cluster table upload");
+        return nullptr;
+    }
+    for (int c = 0; c < ncls; ++c) {
+        pt.cls[c].tab = (const InstStep *)pt.dev + tab_off[c];
+        pt.cls[c].iw = (const int32_t *)((const char *)pt.dev + tab_bytes) + iw_off[c];
+    }
+    ctx->used += pt.bytes;
+    return &ctx->plan_tables.emplace(p, std::move(pt)).first->second;
 }
 
 // Device memory of a batch: every table and buffer is a 256-byte aligned
@@ -178,6 +309,11 @@ pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
     b->bytes += total;
     ctx->used += total;
     if (up_bytes) {
+        if (ctx->up_pending) {  // the previous upload still reads the staging buffer
+            hipError_t e = hipEventSynchronize(ctx->up_done);
+            if (e != hipSuccess) return hip_fail(ctx, e, "upload wait");
+            ctx->up_pending = false;
+        }
         if (ctx->staging_bytes < up_bytes) {
             if (ctx->staging) (void)hipHostFree(ctx->staging);
             ctx->staging = nullptr;
@@ -189,8 +325,11 @@ pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
         }
         char *st = (char *)ctx->staging;
         for (auto &pc : ap.up) std::memcpy(st + pc.off, pc.src, pc.bytes);
-        hipError_t e = hipMemcpyAsync(p, st, up_bytes, hipMemcpyHostToDevice, b->stream);
-        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemcpyAsync");
+        hipError_t e = hipMemcpyAsync(p, st, up_bytes, hipMemcpyHostToDevice, ctx->up_stream);
+        if (e == hipSuccess) e = hipEventRecord(ctx->up_done, ctx->up_stream);
+        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ctx->up_done, 0);
+        if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
+        ctx->up_pending = true;
     }
     for (auto &pc : ap.up) *pc.dst = (char *)p + pc.off;
     for (auto &pc : ap.buf) *pc.dst = (char *)p + pc.off;
@@ -342,14 +481,25 @@ pne_status pne_ctx_create(int device, size_t budget, void *stream, pne_ctx **out
         }
         c->own_stream = true;
     }
+    if (hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming) != hipSuccess) {
+        if (c->up_stream) (void)hipStreamDestroy(c->up_stream);
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return fail(nullptr, PNE_ERR_DEVICE, "upload stream creation failed");
+    }
     *out = c;
     return PNE_OK;
 }
 
 pne_status pne_ctx_destroy(pne_ctx *ctx) {
     if (!ctx) return PNE_ERR_INVALID_ARG;
+    if (ctx->up_stream) (void)hipStreamSynchronize(ctx->up_stream);
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
+    if (ctx->up_done) (void)hipEventDestroy(ctx->up_done);
+    if (ctx->up_stream) (void)hipStreamDestroy(ctx->up_stream);
     if (ctx->staging) (void)hipHostFree(ctx->staging);
+    for (auto &kv : ctx->plan_tables) (void)hipFree(kv.second.dev);
     delete ctx;
     return PNE_OK;
 }
@@ -780,8 +930,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<ClassDesc> classes;
     std::vector<StepDesc> steps;
     std::vector<ClusterBlock> cblocks;
-    std::vector<InstStep> inst_tab;
-    std::vector<int> inst_w;
     std::vector<PlanNet> pnets;
     std::vector<CombineRec> crec(n);
     std::vector<GeoRec> geos;
@@ -836,11 +984,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         cr.pb = p->pb;
     }
     if (cl_lds > 64 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: cluster frontier too large for LDS");
-    // Instance tables per plan (shared by every network using the plan):
-    // for each instance and contraction step, the absorbed slice's element
-    // offset from the network's slice base (excited legs at index 1) and its
-    // leg strides; a network only adds its slice and weight bases.  Blocks
-    // walk the plan's networks in order, each block covering up to 256/group
+    // Classes point at their plan's device instance tables (kept by the
+    // context); a network only adds its slice and weight bases.  Blocks walk
+    // the plan's networks in order, each block covering up to 256/group
     // consecutive (network, instance) pairs of one class.
     std::vector<char> net_cl_fused(n, 0);
     const bool cl_separate = (opt->flags & PNE_FLAG_SEPARATE_REGAUGE) != 0;
@@ -857,6 +1003,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             const Geometry &g = *nets[pn_all[0]]->geo;
             const int c0 = plan_index[p];
             const int ncls = (int)p->classes.size();
+            pne_status pst = PNE_OK;
+            const PlanTables *pt = plan_tables(ctx, p, g, &pst);
+            if (!pt) return pst;
             // A closed network whose BP, gauge and slices run in a persistent
             // block, and whose plan has only scalar and cycle classes, also
             // gets its clusters and term sum from that block.
@@ -882,65 +1031,16 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             }
             const int pnet_begin = (int)pnets.size();
             for (int i : pn) pnets.push_back(PlanNet{sites[b->site_base[i]].slice_off, b->w_base[i]});
-            // slice offsets and strides of the plan's geometry
-            std::vector<int64_t> soff(g.n_sites + 1, 0);
-            for (int s2 = 0; s2 < g.n_sites; ++s2) {
-                int64_t sz = 1;
-                for (int l = 0; l < g.rank[s2]; ++l) sz *= g.dim[g.slot(s2, l)];
-                soff[s2 + 1] = soff[s2] + sz;
-            }
-            auto stride_of = [&](int site, int slot) {
-                int64_t st2 = 1;
-                for (int l = g.rank[site] - 1; l > slot; --l) st2 *= g.dim[g.slot(site, l)];
-                return st2;
-            };
             for (int c = 0; c < ncls; ++c) {
                 ClassDesc &cd = classes[c0 + c];
-                cd.tab_off = (int)inst_tab.size();
-                cd.w_begin = (int)inst_w.size();
-                cd.n_inst = (int)p->inst_cluster[c].size();
+                const PlanTables::Cls &pc = pt->cls[c];
+                cd.tab = pc.tab;
+                cd.iw = pc.iw;
+                cd.n_inst = pc.n_inst;
                 cd.pnet_begin = pnet_begin;
                 cd.n_pnets = (int)pn.size();
-                cd.scalar = (cd.max_f == 1 && cd.out_size == 1) ? 1 : 0;
-                const std::vector<int> &cyc = p->loop_order[c];
-                cd.loop_e = 0;
-                if (!cd.scalar && !cyc.empty() && p->loop_e[c] >= 2 && p->loop_e[c] <= 5 &&
-                    (int)cyc.size() == 3 * cd.n_verts)
-                    cd.loop_e = p->loop_e[c];
-                for (int k = 0; k < cd.n_inst; ++k) {
-                    inst_w.push_back((int)p->w_off[p->inst_cluster[c][k]]);
-                    if (cd.loop_e) {
-                        for (int j = 0; j < cd.n_verts; ++j) {
-                            const int v = cyc[3 * j];
-                            const int site = p->inst_site[c][(size_t)k * cd.n_verts + v];
-                            const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + v];
-                            InstStep r;
-                            std::memset(&r, 0, sizeof r);
-                            const int64_t s_in = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 1])) & 15u));
-                            const int64_t s_out = stride_of(site, (int)((slots >> (4 * cyc[3 * j + 2])) & 15u));
-                            r.xs[0] = (int32_t)s_in;
-                            r.xs[1] = (int32_t)s_out;
-                            r.xoff = (int32_t)(soff[site] + s_in + s_out);  // excited indices start at 1
-                            inst_tab.push_back(r);
-                        }
-                        continue;
-                    }
-                    for (int st2 = 0; st2 < cd.n_steps; ++st2) {
-                        const StepDesc &sd = steps[cd.step_begin + st2];
-                        const int site = p->inst_site[c][(size_t)k * cd.n_verts + sd.vert];
-                        const uint32_t slots = p->inst_slots[c][(size_t)k * cd.n_verts + sd.vert];
-                        InstStep r;
-                        std::memset(&r, 0, sizeof r);
-                        int64_t xo = soff[site];
-                        for (int m = 0; m < sd.n_xl; ++m) {
-                            const int64_t sm = stride_of(site, (int)((slots >> (4 * m)) & 15u));
-                            r.xs[m] = (int32_t)sm;
-                            if (sd.x_excited[m]) xo += sm;  // excited indices start at 1
-                        }
-                        r.xoff = (int32_t)xo;
-                        inst_tab.push_back(r);
-                    }
-                }
+                cd.scalar = pc.scalar;
+                cd.loop_e = pc.loop_e;
             }
             // blocks: networks in order, classes interleaved
             std::vector<int> pend_begin(ncls, 0), pend_count(ncls, 0);
@@ -969,7 +1069,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             for (int c = 0; c < ncls; ++c)
                 if (pend_count[c] > 0) emit(c);
         }
-        if (inst_tab.size() > (size_t)INT32_MAX || pnets.size() > (size_t)INT32_MAX)
+        if (pnets.size() > (size_t)INT32_MAX)
             return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: batch too large");
     }
 
@@ -1019,8 +1119,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(classes, classes);
     UP(steps, steps);
     UP(cblocks, cblocks);
-    UP(inst_tab, inst_tab);
-    UP(inst_w, inst_w);
     UP(pnets, pnets);
     UP(crec, crec);
     std::vector<int> combine_nets;  // networks whose terms the combine launch sums
@@ -1077,11 +1175,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     }
     b->h_state_pinned = b->h_state_slot[0];
     b->h_results_pinned = b->h_results_slot[0];
-    hipError_t e = hipStreamSynchronize(b->stream);
-    if (e != hipSuccess) {
-        free_batch(b.get());
-        return hip_fail(ctx, e, "batch upload");
-    }
     b->msg_off.resize(sites.size());
     for (size_t s = 0; s < sites.size(); ++s) b->msg_off[s] = sites[s].msg_off;
     *out = b.release();

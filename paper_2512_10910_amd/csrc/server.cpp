@@ -1,16 +1,18 @@
 // Request server: continuous batching of independent networks on one device.
 //
 // Clients submit networks from any thread (pne_submit copies the descriptor
-// and the host tensors) and collect results with pne_poll.  One worker
-// thread owns the context: it admits pending requests in arrival order while
-// their estimated device bytes fit the memory budget, groups requests with
-// identical options into one batch (plans are cached per lattice, so a
-// batch of mixed lattices shares nothing but the launches), and keeps up to
-// `pipeline_depth` batches in flight on separate streams, so the host work
-// of the next batch (validation, uploads, tables) overlaps the device work of
-// the current one.  A batch's networks stay resident from admission until
-// its results are copied back.  Each network's result does not depend on
-// which other networks share its batch.
+// and the host tensors) and collect results with pne_poll (or learn which
+// tickets finished from pne_server_completed).  Two threads own the context:
+// the worker admits pending requests in arrival order while their estimated
+// device bytes fit the memory budget, groups requests with identical options
+// into one batch (plans are cached per lattice, so a batch of mixed lattices
+// shares nothing but the launches), and keeps up to `pipeline_depth` batches
+// in flight on separate streams, so the host work of the next batch
+// (validation, uploads, tables) overlaps the device work of the current one;
+// the completion thread hands a batch's results out as soon as the device
+// has finished it.  A batch's networks stay resident from admission until its
+// results are copied back.  Each network's result does not depend on which
+// other networks share its batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -42,7 +44,8 @@ struct Request {
     pne_options opt{};
     // owned copy of the descriptor
     std::vector<int32_t> rank, dims, bond_site, bond_leg, open_leg;
-    std::vector<std::vector<double>> data;
+    std::vector<double> data;     // every site tensor, site after site
+    std::vector<size_t> site_off;  // n_sites + 1 offsets into data
     std::vector<const double *> ptrs;
     pne_network_desc desc{};
     size_t est_bytes = 0;
@@ -64,13 +67,23 @@ bool same_options(const pne_options &a, const pne_options &b) {
 // the cluster weights (one FP64 value per cluster; clusters per bond grow
 // with K, bounded here by 64 per bond).
 size_t estimate_bytes(const Request &r) {
-    size_t entries = 0, slots = 0;
-    for (size_t s = 0; s < r.data.size(); ++s) entries += r.data[s].size();
+    const size_t entries = r.data.size();
+    size_t slots = 0;
     for (int32_t x : r.rank) slots += (size_t)x;
     const size_t esz = r.opt.precision == PNE_FP64 ? 8 : (r.opt.precision == PNE_FP32 ? 4 : 2);
     const size_t msg = 2 * 8 * 4 * slots;  // dims <= 16; generous average
-    return entries * (8 + esz) + msg + 256 * r.data.size() + 64 * 8 * (size_t)r.desc.n_bonds + 4096;
+    return entries * (8 + esz) + msg + 256 * r.rank.size() + 64 * 8 * (size_t)r.desc.n_bonds + 4096;
 }
+
+// A launched batch: its requests, networks and device tensors.
+struct InFlight {
+    pne_batch *batch = nullptr;
+    void *tensors = nullptr;  // device copy of the batch's site tensors (networks borrow it)
+    std::vector<pne_network *> nets;
+    std::vector<Request *> reqs;
+    size_t bytes = 0;
+    Clock::time_point t_launch;
+};
 
 }  // namespace
 
@@ -83,9 +96,16 @@ struct pne_server {
     std::deque<Request *> pending;
     std::unordered_map<uint64_t, std::unique_ptr<Request>> all;
     uint64_t next_ticket = 1;
-    bool stop = false;
+    bool stop = false;        // no more submissions: finish what is queued, then end the worker
+    bool stop_done = false;   // the worker has ended: end the completion thread
     size_t in_use = 0;
-    std::thread worker;
+    std::thread worker;       // admission, preparation and launch
+    std::thread completer;    // waits for launched batches and hands out their results
+    std::condition_variable cv_done;   // wakes the completion thread
+    std::deque<InFlight> inflight;     // launched, oldest first (the worker appends, the completer pops)
+    std::vector<InFlight> graveyard;   // finished; freed while nothing is in flight (frees synchronise)
+    int64_t finished_batches = 0;
+    Clock::time_point busy_since;
     // statistics
     Clock::time_point t0;
     bool any_submit = false;
@@ -96,20 +116,19 @@ struct pne_server {
     double prep_s = 0.0;  // worker time creating networks and batches and launching
     void *staging = nullptr;  // pinned upload staging of the worker
     size_t staging_bytes = 0;
+    // tensor uploads run on their own stream (never behind a batch's
+    // kernels); a batch stream waits on up_done, and the staging buffer is
+    // rewritten only after the previous upload has completed
+    hipStream_t up_stream = nullptr;
+    hipEvent_t up_done = nullptr;
+    bool up_pending = false;
+    std::deque<uint64_t> done_q;  // finished tickets (completion_queue option)
     double wait_s = 0.0;  // worker time blocked on a batch's completion
+    double upload_s = 0.0, networks_s = 0.0, batch_s = 0.0, launch_s = 0.0;  // prep_s split
     std::string err;
 };
 
 namespace {
-
-struct InFlight {
-    pne_batch *batch = nullptr;
-    void *tensors = nullptr;  // device copy of the batch's site tensors (networks borrow it)
-    std::vector<pne_network *> nets;
-    std::vector<Request *> reqs;
-    size_t bytes = 0;
-    Clock::time_point t_launch;
-};
 
 void finish_request(pne_server *sv, Request *r, const pne_result &res, Clock::time_point t) {
     r->res = res;
@@ -121,6 +140,7 @@ void finish_request(pne_server *sv, Request *r, const pne_result &res, Clock::ti
     sv->t_last_done = t;
     if (res.status < 0) ++sv->failed;
     ++sv->completed;
+    if (sv->so.completion_queue) sv->done_q.push_back(r->ticket);
     r->data.clear();
     r->data.shrink_to_fit();
 }
@@ -131,40 +151,170 @@ void fail_request(pne_server *sv, Request *r, pne_status st) {
     finish_request(sv, r, res, Clock::now());
 }
 
-void worker_main(pne_server *sv) {
-    std::deque<InFlight> inflight;
-    std::vector<InFlight> graveyard;  // finished batches freed once the device is idle
-    int launch_count = 0;
-    Clock::time_point busy_since;
-    auto release = [&](InFlight &f) {
-        if (f.batch) pne_batch_destroy(f.batch);
-        for (pne_network *n : f.nets) pne_network_destroy(n);
-        if (f.tensors) (void)hipFree(f.tensors);
-        std::lock_guard<std::mutex> lk(sv->mu);
-        sv->in_use -= std::min(sv->in_use, f.bytes);
+// Copy every request's tensors to its offset in the staging buffer; a large
+// batch is split into byte-balanced runs of requests copied by several
+// threads (one thread's memcpy is far below the host's memory bandwidth).
+void stage_tensors(char *staging, const std::vector<size_t> &toff, const std::vector<Request *> &take) {
+    const size_t total = toff.back();
+    const size_t hw = std::max(1u, std::thread::hardware_concurrency());
+    const size_t nt = std::min<size_t>({8, hw / 2 + 1, total / (4u << 20) + 1, take.size()});
+    auto copy_range = [&](size_t a, size_t b) {
+        for (size_t i = a; i < b; ++i)
+            std::memcpy(staging + toff[i], take[i]->data.data(), take[i]->data.size() * sizeof(double));
     };
+    if (nt <= 1) {
+        copy_range(0, take.size());
+        return;
+    }
+    std::vector<std::thread> th;
+    size_t a = 0;
+    for (size_t t = 0; t < nt && a < take.size(); ++t) {
+        const size_t goal = total * (t + 1) / nt;
+        size_t b = a + 1;
+        while (b < take.size() && toff[b] < goal) ++b;
+        if (t + 1 == nt) b = take.size();
+        if (t + 1 < nt && b < take.size())
+            th.emplace_back(copy_range, a, b);
+        else
+            copy_range(a, b);  // the last run on this thread
+        a = b;
+    }
+    for (auto &x : th) x.join();
+}
+
+void release(pne_server *sv, InFlight &f) {
+    if (f.batch) pne_batch_destroy(f.batch);
+    for (pne_network *n : f.nets) pne_network_destroy(n);
+    if (f.tensors) (void)hipFree(f.tensors);
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->in_use -= std::min(sv->in_use, f.bytes);
+}
+
+// Upload the requests' tensors, create their networks and one batch on
+// stream s, and launch it.  Requests that fail are finished here; false when
+// nothing was launched (f then holds whatever must be released).
+bool prepare_and_launch(pne_server *sv, const std::vector<Request *> &take, hipStream_t s, InFlight &f) {
+    const Clock::time_point tp0 = Clock::now();
+    for (Request *r : take) f.bytes += r->est_bytes;
+    // every request's tensors in one device allocation, uploaded by one copy
+    // from the server's pinned staging buffer on the upload stream; the batch
+    // stream waits for it
+    std::vector<size_t> toff(take.size() + 1, 0);
+    for (size_t i = 0; i < take.size(); ++i) {
+        const size_t b = take[i]->data.size() * sizeof(double);
+        toff[i + 1] = toff[i] + ((b + 255) & ~(size_t)255);
+    }
+    pne_status ust = PNE_OK;
+    if (sv->up_pending) {  // the previous upload still reads the staging buffer
+        if (hipEventSynchronize(sv->up_done) != hipSuccess) ust = PNE_ERR_DEVICE;
+        sv->up_pending = false;
+    }
+    if (ust == PNE_OK && hipMalloc(&f.tensors, std::max<size_t>(toff.back(), 256)) != hipSuccess) {
+        f.tensors = nullptr;
+        ust = PNE_ERR_OUT_OF_MEMORY;
+    }
+    if (ust == PNE_OK && sv->staging_bytes < toff.back()) {
+        if (sv->staging) (void)hipHostFree(sv->staging);
+        sv->staging = nullptr;
+        sv->staging_bytes = 0;
+        const size_t want = std::max(toff.back() + toff.back() / 2, (size_t)1 << 22);
+        if (hipHostMalloc(&sv->staging, want, hipHostMallocDefault) == hipSuccess)
+            sv->staging_bytes = want;
+        else
+            ust = PNE_ERR_OUT_OF_MEMORY;
+    }
+    if (ust == PNE_OK) {
+        stage_tensors((char *)sv->staging, toff, take);
+        if (hipMemcpyAsync(f.tensors, sv->staging, toff.back(), hipMemcpyHostToDevice, sv->up_stream) !=
+                hipSuccess ||
+            hipEventRecord(sv->up_done, sv->up_stream) != hipSuccess ||
+            hipStreamWaitEvent(s, sv->up_done, 0) != hipSuccess)
+            ust = PNE_ERR_DEVICE;
+        else
+            sv->up_pending = true;
+    }
+    const Clock::time_point tp1 = Clock::now();
+    std::vector<Request *> ok;
+    std::vector<const double *> dptr;
+    for (size_t i = 0; i < take.size(); ++i) {
+        Request *r = take[i];
+        pne_network *n = nullptr;
+        pne_status st = ust;
+        if (st == PNE_OK) {
+            const size_t ns = r->rank.size();
+            dptr.resize(ns);
+            const double *d = (const double *)((const char *)f.tensors + toff[i]);
+            for (size_t k = 0; k < ns; ++k) dptr[k] = d + r->site_off[k];
+            pne_network_desc dd = r->desc;
+            dd.site_data = dptr.data();
+            st = pne::network_create_on(sv->ctx, &dd, 1, s, &n);
+        }
+        if (st != PNE_OK) {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            fail_request(sv, r, st);
+            continue;
+        }
+        f.nets.push_back(n);
+        ok.push_back(r);
+    }
+    f.reqs = ok;
+    const Clock::time_point tp2 = Clock::now();
+    if (f.nets.empty()) return false;
+    pne_status st = pne::batch_create_on(sv->ctx, f.nets.data(), (int32_t)f.nets.size(), &ok[0]->opt, s, &f.batch);
+    const Clock::time_point tp3 = Clock::now();
+    if (st == PNE_OK) st = pne_batch_launch(f.batch);
+    if (st != PNE_OK) {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        for (Request *r : ok) fail_request(sv, r, st);
+        return false;
+    }
+    f.t_launch = Clock::now();
+    std::lock_guard<std::mutex> lk(sv->mu);
+    sv->prep_s += seconds_since(tp0, f.t_launch);
+    sv->upload_s += seconds_since(tp0, tp1);
+    sv->networks_s += seconds_since(tp1, tp2);
+    sv->batch_s += seconds_since(tp2, tp3);
+    sv->launch_s += seconds_since(tp3, f.t_launch);
+    return true;
+}
+
+// Admission and preparation: takes pending requests in arrival order while
+// their estimated bytes fit the budget and fewer than pipeline_depth
+// batches are in flight, prepares and launches them, and frees finished
+// batches whenever nothing is in flight.
+void worker_main(pne_server *sv) {
+    int launch_count = 0;
+    const int depth = sv->so.pipeline_depth;
     for (;;) {
         std::vector<Request *> take;
+        std::vector<InFlight> dead;
         {
             std::unique_lock<std::mutex> lk(sv->mu);
-            if (inflight.empty()) {
-                if (!graveyard.empty()) {
-                    lk.unlock();
-                    for (InFlight &f : graveyard) release(f);
-                    graveyard.clear();
-                    lk.lock();
+            int64_t seen = sv->finished_batches;
+            bool blocked = false;  // the oldest pending request waits for memory
+            for (;;) {
+                sv->cv.wait(lk, [&] {
+                    return (!blocked && (int)sv->inflight.size() < depth && !sv->pending.empty()) ||
+                           (sv->inflight.empty() && !sv->graveyard.empty()) ||
+                           (sv->stop && sv->pending.empty() && sv->inflight.empty()) ||
+                           sv->finished_batches != seen;
+                });
+                if (sv->finished_batches != seen) blocked = false;
+                seen = sv->finished_batches;
+                if (sv->inflight.empty() && !sv->graveyard.empty()) {
+                    dead.swap(sv->graveyard);
+                    break;
                 }
-                sv->cv.wait(lk, [&] { return sv->stop || !sv->pending.empty(); });
-                if (sv->stop && sv->pending.empty()) break;
-            }
-            const int depth = sv->so.pipeline_depth;
-            if ((int)inflight.size() < depth && !sv->pending.empty()) {
+                if (sv->stop && sv->pending.empty() && sv->inflight.empty()) break;
+                if ((int)sv->inflight.size() >= depth || sv->pending.empty()) continue;
                 const pne_options head = sv->pending.front()->opt;
                 size_t bytes = 0;
                 for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)take.size() < sv->so.max_batch;) {
                     Request *r = *it;
-                    const bool fits = sv->so.mem_budget == 0 || sv->in_use + bytes + r->est_bytes <= sv->so.mem_budget;
-                    if (same_options(r->opt, head) && (fits || (inflight.empty() && take.empty() && sv->in_use == 0))) {
+                    const bool fits =
+                        sv->so.mem_budget == 0 || sv->in_use + bytes + r->est_bytes <= sv->so.mem_budget;
+                    if (same_options(r->opt, head) &&
+                        (fits || (sv->inflight.empty() && take.empty() && sv->in_use == 0))) {
                         take.push_back(r);
                         bytes += r->est_bytes;
                         it = sv->pending.erase(it);
@@ -174,107 +324,51 @@ void worker_main(pne_server *sv) {
                         ++it;
                     }
                 }
-                sv->in_use += bytes;
+                if (!take.empty()) {
+                    sv->in_use += bytes;
+                    break;
+                }
+                blocked = true;  // nothing fits until a batch finishes and is freed
             }
+            if (dead.empty() && take.empty()) break;  // stopped and drained
         }
-        if (!take.empty()) {
-            const Clock::time_point tp0 = Clock::now();
-            InFlight f;
-            for (Request *r : take) f.bytes += r->est_bytes;
-            hipStream_t s = sv->streams[launch_count % 2];
-            // every request's tensors in one device allocation, uploaded by one
-            // copy from the server's pinned staging buffer on the batch stream
-            // (batch creation synchronises that stream before the staging
-            // buffer is reused)
-            std::vector<size_t> toff(take.size() + 1, 0);
-            for (size_t i = 0; i < take.size(); ++i) {
-                size_t b = 0;
-                for (const auto &v : take[i]->data) b += v.size() * sizeof(double);
-                toff[i + 1] = toff[i] + ((b + 255) & ~(size_t)255);
-            }
-            pne_status ust = PNE_OK;
-            if (hipMalloc(&f.tensors, std::max<size_t>(toff.back(), 256)) != hipSuccess) {
-                f.tensors = nullptr;
-                ust = PNE_ERR_OUT_OF_MEMORY;
-            } else if (sv->staging_bytes < toff.back()) {
-                if (sv->staging) (void)hipHostFree(sv->staging);
-                sv->staging = nullptr;
-                sv->staging_bytes = 0;
-                const size_t want = std::max(toff.back() + toff.back() / 2, (size_t)1 << 22);
-                if (hipHostMalloc(&sv->staging, want, hipHostMallocDefault) == hipSuccess)
-                    sv->staging_bytes = want;
-                else
-                    ust = PNE_ERR_OUT_OF_MEMORY;
-            }
-            if (ust == PNE_OK) {
-                for (size_t i = 0; i < take.size(); ++i) {
-                    char *dst = (char *)sv->staging + toff[i];
-                    for (const auto &v : take[i]->data) {
-                        std::memcpy(dst, v.data(), v.size() * sizeof(double));
-                        dst += v.size() * sizeof(double);
-                    }
-                }
-                if (hipMemcpyAsync(f.tensors, sv->staging, toff.back(), hipMemcpyHostToDevice, s) != hipSuccess)
-                    ust = PNE_ERR_DEVICE;
-            }
-            std::vector<Request *> ok;
-            std::vector<const double *> dptr;
-            for (size_t i = 0; i < take.size(); ++i) {
-                Request *r = take[i];
-                pne_network *n = nullptr;
-                pne_status st = ust;
-                if (st == PNE_OK) {
-                    dptr.resize(r->data.size());
-                    const double *d = (const double *)((const char *)f.tensors + toff[i]);
-                    for (size_t k = 0; k < r->data.size(); ++k) {
-                        dptr[k] = d;
-                        d += r->data[k].size();
-                    }
-                    pne_network_desc dd = r->desc;
-                    dd.site_data = dptr.data();
-                    st = pne::network_create_on(sv->ctx, &dd, 1, s, &n);
-                }
-                if (st != PNE_OK) {
-                    std::lock_guard<std::mutex> lk(sv->mu);
-                    fail_request(sv, r, st);
-                    continue;
-                }
-                f.nets.push_back(n);
-                ok.push_back(r);
-            }
-            f.reqs = ok;
-            if (!f.nets.empty()) {
-                pne_status st = pne::batch_create_on(sv->ctx, f.nets.data(), (int32_t)f.nets.size(), &ok[0]->opt, s,
-                                                     &f.batch);
-                if (st == PNE_OK) st = pne_batch_launch(f.batch);
-                if (st != PNE_OK) {
-                    {
-                        std::lock_guard<std::mutex> lk(sv->mu);
-                        for (Request *r : ok) fail_request(sv, r, st);
-                    }
-                    release(f);
-                    continue;
-                }
-                if (inflight.empty()) busy_since = Clock::now();
-                f.t_launch = Clock::now();
-                {
-                    std::lock_guard<std::mutex> lk(sv->mu);
-                    sv->prep_s += seconds_since(tp0, f.t_launch);
-                }
-                inflight.push_back(std::move(f));
-                ++launch_count;
-                {
-                    std::lock_guard<std::mutex> lk(sv->mu);
-                    ++sv->batches;
-                }
-                continue;  // admit more while below the pipeline depth
-            }
-            release(f);
+        if (!dead.empty()) {
+            for (InFlight &f : dead) release(sv, f);
             continue;
         }
-        if (inflight.empty()) continue;
-        InFlight f = std::move(inflight.front());
-        inflight.pop_front();
+        InFlight f;
+        hipStream_t s = sv->streams[launch_count % 2];
+        if (!prepare_and_launch(sv, take, s, f)) {
+            release(sv, f);
+            continue;
+        }
+        ++launch_count;
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            if (sv->inflight.empty()) sv->busy_since = f.t_launch;
+            sv->inflight.push_back(std::move(f));
+            ++sv->batches;
+        }
+        sv->cv_done.notify_all();
+    }
+    if (sv->up_stream) (void)hipStreamSynchronize(sv->up_stream);
+    if (sv->staging) (void)hipHostFree(sv->staging);
+    sv->staging = nullptr;
+}
+
+// Completion: waits for the oldest launched batch, hands its results to its
+// requests as soon as the device is done (while the worker prepares the next
+// batch), and moves the batch to the graveyard.
+void completer_main(pne_server *sv) {
+    for (;;) {
+        InFlight *fp = nullptr;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_done.wait(lk, [&] { return sv->stop_done || !sv->inflight.empty(); });
+            if (sv->inflight.empty()) break;  // stop_done
+            fp = &sv->inflight.front();       // stays put: the worker only appends
+        }
+        InFlight &f = *fp;
         const size_t n = f.reqs.size();
         std::vector<pne_result> res(n);
         for (size_t i = 0; i < n; ++i) {
@@ -294,16 +388,13 @@ void worker_main(pne_server *sv) {
                     res[i].status = st;  // device error: no result for anyone
                 finish_request(sv, f.reqs[i], res[i], t);
             }
-            if (inflight.empty()) sv->busy_s += seconds_since(busy_since, t);
+            sv->graveyard.push_back(std::move(sv->inflight.front()));
+            sv->inflight.pop_front();
+            if (sv->inflight.empty()) sv->busy_s += seconds_since(sv->busy_since, t);
+            ++sv->finished_batches;
         }
-        if (inflight.empty())
-            release(f);
-        else
-            graveyard.push_back(std::move(f));
+        sv->cv.notify_all();
     }
-    for (InFlight &f : graveyard) release(f);
-    if (sv->staging) (void)hipHostFree(sv->staging);
-    sv->staging = nullptr;
 }
 
 }  // namespace
@@ -329,12 +420,16 @@ pne_status pne_server_create(pne_ctx *ctx, const pne_server_options *opt, pne_se
     if (sv->so.max_batch <= 0) sv->so.max_batch = 1024;
     if (sv->so.pipeline_depth < 1) sv->so.pipeline_depth = 1;
     if (sv->so.pipeline_depth > 2) sv->so.pipeline_depth = 2;
-    for (hipStream_t *s : {&sv->streams[0], &sv->streams[1]})
+    for (hipStream_t *s : {&sv->streams[0], &sv->streams[1], &sv->up_stream})
         if (hipStreamCreateWithFlags(s, hipStreamNonBlocking) != hipSuccess) {
-            for (hipStream_t t : {sv->streams[0], sv->streams[1]})
+            for (hipStream_t t : {sv->streams[0], sv->streams[1], sv->up_stream})
                 if (t) (void)hipStreamDestroy(t);
             return PNE_ERR_DEVICE;
         }
+    if (hipEventCreateWithFlags(&sv->up_done, hipEventDisableTiming) != hipSuccess) {
+        for (hipStream_t t : {sv->streams[0], sv->streams[1], sv->up_stream}) (void)hipStreamDestroy(t);
+        return PNE_ERR_DEVICE;
+    }
     sv->t0 = Clock::now();
     pne_server *p = sv.release();
     int dev = 0;
@@ -342,6 +437,10 @@ pne_status pne_server_create(pne_ctx *ctx, const pne_server_options *opt, pne_se
     p->worker = std::thread([p, dev] {
         (void)hipSetDevice(dev);
         worker_main(p);
+    });
+    p->completer = std::thread([p, dev] {
+        (void)hipSetDevice(dev);
+        completer_main(p);
     });
     *out = p;
     return PNE_OK;
@@ -354,9 +453,16 @@ pne_status pne_server_destroy(pne_server *sv) {
         sv->stop = true;
     }
     sv->cv.notify_all();
-    if (sv->worker.joinable()) sv->worker.join();
-    for (hipStream_t t : {sv->streams[0], sv->streams[1]})
+    if (sv->worker.joinable()) sv->worker.join();  // every request finished, every batch freed
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop_done = true;
+    }
+    sv->cv_done.notify_all();
+    if (sv->completer.joinable()) sv->completer.join();
+    for (hipStream_t t : {sv->streams[0], sv->streams[1], sv->up_stream})
         if (t) (void)hipStreamDestroy(t);
+    if (sv->up_done) (void)hipEventDestroy(sv->up_done);
     delete sv;
     return PNE_OK;
 }
@@ -378,8 +484,7 @@ pne_status pne_submit(pne_server *sv, const pne_network_desc *d, const pne_optio
     r->bond_site.assign(d->bond_site, d->bond_site + 2 * (size_t)d->n_bonds);
     r->bond_leg.assign(d->bond_leg, d->bond_leg + 2 * (size_t)d->n_bonds);
     if (d->n_open > 0) r->open_leg.assign(d->open_leg, d->open_leg + 2 * (size_t)d->n_open);
-    r->data.resize(d->n_sites);
-    r->ptrs.resize(d->n_sites);
+    r->site_off.assign(d->n_sites + 1, 0);
     size_t slot = 0;
     int64_t n_open_values = 1;
     for (int s = 0; s < d->n_sites; ++s) {
@@ -389,11 +494,18 @@ pne_status pne_submit(pne_server *sv, const pne_network_desc *d, const pne_optio
             size *= (size_t)r->dims[slot + l];
         }
         if (!d->site_data[s]) return PNE_ERR_INVALID_ARG;
-        r->data[s].assign(d->site_data[s], d->site_data[s] + size);
-        for (double x : r->data[s])
-            if (!std::isfinite(x)) return PNE_ERR_INVALID_ARG;
-        r->ptrs[s] = r->data[s].data();
+        r->site_off[s + 1] = r->site_off[s] + size;
         slot += r->rank[s];
+    }
+    r->data.resize(r->site_off.back());
+    r->ptrs.resize(d->n_sites);
+    for (int s = 0; s < d->n_sites; ++s) {
+        const size_t size = r->site_off[s + 1] - r->site_off[s];
+        double *dst = r->data.data() + r->site_off[s];
+        std::memcpy(dst, d->site_data[s], size * sizeof(double));
+        for (size_t i = 0; i < size; ++i)
+            if (!std::isfinite(dst[i])) return PNE_ERR_INVALID_ARG;
+        r->ptrs[s] = dst;
     }
     for (int k = 0; k < d->n_open; ++k) {
         const int s = r->open_leg[2 * k], l = r->open_leg[2 * k + 1];
@@ -465,6 +577,10 @@ pne_status pne_server_get_stats(pne_server *sv, pne_server_stats *out) {
     out->busy_s = sv->busy_s;
     out->prep_s = sv->prep_s;
     out->wait_s = sv->wait_s;
+    out->upload_s = sv->upload_s;
+    out->networks_s = sv->networks_s;
+    out->batch_s = sv->batch_s;
+    out->launch_s = sv->launch_s;
     if (!sv->latencies.empty()) {
         std::vector<double> l = sv->latencies;
         std::sort(l.begin(), l.end());
@@ -483,6 +599,18 @@ pne_status pne_server_get_stats(pne_server *sv, pne_server_stats *out) {
         const double span = seconds_since(sv->t_first_submit, sv->t_last_done);
         out->networks_per_s = span > 0 ? (double)sv->completed / span : 0.0;
     }
+    return PNE_OK;
+}
+
+pne_status pne_server_completed(pne_server *sv, uint64_t *tickets, int32_t capacity, int32_t *n) {
+    if (!sv || !tickets || !n || capacity < 0 || !sv->so.completion_queue) return PNE_ERR_INVALID_ARG;
+    std::lock_guard<std::mutex> lk(sv->mu);
+    int32_t k = 0;
+    while (k < capacity && !sv->done_q.empty()) {
+        tickets[k++] = sv->done_q.front();
+        sv->done_q.pop_front();
+    }
+    *n = k;
     return PNE_OK;
 }
 

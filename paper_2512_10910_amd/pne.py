@@ -79,7 +79,8 @@ class ServerOptions(ctypes.Structure):
         ("mem_budget", ctypes.c_size_t),
         ("max_batch", ctypes.c_int32),
         ("pipeline_depth", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 4),
+        ("completion_queue", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -99,6 +100,10 @@ class ServerStats(ctypes.Structure):
         ("busy_s", ctypes.c_double),
         ("prep_s", ctypes.c_double),
         ("wait_s", ctypes.c_double),
+        ("upload_s", ctypes.c_double),
+        ("networks_s", ctypes.c_double),
+        ("batch_s", ctypes.c_double),
+        ("launch_s", ctypes.c_double),
     ]
 
 
@@ -149,6 +154,8 @@ _PROTOS = {
                                   ctypes.POINTER(ctypes.c_uint64)]),
     "pne_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ResultStruct)]),
     "pne_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
+    "pne_server_completed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
+                                            ctypes.POINTER(ctypes.c_int32)]),
     "pne_batch_kernel_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.POINTER(ctypes.c_int64), ctypes.c_int32,
                                               ctypes.c_int32]),
     "pne_batch_cluster_weights": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64,
@@ -528,11 +535,28 @@ class Batch:
 PNE_ERR_NOT_READY = -6
 
 
+class Prepared:
+    """A request marshalled for Server.submit: descriptor arrays with every
+    site tensor in one contiguous FP64 buffer, and its options."""
+
+    def __init__(self, obj, opt):
+        tensors, bonds, open_legs = _net_parts(obj)
+        flat = [np.ascontiguousarray(t, dtype=np.float64).reshape(-1) for t in tensors]
+        self.buf = np.concatenate(flat) if flat else np.zeros(0)
+        offs = np.concatenate([[0], np.cumsum([f.size for f in flat])])[:-1]
+        base = self.buf.ctypes.data
+        self.da = _DescArrays(tensors, bonds, open_legs, data_ptrs=[base + 8 * int(o) for o in offs])
+        self.opt = opt
+        self.open_shape = tuple(int(tensors[a].shape[b]) for a, b in np.asarray(open_legs).reshape(-1, 2)) \
+            if self.da.n_open else ()
+
+
 class Server:
     """Continuous-batching request server on a context (see pne_server_* in
     pne.h).  While it exists, its worker thread is the context's only user."""
 
-    def __init__(self, ctx: Context, mem_budget: int = 0, max_batch: int = 1024, pipeline_depth: int = 2):
+    def __init__(self, ctx: Context, mem_budget: int = 0, max_batch: int = 1024, pipeline_depth: int = 2,
+                 completion_queue: bool = False):
         self.ctx = ctx
         self.lib = ctx.lib
         so = ServerOptions()
@@ -540,22 +564,42 @@ class Server:
         so.mem_budget = int(mem_budget)
         so.max_batch = int(max_batch)
         so.pipeline_depth = int(pipeline_depth)
+        so.completion_queue = 1 if completion_queue else 0
+        self._cq = np.zeros(4096, np.uint64)
         h = ctypes.c_void_p()
         _check(self.lib, self.lib.pne_server_create(ctx.handle, ctypes.byref(so), ctypes.byref(h)))
         self.handle = h
         self._alive = True
         self._open_shape = {}
 
+    @staticmethod
+    def prepare(obj, K=6, precision="fp64", tol=1e-13, max_iter=500, persistent=True) -> "Prepared":
+        """Marshal a request once (descriptor arrays and options), so that
+        submit() only hands it to the server."""
+        return Prepared(obj, _options(K, precision, tol, max_iter, 0, False, persistent))
+
     def submit(self, obj, K=6, precision="fp64", tol=1e-13, max_iter=500, persistent=True) -> int:
-        tensors, bonds, open_legs = _net_parts(obj)
-        da = _DescArrays(tensors, bonds, open_legs)
-        o = _options(K, precision, tol, max_iter, 0, False, persistent)
+        """Queue a network (or a Prepared request, whose own options apply)."""
+        pr = obj if isinstance(obj, Prepared) else Server.prepare(obj, K, precision, tol, max_iter, persistent)
         t = ctypes.c_uint64(0)
-        _check(self.lib, self.lib.pne_submit(self.handle, ctypes.byref(da.desc), ctypes.byref(o), ctypes.byref(t)))
-        if da.n_open:
-            self._open_shape[t.value] = tuple(int(tensors[a].shape[b]) for a, b in
-                                              np.asarray(open_legs).reshape(-1, 2))
+        _check(self.lib, self.lib.pne_submit(self.handle, ctypes.byref(pr.da.desc), ctypes.byref(pr.opt),
+                                             ctypes.byref(t)))
+        if pr.open_shape:
+            self._open_shape[t.value] = pr.open_shape
         return int(t.value)
+
+    def completed(self) -> list:
+        """Tickets finished since the last call (servers made with
+        completion_queue=True), oldest first."""
+        out = []
+        n = ctypes.c_int32(0)
+        while True:
+            _check(self.lib, self.lib.pne_server_completed(
+                self.handle, self._cq.ctypes.data_as(ctypes.POINTER(ctypes.c_uint64)), len(self._cq),
+                ctypes.byref(n)))
+            out.extend(int(x) for x in self._cq[: n.value])
+            if n.value < len(self._cq):
+                return out
 
     def poll(self, ticket: int):
         """Result for `ticket`, or None while it is pending or running."""

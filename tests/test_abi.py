@@ -60,8 +60,9 @@ int main(void) {
   P(pne_result, log_abs) P(pne_result, bp_iters) P(pne_result, bp_residual)
   P(pne_result, n_config_terms) P(pne_result, open_values) P(pne_result, open_capacity)
   printf("sopt %zu\nsstat %zu\n", sizeof(pne_server_options), sizeof(pne_server_stats));
-  P(pne_server_options, max_batch) P(pne_server_options, pipeline_depth)
+  P(pne_server_options, max_batch) P(pne_server_options, pipeline_depth) P(pne_server_options, completion_queue)
   P(pne_server_stats, device_bytes_admitted) P(pne_server_stats, latency_p50_ms) P(pne_server_stats, busy_s)
+  P(pne_server_stats, launch_s)
   return 0;
 }
 ''')
@@ -90,11 +91,13 @@ def test_options_default(lib):
 def test_server_options_default_and_null_context(lib):
     so = B.ServerOptions()
     assert lib.pne_server_options_default(ctypes.byref(so)) == 0
-    assert so.mem_budget == 0 and so.max_batch == 1024 and so.pipeline_depth == 2
+    assert so.mem_budget == 0 and so.max_batch == 1024 and so.pipeline_depth == 2 and so.completion_queue == 0
     h = ctypes.c_void_p()
     assert lib.pne_server_create(None, ctypes.byref(so), ctypes.byref(h)) == B.PNE_ERR_INVALID_ARG
     assert lib.pne_submit(None, None, None, None) == B.PNE_ERR_INVALID_ARG
     assert lib.pne_poll(None, ctypes.c_uint64(1), None) == B.PNE_ERR_INVALID_ARG
+    n = ctypes.c_int32(0)
+    assert lib.pne_server_completed(None, None, 0, ctypes.byref(n)) == B.PNE_ERR_INVALID_ARG
 
 
 def test_context_without_gpu_reports_device_error(lib):

@@ -104,3 +104,25 @@ def test_submit_rejects_request_over_budget(pne):
     sv.close()
     ctx.close()
     assert math.isfinite(0.0)
+
+
+def test_completion_queue_with_prepared_requests(pne):
+    nets = [P.config4_request(i) for i in SMALL_REQUESTS[:8]]
+    alone = _alone(pne, nets, 6, "fp32")
+    ctx = pne.Context(0)
+    sv = pne.Server(ctx, completion_queue=True)
+    reqs = [pne.Server.prepare(n, K=6, precision="fp32") for n in nets]
+    tickets = [sv.submit(r) for r in reqs]
+    seen = []
+    t0 = time.time()
+    while len(seen) < len(tickets):
+        seen += sv.completed()
+        assert time.time() - t0 < 120, "server did not finish"
+        time.sleep(0.001)
+    assert sorted(seen) == sorted(tickets)
+    assert sv.completed() == []
+    for t, a in zip(tickets, alone):
+        r = sv.poll(t)
+        assert r.status == a.status and r.log_abs == a.log_abs
+    sv.close()
+    ctx.close()
