@@ -488,17 +488,29 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
     return res;
 }
 
-// Sites per register-path tile for (D, R), or 0 when the shape takes the LDS path.
-__host__ __device__ constexpr int reg_sites_per_tile(int D, int R) {
-    return (D < 2 || D > 6 || R < 1 || R > 6 || ipow(D, R - reg_trailing(D, R)) > 16)
+// Sites per register-path tile for (D, R) with at most `max_lead` values per
+// lane, or 0 when the shape takes the LDS path.
+__host__ __device__ constexpr int reg_sites_per_tile(int D, int R, int max_lead = 16) {
+    return (D < 2 || D > 6 || R < 1 || R > 6 || ipow(D, R - reg_trailing(D, R)) > max_lead)
                ? 0
                : reg_rows(D, R) * (64 >> ((D <= 2 ? 1 : (D <= 4 ? 2 : 3)) * reg_trailing(D, R)));
+}
+// The per-launch sweep also keeps rank-4 sites of D = 5 and 6 and rank-6
+// sites of D = 3 in registers (25, 36 and 27 values per lane, one site per
+// wavefront): the wide shapes, swept by their own kernel.
+__host__ __device__ constexpr bool wide_shape(int D, int R) {
+    return (R == 4 && (D == 5 || D == 6)) || (R == 6 && D == 3);
 }
 
 // One Jacobi sweep: sweep reads message buffer sweep&1 and writes the other.
 // Tiles of networks that stopped exit at once; the per-network bookkeeping of
 // the previous sweep is folded into the stop test, so one launch is one sweep
 // and no block waits for, or fences against, any other block.
+//
+// WIDE: the kernel for register tiles of the wide shapes (wide_shape), kept
+// apart so that their registers do not lower the occupancy of every other
+// tile.
+template <bool WIDE>
 __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restrict__ sites,
                                                          const BpTile *__restrict__ tiles,
                                                          const int *__restrict__ tile_sites,
@@ -518,6 +530,21 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
     if (s_skip) return;
     const double *min = (sweep & 1) ? msg1 : msg0;
     double *mout = (sweep & 1) ? msg0 : msg1;
+    if (WIDE) {
+        if (threadIdx.x == 0) sh.bad = 0;
+        double res = 0.0;
+        switch (tl.dc * 8 + tl.rank) {
+            case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
+            case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
+            case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
+            default: sh.bad = 1; break;  // not a wide shape: never scheduled here
+        }
+        if (threadIdx.x == 0) {
+            atomicMax(&ns->res_acc[sweep % 3], (unsigned long long)__double_as_longlong(res));
+            if (sh.bad) atomicMin(&ns->status, -4);
+        }
+        return;
+    }
     if (tl.reg) {
         double res = -1.0;
         if (threadIdx.x == 0) sh.bad = 0;
@@ -584,6 +611,9 @@ __global__ void k_bp_close(NetState *st, int n_nets, int k_last, double tol) {
 int bp_tile_threads() { return kBpThreads; }
 
 int bp_reg_sites_per_tile(int D, int R) { return reg_sites_per_tile(D, R); }
+int bp_sweep_reg_sites_per_tile(int D, int R) {
+    return wide_shape(D, R) ? reg_sites_per_tile(D, R, 36) : reg_sites_per_tile(D, R);
+}
 
 size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int max_dim) {
     size_t red = (size_t)n_sites * (size_t)max_dim;
@@ -600,8 +630,13 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
 }
 
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s) {
-    hipLaunchKernelGGL(k_bp_sweep, dim3(b.n_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites, b.tiles,
-                       b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter);
+    if (b.n_narrow_tiles > 0)
+        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites,
+                           b.tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter);
+    if (b.n_tiles > b.n_narrow_tiles)
+        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(b.n_tiles - b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s,
+                           b.sites, b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol,
+                           max_iter);
     return hipGetLastError();
 }
 

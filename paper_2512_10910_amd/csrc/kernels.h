@@ -12,8 +12,11 @@ struct DeviceBatch {
     // tables
     const SiteRec *sites = nullptr;
     int n_sites = 0;
-    const BpTile *tiles = nullptr;      // tiles swept by the per-sweep kernel
+    const BpTile *tiles = nullptr;      // tiles swept by the per-sweep kernels
     int n_tiles = 0;
+    int n_narrow_tiles = 0;             // tiles[0, n_narrow_tiles): every shape but the wide ones;
+                                        // the rest: register tiles of the wide shapes (rank 4 at
+                                        // D = 5, 6; rank 6 at D = 3)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel
     int n_fused = 0;
@@ -68,6 +71,9 @@ enum KernelId { KID_INIT = 0, KID_SWEEP, KID_CLOSE, KID_FUSED, KID_GAUGE, KID_RE
 int bp_tile_threads();
 // sites per tile on the register path for uniform leg dimension D and rank R (0: LDS path)
 int bp_reg_sites_per_tile(int D, int R);
+// sites per register tile of the per-launch sweep (0: LDS path); a superset
+// of the shapes bp_reg_sites_per_tile accepts
+int bp_sweep_reg_sites_per_tile(int D, int R);
 size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int max_dim);
 
 hipError_t launch_init(const DeviceBatch &b, hipStream_t s);

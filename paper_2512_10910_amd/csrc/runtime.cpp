@@ -764,7 +764,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<FusedNet> fused;
     std::vector<FusedGroup> fgroups;
     std::vector<int> fsite_list;
-    std::vector<BpTile> loop_tiles;
+    std::vector<BpTile> loop_tiles, wide_tiles;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
     size_t bp_lds = 0, fused_lds = 0;
@@ -799,9 +799,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             for (int l = 0; l < r0.rank; ++l)
                 if (r0.dim[l] != maxd) dc = 0;
             if (dc < 2 || dc > 6) dc = 0;
-            const int reg_spt = dc ? bp_reg_sites_per_tile(dc, r0.rank) : 0;
+            const int reg_spt = dc ? bp_sweep_reg_sites_per_tile(dc, r0.rank) : 0;
             if (reg_spt > 0) cap = reg_spt;
-            else all_reg = false;
+            if (!(dc && bp_reg_sites_per_tile(dc, r0.rank) > 0)) all_reg = false;  // persistent tiles
             if (!reg_spt && per > 150 * 1024 / 8)
                 return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
             for (size_t k = 0; k < kv.second.size(); k += cap) {
@@ -921,7 +921,10 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             net_fused[i] = 1;
             fused_lds = std::max(fused_lds, pneed * 8);
         } else {
-            loop_tiles.insert(loop_tiles.end(), tiles.begin() + tile_begin, tiles.end());
+            for (size_t t = tile_begin; t < tiles.size(); ++t) {
+                const bool wide = tiles[t].reg && bp_reg_sites_per_tile(tiles[t].dc, tiles[t].rank) == 0;
+                (wide ? wide_tiles : loop_tiles).push_back(tiles[t]);
+            }
             bp_lds = std::max(bp_lds, net_lds);
         }
     }
@@ -1081,6 +1084,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     ArenaPlan ap;
 #define UP(vec, field) ap.upload(vec, &db.field)
     UP(sites, sites);
+    const int n_narrow = (int)loop_tiles.size();
+    loop_tiles.insert(loop_tiles.end(), wide_tiles.begin(), wide_tiles.end());
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
     UP(fused, fused);
@@ -1134,6 +1139,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
 #undef UP
     db.n_sites = (int)sites.size();
     db.n_tiles = (int)loop_tiles.size();
+    db.n_narrow_tiles = n_narrow;
     db.n_fused = (int)fused.size();
     db.fused_lds = fused_lds;
     db.n_nets = n;

@@ -158,6 +158,9 @@ SMALL = [
     ("ising3d_3", lambda: P.ising_3d(3, 0.2), 6),
     ("mixed_dims", lambda: P.grid_from_tensors((3, 3), lambda s, r, o: np.random.default_rng(s).random(
         (2,) * r) + 0.5), 8),
+    # rank-4 sites of D = 5 and 6: the per-launch sweep's wide register tiles
+    ("rand2d_4x4_D5", lambda: P.random_2d(4, 4, 5, "uniform01", seed=13), 6),
+    ("rand2d_6x5_D6_normal", lambda: P.random_2d(6, 5, 6, "normal", seed=14), 6),
 ]
 
 
@@ -448,3 +451,4 @@ def test_two_outstanding_launches(ctx):
     assert pb.kernel_times()["combine"][1] == 1
     pb.wait_arrays()
     assert pb.kernel_times()["combine"][1] == 2
+
