@@ -440,42 +440,54 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
         }
     }
     wave_sync();
-    // normalisation items: (tile k, site j in the tile, leg l)
-    double res = 0.0;
-    for (int n = lane; n < kNT * SPW * R; n += 64) {
-        const int ik = n / (SPW * R);
-        const int irem = n - ik * (SPW * R);
+    // Normalisation, element-parallel: item = (tile k, site j in the tile,
+    // leg l), its D entries on D of a group of P lanes; the norm, the sign
+    // and the residual are group reductions (quad permutations).
+    constexpr int NI = kNT * SPW * R;
+    constexpr int IPP = 64 / P;  // items per pass
+    double res = 0.0;            // this lane's part; the caller reduces over the wave
+#pragma unroll
+    for (int pass = 0; pass < (NI + IPP - 1) / IPP; ++pass) {
+        const int item = pass * IPP + lane / P;
+        const int e = lane & (P - 1);
+        const int ik = item / (SPW * R);
+        const int irem = item - ik * (SPW * R);
         const int ij = irem / R;
         const int il = irem - ij * R;
-        const int ipos = base_pos + ik * SPW + ij;
-        if (ipos >= n_in_group) continue;
-        const int site = int_at(L.list, gl_off + ipos);
-        const int idst = int_at(L.dst, site * kMaxRank + il);
-        const double *raw = out + (ik * SPW + ij) * ND + il * D;
-        double n2 = 0.0, sum = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            n2 = fma(raw[i], raw[i], n2);
-            sum += raw[i];
+        const bool live = item < NI && base_pos + ik * SPW + ij < n_in_group;  // uniform over the group
+        const bool el = live && e < D;
+        double x = 0.0, old = 0.0;
+        int idst = 0;
+        if (live) {
+            const int site = int_at(L.list, gl_off + base_pos + ik * SPW + ij);
+            idst = int_at(L.dst, site * kMaxRank + il) + e;
+            if (el) {
+                x = out[(ik * SPW + ij) * ND + il * D + e];
+                old = p_lds[mi + idst];
+            }
+        }
+        double n2 = x * x, sum = x;
+        n2 += dpp_f64<kDppXor1>(n2);
+        sum += dpp_f64<kDppXor1>(sum);
+        if (P == 4) {
+            n2 += dpp_f64<kDppXor2>(n2);
+            sum += dpp_f64<kDppXor2>(sum);
         }
         const double nrm = sqrt(n2);
-        if (!(nrm > 0.0) || !isfinite(nrm)) {
-            *bad = 1;
-            continue;
-        }
+        const bool ok = nrm > 0.0 && isfinite(nrm);
+        if (live && e == 0 && !ok) *bad = 1;
         const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
-        double d1 = 0.0, d2 = 0.0;
-#pragma unroll
-        for (int i = 0; i < D; ++i) {
-            const double v = raw[i] * inv;
-            const double old = p_lds[mi + idst + i];
-            d1 = fmax(d1, fabs(v - old));
-            d2 = fmax(d2, fabs(v + old));
-            p_lds[mo + idst + i] = v;
+        const double v = x * inv;
+        double d1 = el ? fabs(v - old) : 0.0, d2 = el ? fabs(v + old) : 0.0;
+        d1 = fmax(d1, dpp_f64<kDppXor1>(d1));
+        d2 = fmax(d2, dpp_f64<kDppXor1>(d2));
+        if (P == 4) {
+            d1 = fmax(d1, dpp_f64<kDppXor2>(d1));
+            d2 = fmax(d2, dpp_f64<kDppXor2>(d2));
         }
-        res = fmax(res, fmin(d1, d2));
+        if (el && ok) p_lds[mo + idst] = v;
+        if (live && ok) res = fmax(res, fmin(d1, d2));
     }
-    res = wave_max_p(res);
     wave_sync();
     return res;
 }
@@ -722,7 +734,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     const FusedNet fn = fnets[blockIdx.x];
     NetState *ns = st + fn.net;
     const unsigned long long t_start = wall_clock64();
-    __shared__ double s_res[kPWaves];
+    __shared__ double s_res[2 * kPWaves];
     __shared__ int s_bad;
     __shared__ int s_status;  // the network's status this run (lowered with LDS atomics)
     const int tid = threadIdx.x;
@@ -811,12 +823,16 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
                 wres = fmax(wres, tr);
             }
         }
-        if ((tid & 63) == 0) s_res[wave] = wres;
+        // the tiles return per-lane parts; one wave reduction per step.  The
+        // two residual slots alternate, so a slot is rewritten only after a
+        // later barrier that every wave reaches after reading it.
+        wres = wave_max_p(wres);
+        double *slot = s_res + (sweep & 1) * kPWaves;
+        if ((tid & 63) == 0) slot[wave] = wres;
         __syncthreads();
-        r = s_res[0];
-        for (int w = 1; w < kPWaves; ++w) r = fmax(r, s_res[w]);
-        const int bad = s_bad;
-        __syncthreads();
+        r = slot[0];
+        for (int w = 1; w < kPWaves; ++w) r = fmax(r, slot[w]);
+        const int bad = s_bad;  // only ever set: no barrier needed before it changes again
         if (bad) break;
         // red-black: both colours' latest updates must be within tol
         if (r <= tol && (!rb || (sweep > 0 && r_prev <= tol))) {
