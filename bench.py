@@ -63,17 +63,18 @@ def site_colours(net):
     return col
 
 
-def bp_bytes(net, steps: int, messages_in_lds: bool = False) -> int:
+def bp_bytes(net, steps: int, messages_in_lds: bool = False, red_black: bool = True) -> int:
     """Algorithmic bytes of the BP of one network over `steps` steps: network
-    sweeps under Jacobi; under red-black, step k updates the sites of colour
-    k mod 2 only.  Per updated site: the FP64 tensor read once, and, when the
-    messages live in memory, every incoming message read twice (contraction
-    and residual) and every outgoing message written once.  With
-    messages_in_lds (the persistent block keeps its network's messages in
-    LDS) only the tensors stream, plus one write of the final messages."""
+    sweeps under Jacobi; under red-black (bipartite networks in the
+    persistent kernel), step k updates the sites of colour k mod 2 only.  Per
+    updated site: the FP64 tensor read once, and, when the messages live in
+    memory, every incoming message read twice (contraction and residual) and
+    every outgoing message written once.  With messages_in_lds (the
+    persistent block keeps its network's messages in LDS) only the tensors
+    stream, plus one write of the final messages."""
     msg = 0 if messages_in_lds else 3 * 8
     per = [8 * t.size + msg * sum(t.shape) for t in net.tensors]
-    col = site_colours(net) if len(net.tensors) > 1 else None
+    col = site_colours(net) if (red_black and len(net.tensors) > 1) else None
     if col is None:
         b = steps * sum(per)
     else:
@@ -231,6 +232,98 @@ def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth
     }
 
 
+def kernel_bytes(pne, nets_in, paths, iters, n_clusters, K: int, slice_bytes: int) -> dict:
+    """Algorithmic HBM bytes per kernel for one run of a batch, each network's
+    share going to the kernel that runs that step of it (paths: the
+    library's PATH_* bits per network)."""
+    alg = {}
+
+    def add(k, v):
+        alg[k] = alg.get(k, 0) + v
+
+    for net, path, s, nc in zip(nets_in, paths, iters, n_clusters):
+        pers = bool(path & pne.PATH_PERSISTENT)
+        cl = cluster_bytes(pne, net, K, slice_bytes) - 8 * nc
+        if pers:
+            add("bp_persistent", bp_bytes(net, s, True))
+        else:
+            add("bp_sweep", bp_bytes(net, s, False, red_black=False))
+        if path & pne.PATH_BLOCK_GAUGE:
+            add("bp_persistent", regauge_bytes(net, slice_bytes, True))
+        else:
+            add("regauge", regauge_bytes(net, slice_bytes, False))
+        if path & pne.PATH_BLOCK_TERMS:
+            add("bp_persistent", cl + 8 * nc)
+        else:
+            add("clusters", cl)
+            add("combine", 8 * nc)
+    return alg
+
+
+def workloads_bench(pne, P, steps: int):
+    """The other workloads at batch scale, one JSON line each: step time,
+    networks/s, per-kernel device time (HIP events around every launch) with
+    its algorithmic HBM bytes and roofline fraction, and a sampled check
+    against the FP64 oracle (skipped for the 32x32 D=6 networks, whose oracle
+    takes minutes; the parity tests cover them)."""
+    import torch
+
+    import oracle as O
+
+    cases = [
+        ("4x4 Ising, beta_i = 0.44(1 + 0.01 u_i), K=4, fp64",
+         lambda: [P.ising_2d(4, 4, float(b)) for b in P.config1_betas(65536)], 4, "fp64", True),
+        ("6x6x6 Ising, beta in {0.18, 0.2217, 0.26} x 1365 each, K=6, fp32",
+         lambda: [P.config3_ising_network(b) for b in (0.18, 0.2217, 0.26) for _ in range(1365)], 6, "fp32", True),
+        ("12x12 AKLT double layer, random bond gauge per copy (seed 3000+i), K=8, fp32",
+         lambda: [P.config3_aklt_network(gauge_seed=3000 + i) for i in range(4096)], 8, "fp32", True),
+        ("32x32 D=6 U[0,1], two open dim-2 legs d = 1..8 apart, x16 each, K=8, fp32",
+         lambda: [P.config5_network(d) for d in range(1, 9)] * 16, 8, "fp32", False),
+    ]
+    sb = {"fp64": 8, "fp32": 4, "bf16": 2}
+    for label, make, K, prec, check in cases:
+        nets_in = make()
+        ctx = pne.Context(0)
+        nets = [ctx.network(n) for n in nets_in]
+        b = ctx.batch(nets, K=K, precision=prec, profile=True)
+        b.run_arrays()
+        b.kernel_times(reset=True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = b.run_arrays()
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3 / steps
+        kt = b.kernel_times(reset=True)
+        iters = [int(x) for x in res["bp_iters"]]
+        alg = kernel_bytes(pne, nets_in, b.paths(), iters, [int(x) for x in res["n_cluster_terms"]], K,
+                           sb[prec])
+        nclu = int(res["n_cluster_terms"].sum())
+        kernels = {}
+        for k, (tms, cnt) in kt.items():
+            if cnt == 0:
+                continue
+            d = {"ms_per_step": round(tms / steps, 4), "launches_per_step": cnt / steps}
+            if k in alg and tms > 0:
+                gbs = alg[k] / (tms / steps * 1e-3) / 1e9
+                d.update({"alg_bytes_per_step": alg[k], "achieved_GBps": round(gbs, 1),
+                          "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+            kernels[k] = d
+        out = {"workload": label, "networks": len(nets), "ms_per_step": round(ms, 4),
+               "networks_per_s": round(len(nets) / (ms * 1e-3), 1), "precision": prec, "K": K,
+               "bp_iters_mean": float(np.mean(iters)), "status_min": int(res["status"].min()),
+               "cluster_terms_per_step": nclu, "kernels": kernels}
+        if check:
+            ref = O.pne_contract(nets_in[0], K)
+            out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - ref.log_abs) / max(
+                1.0, abs(ref.log_abs))
+        print(json.dumps(out), flush=True)
+        b.close()
+        for n in nets:
+            n.close()
+        ctx.close()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +340,8 @@ def main():
     ap.add_argument("--serving", type=int, default=1024, metavar="N",
                     help="also run the serving loop on N requests (Poisson arrivals at 0.7 x capacity); 0: skip")
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
+    ap.add_argument("--workloads", action="store_true",
+                    help="instead: the other workloads at batch scale with per-kernel rooflines")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, run plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -264,6 +359,10 @@ def main():
     if not torch.cuda.is_available():
         print("bench.py: no GPU visible", file=sys.stderr)
         sys.exit(1)
+
+    if args.workloads:
+        workloads_bench(pne, P, max(1, min(args.steps, 5)))
+        return
 
     if args.copy_calibration:
         # a plain copy kernel of known size: reads and writes exactly MIB MiB
@@ -327,27 +426,27 @@ def main():
     nets_per_s = n_nets / (ms_step * 1e-3)
     print(f"bench: {ms_step:.3f} ms/step, {nets_per_s:.1f} networks/s", file=sys.stderr, flush=True)
 
-    # roofline of the dominant kernel
+    # roofline of the dominant kernel: algorithmic bytes of the steps it ran
     sweeps = [int(x) for x in results["bp_iters"]]
-    # every network's BP ran in a persistent block, messages in LDS
-    in_lds = kt_all["bp_persistent"][0] > 0 and kt_all["bp_sweep"][0] == 0
-    bytes_sweep = sum(bp_bytes(n, s, in_lds) for s, n in zip(sweeps, nets_in))
-    bytes_regauge = sum(regauge_bytes(n, slice_bytes, in_lds) for n in nets_in)
+    paths = batch.paths()
+    ncl = [int(x) for x in results["n_cluster_terms"]]
+    alg = kernel_bytes(pne, nets_in, paths, sweeps, ncl, args.K, slice_bytes)
+    in_lds = bool((paths & pne.PATH_PERSISTENT).all())
     dom_ms = sum(kt[k][0] for k in timed_kernels) / args.steps
     dom_launches = sum(kt[k][1] for k in timed_kernels)
+    alg_bytes = sum(alg.get(k, 0) for k in timed_kernels) or None
     alg_split = {}
-    if dom in bp_kernels:
-        # every BP kernel of the step together performs all network-sweeps
-        alg_split["bp"] = bytes_sweep
-        if phases["regauge_mean"] > 0 and kt_all["regauge"][0] < 0.02 * kt_all["bp_persistent"][0]:
-            # the persistent blocks also built the gauge and slices
-            alg_split["gauge_slices"] = bytes_regauge
-        if kt_all["clusters"][0] < 0.02 * kt_all["bp_persistent"][0]:
-            # ... and contracted the clusters and summed the terms
-            alg_split["clusters_sum"] = sum(cluster_bytes(pne, n, args.K, slice_bytes) for n in nets_in)
-    elif dom == "regauge":
-        alg_split["gauge_slices"] = bytes_regauge
-    alg_bytes = sum(alg_split.values()) if alg_split else None
+    if "bp_persistent" in timed_kernels:
+        # the persistent kernel's share: BP, in-block gauge and slices, in-block terms
+        for net, pth, st, nc in zip(nets_in, paths, sweeps, ncl):
+            if not pth & pne.PATH_PERSISTENT:
+                continue
+            alg_split["bp"] = alg_split.get("bp", 0) + bp_bytes(net, st, True)
+            if pth & pne.PATH_BLOCK_GAUGE:
+                alg_split["gauge_slices"] = alg_split.get("gauge_slices", 0) + regauge_bytes(net, slice_bytes, True)
+            if pth & pne.PATH_BLOCK_TERMS:
+                alg_split["clusters_sum"] = alg_split.get("clusters_sum", 0) + cluster_bytes(pne, net, args.K,
+                                                                                             slice_bytes)
     achieved = None
     if alg_bytes is not None and dom_ms > 0:
         # bytes per launch / average launch duration == bytes per step / time per step

@@ -136,6 +136,7 @@ pne_status pne_options_default(pne_options *opt);
  * hipStream_t to enqueue on (NULL: the context creates its own stream).
  * Returns PNE_ERR_DEVICE if no device is usable. */
 pne_status pne_ctx_create(int device, size_t mem_budget_bytes, void *hip_stream, pne_ctx **out);
+/* Servers, batches and networks made on ctx must be destroyed first. */
 pne_status pne_ctx_destroy(pne_ctx *ctx);
 /* Message of the last failing call on ctx (never NULL; valid until the next call). */
 const char *pne_last_error(const pne_ctx *ctx);
@@ -214,6 +215,16 @@ pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *l
  * out[5] span to the last block's end.  Writes n entries (zeros when the
  * batch has no persistent networks). */
 pne_status pne_batch_phase_times(pne_batch *batch, double *out, int32_t n);
+
+/* Where each network of the batch runs (fixed at pne_batch_create): out[i]
+ * has bit 0 set when its BP runs in a persistent block, bit 1 when that
+ * block also builds its gauge and slices, bit 2 when it also contracts the
+ * clusters and sums the terms (otherwise those steps have launches of their
+ * own).  n must be the batch's network count. */
+#define PNE_PATH_PERSISTENT 1
+#define PNE_PATH_BLOCK_GAUGE 2
+#define PNE_PATH_BLOCK_TERMS 4
+pne_status pne_batch_paths(pne_batch *batch, int32_t *out, int32_t n);
 
 /* After pne_batch_wait: copy network i's final BP messages to host.  For
  * every bond b, out holds the message arriving at the bond's first site

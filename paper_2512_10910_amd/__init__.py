@@ -18,5 +18,8 @@ from .pne import (  # noqa: F401
     enumerate_clusters,
     load_library,
     LIB_PATH,
+    PATH_BLOCK_GAUGE,
+    PATH_BLOCK_TERMS,
+    PATH_PERSISTENT,
     PRECISIONS,
 )

@@ -27,6 +27,7 @@ namespace {
 
 constexpr int kPThreads = 512;
 constexpr int kPWaves = kPThreads / 64;
+constexpr int kPSmallThreads = 128;
 // tiles in flight per wavefront for a shape with nl register values per tile
 __host__ __device__ constexpr int tiles_in_flight(int nl) { return nl <= 4 ? 2 : 1; }
 
@@ -707,22 +708,24 @@ __device__ __attribute__((noinline)) void p_regauge_dpp(const PLayout L, int cnt
 
 // The scalar and cycle clusters of one network, one instance per thread of
 // the block (kept out of line: its registers stay apart from the BP loop's).
-template <typename S>
+template <typename S, int NT>
 __device__ __attribute__((noinline)) void p_clusters(int class_begin, int n_classes, int64_t w_base,
                                                      int64_t slice_base, const ClassDesc *__restrict__ classes,
                                                      const S *__restrict__ slices, double *__restrict__ w) {
     for (int c = class_begin; c < class_begin + n_classes; ++c) {
         const ClassDesc cd = classes[c];
         const int per = cd.loop_e ? cd.n_verts : cd.n_steps;
-        for (int k = threadIdx.x; k < cd.n_inst; k += kPThreads) {
+        for (int k = threadIdx.x; k < cd.n_inst; k += NT) {
             const InstStep *rec = cd.tab + (int64_t)k * per;
             dev::gst(w + w_base + dev::gld(cd.iw + k), (double)dev::fast_term<S>(cd, rec, slices, slice_base));
         }
     }
 }
 
-template <typename S>
-__global__ void __launch_bounds__(kPThreads) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// NT threads per block: kPThreads for most networks, kPSmallThreads for
+// networks of at most kPSmallSites sites (more of them share a CU).
+template <typename S, int NT>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
 k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict__ groups,
                 const int *__restrict__ site_list, const SiteRec *__restrict__ sites, double *msg0, NetState *st,
                 double tol, int max_iter, S *__restrict__ slices, double *__restrict__ site_log,
@@ -731,10 +734,11 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
                 const CombineRec *__restrict__ crecs, const GeoRec *__restrict__ geos,
                 const Bucket *__restrict__ buckets, const int *__restrict__ pair_a, const int *__restrict__ pair_b,
                 const PairCat *__restrict__ cats, NetResult *__restrict__ results) {
+    constexpr int NW = NT / 64;
     const FusedNet fn = fnets[blockIdx.x];
     NetState *ns = st + fn.net;
     const unsigned long long t_start = wall_clock64();
-    __shared__ double s_res[2 * kPWaves];
+    __shared__ double s_res[2 * NW];
     __shared__ int s_bad;
     __shared__ int s_status;  // the network's status this run (lowered with LDS atomics)
     const int tid = threadIdx.x;
@@ -753,7 +757,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     L.scr = L.soff + ns_;
     const int scr = L.scr + wave * fn.scratch;
     // uniform initial messages 1/sqrt(d): each site fills its incoming slots
-    for (int s = tid; s < ns_; s += kPThreads) {
+    for (int s = tid; s < ns_; s += NT) {
         const SiteRec &r = sites[fn.site_base + s];
         for (int l = 0; l < r.rank; ++l) {
             const double v = 1.0 / sqrt((double)r.dim[l]);
@@ -791,9 +795,9 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
             if (rb && gr.color != (sweep & 1)) continue;
             const int per_chunk = gr.nt * gr.spw;
             const int nchunks = (gr.n_sites + per_chunk - 1) / per_chunk;
-            const int c0 = ((wave - cbase) % kPWaves + kPWaves) % kPWaves;
+            const int c0 = ((wave - cbase) % NW + NW) % NW;
             cbase += nchunks;
-            for (int c = c0; c < nchunks; c += kPWaves) {
+            for (int c = c0; c < nchunks; c += NW) {
                 double tr = 0.0;
                 switch (gr.dc * 8 + gr.rank) {
                     case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
@@ -827,11 +831,11 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         // two residual slots alternate, so a slot is rewritten only after a
         // later barrier that every wave reaches after reading it.
         wres = wave_max_p(wres);
-        double *slot = s_res + (sweep & 1) * kPWaves;
+        double *slot = s_res + (sweep & 1) * NW;
         if ((tid & 63) == 0) slot[wave] = wres;
         __syncthreads();
         r = slot[0];
-        for (int w = 1; w < kPWaves; ++w) r = fmax(r, slot[w]);
+        for (int w = 1; w < NW; ++w) r = fmax(r, slot[w]);
         const int bad = s_bad;  // only ever set: no barrier needed before it changes again
         if (bad) break;
         // red-black: both colours' latest updates must be within tol
@@ -843,7 +847,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     }
     const int last = sweep < max_iter ? sweep : max_iter - 1;
     const int fin = rb ? L.b0 : ((last & 1) ? L.b0 : L.b1);
-    for (int e = tid; e < fn.msg_size; e += kPThreads) msg0[fn.msg_base + e] = p_lds[fin + e];
+    for (int e = tid; e < fn.msg_size; e += NT) msg0[fn.msg_base + e] = p_lds[fin + e];
     if (tid == 0) {
         ns->stop = last;
         ns->iters = last + 1;
@@ -867,9 +871,9 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         const FusedGroup gr = groups[fn.group_begin + g];
         const int spt = regauge_call_sites(gr.dc, gr.rank);
         const int ntl = (gr.n_sites + spt - 1) / spt;
-        const int t0 = ((wave - tbase) % kPWaves + kPWaves) % kPWaves;
+        const int t0 = ((wave - tbase) % NW + NW) % NW;
         tbase += ntl;
-        for (int t = t0; t < ntl; t += kPWaves) {
+        for (int t = t0; t < ntl; t += NW) {
             const int first = gr.list_off + t * spt;
             const int cnt = min(spt, gr.n_sites - t * spt);
 #define PNE_PRG(D_, R_)                                                                                    \
@@ -901,11 +905,11 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     if (!fn.cl_fused) return;
     // Clusters of the network (scalar and cycle classes: one instance per
     // thread, slices just written by this block) and its FP64 term sum.
-    p_clusters<S>(fn.class_begin, fn.n_classes, fn.w_base, reinterpret_cast<const int64_t *>(p_lds + L.soff)[0],
+    p_clusters<S, NT>(fn.class_begin, fn.n_classes, fn.w_base, reinterpret_cast<const int64_t *>(p_lds + L.soff)[0],
                   classes, slices, w);
     __syncthreads();
     const CombineRec cr = crecs[fn.net];
-    dev::combine_closed<kPThreads>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
+    dev::combine_closed<NT>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
                                    s_status, results, p_lds + L.scr);
 }
 
@@ -913,9 +917,10 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
 
 // doubles of dynamic LDS for a persistent block (see PLayout)
 size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers) {
+    const int waves = n_sites <= kPSmallSites ? kPSmallThreads / 64 : kPWaves;
     return (size_t)n_buffers * msg_size + (size_t)n_sites + (size_t)(n_sites + 1) / 2 +
            (size_t)(n_sites * kMaxRank + 1) / 2 + 2 * (size_t)((n_sites + 1) / 2) + (size_t)n_sites +
-           (size_t)kPWaves * scratch_per_wave;
+           (size_t)waves * scratch_per_wave;
 }
 
 // Shapes whose gauge and slices the persistent block builds itself: the DPP
@@ -949,29 +954,36 @@ int bp_persistent_scratch(int spw, int rank, int dim) {
     return bp_persistent_tiles_in_flight(dim, rank) * spw * rank * dim;
 }
 
-hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
-    if (!b.n_fused) return hipSuccess;
+template <int NT>
+void launch_fused_nt(const DeviceBatch &b, const FusedNet *fused, int n, size_t lds, double tol, int max_iter,
+                     hipStream_t s) {
     switch (b.precision) {
         case 0:
-            hipLaunchKernelGGL(k_bp_persistent<double>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
-                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
-                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w,
-                               b.crec, b.geos, b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
+            hipLaunchKernelGGL((k_bp_persistent<double, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
+                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
+                               b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         case 1:
-            hipLaunchKernelGGL(k_bp_persistent<float>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
-                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
-                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w,
-                               b.crec, b.geos, b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
+            hipLaunchKernelGGL((k_bp_persistent<float, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
+                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
+                               b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         default:
-            hipLaunchKernelGGL(k_bp_persistent<uint16_t>, dim3(b.n_fused), dim3(kPThreads), b.fused_lds, s, b.fused,
-                               b.fgroups, b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter,
-                               (uint16_t *)b.slices, b.site_log, b.site_sign, b.fused_regauge, b.classes,
-                               b.w, b.crec, b.geos, b.buckets, b.pair_a, b.pair_b,
-                               b.pair_cats, b.results);
+            hipLaunchKernelGGL((k_bp_persistent<uint16_t, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (uint16_t *)b.slices,
+                               b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
+                               b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
     }
+}
+
+hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
+    const int n_large = b.n_fused - b.n_fused_small;
+    if (n_large > 0) launch_fused_nt<kPThreads>(b, b.fused, n_large, b.fused_lds, tol, max_iter, s);
+    if (b.n_fused_small > 0)
+        launch_fused_nt<kPSmallThreads>(b, b.fused + n_large, b.n_fused_small, b.fused_lds_small, tol, max_iter, s);
     return hipGetLastError();
 }
 

@@ -18,8 +18,10 @@ struct DeviceBatch {
                                         // the rest: register tiles of the wide shapes (rank 4 at
                                         // D = 5, 6; rank 6 at D = 3)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
-    const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel
-    int n_fused = 0;
+    const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel: the large ones,
+    int n_fused = 0;                    // then the n_fused_small of at most kPSmallSites sites
+    int n_fused_small = 0;
+    size_t fused_lds_small = 0;
     const FusedGroup *fgroups = nullptr;
     const int *fsite_list = nullptr;
     size_t fused_lds = 0;
@@ -70,6 +72,9 @@ enum KernelId { KID_INIT = 0, KID_SWEEP, KID_CLOSE, KID_FUSED, KID_GAUGE, KID_RE
 // threads per BP tile and dynamic LDS (doubles) of one BP tile
 int bp_tile_threads();
 // sites per tile on the register path for uniform leg dimension D and rank R (0: LDS path)
+// Networks of at most this many sites run in persistent blocks of 128
+// threads (two waves) instead of 512.
+constexpr int kPSmallSites = 64;
 int bp_reg_sites_per_tile(int D, int R);
 // sites per register tile of the per-launch sweep (0: LDS path); a superset
 // of the shapes bp_reg_sites_per_tile accepts

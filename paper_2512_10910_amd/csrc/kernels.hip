@@ -34,6 +34,29 @@ constexpr int kCbThreads = 256;
 // by the largest magnitude of the vacuum vector (sites with open legs), and
 // store the result in the slice precision.  ln|z'| and its sign are kept in
 // FP64; their sum over sites is ln|Z_BP|.
+// One mode product of the staged site tensor along a leg of dimension DD and
+// stride sl: each thread takes whole fibers (the DD entries along the leg),
+// reads them once and writes the DD outputs, with the same summation order
+// as the per-entry form below.
+template <int DD>
+__device__ inline void mode_product_fibers(const double *b0, double *b1, const double *s_x, int size, int sl) {
+    const int nf = size / DD;
+    for (int f = threadIdx.x; f < nf; f += kRgThreads) {
+        const int hi = f / sl;
+        const int base = hi * DD * sl + (f - hi * sl);
+        double xin[DD];
+#pragma unroll
+        for (int i = 0; i < DD; ++i) xin[i] = b0[base + i * sl];
+#pragma unroll
+        for (int k = 0; k < DD; ++k) {
+            double acc = 0.0;
+#pragma unroll
+            for (int i = 0; i < DD; ++i) acc = fma(xin[i], s_x[i * DD + k], acc);
+            b1[base + k * sl] = acc;
+        }
+    }
+}
+
 template <typename S>
 __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restrict__ sites,
                                                         const int *__restrict__ rg_sites,
@@ -51,7 +74,7 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
     const int size = r.size;
     double *b0 = lds;
     double *b1 = lds + size;
-    for (int e = tid; e < size; e += kRgThreads) b0[e] = r.t[e];
+    for (int e = tid; e < size; e += kRgThreads) b0[e] = gld(r.t + e);
     const double *mb = st[r.net].parity ? msg1 : msg0;
     for (int l = 0; l < r.rank; ++l) {
         const int d = r.dim[l];
@@ -69,12 +92,20 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
             }
             __syncthreads();
             const int sl = r.stride[l];
-            for (int e = tid; e < size; e += kRgThreads) {
-                const int k = (e / sl) % d;
-                const int base = e - k * sl;
-                double acc = 0.0;
-                for (int i = 0; i < d; ++i) acc = fma(b0[base + i * sl], s_x[i * d + k], acc);
-                b1[e] = acc;
+            switch (d) {
+                case 2: mode_product_fibers<2>(b0, b1, s_x, size, sl); break;
+                case 3: mode_product_fibers<3>(b0, b1, s_x, size, sl); break;
+                case 4: mode_product_fibers<4>(b0, b1, s_x, size, sl); break;
+                case 5: mode_product_fibers<5>(b0, b1, s_x, size, sl); break;
+                case 6: mode_product_fibers<6>(b0, b1, s_x, size, sl); break;
+                default:
+                    for (int e = tid; e < size; e += kRgThreads) {
+                        const int k = (e / sl) % d;
+                        const int base = e - k * sl;
+                        double acc = 0.0;
+                        for (int i = 0; i < d; ++i) acc = fma(b0[base + i * sl], s_x[i * d + k], acc);
+                        b1[e] = acc;
+                    }
             }
             double *t = b0;
             b0 = b1;

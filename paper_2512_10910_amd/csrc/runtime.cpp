@@ -108,8 +108,10 @@ struct pne_batch {
     std::vector<hipEvent_t> ev_pool;
     double kt_ms[KID_COUNT] = {0};
     int64_t kt_n[KID_COUNT] = {0};
-    std::vector<NetState> h_state;
+    std::vector<NetState> h_state;  // state of the last waited launch, copied from its slot when needed
+    int state_slot = -1;            // slot of the last waited launch while h_state lags it
     std::vector<FusedNet> h_fused;  // host copy of the persistent-block table
+    std::vector<int32_t> paths;     // per network: PNE_PATH_* bits
     int64_t msg_total = 0;
     std::vector<int> msg_off;  // per global site
     std::vector<int> moff;     // per global slot, relative
@@ -334,6 +336,14 @@ pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
     for (auto &pc : ap.up) *pc.dst = (char *)p + pc.off;
     for (auto &pc : ap.buf) *pc.dst = (char *)p + pc.off;
     return PNE_OK;
+}
+
+// h_state from the last waited launch's pinned slot (once per wait)
+void ensure_state(pne_batch *b) {
+    if (b->state_slot < 0) return;
+    const NetState *src = b->h_state_slot[b->state_slot];
+    b->h_state.assign(src, src + b->nets.size());
+    b->state_slot = -1;
 }
 
 hipError_t enqueue_result_copies(pne_batch *b) {
@@ -767,7 +777,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<BpTile> loop_tiles, wide_tiles;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
-    size_t bp_lds = 0, fused_lds = 0;
+    size_t bp_lds = 0;
     std::vector<char> net_rg_inline(n, 0);  // gauge + slices built by the persistent block
     std::vector<char> net_fused(n, 0);      // BP in a persistent block
     std::vector<int> fused_of_net(n, -1);   // index of the network's persistent block
@@ -879,7 +889,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             }
             rg_scratch = std::max(rg_scratch, bp_persistent_regauge_table(r0.dim[0], r0.rank));
         }
-        rg_scratch = std::max(rg_scratch, 32);  // the in-block term sum's LDS (8 waves x 32)
+        // the in-block term sum needs 153 doubles of the waves' scratch (8 x 32, or 2 x 80 in the
+        // two-wave blocks of small networks)
+        rg_scratch = std::max(rg_scratch, g.n_sites <= kPSmallSites ? 80 : 32);
         if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2) <= fused_budget)
             pscratch = rg_scratch;
         else
@@ -919,7 +931,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             fused_of_net[i] = (int)fused.size();
             fused.push_back(f);
             net_fused[i] = 1;
-            fused_lds = std::max(fused_lds, pneed * 8);
         } else {
             for (size_t t = tile_begin; t < tiles.size(); ++t) {
                 const bool wide = tiles[t].reg && bp_reg_sites_per_tile(tiles[t].dc, tiles[t].rank) == 0;
@@ -1088,8 +1099,25 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     loop_tiles.insert(loop_tiles.end(), wide_tiles.begin(), wide_tiles.end());
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
+    // large networks first, then the small ones (their own launch, 128-thread blocks)
+    std::stable_partition(fused.begin(), fused.end(), [](const FusedNet &f) { return f.n_sites > kPSmallSites; });
+    size_t lds_large = 0, lds_small = 0;
+    int n_small = 0;
+    for (const FusedNet &f : fused) {
+        const size_t need = bp_persistent_lds_doubles(f.msg_size, f.n_sites, f.scratch, f.colors == 2 ? 1 : 2) * 8;
+        if (f.n_sites <= kPSmallSites) {
+            lds_small = std::max(lds_small, need);
+            ++n_small;
+        } else {
+            lds_large = std::max(lds_large, need);
+        }
+    }
     UP(fused, fused);
     b->h_fused = fused;
+    b->paths.assign(n, 0);
+    for (int i = 0; i < n; ++i)
+        b->paths[i] = (net_fused[i] ? PNE_PATH_PERSISTENT : 0) | (net_rg_inline[i] ? PNE_PATH_BLOCK_GAUGE : 0) |
+                      (net_cl_fused[i] ? PNE_PATH_BLOCK_TERMS : 0);
     UP(fgroups, fgroups);
     UP(fsite_list, fsite_list);
     // regauge work: register tiles without open legs, other sites one per block
@@ -1141,7 +1169,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_tiles = (int)loop_tiles.size();
     db.n_narrow_tiles = n_narrow;
     db.n_fused = (int)fused.size();
-    db.fused_lds = fused_lds;
+    db.fused_lds = lds_large;
+    db.fused_lds_small = lds_small;
+    db.n_fused_small = n_small;
     db.n_nets = n;
     db.n_cblocks = (int)cblocks.size();
     db.bp_lds = bp_lds;
@@ -1197,6 +1227,7 @@ pne_status pne_batch_launch(pne_batch *b) {
     const DeviceBatch &db = b->db;
     if (b->n_launched - b->n_waited >= 2) return fail(ctx, PNE_ERR_INVALID_ARG, "two launches already outstanding");
     const int slot = (int)(b->n_launched & 1);
+    if (b->state_slot == slot) ensure_state(b);  // this launch rewrites that slot
     b->h_state_pinned = b->h_state_slot[slot];
     b->h_results_pinned = b->h_results_slot[slot];
     // Graph replay: a batch whose BP runs entirely in persistent blocks has
@@ -1282,14 +1313,14 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
     ++b->n_waited;
     b->h_state_pinned = b->h_state_slot[slot];
     b->h_results_pinned = b->h_results_slot[slot];
-    b->h_state.assign(b->h_state_pinned, b->h_state_pinned + n);
+    b->state_slot = slot;  // h_state is copied only if asked for
     collect_times(b, b->n_waited);
     b->waited = true;
     if (!results) return PNE_OK;
     pne_status worst = PNE_OK;
     for (int i = 0; i < n; ++i) {
         const NetResult &r = b->h_results_pinned[i];
-        const NetState &s = b->h_state[i];
+        const NetState &s = b->h_state_pinned[i];
         const GeoPlan &p = *b->plans[i];
         pne_result &o = results[i];
         double *ov = o.open_values;
@@ -1390,6 +1421,7 @@ pne_status pne_batch_phase_times(pne_batch *b, double *out, int32_t n) {
     unsigned long long t0 = ~0ull, t1 = 0, t2 = 0;
     int cnt = 0;
     const double tick_us = 1000.0 / b->ctx->wall_khz;
+    ensure_state(b);
     for (const FusedNet &f : b->h_fused) {
         const NetState &s = b->h_state[f.net];
         if (s.t_bp < s.t_start || s.t_rg < s.t_bp) continue;
@@ -1413,6 +1445,12 @@ pne_status pne_batch_phase_times(pne_batch *b, double *out, int32_t n) {
     return PNE_OK;
 }
 
+pne_status pne_batch_paths(pne_batch *b, int32_t *out, int32_t n) {
+    if (!b || !out || n != (int32_t)b->paths.size()) return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
+    std::copy(b->paths.begin(), b->paths.end(), out);
+    return PNE_OK;
+}
+
 pne_status pne_batch_messages(pne_batch *b, int32_t i, double *out, int64_t capacity) {
     if (!b || !b->waited || i < 0 || i >= (int)b->nets.size() || !out)
         return fail(b ? b->ctx : nullptr, PNE_ERR_INVALID_ARG, "bad arguments");
@@ -1420,6 +1458,7 @@ pne_status pne_batch_messages(pne_batch *b, int32_t i, double *out, int64_t capa
     int64_t need = 0;
     for (int bb = 0; bb < g.n_bonds; ++bb) need += 2 * g.dim[g.slot(g.bu[bb], g.bul[bb])];
     if (capacity < need) return fail(b->ctx, PNE_ERR_INVALID_ARG, "capacity too small");
+    ensure_state(b);
     const double *src = b->h_state[i].parity ? b->db.msg1 : b->db.msg0;
     std::vector<double> host(b->msg_total);
     HIP_TRY(b->ctx, hipMemcpy(host.data(), src, sizeof(double) * b->msg_total, hipMemcpyDeviceToHost));

@@ -10,6 +10,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 from dataclasses import dataclass, field
 
 import numpy as np
@@ -144,6 +145,7 @@ _PROTOS = {
                                               _i32p, _i32p]),
     "pne_batch_messages": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _f64p, ctypes.c_int64]),
     "pne_batch_phase_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32]),
+    "pne_batch_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "pne_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                     ctypes.POINTER(Options), ctypes.c_int32, ctypes.POINTER(Options)]),
     "pne_server_options_default": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
@@ -286,6 +288,7 @@ PNE_FLAG_BP_JACOBI = 4
 PNE_FLAG_SEPARATE_REGAUGE = 8
 PNE_FLAG_GRAPH = 16
 PNE_FLAG_AUTOTUNE = 32
+PATH_PERSISTENT, PATH_BLOCK_GAUGE, PATH_BLOCK_TERMS = 1, 2, 4
 
 
 def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
@@ -319,9 +322,16 @@ class Context:
         _check(self.lib, self.lib.pne_ctx_create(int(device), int(mem_budget), sp, ctypes.byref(h)))
         self.handle = h
         self._alive = True
+        self._children = weakref.WeakSet()  # servers, batches and networks made on this context
 
     def close(self):
+        """Destroy the context, after every server, batch and network made on it."""
         if self._alive:
+            kids = list(self._children)
+            for kind in (Server, Batch, Network):
+                for k in kids:
+                    if isinstance(k, kind):
+                        k.close()
             self.lib.pne_ctx_destroy(self.handle)
             self._alive = False
 
@@ -392,6 +402,7 @@ class Network:
         self.handle = h
         self._desc = da
         self._alive = True
+        ctx._children.add(self)
 
     def close(self):
         if self._alive:
@@ -420,6 +431,7 @@ class Batch:
                                                  ctypes.byref(h)), ctx.handle)
         self.handle = h
         self._alive = True
+        ctx._children.add(self)
         n = len(self.nets)
         self._res = (ResultStruct * n)()
         self._open = []
@@ -494,6 +506,13 @@ class Batch:
             self.handle, ms.ctypes.data_as(_f64p), cnt.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), n,
             1 if reset else 0), self.ctx.handle)
         return {k: (float(ms[i]), int(cnt[i])) for i, k in enumerate(KERNEL_NAMES)}
+
+    def paths(self) -> np.ndarray:
+        """Per network: PATH_* bits (persistent block, in-block gauge, in-block terms)."""
+        out = np.zeros(len(self.nets), np.int32)
+        _check(self.ctx.lib, self.ctx.lib.pne_batch_paths(self.handle, out.ctypes.data_as(
+            ctypes.POINTER(ctypes.c_int32)), len(self.nets)), self.ctx.handle)
+        return out
 
     def phase_times(self) -> dict:
         """Persistent-block phase durations of the last run (microseconds)."""
@@ -571,6 +590,7 @@ class Server:
         self.handle = h
         self._alive = True
         self._open_shape = {}
+        ctx._children.add(self)
 
     @staticmethod
     def prepare(obj, K=6, precision="fp64", tol=1e-13, max_iter=500, persistent=True) -> "Prepared":

@@ -452,3 +452,42 @@ def test_two_outstanding_launches(ctx):
     pb.wait_arrays()
     assert pb.kernel_times()["combine"][1] == 2
 
+
+
+def test_batch_paths(ctx):
+    """The per-network path report: a closed 16x16 network runs every step in
+    its persistent block; an open network is swept launch by launch; the
+    separate-regauge flag moves the gauge and the terms out of the block."""
+    closed = ctx.network(P.config2_network(4, 2000))
+    opened = ctx.network(P.random_2d(4, 4, 3, "uniform01", seed=32, open_sites={5: 2, 6: 2}))
+    b = ctx.batch([closed, opened], K=6, precision="fp32")
+    full = pne_mod().PATH_PERSISTENT | pne_mod().PATH_BLOCK_GAUGE | pne_mod().PATH_BLOCK_TERMS
+    assert list(b.paths()) == [full, 0]
+    b2 = ctx.batch([closed], K=6, precision="fp32", fused_regauge=False)
+    assert list(b2.paths()) == [pne_mod().PATH_PERSISTENT]
+
+
+def pne_mod():
+    import paper_2512_10910_amd as m
+
+    return m
+
+
+def test_small_and_large_networks_in_one_batch(ctx):
+    """Networks of at most 64 sites run in their own launch of two-wave
+    blocks; in a batch with large networks each result equals the network's
+    result alone (same kernels, same per-network reduction order) and the
+    oracle's."""
+    nets_in = [P.random_2d(4, 4, 3, "uniform01", seed=70), P.config2_network(4, 2000),
+               P.random_2d(8, 8, 4, "uniform01", seed=71), P.ising_2d(4, 4, 0.44),
+               P.random_2d(9, 8, 2, "normal", seed=72)]
+    nets = [ctx.network(n) for n in nets_in]
+    b = ctx.batch(nets, K=6, precision="fp64")
+    assert (b.paths() & pne_mod().PATH_PERSISTENT).all()
+    mixed = b.run()
+    for n, r in zip(nets, mixed):
+        alone = ctx.batch([n], K=6, precision="fp64").run()[0]
+        assert r.log_abs == alone.log_abs and r.sign == alone.sign and r.bp_iters == alone.bp_iters
+    for i in (0, 2, 3):
+        ref = O.pne_contract(nets_in[i], 6)
+        _check_closed(mixed[i], ref, 1e-10)
