@@ -63,6 +63,7 @@ struct DeviceBatch {
     const int *pair_a = nullptr, *pair_b = nullptr;
     const PairCat *pair_cats = nullptr;
     NetResult *results = nullptr;
+    double *open_out = nullptr;  // open networks' output tensors (CombineRec::open_off)
 };
 
 // kernel identifiers for per-kernel timing (KID_GAUGE stays as a slot: the

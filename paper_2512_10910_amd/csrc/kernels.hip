@@ -347,7 +347,8 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                                                         const PairCat *__restrict__ cats, const double *__restrict__ w,
                                                         const double *__restrict__ site_log,
                                                         const int *__restrict__ site_sign, const double *__restrict__ vac,
-                                                        const NetState *__restrict__ st, NetResult *__restrict__ out) {
+                                                        const NetState *__restrict__ st, NetResult *__restrict__ out,
+                                                        double *__restrict__ open_out) {
     const int net = combine_nets[blockIdx.x];
     const CombineRec cr = recs[net];
     const GeoRec gr = geos[cr.geo];
@@ -468,7 +469,6 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
         const double tot = 1.0 + SC;
         res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
         res.log_abs = lg + log(fabs(tot));
-        for (int e = 0; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
     } else {
         // Wc(<= budget) helper: sum of closed bucket sums with size <= budget
         auto wc_upto = [&](int budget) {
@@ -517,9 +517,8 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                     }
                 }
                 v -= psum[4][e];
-                res.open[e] = sign_bp * v;
+                open_out[cr.open_off + e] = sign_bp * v;
             }
-        for (int e = pa * pb; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
         res.sign = sign_bp;
         res.log_abs = lg;
     }
@@ -582,7 +581,7 @@ hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
     if (!b.n_combine) return hipSuccess;
     hipLaunchKernelGGL(k_combine, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
                        b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.w, b.site_log, b.site_sign, b.vac, b.state,
-                       b.results);
+                       b.results, b.open_out);
     return hipGetLastError();
 }
 

@@ -168,7 +168,8 @@ struct CombineRec {
     int32_t n_sites;
     int32_t vac_a, vac_b;  // vacuum offsets of the open sites (-1 if none)
     int32_t pa, pb;        // open dims of A and B (1 if absent)
-    int32_t pad1, pad2;
+    int32_t open_off;      // first entry of the network's pa*pb open output (-1: closed network)
+    int32_t pad1;
 };
 
 // Per-network device result.
@@ -178,8 +179,7 @@ struct NetResult {
     double sum;            // closed networks: the retained-term sum S (Z = Z_BP (1+S))
     int32_t sign;
     int32_t status;
-    double open[kMaxOpenOut];
-};
+};  // an open network's output tensor goes to the batch's open-output buffer
 
 // Geometry-level combine tables.
 struct GeoRec {

@@ -90,6 +90,9 @@ struct pne_batch {
     NetResult *h_results_pinned = nullptr;
     NetState *h_state_slot[2] = {nullptr, nullptr};
     NetResult *h_results_slot[2] = {nullptr, nullptr};
+    double *h_open_slot[2] = {nullptr, nullptr};  // open outputs of each slot's launch
+    std::vector<int32_t> open_off;                 // per network: offset in the open outputs, -1 if closed
+    int64_t open_total = 0;
     void *h_pinned = nullptr;               // the one pinned block holding both slots
     hipEvent_t done_slot[2] = {nullptr, nullptr};
     int64_t n_launched = 0, n_waited = 0;
@@ -351,6 +354,12 @@ hipError_t enqueue_result_copies(pne_batch *b) {
     hipError_t e = hipMemcpyAsync(b->h_results_pinned, b->db.results, sizeof(NetResult) * n, hipMemcpyDeviceToHost,
                                   b->stream);
     if (e != hipSuccess) return e;
+    if (b->open_total > 0) {
+        const int slot = (int)(b->h_results_pinned == b->h_results_slot[1]);
+        e = hipMemcpyAsync(b->h_open_slot[slot], b->db.open_out, sizeof(double) * b->open_total,
+                           hipMemcpyDeviceToHost, b->stream);
+        if (e != hipSuccess) return e;
+    }
     return hipMemcpyAsync(b->h_state_pinned, b->db.state, sizeof(NetState) * n, hipMemcpyDeviceToHost, b->stream);
 }
 
@@ -382,7 +391,15 @@ hipEvent_t take_event(pne_batch *b) {
 // Launch `fn` on the batch stream, bracketed by events when profiling.
 template <class F>
 hipError_t timed(pne_batch *b, int kid, F &&fn) {
-    const bool prof = (b->opt.flags & PNE_FLAG_PROFILE) != 0 &&
+    // launchers with nothing to do enqueue nothing, and are not timed either
+    const DeviceBatch &db = b->db;
+    const bool work = kid == KID_INIT ? (db.n_init_sites > 0 || db.n_init_nets > 0)
+                    : kid == KID_FUSED ? db.n_fused > 0
+                    : kid == KID_REGAUGE ? (db.n_rg_tiles > 0 || db.n_rg_sites > 0)
+                    : kid == KID_CLUSTERS ? db.n_cblocks > 0
+                    : kid == KID_COMBINE ? db.n_combine > 0
+                    : true;
+    const bool prof = work && (b->opt.flags & PNE_FLAG_PROFILE) != 0 &&
                       (b->opt.profile_kernels == 0 || ((b->opt.profile_kernels >> kid) & 1));
     hipStream_t s = b->stream;
     hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -954,6 +971,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::map<const GeoPlan *, int> geo_index;
     int64_t wtot = 0;
     b->w_base.resize(n);
+    b->open_off.assign(n, -1);
     size_t cl_lds = 0;
     for (int i = 0; i < n; ++i) {
         const GeoPlan *p = b->plans[i].get();
@@ -996,6 +1014,12 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         cr.vac_b = p->open_b >= 0 ? sites[b->site_base[i] + p->open_b].vac_off : -1;
         cr.pa = p->pa;
         cr.pb = p->pb;
+        cr.open_off = -1;
+        if (p->open_a >= 0) {
+            cr.open_off = (int32_t)b->open_total;
+            b->open_total += (int64_t)p->pa * p->pb;
+        }
+        b->open_off[i] = cr.open_off;
     }
     if (cl_lds > 64 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: cluster frontier too large for LDS");
     // Classes point at their plan's device instance tables (kept by the
@@ -1188,6 +1212,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     AL(sizeof(double) * std::max<int64_t>(vac, 1), vac, double *);
     AL(sizeof(double) * std::max<int64_t>(wtot, 1), w, double *);
     AL(sizeof(NetResult) * n, results, NetResult *);
+    AL(sizeof(double) * std::max<int64_t>(b->open_total, 1), open_out, double *);
 #undef AL
     st = commit_arena(b.get(), ap);
     if (st != PNE_OK) {
@@ -1196,7 +1221,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     }
     // one pinned block for the per-network state and results read back by every wait
     const size_t st_bytes = align256(sizeof(NetState) * n);
-    const size_t slot_bytes = st_bytes + align256(sizeof(NetResult) * n);
+    const size_t res_bytes = align256(sizeof(NetResult) * n);
+    const size_t slot_bytes = st_bytes + res_bytes + align256(sizeof(double) * std::max<int64_t>(b->open_total, 1));
     if (hipHostMalloc(&b->h_pinned, 2 * slot_bytes, hipHostMallocDefault) != hipSuccess) {
         free_batch(b.get());
         return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
@@ -1204,6 +1230,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     for (int k = 0; k < 2; ++k) {
         b->h_state_slot[k] = (NetState *)((char *)b->h_pinned + k * slot_bytes);
         b->h_results_slot[k] = (NetResult *)((char *)b->h_pinned + k * slot_bytes + st_bytes);
+        b->h_open_slot[k] = (double *)((char *)b->h_pinned + k * slot_bytes + st_bytes + res_bytes);
         if (hipEventCreateWithFlags(&b->done_slot[k], hipEventDisableTiming) != hipSuccess) {
             free_batch(b.get());
             return fail(ctx, PNE_ERR_DEVICE, "event creation failed");
@@ -1340,7 +1367,8 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
             if (!ov || cap < m) {
                 st = PNE_ERR_INVALID_ARG;
             } else {
-                for (int e = 0; e < m; ++e) ov[e] = r.open[e];
+                const double *src = b->h_open_slot[slot] + b->open_off[i];
+                for (int e = 0; e < m; ++e) ov[e] = src[e];
                 o.n_open_values = m;
             }
         }

@@ -178,7 +178,6 @@ __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, 
     const double tot = 1.0 + SC;
     res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
     res.log_abs = lg + log(fabs(tot));
-    for (int e = 0; e < kMaxOpenOut; ++e) res.open[e] = 0.0;
     out[net] = res;
 }
 
