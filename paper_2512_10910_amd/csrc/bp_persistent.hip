@@ -334,10 +334,7 @@ __host__ __device__ constexpr bool dpp_shape(int D, int R) {
 // tiles per wavefront step: two for small register sets, fewer when the
 // tiles' (site, leg) items would exceed one wavefront
 __host__ __device__ constexpr int dpp_tiles_in_flight(int D, int R) {
-    return (tiles_in_flight(ipw(D, R - (R < 2 ? R : 2))) == 2 &&
-            2 * (64 >> ((D <= 2 ? 1 : 2) * (R < 2 ? R : 2))) * R <= 64)
-               ? 2
-               : 1;
+    return ipw(D, R - (R < 2 ? R : 2)) <= 4 ? 2 : 1;  // more register values per lane spill at two
 }
 
 template <int D, int R>

@@ -282,6 +282,8 @@ bool prepare_and_launch(pne_server *sv, const std::vector<Request *> &take, hipS
 // their estimated bytes fit the budget and fewer than pipeline_depth
 // batches are in flight, prepares and launches them, and frees finished
 // batches whenever nothing is in flight.
+constexpr int kGraveyardMax = 8;
+
 void worker_main(pne_server *sv) {
     int launch_count = 0;
     const int depth = sv->so.pipeline_depth;
@@ -293,15 +295,20 @@ void worker_main(pne_server *sv) {
             int64_t seen = sv->finished_batches;
             bool blocked = false;  // the oldest pending request waits for memory
             for (;;) {
+                // finished batches are freed while nothing is in flight (a free
+                // synchronises the device), or once kGraveyardMax pile up
+                auto release_now = [&] {
+                    return !sv->graveyard.empty() &&
+                           (sv->inflight.empty() || (int)sv->graveyard.size() >= kGraveyardMax);
+                };
                 sv->cv.wait(lk, [&] {
                     return (!blocked && (int)sv->inflight.size() < depth && !sv->pending.empty()) ||
-                           (sv->inflight.empty() && !sv->graveyard.empty()) ||
-                           (sv->stop && sv->pending.empty() && sv->inflight.empty()) ||
+                           release_now() || (sv->stop && sv->pending.empty() && sv->inflight.empty()) ||
                            sv->finished_batches != seen;
                 });
                 if (sv->finished_batches != seen) blocked = false;
                 seen = sv->finished_batches;
-                if (sv->inflight.empty() && !sv->graveyard.empty()) {
+                if (release_now()) {
                     dead.swap(sv->graveyard);
                     break;
                 }
