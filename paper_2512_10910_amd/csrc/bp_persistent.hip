@@ -733,6 +733,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
                 const PairCat *__restrict__ cats, NetResult *__restrict__ results) {
     constexpr int NW = NT / 64;
     const FusedNet fn = fnets[blockIdx.x];
+    if (fn.prio) __builtin_amdgcn_s_setprio(2);
     NetState *ns = st + fn.net;
     const unsigned long long t_start = wall_clock64();
     __shared__ double s_res[2 * NW];

@@ -60,7 +60,7 @@ struct FusedNet {
     int32_t cl_fused;     // 1: ... and contracts its clusters and sums its terms (closed network)
     int32_t class_begin;  // the network's plan classes (cl_fused)
     int32_t n_classes;
-    int32_t pad;
+    int32_t prio;         // wave issue priority (0..3): higher for networks with more work per step
     int64_t w_base;       // the network's first cluster weight (cl_fused)
 };
 

@@ -1123,6 +1123,21 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     loop_tiles.insert(loop_tiles.end(), wide_tiles.begin(), wide_tiles.end());
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
+    // Wave priority by work per BP step (tensor entries): where blocks of light
+    // and heavy networks share a CU, the heavy ones get the issue slots first,
+    // so both finish closer together and the heavy ones leave a shorter tail.
+    if (!fused.empty()) {
+        std::vector<int64_t> work(fused.size());
+        for (size_t k = 0; k < fused.size(); ++k) {
+            int64_t wk = 0;
+            for (int s2 = 0; s2 < fused[k].n_sites; ++s2) wk += sites[fused[k].site_base + s2].size;
+            work[k] = wk;
+        }
+        std::vector<int64_t> sorted_work(work);
+        std::sort(sorted_work.begin(), sorted_work.end());
+        const int64_t light = sorted_work[sorted_work.size() / 4];  // lower quartile
+        for (size_t k = 0; k < fused.size(); ++k) fused[k].prio = work[k] >= 2 * light ? 1 : 0;
+    }
     // large networks first, then the small ones (their own launch, 128-thread blocks)
     std::stable_partition(fused.begin(), fused.end(), [](const FusedNet &f) { return f.n_sites > kPSmallSites; });
     size_t lds_large = 0, lds_small = 0;
