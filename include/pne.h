@@ -200,10 +200,12 @@ pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const
                         pne_options *best);
 
 /* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
- * measured with HIP events recorded on the context stream around each launch.
- * Index k: 0 init, 1 BP sweep (per-launch), 2 BP close, 3 persistent BP,
- * 4 bond gauge (no launches of its own: built inside the regauge kernels),
- * 5 gauge + regauge / slices, 6 cluster contraction, 7 combine.  Writes n entries; reset != 0
+ * measured with HIP events recorded on the batch's stream around each launch.
+ * Index k: 0 init, 1 BP sweep (per-launch), 2 BP close, 3 persistent BP
+ * (both of its launches: large and small networks), 4 bond gauge (no
+ * launches of its own: built inside the regauge kernels), 5 gauge + regauge
+ * / slices, 6 cluster contraction, 7 combine.  A step with nothing to do for
+ * a kernel launches nothing and counts nothing.  Writes n entries; reset != 0
  * clears the accumulators afterwards. */
 pne_status pne_batch_kernel_times(pne_batch *batch, double *ms_total, int64_t *launches, int32_t n,
                                   int32_t reset);
