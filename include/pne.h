@@ -150,6 +150,32 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int da
                               pne_network **out);
 pne_status pne_network_destroy(pne_network *net);
 
+/* User partitions (Sec. II.A-C, Eqs. A4, A6, A8-A10).  Partition p transects
+ * the bonds part_bond[part_begin[p] .. part_begin[p+1]) (part_begin has
+ * n_partitions + 1 entries, part_begin[0] == 0); its projector is the product
+ * of the rank-1 BP projectors of those bonds (Eq. A10), so a multi-index
+ * partition keeps its bonds together.  Bonds transected by no partition carry
+ * the identity.  Partitions may share bonds.  n_partitions == 0 restores the
+ * default (every bond expanded, degree cap only).
+ *
+ * Result of a network with partitions: the exact value minus the residue of
+ * the linear or combinatorial form (both drop the same residue, the network
+ * with Q_p on every partition), further restricted to configurations of at
+ * most K excited bonds.  With K >= n_bonds (and K <= 32) it is exactly the
+ * paper's partitioned expansion with the residue dropped; n_config_terms then
+ * counts the retained loop configurations.  In the rank-1 BP gauge the
+ * residue is the sum of the dangling-free configurations that excite at
+ * least one bond of every partition (Eq. A9), which is how the library
+ * evaluates it: every retained configuration is listed at plan time, so the
+ * envelope is small networks (at most 2^24 listed cluster entries).
+ *
+ * Closed networks only (open legs: PNE_ERR_UNSUPPORTED); 1 <= n_partitions
+ * <= 32; every partition transects at least one bond, no bond twice.
+ * Batches already created keep the partitions they were made with.  Arrays are
+ * copied; the caller keeps ownership. */
+pne_status pne_network_set_partitions(pne_network *net, int32_t n_partitions, const int32_t *part_begin,
+                                      const int32_t *part_bond);
+
 /* Prepare a batch: enumerate (or fetch cached) retained clusters per network
  * geometry, build contraction plans and device tables, allocate the batch's
  * device working memory.  The networks must stay alive while the batch does. */
@@ -185,6 +211,16 @@ pne_status pne_contract_batch(pne_ctx *ctx, pne_network *const *nets, int32_t n,
  * bond ids ascending, clusters in the library's order). */
 pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64_t *n_clusters,
                                   int64_t *n_entries, int32_t *sizes, int32_t *bonds);
+
+/* Host only (no device needed): the number of retained clusters and of
+ * retained configurations (collections of vertex-disjoint clusters, the
+ * empty one excluded) the library would evaluate for this geometry at degree
+ * cap K, with the given partitions (n_partitions == 0: none; same rules as
+ * pne_network_set_partitions).  The counts equal pne_result's
+ * n_cluster_terms and n_config_terms. */
+pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t n_partitions,
+                                    const int32_t *part_begin, const int32_t *part_bond, int64_t *n_clusters,
+                                    int64_t *n_configs);
 
 /* Autotune: for the batch these networks and options would form, time the
  * execution variants (gauge + slices inside the persistent BP block or in

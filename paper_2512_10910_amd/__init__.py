@@ -16,6 +16,7 @@ from .pne import (  # noqa: F401
     Prepared,
     Server,
     enumerate_clusters,
+    count_configurations,
     load_library,
     LIB_PATH,
     PATH_BLOCK_GAUGE,

@@ -7,6 +7,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <functional>
 #include <map>
 #include <numeric>
 #include <set>
@@ -14,6 +15,8 @@
 namespace pne {
 
 namespace {
+
+constexpr size_t kMaxListed = size_t(1) << 24;  // cluster entries over all listed configurations
 
 uint64_t mix(uint64_t h, uint64_t v) {
     h ^= v + 0x9e3779b97f4a7c15ULL + (h << 6) + (h >> 2);
@@ -25,7 +28,64 @@ uint64_t mix(uint64_t h, uint64_t v) {
 bool Geometry::same_as(const Geometry &o) const {
     return n_sites == o.n_sites && n_bonds == o.n_bonds && n_open == o.n_open && rank == o.rank &&
            dim == o.dim && bu == o.bu && bul == o.bul && bv == o.bv && bvl == o.bvl &&
-           open_site == o.open_site && open_slot == o.open_slot;
+           open_site == o.open_site && open_slot == o.open_slot && part_off == o.part_off &&
+           part_bond == o.part_bond;
+}
+
+namespace {
+
+uint64_t geometry_hash(const Geometry &g) {
+    uint64_t h = 1469598103934665603ULL;
+    h = mix(h, g.n_sites);
+    h = mix(h, g.n_bonds);
+    h = mix(h, g.n_open);
+    for (int x : g.rank) h = mix(h, x);
+    for (int x : g.dim) h = mix(h, x);
+    for (int b = 0; b < g.n_bonds; ++b) {
+        h = mix(h, g.bu[b]);
+        h = mix(h, g.bul[b]);
+        h = mix(h, g.bv[b]);
+        h = mix(h, g.bvl[b]);
+    }
+    for (int k = 0; k < g.n_open; ++k) {
+        h = mix(h, g.open_site[k]);
+        h = mix(h, g.open_slot[k]);
+    }
+    if (g.n_parts() > 0) {
+        h = mix(h, 0x70617274ULL);
+        for (int x : g.part_off) h = mix(h, x);
+        for (int x : g.part_bond) h = mix(h, x);
+    }
+    return h;
+}
+
+}  // namespace
+
+std::string set_partitions(Geometry *g, int n, const int32_t *begin, const int32_t *bond) {
+    if (n < 0) return "negative partition count";
+    if (n > 0 && (!begin || !bond)) return "partition arrays missing";
+    if (n > kMaxParts) return "unsupported: more than 32 partitions";
+    if (n > 0 && g->n_open > 0) return "unsupported: partitions on a network with open legs";
+    std::vector<int> off{0}, bonds;
+    std::vector<uint32_t> parts(g->n_bonds, 0u);
+    if (n > 0 && begin[0] != 0) return "partition offsets must start at 0";
+    for (int p = 0; p < n; ++p) {
+        if (begin[p + 1] <= begin[p]) return "a partition transects no bond";
+        for (int k = begin[p]; k < begin[p + 1]; ++k) {
+            int b = bond[k];
+            if (b < 0 || b >= g->n_bonds) return "partition bond out of range";
+            if (parts[b] & (1u << p)) return "bond listed twice in one partition";
+            parts[b] |= 1u << p;
+            bonds.push_back(b);
+        }
+        off.push_back((int)bonds.size());
+    }
+    g->part_off = std::move(off);
+    g->part_bond = std::move(bonds);
+    if (n > 0) g->bond_parts = std::move(parts);
+    else g->bond_parts.clear();
+    g->hash = geometry_hash(*g);
+    return "";
 }
 
 std::string build_geometry(const pne_network_desc *d, Geometry *g) {
@@ -96,23 +156,7 @@ std::string build_geometry(const pne_network_desc *d, Geometry *g) {
     }
     for (int64_t sl = 0; sl < nslots; ++sl)
         if (g->partner[sl] < 0) return "a leg is neither bonded nor open";
-    uint64_t h = 1469598103934665603ULL;
-    h = mix(h, g->n_sites);
-    h = mix(h, g->n_bonds);
-    h = mix(h, g->n_open);
-    for (int x : g->rank) h = mix(h, x);
-    for (int x : g->dim) h = mix(h, x);
-    for (int b = 0; b < g->n_bonds; ++b) {
-        h = mix(h, g->bu[b]);
-        h = mix(h, g->bul[b]);
-        h = mix(h, g->bv[b]);
-        h = mix(h, g->bvl[b]);
-    }
-    for (int k = 0; k < g->n_open; ++k) {
-        h = mix(h, g->open_site[k]);
-        h = mix(h, g->open_slot[k]);
-    }
-    g->hash = h;
+    g->hash = geometry_hash(*g);
     return "";
 }
 
@@ -677,6 +721,61 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
             for (size_t m = 0; m < lc.vslots[v].size(); ++m) packed |= (uint32_t)lc.vslots[v][m] << (4 * m);
             plan->inst_slots[cid].push_back(packed);
         }
+    }
+
+    if (g.n_parts() > 0) {
+        // User partitions (Eq. A4 / A6 with factorised multi-index projectors,
+        // Eq. A8 / A10).  Dropping the residue removes exactly the
+        // configurations that excite at least one bond of every partition
+        // (with rank-1 P, Q_p = I - P_p is the sum of the terms with some bond
+        // of p excited, Eq. A9), so the retained configurations are the
+        // vertex-disjoint cluster sets of degree <= K whose excited bonds miss
+        // some partition.  They are listed one by one.
+        plan->listed = true;
+        const int np = g.n_parts();
+        const uint32_t full = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
+        plan->cmask.assign(nc, 0u);
+        std::vector<std::vector<int>> vs(nc);
+        for (int c = 0; c < nc; ++c) {
+            std::set<int> s2;
+            for (int p = cl.off[c]; p < cl.off[c + 1]; ++p) {
+                plan->cmask[c] |= g.bond_parts[cl.bonds[p]];
+                s2.insert(g.bu[cl.bonds[p]]);
+                s2.insert(g.bv[cl.bonds[p]]);
+            }
+            vs[c].assign(s2.begin(), s2.end());
+        }
+        plan->coll_off.assign(1, 0);
+        plan->coll_cl.clear();
+        std::vector<int> chosen;
+        std::vector<char> used(g.n_sites, 0);
+        bool too_many = false;
+        // depth-first over clusters in increasing index: each collection once
+        std::function<void(int, int, uint32_t)> dfs = [&](int from, int deg, uint32_t mask) {
+            for (int c = from; c < nc && !too_many; ++c) {
+                if (deg + plan->csize[c] > K) continue;
+                bool free = true;
+                for (int v : vs[c]) free = free && !used[v];
+                if (!free) continue;
+                const uint32_t m = mask | plan->cmask[c];
+                if (m == full) continue;  // excluded, and so is every superset
+                chosen.push_back(c);
+                for (int v : vs[c]) used[v] = 1;
+                plan->coll_cl.insert(plan->coll_cl.end(), chosen.begin(), chosen.end());
+                plan->coll_off.push_back((int)plan->coll_cl.size());
+                if (plan->coll_cl.size() > kMaxListed) too_many = true;
+                dfs(c + 1, deg + plan->csize[c], m);
+                for (int v : vs[c]) used[v] = 0;
+                chosen.pop_back();
+            }
+        };
+        dfs(0, 0, 0u);
+        if (too_many) {
+            *err = "unsupported: too many retained configurations to list";
+            return nullptr;
+        }
+        plan->n_configs = (int64_t)plan->coll_off.size() - 1;
+        return plan;
     }
 
     // overlapping pairs within the budget (categories used by the sum)

@@ -24,7 +24,14 @@ struct Geometry {
     std::vector<int> partner;    // per global slot: slot receiving its outgoing message
     std::vector<int> is_open;    // per global slot
     std::vector<int> open_sites; // distinct sites with open legs, by first open leg
+    // user partitions (Sec. II.A-C): partition p transects bonds
+    // part_bond[part_off[p] .. part_off[p+1]); empty when every bond is its
+    // own partition under the degree cap only
+    std::vector<int> part_off{0}, part_bond;
+    std::vector<uint32_t> bond_parts;  // per bond: bit p set if partition p transects it
     uint64_t hash = 0;
+
+    int n_parts() const { return (int)part_off.size() - 1; }
 
     int slot(int s, int l) const { return slot_base[s] + l; }
     bool same_as(const Geometry &o) const;
@@ -32,6 +39,11 @@ struct Geometry {
 
 // Validate a descriptor and fill *g.  Returns an empty string or the reason.
 std::string build_geometry(const pne_network_desc *desc, Geometry *g);
+
+// Replace the partitions of *g (n = 0 clears them) and rehash.  Returns an
+// empty string or the reason (prefixed "unsupported:" when valid but outside
+// the implemented envelope).
+std::string set_partitions(Geometry *g, int n, const int32_t *begin, const int32_t *bond);
 
 struct ClusterList {
     std::vector<int> off{0};  // cluster c: bonds[off[c] .. off[c+1])
@@ -62,6 +74,14 @@ struct GeoPlan {
     // leg to the next vertex); empty otherwise
     std::vector<std::vector<int>> loop_order;
     std::vector<int> loop_e;
+
+    // with user partitions: every retained configuration listed as its
+    // clusters coll_cl[coll_off[k] .. coll_off[k+1]) (pairwise vertex-disjoint,
+    // total degree <= K, leaving at least one partition unexcited); empty
+    // otherwise
+    std::vector<uint32_t> cmask;      // per cluster: partitions it excites
+    std::vector<int> coll_off, coll_cl;
+    bool listed = false;
 
     std::vector<Bucket> buckets;
     std::vector<int> pair_a, pair_b;  // overlapping cluster pairs (|a|+|b| <= K)

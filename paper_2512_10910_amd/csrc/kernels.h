@@ -62,6 +62,7 @@ struct DeviceBatch {
     const Bucket *buckets = nullptr;
     const int *pair_a = nullptr, *pair_b = nullptr;
     const PairCat *pair_cats = nullptr;
+    const int *coll_off = nullptr, *coll_cl = nullptr;  // listed configurations (user partitions)
     NetResult *results = nullptr;
     double *open_out = nullptr;  // open networks' output tensors (CombineRec::open_off)
 };

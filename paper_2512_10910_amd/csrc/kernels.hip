@@ -344,7 +344,9 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                                                         const GeoRec *__restrict__ geos,
                                                         const Bucket *__restrict__ buckets,
                                                         const int *__restrict__ pair_a, const int *__restrict__ pair_b,
-                                                        const PairCat *__restrict__ cats, const double *__restrict__ w,
+                                                        const PairCat *__restrict__ cats,
+                                                        const int *__restrict__ coll_off,
+                                                        const int *__restrict__ coll_cl, const double *__restrict__ w,
                                                         const double *__restrict__ site_log,
                                                         const int *__restrict__ site_sign, const double *__restrict__ vac,
                                                         const NetState *__restrict__ st, NetResult *__restrict__ out,
@@ -367,6 +369,34 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
     }
     lg = block_sum(lg, red);
     neg = block_sum(neg, red);
+
+    if (gr.listed) {
+        // User partitions (closed networks): every retained configuration is
+        // listed with its clusters; its value is the product of their
+        // weights.  Each thread sums its configurations in list order, then
+        // the block sum adds the per-thread sums in a fixed order.
+        const int *off = coll_off + gr.coll_begin;
+        const int *cls = coll_cl + gr.coll_cl_begin;
+        double v = 0.0;
+        for (int k = tid; k < gr.n_colls; k += kCbThreads) {
+            double prod = 1.0;
+            const int j1 = gld(&off[k + 1]);
+            for (int j = gld(&off[k]); j < j1; ++j) prod *= wn[gld(&cls[j])];
+            v += prod;
+        }
+        v = block_sum(v, red);
+        if (tid != 0) return;
+        NetResult res;
+        res.status = st[net].status;
+        res.log_bp = lg;
+        res.sum = v;
+        const int sign_bp = ((int)neg & 1) ? -1 : 1;
+        const double tot = 1.0 + v;
+        res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
+        res.log_abs = lg + log(fabs(tot));
+        out[net] = res;
+        return;
+    }
 
     for (int i = tid; i < 4 * 33; i += kCbThreads) bidx[i / 33][i % 33] = -1;
     __syncthreads();
@@ -580,7 +610,8 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
     if (!b.n_combine) return hipSuccess;
     hipLaunchKernelGGL(k_combine, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
-                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.w, b.site_log, b.site_sign, b.vac, b.state,
+                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.coll_off, b.coll_cl, b.w, b.site_log,
+                       b.site_sign, b.vac, b.state,
                        b.results, b.open_out);
     return hipGetLastError();
 }

@@ -10,6 +10,7 @@ constexpr int kMaxDim = 16;    // largest leg dimension
 constexpr int kMaxLab = 8;     // index labels touched by one contraction step
 constexpr int kMaxVerts = 16;  // sites in one cluster
 constexpr int kMaxOpenOut = 64;  // entries of an open-index output tensor
+constexpr int kMaxParts = 32;    // user partitions of one network
 
 // One site of one network in a batch (device table).
 struct SiteRec {
@@ -190,6 +191,10 @@ struct GeoRec {
     int32_t n_pairs;
     int32_t pair_cat_begin;  // categories of pairs (contiguous ranges)
     int32_t n_pair_cats;
+    int32_t listed;        // 1: the configurations are listed (user partitions)
+    int32_t coll_begin;    // listed: index of the first offset in the collection offsets
+    int32_t n_colls;       // listed: number of retained configurations
+    int32_t coll_cl_begin; // listed: index of the first entry in the collection clusters
     int32_t pad;
 };
 

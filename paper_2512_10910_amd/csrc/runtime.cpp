@@ -605,6 +605,18 @@ pne_status pne::network_create_on(pne_ctx *ctx, const pne_network_desc *desc, in
 extern "C" {
 
 
+pne_status pne_network_set_partitions(pne_network *net, int32_t n_partitions, const int32_t *part_begin,
+                                      const int32_t *part_bond) {
+    if (!net) return fail(nullptr, PNE_ERR_INVALID_ARG, "null network");
+    // copy on write: batches made before keep the geometry they planned with
+    auto g = std::make_shared<Geometry>(*net->geo);
+    std::string why = set_partitions(g.get(), n_partitions, part_begin, part_bond);
+    if (!why.empty())
+        return fail(net->ctx, why.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, why);
+    net->geo = g;
+    return PNE_OK;
+}
+
 pne_status pne_network_destroy(pne_network *net) {
     if (!net) return PNE_ERR_INVALID_ARG;
     if (net->owned) {
@@ -967,6 +979,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<Bucket> buckets;
     std::vector<int> pair_a, pair_b;
     std::vector<PairCat> pair_cats;
+    std::vector<int> coll_off, coll_cl;
     std::map<const GeoPlan *, int> plan_index;  // -> first class id
     std::map<const GeoPlan *, int> geo_index;
     int64_t wtot = 0;
@@ -1000,6 +1013,16 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             gr.pair_cat_begin = (int)pair_cats.size();
             gr.n_pair_cats = (int)p->pair_cats.size();
             pair_cats.insert(pair_cats.end(), p->pair_cats.begin(), p->pair_cats.end());
+            if (p->listed) {
+                gr.listed = 1;
+                gr.coll_begin = (int)coll_off.size();
+                gr.n_colls = (int)p->coll_off.size() - 1;
+                gr.coll_cl_begin = (int)coll_cl.size();
+                coll_off.insert(coll_off.end(), p->coll_off.begin(), p->coll_off.end());
+                coll_cl.insert(coll_cl.end(), p->coll_cl.begin(), p->coll_cl.end());
+                if (coll_cl.size() > (size_t)INT32_MAX / 2)
+                    return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: too many listed configurations");
+            }
             geo_index[p] = (int)geos.size();
             geos.push_back(gr);
         }
@@ -1047,7 +1070,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             // A closed network whose BP, gauge and slices run in a persistent
             // block, and whose plan has only scalar and cycle classes, also
             // gets its clusters and term sum from that block.
-            bool plan_fast = g.n_open == 0 && !cl_separate;
+            bool plan_fast = g.n_open == 0 && !cl_separate && !p->listed;
             for (int c = 0; c < ncls && plan_fast; ++c) {
                 const ClassDesc &cd = classes[c0 + c];
                 const bool sc = cd.max_f == 1 && cd.out_size == 1;
@@ -1203,6 +1226,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(pair_a, pair_a);
     UP(pair_b, pair_b);
     UP(pair_cats, pair_cats);
+    UP(coll_off, coll_off);
+    UP(coll_cl, coll_cl);
 #undef UP
     db.n_sites = (int)sites.size();
     db.n_tiles = (int)loop_tiles.size();
@@ -1441,6 +1466,24 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
     }
     *n_clusters = cl.count();
     *n_entries = (int64_t)cl.bonds.size();
+    return PNE_OK;
+}
+
+pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t n_partitions,
+                                    const int32_t *part_begin, const int32_t *part_bond, int64_t *n_clusters,
+                                    int64_t *n_configs) {
+    if (!desc || !n_clusters || !n_configs) return fail(nullptr, PNE_ERR_INVALID_ARG, "null argument");
+    if (K < 0 || K > 32) return fail(nullptr, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
+    Geometry g;
+    std::string why = build_geometry(desc, &g);
+    if (why.empty()) why = set_partitions(&g, n_partitions, part_begin, part_bond);
+    if (!why.empty())
+        return fail(nullptr, why.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, why);
+    std::string err;
+    auto p = build_plan(g, K, &err);
+    if (!p) return fail(nullptr, err.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
+    *n_clusters = p->clusters.count();
+    *n_configs = p->n_configs;
     return PNE_OK;
 }
 

@@ -130,6 +130,10 @@ _PROTOS = {
     "pne_network_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(NetworkDesc), ctypes.c_int,
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "pne_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pne_network_set_partitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i32p]),
+    "pne_count_configurations": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32, ctypes.c_int32, _i32p,
+                                                _i32p, ctypes.POINTER(ctypes.c_int64),
+                                                ctypes.POINTER(ctypes.c_int64)]),
     "pne_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                         ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]),
     "pne_batch_launch": (ctypes.c_int, [ctypes.c_void_p]),
@@ -236,6 +240,30 @@ def _net_parts(obj):
     bonds = np.asarray(obj.bonds)
     open_legs = getattr(obj, "open_legs", None)
     return tensors, bonds, open_legs
+
+
+def _partition_arrays(partitions):
+    parts = [np.asarray(p, dtype=np.int32).reshape(-1) for p in partitions]
+    begin = np.zeros(len(parts) + 1, dtype=np.int32)
+    for k, p in enumerate(parts):
+        begin[k + 1] = begin[k] + p.size
+    bonds = np.concatenate(parts).astype(np.int32) if parts else np.zeros(1, np.int32)
+    return parts, np.ascontiguousarray(begin), np.ascontiguousarray(bonds)
+
+
+def count_configurations(obj, K: int, partitions=()):
+    """Host-only: (retained clusters, retained configurations) at degree cap K."""
+    lib = load_library()
+    tensors, bonds, open_legs = _net_parts(obj)
+    shapes = [np.empty(t.shape, dtype=np.float64) if isinstance(t, np.ndarray) else np.empty(tuple(t.shape))
+              for t in tensors]
+    da = _DescArrays(shapes, bonds, open_legs, data_ptrs=[1] * len(tensors))
+    parts, begin, pb = _partition_arrays(partitions)
+    nc = ctypes.c_int64(0)
+    ncf = ctypes.c_int64(0)
+    _check(lib, lib.pne_count_configurations(ctypes.byref(da.desc), K, len(parts), begin.ctypes.data_as(_i32p),
+                                             pb.ctypes.data_as(_i32p), ctypes.byref(nc), ctypes.byref(ncf)))
+    return nc.value, ncf.value
 
 
 def enumerate_clusters(obj, K: int):
@@ -403,6 +431,16 @@ class Network:
         self._desc = da
         self._alive = True
         ctx._children.add(self)
+
+    def set_partitions(self, partitions):
+        """Partitions as lists of bond indices (Eqs. A4, A6, A8-A10); [] clears.
+
+        Batches made afterwards expand the network over these partitions
+        (closed networks; see pne_network_set_partitions)."""
+        parts, begin, bonds = _partition_arrays(partitions)
+        _check(self.ctx.lib, self.ctx.lib.pne_network_set_partitions(
+            self.handle, len(parts), begin.ctypes.data_as(_i32p), bonds.ctypes.data_as(_i32p)), self.ctx.handle)
+        self.partitions = [p.tolist() for p in parts]
 
     def close(self):
         if self._alive:

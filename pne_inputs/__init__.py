@@ -28,4 +28,10 @@ from .networks import (  # noqa: F401
     config4_request,
     config4_arrivals,
     config5_network,
+    ISING_BETA_C,
+    bond_index,
+    small_network,
+    double_loop_partitions,
+    grid3_single_partitions,
+    grid3_multi_partitions,
 )

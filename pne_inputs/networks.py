@@ -371,3 +371,70 @@ def config5_network(d: int, L: int = 32, D: int = 6, phys: int = 2) -> Network:
     net = random_2d(L, L, D, "uniform01", 5000 + d, open_sites={a: phys, b: phys})
     net.info.update(open_sites=(a, b), separation=d)
     return net
+
+
+# ----------------------------------------------------------------------------
+# small networks with user partitions (Sec. III.A-C): geometry of the
+# double-loop (3 x 2 sites) and 3 x 3 examples and their partition choices
+
+
+ISING_BETA_C = 0.5 * math.log(1.0 + math.sqrt(2.0))  # critical coupling of the 2D Ising model
+
+
+def bond_index(net: Network, u: int, v: int) -> int:
+    """Index of the bond joining sites u and v."""
+    for b, (a, _, c, _) in enumerate(net.bonds):
+        if {int(a), int(c)} == {u, v}:
+            return b
+    raise KeyError((u, v))
+
+
+def small_network(Lx: int, Ly: int, kind: str = "random", D: int = 4, seed: int = 0,
+                  bias: float = 1.0) -> Network:
+    """Lx x Ly open-boundary network of one of the paper's three tensor kinds.
+
+    kind "ising": critical 2D Ising (D = 2); "aklt": AKLT PEPS norm (D = 4);
+    "random": entries drawn i.i.d. uniform in [-1 + bias, 1 + bias]
+    (Appendix A.3) with bond dimension D.
+    """
+    if kind == "ising":
+        return ising_2d(Lx, Ly, ISING_BETA_C)
+    if kind == "aklt":
+        return aklt_2d(Lx, Ly)
+    if kind == "random":
+        return random_2d(Lx, Ly, D, dist=("uniform", -1.0 + bias, 1.0 + bias), seed=seed)
+    raise ValueError(kind)
+
+
+def double_loop_partitions(net: Network):
+    """The three vertical bonds of the 3 x 2 double loop, one partition each."""
+    return [[bond_index(net, x, x + 3)] for x in range(3)]
+
+
+def grid3_single_partitions(net: Network):
+    """Four single-index partitions of the 3 x 3 network: the centre's bonds."""
+    return [[bond_index(net, 4, t)] for t in (1, 3, 5, 7)]
+
+
+def grid3_multi_partitions(net: Network):
+    """Six multi-index partitions of the 3 x 3 network (site s = x + 3 y).
+
+    Two vertical lines (between columns 0|1 and 1|2), two horizontal lines
+    (between rows 0|1 and 1|2) and two anti-diagonal lines (between the
+    diagonals x + y = 1|2 and x + y = 2|3); each transects every bond that
+    crosses it.
+    """
+    def cut(pred):
+        return [b for b, (u, _, v, _) in enumerate(net.bonds) if pred(int(u), int(v))]
+
+    def xy(s):
+        return s % 3, s // 3
+
+    parts = []
+    for c in (0, 1):
+        parts.append(cut(lambda u, v, c=c: {xy(u)[0], xy(v)[0]} == {c, c + 1}))
+    for r in (0, 1):
+        parts.append(cut(lambda u, v, r=r: {xy(u)[1], xy(v)[1]} == {r, r + 1}))
+    for d in (1, 2):
+        parts.append(cut(lambda u, v, d=d: {sum(xy(u)), sum(xy(v))} == {d, d + 1}))
+    return parts
