@@ -280,11 +280,24 @@ def workloads_bench(pne, P, steps: int):
         ("32x32 D=6 U[0,1], two open dim-2 legs d = 1..8 apart, x16 each, K=8, fp32",
          lambda: [P.config5_network(d) for d in range(1, 9)] * 16, 8, "fp32", False),
     ]
+    # user partitions (Eqs. A4, A6): complete expansion over the partitions
+    parted = [
+        ("3x3 U[0,2] D=4 (seed 50000+i), six multi-index partitions, Eq. A6 complete (K=12), fp64",
+         lambda: [P.small_network(3, 3, "random", 4, seed=50000 + i) for i in range(8192)], 12, "fp64", True,
+         P.grid3_multi_partitions),
+        ("3x2 double loop U[0,2] D=6 (seed 60000+i), three vertical partitions, Eq. A4 complete (K=7), fp64",
+         lambda: [P.small_network(3, 2, "random", 6, seed=60000 + i) for i in range(16384)], 7, "fp64", True,
+         P.double_loop_partitions),
+    ]
     sb = {"fp64": 8, "fp32": 4, "bf16": 2}
-    for label, make, K, prec, check in cases:
+    for label, make, K, prec, check, *rest in [c + (None,) for c in cases] + parted:
+        parts_of = rest[0]
         nets_in = make()
         ctx = pne.Context(0)
         nets = [ctx.network(n) for n in nets_in]
+        if parts_of is not None:
+            for n, x in zip(nets, nets_in):
+                n.set_partitions(parts_of(x))
         b = ctx.batch(nets, K=K, precision=prec, profile=True)
         b.run_arrays()
         b.kernel_times(reset=True)
@@ -313,7 +326,12 @@ def workloads_bench(pne, P, steps: int):
                "networks_per_s": round(len(nets) / (ms * 1e-3), 1), "precision": prec, "K": K,
                "bp_iters_mean": float(np.mean(iters)), "status_min": int(res["status"].min()),
                "cluster_terms_per_step": nclu, "kernels": kernels}
-        if check:
+        if check and parts_of is not None:
+            from oracle import partitioned as PT
+
+            _, lg = PT.combinatorial_pne(nets_in[0], parts_of(nets_in[0]))
+            out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - lg) / max(1.0, abs(lg))
+        elif check:
             ref = O.pne_contract(nets_in[0], K)
             out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - ref.log_abs) / max(
                 1.0, abs(ref.log_abs))
