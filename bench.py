@@ -260,6 +260,49 @@ def kernel_bytes(pne, nets_in, paths, iters, n_clusters, K: int, slice_bytes: in
     return alg
 
 
+def strip_bytes(chi: int, k: int) -> int:
+    """Algorithmic HBM bytes of one width-k transfer-matrix application: the
+    first pass reads chi^k and writes chi^(k+1) entries, each middle pass
+    reads and writes chi^(k+1), the last reads chi^(k+1) plus the input
+    vector and writes chi^k (FP64)."""
+    if k == 1:
+        return 8 * 3 * chi
+    return 8 * (3 * chi ** k + 2 * (k - 1) * chi ** (k + 1))
+
+
+def strips_bench(pne, P, L: int = 12, betas=(0.3, 0.4, 0.4407, 0.5, 0.6)):
+    """Infinite 2D Ising, 2x2 blocked (chi = 4, four spins per tensor), width-L
+    strips in both directions (Sec. IV.B): wall time per coupling, the free
+    energy per spin against Onsager's, and the streaming passes' algorithmic
+    bytes over that wall time."""
+    import torch
+
+    from oracle import strips as S
+
+    ctx = pne.Context(0)
+    ctx.strip_expand(P.ising_blocked_tensor(0.3), 2)
+    for beta in betas:
+        A = P.ising_blocked_tensor(beta)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = ctx.strip_expand(A, L)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        its = [int(x) for x in r["iters"]]
+        alg = sum(its[d * L + k - 1] * strip_bytes(4, k) for d in (0, 1) for k in range(1, L + 1))
+        gbs = alg / (ms * 1e-3) / 1e9
+        exact = S.onsager_f(beta)
+        out = {"workload": f"infinite 2D Ising, 2x2 blocked (chi=4), width-{L} strips both directions, fp64",
+               "beta": beta, "ms": round(ms, 2), "f_per_spin": r["f"] / 4, "f_bp_per_spin": r["f_bp"] / 4,
+               "onsager_f_per_spin": exact, "abs_err_per_spin": abs(r["f"] / 4 - exact),
+               "bp_abs_err_per_spin": abs(r["f_bp"] / 4 - exact), "status": r["status"],
+               "power_iters": r["power_iters"], "power_iters_width_L": [its[L - 1], its[2 * L - 1]],
+               "alg_bytes": alg, "achieved_GBps_over_wall": round(gbs, 1),
+               "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)}
+        print(json.dumps(out), flush=True)
+    ctx.close()
+
+
 def workloads_bench(pne, P, steps: int):
     """The other workloads at batch scale, one JSON line each: step time,
     networks/s, per-kernel device time (HIP events around every launch) with
@@ -360,6 +403,8 @@ def main():
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
     ap.add_argument("--workloads", action="store_true",
                     help="instead: the other workloads at batch scale with per-kernel rooflines")
+    ap.add_argument("--strips", type=int, default=0, metavar="L",
+                    help="instead: only the infinite-lattice strip expansion at width L")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, run plain device copies of MIB MiB (HBM counter calibration)")
     args = ap.parse_args()
@@ -380,6 +425,10 @@ def main():
 
     if args.workloads:
         workloads_bench(pne, P, max(1, min(args.steps, 5)))
+        strips_bench(pne, P)
+        return
+    if args.strips:
+        strips_bench(pne, P, L=args.strips)
         return
 
     if args.copy_calibration:

@@ -344,6 +344,84 @@ pne_status pne_server_get_stats(pne_server *server, pne_server_stats *out);
  * option or with a NULL argument. */
 pne_status pne_server_completed(pne_server *server, uint64_t *tickets, int32_t capacity, int32_t *n);
 
+/* ------------------------------------------------------------------------
+ * Strip expansion of an infinite, translation-invariant square lattice
+ * (Sec. IV.B).  One tensor A repeats on every site; the result is the free
+ * energy per site f = -lim ln Z_N / N.
+ *
+ * The lattice is expanded over width-L strip partitions: L vertical
+ * partitions (every L-th column line at offsets 0..L-1, each transecting the
+ * horizontal bonds that cross it) and, with two_d, L horizontal ones.  P on a
+ * bond is the rank-1 projector of the uniform BP fixed point (Eq. A7, oblique
+ * form, which includes 1 / (message overlap)).  Per unit cell (L x L sites,
+ * or L sites of a row with vertical partitions only) the combinatorial form
+ * (Eq. A6) sums, over non-empty sets of partitions with sign + for an odd
+ * count and - for an even one, the product of the pieces the partitions cut
+ * the cell into:
+ *   lam_k   leading eigenvalue of the width-k vertical transfer matrix (k
+ *           sites in a row, the outer legs capped by the BP messages), over
+ *           the horizontal bond overlap;
+ *   gam_k   the same for width-k horizontal strips;
+ *   Z_kp    the k-column, p-row patch with every outer leg capped, over
+ *           n_v^k n_h^p;
+ * strips of width g contribute lam_g per row (gam_g per column), patches
+ * Z_(gv)(gh).  For L = 2 and vertical strips only this is
+ * f = -ln(2 lam_2 - lam_1^2) / 2; with both directions it is the paper's
+ * R_1 - R_2 + R_3 - R_4 form.
+ *
+ * Everything runs on the device: BP, power iteration of every transfer
+ * matrix (k streaming passes per application over a chi^k vector), the
+ * patches (the first L applications of the vertical iteration started from
+ * the product of the top caps), and the cell sum.  Leading eigenvalues must
+ * be real and dominant (positive tensors, for instance); a power iteration
+ * that does not reach power_tol within power_max_iter steps gives the
+ * warning status with its last estimate.
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t L;              /* strip width, 1..16 (chi^(L+1) <= 2^28)                */
+    int32_t two_d;          /* 1: vertical and horizontal strips; 0: vertical only  */
+    double bp_tol;          /* BP stop: largest entry change (1e-14)                  */
+    int32_t bp_max_iter;    /* BP sweep cap (10000)                                   */
+    int32_t power_max_iter; /* power-iteration cap per strip (20000), >= L           */
+    double power_tol;       /* stop when two successive relative changes of the
+                               eigenvalue estimate are <= power_tol (1e-13)           */
+    int32_t check_every;    /* iterations between host convergence checks (8)        */
+    int32_t reserved[3];
+} pne_strip_options;
+
+typedef struct {
+    int32_t status;         /* pne_status; WARN_BP_NOT_CONVERGED also when a power
+                               iteration hit its cap                                  */
+    int32_t bp_iters;       /* BP sweeps                                              */
+    double f;               /* free energy per site from the strip expansion         */
+    double f_bp;            /* -ln(z / (n_h n_v)): the BP value per site              */
+    double bp_residual;     /* last BP sweep's largest entry change                   */
+    double cell_sum;        /* the per-cell sum, with every piece divided by the BP
+                               value per site to the power of its site count          */
+    int32_t power_iters;    /* power-iteration steps over all strips                  */
+    int32_t n_unconverged;  /* strips whose power iteration hit the cap               */
+    double *lam;            /* caller buffer [L] or NULL: lam_k / w_bp^k, k = 1..L   */
+    double *gam;            /* caller buffer [L] or NULL (two_d): gam_k / w_bp^k     */
+    double *patch;          /* caller buffer [L*L] or NULL (two_d): Z_kp / w_bp^(k p)
+                               at [(k-1) L + (p-1)]                                   */
+    int32_t *iters;         /* caller buffer [2*L] or NULL: power-iteration steps of
+                               width k at [k-1] (vertical) and [L+k-1] (horizontal)  */
+    int64_t reserved;
+} pne_strip_result;
+
+/* Defaults: L = 2, two_d = 1, tolerances and caps as listed above. */
+pne_status pne_strip_options_default(pne_strip_options *opt);
+/* A: host FP64 tensor, C order over (-x, +x, -y, +y), every leg of dimension
+ * chi (2..6); copied.  res: filled; its lam/gam/patch buffers, when not
+ * NULL, receive the per-width values.  Device memory: about
+ * 16 (chi^L + chi^(L+1)) bytes, allocated and freed by the call; runs on the
+ * context's stream and returns when done.  Errors: INVALID_ARG (null, L or
+ * caps out of range, non-finite entry), UNSUPPORTED (chi, size),
+ * OUT_OF_MEMORY, SINGULAR (BP value per site not positive, a zero bond
+ * overlap, or a cell sum that is not positive). */
+pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t chi, const pne_strip_options *opt,
+                            pne_strip_result *res);
+
 #ifdef __cplusplus
 }
 #endif

@@ -537,6 +537,10 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on
 
 }  // extern "C"
 
+hipStream_t pne::ctx_stream(pne_ctx *ctx) { return ctx->stream; }
+int pne::ctx_device(pne_ctx *ctx) { return ctx->device; }
+pne_status pne::ctx_fail(pne_ctx *ctx, pne_status st, const std::string &msg) { return fail(ctx, st, msg); }
+
 pne_status pne::network_create_on(pne_ctx *ctx, const pne_network_desc *desc, int on_device, hipStream_t stream,
                                   pne_network **out) {
     if (!ctx || !desc || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "null argument");

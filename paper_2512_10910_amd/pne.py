@@ -121,6 +121,37 @@ RESULT_DTYPE = np.dtype({
 })
 
 
+class StripOptions(ctypes.Structure):
+    _fields_ = [
+        ("L", ctypes.c_int32),
+        ("two_d", ctypes.c_int32),
+        ("bp_tol", ctypes.c_double),
+        ("bp_max_iter", ctypes.c_int32),
+        ("power_max_iter", ctypes.c_int32),
+        ("power_tol", ctypes.c_double),
+        ("check_every", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
+    ]
+
+
+class StripResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("bp_iters", ctypes.c_int32),
+        ("f", ctypes.c_double),
+        ("f_bp", ctypes.c_double),
+        ("bp_residual", ctypes.c_double),
+        ("cell_sum", ctypes.c_double),
+        ("power_iters", ctypes.c_int32),
+        ("n_unconverged", ctypes.c_int32),
+        ("lam", _f64p),
+        ("gam", _f64p),
+        ("patch", _f64p),
+        ("iters", ctypes.POINTER(ctypes.c_int32)),
+        ("reserved", ctypes.c_int64),
+    ]
+
+
 # exported C symbols and their prototypes: (restype, argtypes)
 _PROTOS = {
     "pne_options_default": (ctypes.c_int, [ctypes.POINTER(Options)]),
@@ -131,6 +162,9 @@ _PROTOS = {
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "pne_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pne_network_set_partitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i32p]),
+    "pne_strip_options_default": (ctypes.c_int, [ctypes.POINTER(StripOptions)]),
+    "pne_strip_expand": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32, ctypes.POINTER(StripOptions),
+                                        ctypes.POINTER(StripResult)]),
     "pne_count_configurations": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32, ctypes.c_int32, _i32p,
                                                 _i32p, ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.POINTER(ctypes.c_int64)]),
@@ -395,6 +429,37 @@ class Context:
                                                ctypes.byref(best)), self.handle)
         return {"graph": bool(best.flags & PNE_FLAG_GRAPH),
                 "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags)}
+
+    def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
+                     power_max_iter: int = 20000, check_every: int = 8) -> dict:
+        """Strip expansion of the infinite lattice of tensor A (legs -x, +x, -y, +y;
+        Sec. IV.B): free energy per site and the per-width quantities."""
+        A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
+        if A.ndim != 4 or len(set(A.shape)) != 1:
+            raise ValueError("A must be a rank-4 tensor with equal leg dimensions")
+        chi = int(A.shape[0])
+        opt = StripOptions()
+        _check(self.lib, self.lib.pne_strip_options_default(ctypes.byref(opt)))
+        opt.L, opt.two_d, opt.bp_tol = int(L), 1 if two_d else 0, float(bp_tol)
+        opt.power_tol, opt.power_max_iter, opt.check_every = float(power_tol), int(power_max_iter), int(check_every)
+        lam = np.zeros(L)
+        gam = np.zeros(L)
+        patch = np.zeros((L, L))
+        res = StripResult()
+        res.lam = lam.ctypes.data_as(_f64p)
+        res.gam = gam.ctypes.data_as(_f64p)
+        res.patch = patch.ctypes.data_as(_f64p)
+        iters = np.zeros(2 * L, np.int32)
+        res.iters = iters.ctypes.data_as(ctypes.POINTER(ctypes.c_int32))
+        st = _check(self.lib, self.lib.pne_strip_expand(self.handle, A.ctypes.data_as(_f64p), chi, ctypes.byref(opt),
+                                                        ctypes.byref(res)), self.handle)
+        out = {"status": int(st), "f": res.f, "f_bp": res.f_bp, "bp_iters": res.bp_iters,
+               "bp_residual": res.bp_residual, "cell_sum": res.cell_sum, "power_iters": res.power_iters,
+               "n_unconverged": res.n_unconverged, "lam_ratio": lam, "iters": iters}
+        if two_d:
+            out["gam_ratio"] = gam
+            out["patch_ratio"] = patch
+        return out
 
     def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
         b = self.batch([net], K, precision, tol, max_iter)

@@ -438,3 +438,33 @@ def grid3_multi_partitions(net: Network):
     for d in (1, 2):
         parts.append(cut(lambda u, v, d=d: {sum(xy(u)), sum(xy(v))} == {d, d + 1}))
     return parts
+
+
+# ----------------------------------------------------------------------------
+# uniform tensors of infinite square lattices (Sec. IV.B); legs (-x, +x, -y, +y)
+
+
+def ising_uniform_tensor(beta: float, J: float = 1.0) -> np.ndarray:
+    """One Ising site of the infinite square lattice (bond dimension 2)."""
+    return _ising_site(_ising_w(beta, J), 4)
+
+
+def ising_blocked_tensor(beta: float, J: float = 1.0) -> np.ndarray:
+    """2 x 2 block of Ising sites (four spins), bond dimension 4.
+
+    Block sites a (top left), b (top right), c (bottom left), d (bottom
+    right), each with legs (-x, +x, -y, +y); the four inner bonds are summed.
+    A merged outer leg is 2 * (top or left spin's bond) + (other spin's bond):
+    -x = (a, c), +x = (b, d), -y = (a, b), +y = (c, d).
+    """
+    T = ising_uniform_tensor(beta, J)
+    # inner bonds: a.+x = b.-x (p), a.+y = c.-y (q), b.+y = d.-y (s), c.+x = d.-x (t)
+    full = np.einsum("Lpuq,pRvs,Mtqe,tNsf->LMRNuvef", T, T, T, T, optimize=True)
+    # legs: -x = (L: a, M: c), +x = (R: b, N: d), -y = (u: a, v: b), +y = (e: c, f: d)
+    return np.ascontiguousarray(full.reshape(4, 4, 4, 4))
+
+
+def random_uniform_tensor(chi: int, seed: int = 0, bias: float = 1.0) -> np.ndarray:
+    """Uniform tensor with entries i.i.d. uniform in [-1 + bias, 1 + bias]."""
+    rng = np.random.default_rng(seed)
+    return rng.uniform(-1.0 + bias, 1.0 + bias, (chi,) * 4)

@@ -63,6 +63,10 @@ int main(void) {
   P(pne_server_options, max_batch) P(pne_server_options, pipeline_depth) P(pne_server_options, completion_queue)
   P(pne_server_stats, device_bytes_admitted) P(pne_server_stats, latency_p50_ms) P(pne_server_stats, busy_s)
   P(pne_server_stats, launch_s)
+  printf("stopt %zu\nstres %zu\n", sizeof(pne_strip_options), sizeof(pne_strip_result));
+  P(pne_strip_options, bp_tol) P(pne_strip_options, power_max_iter) P(pne_strip_options, power_tol)
+  P(pne_strip_options, check_every) P(pne_strip_result, f) P(pne_strip_result, cell_sum)
+  P(pne_strip_result, power_iters) P(pne_strip_result, lam) P(pne_strip_result, iters)
   return 0;
 }
 ''')
@@ -74,11 +78,14 @@ int main(void) {
     assert int(out["res"]) == ctypes.sizeof(B.ResultStruct)
     assert int(out["sopt"]) == ctypes.sizeof(B.ServerOptions)
     assert int(out["sstat"]) == ctypes.sizeof(B.ServerStats)
+    assert int(out["stopt"]) == ctypes.sizeof(B.StripOptions)
+    assert int(out["stres"]) == ctypes.sizeof(B.StripResult)
     for key, val in out.items():
         if "." in key:
             T, f = key.split(".")
             cls = {"pne_network_desc": B.NetworkDesc, "pne_options": B.Options, "pne_result": B.ResultStruct,
-                   "pne_server_options": B.ServerOptions, "pne_server_stats": B.ServerStats}[T]
+                   "pne_server_options": B.ServerOptions, "pne_server_stats": B.ServerStats,
+                   "pne_strip_options": B.StripOptions, "pne_strip_result": B.StripResult}[T]
             assert getattr(cls, f).offset == int(val), key
 
 
@@ -176,3 +183,13 @@ def test_three_open_sites_unsupported(lib):
     t = [np.ones((2, 2, 2)), np.ones((2, 2, 2)), np.ones((2, 2, 2))]
     bonds = [(0, 0, 1, 0), (1, 1, 2, 0), (2, 1, 0, 1)]
     assert _desc_status(t, bonds, [(0, 2), (1, 2), (2, 2)]) == B.PNE_ERR_UNSUPPORTED
+
+
+def test_strip_options_default_and_null_arguments(lib):
+    opt = B.StripOptions()
+    assert lib.pne_strip_options_default(ctypes.byref(opt)) == 0
+    assert (opt.L, opt.two_d, opt.bp_max_iter, opt.power_max_iter, opt.check_every) == (2, 1, 10000, 20000, 8)
+    assert opt.bp_tol == 1e-14 and opt.power_tol == 1e-13
+    assert lib.pne_strip_options_default(None) == -1
+    res = B.StripResult()
+    assert lib.pne_strip_expand(None, None, 2, ctypes.byref(opt), ctypes.byref(res)) == -1
