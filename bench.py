@@ -260,13 +260,17 @@ def kernel_bytes(pne, nets_in, paths, iters, n_clusters, K: int, slice_bytes: in
     return alg
 
 
-def strip_bytes(chi: int, k: int) -> int:
+def strip_bytes(chi: int, k: int, paired: bool = True) -> int:
     """Algorithmic HBM bytes of one width-k transfer-matrix application: the
     first pass reads chi^k and writes chi^(k+1) entries, each middle pass
     reads and writes chi^(k+1), the last reads chi^(k+1) plus the input
-    vector and writes chi^k (FP64)."""
-    if k == 1:
-        return 8 * 3 * chi
+    vector and writes chi^k (FP64).  Paired passes (chi <= 4) apply two sites
+    each, so a width-k application makes about k/2 passes instead of k."""
+    if k == 1 or (k == 2 and paired and chi <= 4):
+        return 8 * 3 * chi ** k
+    if paired and chi <= 4:
+        n_mid = (k - 4) // 2 if k % 2 == 0 else (k - 3) // 2
+        return 8 * (3 * chi ** k + 2 * (1 + n_mid) * chi ** (k + 1))
     return 8 * (3 * chi ** k + 2 * (k - 1) * chi ** (k + 1))
 
 

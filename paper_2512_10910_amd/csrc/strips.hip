@@ -280,6 +280,183 @@ __global__ void __launch_bounds__(kSt) k_strip_pass(const double *__restrict__ X
     }
 }
 
+// Two neighbouring sites j, j+1 in one pass (chi <= 4): input
+// [h][pre][i1][i2][post], output [h'][pre][o1][o2][post].  Site j maps
+// (h, i1) -> (g, o1) for every i2 with M1 ((HI chi) x (chi chi)); site j+1
+// maps (g, i2) -> (h', o2) for every o1 with M2 ((chi chi) x (HO chi)).
+// A block takes 64 consecutive (pre, post) positions and stages their inputs
+// in LDS; wave w then computes every output with o1 = w, so a thread keeps
+// only one chi x chi slice of the intermediate.  Staging follows memory
+// order: with post >= 64 a wave's 64 positions are 64 consecutive doubles
+// for every input index; with post < 64 (the last sites of an application)
+// the block's positions cover whole rows of post, so for each h its inputs
+// are one contiguous run of 64 chi^2 doubles, copied as such, and the
+// outputs are written back the same way through LDS.  Halves the passes over
+// the vector; the rest as in k_strip_pass.
+template <int CV, int HI, int HO, bool LAST, bool CONTIG>
+__global__ void __launch_bounds__(64 * CV) k_strip_pass2(const double *__restrict__ X, double *__restrict__ Y,
+                                                         const double *__restrict__ M1, const double *__restrict__ M2,
+                                                         int64_t pre, int64_t post, int post_shift,
+                                                         const double *__restrict__ scale,
+                                                         const double *__restrict__ Xo,
+                                                         const double *__restrict__ bv, int pre_digits,
+                                                         double *__restrict__ partials) {
+    constexpr int G = CV;                               // bond between the two sites
+    constexpr int NT = 64 * CV;                         // threads
+    constexpr int NV = HI * CV * CV;                    // inputs per position
+    constexpr int NO = HO * CV * CV;                    // outputs per position
+    constexpr int NB = (CONTIG && NO > NV) ? NO : NV;
+    constexpr int RUN = 64 * CV * CV;                   // contiguous run per bond index h
+    __shared__ double buf[NB][64];
+    __shared__ double bq[CONTIG && LAST ? 64 : 1];      // bottom-cap product per local row
+    __shared__ double red[3][CV];
+    const int tid = threadIdx.x, pos = tid & 63;
+    // the wave's o1 is uniform, so the site matrices are read with scalar
+    // loads straight from global memory (no LDS traffic for them)
+    const int o1 = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int64_t n = pre * post;
+    const int64_t t0 = (int64_t)blockIdx.x * 64;
+    const int64_t t = t0 + pos;
+    const double s = HI == 1 ? gld(scale) : 1.0;
+    // CONTIG (post = 2^post_shift < 64, n a multiple of 64): the block holds
+    // whole rows p0 .. p0 + 64/post - 1, and for each h its inputs are the run
+    // ((pl * CV + i1) * CV + i2) * post + q at (h pre + p0) CV^2 post.
+    const int64_t p0 = t0 >> post_shift;
+    const int pmask = (1 << post_shift) - 1;
+    if (CONTIG) {
+        for (int e = tid; e < HI * RUN; e += NT) {
+            const int h = e / RUN, r = e - h * RUN;
+            const int q = r & pmask, rest = r >> post_shift;
+            const int i2 = rest % CV, i1 = (rest / CV) % CV, pl = rest / (CV * CV);
+            buf[(h * CV + i1) * CV + i2][(pl << post_shift) + q] =
+                s * gld(&X[((int64_t)h * pre + p0) * (CV * CV) * post + r]);
+        }
+        if (LAST && tid < (64 >> post_shift)) {
+            int64_t r = p0 + tid;
+            double b = 1.0;
+            for (int d = 0; d < pre_digits; ++d) {
+                b *= bv[r % CV];
+                r /= CV;
+            }
+            bq[tid] = b;
+        }
+    } else if (t < n) {
+        // input (h, i1, i2) of position (p, q) sits at p CV^2 post + q +
+        // h pre CV^2 post + (i1 CV + i2) post
+        const int64_t p = t / post, q = t - p * post;
+        const double *xp = X + p * (CV * CV) * post + q;
+        const int64_t hs = pre * (CV * CV) * post;
+        for (int v = o1; v < NV; v += CV) {
+            const int h = v / (CV * CV), c = v % (CV * CV);
+            buf[v][pos] = s * gld(xp + h * hs + c * post);
+        }
+    }
+    __syncthreads();
+    double sxy = 0.0, syy = 0.0, sby = 0.0;
+    if (t < n) {
+        // mid[g][i2] = sum_{h, i1} M1[(h, i1), (g, o1)] x[(h, i1, i2)]; each
+        // staged input is read from LDS once
+        double mid[G][CV];
+#pragma unroll
+        for (int g = 0; g < G; ++g)
+#pragma unroll
+            for (int i2 = 0; i2 < CV; ++i2) mid[g][i2] = 0.0;
+#pragma unroll 4
+        for (int e = 0; e < HI * CV; ++e)
+#pragma unroll
+            for (int i2 = 0; i2 < CV; ++i2) {
+                const double x = buf[e * CV + i2][pos];
+#pragma unroll
+                for (int g = 0; g < G; ++g) mid[g][i2] = fma(M1[e * (G * CV) + g * CV + o1], x, mid[g][i2]);
+            }
+        double bpre = 1.0;
+        int64_t p = 0, q = 0;
+        double *yp = Y;
+        const double *xop = Xo;
+        if (!CONTIG) {
+            p = t / post;
+            q = t - p * post;
+            // output (h', o1, o2) at p CV^2 post + q + h' pre CV^2 post + (o1 CV + o2) post
+            yp = Y + p * (CV * CV) * post + q + (int64_t)(o1 * CV) * post;
+            if (LAST) xop = Xo + p * (CV * CV) * post + q + (int64_t)(o1 * CV) * post;
+            if (LAST) {
+                int64_t r = p;
+                for (int d = 0; d < pre_digits; ++d) {
+                    bpre *= bv[r % CV];
+                    r /= CV;
+                }
+            }
+        }
+        double out[CONTIG ? HO : 1][CV];
+        // y[(h', o1, o2)] = sum_{g, i2} m2[(g, i2), (h', o2)] mid[g][i2]
+#pragma unroll
+        for (int h = 0; h < HO; ++h)
+#pragma unroll
+            for (int o2 = 0; o2 < CV; ++o2) {
+                double acc = 0.0;
+#pragma unroll
+                for (int g = 0; g < G; ++g)
+#pragma unroll
+                    for (int i2 = 0; i2 < CV; ++i2)
+                        acc = fma(M2[(g * CV + i2) * (HO * CV) + h * CV + o2], mid[g][i2], acc);
+                if (CONTIG) {
+                    out[CONTIG ? h : 0][o2] = acc;
+                } else {
+                    const int64_t oi = (int64_t)h * pre * (CV * CV) * post + o2 * post;
+                    gst(yp + oi, acc);
+                    if (LAST) {
+                        const double x0 = gld(xop + oi);
+                        sxy = fma(x0, acc, sxy);
+                        syy = fma(acc, acc, syy);
+                        sby = fma(bpre * bv[o1] * bv[o2], acc, sby);
+                    }
+                }
+            }
+        if (CONTIG) {
+            __syncthreads();  // every read of the staged inputs is done (all positions are < n here)
+#pragma unroll
+            for (int h = 0; h < HO; ++h)
+#pragma unroll
+                for (int o2 = 0; o2 < CV; ++o2) buf[(h * CV + o1) * CV + o2][pos] = out[CONTIG ? h : 0][o2];
+        }
+    }
+    if (CONTIG) {
+        __syncthreads();
+        for (int e = tid; e < HO * RUN; e += NT) {
+            const int h = e / RUN, r = e - h * RUN;
+            const int q = r & pmask, rest = r >> post_shift;
+            const int c2 = rest % CV, c1 = (rest / CV) % CV, pl = rest / (CV * CV);
+            const double y = buf[(h * CV + c1) * CV + c2][(pl << post_shift) + q];
+            const int64_t oi = ((int64_t)h * pre + p0) * (CV * CV) * post + r;
+            gst(&Y[oi], y);
+            if (LAST) {
+                const double x0 = gld(&Xo[oi]);
+                sxy = fma(x0, y, sxy);
+                syy = fma(y, y, syy);
+                sby = fma(bq[CONTIG && LAST ? pl : 0] * bv[c1] * bv[c2], y, sby);
+            }
+        }
+    }
+    if (LAST) {
+        for (int o = 32; o > 0; o >>= 1) {
+            sxy += __shfl_xor(sxy, o, 64);
+            syy += __shfl_xor(syy, o, 64);
+            sby += __shfl_xor(sby, o, 64);
+        }
+        if (pos == 0) {
+            red[0][o1] = sxy;
+            red[1][o1] = syy;
+            red[2][o1] = sby;
+        }
+        __syncthreads();
+        if (tid < 3) {
+            double v = 0.0;
+            for (int k = 0; k < CV; ++k) v += red[tid][k];
+            partials[(int64_t)blockIdx.x * 3 + tid] = v;
+        }
+    }
+}
+
 // Sum of the last pass's block sums in a fixed order; hist[4 it ..] =
 // (x.y, y.y, b.y, scale applied this iteration); the next scale is 1/|y|.
 __global__ void __launch_bounds__(kSt) k_strip_reduce(const double *__restrict__ partials, int64_t nblocks,
@@ -439,6 +616,59 @@ hipError_t launch_pass(int variant, const double *X, double *Y, const double *M,
     return hipGetLastError();
 }
 
+template <int CV, bool CONTIG>
+hipError_t launch_pair_c(int variant, const double *X, double *Y, const double *M1, const double *M2, int64_t pre,
+                         int64_t post, int post_shift, const double *scale, const double *Xo, const double *bv,
+                         int pre_digits, double *partials, hipStream_t s) {
+    const int64_t n = pre * post;
+    const dim3 grid((unsigned)((n + 63) / 64)), block(64 * CV);
+    switch (variant) {
+        case 0:  // first two sites
+            hipLaunchKernelGGL((k_strip_pass2<CV, 1, CV, false, CONTIG>), grid, block, 0, s, X, Y, M1, M2, pre, post,
+                               post_shift, scale, Xo, bv, pre_digits, partials);
+            break;
+        case 1:  // two middle sites
+            hipLaunchKernelGGL((k_strip_pass2<CV, CV, CV, false, CONTIG>), grid, block, 0, s, X, Y, M1, M2, pre,
+                               post, post_shift, scale, Xo, bv, pre_digits, partials);
+            break;
+        case 2:  // the last two sites
+            hipLaunchKernelGGL((k_strip_pass2<CV, CV, 1, true, CONTIG>), grid, block, 0, s, X, Y, M1, M2, pre, post,
+                               post_shift, scale, Xo, bv, pre_digits, partials);
+            break;
+        default:  // both sites of a width-2 strip
+            hipLaunchKernelGGL((k_strip_pass2<CV, 1, 1, true, CONTIG>), grid, block, 0, s, X, Y, M1, M2, pre, post,
+                               post_shift, scale, Xo, bv, pre_digits, partials);
+            break;
+    }
+    return hipGetLastError();
+}
+
+// Whole rows of post in every block of 64 positions: post a power of two
+// below 64 and the position count a multiple of 64.
+template <int CV>
+hipError_t launch_pair(int variant, const double *X, double *Y, const double *M1, const double *M2, int64_t pre,
+                       int64_t post, const double *scale, const double *Xo, const double *bv, int pre_digits,
+                       double *partials, hipStream_t s) {
+    const int64_t n = pre * post;
+    if (post < 64 && (post & (post - 1)) == 0 && n % 64 == 0) {
+        int shift = 0;
+        while ((int64_t(1) << shift) < post) ++shift;
+        return launch_pair_c<CV, true>(variant, X, Y, M1, M2, pre, post, shift, scale, Xo, bv, pre_digits, partials,
+                                       s);
+    }
+    return launch_pair_c<CV, false>(variant, X, Y, M1, M2, pre, post, 0, scale, Xo, bv, pre_digits, partials, s);
+}
+
+hipError_t pair(int chi, int variant, const double *X, double *Y, const double *M1, const double *M2, int64_t pre,
+                int64_t post, const double *scale, const double *Xo, const double *bv, int pre_digits,
+                double *partials, hipStream_t s) {
+    switch (chi) {
+        case 2: return launch_pair<2>(variant, X, Y, M1, M2, pre, post, scale, Xo, bv, pre_digits, partials, s);
+        case 3: return launch_pair<3>(variant, X, Y, M1, M2, pre, post, scale, Xo, bv, pre_digits, partials, s);
+        default: return launch_pair<4>(variant, X, Y, M1, M2, pre, post, scale, Xo, bv, pre_digits, partials, s);
+    }
+}
+
 hipError_t pass(int chi, int variant, const double *X, double *Y, const double *M, int64_t pre, int64_t post,
                 const double *scale, const double *Xo, const double *bv, int pre_digits, double *partials,
                 hipStream_t s) {
@@ -498,7 +728,7 @@ extern "C" pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t ch
     const int c4 = chi * chi * chi * chi;
     const int mats = c4 + 2 * chi * chi * chi + chi * chi + 2 * chi;
     const int64_t vec = ipow(chi, L);
-    const int64_t nblk_max = (ipow(chi, L - 1) + kSt - 1) / kSt;
+    const int64_t nblk_max = std::max((ipow(chi, L - 1) + kSt - 1) / kSt, (ipow(chi, std::max(L - 2, 0)) + 63) / 64);
     const int hist_n = 4 * opt->power_max_iter;
     // one allocation: A, msg, scalars, mats x2, out lam/gam/patch, combine out, scale, hist, partials,
     // x, y, t0, t1
@@ -561,13 +791,38 @@ extern "C" pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t ch
             hipLaunchKernelGGL(k_fill_product, dim3((unsigned)((nk + kSt - 1) / kSt)), dim3(kSt), 0, s, x, top, chi, k,
                                nk, D(oScale));
             ST_TRY(hipGetLastError());
-            const int64_t nblk = (ipow(chi, k - 1) + kSt - 1) / kSt;
+            // the last pass runs one thread per chi^2 outputs (a pair) or chi (one site)
+            const bool paired = chi <= 4 && !opt->single_site_passes;
+            // the last pass is a pair (64 positions per block) when k is even
+            const bool last_pair = paired && k >= 2 && k % 2 == 0;
+            const int64_t nblk = k == 1 ? 1
+                                 : last_pair ? (ipow(chi, k - 2) + 63) / 64
+                                             : (ipow(chi, k - 1) + kSt - 1) / kSt;
             const int min_it = (dir == 0 && opt->two_d) ? L : 2;
             int it = 0, n_done = 0;
             bool conv = false;
             while (it < opt->power_max_iter && !conv) {
                 if (k == 1) {
                     ST_TRY(pass(chi, 3, x, y, Msingle, 1, 1, D(oScale), x, bot, 0, D(oPart), s));
+                } else if (paired && k == 2) {
+                    ST_TRY(pair(chi, 3, x, y, Mfirst, Mlast, 1, 1, D(oScale), x, bot, 0, D(oPart), s));
+                } else if (paired) {
+                    // sites (1, 2) from x, then pairs (j, j + 1); the last one or two sites write y
+                    double *t0 = D(oT0), *t1 = D(oT1);
+                    ST_TRY(pair(chi, 0, x, t0, Mfirst, Mmid, 1, ipow(chi, k - 2), D(oScale), nullptr, nullptr, 0,
+                                nullptr, s));
+                    int j = 3;  // next site to apply
+                    while (k - j + 1 > 2) {
+                        ST_TRY(pair(chi, 1, t0, t1, Mmid, Mmid, ipow(chi, j - 1), ipow(chi, k - j - 1), nullptr,
+                                    nullptr, nullptr, 0, nullptr, s));
+                        std::swap(t0, t1);
+                        j += 2;
+                    }
+                    if (k - j + 1 == 2)
+                        ST_TRY(pair(chi, 2, t0, y, Mmid, Mlast, ipow(chi, k - 2), 1, nullptr, x, bot, k - 2, D(oPart),
+                                    s));
+                    else
+                        ST_TRY(pass(chi, 2, t0, y, Mlast, ipow(chi, k - 1), 1, nullptr, x, bot, k - 1, D(oPart), s));
                 } else {
                     double *t0 = D(oT0), *t1 = D(oT1);
                     ST_TRY(pass(chi, 0, x, t0, Mfirst, 1, ipow(chi, k - 1), D(oScale), nullptr, nullptr, 0, nullptr,

@@ -130,7 +130,8 @@ class StripOptions(ctypes.Structure):
         ("power_max_iter", ctypes.c_int32),
         ("power_tol", ctypes.c_double),
         ("check_every", ctypes.c_int32),
-        ("reserved", ctypes.c_int32 * 3),
+        ("single_site_passes", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 2),
     ]
 
 
@@ -431,7 +432,7 @@ class Context:
                 "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags)}
 
     def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
-                     power_max_iter: int = 20000, check_every: int = 8) -> dict:
+                     power_max_iter: int = 20000, check_every: int = 8, single_site_passes: bool = False) -> dict:
         """Strip expansion of the infinite lattice of tensor A (legs -x, +x, -y, +y;
         Sec. IV.B): free energy per site and the per-width quantities."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
@@ -442,6 +443,7 @@ class Context:
         _check(self.lib, self.lib.pne_strip_options_default(ctypes.byref(opt)))
         opt.L, opt.two_d, opt.bp_tol = int(L), 1 if two_d else 0, float(bp_tol)
         opt.power_tol, opt.power_max_iter, opt.check_every = float(power_tol), int(power_max_iter), int(check_every)
+        opt.single_site_passes = 1 if single_site_passes else 0
         lam = np.zeros(L)
         gam = np.zeros(L)
         patch = np.zeros((L, L))

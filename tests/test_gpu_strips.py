@@ -51,10 +51,13 @@ def _rel(a, b):
     return abs(a - b) / max(abs(b), 1e-300)
 
 
+@pytest.mark.parametrize("single_site", [False, True])
 @pytest.mark.parametrize("name,make,L", CASES)
-def test_strip_expansion_matches_oracle(ctx, name, make, L):
+def test_strip_expansion_matches_oracle(ctx, name, make, L, single_site):
+    """Both pass layouts: two neighbouring sites per pass (chi <= 4, the
+    default) and one site per pass."""
     A = make()
-    r = ctx.strip_expand(A, L)
+    r = ctx.strip_expand(A, L, single_site_passes=single_site)
     ref = S.strip_expansion(A, L)
     w = math.exp(-ref["f_bp"])
     print(name, r["f"], ref["f"], r["power_iters"], flush=True)
@@ -83,6 +86,8 @@ def test_blocked_ising_full_width(ctx):
     beta = 0.3
     A = P.ising_blocked_tensor(beta)
     r = ctx.strip_expand(A, 12)
+    r1 = ctx.strip_expand(A, 12, single_site_passes=True)
+    assert abs(r["f"] - r1["f"]) < 1e-13
     assert r["status"] == 0 and r["n_unconverged"] == 0
     m = S.uniform_bp(A)
     w = S.bp_site_weight(A, m)
