@@ -335,6 +335,10 @@ def workloads_bench(pne, P, steps: int):
         ("3x2 double loop U[0,2] D=6 (seed 60000+i), three vertical partitions, Eq. A4 complete (K=7), fp64",
          lambda: [P.small_network(3, 2, "random", 6, seed=60000 + i) for i in range(16384)], 7, "fp64", True,
          P.double_loop_partitions),
+        ("3x4 U[0,2] D=4 (seed 70000+i), five lines with the two 3x3 principal terms refined by six partitions "
+         "(recursive, Sec. IV.A), complete (K=17), fp64",
+         lambda: [P.small_network(3, 4, "random", 4, seed=70000 + i) for i in range(8192)], 17, "fp64", True,
+         P.grid3x4_recursive_partitions),
     ]
     sb = {"fp64": 8, "fp32": 4, "bf16": 2}
     for label, make, K, prec, check, *rest in [c + (None,) for c in cases] + parted:
@@ -344,7 +348,11 @@ def workloads_bench(pne, P, steps: int):
         nets = [ctx.network(n) for n in nets_in]
         if parts_of is not None:
             for n, x in zip(nets, nets_in):
-                n.set_partitions(parts_of(x))
+                pp = parts_of(x)
+                parts, subs = pp if isinstance(pp, tuple) else (pp, {})
+                n.set_partitions(parts)
+                for sx, inner in subs.items():
+                    n.set_subpartitions(sx, inner)
         b = ctx.batch(nets, K=K, precision=prec, profile=True)
         b.run_arrays()
         b.kernel_times(reset=True)
@@ -376,7 +384,9 @@ def workloads_bench(pne, P, steps: int):
         if check and parts_of is not None:
             from oracle import partitioned as PT
 
-            _, lg = PT.combinatorial_pne(nets_in[0], parts_of(nets_in[0]))
+            pp = parts_of(nets_in[0])
+            parts, subs = pp if isinstance(pp, tuple) else (pp, {})
+            _, lg = PT.recursive_pne(nets_in[0], parts, subs)
             out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - lg) / max(1.0, abs(lg))
         elif check:
             ref = O.pne_contract(nets_in[0], K)

@@ -176,6 +176,20 @@ pne_status pne_network_destroy(pne_network *net);
 pne_status pne_network_set_partitions(pne_network *net, int32_t n_partitions, const int32_t *part_begin,
                                       const int32_t *part_bond);
 
+/* Recursive partitioning (Sec. IV.A).  The term of the first-level subset
+ * x_mask (bit p: partition p inserts its P; a non-empty subset of the
+ * partitions set above) is not contracted whole but expanded again, in the
+ * combinatorial form, over its own sub-partitions (same layout as
+ * pne_network_set_partitions); the sub-expansion drops its own residue.
+ * Calling again for the same x_mask replaces its sub-partitions, n_sub == 0
+ * removes them, and pne_network_set_partitions clears them all.  In the
+ * library's evaluation a loop configuration then counts with an integer
+ * coefficient: the signed number of first-level subsets that keep it (none
+ * of their bonds excited, and, where refined, some sub-partition left
+ * unexcited).  Same envelope as pne_network_set_partitions. */
+pne_status pne_network_set_subpartitions(pne_network *net, uint32_t x_mask, int32_t n_sub,
+                                         const int32_t *sub_begin, const int32_t *sub_bond);
+
 /* Prepare a batch: enumerate (or fetch cached) retained clusters per network
  * geometry, build contraction plans and device tables, allocate the batch's
  * device working memory.  The networks must stay alive while the batch does. */

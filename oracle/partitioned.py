@@ -167,3 +167,36 @@ def count_retained(net, partitions, K):
             continue
         count += 1
     return count
+
+
+def recursive_pne(net, partitions, subpartitions, proj=None):
+    """(sign, ln|Z|): recursive partitioning (Sec. IV.A) written out.
+
+    Eq. A6 over the first-level partitions, except that the term of each
+    subset x that `subpartitions` maps (key: tuple of partition indices,
+    ascending) to a list of sub-partitions is itself expanded: it becomes the
+    combinatorial form, residue dropped, of the network with P on x's bonds,
+    over those sub-partitions (P on their bonds as well, the identity
+    elsewhere)."""
+    parts = _check_partitions(net, partitions)
+    subs = {tuple(sorted(k)): _check_partitions(net, v) for k, v in subpartitions.items()}
+    if proj is None:
+        proj = bp_projectors(net)
+    eye = [np.eye(net.bond_dim(b)) for b in range(net.n_bonds)]
+    out = []
+    for x in subsets(len(parts)):
+        sx = 1 if len(x) % 2 == 1 else -1
+        base = set(b for p in x for b in parts[p])
+        inner = subs.get(tuple(x))
+        if not inner:
+            ops = [proj[b][0] if b in base else eye[b] for b in range(net.n_bonds)]
+            ls, v = _term(net, ops)
+            out.append((sx, ls, v))
+            continue
+        for y in subsets(len(inner)):
+            sy = 1 if len(y) % 2 == 1 else -1
+            cut = base | set(b for r in y for b in inner[r])
+            ops = [proj[b][0] if b in cut else eye[b] for b in range(net.n_bonds)]
+            ls, v = _term(net, ops)
+            out.append((sx * sy, ls, v))
+    return _scaled_sum(out)

@@ -29,7 +29,7 @@ bool Geometry::same_as(const Geometry &o) const {
     return n_sites == o.n_sites && n_bonds == o.n_bonds && n_open == o.n_open && rank == o.rank &&
            dim == o.dim && bu == o.bu && bul == o.bul && bv == o.bv && bvl == o.bvl &&
            open_site == o.open_site && open_slot == o.open_slot && part_off == o.part_off &&
-           part_bond == o.part_bond;
+           part_bond == o.part_bond && subs == o.subs;
 }
 
 namespace {
@@ -55,6 +55,11 @@ uint64_t geometry_hash(const Geometry &g) {
         h = mix(h, 0x70617274ULL);
         for (int x : g.part_off) h = mix(h, x);
         for (int x : g.part_bond) h = mix(h, x);
+        for (const auto &sp : g.subs) {
+            h = mix(h, 0x73756270ULL ^ sp.x);
+            for (int x : sp.off) h = mix(h, x);
+            for (int x : sp.bond) h = mix(h, x);
+        }
     }
     return h;
 }
@@ -84,6 +89,41 @@ std::string set_partitions(Geometry *g, int n, const int32_t *begin, const int32
     g->part_bond = std::move(bonds);
     if (n > 0) g->bond_parts = std::move(parts);
     else g->bond_parts.clear();
+    g->subs.clear();
+    g->hash = geometry_hash(*g);
+    return "";
+}
+
+std::string set_subpartitions(Geometry *g, uint32_t x, int n, const int32_t *begin, const int32_t *bond) {
+    const int np = g->n_parts();
+    if (np == 0) return "no partitions to refine";
+    const uint32_t full = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
+    if (x == 0 || (x & ~full)) return "subset is empty or names a partition that does not exist";
+    if (n < 0) return "negative sub-partition count";
+    if (n > kMaxParts) return "unsupported: more than 32 sub-partitions";
+    if (n > 0 && (!begin || !bond)) return "sub-partition arrays missing";
+    if (n > 0 && begin[0] != 0) return "sub-partition offsets must start at 0";
+    Geometry::SubParts sp;
+    sp.x = x;
+    for (int p = 0; p < n; ++p) {
+        if (begin[p + 1] <= begin[p]) return "a sub-partition transects no bond";
+        std::vector<char> seen(g->n_bonds, 0);
+        for (int k = begin[p]; k < begin[p + 1]; ++k) {
+            int b = bond[k];
+            if (b < 0 || b >= g->n_bonds) return "sub-partition bond out of range";
+            if (seen[b]) return "bond listed twice in one sub-partition";
+            seen[b] = 1;
+            sp.bond.push_back(b);
+        }
+        sp.off.push_back((int)sp.bond.size());
+    }
+    auto it = std::find_if(g->subs.begin(), g->subs.end(), [&](const Geometry::SubParts &e) { return e.x == x; });
+    if (it != g->subs.end()) g->subs.erase(it);
+    if (n > 0) {
+        g->subs.push_back(std::move(sp));
+        std::sort(g->subs.begin(), g->subs.end(),
+                  [](const Geometry::SubParts &a, const Geometry::SubParts &b) { return a.x < b.x; });
+    }
     g->hash = geometry_hash(*g);
     return "";
 }
@@ -745,31 +785,69 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
             }
             vs[c].assign(s2.begin(), s2.end());
         }
+        // Recursive partitioning: the term of first-level subset x, when x has
+        // sub-partitions R_x, keeps only the configurations that leave some
+        // sub-partition of R_x unexcited.  A configuration S then counts with
+        //   c(S) = sum over non-empty x with no bond of x excited of
+        //          (-1)^(|x|+1) [R_x absent, or S misses a sub-partition of R_x],
+        // which is 1 for every S that misses a partition when nothing is refined.
+        const int ns = (int)g.subs.size();
+        std::vector<uint32_t> sfull(ns);
+        std::vector<std::vector<uint32_t>> csub(ns, std::vector<uint32_t>(nc, 0u));
+        for (int e = 0; e < ns; ++e) {
+            const auto &sp = g.subs[e];
+            const int nsp = (int)sp.off.size() - 1;
+            sfull[e] = nsp == 32 ? 0xffffffffu : ((1u << nsp) - 1u);
+            std::vector<uint32_t> bmask(g.n_bonds, 0u);
+            for (int r = 0; r < nsp; ++r)
+                for (int k = sp.off[r]; k < sp.off[r + 1]; ++k) bmask[sp.bond[k]] |= 1u << r;
+            for (int c = 0; c < nc; ++c)
+                for (int q = cl.off[c]; q < cl.off[c + 1]; ++q) csub[e][c] |= bmask[cl.bonds[q]];
+        }
+        auto coefficient = [&](uint32_t mask, const std::vector<uint32_t> &smask) {
+            const uint32_t comp = full & ~mask;
+            int64_t coef = 0;
+            for (uint32_t x = comp; x != 0; x = (x - 1) & comp) {
+                int keep = 1;
+                for (int e = 0; e < ns; ++e)
+                    if (g.subs[e].x == x) keep = smask[e] != sfull[e];
+                coef += (__builtin_popcount(x) & 1) ? keep : -keep;
+            }
+            return coef;
+        };
         plan->coll_off.assign(1, 0);
         plan->coll_cl.clear();
+        plan->coll_coef.clear();
         std::vector<int> chosen;
         std::vector<char> used(g.n_sites, 0);
         bool too_many = false;
         // depth-first over clusters in increasing index: each collection once
-        std::function<void(int, int, uint32_t)> dfs = [&](int from, int deg, uint32_t mask) {
-            for (int c = from; c < nc && !too_many; ++c) {
-                if (deg + plan->csize[c] > K) continue;
-                bool free = true;
-                for (int v : vs[c]) free = free && !used[v];
-                if (!free) continue;
-                const uint32_t m = mask | plan->cmask[c];
-                if (m == full) continue;  // excluded, and so is every superset
-                chosen.push_back(c);
-                for (int v : vs[c]) used[v] = 1;
-                plan->coll_cl.insert(plan->coll_cl.end(), chosen.begin(), chosen.end());
-                plan->coll_off.push_back((int)plan->coll_cl.size());
-                if (plan->coll_cl.size() > kMaxListed) too_many = true;
-                dfs(c + 1, deg + plan->csize[c], m);
-                for (int v : vs[c]) used[v] = 0;
-                chosen.pop_back();
-            }
-        };
-        dfs(0, 0, 0u);
+        std::function<void(int, int, uint32_t, const std::vector<uint32_t> &)> dfs =
+            [&](int from, int deg, uint32_t mask, const std::vector<uint32_t> &smask) {
+                std::vector<uint32_t> sm(ns);
+                for (int c = from; c < nc && !too_many; ++c) {
+                    if (deg + plan->csize[c] > K) continue;
+                    bool free = true;
+                    for (int v : vs[c]) free = free && !used[v];
+                    if (!free) continue;
+                    const uint32_t m = mask | plan->cmask[c];
+                    if (m == full) continue;  // no term keeps it, nor any superset
+                    for (int e = 0; e < ns; ++e) sm[e] = smask[e] | csub[e][c];
+                    chosen.push_back(c);
+                    for (int v : vs[c]) used[v] = 1;
+                    const int64_t coef = ns ? coefficient(m, sm) : 1;
+                    if (coef != 0) {  // a zero coefficient may still extend to a non-zero one
+                        plan->coll_cl.insert(plan->coll_cl.end(), chosen.begin(), chosen.end());
+                        plan->coll_off.push_back((int)plan->coll_cl.size());
+                        if (ns) plan->coll_coef.push_back((double)coef);
+                        if (plan->coll_cl.size() > kMaxListed) too_many = true;
+                    }
+                    dfs(c + 1, deg + plan->csize[c], m, sm);
+                    for (int v : vs[c]) used[v] = 0;
+                    chosen.pop_back();
+                }
+            };
+        dfs(0, 0, 0u, std::vector<uint32_t>(ns, 0u));
         if (too_many) {
             *err = "unsupported: too many retained configurations to list";
             return nullptr;

@@ -29,6 +29,14 @@ struct Geometry {
     // own partition under the degree cap only
     std::vector<int> part_off{0}, part_bond;
     std::vector<uint32_t> bond_parts;  // per bond: bit p set if partition p transects it
+    // recursive partitioning (Sec. IV.A): the term of first-level subset x is
+    // itself expanded over sub-partitions (same layout as part_off/part_bond)
+    struct SubParts {
+        uint32_t x = 0;
+        std::vector<int> off{0}, bond;
+        bool operator==(const SubParts &o) const { return x == o.x && off == o.off && bond == o.bond; }
+    };
+    std::vector<SubParts> subs;  // sorted by x
     uint64_t hash = 0;
 
     int n_parts() const { return (int)part_off.size() - 1; }
@@ -44,6 +52,10 @@ std::string build_geometry(const pne_network_desc *desc, Geometry *g);
 // empty string or the reason (prefixed "unsupported:" when valid but outside
 // the implemented envelope).
 std::string set_partitions(Geometry *g, int n, const int32_t *begin, const int32_t *bond);
+
+// Give the first-level subset x (a non-empty set of the partitions) its own
+// sub-partitions (n = 0 removes them) and rehash.
+std::string set_subpartitions(Geometry *g, uint32_t x, int n, const int32_t *begin, const int32_t *bond);
 
 struct ClusterList {
     std::vector<int> off{0};  // cluster c: bonds[off[c] .. off[c+1])
@@ -81,6 +93,7 @@ struct GeoPlan {
     // otherwise
     std::vector<uint32_t> cmask;      // per cluster: partitions it excites
     std::vector<int> coll_off, coll_cl;
+    std::vector<double> coll_coef;    // per listed configuration, with sub-partitions; empty otherwise
     bool listed = false;
 
     std::vector<Bucket> buckets;

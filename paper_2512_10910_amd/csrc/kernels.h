@@ -63,6 +63,7 @@ struct DeviceBatch {
     const int *pair_a = nullptr, *pair_b = nullptr;
     const PairCat *pair_cats = nullptr;
     const int *coll_off = nullptr, *coll_cl = nullptr;  // listed configurations (user partitions)
+    const double *coll_coef = nullptr;                   // their coefficients (recursive partitioning)
     NetResult *results = nullptr;
     double *open_out = nullptr;  // open networks' output tensors (CombineRec::open_off)
 };

@@ -346,7 +346,9 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                                                         const int *__restrict__ pair_a, const int *__restrict__ pair_b,
                                                         const PairCat *__restrict__ cats,
                                                         const int *__restrict__ coll_off,
-                                                        const int *__restrict__ coll_cl, const double *__restrict__ w,
+                                                        const int *__restrict__ coll_cl,
+                                                        const double *__restrict__ coll_coef,
+                                                        const double *__restrict__ w,
                                                         const double *__restrict__ site_log,
                                                         const int *__restrict__ site_sign, const double *__restrict__ vac,
                                                         const NetState *__restrict__ st, NetResult *__restrict__ out,
@@ -373,13 +375,15 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
     if (gr.listed) {
         // User partitions (closed networks): every retained configuration is
         // listed with its clusters; its value is the product of their
-        // weights.  Each thread sums its configurations in list order, then
-        // the block sum adds the per-thread sums in a fixed order.
+        // weights, times its integer coefficient under recursive
+        // partitioning.  Each thread sums its configurations in list order,
+        // then the block sum adds the per-thread sums in a fixed order.
         const int *off = coll_off + gr.coll_begin;
         const int *cls = coll_cl + gr.coll_cl_begin;
+        const double *coef = gr.coef_begin >= 0 ? coll_coef + gr.coef_begin : nullptr;
         double v = 0.0;
         for (int k = tid; k < gr.n_colls; k += kCbThreads) {
-            double prod = 1.0;
+            double prod = coef ? gld(&coef[k]) : 1.0;
             const int j1 = gld(&off[k + 1]);
             for (int j = gld(&off[k]); j < j1; ++j) prod *= wn[gld(&cls[j])];
             v += prod;
@@ -610,7 +614,7 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
     if (!b.n_combine) return hipSuccess;
     hipLaunchKernelGGL(k_combine, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
-                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.coll_off, b.coll_cl, b.w, b.site_log,
+                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.coll_off, b.coll_cl, b.coll_coef, b.w, b.site_log,
                        b.site_sign, b.vac, b.state,
                        b.results, b.open_out);
     return hipGetLastError();

@@ -195,7 +195,7 @@ struct GeoRec {
     int32_t coll_begin;    // listed: index of the first offset in the collection offsets
     int32_t n_colls;       // listed: number of retained configurations
     int32_t coll_cl_begin; // listed: index of the first entry in the collection clusters
-    int32_t pad;
+    int32_t coef_begin;    // listed with sub-partitions: first coefficient; -1: every coefficient is 1
 };
 
 struct Bucket {

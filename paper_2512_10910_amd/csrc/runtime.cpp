@@ -621,6 +621,17 @@ pne_status pne_network_set_partitions(pne_network *net, int32_t n_partitions, co
     return PNE_OK;
 }
 
+pne_status pne_network_set_subpartitions(pne_network *net, uint32_t x_mask, int32_t n_sub, const int32_t *sub_begin,
+                                         const int32_t *sub_bond) {
+    if (!net) return fail(nullptr, PNE_ERR_INVALID_ARG, "null network");
+    auto g = std::make_shared<Geometry>(*net->geo);
+    std::string why = set_subpartitions(g.get(), x_mask, n_sub, sub_begin, sub_bond);
+    if (!why.empty())
+        return fail(net->ctx, why.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, why);
+    net->geo = g;
+    return PNE_OK;
+}
+
 pne_status pne_network_destroy(pne_network *net) {
     if (!net) return PNE_ERR_INVALID_ARG;
     if (net->owned) {
@@ -984,6 +995,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<int> pair_a, pair_b;
     std::vector<PairCat> pair_cats;
     std::vector<int> coll_off, coll_cl;
+    std::vector<double> coll_coef;
     std::map<const GeoPlan *, int> plan_index;  // -> first class id
     std::map<const GeoPlan *, int> geo_index;
     int64_t wtot = 0;
@@ -1024,6 +1036,11 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 gr.coll_cl_begin = (int)coll_cl.size();
                 coll_off.insert(coll_off.end(), p->coll_off.begin(), p->coll_off.end());
                 coll_cl.insert(coll_cl.end(), p->coll_cl.begin(), p->coll_cl.end());
+                gr.coef_begin = -1;
+                if (!p->coll_coef.empty()) {
+                    gr.coef_begin = (int)coll_coef.size();
+                    coll_coef.insert(coll_coef.end(), p->coll_coef.begin(), p->coll_coef.end());
+                }
                 if (coll_cl.size() > (size_t)INT32_MAX / 2)
                     return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: too many listed configurations");
             }
@@ -1232,6 +1249,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(pair_cats, pair_cats);
     UP(coll_off, coll_off);
     UP(coll_cl, coll_cl);
+    UP(coll_coef, coll_coef);
 #undef UP
     db.n_sites = (int)sites.size();
     db.n_tiles = (int)loop_tiles.size();

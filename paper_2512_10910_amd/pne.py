@@ -163,6 +163,8 @@ _PROTOS = {
                                           ctypes.POINTER(ctypes.c_void_p)]),
     "pne_network_destroy": (ctypes.c_int, [ctypes.c_void_p]),
     "pne_network_set_partitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i32p]),
+    "pne_network_set_subpartitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _i32p,
+                                                     _i32p]),
     "pne_strip_options_default": (ctypes.c_int, [ctypes.POINTER(StripOptions)]),
     "pne_strip_expand": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32, ctypes.POINTER(StripOptions),
                                         ctypes.POINTER(StripResult)]),
@@ -508,6 +510,17 @@ class Network:
         _check(self.ctx.lib, self.ctx.lib.pne_network_set_partitions(
             self.handle, len(parts), begin.ctypes.data_as(_i32p), bonds.ctypes.data_as(_i32p)), self.ctx.handle)
         self.partitions = [p.tolist() for p in parts]
+
+    def set_subpartitions(self, x, subpartitions):
+        """Recursive partitioning: expand the term of first-level subset x (an
+        iterable of partition indices) over its own sub-partitions (lists of
+        bond indices); [] removes them."""
+        mask = 0
+        for p in x:
+            mask |= 1 << int(p)
+        parts, begin, bonds = _partition_arrays(subpartitions)
+        _check(self.ctx.lib, self.ctx.lib.pne_network_set_subpartitions(
+            self.handle, mask, len(parts), begin.ctypes.data_as(_i32p), bonds.ctypes.data_as(_i32p)), self.ctx.handle)
 
     def close(self):
         if self._alive:

@@ -34,6 +34,7 @@ from .networks import (  # noqa: F401
     double_loop_partitions,
     grid3_single_partitions,
     grid3_multi_partitions,
+    grid3x4_recursive_partitions,
     ising_uniform_tensor,
     ising_blocked_tensor,
     random_uniform_tensor,

@@ -468,3 +468,38 @@ def random_uniform_tensor(chi: int, seed: int = 0, bias: float = 1.0) -> np.ndar
     """Uniform tensor with entries i.i.d. uniform in [-1 + bias, 1 + bias]."""
     rng = np.random.default_rng(seed)
     return rng.uniform(-1.0 + bias, 1.0 + bias, (chi,) * 4)
+
+
+def grid3x4_recursive_partitions(net: Network):
+    """The 3 x 4 example of recursive partitioning (site s = x + 3 y): three
+    horizontal lines (between rows 0|1, 1|2, 2|3) and two vertical lines
+    (between columns 0|1, 1|2) as first-level partitions 0..2 and 3..4.  The
+    two principal terms that leave a 3 x 3 block whole (the top and bottom
+    horizontal cuts) are refined by the six-partition expansion of that
+    block.  Returns (partitions, {subset: sub-partitions})."""
+    def xy(s):
+        return s % 3, s // 3
+
+    def cut(pred):
+        return [b for b, (u, _, v, _) in enumerate(net.bonds) if pred(int(u), int(v))]
+
+    parts = []
+    for r in (0, 1, 2):
+        parts.append(cut(lambda u, v, r=r: {xy(u)[1], xy(v)[1]} == {r, r + 1}))
+    for c in (0, 1):
+        parts.append(cut(lambda u, v, c=c: {xy(u)[0], xy(v)[0]} == {c, c + 1}))
+
+    def block_parts(y0):
+        inside = lambda u, v: y0 <= xy(u)[1] <= y0 + 2 and y0 <= xy(v)[1] <= y0 + 2
+        sub = []
+        for c in (0, 1):
+            sub.append(cut(lambda u, v, c=c: inside(u, v) and {xy(u)[0], xy(v)[0]} == {c, c + 1}))
+        for r in (0, 1):
+            sub.append(cut(lambda u, v, r=r: inside(u, v) and {xy(u)[1] - y0, xy(v)[1] - y0} == {r, r + 1}))
+        for d in (1, 2):
+            sub.append(cut(lambda u, v, d=d: inside(u, v)
+                           and {xy(u)[0] + xy(u)[1] - y0, xy(v)[0] + xy(v)[1] - y0} == {d, d + 1}))
+        return sub
+
+    # cutting between rows 0|1 leaves rows 1..3 whole; between rows 2|3, rows 0..2
+    return parts, {(0,): block_parts(1), (2,): block_parts(0)}

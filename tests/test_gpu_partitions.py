@@ -188,3 +188,58 @@ def test_workload_batch_sampled(ctx):
         s, lg = PT.combinatorial_pne(raw[i], parts)
         assert arr["sign"][i] == s and abs(arr["log_abs"][i] - lg) <= 1e-10, i
     b.close()
+
+
+# ----------------------------------------------------------------------------
+# recursive partitioning (Sec. IV.A)
+
+
+@pytest.mark.parametrize("kind,D,seed", [("random", 3, 1), ("random", 4, 2), ("ising", 2, 0), ("aklt", 4, 0)])
+def test_recursive_three_by_four_matches_oracle(ctx, kind, D, seed):
+    """The 3 x 4 example: five first-level lines, the two principal terms
+    with a whole 3 x 3 block refined by its six partitions; complete
+    expansion in FP64 against the oracle's literal recursion."""
+    net = P.small_network(3, 4, kind, D, seed=seed)
+    parts, subs = P.grid3x4_recursive_partitions(net)
+    n = _partitioned(ctx, net, parts)
+    for x, inner in subs.items():
+        n.set_subpartitions(x, inner)
+    r = ctx.contract(n, K=net.n_bonds, precision="fp64")
+    s, lg = PT.recursive_pne(net, parts, subs)
+    print(kind, r.log_abs, lg, r.n_config_terms, flush=True)
+    assert r.status == 0 and r.sign == s
+    assert abs(r.log_abs - lg) <= 1e-10, f"|dlnZ|={abs(r.log_abs - lg):.3e}"
+
+
+def test_recursive_single_index_and_clearing(ctx):
+    net = P.small_network(3, 3, "random", 3, seed=14, bias=0.8)
+    parts = P.grid3_single_partitions(net)
+    subs = {(0,): [[0], [2], [9], [11]], (1, 2): [[5], [6]]}
+    n = _partitioned(ctx, net, parts)
+    for x, inner in subs.items():
+        n.set_subpartitions(x, inner)
+    r = ctx.contract(n, K=12, precision="fp64")
+    s, lg = PT.recursive_pne(net, parts, subs)
+    assert r.sign == s and abs(r.log_abs - lg) <= 1e-10
+    # removing one refinement, then resetting the partitions, restores the plain forms
+    n.set_subpartitions((1, 2), [])
+    r2 = ctx.contract(n, K=12, precision="fp64")
+    s2, lg2 = PT.recursive_pne(net, parts, {(0,): subs[(0,)]})
+    assert r2.sign == s2 and abs(r2.log_abs - lg2) <= 1e-10
+    n.set_partitions(parts)
+    r3 = ctx.contract(n, K=12, precision="fp64")
+    s3, lg3 = PT.combinatorial_pne(net, parts)
+    assert r3.sign == s3 and abs(r3.log_abs - lg3) <= 1e-10
+
+
+def test_invalid_subpartitions_are_errors(ctx):
+    import paper_2512_10910_amd as pne
+
+    raw = P.small_network(3, 3, "random", 2, seed=1)
+    n = ctx.network(raw)
+    with pytest.raises(pne.PNEError):
+        n.set_subpartitions((0,), [[1]])  # no partitions yet
+    n.set_partitions(P.grid3_single_partitions(raw))
+    for x, bad in (((7,), [[1]]), ((0,), [[]]), ((0,), [[99]]), ((0,), [[1, 1]])):
+        with pytest.raises(pne.PNEError):
+            n.set_subpartitions(x, bad)

@@ -208,3 +208,93 @@ def test_planted_mistakes_fail_the_pins(monkeypatch, mutation):
                             lambda net, *a: [(p.T.copy(), np.eye(p.shape[0]) - p.T, n)
                                              for (p, q, n) in orig_proj(net, *a)])
     assert not _double_loop_pins_hold()
+
+
+# ----------------------------------------------------------------------------
+# recursive partitioning (Sec. IV.A)
+
+
+def test_recursive_form_plus_residues_is_exact():
+    """Single-index partitions refined by single-index sub-partitions: the
+    exact value is the recursive expansion plus the first-level residue plus,
+    for each refined subset x, its sub-residue (P on x's bonds, Q on the
+    sub-partition bonds) with the sign of x."""
+    net = P.small_network(3, 3, "random", 3, seed=14, bias=0.8)
+    parts = P.grid3_single_partitions(net)
+    subs = {(0,): [[0], [2], [9], [11]], (1, 2): [[5], [6]]}
+    proj = PT.bp_projectors(net)
+    z0 = _z0(net)
+    rec = _val(PT.recursive_pne(net, parts, subs, proj))
+    res1 = _val(PT.residue(net, parts, proj))
+    total = rec + res1
+    for x, inner in subs.items():
+        base = set(b for p in x for b in parts[p])
+        ops = [np.eye(net.bond_dim(b)) for b in range(net.n_bonds)]
+        for b in base:
+            ops[b] = proj[b][0]
+        for r in inner:
+            b = r[0]
+            ops[b] = proj[b][0] @ proj[b][1] if b in base else proj[b][1]
+        ls, t = O.literal_term(net, ops)
+        total += (1 if len(x) % 2 == 1 else -1) * float(t) * math.exp(ls)
+    assert abs(total - z0) <= 1e-12 * abs(z0)
+
+
+def test_recursive_residue_by_brute_force_coefficients():
+    """Multi-index partitions on 3 x 3 (the two vertical lines), the first
+    principal term refined by lines inside columns 1-2.  Z0 minus the
+    recursive expansion equals the sum over all 2^12 excitation patterns S of
+    (1 - c(S)) Z(Q on S, P elsewhere), with c(S) the signed count of the
+    first-level subsets x whose bonds S avoids and which, where refined, have
+    a sub-partition that S avoids."""
+    net = P.small_network(3, 3, "random", 2, seed=15, bias=0.8)
+    multi = P.grid3_multi_partitions(net)
+    parts = [multi[0], multi[1]]
+    inner = [[b for b in multi[2] if b not in multi[0]], [b for b in multi[3] if b not in multi[0]], multi[5]]
+    subs = {(0,): inner}
+    proj = PT.bp_projectors(net)
+    z0 = _z0(net)
+    rec = _val(PT.recursive_pne(net, parts, subs, proj))
+    psets = [set(p) for p in parts]
+    isets = [set(r) for r in inner]
+
+    def coef(S):
+        S = set(S)
+        c = 0
+        for x in PT.subsets(len(parts)):
+            if any(psets[p] & S for p in x):
+                continue
+            keep = 1
+            if tuple(x) in subs:
+                keep = 0 if all(r & S for r in isets) else 1
+            c += keep if len(x) % 2 == 1 else -keep
+        return c
+
+    resid = 0.0
+    M = net.n_bonds
+    for mask in range(1 << M):
+        y = [b for b in range(M) if mask >> b & 1]
+        w = 1 - coef(y)
+        if w == 0:
+            continue
+        ops = [proj[b][1] if (mask >> b & 1) else proj[b][0] for b in range(M)]
+        lt, tt = O.literal_term(net, ops)
+        resid += w * float(tt) * math.exp(lt)
+    assert abs(z0 - rec - resid) <= 1e-12 * abs(z0)
+
+
+def test_paper_three_by_four_example_geometry():
+    """Three horizontal and two vertical lines on 3 x 4; the principal terms of
+    the top and bottom cuts keep a 3 x 3 block whole and are refined by that
+    block's six partitions (every sub-partition lies inside the block)."""
+    net = P.small_network(3, 4, "random", 2, seed=1)
+    parts, subs = P.grid3x4_recursive_partitions(net)
+    assert [len(p) for p in parts] == [3, 3, 3, 4, 4]
+    assert set(subs) == {(0,), (2,)}
+    for x, inner in subs.items():
+        y0 = 1 if x == (0,) else 0
+        assert len(inner) == 6
+        for r in inner:
+            for b in r:
+                u, _, v, _ = (int(q) for q in net.bonds[b])
+                assert y0 <= u // 3 <= y0 + 2 and y0 <= v // 3 <= y0 + 2
