@@ -307,6 +307,41 @@ def strips_bench(pne, P, L: int = 12, betas=(0.3, 0.4, 0.4407, 0.5, 0.6)):
     ctx.close()
 
 
+def rank_bench(pne, P, n: int = 4096):
+    """Rank-r projectors from weight passing (Sec. V.B's setting, reduced):
+    n coarse-grained 6x6 Ising lattices (3x3 blocks of 2x2 spins, chi = 4)
+    with beta spread over [0.6, 0.9] (below T_c), four single-index
+    partitions (the centre's bonds), linear form, rank 1 and rank 2: wall
+    time and networks/s, and sampled errors against the exact contraction."""
+    import torch
+
+    import oracle as O
+
+    betas = np.linspace(0.6, 0.9, n)
+    raws = [P.ising_blocked_lattice(6, 2, float(b)) for b in betas]
+    ctx = pne.Context(0)
+    nets = [ctx.network(x) for x in raws]
+    parts = P.grid3_single_partitions(raws[0])
+    ctx.rank_expand(nets[:8], 3, 3, parts, rank=2, form="linear")
+    samples = [0, n // 2, n - 1]
+    exact = [O.exact_log_contract(raws[i])[1] for i in samples]
+    for r in (1, 2):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.rank_expand(nets, 3, 3, parts, rank=r, form="linear")
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        errs = [abs(float(out["log_abs"][i]) - e) for i, e in zip(samples, exact)]
+        print(json.dumps({"workload": f"coarse-grained 6x6 Ising below T_c (3x3, chi=4), rank-{r} weight-passing "
+                          "projectors, four centre bonds, Eq. A4, fp64", "networks": n, "ms": round(ms, 2),
+                          "networks_per_s": round(n / (ms * 1e-3), 1), "mean_sweeps": float(out["sweeps"].mean()),
+                          "status_min": int(out["status"].min()),
+                          "abs_err_lnZ_vs_exact_samples": errs}), flush=True)
+    for x in nets:
+        x.close()
+    ctx.close()
+
+
 def workloads_bench(pne, P, steps: int):
     """The other workloads at batch scale, one JSON line each: step time,
     networks/s, per-kernel device time (HIP events around every launch) with
@@ -440,6 +475,7 @@ def main():
     if args.workloads:
         workloads_bench(pne, P, max(1, min(args.steps, 5)))
         strips_bench(pne, P)
+        rank_bench(pne, P)
         return
     if args.strips:
         strips_bench(pne, P, L=args.strips)

@@ -438,6 +438,63 @@ pne_status pne_strip_options_default(pne_strip_options *opt);
 pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t chi, const pne_strip_options *opt,
                             pne_strip_result *res);
 
+/* ------------------------------------------------------------------------
+ * Rank-r projectors from weight passing (Sec. V, Appendix C), on batches of
+ * small closed 2D lattices.
+ *
+ * Weight passing puts a diagonal weight S_b on every bond (initially 1) and
+ * sweeps over the bonds: with A', B' the two site tensors with the weights of
+ * their other bonds applied, A' = U_A S_A V_A^T (other legs x this leg),
+ * B' = U_B S_B V_B^T (this leg x other legs), S_A V_A^T S_b U_B S_B =
+ * U_C S_C V_C^T (Eqs. weight1, weight2), the tensors take the gauge change of
+ * Eq. weight3 and S_b becomes S_C^a (rescaled to a largest entry of 1, the
+ * scale kept in log_scale).  a ramps linearly up to alpha over the first
+ * ramp_sweeps sweeps; sweeps stop once no weight entry moves by more than tol.
+ * In that gauge the weights decrease along each bond, and the rank-r
+ * projector of a bond keeps its first r indices: P = diag(1_r, 0), Q = I - P.
+ *
+ * The expansion over the given partitions (bond lists) is the combinatorial
+ * form (form 0, Eq. A6) or the linear form (form 1, Eq. A4, single-index
+ * partitions in the given order), the residue dropped; each term contracts
+ * the gauged lattice exactly with S_b P, S_b Q or S_b on every bond.  With
+ * r = chi every P is the identity and the result is the exact value.
+ *
+ * Envelope: every network in the call has the same geometry, a closed
+ * Lx x Ly lattice with sites numbered x + Lx y, bonds between lattice
+ * neighbours only, one bond dimension chi <= 4, Lx Ly <= 16,
+ * chi^(Lx+1) <= 1024, 1..16 partitions.  Networks are read in place (device
+ * copies made by pne_network_create).  Device memory is allocated and freed
+ * by the call; it returns when done.  Per network: status (SINGULAR when a
+ * singular value vanished; WARN_BP_NOT_CONVERGED when weight passing hit
+ * max_sweeps), sweeps, and (sign, ln|Z|).
+ * ------------------------------------------------------------------------ */
+typedef struct {
+    int32_t rank;        /* r, 1..chi (2)                                 */
+    int32_t form;        /* 0: combinatorial (Eq. A6); 1: linear (Eq. A4)  */
+    double alpha;        /* weight exponent a (0.8)                        */
+    int32_t ramp_sweeps; /* sweeps over which a ramps up to alpha (10)     */
+    int32_t max_sweeps;  /* sweep cap (2000)                               */
+    double tol;          /* largest weight change to stop (1e-12)          */
+    int32_t reserved[4];
+} pne_rank_options;
+
+typedef struct {
+    int32_t status;      /* pne_status of the network                      */
+    int32_t sweeps;      /* weight-passing sweeps                          */
+    int32_t sign;        /* +1, -1 (0 if the sum is 0)                     */
+    int32_t pad;
+    double log_abs;      /* ln|Z| of the expansion                         */
+    double log_scale;    /* the log-scale carried out of weight passing    */
+} pne_rank_result;
+
+pne_status pne_rank_options_default(pne_rank_options *opt);
+/* nets[0..n-1]: the batch; Lx, Ly: the lattice shape; partitions as in
+ * pne_network_set_partitions; results: n entries.  Returns the first
+ * non-zero per-network status, or an argument error before any device work. */
+pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, int32_t n, int32_t Lx, int32_t Ly,
+                           int32_t n_partitions, const int32_t *part_begin, const int32_t *part_bond,
+                           const pne_rank_options *opt, pne_rank_result *results);
+
 #ifdef __cplusplus
 }
 #endif

@@ -537,6 +537,22 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int on
 
 }  // extern "C"
 
+int pne::network_sites(pne_network *net) { return net->geo->n_sites; }
+bool pne::network_graph(pne_network *net, std::vector<int> *rank, std::vector<int> *bond_dims, std::vector<int> *bu,
+                        std::vector<int> *bul, std::vector<int> *bv, std::vector<int> *bvl) {
+    const Geometry &g = *net->geo;
+    if (g.n_open > 0) return false;
+    *rank = g.rank;
+    *bu = g.bu;
+    *bul = g.bul;
+    *bv = g.bv;
+    *bvl = g.bvl;
+    bond_dims->clear();
+    for (int b = 0; b < g.n_bonds; ++b) bond_dims->push_back(g.dim[g.slot(g.bu[b], g.bul[b])]);
+    return true;
+}
+const double *pne::network_site_ptr(pne_network *net, int site) { return net->dptr[site]; }
+bool pne::same_geometry(pne_network *a, pne_network *b) { return a->geo->same_as(*b->geo); }
 hipStream_t pne::ctx_stream(pne_ctx *ctx) { return ctx->stream; }
 int pne::ctx_device(pne_ctx *ctx) { return ctx->device; }
 pne_status pne::ctx_fail(pne_ctx *ctx, pne_status st, const std::string &msg) { return fail(ctx, st, msg); }

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime.h>
 
 #include <string>
+#include <vector>
 
 #include "pne.h"
 
@@ -19,6 +20,13 @@ pne_status batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t n, co
 // Context access for the other entry points (strip expansions).
 hipStream_t ctx_stream(pne_ctx *ctx);
 int ctx_device(pne_ctx *ctx);
+// Network access for the other entry points: site count, graph (false when
+// the network has open legs), per-site device tensor, geometry equality.
+int network_sites(pne_network *net);
+bool network_graph(pne_network *net, std::vector<int> *rank, std::vector<int> *bond_dims, std::vector<int> *bu,
+                   std::vector<int> *bul, std::vector<int> *bv, std::vector<int> *bvl);
+const double *network_site_ptr(pne_network *net, int site);
+bool same_geometry(pne_network *a, pne_network *b);
 // Record msg as the context's last error and return st.
 pne_status ctx_fail(pne_ctx *ctx, pne_status st, const std::string &msg);
 

@@ -153,6 +153,29 @@ class StripResult(ctypes.Structure):
     ]
 
 
+class RankOptions(ctypes.Structure):
+    _fields_ = [
+        ("rank", ctypes.c_int32),
+        ("form", ctypes.c_int32),
+        ("alpha", ctypes.c_double),
+        ("ramp_sweeps", ctypes.c_int32),
+        ("max_sweeps", ctypes.c_int32),
+        ("tol", ctypes.c_double),
+        ("reserved", ctypes.c_int32 * 4),
+    ]
+
+
+class RankResult(ctypes.Structure):
+    _fields_ = [
+        ("status", ctypes.c_int32),
+        ("sweeps", ctypes.c_int32),
+        ("sign", ctypes.c_int32),
+        ("pad", ctypes.c_int32),
+        ("log_abs", ctypes.c_double),
+        ("log_scale", ctypes.c_double),
+    ]
+
+
 # exported C symbols and their prototypes: (restype, argtypes)
 _PROTOS = {
     "pne_options_default": (ctypes.c_int, [ctypes.POINTER(Options)]),
@@ -165,6 +188,10 @@ _PROTOS = {
     "pne_network_set_partitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int32, _i32p, _i32p]),
     "pne_network_set_subpartitions": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint32, ctypes.c_int32, _i32p,
                                                      _i32p]),
+    "pne_rank_options_default": (ctypes.c_int, [ctypes.POINTER(RankOptions)]),
+    "pne_rank_expand": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p,
+                                       ctypes.POINTER(RankOptions), ctypes.POINTER(RankResult)]),
     "pne_strip_options_default": (ctypes.c_int, [ctypes.POINTER(StripOptions)]),
     "pne_strip_expand": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32, ctypes.POINTER(StripOptions),
                                         ctypes.POINTER(StripResult)]),
@@ -432,6 +459,27 @@ class Context:
                                                ctypes.byref(best)), self.handle)
         return {"graph": bool(best.flags & PNE_FLAG_GRAPH),
                 "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags)}
+
+    def rank_expand(self, nets, Lx: int, Ly: int, partitions, rank: int = 2, form: str = "combinatorial",
+                    alpha: float = 0.8, ramp_sweeps: int = 10, max_sweeps: int = 2000, tol: float = 1e-12):
+        """Rank-r weight-passing projectors and the partitioned expansion on a
+        batch of Lx x Ly lattice networks (Sec. V): per network (status,
+        sweeps, sign, ln|Z|, log_scale) as a structured array."""
+        nets = list(nets)
+        opt = RankOptions()
+        _check(self.lib, self.lib.pne_rank_options_default(ctypes.byref(opt)))
+        opt.rank, opt.form = int(rank), {"combinatorial": 0, "linear": 1}[form]
+        opt.alpha, opt.ramp_sweeps, opt.max_sweeps, opt.tol = float(alpha), int(ramp_sweeps), int(max_sweeps), float(tol)
+        parts, begin, bonds = _partition_arrays(partitions)
+        arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
+        res = (RankResult * len(nets))()
+        st = self.lib.pne_rank_expand(self.handle, arr, len(nets), int(Lx), int(Ly), len(parts),
+                                      begin.ctypes.data_as(_i32p), bonds.ctypes.data_as(_i32p), ctypes.byref(opt), res)
+        if st < 0 and st not in (PNE_ERR_SINGULAR,):
+            _check(self.lib, st, self.handle)
+        dt = np.dtype([("status", np.int32), ("sweeps", np.int32), ("sign", np.int32), ("pad", np.int32),
+                       ("log_abs", np.float64), ("log_scale", np.float64)])
+        return np.frombuffer(bytes(res), dtype=dt).copy()
 
     def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
                      power_max_iter: int = 20000, check_every: int = 8, single_site_passes: bool = False) -> dict:

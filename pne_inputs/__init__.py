@@ -38,4 +38,6 @@ from .networks import (  # noqa: F401
     ising_uniform_tensor,
     ising_blocked_tensor,
     random_uniform_tensor,
+    block_lattice,
+    ising_blocked_lattice,
 )

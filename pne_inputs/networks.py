@@ -503,3 +503,68 @@ def grid3x4_recursive_partitions(net: Network):
 
     # cutting between rows 0|1 leaves rows 1..3 whole; between rows 2|3, rows 0..2
     return parts, {(0,): block_parts(1), (2,): block_parts(0)}
+
+
+def block_lattice(net: Network, Lx: int, Ly: int, b: int) -> Network:
+    """Group b x b blocks of an Lx x Ly lattice network (site s = x + Lx y,
+    canonical legs) into one site each, merging the b parallel legs that
+    leave a block on one side into one leg (the first of them most
+    significant).  Only exact contraction of the block's inner bonds: an
+    input construction (the paper coarse-grains Ising lattices this way)."""
+    assert Lx % b == 0 and Ly % b == 0
+    site_dirs, _ = _lattice((Lx, Ly))
+    BX, BY = Lx // b, Ly // b
+    bdirs, _ = _lattice((BX, BY))
+    tensors = []
+    for by in range(BY):
+        for bx in range(BX):
+            sites = [(bx * b + i) + Lx * (by * b + j) for j in range(b) for i in range(b)]
+            letters = iter("abcdefghijklmnopqrstuvwxyzABCDEFGHIJKLMNOPQRSTUVWXYZ")
+            bond_lab = {}
+            ops, subs = [], []
+            for s in sites:
+                x, y = s % Lx, s // Lx
+                lab = []
+                for d, slot in sorted(site_dirs[s].items(), key=lambda kv: kv[1]):
+                    nx, ny = x + (d == "+x") - (d == "-x"), y + (d == "+y") - (d == "-y")
+                    key = tuple(sorted([(x, y), (nx, ny)]))
+                    if key not in bond_lab:
+                        bond_lab[key] = next(letters)
+                    lab.append(bond_lab[key])
+                ops.append(net.tensors[s])
+                subs.append("".join(lab))
+            # outer legs per direction, ordered along the side
+            groups = {}
+            for s in sites:
+                x, y = s % Lx, s // Lx
+                for d in site_dirs[s]:
+                    nx, ny = x + (d == "+x") - (d == "-x"), y + (d == "+y") - (d == "-y")
+                    if nx // b == bx and ny // b == by:
+                        continue
+                    key = tuple(sorted([(x, y), (nx, ny)]))
+                    pos = y if d in ("-x", "+x") else x
+                    groups.setdefault(d, []).append((pos, bond_lab[key]))
+            out = []
+            for d in _DIRS[:4]:
+                if d in bdirs[bx + BX * by]:
+                    out.extend(l for _, l in sorted(groups[d]))
+            T = np.einsum(",".join(subs) + "->" + "".join(out), *ops, optimize=True)
+            shape = []
+            k = 0
+            for d in _DIRS[:4]:
+                if d in bdirs[bx + BX * by]:
+                    m = len(groups[d])
+                    shape.append(int(np.prod(T.shape[k:k + m])))
+                    k += m
+            tensors.append(np.ascontiguousarray(T.reshape(shape)))
+    _, bonds = _lattice((BX, BY))
+    out = Network(tensors, bonds, name=f"{net.name}_blocked{b}", info={"shape": (BX, BY)})
+    return out
+
+
+def ising_blocked_lattice(L: int, b: int, beta: float) -> Network:
+    """The L x L open Ising lattice coarse-grained into (L/b) x (L/b) blocks of
+    b x b spins (bond dimension 2^b)."""
+    net = block_lattice(ising_2d(L, L, beta), L, L, b)
+    net.info.update(model="ising", beta=beta, spins=L * L)
+    return net

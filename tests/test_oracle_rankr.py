@@ -1,0 +1,97 @@
+"""Pins of the rank-r (weight passing) oracle, Sec. V and Appendix C.
+
+Independent of the oracle's arithmetic: weight passing is a change of gauge,
+so the gauged network with its weights contracts to the exact value; rank r =
+chi makes P the identity, so one partition gives the exact value; each form
+plus its residue (Q on the partitioned bonds, contracted directly) is exact;
+and below the critical temperature the Ising model is badly served by rank 1
+(two BP sectors) and well served by rank 2 (Sec. V.B), on a reduced version
+of the paper's coarse-grained lattice.
+"""
+
+import math
+
+import numpy as np
+import pytest
+
+import oracle as O
+import pne_inputs as P
+from oracle import rankr as R
+
+
+def _z0(net):
+    s, lg = O.exact_log_contract(net)
+    return s, lg
+
+
+@pytest.mark.parametrize("make", [lambda: P.small_network(3, 3, "random", 3, seed=3),
+                                  lambda: P.ising_blocked_lattice(6, 2, 0.6),
+                                  lambda: P.small_network(3, 2, "random", 4, seed=5)])
+def test_weight_passing_is_a_gauge_change(make):
+    net = make()
+    wp = R.weight_passing(net)
+    assert wp[4]
+    s, lg = R.gauged_value(net, wp)
+    s0, lg0 = _z0(net)
+    assert s == s0 and abs(lg - lg0) < 1e-11
+    for w in wp[1]:
+        assert abs(w.max() - 1.0) < 1e-15 and np.all(np.diff(w) <= 1e-15)
+
+
+def test_full_rank_is_exact():
+    net = P.small_network(3, 3, "random", 3, seed=4)
+    wp = R.weight_passing(net)
+    s0, lg0 = _z0(net)
+    for form, parts in (("linear", P.grid3_single_partitions(net)), ("combinatorial", P.grid3_multi_partitions(net))):
+        s, lg = R.rank_expansion(net, parts, 3, form, wp=wp)
+        assert s == s0 and abs(lg - lg0) < 1e-11
+
+
+@pytest.mark.parametrize("r", [1, 2])
+def test_linear_form_plus_residue_is_exact(r):
+    """Eq. A4 with rank-r P: the sum of the terms plus the network with Q on
+    every partitioned bond is the exact value."""
+    net = P.small_network(3, 3, "random", 3, seed=6)
+    wp = R.weight_passing(net)
+    parts = P.grid3_single_partitions(net)
+    s, lg = R.rank_expansion(net, parts, r, "linear", wp=wp)
+    T, S, log_scale = wp[0], wp[1], wp[2]
+    ops = list(S)
+    for p in parts:
+        b = p[0]
+        ops[b] = np.where(np.arange(len(S[b])) < r, 0.0, S[b])
+    ls, v = R._contract(net, T, ops)
+    s0, lg0 = _z0(net)
+    total = s * math.exp(lg - lg0) + v * math.exp(ls + log_scale - lg0)
+    assert abs(total - s0) < 1e-11
+
+
+def test_combinatorial_and_linear_agree_for_single_index_partitions():
+    net = P.small_network(3, 3, "random", 3, seed=7)
+    wp = R.weight_passing(net)
+    parts = P.grid3_single_partitions(net)
+    a = R.rank_expansion(net, parts, 2, "linear", wp=wp)
+    b = R.rank_expansion(net, parts, 2, "combinatorial", wp=wp)
+    assert a[0] == b[0] and abs(a[1] - b[1]) < 1e-12
+
+
+def test_subcritical_ising_needs_rank_two():
+    """Below T_c (beta = 0.7 > 0.4407) the coarse-grained 6 x 6 Ising lattice
+    (3 x 3 blocks of 2 x 2 spins): rank 1 misses a spin sector (error of
+    order 10%), rank 2 captures both (error below 1e-6)."""
+    net = P.ising_blocked_lattice(6, 2, 0.7)
+    wp = R.weight_passing(net)
+    s0, lg0 = _z0(net)
+    parts = P.grid3_single_partitions(net)
+    err = {}
+    for r in (1, 2):
+        s, lg = R.rank_expansion(net, parts, r, "linear", wp=wp)
+        err[r] = abs(s * math.exp(lg - lg0) - 1.0)
+    assert err[1] > 1e-2 and err[2] < 1e-6
+
+
+def test_blocking_preserves_the_partition_function():
+    for beta in (0.3, 0.7):
+        lz = O.ising_bruteforce_logz(16, [(int(u), int(v)) for (u, _, v, _) in P.ising_2d(4, 4, beta).bonds], beta)
+        s, lg = O.exact_log_contract(P.ising_blocked_lattice(4, 2, beta))
+        assert s == 1 and abs(lg - lz) < 1e-12
