@@ -452,6 +452,8 @@ def main():
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
     ap.add_argument("--workloads", action="store_true",
                     help="instead: the other workloads at batch scale with per-kernel rooflines")
+    ap.add_argument("--rank", type=int, default=0, metavar="N",
+                    help="instead: only the rank-r weight-passing workload on N lattices")
     ap.add_argument("--strips", type=int, default=0, metavar="L",
                     help="instead: only the infinite-lattice strip expansion at width L")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
@@ -479,6 +481,9 @@ def main():
         return
     if args.strips:
         strips_bench(pne, P, L=args.strips)
+        return
+    if args.rank:
+        rank_bench(pne, P, n=args.rank)
         return
 
     if args.copy_calibration:
