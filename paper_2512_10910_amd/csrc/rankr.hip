@@ -34,6 +34,7 @@ struct RkGeo {
     int32_t bu[kRkBonds], bul[kRkBonds], bv[kRkBonds], bvl[kRkBonds];
     int32_t leg_bond[kRkSites][4];  // bond on each leg slot (-1: none)
     int32_t dir_slot[kRkSites][4];  // slot of direction (-x, +x, -y, +y), -1 if absent
+    int32_t toff[kRkSites + 1];     // packed offsets of the site tensors (chi^rank each)
 };
 
 __device__ inline int tsize(int rank, int chi) {
@@ -130,14 +131,17 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
                                                        double alpha, int ramp, int max_sweeps, double tol) {
     const RkGeo &geo = *geo_p;
     const int net = blockIdx.x, lane = threadIdx.x, chi = geo.chi;
-    __shared__ double T[kRkSites][kRkSite];
+    // site tensors packed at their own sizes (dynamic LDS of toff[n_sites]
+    // doubles), so several networks share a CU
+    extern __shared__ double Tpack[];
+    auto T = [&](int s) { return Tpack + geo.toff[s]; };
     __shared__ double S[kRkBonds][kRkChi];
     __shared__ double a[kRkSite], bm[kRkSite];   // A' and B'^T, column-major (others x chi)
     __shared__ double VA[16], VB[16], VC[16], sA[4], sB[4], sC[4], M[16], WA[16], WB[16], nt[kRkSite];
     __shared__ double change;
     double *Tg = T_all + (size_t)net * kRkSites * kRkSite;
     for (int s = 0; s < geo.n_sites; ++s)
-        for (int e = lane; e < tsize(geo.rank[s], chi); e += kRkWp) T[s][e] = Tg[(size_t)s * kRkSite + e];
+        for (int e = lane; e < tsize(geo.rank[s], chi); e += kRkWp) T(s)[e] = Tg[(size_t)s * kRkSite + e];
     for (int e = lane; e < geo.n_bonds * chi; e += kRkWp) S[e / chi][e % chi] = 1.0;
     double log_scale = 0.0;
     int status = 0, sweep = 0;
@@ -166,7 +170,7 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
                         if (ob >= 0) w *= S[ob][dg];
                     }
                 }
-                a[ii * mu + oth] = T[u][e] * w;
+                a[ii * mu + oth] = T(u)[e] * w;
             }
             for (int e = lane; e < tsize(rv, chi); e += kRkWp) {
                 int rem = e, oth = 0, ii = 0;
@@ -183,7 +187,7 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
                         if (ob >= 0) w *= S[ob][dg];
                     }
                 }
-                bm[ii * mv + oth] = T[v][e] * w;
+                bm[ii * mv + oth] = T(v)[e] * w;
             }
             __syncthreads();
             // A' = U_A S_A V_A^T ; B'^T = V_B S_B U_B^T, so U_B = (rotations of B'^T)
@@ -219,22 +223,22 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
                 for (int l = ru - 1; l > lu; --l) stride *= chi;
                 const int j = (e / stride) % chi, base = e - j * stride;
                 double x = 0.0;
-                for (int i = 0; i < chi; ++i) x = fma(T[u][base + i * stride], WA[i * chi + j], x);
+                for (int i = 0; i < chi; ++i) x = fma(T(u)[base + i * stride], WA[i * chi + j], x);
                 nt[e] = x;
             }
             __syncthreads();
-            for (int e = lane; e < tsize(ru, chi); e += kRkWp) T[u][e] = nt[e];
+            for (int e = lane; e < tsize(ru, chi); e += kRkWp) T(u)[e] = nt[e];
             __syncthreads();
             for (int e = lane; e < tsize(rv, chi); e += kRkWp) {
                 int stride = 1;
                 for (int l = rv - 1; l > lv; --l) stride *= chi;
                 const int j = (e / stride) % chi, base = e - j * stride;
                 double x = 0.0;
-                for (int i = 0; i < chi; ++i) x = fma(WB[j * chi + i], T[v][base + i * stride], x);
+                for (int i = 0; i < chi; ++i) x = fma(WB[j * chi + i], T(v)[base + i * stride], x);
                 nt[e] = x;
             }
             __syncthreads();
-            for (int e = lane; e < tsize(rv, chi); e += kRkWp) T[v][e] = nt[e];
+            for (int e = lane; e < tsize(rv, chi); e += kRkWp) T(v)[e] = nt[e];
             if (lane == 0) {
                 double mx = 0.0;
                 for (int k = 0; k < chi; ++k) mx = fmax(mx, pow(sC[k], al));
@@ -262,7 +266,7 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
         if (!status) status = PNE_WARN_BP_NOT_CONVERGED;
     }
     for (int s = 0; s < geo.n_sites; ++s)
-        for (int e = lane; e < tsize(geo.rank[s], chi); e += kRkWp) Tg[(size_t)s * kRkSite + e] = T[s][e];
+        for (int e = lane; e < tsize(geo.rank[s], chi); e += kRkWp) Tg[(size_t)s * kRkSite + e] = T(s)[e];
     for (int e = lane; e < geo.n_bonds * chi; e += kRkWp)
         S_all[(size_t)net * kRkBonds * kRkChi + (e / chi) * kRkChi + e % chi] = S[e / chi][e % chi];
     if (lane == 0) {
@@ -457,9 +461,13 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
     geo.chi = chi;
     geo.Lx = Lx;
     geo.Ly = Ly;
+    geo.toff[0] = 0;
     for (int s = 0; s < n_sites; ++s) {
         geo.rank[s] = rank[s];
         for (int l = 0; l < 4; ++l) geo.leg_bond[s][l] = geo.dir_slot[s][l] = -1;
+        int z = 1;
+        for (int l = 0; l < rank[s]; ++l) z *= chi;
+        geo.toff[s + 1] = geo.toff[s] + z;
     }
     for (int b = 0; b < nb; ++b) {
         int u = bu[b], lu = bul[b], v = bv[b], lv = bvl[b];
@@ -569,7 +577,8 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
     hipLaunchKernelGGL(k_rank_gather, dim3(n), dim3(256), 0, s, reinterpret_cast<const double *const *>(B + oSrc),
                        reinterpret_cast<const int *>(B + oSizes), n_sites, reinterpret_cast<double *>(B + oT));
     RK_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_weight_pass, dim3(n), dim3(kRkWp), 0, s, reinterpret_cast<const RkGeo *>(B + oGeo),
+    hipLaunchKernelGGL(k_weight_pass, dim3(n), dim3(kRkWp), (size_t)geo.toff[n_sites] * sizeof(double), s,
+                       reinterpret_cast<const RkGeo *>(B + oGeo),
                        reinterpret_cast<double *>(B + oT), reinterpret_cast<double *>(B + oS),
                        reinterpret_cast<double *>(B + oLog), reinterpret_cast<int *>(B + oSw),
                        reinterpret_cast<int *>(B + oSt), opt->alpha, opt->ramp_sweeps, opt->max_sweeps, opt->tol);
