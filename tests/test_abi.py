@@ -193,3 +193,36 @@ def test_strip_options_default_and_null_arguments(lib):
     assert lib.pne_strip_options_default(None) == -1
     res = B.StripResult()
     assert lib.pne_strip_expand(None, None, 2, ctypes.byref(opt), ctypes.byref(res)) == -1
+
+
+def test_rank_and_partition_entry_points_reject_null_arguments(lib):
+    opt = B.RankOptions()
+    assert lib.pne_rank_options_default(ctypes.byref(opt)) == 0
+    assert (opt.rank, opt.form, opt.ramp_sweeps, opt.max_sweeps) == (2, 0, 10, 2000)
+    assert opt.alpha == 0.8 and opt.tol == 1e-12
+    assert lib.pne_rank_options_default(None) == -1
+    res = (B.RankResult * 1)()
+    begin = (ctypes.c_int32 * 2)(0, 1)
+    bond = (ctypes.c_int32 * 1)(0)
+    assert lib.pne_rank_expand(None, None, 1, 3, 3, 1, begin, bond, ctypes.byref(opt), res) == -1
+    assert lib.pne_network_set_partitions(None, 1, begin, bond) == -1
+    assert lib.pne_network_set_subpartitions(None, 1, 1, begin, bond) == -1
+
+
+def test_rank_structs_match_header(tmp_path):
+    src = tmp_path / "rank.c"
+    src.write_text(r'''
+#include <stdio.h>
+#include <stddef.h>
+#include "pne.h"
+int main(void) {
+  printf("%zu %zu %zu %zu %zu\n", sizeof(pne_rank_options), sizeof(pne_rank_result),
+         offsetof(pne_rank_options, tol), offsetof(pne_rank_result, log_abs), offsetof(pne_rank_result, log_scale));
+  return 0;
+}
+''')
+    exe = tmp_path / "rank"
+    subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
+    a, b, c, d, e = (int(x) for x in subprocess.check_output([str(exe)]).split())
+    assert a == ctypes.sizeof(B.RankOptions) and b == ctypes.sizeof(B.RankResult)
+    assert c == B.RankOptions.tol.offset and d == B.RankResult.log_abs.offset and e == B.RankResult.log_scale.offset
