@@ -399,7 +399,7 @@ typedef struct {
     int32_t power_max_iter; /* power-iteration cap per strip (20000), >= L           */
     double power_tol;       /* stop when two successive relative changes of the
                                eigenvalue estimate are <= power_tol (1e-13)           */
-    int32_t check_every;    /* iterations between host convergence checks (8)        */
+    int32_t check_every;    /* iterations between host convergence checks (4)        */
     int32_t single_site_passes; /* 1: one site per pass over the vector; 0 (default):
                                two neighbouring sites per pass where chi <= 4        */
     int32_t reserved[2];

@@ -708,7 +708,7 @@ extern "C" pne_status pne_strip_options_default(pne_strip_options *opt) {
     opt->bp_max_iter = 10000;
     opt->power_tol = 1e-13;
     opt->power_max_iter = 20000;
-    opt->check_every = 8;
+    opt->check_every = 4;
     return PNE_OK;
 }
 

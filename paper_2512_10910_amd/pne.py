@@ -482,7 +482,7 @@ class Context:
         return np.frombuffer(bytes(res), dtype=dt).copy()
 
     def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
-                     power_max_iter: int = 20000, check_every: int = 8, single_site_passes: bool = False) -> dict:
+                     power_max_iter: int = 20000, check_every: int = 4, single_site_passes: bool = False) -> dict:
         """Strip expansion of the infinite lattice of tensor A (legs -x, +x, -y, +y;
         Sec. IV.B): free energy per site and the per-width quantities."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))

@@ -188,7 +188,7 @@ def test_three_open_sites_unsupported(lib):
 def test_strip_options_default_and_null_arguments(lib):
     opt = B.StripOptions()
     assert lib.pne_strip_options_default(ctypes.byref(opt)) == 0
-    assert (opt.L, opt.two_d, opt.bp_max_iter, opt.power_max_iter, opt.check_every) == (2, 1, 10000, 20000, 8)
+    assert (opt.L, opt.two_d, opt.bp_max_iter, opt.power_max_iter, opt.check_every) == (2, 1, 10000, 20000, 4)
     assert opt.bp_tol == 1e-14 and opt.power_tol == 1e-13
     assert lib.pne_strip_options_default(None) == -1
     res = B.StripResult()
