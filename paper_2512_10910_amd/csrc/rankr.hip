@@ -125,12 +125,14 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
 // Weight passing on one network per block.  T (in/out): the network's site
 // tensors, chi^rank each at kRkSite strides; S (out): weights per bond,
 // decreasing; out_log: the carried log-scale; out_sweeps, status.
+template <int CHI>
 __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__ geo_p, double *__restrict__ T_all,
                                                        double *__restrict__ S_all, double *__restrict__ log_all,
                                                        int *__restrict__ sweeps_all, int *__restrict__ status_all,
                                                        double alpha, int ramp, int max_sweeps, double tol) {
     const RkGeo &geo = *geo_p;
-    const int net = blockIdx.x, lane = threadIdx.x, chi = geo.chi;
+    const int net = blockIdx.x, lane = threadIdx.x;
+    constexpr int chi = CHI;  // index arithmetic by a constant
     // site tensors packed at their own sizes (dynamic LDS of toff[n_sites]
     // doubles), so several networks share a CU
     extern __shared__ double Tpack[];
@@ -138,6 +140,7 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
     __shared__ double S[kRkBonds][kRkChi];
     __shared__ double a[kRkSite], bm[kRkSite];   // A' and B'^T, column-major (others x chi)
     __shared__ double VA[16], VB[16], VC[16], sA[4], sB[4], sC[4], M[16], WA[16], WB[16], nt[kRkSite];
+    __shared__ double pa[4], ph[4];  // S_C^a and S_C^((1-a)/2) of the bond being updated
     __shared__ double change;
     double *Tg = T_all + (size_t)net * kRkSites * kRkSite;
     for (int s = 0; s < geo.n_sites; ++s)
@@ -204,14 +207,19 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
             jacobi_svd(M, chi, chi, VC, sC);  // M columns now U_C S_C
             const double sgm = sA[chi - 1] > 0.0 && sB[chi - 1] > 0.0 && sC[chi - 1] > 0.0 ? 1.0 : 0.0;
             if (sgm == 0.0) status = PNE_ERR_SINGULAR;
+            if (lane < chi) {
+                pa[lane] = pow(sC[lane], al);
+                ph[lane] = pow(sC[lane], 0.5 * (1.0 - al));
+            }
+            __syncthreads();
             // W_A = V_A S_A^-1 U_C S_C^((1-a)/2);  W_B = S_C^((1-a)/2) V_C^T S_B^-1 U_B^T
             if (lane < chi * chi) {
                 const int i = lane / chi, j = lane % chi;
-                const double h = pow(sC[j], 0.5 * (1.0 - al));
+                const double h = ph[j];
                 double x = 0.0;
                 for (int k = 0; k < chi; ++k) x = fma(VA[i * chi + k] / sA[k], M[j * chi + k] / sC[j], x);
                 WA[i * chi + j] = x * h;
-                const double h2 = pow(sC[i], 0.5 * (1.0 - al));
+                const double h2 = ph[i];
                 double y = 0.0;
                 for (int k = 0; k < chi; ++k) y = fma(VC[k * chi + i] / sB[k], VB[j * chi + k], y);
                 WB[i * chi + j] = h2 * y;
@@ -239,22 +247,18 @@ __global__ void __launch_bounds__(kRkWp) k_weight_pass(const RkGeo *__restrict__
             }
             __syncthreads();
             for (int e = lane; e < tsize(rv, chi); e += kRkWp) T(v)[e] = nt[e];
+            double mx = 0.0;
+            for (int k = 0; k < chi; ++k) mx = fmax(mx, pa[k]);
             if (lane == 0) {
-                double mx = 0.0;
-                for (int k = 0; k < chi; ++k) mx = fmax(mx, pow(sC[k], al));
                 double ch = change;
                 for (int k = 0; k < chi; ++k) {
-                    const double nw = pow(sC[k], al) / mx;
+                    const double nw = pa[k] / mx;
                     ch = fmax(ch, fabs(nw - S[b][k]));
                     S[b][k] = nw;
                 }
                 change = ch;
             }
-            {
-                double mx = 0.0;
-                for (int k = 0; k < chi; ++k) mx = fmax(mx, pow(sC[k], al));
-                log_scale += log(mx);
-            }
+            log_scale += log(mx);
             __syncthreads();
         }
         const bool done = change <= tol && sweep >= ramp;
@@ -577,11 +581,33 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
     hipLaunchKernelGGL(k_rank_gather, dim3(n), dim3(256), 0, s, reinterpret_cast<const double *const *>(B + oSrc),
                        reinterpret_cast<const int *>(B + oSizes), n_sites, reinterpret_cast<double *>(B + oT));
     RK_TRY(hipGetLastError());
-    hipLaunchKernelGGL(k_weight_pass, dim3(n), dim3(kRkWp), (size_t)geo.toff[n_sites] * sizeof(double), s,
-                       reinterpret_cast<const RkGeo *>(B + oGeo),
-                       reinterpret_cast<double *>(B + oT), reinterpret_cast<double *>(B + oS),
-                       reinterpret_cast<double *>(B + oLog), reinterpret_cast<int *>(B + oSw),
-                       reinterpret_cast<int *>(B + oSt), opt->alpha, opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+    {
+        const size_t lds = (size_t)geo.toff[n_sites] * sizeof(double);
+        auto *g = reinterpret_cast<const RkGeo *>(B + oGeo);
+        auto *T = reinterpret_cast<double *>(B + oT);
+        auto *Sw = reinterpret_cast<double *>(B + oS);
+        auto *Lg = reinterpret_cast<double *>(B + oLog);
+        auto *Sp = reinterpret_cast<int *>(B + oSw);
+        auto *St = reinterpret_cast<int *>(B + oSt);
+        switch (chi) {
+            case 1:
+                hipLaunchKernelGGL(k_weight_pass<1>, dim3(n), dim3(kRkWp), lds, s, g, T, Sw, Lg, Sp, St, opt->alpha,
+                                   opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+                break;
+            case 2:
+                hipLaunchKernelGGL(k_weight_pass<2>, dim3(n), dim3(kRkWp), lds, s, g, T, Sw, Lg, Sp, St, opt->alpha,
+                                   opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+                break;
+            case 3:
+                hipLaunchKernelGGL(k_weight_pass<3>, dim3(n), dim3(kRkWp), lds, s, g, T, Sw, Lg, Sp, St, opt->alpha,
+                                   opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+                break;
+            default:
+                hipLaunchKernelGGL(k_weight_pass<4>, dim3(n), dim3(kRkWp), lds, s, g, T, Sw, Lg, Sp, St, opt->alpha,
+                                   opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+                break;
+        }
+    }
     RK_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_lattice_terms, dim3((unsigned)n * n_terms), dim3(256), 0, s,
                        reinterpret_cast<const RkGeo *>(B + oGeo), reinterpret_cast<const double *>(B + oT),
