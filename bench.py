@@ -276,7 +276,7 @@ def strip_bytes(chi: int, k: int, paired: bool = True) -> int:
 
 def strips_bench(pne, P, L: int = 12, betas=(0.3, 0.4, 0.4407, 0.5, 0.6)):
     """Infinite 2D Ising, 2x2 blocked (chi = 4, four spins per tensor), width-L
-    strips in both directions (Sec. IV.B): wall time per coupling, the free
+    strips in both directions (Sec. IV.C): wall time per coupling, the free
     energy per spin against Onsager's, and the streaming passes' algorithmic
     bytes over that wall time."""
     import torch
@@ -333,7 +333,7 @@ def rank_bench(pne, P, n: int = 4096):
         ms = (time.perf_counter() - t0) * 1e3
         errs = [abs(float(out["log_abs"][i]) - e) for i, e in zip(samples, exact)]
         print(json.dumps({"workload": f"coarse-grained 6x6 Ising below T_c (3x3, chi=4), rank-{r} weight-passing "
-                          "projectors, four centre bonds, Eq. A4, fp64", "networks": n, "ms": round(ms, 2),
+                          "projectors, four centre bonds, Eq. (4), fp64", "networks": n, "ms": round(ms, 2),
                           "networks_per_s": round(n / (ms * 1e-3), 1), "mean_sweeps": float(out["sweeps"].mean()),
                           "status_min": int(out["status"].min()),
                           "abs_err_lnZ_vs_exact_samples": errs}), flush=True)
@@ -362,12 +362,12 @@ def workloads_bench(pne, P, steps: int):
         ("32x32 D=6 U[0,1], two open dim-2 legs d = 1..8 apart, x16 each, K=8, fp32",
          lambda: [P.config5_network(d) for d in range(1, 9)] * 16, 8, "fp32", False),
     ]
-    # user partitions (Eqs. A4, A6): complete expansion over the partitions
+    # user partitions (Eqs. (4), (7)): complete expansion over the partitions
     parted = [
-        ("3x3 U[0,2] D=4 (seed 50000+i), six multi-index partitions, Eq. A6 complete (K=12), fp64",
+        ("3x3 U[0,2] D=4 (seed 50000+i), six multi-index partitions, Eq. (7) complete (K=12), fp64",
          lambda: [P.small_network(3, 3, "random", 4, seed=50000 + i) for i in range(8192)], 12, "fp64", True,
          P.grid3_multi_partitions),
-        ("3x2 double loop U[0,2] D=6 (seed 60000+i), three vertical partitions, Eq. A4 complete (K=7), fp64",
+        ("3x2 double loop U[0,2] D=6 (seed 60000+i), three vertical partitions, Eq. (4) complete (K=7), fp64",
          lambda: [P.small_network(3, 2, "random", 6, seed=60000 + i) for i in range(16384)], 7, "fp64", True,
          P.double_loop_partitions),
         ("3x4 U[0,2] D=4 (seed 70000+i), five lines with the two 3x3 principal terms refined by six partitions "

@@ -5,11 +5,11 @@
  * Approximate Tensor Network Contractions"):
  *
  *   Input  : a tensor network — site tensors T_r joined by indices (Sec. II.A,
- *            Eq. A1) — optionally with open indices (Sec. III.D).
- *   Method : every bond is a single-index partition P_b + Q_b = I (Eq. A2);
+ *            Eq. (1)) — optionally with open indices (Sec. III.D).
+ *   Method : every bond is a single-index partition P_b + Q_b = I (Eq. (2));
  *            P_b is the rank-1 projector made from the two fixed-point belief
- *            propagation messages on the bond (Eq. A7), symmetrised by the
- *            gauge of Appendix B; the complete P/Q expansion (Eq. A4) is
+ *            propagation messages on the bond (Eq. (8)), symmetrised by the
+ *            gauge of Appendix B; the complete P/Q expansion (Eq. (4)) is
  *            truncated to configurations of at most K excited (Q) bonds that
  *            have no dangling excitation (Sec. III.A-B, "degree").
  *   Output : the approximate contraction value as (sign, ln|Z|), or, for a
@@ -150,10 +150,10 @@ pne_status pne_network_create(pne_ctx *ctx, const pne_network_desc *desc, int da
                               pne_network **out);
 pne_status pne_network_destroy(pne_network *net);
 
-/* User partitions (Sec. II.A-C, Eqs. A4, A6, A8-A10).  Partition p transects
+/* User partitions (Sec. II.A-C, Eqs. (4), (7), (9)-(11)).  Partition p transects
  * the bonds part_bond[part_begin[p] .. part_begin[p+1]) (part_begin has
  * n_partitions + 1 entries, part_begin[0] == 0); its projector is the product
- * of the rank-1 BP projectors of those bonds (Eq. A10), so a multi-index
+ * of the rank-1 BP projectors of those bonds (Eq. (11)), so a multi-index
  * partition keeps its bonds together.  Bonds transected by no partition carry
  * the identity.  Partitions may share bonds.  n_partitions == 0 restores the
  * default (every bond expanded, degree cap only).
@@ -165,7 +165,7 @@ pne_status pne_network_destroy(pne_network *net);
  * paper's partitioned expansion with the residue dropped; n_config_terms then
  * counts the retained loop configurations.  In the rank-1 BP gauge the
  * residue is the sum of the dangling-free configurations that excite at
- * least one bond of every partition (Eq. A9), which is how the library
+ * least one bond of every partition (Eq. (10)), which is how the library
  * evaluates it: every retained configuration is listed at plan time, so the
  * envelope is small networks (at most 2^24 listed cluster entries).
  *
@@ -360,16 +360,16 @@ pne_status pne_server_completed(pne_server *server, uint64_t *tickets, int32_t c
 
 /* ------------------------------------------------------------------------
  * Strip expansion of an infinite, translation-invariant square lattice
- * (Sec. IV.B).  One tensor A repeats on every site; the result is the free
+ * (Sec. IV.C).  One tensor A repeats on every site; the result is the free
  * energy per site f = -lim ln Z_N / N.
  *
  * The lattice is expanded over width-L strip partitions: L vertical
  * partitions (every L-th column line at offsets 0..L-1, each transecting the
  * horizontal bonds that cross it) and, with two_d, L horizontal ones.  P on a
- * bond is the rank-1 projector of the uniform BP fixed point (Eq. A7, oblique
+ * bond is the rank-1 projector of the uniform BP fixed point (Eq. (8), oblique
  * form, which includes 1 / (message overlap)).  Per unit cell (L x L sites,
  * or L sites of a row with vertical partitions only) the combinatorial form
- * (Eq. A6) sums, over non-empty sets of partitions with sign + for an odd
+ * (Eq. (7)) sums, over non-empty sets of partitions with sign + for an odd
  * count and - for an even one, the product of the pieces the partitions cut
  * the cell into:
  *   lam_k   leading eigenvalue of the width-k vertical transfer matrix (k
@@ -446,15 +446,15 @@ pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t chi, const pn
  * sweeps over the bonds: with A', B' the two site tensors with the weights of
  * their other bonds applied, A' = U_A S_A V_A^T (other legs x this leg),
  * B' = U_B S_B V_B^T (this leg x other legs), S_A V_A^T S_b U_B S_B =
- * U_C S_C V_C^T (Eqs. weight1, weight2), the tensors take the gauge change of
- * Eq. weight3 and S_b becomes S_C^a (rescaled to a largest entry of 1, the
+ * U_C S_C V_C^T (Eqs. (C1), (C2)), the tensors take the gauge change of
+ * Eq. (C3) and S_b becomes S_C^a (rescaled to a largest entry of 1, the
  * scale kept in log_scale).  a ramps linearly up to alpha over the first
  * ramp_sweeps sweeps; sweeps stop once no weight entry moves by more than tol.
  * In that gauge the weights decrease along each bond, and the rank-r
  * projector of a bond keeps its first r indices: P = diag(1_r, 0), Q = I - P.
  *
  * The expansion over the given partitions (bond lists) is the combinatorial
- * form (form 0, Eq. A6) or the linear form (form 1, Eq. A4, single-index
+ * form (form 0, Eq. (7)) or the linear form (form 1, Eq. (4), single-index
  * partitions in the given order), the residue dropped; each term contracts
  * the gauged lattice exactly with S_b P, S_b Q or S_b on every bond.  With
  * r = chi every P is the identity and the result is the exact value.
@@ -470,7 +470,7 @@ pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t chi, const pn
  * ------------------------------------------------------------------------ */
 typedef struct {
     int32_t rank;        /* r, 1..chi (2)                                 */
-    int32_t form;        /* 0: combinatorial (Eq. A6); 1: linear (Eq. A4)  */
+    int32_t form;        /* 0: combinatorial (Eq. (7)); 1: linear (Eq. (4))  */
     double alpha;        /* weight exponent a (0.8)                        */
     int32_t ramp_sweeps; /* sweeps over which a ramps up to alpha (10)     */
     int32_t max_sweeps;  /* sweep cap (2000)                               */

@@ -2,12 +2,12 @@
 
 TEST INFRASTRUCTURE ONLY.
 
-* exact_contract: Eq. A1 evaluated by absorbing sites one at a time.
+* exact_contract: Eq. (1) evaluated by absorbing sites one at a time.
 * ising_bruteforce_logz: the Ising partition function summed over all spin
   states, straight from the Boltzmann weights (independent of any tensor
   encoding).
 * full_expansion_sum: the complete P/Q expansion, every one of the 2^M
-  configurations contracted literally (Eq. A4/A6 are regroupings of it).
+  configurations contracted literally (Eqs. (4)/(7) are regroupings of it).
 """
 
 from __future__ import annotations
@@ -19,7 +19,7 @@ import numpy as np
 
 
 def exact_contract(net):
-    """Exact contraction (Eq. A1); returns (log_scale, tensor).
+    """Exact contraction (Eq. (1)); returns (log_scale, tensor).
 
     Z = tensor * exp(log_scale); the tensor has one axis per open leg in the
     network's open-leg order (a 0-d array for a closed network).  Sites are

@@ -3,18 +3,18 @@
 TEST INFRASTRUCTURE ONLY (see package docstring).  FP64 throughout.
 
 A partition p transects a set of bonds.  Its projector is the product of the
-rank-1 BP projectors of those bonds (Eq. A8 with Eq. A10); in the network's
+rank-1 BP projectors of those bonds (Eq. (9) with Eq. (11)); in the network's
 own gauge the rank-1 projector of a bond is the oblique P_b = a c^T / (a . c)
 built from the two fixed-point messages, which is the symmetrised projector of
 Appendix B written back in the original gauge.  Bonds that no partition
 transects carry the identity.
 
-* ``combinatorial_terms`` writes out Eq. A6: for every non-empty subset x of
+* ``combinatorial_terms`` writes out Eq. (7): for every non-empty subset x of
   the partitions, the whole network with P_b inserted on every bond
   transected by a partition in x, contracted exactly, with sign + for odd |x|
   and - for even |x|.  Where two partitions of x share a bond, P_b is
   inserted once (P_b P_b = P_b).
-* ``linear_terms`` writes out Eq. A4 for single-index partitions taken in the
+* ``linear_terms`` writes out Eq. (4) for single-index partitions taken in the
   given order: term r has Q on the bonds of partitions 0..r-1, P on the bond
   of partition r and the identity elsewhere.
 * ``residue`` is Eq. res for single-index partitions: Q on every partitioned
@@ -89,7 +89,7 @@ def subsets(n_parts):
 
 
 def combinatorial_terms(net, partitions, proj=None):
-    """Eq. A6 without its residue: list of (sign, log_scale, value, subset)."""
+    """Eq. (7) without its residue: list of (sign, log_scale, value, subset)."""
     parts = _check_partitions(net, partitions)
     if proj is None:
         proj = bp_projectors(net)
@@ -106,12 +106,12 @@ def combinatorial_terms(net, partitions, proj=None):
 
 
 def combinatorial_pne(net, partitions, proj=None):
-    """(sign, ln|Z_PNE|): Eq. A6 with the residue dropped."""
+    """(sign, ln|Z_PNE|): Eq. (7) with the residue dropped."""
     return _scaled_sum([(s, ls, v) for (s, ls, v, _) in combinatorial_terms(net, partitions, proj)])
 
 
 def linear_pne(net, partitions, proj=None):
-    """(sign, ln|Z_PNE|): Eq. A4 with the residue dropped (single-index partitions)."""
+    """(sign, ln|Z_PNE|): Eq. (4) with the residue dropped (single-index partitions)."""
     parts = _check_partitions(net, partitions)
     if any(len(p) != 1 for p in parts):
         raise ValueError("the linear form is written for single-index partitions")
@@ -172,7 +172,7 @@ def count_retained(net, partitions, K):
 def recursive_pne(net, partitions, subpartitions, proj=None):
     """(sign, ln|Z|): recursive partitioning (Sec. IV.A) written out.
 
-    Eq. A6 over the first-level partitions, except that the term of each
+    Eq. (7) over the first-level partitions, except that the term of each
     subset x that `subpartitions` maps (key: tuple of partition indices,
     ascending) to a list of sub-partitions is itself expanded: it becomes the
     combinatorial form, residue dropped, of the network with P on x's bonds,

@@ -4,15 +4,15 @@ TEST INFRASTRUCTURE ONLY (see package docstring).  FP64 throughout.
 
 What is computed (paper Sec. II and III):
 
-* Every bond is its own single-index partition with P_b + Q_b = I (Eq. A2).
+* Every bond is its own single-index partition with P_b + Q_b = I (Eq. (2)).
   P_b is the rank-1 projector built from the two fixed-point BP messages on
-  the bond (Eq. A7).  With a_b the message arriving at the bond's first site
+  the bond (Eq. (8)).  With a_b the message arriving at the bond's first site
   u and c_b the one arriving at its second site v, the oblique form
   P_b = a_b c_b^T / (a_b . c_b) is the symmetrised projector of Appendix B
   written back in the original gauge, so no SVD is needed here.
 * The complete P/Q expansion over all bonds is the sum over configurations y
   (the set of bonds carrying Q) of Z(y), the network with Q on y and P
-  elsewhere (Eq. A4/A6 are regroupings of this sum).
+  elsewhere (Eqs. (4)/(7) are regroupings of this sum).
 * Retained terms: configurations of degree |y| <= K without dangling
   excitations (a site with exactly one excited bond), which vanish at a BP
   fixed point (Sec. III.A-B).  Sites with open legs are exempt from the
@@ -119,7 +119,7 @@ def bp_messages(net, tol=1e-13, max_iter=500):
 
 
 # ----------------------------------------------------------------------------
-# projectors (Eq. A2, A7 and Appendix B in oblique form)
+# projectors (Eqs. (2), (8) and Appendix B in oblique form)
 
 
 def projectors(net, inc):

@@ -9,9 +9,9 @@ site u (tensor A) and leg lv of site v (tensor B):
 * A' is A with the weights of all its other bonds multiplied onto their legs,
   read as a matrix (other legs) x (leg lu); its SVD A' = U_A S_A V_A^T.
 * B' likewise, read as (leg lv) x (other legs); its SVD B' = U_B S_B V_B^T.
-* S_A V_A^T diag(S_b) U_B S_B = U_C S_C V_C^T (Eq. weight2).
+* S_A V_A^T diag(S_b) U_B S_B = U_C S_C V_C^T (Eq. (C2)).
 * A <- A x_lu (V_A S_A^-1 U_C S_C^((1-a)/2)), B <- (S_C^((1-a)/2) V_C^T
-  S_B^-1 U_B^T) x_lv B, S_b <- S_C^a (Eq. weight3): a pure change of gauge
+  S_B^-1 U_B^T) x_lv B, S_b <- S_C^a (Eq. (C3)): a pure change of gauge
   of the network with its weights.
 * The new weight is rescaled to a largest entry of 1, the scale carried in a
   log-factor of the network value.
@@ -114,7 +114,7 @@ def _contract(net, T, ops):
 
 def rank_expansion(net, partitions, r, form="combinatorial", wp=None, **wp_kw):
     """(sign, ln|Z|) of the partitioned expansion with rank-r weight-passing
-    projectors, the residue dropped: Eq. A6 over the partitions, or Eq. A4
+    projectors, the residue dropped: Eq. (7) over the partitions, or Eq. (4)
     (single-index partitions, in the given order)."""
     if wp is None:
         wp = weight_passing(net, **wp_kw)

@@ -1,4 +1,4 @@
-"""Oracle: strip expansions of infinite uniform square-lattice networks (Sec. IV.B).
+"""Oracle: strip expansions of infinite uniform square-lattice networks (Sec. IV.C).
 
 TEST INFRASTRUCTURE ONLY (see package docstring).  FP64 throughout.
 
@@ -7,7 +7,7 @@ Its BP fixed point is translation invariant: four messages mL, mR, mU, mD,
 the ones arriving on a site's -x, +x, -y and +y legs.  The rank-1 projector of
 a horizontal bond is P = mR mL^T / n_h with n_h = mR . mL (the message
 arriving at the left site's +x leg times the one arriving at the right
-site's -x leg), and likewise n_v = mD . mU vertically (Eq. A7 in the
+site's -x leg), and likewise n_v = mD . mU vertically (Eq. (8) in the
 oblique form).
 
 A partition is the set of horizontal bonds (vertical partition lines) that
@@ -23,7 +23,7 @@ L x L sites):
 * patch_hat[k][p]  the k x p patch (k columns, p rows) with every outer leg
                capped by its arriving message, divided by n_v^k n_h^p.
 
-The combinatorial form (Eq. A6) over the L vertical (and L horizontal)
+The combinatorial form (Eq. (7)) over the L vertical (and L horizontal)
 partitions, taken per unit cell as the paper does, gives
 
   1D: f = -(1/L)   log sum_{xv != 0} (-1)^(|xv|+1) prod_{gaps g of xv} lam_hat[g]
@@ -148,7 +148,7 @@ def gaps(x, L):
 
 
 def strip_combination(lam, gam, patch, L, two_d=True):
-    """The per-cell sum of Eq. A6 over the strip partitions (lam, gam indexed
+    """The per-cell sum of Eq. (7) over the strip partitions (lam, gam indexed
     1..L, patch[k][p]); returns the free energy per site."""
     total = 0.0
     offs = range(L)

@@ -764,11 +764,11 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
     }
 
     if (g.n_parts() > 0) {
-        // User partitions (Eq. A4 / A6 with factorised multi-index projectors,
-        // Eq. A8 / A10).  Dropping the residue removes exactly the
+        // User partitions (Eqs. (4) / (7) with factorised multi-index projectors,
+        // Eqs. (9) / (11)).  Dropping the residue removes exactly the
         // configurations that excite at least one bond of every partition
         // (with rank-1 P, Q_p = I - P_p is the sum of the terms with some bond
-        // of p excited, Eq. A9), so the retained configurations are the
+        // of p excited, Eq. (10)), so the retained configurations are the
         // vertex-disjoint cluster sets of degree <= K whose excited bonds miss
         // some partition.  They are listed one by one.
         plan->listed = true;

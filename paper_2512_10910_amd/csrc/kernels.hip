@@ -9,7 +9,7 @@
 //               terms of Sec. III.A-B; every term keeps the original geometry
 //               with modified tensors, Sec. VI)
 //   k_combine   per network: FP64 sum of the retained configurations
-//               (Eq. A4 truncated to degree <= K, vertex-disjoint products)
+//               (Eq. (4) truncated to degree <= K, vertex-disjoint products)
 #include <hip/hip_runtime.h>
 
 #include <cstdint>

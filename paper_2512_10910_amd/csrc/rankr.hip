@@ -1,10 +1,10 @@
 // Rank-r projectors from weight passing (Sec. V, Appendix C) on small closed
 // lattice networks, batched: one block per network runs the weight-passing
-// sweeps (Eqs. weight1-weight3) with one-sided Jacobi SVDs, then one block
+// sweeps (Eqs. (C1)-(C3)) with one-sided Jacobi SVDs, then one block
 // per (network, term) contracts the gauged lattice with a diagonal operator
 // on every bond (the weight S_b restricted to its first r indices for P, to
 // the rest for Q, or whole), and one block per network adds the terms of the
-// linear (Eq. A4) or combinatorial (Eq. A6) form.
+// linear (Eq. (4)) or combinatorial (Eq. (7)) form.
 #include <hip/hip_runtime.h>
 
 #include <cmath>

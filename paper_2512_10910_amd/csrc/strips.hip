@@ -1,5 +1,5 @@
 // Strip expansion of an infinite, translation-invariant square-lattice
-// network (Sec. IV.B).  One tensor A[l, r, u, d] (legs -x, +x, -y, +y, bond
+// network (Sec. IV.C).  One tensor A[l, r, u, d] (legs -x, +x, -y, +y, bond
 // dimension chi) repeats on every site.  The path:
 //
 //   1. uniform BP: the four messages arriving on a site's legs (k_uniform_bp);
@@ -12,7 +12,7 @@
 //      iteration starts from the product of the top caps, so its first L
 //      applications also give the capped k x p patches (dot with the product
 //      of the bottom caps, fused into the last pass);
-//   3. the combinatorial sum (Eq. A6) over the L vertical and L horizontal
+//   3. the combinatorial sum (Eq. (7)) over the L vertical and L horizontal
 //      strip partitions per unit cell (k_strip_combine).
 //
 // Every quantity is divided by the BP value per site raised to its number of
@@ -542,7 +542,7 @@ __device__ double cyclic_sum(const double *c, int L) {
     return -t;
 }
 
-// The per-cell sum of Eq. A6 over the strip partitions, and f.  Vertical
+// The per-cell sum of Eq. (7) over the strip partitions, and f.  Vertical
 // strips only (two_d == 0): S = cyclic_sum(lam).  Both directions: the
 // subsets with only vertical (only horizontal) partitions give
 // cyclic_sum(lam^L) (cyclic_sum(gam^L)); a non-empty horizontal subset xh

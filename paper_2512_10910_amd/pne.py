@@ -484,7 +484,7 @@ class Context:
     def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
                      power_max_iter: int = 20000, check_every: int = 4, single_site_passes: bool = False) -> dict:
         """Strip expansion of the infinite lattice of tensor A (legs -x, +x, -y, +y;
-        Sec. IV.B): free energy per site and the per-width quantities."""
+        Sec. IV.C): free energy per site and the per-width quantities."""
         A = np.ascontiguousarray(np.asarray(A, dtype=np.float64))
         if A.ndim != 4 or len(set(A.shape)) != 1:
             raise ValueError("A must be a rank-4 tensor with equal leg dimensions")
@@ -550,7 +550,7 @@ class Network:
         ctx._children.add(self)
 
     def set_partitions(self, partitions):
-        """Partitions as lists of bond indices (Eqs. A4, A6, A8-A10); [] clears.
+        """Partitions as lists of bond indices (Eqs. (4), (7), (9)-(11)); [] clears.
 
         Batches made afterwards expand the network over these partitions
         (closed networks; see pne_network_set_partitions)."""

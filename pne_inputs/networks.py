@@ -441,7 +441,7 @@ def grid3_multi_partitions(net: Network):
 
 
 # ----------------------------------------------------------------------------
-# uniform tensors of infinite square lattices (Sec. IV.B); legs (-x, +x, -y, +y)
+# uniform tensors of infinite square lattices (Sec. IV.C); legs (-x, +x, -y, +y)
 
 
 def ising_uniform_tensor(beta: float, J: float = 1.0) -> np.ndarray:

@@ -1,8 +1,8 @@
-"""GPU parity for user partitions (Sec. II.A-C, Eqs. A4, A6, A8-A10).
+"""GPU parity for user partitions (Sec. II.A-C, Eqs. (4), (7), (9)-(11)).
 
 The library evaluates a partitioned network as the BP vacuum times the sum of
 the listed loop configurations that leave some partition unexcited; the
-oracle evaluates Eq. A6 directly, as signed exact contractions of the network
+oracle evaluates Eq. (7) directly, as signed exact contractions of the network
 with P inserted on the transected bonds.  The two share nothing but the
 inputs.
 
@@ -172,7 +172,7 @@ def test_invalid_partitions_are_errors(ctx):
 def test_workload_batch_sampled(ctx):
     """The benchmark's partition workload at its full size: 8192 3 x 3
     networks (D = 4, U[0, 2]) with six multi-index partitions, complete
-    expansion, FP64 terms; sampled networks against Eq. A6."""
+    expansion, FP64 terms; sampled networks against Eq. (7)."""
     nb = 8192
     raw = [P.small_network(3, 3, "random", 4, seed=50000 + i, bias=1.0) for i in range(nb)]
     parts = P.grid3_multi_partitions(raw[0])

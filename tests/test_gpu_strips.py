@@ -1,4 +1,4 @@
-"""GPU parity for the infinite-lattice strip expansion (Sec. IV.B).
+"""GPU parity for the infinite-lattice strip expansion (Sec. IV.C).
 
 The HIP path (uniform BP, power iteration of every strip transfer matrix,
 patches, cell sum) against the oracle's dense transfer matrices and exact

@@ -1,11 +1,11 @@
 """Pins of the partitioned-expansion oracle (user partitions, Sec. II.A-C).
 
-The two forms (Eq. A4, Eq. A6) are checked against facts that do not come from
-the oracle's own inclusion-exclusion: the exact contraction (Eq. A1), the
+The two forms (Eq. (4), Eq. (7)) are checked against facts that do not come from
+the oracle's own inclusion-exclusion: the exact contraction (Eq. (1)), the
 residue written out directly (Q on every partition, Eq. res), the double-loop
 example whose residue is a single degree-seven loop term (Sec. III.A), a
 brute-force spin sum for the Ising model, a brute-force sum over every
-excitation pattern for multi-index partitions (Eq. A9), and the term count of
+excitation pattern for multi-index partitions (Eq. (10)), and the term count of
 the six-partition 3 x 3 expansion.  The host planner of the library is checked
 against the oracle's brute-force count of retained configurations (no GPU
 needed).
@@ -69,7 +69,7 @@ def test_double_loop_ising_is_exact():
 @pytest.mark.parametrize("Lx,Ly,parts_of,seed", [(3, 2, P.double_loop_partitions, 5),
                                                   (3, 3, P.grid3_single_partitions, 6)])
 def test_single_index_forms_plus_residue_are_exact(Lx, Ly, parts_of, seed):
-    """Eq. A4 and Eq. A6 each add up, with the residue, to the exact value,
+    """Eq. (4) and Eq. (7) each add up, with the residue, to the exact value,
     for BP projectors and for arbitrary rank-1 projectors alike."""
     net = P.small_network(Lx, Ly, "random", 3, seed=seed, bias=0.7)
     parts = parts_of(net)
@@ -93,7 +93,7 @@ def test_single_index_forms_plus_residue_are_exact(Lx, Ly, parts_of, seed):
 def test_multi_index_residue_is_every_partition_excited():
     """Six multi-index partitions on 3 x 3: Z0 minus the combinatorial form
     equals the sum over all 2^12 excitation patterns that excite at least one
-    bond of every partition (Eq. A9: Q_p is the sum of the patterns of p with
+    bond of every partition (Eq. (10): Q_p is the sum of the patterns of p with
     an excited bond)."""
     net = P.small_network(3, 3, "random", 2, seed=8, bias=0.8)
     parts = [set(p) for p in P.grid3_multi_partitions(net)]

@@ -3,7 +3,7 @@
 Every check here is independent of the oracle's own arithmetic: brute-force
 spin sums, the high-temperature (HT) closed form with even-subgraph counts
 taken from the cycle space, eigenvalues from LAPACK, exact contractions and
-the complete-expansion identity (Eq. A2-A4: P + Q = I on every bond).
+the complete-expansion identity (Eqs. (2)-(4): P + Q = I on every bond).
 """
 
 import itertools
@@ -264,7 +264,7 @@ def test_open_network_low_order_error_is_small():
     r = O.pne_contract(net, 6)
     le, ex = O.exact_contract(net)
     approx = r.open_values * math.exp(r.log_abs - le)
-    err = np.linalg.norm(approx - ex) / np.linalg.norm(ex)  # Eq. B2
+    err = np.linalg.norm(approx - ex) / np.linalg.norm(ex)  # Eq. (14)
     assert err < 1e-3
 
 

@@ -49,7 +49,7 @@ def test_full_rank_is_exact():
 
 @pytest.mark.parametrize("r", [1, 2])
 def test_linear_form_plus_residue_is_exact(r):
-    """Eq. A4 with rank-r P: the sum of the terms plus the network with Q on
+    """Eq. (4) with rank-r P: the sum of the terms plus the network with Q on
     every partitioned bond is the exact value."""
     net = P.small_network(3, 3, "random", 3, seed=6)
     wp = R.weight_passing(net)

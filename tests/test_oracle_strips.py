@@ -1,4 +1,4 @@
-"""Pins of the strip-expansion oracle (infinite lattices, Sec. IV.B).
+"""Pins of the strip-expansion oracle (infinite lattices, Sec. IV.C).
 
 Independent of the oracle's own construction: Ising strips and patches from
 the spin basis (transfer matrices with exp(beta s s') bond weights, brute
@@ -168,7 +168,7 @@ def test_product_tensor_is_exact_at_every_width():
 
 def test_the_printed_width_two_and_three_formulas():
     """General-L subset sums reproduce the paper's L = 2 formulas (and the
-    L = 3 vertical one, with the sign Eq. A6 gives the pair terms)."""
+    L = 3 vertical one, with the sign Eq. (7) gives the pair terms)."""
     rng = np.random.default_rng(3)
     lam = {k: rng.uniform(0.9, 1.1) * 2 ** k for k in (1, 2, 3)}
     gam = {k: rng.uniform(0.9, 1.1) * 2 ** k for k in (1, 2)}
