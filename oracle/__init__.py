@@ -17,6 +17,7 @@ from .pne_oracle import (  # noqa: F401
     bp_messages,
     projectors,
     vacuum,
+    dangling_max,
     enumerate_clusters,
     cluster_weight,
     enumerate_collections,

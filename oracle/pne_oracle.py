@@ -75,7 +75,7 @@ def _contract_except(t, msgs, keep):
     return out
 
 
-def bp_messages(net, tol=1e-13, max_iter=500):
+def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0):
     """Jacobi BP from uniform messages.
 
     Every directed message starts at 1/sqrt(d).  A sweep recomputes every
@@ -84,9 +84,17 @@ def bp_messages(net, tol=1e-13, max_iter=500):
     residual is the largest sign-insensitive infinity-norm change over all
     messages; sweeps stop once it is <= tol or after max_iter sweeps.
 
+    Damping (not part of the paper's method; 0 by default): with
+    0 <= damping < 1 the stored message is the mix
+    (1 - damping) * m_new + damping * m_old of the normalised update and the
+    same directed message of the previous sweep, normalised and sign-fixed
+    again; the residual then compares the stored message with m_old.
+
     Returns (inc, iters, residual, converged), where inc[s][l] is the message
     arriving at leg l of site s.
     """
+    if not (0.0 <= damping < 1.0):
+        raise ValueError("damping must be in [0, 1)")
     partner = _partners(net)
     T = net.tensors
     inc = [[np.full(d, 1.0 / math.sqrt(d)) for d in t.shape] for t in T]
@@ -104,6 +112,14 @@ def bp_messages(net, tol=1e-13, max_iter=500):
                 if m.sum() < 0:
                     m = -m
                 s2, l2 = partner[(s, l)]
+                if damping > 0.0:
+                    m = (1.0 - damping) * m + damping * inc[s2][l2]
+                    nrm = float(np.sqrt(np.sum(m * m)))
+                    if not (nrm > 0.0) or not np.isfinite(nrm):
+                        raise FloatingPointError(f"zero damped message at site {s} leg {l}")
+                    m = m / nrm
+                    if m.sum() < 0:
+                        m = -m
                 new[s2][l2] = m
         residual = 0.0
         for s, t in enumerate(T):
@@ -160,15 +176,62 @@ def vacuum(net, inc):
     return out
 
 
+def dangling_max(net, inc):
+    """Size of the dropped dangling terms (Sec. III.A-B: a site with a single
+    excited bond gives a term that vanishes at a BP fixed point).
+
+    For every bond b = (u, v) with a = the message arriving at u, c = the one
+    arriving at v and n = a . c, let y_u (y_v) be the site tensor of u (v)
+    with every other leg capped by its arriving message.  The excited part of
+    the single-leg term is measured in the excited basis of the symmetrising
+    gauge (Appendix B): on the bond's first site the component of y_u
+    orthogonal to c, on its second site Q y_v with Q = I - a c^T / n, each
+    relative to the site's vacuum value (y_u . a / n, resp. y_v . c):
+
+        d_u = |(I - c c^T / |c|^2) y_u| |n| / |y_u . a|,
+        d_v = |y_v - a (c . y_v) / n| / |c . y_v|.
+
+    Returns the largest d over every bond end at a site without open legs
+    (0.0 for a network without such bonds).  It is 0 at a BP fixed point,
+    where y_u is parallel to c and y_v to a.
+
+    Parity: pinned by the fixed-point zero and by the bound
+    |w_{b}| <= d_u d_v on the explicitly contracted single-bond term.
+    """
+    open_site = _open_slots(net)
+    worst = 0.0
+    for (u, lu, v, lv) in net.bonds:
+        u, lu, v, lv = int(u), int(lu), int(v), int(lv)
+        a = inc[u][lu]
+        c = inc[v][lv]
+        if len(a) < 2:
+            continue  # a bond of dimension 1 has no excited index
+        n = float(a @ c)
+        if u not in open_site:
+            y = np.asarray(_contract_except(net.tensors[u], inc[u], lu), dtype=np.float64)
+            perp = y - c * (float(c @ y) / float(c @ c))
+            worst = max(worst, float(np.linalg.norm(perp)) * abs(n) / abs(float(y @ a)))
+        if v not in open_site:
+            y = np.asarray(_contract_except(net.tensors[v], inc[v], lv), dtype=np.float64)
+            q = y - a * (float(c @ y) / n)
+            worst = max(worst, float(np.linalg.norm(q)) / abs(float(c @ y)))
+    return worst
+
+
 # ----------------------------------------------------------------------------
 # term enumeration (Sec. III.A-B)
 
 
-def enumerate_clusters(net, K):
-    """Connected, dangling-free bond sets of size <= K (open sites exempt)."""
+def enumerate_clusters(net, K, full=False):
+    """Connected, dangling-free bond sets of size <= K (open sites exempt).
+
+    full=True drops the dangling rule: every connected bond set of size <= K
+    (the components of the complete expansion's configurations)."""
     exempt = np.zeros(net.n_sites, np.uint8)
     for (s, _) in net.open_legs:
         exempt[int(s)] = 1
+    if full:
+        exempt[:] = 1
     if net.n_bonds == 0 or K <= 0:
         return []
     return _enum.enum_clusters(net.n_sites, net.bonds[:, 0], net.bonds[:, 2], exempt, K)
@@ -270,18 +333,29 @@ class OracleResult:
     n_clusters: int
     n_configs: int
     open_values: np.ndarray | None = None
+    dangling_max: float = 0.0
     clusters: list = field(default_factory=list)
     weights: list = field(default_factory=list)
     inc: list | None = None
 
 
-def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False):
+def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop", damping=0.0):
     """Loop-truncated PNE of a closed or open network.
 
     Closed network: returns (sign, ln|Z|).  Open network: Out = open_values *
     exp(log_abs) with axes in the network's open-leg order.
+
+    mode "loop": configurations of degree <= K without dangling sites (the
+    retained terms).  mode "full": every configuration of degree <= K, the
+    dangling ones included (closed networks); with K >= n_bonds this is the
+    complete expansion of Eqs. (2)-(4), equal to the exact contraction for
+    any rank-1 projectors, converged or not.
     """
-    inc, iters, residual, converged = bp_messages(net, tol, max_iter)
+    if mode not in ("loop", "full"):
+        raise ValueError("mode must be 'loop' or 'full'")
+    if mode == "full" and net.n_open:
+        raise ValueError("full mode is for closed networks")
+    inc, iters, residual, converged = bp_messages(net, tol, max_iter, damping)
     proj = projectors(net, inc)
     z = vacuum(net, inc)
     open_site = _open_slots(net)
@@ -301,7 +375,7 @@ def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False):
         log_scale -= math.log(abs(n))
         sign *= 1 if n > 0 else -1
 
-    clusters = enumerate_clusters(net, K)
+    clusters = enumerate_clusters(net, K, full=(mode == "full"))
     weights = [cluster_weight(net, inc, proj, z, c) for c in clusters]
     sizes = [len(c) for c in clusters]
     vsets = [cluster_sites(net, c) for c in clusters]
@@ -350,6 +424,7 @@ def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False):
                            bp_residual=residual, converged=converged,
                            n_clusters=len(clusters), n_configs=len(colls),
                            open_values=sign * out)
+    res.dangling_max = dangling_max(net, inc)
     if keep_details:
         res.clusters = clusters
         res.weights = weights

@@ -737,7 +737,10 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     NetState *ns = st + fn.net;
     const unsigned long long t_start = wall_clock64();
     __shared__ double s_res[2 * NW];
-    __shared__ int s_bad;
+    // a singular message in step k sets s_bad[k & 1]: every wave reads the
+    // slot of its own step after that step's barrier, so all waves leave the
+    // loop at the same step (a fast wave's next step writes the other slot)
+    __shared__ int s_bad[2];
     __shared__ int s_status;  // the network's status this run (lowered with LDS atomics)
     const int tid = threadIdx.x;
     const int wave = tid >> 6;
@@ -771,7 +774,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         reinterpret_cast<int64_t *>(p_lds + L.soff)[s] = r.slice_off;
     }
     if (tid == 0) {
-        s_bad = 0;
+        s_bad[0] = 0;
+        s_bad[1] = 0;
         s_status = 0;
     }
     __syncthreads();
@@ -786,6 +790,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         const int mi = (sweep & 1) ? L.b1 : L.b0;
         const int mo = (sweep & 1) ? L.b0 : L.b1;
         double wres = 0.0;
+        int *bad_slot = &s_bad[sweep & 1];
         // chunks of all groups in one sequence, dealt round-robin to the waves
         int cbase = 0;
         for (int g = 0; g < fn.n_groups; ++g) {
@@ -798,28 +803,28 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
             for (int c = c0; c < nchunks; c += NW) {
                 double tr = 0.0;
                 switch (gr.dc * 8 + gr.rank) {
-                    case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 18: tr = ptiles_dpp<2, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 19: tr = ptiles_dpp<2, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 20: tr = ptiles_dpp<2, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 21: tr = ptiles_dpp<2, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 22: tr = ptiles_dpp<2, 6>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 25: tr = ptiles_dpp<3, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 26: tr = ptiles_dpp<3, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 27: tr = ptiles_dpp<3, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 28: tr = ptiles_dpp<3, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 29: tr = ptiles<3, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 33: tr = ptiles_dpp<4, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 34: tr = ptiles_dpp<4, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 35: tr = ptiles_dpp<4, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 36: tr = ptiles_dpp<4, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 37: tr = ptiles<4, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 41: tr = ptiles<5, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 42: tr = ptiles<5, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 43: tr = ptiles<5, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 49: tr = ptiles<6, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 50: tr = ptiles<6, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
-                    case 51: tr = ptiles<6, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, &s_bad); break;
+                    case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 18: tr = ptiles_dpp<2, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 19: tr = ptiles_dpp<2, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 20: tr = ptiles_dpp<2, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 21: tr = ptiles_dpp<2, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 22: tr = ptiles_dpp<2, 6>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 25: tr = ptiles_dpp<3, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 26: tr = ptiles_dpp<3, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 27: tr = ptiles_dpp<3, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 28: tr = ptiles_dpp<3, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 29: tr = ptiles<3, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 33: tr = ptiles_dpp<4, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 34: tr = ptiles_dpp<4, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 35: tr = ptiles_dpp<4, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 36: tr = ptiles_dpp<4, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 37: tr = ptiles<4, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 41: tr = ptiles<5, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 42: tr = ptiles<5, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 43: tr = ptiles<5, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 49: tr = ptiles<6, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 50: tr = ptiles<6, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                    case 51: tr = ptiles<6, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
                     default: break;
                 }
                 wres = fmax(wres, tr);
@@ -834,8 +839,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         __syncthreads();
         r = slot[0];
         for (int w = 1; w < NW; ++w) r = fmax(r, slot[w]);
-        const int bad = s_bad;  // only ever set: no barrier needed before it changes again
-        if (bad) break;
+        // both slots are still clear whenever the loop goes on
+        if (*bad_slot) break;
         // red-black: both colours' latest updates must be within tol
         if (r <= tol && (!rb || (sweep > 0 && r_prev <= tol))) {
             conv = true;
@@ -852,7 +857,7 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         ns->parity = 0;
         ns->residual = rb ? fmax(r, r_prev) : r;
         ns->converged = conv ? 1 : 0;
-        if (s_bad) s_status = -4;
+        if (s_bad[0] | s_bad[1]) s_status = -4;
         ns->status = s_status;
         ns->t_start = t_start;
         ns->t_bp = wall_clock64();
