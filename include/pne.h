@@ -42,6 +42,8 @@ extern "C" {
 typedef enum {
     PNE_OK = 0,
     PNE_WARN_BP_NOT_CONVERGED = 1, /* result computed from the last BP sweep */
+    PNE_WARN_PRECISION = 2,        /* reduced term precision: the estimated error of the result
+                                      (pne_result.term_err_est) exceeds pne_options.err_bound */
     PNE_ERR_INVALID_ARG = -1,      /* malformed network, options or pointer */
     PNE_ERR_UNSUPPORTED = -2,      /* outside the implemented envelope */
     PNE_ERR_OUT_OF_MEMORY = -3,    /* device allocation failed or budget exceeded */
@@ -80,6 +82,17 @@ typedef enum {
     PNE_BF16 = 2  /* BF16 slices, FP32 arithmetic with FP32 accumulation */
 } pne_precision;
 
+/* Which configurations are summed (Sec. II.A, Sec. III.A-B). */
+typedef enum {
+    PNE_MODE_LOOP = 0, /* degree <= K, no dangling site (a site with exactly one excited bond;
+                          sites with open legs exempt): the retained terms of the method */
+    PNE_MODE_FULL = 1  /* every configuration of degree <= K, dangling ones included.  With
+                          K >= n_bonds this is the complete P/Q expansion of Eqs. (2)-(4), equal
+                          to the exact contraction for any rank-1 projectors, converged or not: a
+                          self-check for tiny networks.  Closed networks without user partitions,
+                          at most 20 bonds (UNSUPPORTED otherwise). */
+} pne_mode;
+
 /* A tensor network (Sec. II.A).  Every leg slot of every site is either
  * joined by exactly one bond or listed exactly once as an open leg. */
 typedef struct {
@@ -104,6 +117,18 @@ typedef struct {
     uint32_t flags;       /* PNE_FLAG_* bits (0: defaults)                       */
     int32_t profile_kernels; /* with PNE_FLAG_PROFILE: bit k times kernel index k of
                                 pne_batch_kernel_times only; 0 times every kernel  */
+    int32_t mode;         /* pne_mode (PNE_MODE_LOOP)                            */
+    int32_t reserved0;
+    double bp_damping;    /* 0 <= lambda < 1 (0): every stored message is the
+                             normalised, sign-fixed mix (1-lambda) m_new +
+                             lambda m_old of the normalised update and the same
+                             directed message of the previous sweep; the
+                             residual compares the stored message with m_old.
+                             lambda > 0 runs Jacobi sweeps launch by launch.   */
+    double err_bound;     /* reduced-precision bound (1e-5): a closed result whose
+                             term_err_est / max(1, |ln|Z||) exceeds it, or an open
+                             one whose term_err_est exceeds it, is returned with
+                             PNE_WARN_PRECISION (FP64 mode never warns)          */
 } pne_options;
 
 /* One network's result.  Closed network: Z = sign * exp(log_abs).  Open
@@ -121,6 +146,24 @@ typedef struct {
     int64_t n_config_terms;  /* retained configurations (collections), excl. 0  */
     double *open_values;     /* caller buffer for open networks, or NULL        */
     int64_t open_capacity;   /* entries available in open_values                */
+    /* Size of the dropped dangling terms (Sec. III.A-B), 0 at a BP fixed
+     * point: over every bond end at a site without open legs, the 2-norm of
+     * the excited entries of the site's single-leg slice (the site tensor
+     * with every other leg on its vacuum vector, over z'_v, in the excited
+     * basis of Appendix B: an orthonormal basis of c^perp at the bond's
+     * first site, Q^T of it at the second).  Read from the stored slices, so
+     * in the term precision. */
+    double dangling_max;
+    /* First-order estimate of the error the term precision puts into the
+     * result: with u the unit roundoff of the slices (2^-53, 2^-24, 2^-8),
+     * v that of the term arithmetic (2^-53 in FP64 mode, else 2^-24), A_s the
+     * sum of |w_c| over clusters of s bonds and A their total,
+     *   E = (sum_s ((s + 1) u + s v) A_s) (1 + A)
+     * (a term of s bonds multiplies at most s + 1 slices), reported as
+     * E / |1 + S| for a closed network (an estimate of |delta ln|Z||) and
+     * E / max|Out| for an open one (relative entry error).  It assumes no
+     * cancellation inside a cluster's own index sum. */
+    double term_err_est;
 } pne_result;
 
 typedef struct pne_ctx pne_ctx;
@@ -128,7 +171,8 @@ typedef struct pne_network pne_network;
 typedef struct pne_batch pne_batch;
 typedef struct pne_server pne_server;
 
-/* Fill *opt with defaults: K=4, FP64, tol 1e-13, 500 sweeps. */
+/* Fill *opt with defaults: K=4, FP64, tol 1e-13, 500 sweeps, LOOP mode, no
+ * damping, err_bound 1e-5. */
 pne_status pne_options_default(pne_options *opt);
 
 /* Create a context on HIP device `device`.  mem_budget_bytes bounds the
@@ -229,10 +273,10 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
 /* Host only (no device needed): the number of retained clusters and of
  * retained configurations (collections of vertex-disjoint clusters, the
  * empty one excluded) the library would evaluate for this geometry at degree
- * cap K, with the given partitions (n_partitions == 0: none; same rules as
- * pne_network_set_partitions).  The counts equal pne_result's
- * n_cluster_terms and n_config_terms. */
-pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t n_partitions,
+ * cap K in the given pne_mode, with the given partitions (n_partitions == 0:
+ * none; same rules as pne_network_set_partitions; PNE_MODE_FULL takes none).
+ * The counts equal pne_result's n_cluster_terms and n_config_terms. */
+pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t mode, int32_t n_partitions,
                                     const int32_t *part_begin, const int32_t *part_bond, int64_t *n_clusters,
                                     int64_t *n_configs);
 

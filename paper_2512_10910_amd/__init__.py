@@ -23,4 +23,8 @@ from .pne import (  # noqa: F401
     PATH_BLOCK_TERMS,
     PATH_PERSISTENT,
     PRECISIONS,
+    MODES,
+    PNE_OK,
+    PNE_WARN_BP_NOT_CONVERGED,
+    PNE_WARN_PRECISION,
 )

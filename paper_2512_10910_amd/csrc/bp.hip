@@ -108,7 +108,7 @@ constexpr int kFusedTileSites = 16;  // largest register tile inside the fused k
 template <int DC>
 __device__ void sweep_tile(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
                            const double *__restrict__ min, double *__restrict__ mout, NetState *ns, int sweep,
-                           double *lds, TileShared &sh) {
+                           double *lds, TileShared &sh, double damp) {
     const double **s_t = sh.t;
     int *s_msg = sh.msg;
     int *s_dst = sh.dst;
@@ -258,10 +258,26 @@ __device__ void sweep_tile(const BpTile &tl, const SiteRec *__restrict__ sites, 
             continue;
         }
         const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
+        double dinv = 1.0;  // damped: the mix is normalised and sign-fixed again
+        if (damp > 0.0) {
+            double m2 = 0.0, msum = 0.0;
+            for (int k = 0; k < d; ++k) {
+                const double x = (1.0 - damp) * (raw[k] * inv) + damp * old[k];
+                m2 = fma(x, x, m2);
+                msum += x;
+            }
+            const double mn = sqrt(m2);
+            if (!(mn > 0.0) || !isfinite(mn)) {
+                s_bad = 1;
+                continue;
+            }
+            dinv = (msum < 0.0 ? -1.0 : 1.0) / mn;
+        }
         const int dst = s_dst[j * kMaxRank + l];
         double d1 = 0.0, d2 = 0.0;
         for (int k = 0; k < d; ++k) {
-            const double v = raw[k] * inv;
+            double v = raw[k] * inv;
+            if (damp > 0.0) v = ((1.0 - damp) * v + damp * old[k]) * dinv;
             d1 = fmax(d1, fabs(v - old[k]));
             d2 = fmax(d2, fabs(v + old[k]));
             mout[dst + k] = v;
@@ -324,7 +340,8 @@ __device__ inline void tile_sync() {
 // tile's residual (valid in every lane); sets *bad on a zero message.
 template <int D, int R, bool WAVE, class SH, int ROWS = 0>
 __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
-                            const double *min, double *mout, int msg_base, double *lds, SH &sh, int *bad) {
+                            const double *min, double *mout, int msg_base, double *lds, SH &sh, int *bad,
+                            double damp) {
     constexpr int P = RegShape<D>::P;
     constexpr int B = RegShape<D>::B;
     constexpr int T = reg_trailing(D, R);
@@ -472,11 +489,28 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
             continue;
         }
         const double inv = (sum < 0.0 ? -1.0 : 1.0) / nrm;  // L2 norm, sign fixed so the sum is >= 0
+        double dinv = 1.0;  // damped: the mix is normalised and sign-fixed again
+        if (damp > 0.0) {
+            double m2 = 0.0, msum = 0.0;
+#pragma unroll
+            for (int k = 0; k < D; ++k) {
+                const double x = (1.0 - damp) * (raw[k] * inv) + damp * oldv[k];
+                m2 = fma(x, x, m2);
+                msum += x;
+            }
+            const double mn = sqrt(m2);
+            if (!(mn > 0.0) || !isfinite(mn)) {
+                *bad = 1;
+                continue;
+            }
+            dinv = (msum < 0.0 ? -1.0 : 1.0) / mn;
+        }
         const int dst = sh.dst[j * kMaxRank + l];
         double d1 = 0.0, d2 = 0.0;
 #pragma unroll
         for (int k = 0; k < D; ++k) {
-            const double v = raw[k] * inv;
+            double v = raw[k] * inv;
+            if (damp > 0.0) v = ((1.0 - damp) * v + damp * oldv[k]) * dinv;
             d1 = fmax(d1, fabs(v - oldv[k]));
             d2 = fmax(d2, fabs(v + oldv[k]));
             mout[dst + k] = v;
@@ -515,7 +549,7 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
                                                          const BpTile *__restrict__ tiles,
                                                          const int *__restrict__ tile_sites,
                                                          double *msg0, double *msg1, NetState *st, int sweep,
-                                                         double tol, int max_iter) {
+                                                         double tol, int max_iter, double damp) {
     const BpTile tl = tiles[blockIdx.x];
     NetState *ns = st + tl.net;
     extern __shared__ double lds[];
@@ -534,9 +568,9 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
         if (threadIdx.x == 0) sh.bad = 0;
         double res = 0.0;
         switch (tl.dc * 8 + tl.rank) {
-            case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
+            case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
             default: sh.bad = 1; break;  // not a wide shape: never scheduled here
         }
         if (threadIdx.x == 0) {
@@ -549,28 +583,28 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
         double res = -1.0;
         if (threadIdx.x == 0) sh.bad = 0;
         switch (tl.dc * 8 + tl.rank) {
-            case 17: res = sweep_reg<2, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 18: res = sweep_reg<2, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 19: res = sweep_reg<2, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 20: res = sweep_reg<2, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 21: res = sweep_reg<2, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 22: res = sweep_reg<2, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 25: res = sweep_reg<3, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 26: res = sweep_reg<3, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 27: res = sweep_reg<3, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 28: res = sweep_reg<3, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 29: res = sweep_reg<3, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 33: res = sweep_reg<4, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 34: res = sweep_reg<4, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 35: res = sweep_reg<4, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 36: res = sweep_reg<4, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 37: res = sweep_reg<4, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 41: res = sweep_reg<5, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 42: res = sweep_reg<5, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 43: res = sweep_reg<5, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 49: res = sweep_reg<6, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 50: res = sweep_reg<6, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
-            case 51: res = sweep_reg<6, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad); break;
+            case 17: res = sweep_reg<2, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 18: res = sweep_reg<2, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 19: res = sweep_reg<2, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 20: res = sweep_reg<2, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 21: res = sweep_reg<2, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 22: res = sweep_reg<2, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 25: res = sweep_reg<3, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 26: res = sweep_reg<3, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 27: res = sweep_reg<3, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 28: res = sweep_reg<3, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 29: res = sweep_reg<3, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 33: res = sweep_reg<4, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 34: res = sweep_reg<4, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 35: res = sweep_reg<4, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 36: res = sweep_reg<4, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 37: res = sweep_reg<4, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 41: res = sweep_reg<5, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 42: res = sweep_reg<5, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 43: res = sweep_reg<5, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 49: res = sweep_reg<6, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 50: res = sweep_reg<6, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 51: res = sweep_reg<6, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
             default: break;
         }
         if (res >= 0.0) {
@@ -582,12 +616,12 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
         }
     }
     switch (tl.dc) {
-        case 2: sweep_tile<2>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
-        case 3: sweep_tile<3>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
-        case 4: sweep_tile<4>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
-        case 5: sweep_tile<5>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
-        case 6: sweep_tile<6>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
-        default: sweep_tile<0>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh); break;
+        case 2: sweep_tile<2>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
+        case 3: sweep_tile<3>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
+        case 4: sweep_tile<4>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
+        case 5: sweep_tile<5>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
+        case 6: sweep_tile<6>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
+        default: sweep_tile<0>(tl, sites, tile_sites, min, mout, ns, sweep, lds, sh, damp); break;
     }
 }
 
@@ -632,11 +666,11 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s) {
     if (b.n_narrow_tiles > 0)
         hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites,
-                           b.tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter);
+                           b.tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.damping);
     if (b.n_tiles > b.n_narrow_tiles)
         hipLaunchKernelGGL(k_bp_sweep<true>, dim3(b.n_tiles - b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s,
                            b.sites, b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol,
-                           max_iter);
+                           max_iter, b.damping);
     return hipGetLastError();
 }
 

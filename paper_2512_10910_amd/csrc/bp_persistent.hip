@@ -912,8 +912,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
                   classes, slices, w);
     __syncthreads();
     const CombineRec cr = crecs[fn.net];
-    dev::combine_closed<NT>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
-                                   s_status, results, p_lds + L.scr);
+    dev::combine_closed<NT, S>(fn.net, cr, geos[cr.geo], buckets, pair_a, pair_b, cats, w, site_log, site_sign,
+                               sites, slices, s_status, results, p_lds + L.scr);
 }
 
 }  // namespace

@@ -221,7 +221,7 @@ struct Enum {
     int root = 0;
     ClusterList *out;
 
-    Enum(const Geometry &g_, int K_, ClusterList *o) : g(g_), K(K_), out(o) {
+    Enum(const Geometry &g_, int K_, ClusterList *o, bool full) : g(g_), K(K_), out(o) {
         inc_ptr.assign(g.n_sites + 1, 0);
         for (int b = 0; b < g.n_bonds; ++b) {
             inc_ptr[g.bu[b] + 1]++;
@@ -234,7 +234,9 @@ struct Enum {
             inc[fill[g.bu[b]]++] = b;
             inc[fill[g.bv[b]]++] = b;
         }
-        exempt.assign(g.n_sites, 0);
+        // the dangling rule exempts sites with open legs, and every site when
+        // the complete expansion is wanted
+        exempt.assign(g.n_sites, full ? 1 : 0);
         for (int s : g.open_site) exempt[s] = 1;
         deg.assign(g.n_sites, 0);
         seen.assign(g.n_bonds, 0);
@@ -322,11 +324,11 @@ struct Enum {
 
 }  // namespace
 
-void enumerate_clusters(const Geometry &g, int K, ClusterList *out) {
+void enumerate_clusters(const Geometry &g, int K, ClusterList *out, bool full) {
     out->off.assign(1, 0);
     out->bonds.clear();
     if (K <= 0 || g.n_bonds == 0) return;
-    Enum e(g, K, out);
+    Enum e(g, K, out, full);
     e.run();
 }
 
@@ -619,9 +621,19 @@ bool build_steps(const LocalCluster &lc, const std::vector<int> &order, std::vec
 
 }  // namespace
 
-std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) {
+std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err, bool full) {
     auto plan = std::make_shared<GeoPlan>();
     plan->K = K;
+    if (full) {
+        if (g.n_open > 0 || g.n_parts() > 0) {
+            *err = "unsupported: the complete-expansion mode takes closed networks without partitions";
+            return nullptr;
+        }
+        if (g.n_bonds > kMaxFullBonds) {
+            *err = "unsupported: the complete-expansion mode takes at most 20 bonds";
+            return nullptr;
+        }
+    }
     if ((int)g.open_sites.size() > 2) {
         *err = "unsupported: more than two sites carry open legs";
         return nullptr;
@@ -656,7 +668,7 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
     }
 
     ClusterList raw;
-    enumerate_clusters(g, K, &raw);
+    enumerate_clusters(g, K, &raw, full);
     int nc = raw.count();
 
     // type and size, then order clusters by (type, size, discovery)
@@ -763,7 +775,7 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
         }
     }
 
-    if (g.n_parts() > 0) {
+    if (g.n_parts() > 0 || full) {
         // User partitions (Eqs. (4) / (7) with factorised multi-index projectors,
         // Eqs. (9) / (11)).  Dropping the residue removes exactly the
         // configurations that excite at least one bond of every partition
@@ -771,15 +783,17 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
         // of p excited, Eq. (10)), so the retained configurations are the
         // vertex-disjoint cluster sets of degree <= K whose excited bonds miss
         // some partition.  They are listed one by one.
+        // The complete-expansion mode lists every configuration of degree <= K
+        // the same way, as its connected components, with no partition to miss.
         plan->listed = true;
         const int np = g.n_parts();
-        const uint32_t full = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
+        const uint32_t all_parts = np == 32 ? 0xffffffffu : ((1u << np) - 1u);
         plan->cmask.assign(nc, 0u);
         std::vector<std::vector<int>> vs(nc);
         for (int c = 0; c < nc; ++c) {
             std::set<int> s2;
             for (int p = cl.off[c]; p < cl.off[c + 1]; ++p) {
-                plan->cmask[c] |= g.bond_parts[cl.bonds[p]];
+                if (np > 0) plan->cmask[c] |= g.bond_parts[cl.bonds[p]];
                 s2.insert(g.bu[cl.bonds[p]]);
                 s2.insert(g.bv[cl.bonds[p]]);
             }
@@ -805,7 +819,7 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
                 for (int q = cl.off[c]; q < cl.off[c + 1]; ++q) csub[e][c] |= bmask[cl.bonds[q]];
         }
         auto coefficient = [&](uint32_t mask, const std::vector<uint32_t> &smask) {
-            const uint32_t comp = full & ~mask;
+            const uint32_t comp = all_parts & ~mask;
             int64_t coef = 0;
             for (uint32_t x = comp; x != 0; x = (x - 1) & comp) {
                 int keep = 1;
@@ -831,7 +845,7 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err) 
                     for (int v : vs[c]) free = free && !used[v];
                     if (!free) continue;
                     const uint32_t m = mask | plan->cmask[c];
-                    if (m == full) continue;  // no term keeps it, nor any superset
+                    if (np > 0 && m == all_parts) continue;  // no term keeps it, nor any superset
                     for (int e = 0; e < ns; ++e) sm[e] = smask[e] | csub[e][c];
                     chosen.push_back(c);
                     for (int v : vs[c]) used[v] = 1;

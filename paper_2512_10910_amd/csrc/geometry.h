@@ -64,8 +64,9 @@ struct ClusterList {
 };
 
 // Every connected bond set of size <= K whose sites all have degree >= 2
-// inside the set (sites with open legs: >= 1).  Bonds of a cluster ascending.
-void enumerate_clusters(const Geometry &g, int K, ClusterList *out);
+// inside the set (sites with open legs: >= 1); with full, every connected
+// bond set of size <= K.  Bonds of a cluster ascending.
+void enumerate_clusters(const Geometry &g, int K, ClusterList *out, bool full = false);
 
 struct GeoPlan {
     int K = 0;
@@ -104,8 +105,14 @@ struct GeoPlan {
     size_t max_f = 1;
 };
 
+// Largest network the complete-expansion mode lists (2^20 - 1 configurations).
+constexpr int kMaxFullBonds = 20;
+
 // Build the plan; returns nullptr and sets *err (prefixed "unsupported:" when
-// the geometry is valid but outside the implemented envelope).
-std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err);
+// the geometry is valid but outside the implemented envelope).  full: every
+// configuration of degree <= K, dangling ones included, each listed as its
+// vertex-disjoint connected components (closed networks without partitions,
+// at most kMaxFullBonds bonds).
+std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err, bool full = false);
 
 }  // namespace pne

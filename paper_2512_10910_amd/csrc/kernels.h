@@ -38,6 +38,7 @@ struct DeviceBatch {
     double *msg0 = nullptr, *msg1 = nullptr;
     void *slices = nullptr;
     int precision = 0;
+    double damping = 0.0;          // BP damping of the per-launch sweeps
     double *site_log = nullptr;
     int *site_sign = nullptr;
     double *vac = nullptr;

@@ -339,6 +339,7 @@ __device__ double block_sum(double v, double *red) {
 // the overlaps being the explicitly listed pairs of clusters that share a
 // site.  Open networks combine vacuum vectors and open-cluster tensors the
 // same way, one tensor product per configuration.
+template <typename S>
 __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ combine_nets,
                                                         const CombineRec *__restrict__ recs,
                                                         const GeoRec *__restrict__ geos,
@@ -352,7 +353,9 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                                                         const double *__restrict__ site_log,
                                                         const int *__restrict__ site_sign, const double *__restrict__ vac,
                                                         const NetState *__restrict__ st, NetResult *__restrict__ out,
-                                                        double *__restrict__ open_out) {
+                                                        double *__restrict__ open_out,
+                                                        const SiteRec *__restrict__ sites,
+                                                        const S *__restrict__ slices) {
     const int net = combine_nets[blockIdx.x];
     const CombineRec cr = recs[net];
     const GeoRec gr = geos[cr.geo];
@@ -371,6 +374,8 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
     }
     lg = block_sum(lg, red);
     neg = block_sum(neg, red);
+    double dangling, err;
+    net_diagnostics<kCbThreads, S>(cr, gr, buckets, sites, slices, wn, red, &dangling, &err);
 
     if (gr.listed) {
         // User partitions (closed networks): every retained configuration is
@@ -394,8 +399,10 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
         res.status = st[net].status;
         res.log_bp = lg;
         res.sum = v;
+        res.dangling = dangling;
         const int sign_bp = ((int)neg & 1) ? -1 : 1;
         const double tot = 1.0 + v;
+        res.err_est = err / fabs(tot);
         res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
         res.log_abs = lg + log(fabs(tot));
         out[net] = res;
@@ -499,10 +506,12 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
     }
     SC -= psum[0][0];
     res.sum = SC;
+    res.dangling = dangling;
     if (cr.vac_a < 0) {
         const double tot = 1.0 + SC;
         res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
         res.log_abs = lg + log(fabs(tot));
+        res.err_est = err / fabs(tot);
     } else {
         // Wc(<= budget) helper: sum of closed bucket sums with size <= budget
         auto wc_upto = [&](int budget) {
@@ -517,6 +526,7 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
         for (int i = 0; i < pa; ++i) xa[i] = vac[cr.vac_a + i];
         for (int j = 0; j < pb; ++j) xb[j] = cr.vac_b >= 0 ? vac[cr.vac_b + j] : 1.0;
         double VA[kMaxOpenOut], VB[kMaxOpenOut];
+        double omax = 0.0;
         for (int i = 0; i < pa; ++i) {
             double v = 0.0;
             for (int s = 1; s <= K; ++s) {
@@ -552,9 +562,11 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
                 }
                 v -= psum[4][e];
                 open_out[cr.open_off + e] = sign_bp * v;
+                omax = fmax(omax, fabs(v));
             }
         res.sign = sign_bp;
         res.log_abs = lg;
+        res.err_est = omax > 0.0 ? err / omax : err;
     }
     out[net] = res;
 }
@@ -611,12 +623,20 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename S>
+static void launch_combine_t(const DeviceBatch &b, hipStream_t s) {
+    hipLaunchKernelGGL(k_combine<S>, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
+                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.coll_off, b.coll_cl, b.coll_coef, b.w, b.site_log,
+                       b.site_sign, b.vac, b.state, b.results, b.open_out, b.sites, (const S *)b.slices);
+}
+
 hipError_t launch_combine(const DeviceBatch &b, hipStream_t s) {
     if (!b.n_combine) return hipSuccess;
-    hipLaunchKernelGGL(k_combine, dim3(b.n_combine), dim3(kCbThreads), 0, s, b.combine_nets, b.crec, b.geos,
-                       b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.coll_off, b.coll_cl, b.coll_coef, b.w, b.site_log,
-                       b.site_sign, b.vac, b.state,
-                       b.results, b.open_out);
+    switch (b.precision) {
+        case 0: launch_combine_t<double>(b, s); break;
+        case 1: launch_combine_t<float>(b, s); break;
+        default: launch_combine_t<uint16_t>(b, s); break;
+    }
     return hipGetLastError();
 }
 

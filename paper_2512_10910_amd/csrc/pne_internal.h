@@ -178,6 +178,8 @@ struct NetResult {
     double log_abs;
     double log_bp;
     double sum;            // closed networks: the retained-term sum S (Z = Z_BP (1+S))
+    double dangling;       // largest excited norm of a single-leg slice (0 at a BP fixed point)
+    double err_est;        // first-order estimate of the term precision's error (see pne_result)
     int32_t sign;
     int32_t status;
 };  // an open network's output tensor goes to the batch's open-output buffer

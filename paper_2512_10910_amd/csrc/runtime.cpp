@@ -5,6 +5,8 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -21,7 +23,7 @@ using namespace pne;
 
 struct PlanEntry {
     std::shared_ptr<Geometry> geo;
-    std::map<int, std::shared_ptr<GeoPlan>> plans;  // by K
+    std::map<int, std::shared_ptr<GeoPlan>> plans;  // by K, with bit 8 set for the complete-expansion mode
 };
 
 // Device instance tables of one plan, built and uploaded once per context:
@@ -81,6 +83,11 @@ struct pne_batch {
     std::vector<int> site_base;                   // per net
     std::vector<int64_t> w_base;                  // per net
     std::vector<void *> allocs;
+    // Fixed device region (the allocation-free entry point): tables and
+    // buffers are placed there, results go to pageable host memory and
+    // completion is a stream synchronisation (no events, one launch at a time).
+    bool fixed = false;
+    std::vector<char> h_host;
     size_t bytes = 0;
     DeviceBatch db;
     // Two pinned result slots: a batch may have two launches outstanding;
@@ -143,8 +150,8 @@ pne_status hip_fail(pne_ctx *ctx, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
-std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> &g, int K, std::string *err,
-                                  std::shared_ptr<Geometry> *canon) {
+std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> &g, int K, bool full,
+                                  std::string *err, std::shared_ptr<Geometry> *canon) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto range = ctx->cache.equal_range(g->hash);
     PlanEntry *pe = nullptr;
@@ -158,22 +165,27 @@ std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> 
         pe = &it->second;
     }
     if (canon) *canon = pe->geo;
-    auto f = pe->plans.find(K);
+    const int key = K | (full ? 1 << 8 : 0);  // K <= 32
+    auto f = pe->plans.find(key);
     if (f != pe->plans.end()) return f->second;
-    auto p = build_plan(*pe->geo, K, err);
-    if (p) pe->plans[K] = p;
+    auto p = build_plan(*pe->geo, K, err, full);
+    if (p) pe->plans[key] = p;
     return p;
 }
 
 size_t align256(size_t x);
 
-// The plan's device instance tables (see PlanTables), built on its first use
-// with g its geometry; the upload is complete on return.
-// nullptr (with *st set) when the device memory cannot be had.
-const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g, pne_status *st) {
-    std::lock_guard<std::mutex> lk(ctx->mu);
-    auto it = ctx->plan_tables.find(p);
-    if (it != ctx->plan_tables.end()) return &it->second;
+// Host contents of a plan's instance tables (see PlanTables): the records of
+// every class instance, instance-major per class, and every instance's
+// weight offset; tab_off / iw_off give each class's first entry.
+struct PlanTablesHost {
+    std::vector<InstStep> tab;
+    std::vector<int32_t> iw;
+    std::vector<size_t> tab_off, iw_off;
+    PlanTables pt;  // per-class counts and kinds (device pointers unset)
+};
+
+void plan_tables_host(const GeoPlan *p, const Geometry &g, PlanTablesHost *h) {
     std::vector<int64_t> soff(g.n_sites + 1, 0);
     for (int s2 = 0; s2 < g.n_sites; ++s2) {
         int64_t sz = 1;
@@ -186,10 +198,12 @@ const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g,
         return st2;
     };
     const int ncls = (int)p->classes.size();
-    std::vector<InstStep> tab;
-    std::vector<int32_t> iw;
-    std::vector<size_t> tab_off(ncls), iw_off(ncls);
-    PlanTables pt;
+    std::vector<InstStep> &tab = h->tab;
+    std::vector<int32_t> &iw = h->iw;
+    std::vector<size_t> &tab_off = h->tab_off, &iw_off = h->iw_off;
+    tab_off.assign(ncls, 0);
+    iw_off.assign(ncls, 0);
+    PlanTables &pt = h->pt;
     pt.cls.resize(ncls);
     for (int c = 0; c < ncls; ++c) {
         const ClassDesc &cd = p->classes[c];
@@ -237,6 +251,21 @@ const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g,
             }
         }
     }
+}
+
+// The plan's device instance tables (see PlanTables), built on its first use
+// with g its geometry; the upload is complete on return.
+// nullptr (with *st set) when the device memory cannot be had.
+const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g, pne_status *st) {
+    std::lock_guard<std::mutex> lk(ctx->mu);
+    auto it = ctx->plan_tables.find(p);
+    if (it != ctx->plan_tables.end()) return &it->second;
+    PlanTablesHost h;
+    plan_tables_host(p, g, &h);
+    const std::vector<InstStep> &tab = h.tab;
+    const std::vector<int32_t> &iw = h.iw;
+    PlanTables pt = h.pt;
+    const int ncls = (int)p->classes.size();
     const size_t tab_bytes = align256(std::max<size_t>(1, tab.size()) * sizeof(InstStep));
     pt.bytes = tab_bytes + align256(std::max<size_t>(1, iw.size()) * sizeof(int32_t));
     if (ctx->budget && ctx->used + pt.bytes > ctx->budget) {
@@ -260,8 +289,8 @@ const PlanTables *plan_tables(pne_ctx *ctx, const GeoPlan *p, const Geometry &g,
         return nullptr;
     }
     for (int c = 0; c < ncls; ++c) {
-        pt.cls[c].tab = (const InstStep *)pt.dev + tab_off[c];
-        pt.cls[c].iw = (const int32_t *)((const char *)pt.dev + tab_bytes) + iw_off[c];
+        pt.cls[c].tab = (const InstStep *)pt.dev + h.tab_off[c];
+        pt.cls[c].iw = (const int32_t *)((const char *)pt.dev + tab_bytes) + h.iw_off[c];
     }
     ctx->used += pt.bytes;
     return &ctx->plan_tables.emplace(p, std::move(pt)).first->second;
@@ -294,7 +323,11 @@ struct ArenaPlan {
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
+// Lay the pieces out, place them (a new allocation, or the batch's fixed
+// region when `fixed` is set), let `fixup` patch host contents that hold
+// device addresses of other pieces, then upload the host contents.
+pne_status commit_arena(pne_batch *b, ArenaPlan &ap, const StaticArena *fixed,
+                        const std::function<void()> &fixup) {
     pne_ctx *ctx = b->ctx;
     size_t off = 0;
     for (auto &pc : ap.up) {
@@ -307,37 +340,55 @@ pne_status commit_arena(pne_batch *b, ArenaPlan &ap) {
         off += align256(pc.bytes);
     }
     const size_t total = off;
-    if (ctx->budget && ctx->used + total > ctx->budget) return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
     void *p = nullptr;
-    if (hipMalloc(&p, total) != hipSuccess) return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
-    b->allocs.push_back(p);
-    b->bytes += total;
-    ctx->used += total;
-    if (up_bytes) {
-        if (ctx->up_pending) {  // the previous upload still reads the staging buffer
-            hipError_t e = hipEventSynchronize(ctx->up_done);
-            if (e != hipSuccess) return hip_fail(ctx, e, "upload wait");
-            ctx->up_pending = false;
-        }
-        if (ctx->staging_bytes < up_bytes) {
-            if (ctx->staging) (void)hipHostFree(ctx->staging);
-            ctx->staging = nullptr;
-            ctx->staging_bytes = 0;
-            const size_t want = std::max(up_bytes + up_bytes / 2, (size_t)1 << 20);
-            if (hipHostMalloc(&ctx->staging, want, hipHostMallocDefault) != hipSuccess)
-                return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
-            ctx->staging_bytes = want;
-        }
-        char *st = (char *)ctx->staging;
-        for (auto &pc : ap.up) std::memcpy(st + pc.off, pc.src, pc.bytes);
-        hipError_t e = hipMemcpyAsync(p, st, up_bytes, hipMemcpyHostToDevice, ctx->up_stream);
-        if (e == hipSuccess) e = hipEventRecord(ctx->up_done, ctx->up_stream);
-        if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ctx->up_done, 0);
-        if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
-        ctx->up_pending = true;
+    if (fixed) {
+        if (total > fixed->cap)
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "batch needs " + std::to_string(total) +
+                                                        " bytes, more than the fixed scratch region holds (" +
+                                                        std::to_string(fixed->cap) + ")");
+        p = fixed->base;
+    } else {
+        if (ctx->budget && ctx->used + total > ctx->budget)
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "memory budget exceeded");
+        if (hipMalloc(&p, total) != hipSuccess) return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "device allocation failed");
+        b->allocs.push_back(p);
+        b->bytes += total;
+        ctx->used += total;
     }
     for (auto &pc : ap.up) *pc.dst = (char *)p + pc.off;
     for (auto &pc : ap.buf) *pc.dst = (char *)p + pc.off;
+    if (fixup) fixup();
+    if (!up_bytes) return PNE_OK;
+    if (fixed) {
+        // pageable staging on the batch stream, complete before returning
+        std::vector<char> st(up_bytes);
+        for (auto &pc : ap.up) std::memcpy(st.data() + pc.off, pc.src, pc.bytes);
+        hipError_t e = hipMemcpyAsync(p, st.data(), up_bytes, hipMemcpyHostToDevice, b->stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+        if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
+        return PNE_OK;
+    }
+    if (ctx->up_pending) {  // the previous upload still reads the staging buffer
+        hipError_t e = hipEventSynchronize(ctx->up_done);
+        if (e != hipSuccess) return hip_fail(ctx, e, "upload wait");
+        ctx->up_pending = false;
+    }
+    if (ctx->staging_bytes < up_bytes) {
+        if (ctx->staging) (void)hipHostFree(ctx->staging);
+        ctx->staging = nullptr;
+        ctx->staging_bytes = 0;
+        const size_t want = std::max(up_bytes + up_bytes / 2, (size_t)1 << 20);
+        if (hipHostMalloc(&ctx->staging, want, hipHostMallocDefault) != hipSuccess)
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+        ctx->staging_bytes = want;
+    }
+    char *st = (char *)ctx->staging;
+    for (auto &pc : ap.up) std::memcpy(st + pc.off, pc.src, pc.bytes);
+    hipError_t e = hipMemcpyAsync(p, st, up_bytes, hipMemcpyHostToDevice, ctx->up_stream);
+    if (e == hipSuccess) e = hipEventRecord(ctx->up_done, ctx->up_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(b->stream, ctx->up_done, 0);
+    if (e != hipSuccess) return hip_fail(ctx, e, "table upload");
+    ctx->up_pending = true;
     return PNE_OK;
 }
 
@@ -475,6 +526,9 @@ pne_status pne_options_default(pne_options *opt) {
     opt->bp_tol = 1e-13;
     opt->bp_max_iter = 500;
     opt->bp_check_every = 0;
+    opt->mode = PNE_MODE_LOOP;
+    opt->bp_damping = 0.0;
+    opt->err_bound = 1e-5;
     return PNE_OK;
 }
 
@@ -671,7 +725,8 @@ pne_status pne_batch_create(pne_ctx *ctx, pne_network *const *nets, int32_t n, c
 }
 
 // Signature of a batch for the tuning cache: the multiset of network
-// geometries, K, the precision and the flags that change results.
+// geometries, K, the precision, the mode, the damping and the flags that
+// change results.
 static uint64_t batch_signature(pne_network *const *nets, int32_t n, const pne_options *opt) {
     std::vector<uint64_t> h(n);
     for (int i = 0; i < n; ++i) h[i] = nets[i]->geo->hash;
@@ -684,6 +739,10 @@ static uint64_t batch_signature(pne_network *const *nets, int32_t n, const pne_o
     mix((uint64_t)opt->max_excited);
     mix((uint64_t)opt->precision);
     mix((uint64_t)(opt->flags & (PNE_FLAG_NO_PERSISTENT | PNE_FLAG_BP_JACOBI)));
+    mix((uint64_t)opt->mode);
+    uint64_t damp_bits;
+    std::memcpy(&damp_bits, &opt->bp_damping, sizeof damp_bits);
+    mix(damp_bits);
     return x;
 }
 
@@ -731,18 +790,25 @@ pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const
 }  // extern "C"
 
 pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
-                                hipStream_t stream, pne_batch **out) {
+                                hipStream_t stream, pne_batch **out, const StaticArena *fixed) {
     if (!ctx || !nets || n <= 0 || !opt || !out) return fail(ctx, PNE_ERR_INVALID_ARG, "bad batch arguments");
     *out = nullptr;
     if (opt->max_excited < 0 || opt->max_excited > 32) return fail(ctx, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
     if (opt->precision < 0 || opt->precision > 2) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown precision");
     if (!(opt->bp_tol >= 0.0) || opt->bp_max_iter < 1) return fail(ctx, PNE_ERR_INVALID_ARG, "bad BP options");
+    if (opt->mode != PNE_MODE_LOOP && opt->mode != PNE_MODE_FULL) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown mode");
+    if (!(opt->bp_damping >= 0.0 && opt->bp_damping < 1.0))
+        return fail(ctx, PNE_ERR_INVALID_ARG, "bp_damping must be in [0, 1)");
+    if (!(opt->err_bound >= 0.0)) return fail(ctx, PNE_ERR_INVALID_ARG, "err_bound must be >= 0");
+    if (fixed && (opt->flags & (PNE_FLAG_PROFILE | PNE_FLAG_GRAPH | PNE_FLAG_AUTOTUNE)))
+        return fail(ctx, PNE_ERR_INVALID_ARG, "profiling, graph replay and autotuning allocate: not available here");
     for (int i = 0; i < n; ++i)
         if (!nets[i] || nets[i]->ctx != ctx) return fail(ctx, PNE_ERR_INVALID_ARG, "network from another context");
 
     auto b = std::make_unique<pne_batch>();
     b->ctx = ctx;
     b->stream = stream;
+    b->fixed = fixed != nullptr;
     b->nets.assign(nets, nets + n);
     b->opt = *opt;
     const int K = opt->max_excited;
@@ -753,7 +819,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     for (int i = 0; i < n; ++i) {
         std::string err;
         std::shared_ptr<Geometry> canon;
-        auto p = get_plan(ctx, nets[i]->geo, K, &err, &canon);
+        auto p = get_plan(ctx, nets[i]->geo, K, opt->mode == PNE_MODE_FULL, &err, &canon);
         if (!p) {
             bool unsup = err.rfind("unsupported", 0) == 0;
             return fail(ctx, unsup ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
@@ -957,7 +1023,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         else
             rg_inline = false;
         const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2);
-        if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT)) {
+        // damped BP runs launch by launch (Jacobi, the damped mix in the per-launch normalisation)
+        if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT) && opt->bp_damping == 0.0) {
             FusedNet f;
             std::memset(&f, 0, sizeof f);
             f.net = i;
@@ -1088,6 +1155,14 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     // consecutive (network, instance) pairs of one class.
     std::vector<char> net_cl_fused(n, 0);
     const bool cl_separate = (opt->flags & PNE_FLAG_SEPARATE_REGAUGE) != 0;
+    // fixed region: per plan, the host instance tables and their device addresses
+    struct FixedPlanTables {
+        PlanTablesHost h;
+        int class_begin = 0;
+        const InstStep *tab_dev = nullptr;
+        const int32_t *iw_dev = nullptr;
+    };
+    std::deque<FixedPlanTables> fixed_tables;
     {
         std::map<const GeoPlan *, std::vector<int>> nets_of_plan;
         std::vector<const GeoPlan *> plan_order;
@@ -1102,7 +1177,18 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             const int c0 = plan_index[p];
             const int ncls = (int)p->classes.size();
             pne_status pst = PNE_OK;
-            const PlanTables *pt = plan_tables(ctx, p, g, &pst);
+            const PlanTables *pt = nullptr;
+            if (fixed) {
+                // the instance tables go into the batch's own region (uploaded
+                // with the other tables; class pointers patched at commit)
+                fixed_tables.emplace_back();
+                FixedPlanTables &ft = fixed_tables.back();
+                plan_tables_host(p, g, &ft.h);
+                ft.class_begin = c0;
+                pt = &ft.h.pt;
+            } else {
+                pt = plan_tables(ctx, p, g, &pst);
+            }
             if (!pt) return pst;
             // A closed network whose BP, gauge and slices run in a persistent
             // block, and whose plan has only scalar and cycle classes, also
@@ -1266,6 +1352,10 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(coll_off, coll_off);
     UP(coll_cl, coll_cl);
     UP(coll_coef, coll_coef);
+    for (FixedPlanTables &ft : fixed_tables) {
+        ap.upload(ft.h.tab, &ft.tab_dev);
+        ap.upload(ft.h.iw, &ft.iw_dev);
+    }
 #undef UP
     db.n_sites = (int)sites.size();
     db.n_tiles = (int)loop_tiles.size();
@@ -1280,6 +1370,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.regauge_lds = regauge_lds;
     db.cluster_lds = cl_lds;
     db.precision = prec;
+    db.damping = opt->bp_damping;
 #define AL(bytes, field, type) ap.buffer((bytes), &db.field)
     AL(sizeof(NetState) * n, state, NetState *);
     AL(sizeof(double) * msg, msg0, double *);
@@ -1292,7 +1383,17 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     AL(sizeof(NetResult) * n, results, NetResult *);
     AL(sizeof(double) * std::max<int64_t>(b->open_total, 1), open_out, double *);
 #undef AL
-    st = commit_arena(b.get(), ap);
+    // classes of plans whose instance tables sit in the fixed region point at
+    // them once the region's layout is known (before the upload copies them)
+    auto fixup = [&]() {
+        for (FixedPlanTables &ft : fixed_tables)
+            for (size_t c = 0; c < ft.h.pt.cls.size(); ++c) {
+                ClassDesc &cd = classes[ft.class_begin + c];
+                cd.tab = ft.tab_dev ? ft.tab_dev + ft.h.tab_off[c] : nullptr;
+                cd.iw = ft.iw_dev ? ft.iw_dev + ft.h.iw_off[c] : nullptr;
+            }
+    };
+    st = commit_arena(b.get(), ap, fixed, fixup);
     if (st != PNE_OK) {
         free_batch(b.get());
         return st;
@@ -1301,14 +1402,22 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     const size_t st_bytes = align256(sizeof(NetState) * n);
     const size_t res_bytes = align256(sizeof(NetResult) * n);
     const size_t slot_bytes = st_bytes + res_bytes + align256(sizeof(double) * std::max<int64_t>(b->open_total, 1));
-    if (hipHostMalloc(&b->h_pinned, 2 * slot_bytes, hipHostMallocDefault) != hipSuccess) {
-        free_batch(b.get());
-        return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+    char *slots = nullptr;
+    if (fixed) {
+        b->h_host.assign(2 * slot_bytes + 256, 0);  // pageable; copies complete at the stream synchronisation
+        slots = b->h_host.data() + (256 - (reinterpret_cast<uintptr_t>(b->h_host.data()) & 255)) % 256;
+    } else {
+        if (hipHostMalloc(&b->h_pinned, 2 * slot_bytes, hipHostMallocDefault) != hipSuccess) {
+            free_batch(b.get());
+            return fail(ctx, PNE_ERR_OUT_OF_MEMORY, "pinned allocation failed");
+        }
+        slots = (char *)b->h_pinned;
     }
     for (int k = 0; k < 2; ++k) {
-        b->h_state_slot[k] = (NetState *)((char *)b->h_pinned + k * slot_bytes);
-        b->h_results_slot[k] = (NetResult *)((char *)b->h_pinned + k * slot_bytes + st_bytes);
-        b->h_open_slot[k] = (double *)((char *)b->h_pinned + k * slot_bytes + st_bytes + res_bytes);
+        b->h_state_slot[k] = (NetState *)(slots + k * slot_bytes);
+        b->h_results_slot[k] = (NetResult *)(slots + k * slot_bytes + st_bytes);
+        b->h_open_slot[k] = (double *)(slots + k * slot_bytes + st_bytes + res_bytes);
+        if (fixed) continue;
         if (hipEventCreateWithFlags(&b->done_slot[k], hipEventDisableTiming) != hipSuccess) {
             free_batch(b.get());
             return fail(ctx, PNE_ERR_DEVICE, "event creation failed");
@@ -1330,7 +1439,8 @@ pne_status pne_batch_launch(pne_batch *b) {
     pne_ctx *ctx = b->ctx;
     hipStream_t s = b->stream;
     const DeviceBatch &db = b->db;
-    if (b->n_launched - b->n_waited >= 2) return fail(ctx, PNE_ERR_INVALID_ARG, "two launches already outstanding");
+    if (b->n_launched - b->n_waited >= (b->fixed ? 1 : 2))
+        return fail(ctx, PNE_ERR_INVALID_ARG, "too many launches outstanding");
     const int slot = (int)(b->n_launched & 1);
     if (b->state_slot == slot) ensure_state(b);  // this launch rewrites that slot
     b->h_state_pinned = b->h_state_slot[slot];
@@ -1401,7 +1511,7 @@ pne_status pne_batch_launch(pne_batch *b) {
     // results and state go to pinned memory in the same stream order, so the
     // host can enqueue further work (another batch) before waiting on this one
     HIP_TRY(ctx, enqueue_result_copies(b));
-    HIP_TRY(ctx, hipEventRecord(b->done_slot[slot], s));
+    if (b->done_slot[slot]) HIP_TRY(ctx, hipEventRecord(b->done_slot[slot], s));
     ++b->n_launched;
     b->launched = true;
     b->waited = false;
@@ -1414,7 +1524,10 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
     pne_ctx *ctx = b->ctx;
     const int n = (int)b->nets.size();
     const int slot = (int)(b->n_waited & 1);
-    HIP_TRY(ctx, hipEventSynchronize(b->done_slot[slot]));
+    if (b->done_slot[slot])
+        HIP_TRY(ctx, hipEventSynchronize(b->done_slot[slot]));
+    else
+        HIP_TRY(ctx, hipStreamSynchronize(b->stream));
     ++b->n_waited;
     b->h_state_pinned = b->h_state_slot[slot];
     b->h_results_pinned = b->h_results_slot[slot];
@@ -1438,8 +1551,15 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
         o.log_abs_bp = r.log_bp;
         o.sign = r.sign;
         o.n_open_values = 0;
+        o.dangling_max = r.dangling;
+        o.term_err_est = r.err_est;
         int st = s.status < 0 ? s.status : (s.converged ? PNE_OK : PNE_WARN_BP_NOT_CONVERGED);
         if (st >= 0 && !std::isfinite(r.log_abs)) st = PNE_ERR_SINGULAR;
+        if (st == PNE_OK && b->opt.precision != PNE_FP64) {
+            // closed: |delta ln|Z|| relative to max(1, |ln|Z||); open: relative entry error
+            const double rel = p.open_a >= 0 ? r.err_est : r.err_est / std::max(1.0, std::fabs(r.log_abs));
+            if (!(rel <= b->opt.err_bound)) st = PNE_WARN_PRECISION;
+        }
         if (st >= 0 && p.open_a >= 0) {
             int m = p.pa * p.pb;
             if (!ov || cap < m) {
@@ -1507,18 +1627,19 @@ pne_status pne_enumerate_clusters(const pne_network_desc *desc, int32_t K, int64
     return PNE_OK;
 }
 
-pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t n_partitions,
+pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int32_t mode, int32_t n_partitions,
                                     const int32_t *part_begin, const int32_t *part_bond, int64_t *n_clusters,
                                     int64_t *n_configs) {
     if (!desc || !n_clusters || !n_configs) return fail(nullptr, PNE_ERR_INVALID_ARG, "null argument");
     if (K < 0 || K > 32) return fail(nullptr, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
+    if (mode != PNE_MODE_LOOP && mode != PNE_MODE_FULL) return fail(nullptr, PNE_ERR_INVALID_ARG, "unknown mode");
     Geometry g;
     std::string why = build_geometry(desc, &g);
     if (why.empty()) why = set_partitions(&g, n_partitions, part_begin, part_bond);
     if (!why.empty())
         return fail(nullptr, why.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, why);
     std::string err;
-    auto p = build_plan(g, K, &err);
+    auto p = build_plan(g, K, &err, mode == PNE_MODE_FULL);
     if (!p) return fail(nullptr, err.rfind("unsupported", 0) == 0 ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
     *n_clusters = p->clusters.count();
     *n_configs = p->n_configs;

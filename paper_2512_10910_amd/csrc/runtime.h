@@ -14,8 +14,18 @@ namespace pne {
 
 pne_status network_create_on(pne_ctx *ctx, const pne_network_desc *desc, int on_device, hipStream_t stream,
                              pne_network **out);
+// A device region a batch places all its tables and buffers in instead of
+// allocating (the allocation-free entry point).
+struct StaticArena {
+    char *base = nullptr;
+    size_t cap = 0;
+};
+
+// fixed != nullptr: no device or pinned allocation, no events; the batch
+// allows one outstanding launch, and the flags PROFILE, GRAPH and AUTOTUNE
+// are refused.
 pne_status batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt,
-                           hipStream_t stream, pne_batch **out);
+                           hipStream_t stream, pne_batch **out, const StaticArena *fixed = nullptr);
 
 // Context access for the other entry points (strip expansions).
 hipStream_t ctx_stream(pne_ctx *ctx);

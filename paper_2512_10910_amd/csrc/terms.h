@@ -91,18 +91,94 @@ __device__ inline double block_sum_nt(double v, double *red) {
     return t;
 }
 
+// Largest of one value per thread over a block of NT threads.
+template <int NT>
+__device__ inline double block_max_nt(double v, double *red) {
+    const int tid = threadIdx.x;
+    for (int o = 32; o > 0; o >>= 1) v = fmax(v, __shfl_xor(v, o, 64));
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
+    __syncthreads();
+    double t = 0.0;
+    for (int k = 0; k < NT / 64; ++k) t = fmax(t, red[k]);
+    __syncthreads();
+    return t;
+}
+
+// Unit roundoff of the slice precision (RNE from FP64), and of the term
+// arithmetic (FP32 accumulation for FP32 and BF16 slices).
+template <typename S>
+__host__ __device__ constexpr double unit_roundoff() {
+    return sizeof(S) == 8 ? 0x1p-53 : (sizeof(S) == 4 ? 0x1p-24 : 0x1p-8);
+}
+template <typename S>
+__host__ __device__ constexpr double arith_roundoff() {
+    return sizeof(S) == 8 ? 0x1p-53 : 0x1p-24;
+}
+
+// Per-network diagnostics by a block of NT threads (results in every thread).
+//   dangling: over the network's sites without open legs and every leg l of
+//     dimension d >= 2, the 2-norm of the slice entries k * stride_l,
+//     k = 1..d-1 (every other leg at its vacuum index 0; the slice is the
+//     regauged tensor over z'_v).  These are the single-excitation terms the
+//     dangling rule drops (Sec. III.A-B); they vanish at a BP fixed point.
+//   err: (sum_s ((s + 1) u + s v) A_s) (1 + A), with A_s the sum of |w|
+//     over the clusters of s bonds (every entry of an open cluster's tensor)
+//     and A = sum_s A_s: a first-order estimate of the error that slices
+//     rounded to unit roundoff u (a term of s bonds multiplies at most s + 1
+//     slices) and term arithmetic of unit roundoff v put into the sum of the
+//     retained terms; the factor 1 + A covers the products of two clusters.
+template <int NT, typename S>
+__device__ inline void net_diagnostics(const CombineRec &cr, const GeoRec &gr, const Bucket *__restrict__ buckets,
+                                       const SiteRec *__restrict__ sites, const S *__restrict__ slices,
+                                       const double *__restrict__ wn, double *red, double *dangling, double *err) {
+    const int tid = threadIdx.x;
+    double dm = 0.0;
+    for (int s = tid; s < cr.n_sites; s += NT) {
+        const SiteRec *r = sites + cr.site_begin + s;
+        if (gld(&r->open_mask) != 0) continue;
+        const int rank = gld(&r->rank);
+        const int64_t so = gld(&r->slice_off);
+        for (int l = 0; l < rank; ++l) {
+            const int d = gld(&r->dim[l]), st = gld(&r->stride[l]);
+            double n2 = 0.0;
+            for (int k = 1; k < d; ++k) {
+                const double x = (double)SliceIO<S>::load(slices, so + (int64_t)k * st);
+                n2 = fma(x, x, n2);
+            }
+            dm = fmax(dm, sqrt(n2));
+        }
+    }
+    *dangling = block_max_nt<NT>(dm, red);
+    double ws = 0.0, wt = 0.0;
+    const int nb = gr.n_buckets < 64 ? gr.n_buckets : 64;
+    for (int b = 0; b < nb; ++b) {
+        const Bucket bk = buckets[gr.bucket_begin + b];
+        const int64_t n = (int64_t)(bk.end - bk.begin) * bk.osz;
+        double a = 0.0;
+        for (int64_t e = tid; e < n; e += NT) a += fabs(wn[bk.w_begin + e]);
+        ws = fma((bk.size + 1) * unit_roundoff<S>() + bk.size * arith_roundoff<S>(), a, ws);
+        wt += a;
+    }
+    ws = block_sum_nt<NT>(ws, red);
+    wt = block_sum_nt<NT>(wt, red);
+    *err = ws * (1.0 + wt);
+}
+
 // FP64 sum of a closed network's retained configurations by a block of NT
 // threads (the closed case of the combine kernel): with W_s the sum of the
 // weights of clusters of size s and Q_s the sum of their squares,
 //   S = sum_s W_s + sum_{s<s', s+s'<=K} W_s W_s' + sum_{2s<=K} (W_s^2 - Q_s)/2
 //       - (sum over listed overlapping pairs of w_a w_b),
 // ln|Z| = sum_v ln|z'_v| + ln|1 + S|; `status` is the network's status this
-// run.  lds: 8 + 2*64 + 33 doubles.
-template <int NT>
+// run.  Also records the dangling measure and the precision estimate
+// (net_diagnostics).  lds: 8 + 2*64 + 33 doubles.
+template <int NT, typename S>
 __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, const Bucket *__restrict__ buckets,
                                const int *__restrict__ pair_a, const int *__restrict__ pair_b,
                                const PairCat *__restrict__ cats, const double *__restrict__ w,
                                const double *__restrict__ site_log, const int *__restrict__ site_sign,
+                               const SiteRec *__restrict__ sites, const S *__restrict__ slices,
                                int status, NetResult *__restrict__ out, double *lds) {
     const int tid = threadIdx.x;
     double *red = lds;
@@ -117,6 +193,8 @@ __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, 
     }
     lg = block_sum_nt<NT>(lg, red);
     neg = block_sum_nt<NT>(neg, red);
+    double dangling, err;
+    net_diagnostics<NT, S>(cr, gr, buckets, sites, slices, wn, red, &dangling, &err);
     for (int i = tid; i < 33; i += NT) bidx[i] = -1;
     __syncthreads();
     const int nb = gr.n_buckets < 64 ? gr.n_buckets : 64;
@@ -174,8 +252,10 @@ __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, 
     res.status = status;
     res.log_bp = lg;
     res.sum = SC;
+    res.dangling = dangling;
     const int sign_bp = ((int)neg & 1) ? -1 : 1;
     const double tot = 1.0 + SC;
+    res.err_est = err / fabs(tot);
     res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
     res.log_abs = lg + log(fabs(tot));
     out[net] = res;

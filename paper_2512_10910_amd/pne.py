@@ -20,6 +20,7 @@ LIB_PATH = os.path.join(_HERE, "libpne.so")
 
 PNE_OK = 0
 PNE_WARN_BP_NOT_CONVERGED = 1
+PNE_WARN_PRECISION = 2
 PNE_ERR_INVALID_ARG = -1
 PNE_ERR_UNSUPPORTED = -2
 PNE_ERR_OUT_OF_MEMORY = -3
@@ -28,6 +29,7 @@ PNE_ERR_DEVICE = -5
 PNE_ERR_NOT_READY = -6
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
+MODES = {"loop": 0, "full": 1}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)
@@ -56,6 +58,10 @@ class Options(ctypes.Structure):
         ("bp_check_every", ctypes.c_int32),
         ("flags", ctypes.c_uint32),
         ("profile_kernels", ctypes.c_int32),
+        ("mode", ctypes.c_int32),
+        ("reserved0", ctypes.c_int32),
+        ("bp_damping", ctypes.c_double),
+        ("err_bound", ctypes.c_double),
     ]
 
 
@@ -72,6 +78,8 @@ class ResultStruct(ctypes.Structure):
         ("n_config_terms", ctypes.c_int64),
         ("open_values", _f64p),
         ("open_capacity", ctypes.c_int64),
+        ("dangling_max", ctypes.c_double),
+        ("term_err_est", ctypes.c_double),
     ]
 
 
@@ -109,14 +117,14 @@ class ServerStats(ctypes.Structure):
 
 
 # numpy view of pne_result (same field offsets as the C struct)
+_RESULT_FIELDS = ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
+                  "n_cluster_terms", "n_config_terms", "open_values", "open_capacity", "dangling_max",
+                  "term_err_est"]
 RESULT_DTYPE = np.dtype({
-    "names": ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
-              "n_cluster_terms", "n_config_terms", "open_values", "open_capacity"],
+    "names": _RESULT_FIELDS,
     "formats": [np.int32, np.int32, np.float64, np.float64, np.int32, np.int32, np.float64, np.int64, np.int64,
-                np.uint64, np.int64],
-    "offsets": [getattr(ResultStruct, f).offset for f in
-                ["status", "sign", "log_abs", "log_abs_bp", "bp_iters", "n_open_values", "bp_residual",
-                 "n_cluster_terms", "n_config_terms", "open_values", "open_capacity"]],
+                np.uint64, np.int64, np.float64, np.float64],
+    "offsets": [getattr(ResultStruct, f).offset for f in _RESULT_FIELDS],
     "itemsize": ctypes.sizeof(ResultStruct),
 })
 
@@ -195,8 +203,8 @@ _PROTOS = {
     "pne_strip_options_default": (ctypes.c_int, [ctypes.POINTER(StripOptions)]),
     "pne_strip_expand": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32, ctypes.POINTER(StripOptions),
                                         ctypes.POINTER(StripResult)]),
-    "pne_count_configurations": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32, ctypes.c_int32, _i32p,
-                                                _i32p, ctypes.POINTER(ctypes.c_int64),
+    "pne_count_configurations": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_int32, _i32p, _i32p, ctypes.POINTER(ctypes.c_int64),
                                                 ctypes.POINTER(ctypes.c_int64)]),
     "pne_batch_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                         ctypes.POINTER(Options), ctypes.POINTER(ctypes.c_void_p)]),
@@ -315,8 +323,9 @@ def _partition_arrays(partitions):
     return parts, np.ascontiguousarray(begin), np.ascontiguousarray(bonds)
 
 
-def count_configurations(obj, K: int, partitions=()):
-    """Host-only: (retained clusters, retained configurations) at degree cap K."""
+def count_configurations(obj, K: int, partitions=(), mode="loop"):
+    """Host-only: (retained clusters, retained configurations) at degree cap K
+    in the given mode ("loop" or "full")."""
     lib = load_library()
     tensors, bonds, open_legs = _net_parts(obj)
     shapes = [np.empty(t.shape, dtype=np.float64) if isinstance(t, np.ndarray) else np.empty(tuple(t.shape))
@@ -325,7 +334,8 @@ def count_configurations(obj, K: int, partitions=()):
     parts, begin, pb = _partition_arrays(partitions)
     nc = ctypes.c_int64(0)
     ncf = ctypes.c_int64(0)
-    _check(lib, lib.pne_count_configurations(ctypes.byref(da.desc), K, len(parts), begin.ctypes.data_as(_i32p),
+    _check(lib, lib.pne_count_configurations(ctypes.byref(da.desc), K, MODES[mode], len(parts),
+                                             begin.ctypes.data_as(_i32p),
                                              pb.ctypes.data_as(_i32p), ctypes.byref(nc), ctypes.byref(ncf)))
     return nc.value, ncf.value
 
@@ -367,6 +377,8 @@ class Result:
     n_cluster_terms: int
     n_config_terms: int
     open_values: np.ndarray | None = None
+    dangling_max: float = 0.0
+    term_err_est: float = 0.0
 
     @property
     def ok(self) -> bool:
@@ -384,7 +396,7 @@ PATH_PERSISTENT, PATH_BLOCK_GAUGE, PATH_BLOCK_TERMS = 1, 2, 4
 
 
 def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
-             fused_regauge=True, graph=False, autotune=False):
+             fused_regauge=True, graph=False, autotune=False, mode="loop", damping=0.0, err_bound=1e-5):
     """profile: False, True (every kernel) or a list of KERNEL_NAMES to time."""
     lib = load_library()
     o = Options()
@@ -399,6 +411,9 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.flags = (PNE_FLAG_PROFILE if profile else 0) | (0 if persistent else PNE_FLAG_NO_PERSISTENT) | \
         (PNE_FLAG_BP_JACOBI if jacobi else 0) | (0 if fused_regauge else PNE_FLAG_SEPARATE_REGAUGE) | \
         (PNE_FLAG_GRAPH if graph else 0) | (PNE_FLAG_AUTOTUNE if autotune else 0)
+    o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
+    o.bp_damping = float(damping)
+    o.err_bound = float(err_bound)
     return o
 
 
@@ -441,14 +456,16 @@ class Context:
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
               profile=False, persistent=True, jacobi=False, fused_regauge=True, graph=False,
-              autotune=False) -> "Batch":
+              autotune=False, mode="loop", damping=0.0, err_bound=1e-5) -> "Batch":
         """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
         in the persistent kernel even on bipartite networks; fused_regauge=
         False: gauge + slices in their own launch; graph=True: replay a
         captured HIP graph; autotune=True: pick the variant by measurement
-        (cached per batch signature in the context)."""
+        (cached per batch signature in the context); mode="full": every
+        configuration of degree <= K, dangling ones included; damping: BP
+        damping in [0, 1); err_bound: reduced-precision warning bound."""
         return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi,
-                     fused_regauge, graph, autotune)
+                     fused_regauge, graph, autotune, mode, damping, err_bound)
 
     def autotune(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, trials=3) -> dict:
         """Time the execution variants for this batch; returns the chosen flags."""
@@ -513,8 +530,8 @@ class Context:
             out["patch_ratio"] = patch
         return out
 
-    def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500) -> Result:
-        b = self.batch([net], K, precision, tol, max_iter)
+    def contract(self, net, K=4, precision="fp64", tol=1e-13, max_iter=500, **kw) -> Result:
+        b = self.batch([net], K, precision, tol, max_iter, **kw)
         try:
             return b.run()[0]
         finally:
@@ -586,11 +603,12 @@ class Batch:
     """Prepared batch: plans and device tables built once, run many times."""
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
-                 persistent=True, jacobi=False, fused_regauge=True, graph=False, autotune=False):
+                 persistent=True, jacobi=False, fused_regauge=True, graph=False, autotune=False, mode="loop",
+                 damping=0.0, err_bound=1e-5):
         self.ctx = ctx
         self.nets = list(nets)
         self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge,
-                            graph, autotune)
+                            graph, autotune, mode, damping, err_bound)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),
@@ -635,7 +653,7 @@ class Batch:
             if net.n_open and r.n_open_values:
                 ov = self._open[i][: r.n_open_values].copy().reshape(net.open_shape)
             out.append(Result(r.status, r.sign, r.log_abs, r.log_abs_bp, r.bp_iters, r.bp_residual,
-                              r.n_cluster_terms, r.n_config_terms, ov))
+                              r.n_cluster_terms, r.n_config_terms, ov, r.dangling_max, r.term_err_est))
         return out
 
     def run(self, raise_on_error: bool = False):
@@ -803,7 +821,7 @@ class Server:
         self._open_shape.pop(ticket, None)
         ov = buf[: r.n_open_values].copy().reshape(shape) if (m and r.n_open_values) else None
         return Result(r.status, r.sign, r.log_abs, r.log_abs_bp, r.bp_iters, r.bp_residual, r.n_cluster_terms,
-                      r.n_config_terms, ov)
+                      r.n_config_terms, ov, r.dangling_max, r.term_err_est)
 
     def stats(self) -> dict:
         st = ServerStats()

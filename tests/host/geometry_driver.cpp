@@ -127,6 +127,24 @@ int main() {
         expect(!set_subpartitions(&g, 1u, 1, sb, bad).empty(), "out-of-range sub-partition bond refused");
         expect(set_partitions(&g, 0, nullptr, nullptr).empty(), "clear partitions");
     }
+    // complete-expansion mode: every connected bond set, every configuration listed
+    {
+        Lattice L(3, 3, 2);
+        Geometry g;
+        expect(build_geometry(&L.desc, &g).empty(), "3x3 geometry");
+        for (int K : {1, 4, 12}) {
+            std::string err;
+            auto p = build_plan(g, K, &err, true);
+            expect(p != nullptr && p->listed, "complete-expansion plan");
+        }
+        std::string err;
+        auto p = build_plan(g, 12, &err, true);
+        expect(p && p->n_configs == 4095, "2^12 - 1 configurations");
+        Lattice B(5, 3, 2);  // 22 bonds
+        Geometry gb;
+        expect(build_geometry(&B.desc, &gb).empty(), "5x3 geometry");
+        expect(build_plan(gb, 4, &err, true) == nullptr, "complete expansion above 20 bonds refused");
+    }
     // malformed descriptors
     {
         Lattice L(3, 3, 2);

@@ -57,8 +57,10 @@ int main(void) {
   printf("desc %zu\nopt %zu\nres %zu\n", sizeof(pne_network_desc), sizeof(pne_options), sizeof(pne_result));
   P(pne_network_desc, site_rank) P(pne_network_desc, site_data)
   P(pne_options, bp_tol) P(pne_options, bp_max_iter) P(pne_options, flags)
+  P(pne_options, mode) P(pne_options, bp_damping) P(pne_options, err_bound)
   P(pne_result, log_abs) P(pne_result, bp_iters) P(pne_result, bp_residual)
   P(pne_result, n_config_terms) P(pne_result, open_values) P(pne_result, open_capacity)
+  P(pne_result, dangling_max) P(pne_result, term_err_est)
   printf("sopt %zu\nsstat %zu\n", sizeof(pne_server_options), sizeof(pne_server_stats));
   P(pne_server_options, max_batch) P(pne_server_options, pipeline_depth) P(pne_server_options, completion_queue)
   P(pne_server_stats, device_bytes_admitted) P(pne_server_stats, latency_p50_ms) P(pne_server_stats, busy_s)
@@ -93,6 +95,7 @@ def test_options_default(lib):
     o = B.Options()
     assert lib.pne_options_default(ctypes.byref(o)) == 0
     assert o.max_excited == 4 and o.precision == 0 and o.bp_tol == 1e-13 and o.bp_max_iter == 500
+    assert o.mode == 0 and o.bp_damping == 0.0 and o.err_bound == 1e-5
 
 
 def test_server_options_default_and_null_context(lib):
@@ -226,3 +229,33 @@ int main(void) {
     a, b, c, d, e = (int(x) for x in subprocess.check_output([str(exe)]).split())
     assert a == ctypes.sizeof(B.RankOptions) and b == ctypes.sizeof(B.RankResult)
     assert c == B.RankOptions.tol.offset and d == B.RankResult.log_abs.offset and e == B.RankResult.log_scale.offset
+
+
+@pytest.mark.parametrize("shape,K", [((3, 3), 12), ((3, 3), 5), ((2, 4), 10), ((3, 4), 17)])
+def test_full_mode_counts_match_oracle(lib, shape, K):
+    """The complete-expansion mode lists every bond subset of size <= K as its
+    connected components: sum_k C(M, k) configurations, and the oracle's
+    connected sets (no dangling rule) as clusters."""
+    import math
+
+    net = P.random_2d(shape[0], shape[1], 2, "uniform01", seed=1)
+    M = net.n_bonds
+    nc, ncf = pne.count_configurations(net, K, mode="full")
+    assert ncf == sum(math.comb(M, k) for k in range(1, min(K, M) + 1))
+    assert nc == len(O.enumerate_clusters(net, K, full=True))
+    loop_nc, _ = pne.count_configurations(net, K)
+    assert loop_nc == len(O.enumerate_clusters(net, K)) < nc
+
+
+def test_full_mode_envelope(lib):
+    big = P.random_2d(5, 3, 2, "uniform01", seed=1)  # 22 bonds
+    with pytest.raises(pne.PNEError) as ei:
+        pne.count_configurations(big, 4, mode="full")
+    assert ei.value.status == B.PNE_ERR_UNSUPPORTED
+    opn = P.random_2d(3, 3, 2, "uniform01", seed=2, open_sites={4: 2})
+    with pytest.raises(pne.PNEError) as ei:
+        pne.count_configurations(opn, 4, mode="full")
+    assert ei.value.status == B.PNE_ERR_UNSUPPORTED
+    with pytest.raises(pne.PNEError) as ei:
+        pne.count_configurations(P.random_2d(3, 3, 2, "uniform01", seed=2), 4, [[0]], mode="full")
+    assert ei.value.status == B.PNE_ERR_UNSUPPORTED

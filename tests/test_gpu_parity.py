@@ -182,12 +182,11 @@ def test_small_networks_reduced_precision(ctx, name, make, K, precision):
     r, _, _ = _run(ctx, net, K, precision)
     ref = O.pne_contract(net, K)
     if precision == "bf16" and name.startswith("aklt"):
-        # BF16 slices carry 8 mantissa bits; with O(1) loop corrections
-        # (S ~ 0.4 here) the term sum keeps only ~2-3 digits.  The 1e-5 bound
-        # holds where corrections are small (random U[0,1] / N(1,0.3) inputs).
-        d = abs(r.log_abs - ref.log_abs)
-        assert d < 2 ** -7 * abs(ref.log_abs - ref.log_abs_bp) * 4, d
+        # O(1) loop corrections: BF16 slices (8-bit mantissa) cannot meet the
+        # bound, and the library says so (tests/test_gpu_modes.py covers it)
+        assert r.status == 2 and abs(r.log_abs - ref.log_abs) <= r.term_err_est
         return
+    assert r.status == 0, (r.status, r.term_err_est)
     _check_closed(r, ref, 1e-5)
 
 
@@ -303,15 +302,24 @@ def test_config2_random_16x16(ctx, D, seed):
         _check_closed(r, ref, 1e-5)
 
 
-@pytest.mark.parametrize("beta,val", [(0.18, 158.852294287657), (0.2217, 163.721323202172),
-                                      (0.26, 169.055513732165)])
-def test_config3_ising_6cube(ctx, beta, val):
+@pytest.mark.parametrize("beta", [0.18, 0.2217, 0.26])
+def test_config3_ising_6cube(ctx, beta):
+    """6^3 Ising at K = 6 against the oracle and against the high-temperature
+    closed form 216 ln 2 + 540 ln cosh b + ln(1 + 450 t^4 + 2720 t^6),
+    t = tanh b, evaluated in FP64 here (its own rounding is ~1e-13)."""
     net = P.config3_ising_network(beta)
+    ref = O.pne_contract(net, 6)
+    t = math.tanh(beta)
+    closed = 216 * math.log(2.0) + 540 * math.log(math.cosh(beta)) + math.log1p(450 * t ** 4 + 2720 * t ** 6)
+    assert abs(ref.log_abs - closed) <= 1e-12 * closed
     for prec in ("fp64", "fp32"):
         r, _, _ = _run(ctx, net, 6, prec)
-        assert r.status == 0
-        tol = 1e-10 if prec == "fp64" else 1e-5 * val
-        assert abs(r.log_abs - val) < max(tol, 1e-9), (prec, r.log_abs)
+        assert r.status == 0 and r.sign == 1
+        d = abs(r.log_abs - ref.log_abs)
+        if prec == "fp64":
+            assert d <= 1e-10 and abs(r.log_abs - closed) <= 1e-10, (d, r.log_abs - closed)
+        else:
+            assert d / abs(ref.log_abs) <= 1e-5
     assert r.n_cluster_terms == 3170
 
 
