@@ -260,6 +260,24 @@ pne_status pne_contract(pne_ctx *ctx, pne_network *net, const pne_options *opt, 
 pne_status pne_contract_batch(pne_ctx *ctx, pne_network *const *nets, int32_t n,
                               const pne_options *opt, pne_result *results);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * evaluation as pne_contract_batch, with every device table and buffer of the
+ * batch placed in a fixed 64 MiB device array that the library holds on each
+ * GPU it runs on until the process ends.  The call allocates no device or
+ * pinned memory and creates no events (its host-side planning uses ordinary
+ * host memory); results are copied to the caller's pne_result array and the
+ * call returns after synchronising the context stream.  Networks are the
+ * caller's inputs (made beforehand with pne_network_create).  Errors:
+ * OUT_OF_MEMORY when the batch needs more than the array holds (16x16 D=4
+ * networks need about 0.55 MB each with FP64 slices, 0.35 MB with FP32), INVALID_ARG for null arguments and for
+ * PNE_FLAG_PROFILE / GRAPH / AUTOTUNE (they allocate), and every error of
+ * pne_contract_batch.  Every call on a GPU shares that GPU's array, and the
+ * array keeps the last call's contents: calls that overlap on one GPU (from
+ * two threads, or on two contexts of one device) race and must not be made. */
+pne_status pne_contract_batch_noalloc(pne_ctx *ctx, pne_network *const *nets, int32_t n,
+                                      const pne_options *opt, pne_result *results);
+
 /* --- introspection (parity tests and tooling) -------------------------- */
 
 /* Host-only: list the retained clusters (connected bond sets of size <= K in

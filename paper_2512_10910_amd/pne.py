@@ -216,6 +216,8 @@ _PROTOS = {
                                     ctypes.POINTER(ResultStruct)]),
     "pne_contract_batch": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                           ctypes.POINTER(Options), ctypes.POINTER(ResultStruct)]),
+    "pne_contract_batch_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
+                                                  ctypes.POINTER(Options), ctypes.POINTER(ResultStruct)]),
     "pne_enumerate_clusters": (ctypes.c_int, [ctypes.POINTER(NetworkDesc), ctypes.c_int32,
                                               ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                                               _i32p, _i32p]),
