@@ -21,6 +21,7 @@ from .pne_oracle import (  # noqa: F401
     enumerate_clusters,
     cluster_weight,
     enumerate_collections,
+    cumulant_sum,
     pne_contract,
     literal_term,
     OracleResult,

@@ -318,6 +318,37 @@ def enumerate_collections(clusters, sizes, vsets, K):
     return res
 
 
+def cumulant_sum(weights, sizes, vsets, K):
+    """Exponentiated (cumulant) form of the retained-term sum.
+
+    With the clusters as polymers, two of them incompatible when they share
+    a site, the sum over vertex-disjoint collections is 1 + S =
+    sum_collections prod w, and its logarithm is the Mayer cluster series
+    ln(1 + S) = sum over ordered tuples of polymers whose incompatibility
+    graph is connected, of phi(tuple) / n! prod w (phi = 1 for one polymer,
+    -1 for two incompatible ones).  Truncated at total degree K < 3 * the
+    smallest cluster, only one- and two-polymer tuples remain:
+
+        F = sum_c w_c - 1/2 sum_{(c, c') incompatible, |c| + |c'| <= K} w_c w_c',
+
+    the ordered pairs including c = c'.  Each term is local, so F is additive
+    over disjoint parts of a network; ln Z ~ ln Z_BP + F.
+    """
+    n = len(weights)
+    if n == 0:
+        return 0.0
+    if 3 * min(sizes) <= K:
+        raise ValueError("the second-order cumulant form needs K < 3 * (smallest cluster size)")
+    F = 0.0
+    for i in range(n):
+        F += float(weights[i])
+    for i in range(n):
+        for j in range(n):
+            if sizes[i] + sizes[j] <= K and (i == j or vsets[i] & vsets[j]):
+                F -= 0.5 * float(weights[i]) * float(weights[j])
+    return F
+
+
 # ----------------------------------------------------------------------------
 # the full evaluation
 
@@ -349,12 +380,14 @@ def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop
     retained terms).  mode "full": every configuration of degree <= K, the
     dangling ones included (closed networks); with K >= n_bonds this is the
     complete expansion of Eqs. (2)-(4), equal to the exact contraction for
-    any rank-1 projectors, converged or not.
+    any rank-1 projectors, converged or not.  mode "cumulant": the same
+    retained clusters in exponentiated form (see cumulant_sum), closed
+    networks.
     """
-    if mode not in ("loop", "full"):
-        raise ValueError("mode must be 'loop' or 'full'")
-    if mode == "full" and net.n_open:
-        raise ValueError("full mode is for closed networks")
+    if mode not in ("loop", "full", "cumulant"):
+        raise ValueError("mode must be 'loop', 'full' or 'cumulant'")
+    if mode != "loop" and net.n_open:
+        raise ValueError(f"{mode} mode is for closed networks")
     inc, iters, residual, converged = bp_messages(net, tol, max_iter, damping)
     proj = projectors(net, inc)
     z = vacuum(net, inc)
@@ -379,6 +412,15 @@ def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop
     weights = [cluster_weight(net, inc, proj, z, c) for c in clusters]
     sizes = [len(c) for c in clusters]
     vsets = [cluster_sites(net, c) for c in clusters]
+    if mode == "cumulant":
+        F = cumulant_sum(weights, sizes, vsets, K)
+        res = OracleResult(sign=sign, log_abs=log_scale + F, log_abs_bp=log_scale, bp_iters=iters,
+                           bp_residual=residual, converged=converged, n_clusters=len(clusters),
+                           n_configs=len(clusters))
+        res.dangling_max = dangling_max(net, inc)
+        if keep_details:
+            res.clusters, res.weights, res.inc = clusters, weights, inc
+        return res
     colls = enumerate_collections(clusters, sizes, vsets, K)
 
     if net.n_open == 0:

@@ -153,3 +153,110 @@ def test_full_mode_planted_mistake_is_caught(monkeypatch):
     monkeypatch.setattr(PO, "enumerate_clusters", lambda n, K, full=False: real(n, K, full=False))
     bad = O.pne_contract(net, net.n_bonds, max_iter=2, mode="full")
     assert abs(bad.log_abs - le) > 1e-9
+
+
+# ----------------------------------------------------------------------------
+# exponentiated (cumulant) form
+
+
+def _even_counts(Lx, Ly):
+    """Size histogram of the even subgraphs of an Lx x Ly grid (XOR of plaquettes)."""
+    idx = {}
+    for y in range(Ly):
+        for x in range(Lx):
+            s = x + Lx * y
+            if x + 1 < Lx:
+                idx[(s, s + 1)] = len(idx)
+            if y + 1 < Ly:
+                idx[(s, s + Lx)] = len(idx)
+    basis = []
+    for y in range(Ly - 1):
+        for x in range(Lx - 1):
+            s = x + Lx * y
+            basis.append((1 << idx[(s, s + 1)]) | (1 << idx[(s, s + Lx)]) | (1 << idx[(s + 1, s + 1 + Lx)])
+                         | (1 << idx[(s + Lx, s + Lx + 1)]))
+    counts = {}
+    for bits in range(1 << len(basis)):
+        m = 0
+        for i in range(len(basis)):
+            if bits >> i & 1:
+                m ^= basis[i]
+        k = bin(m).count("1")
+        counts[k] = counts.get(k, 0) + 1
+    return counts
+
+
+def _log_series(counts, K):
+    """Integer Taylor coefficients c_k, k <= K, of ln(1 + sum_k g_k t^k) when
+    every g_k with k > 0 has k >= 4 and K < 12 (so P^3 is beyond t^K):
+    ln(1 + P) = P - P^2 / 2 mod t^12."""
+    P = {k: c for k, c in counts.items() if k > 0}
+    out = {}
+    for k, c in P.items():
+        if k <= K:
+            out[k] = out.get(k, 0) + c
+    for a, ca in P.items():
+        for b, cb in P.items():
+            if a + b <= K:
+                out[a + b] = out.get(a + b, 0) - 0.5 * ca * cb
+    return out
+
+
+@pytest.mark.parametrize("Lx,Ly,beta,K", [(4, 4, 0.44, 8), (5, 4, 0.3, 10), (5, 5, 0.4, 8), (4, 4, 0.25, 6)])
+def test_cumulant_form_equals_the_log_of_the_ht_series(Lx, Ly, beta, K):
+    """Ising at the paramagnetic point: every retained cluster weighs t^|c|
+    (t = tanh beta), so the cumulant form must equal N ln 2 + M ln cosh beta
+    plus the Taylor coefficients (to t^K) of ln(1 + sum_k g_k t^k), with g_k
+    the brute-force even-subgraph counts."""
+    net = P.ising_2d(Lx, Ly, beta)
+    r = O.pne_contract(net, K, mode="cumulant")
+    t = math.tanh(beta)
+    c = _log_series(_even_counts(Lx, Ly), K)
+    expect = net.n_sites * math.log(2.0) + net.n_bonds * math.log(math.cosh(beta)) + \
+        sum(v * t ** k for k, v in c.items())
+    assert r.sign == 1
+    assert abs(r.log_abs - expect) < 1e-12 * expect
+
+
+def _disjoint_union(a, b):
+    tens = list(a.tensors) + list(b.tensors)
+    bonds = np.concatenate([np.asarray(a.bonds), np.asarray(b.bonds) + np.array([a.n_sites, 0, a.n_sites, 0])])
+    return P.Network(tens, bonds.astype(np.int32), np.zeros((0, 2), np.int32))
+
+
+def test_cumulant_form_is_additive_over_disjoint_parts():
+    a = P.random_2d(4, 4, 3, "normal", seed=41)
+    b = P.random_2d(5, 3, 2, "uniform01", seed=42)
+    ab = _disjoint_union(a, b)
+    K = 8
+    fa, fb, fab = (O.pne_contract(x, K, mode="cumulant") for x in (a, b, ab))
+    assert abs(fab.log_abs - (fa.log_abs + fb.log_abs)) < 1e-11
+    # the truncated sum over collections is not: products of clusters from
+    # both parts beyond degree K are dropped
+    la, lb, lab = (O.pne_contract(x, K) for x in (a, b, ab))
+    assert abs(lab.log_abs - (la.log_abs + lb.log_abs)) > 1e-9
+
+
+def test_cumulant_form_needs_small_K():
+    with pytest.raises(ValueError):
+        O.pne_contract(P.ising_2d(4, 4, 0.3), 12, mode="cumulant")
+    with pytest.raises(ValueError):
+        O.pne_contract(P.random_2d(3, 3, 2, "uniform01", seed=3, open_sites={4: 2}), 4, mode="cumulant")
+
+
+def test_cumulant_planted_mistake_is_caught(monkeypatch):
+    """Leaving out the self-pairs (c, c) breaks the HT pin."""
+    from oracle import pne_oracle as PO
+
+    def no_self(weights, sizes, vsets, K):
+        F = sum(float(w) for w in weights)
+        for i in range(len(weights)):
+            for j in range(len(weights)):
+                if i != j and sizes[i] + sizes[j] <= K and vsets[i] & vsets[j]:
+                    F -= 0.5 * float(weights[i]) * float(weights[j])
+        return F
+
+    net = P.ising_2d(4, 4, 0.44)
+    good = O.pne_contract(net, 8, mode="cumulant").log_abs
+    monkeypatch.setattr(PO, "cumulant_sum", no_self)
+    assert abs(O.pne_contract(net, 8, mode="cumulant").log_abs - good) > 1e-6
