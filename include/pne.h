@@ -86,11 +86,20 @@ typedef enum {
 typedef enum {
     PNE_MODE_LOOP = 0, /* degree <= K, no dangling site (a site with exactly one excited bond;
                           sites with open legs exempt): the retained terms of the method */
-    PNE_MODE_FULL = 1  /* every configuration of degree <= K, dangling ones included.  With
+    PNE_MODE_FULL = 1, /* every configuration of degree <= K, dangling ones included.  With
                           K >= n_bonds this is the complete P/Q expansion of Eqs. (2)-(4), equal
                           to the exact contraction for any rank-1 projectors, converged or not: a
                           self-check for tiny networks.  Closed networks without user partitions,
                           at most 20 bonds (UNSUPPORTED otherwise). */
+    PNE_MODE_CUMULANT = 2 /* the retained clusters of LOOP mode in exponentiated form: with the
+                          clusters as polymers, incompatible when they share a site, ln(1 + S)
+                          is replaced by its Mayer series to second order,
+                            F = sum_c w_c - 1/2 sum_{(c,c') incompatible, |c|+|c'| <= K} w_c w_c'
+                          (ordered pairs, c = c' included), and ln|Z| = ln|Z_BP| + F, sign that
+                          of Z_BP.  F is additive over distant parts of a network (size
+                          extensive).  Closed networks without user partitions, K < 3 x the
+                          smallest cluster (UNSUPPORTED otherwise); pne_result.n_config_terms
+                          then counts clusters. */
 } pne_mode;
 
 /* A tensor network (Sec. II.A).  Every leg slot of every site is either

@@ -507,7 +507,17 @@ __global__ void __launch_bounds__(kCbThreads) k_combine(const int *__restrict__ 
     SC -= psum[0][0];
     res.sum = SC;
     res.dangling = dangling;
-    if (cr.vac_a < 0) {
+    if (cr.cumulant) {
+        double bw0[64], bq0[64];
+        for (int b = 0; b < nb; ++b) {
+            bw0[b] = bsum[b][0];
+            bq0[b] = bsq[b];
+        }
+        res.sum = cumulant_form(bw0, bq0, [&](int s) { return B(0, s); }, K, psum[0][0]);
+        res.sign = sign_bp;
+        res.log_abs = lg + res.sum;
+        res.err_est = err;
+    } else if (cr.vac_a < 0) {
         const double tot = 1.0 + SC;
         res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);
         res.log_abs = lg + log(fabs(tot));

@@ -170,7 +170,7 @@ struct CombineRec {
     int32_t vac_a, vac_b;  // vacuum offsets of the open sites (-1 if none)
     int32_t pa, pb;        // open dims of A and B (1 if absent)
     int32_t open_off;      // first entry of the network's pa*pb open output (-1: closed network)
-    int32_t pad1;
+    int32_t cumulant;      // 1: closed network summed in exponentiated (cumulant) form
 };
 
 // Per-network device result.

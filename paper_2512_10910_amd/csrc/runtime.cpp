@@ -796,7 +796,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     if (opt->max_excited < 0 || opt->max_excited > 32) return fail(ctx, PNE_ERR_INVALID_ARG, "K must be in [0, 32]");
     if (opt->precision < 0 || opt->precision > 2) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown precision");
     if (!(opt->bp_tol >= 0.0) || opt->bp_max_iter < 1) return fail(ctx, PNE_ERR_INVALID_ARG, "bad BP options");
-    if (opt->mode != PNE_MODE_LOOP && opt->mode != PNE_MODE_FULL) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown mode");
+    if (opt->mode < PNE_MODE_LOOP || opt->mode > PNE_MODE_CUMULANT) return fail(ctx, PNE_ERR_INVALID_ARG, "unknown mode");
     if (!(opt->bp_damping >= 0.0 && opt->bp_damping < 1.0))
         return fail(ctx, PNE_ERR_INVALID_ARG, "bp_damping must be in [0, 1)");
     if (!(opt->err_bound >= 0.0)) return fail(ctx, PNE_ERR_INVALID_ARG, "err_bound must be >= 0");
@@ -825,6 +825,12 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             return fail(ctx, unsup ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
         }
         if ((int)p->buckets.size() > 64) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: too many term buckets");
+        if (opt->mode == PNE_MODE_CUMULANT) {
+            if (p->open_a >= 0 || p->listed)
+                return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: the cumulant form takes closed networks without partitions");
+            if (!p->csize.empty() && 3 * *std::min_element(p->csize.begin(), p->csize.end()) <= K)
+                return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: the second-order cumulant form needs K < 3 x the smallest cluster");
+        }
         b->plans.push_back(p);
     }
 
@@ -1142,6 +1148,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         cr.pa = p->pa;
         cr.pb = p->pb;
         cr.open_off = -1;
+        cr.cumulant = opt->mode == PNE_MODE_CUMULANT ? 1 : 0;
         if (p->open_a >= 0) {
             cr.open_off = (int32_t)b->open_total;
             b->open_total += (int64_t)p->pa * p->pb;
@@ -1546,7 +1553,7 @@ pne_status pne_batch_wait(pne_batch *b, pne_result *results) {
         o.bp_iters = s.iters;
         o.bp_residual = s.residual;
         o.n_cluster_terms = p.clusters.count();
-        o.n_config_terms = p.n_configs;
+        o.n_config_terms = b->opt.mode == PNE_MODE_CUMULANT ? p.clusters.count() : p.n_configs;
         o.log_abs = r.log_abs;
         o.log_abs_bp = r.log_bp;
         o.sign = r.sign;

@@ -165,6 +165,24 @@ __device__ inline void net_diagnostics(const CombineRec &cr, const GeoRec &gr, c
     *err = ws * (1.0 + wt);
 }
 
+// Exponentiated form of a closed network's retained terms (one thread): the
+// Mayer series of ln(1 + S) over the clusters as polymers, to second order,
+//   F = sum_s W_s - 1/2 sum_{2s <= K} Q_s - (sum over overlapping pairs a < b
+//       with |a| + |b| <= K of w_a w_b),
+// W_s, Q_s the sum of the weights (their squares) of clusters of s bonds,
+// bucket(s) the bucket of closed clusters of size s (or -1).
+template <class BF>
+__device__ inline double cumulant_form(const double *bw, const double *bq, BF bucket, int K, double pv) {
+    double F = 0.0;
+    for (int s = 1; s <= K; ++s) {
+        const int b = bucket(s);
+        if (b < 0) continue;
+        F += bw[b];
+        if (2 * s <= K) F -= 0.5 * bq[b];
+    }
+    return F - pv;
+}
+
 // FP64 sum of a closed network's retained configurations by a block of NT
 // threads (the closed case of the combine kernel): with W_s the sum of the
 // weights of clusters of size s and Q_s the sum of their squares,
@@ -251,9 +269,17 @@ __device__ void combine_closed(int net, const CombineRec &cr, const GeoRec &gr, 
     NetResult res;
     res.status = status;
     res.log_bp = lg;
-    res.sum = SC;
     res.dangling = dangling;
     const int sign_bp = ((int)neg & 1) ? -1 : 1;
+    if (cr.cumulant) {
+        res.sum = cumulant_form(bw, bq, B, K, pv);
+        res.sign = sign_bp;
+        res.log_abs = lg + res.sum;
+        res.err_est = err;
+        out[net] = res;
+        return;
+    }
+    res.sum = SC;
     const double tot = 1.0 + SC;
     res.err_est = err / fabs(tot);
     res.sign = tot == 0.0 ? 0 : (tot > 0.0 ? sign_bp : -sign_bp);

@@ -29,7 +29,7 @@ PNE_ERR_DEVICE = -5
 PNE_ERR_NOT_READY = -6
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
-MODES = {"loop": 0, "full": 1}
+MODES = {"loop": 0, "full": 1, "cumulant": 2}
 
 _i32p = ctypes.POINTER(ctypes.c_int32)
 _f64p = ctypes.POINTER(ctypes.c_double)

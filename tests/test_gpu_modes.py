@@ -151,3 +151,39 @@ def test_bf16_on_random_networks_meets_the_bound_without_warning(ctx):
         assert r.status == 0, (r.status, r.term_err_est)
         assert d / max(1.0, abs(ref.log_abs)) <= 1e-5
         assert d <= max(r.term_err_est, 1e-12)
+
+
+@pytest.mark.parametrize("name,make,K", [
+    ("ising_4x4", lambda: P.ising_2d(4, 4, 0.44), 8),
+    ("rand_6x5_D3", lambda: P.random_2d(6, 5, 3, "normal", seed=44), 8),
+    ("rand3d_3_D3", lambda: P.random_3d(3, 3, "uniform01", seed=11), 6),
+    ("config2_D4", lambda: P.config2_network(4, 2000), 6),
+    ("aklt_12x12", lambda: P.config3_aklt_network(), 8),
+    ("ising3d_6", lambda: P.config3_ising_network(0.2217), 6),
+])
+def test_cumulant_form_matches_oracle(ctx, name, make, K):
+    """PNE_MODE_CUMULANT on both combine paths (the persistent block's and the
+    combine launch's) against the oracle's second-order Mayer series."""
+    net_in = make()
+    ref = O.pne_contract(net_in, K, mode="cumulant")
+    net = ctx.network(net_in)
+    for fused in (True, False):
+        r = ctx.contract(net, K=K, mode="cumulant", fused_regauge=fused)
+        assert r.status == 0 and r.sign == ref.sign
+        assert abs(r.log_abs - ref.log_abs) <= 1e-10, (fused, r.log_abs - ref.log_abs)
+        assert r.n_config_terms == r.n_cluster_terms == ref.n_clusters
+    r32 = ctx.contract(net, K=K, mode="cumulant", precision="fp32")
+    assert r32.status == 0 and abs(r32.log_abs - ref.log_abs) / max(1.0, abs(ref.log_abs)) <= 1e-5
+
+
+def test_cumulant_form_refusals(ctx):
+    import paper_2512_10910_amd as pne
+
+    closed = ctx.network(P.ising_2d(4, 4, 0.3))
+    with pytest.raises(pne.PNEError) as ei:
+        ctx.batch([closed], K=12, mode="cumulant")
+    assert ei.value.status == -2
+    opened = ctx.network(P.random_2d(4, 4, 3, "uniform01", seed=32, open_sites={5: 2, 6: 2}))
+    with pytest.raises(pne.PNEError) as ei:
+        ctx.batch([opened], K=6, mode="cumulant")
+    assert ei.value.status == -2
