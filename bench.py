@@ -342,6 +342,200 @@ def rank_bench(pne, P, n: int = 4096):
     ctx.close()
 
 
+def _cpu_worker(job):
+    """One oracle evaluation of a benchmark network in a single-threaded
+    worker process; returns its wall time."""
+    D, seed, K = job
+    try:
+        from threadpoolctl import threadpool_limits
+    except Exception:  # pragma: no cover
+        threadpool_limits = None
+    import oracle as O
+    import pne_inputs as P
+
+    net = P.config2_network(D, seed)
+    with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
+        t0 = time.perf_counter()
+        O.pne_contract(net, K)
+        return time.perf_counter() - t0
+
+
+def cpu_baseline(K: int, per_core: int, n_seeds: int) -> dict:
+    """The FP64 CPU oracle on the host's cores, one single-threaded process
+    per core (at most 16, the machine's CPU share), over a bounded sample of the
+    benchmark workload (per_core networks per process, alternating D = 4 and
+    D = 3, seeds 2000+i).  Runs before anything initialises the GPU, so the
+    worker processes are plain forks of a CPU-only interpreter."""
+    import multiprocessing as mp
+
+    cores = max(1, min(os.cpu_count() or 1, 16))
+    jobs = [((4, 3)[i % 2], 2000 + (i // 2) % n_seeds, K) for i in range(cores * per_core)]
+    ctx = mp.get_context("fork")
+    with ctx.Pool(cores) as pool:
+        t0 = time.perf_counter()
+        times = pool.map(_cpu_worker, jobs, chunksize=per_core)
+        wall = time.perf_counter() - t0
+    return {
+        "value": round(len(jobs) / wall, 4),
+        "unit": "networks/s",
+        "cores": cores,
+        "kind": "oracle",
+        "sample": f"{len(jobs)} networks of this workload (half D=4, half D=3, seeds 2000+), FP64 oracle, "
+                  f"{cores} single-threaded processes x {per_core} networks, {wall:.1f}s wall, "
+                  f"{sum(times):.1f}s of CPU work; host nproc={os.cpu_count()}",
+        "latency_s_per_network_1thread": round(float(np.mean(times)), 4),
+    }
+
+
+def measure_batch(pne, ctx, nets_in, nets, K: int, prec: str, steps: int) -> dict:
+    """Step time of one batch (whole path, results back each step), then a
+    separate pass with HIP events around every launch for the per-kernel
+    split and each kernel's algorithmic bytes over its device time."""
+    import torch
+
+    sb = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
+    b = ctx.batch(nets, K=K, precision=prec)
+    res = b.run_arrays()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        res = b.run_arrays()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    paths = b.paths()
+    b.close()
+    pb = ctx.batch(nets, K=K, precision=prec, profile=True)
+    pb.run_arrays()
+    pb.kernel_times(reset=True)
+    for _ in range(steps):
+        pb.run_arrays()
+    kt = pb.kernel_times(reset=True)
+    pb.close()
+    iters = [int(x) for x in res["bp_iters"]]
+    alg = kernel_bytes(pne, nets_in, paths, iters, [int(x) for x in res["n_cluster_terms"]], K, sb)
+    kernels = {}
+    for k, (tms, cnt) in kt.items():
+        if cnt == 0:
+            continue
+        d = {"ms_per_step": round(tms / steps, 4), "launches_per_step": cnt / steps}
+        if k in alg and tms > 0:
+            gbs = alg[k] / (tms / steps * 1e-3) / 1e9
+            d.update({"alg_bytes_per_step": alg[k], "achieved_GBps": round(gbs, 1),
+                      "frac_of_hbm_peak": round(gbs / HBM_PEAK_GBS, 4)})
+        kernels[k] = d
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"]) if kernels else None
+    n = len(nets)
+    return {"networks": n, "precision": prec, "K": K, "ms_per_step": round(ms, 4),
+            "networks_per_s": round(n / (ms * 1e-3), 1),
+            "terms_per_s": round(float(res["n_cluster_terms"].sum()) / (ms * 1e-3), 1),
+            "bp_iters_mean": float(np.mean(iters)), "status_counts": {int(s): int((res["status"] == s).sum())
+                                                                        for s in np.unique(res["status"])},
+            "dominant_kernel": dom, "dominant_frac_of_hbm_peak": kernels[dom].get("frac_of_hbm_peak") if dom else None,
+            "kernels": kernels, "_res": res}
+
+
+def other_configs(pne, P, steps: int) -> dict:
+    """The remaining benchmark configurations at batch scale, each with its
+    per-kernel rooflines and an accuracy check: 4x4 Ising (16384 betas),
+    6^3 Ising (three betas x 1365), 12x12 AKLT (4096 copies), and the 32x32
+    D=6 open-index networks at d = 1..8 (x16) in FP64, FP32 and BF16 terms
+    against the stored oracle outputs."""
+    import oracle as O
+
+    out = {}
+    ctx = pne.Context(0)
+
+    def run(label, nets_in, K, prec, reuse=None):
+        objs = reuse if reuse is not None else [ctx.network(x) for x in nets_in]
+        m = measure_batch(pne, ctx, nets_in, objs, K, prec, steps)
+        m = {"workload": label, **m}
+        print(f"bench: {label}, {prec}: {m['networks_per_s']} networks/s", file=sys.stderr, flush=True)
+        return m, objs
+
+    # config 1
+    betas = P.config1_betas(16384)
+    c1_in = [P.ising_2d(4, 4, float(bb)) for bb in betas]
+    m, objs = run("4x4 Ising, beta_i = 0.44(1 + 0.01 u_i), 16384 networks, K=4", c1_in, 4, "fp64")
+    res = m.pop("_res")
+    errs = [abs(float(res["log_abs"][i]) - O.pne_contract(c1_in[i], 4).log_abs) for i in (0, 1, 16383)]
+    m["max_abs_err_log_vs_oracle_samples"] = max(errs)
+    out["config1_ising_4x4"] = m
+    for x in objs:
+        x.close()
+    # config 3, Ising
+    base = {bb: P.config3_ising_network(bb) for bb in (0.18, 0.2217, 0.26)}
+    c3_in = [base[bb] for bb in (0.18, 0.2217, 0.26) for _ in range(1365)]
+    m, objs = run("6x6x6 Ising, beta in {0.18, 0.2217, 0.26} x 1365, K=6", c3_in, 6, "fp32")
+    res = m.pop("_res")
+    errs = []
+    for j, bb in enumerate((0.18, 0.2217, 0.26)):
+        tt = math.tanh(bb)
+        closed = 216 * math.log(2.0) + 540 * math.log(math.cosh(bb)) + math.log1p(450 * tt ** 4 + 2720 * tt ** 6)
+        errs.append(abs(float(res["log_abs"][j * 1365]) - closed) / closed)
+    m["max_rel_err_log_vs_closed_form"] = max(errs)
+    out["config3_ising_6cube"] = m
+    for x in objs:
+        x.close()
+    # config 3, AKLT
+    aklt = P.config3_aklt_network()
+    ref = O.pne_contract(aklt, 8)
+    for prec in ("fp32", "bf16"):
+        m, objs = run(f"12x12 AKLT double layer, 4096 copies, K=8", [aklt] * 4096, 8, prec)
+        res = m.pop("_res")
+        m["rel_err_log_vs_oracle"] = abs(float(res["log_abs"][0]) - ref.log_abs) / abs(ref.log_abs)
+        out[f"config3_aklt_12x12_{prec}"] = m
+        for x in objs:
+            x.close()
+    # config 5
+    with open(os.path.join(ROOT, "tests", "golden", "config5_oracle.json")) as fh:
+        gold = json.load(fh)["results"]
+    c5_uniq = [P.config5_network(d) for d in range(1, 9)]
+    c5_in = c5_uniq * 16
+    objs = [ctx.network(x) for x in c5_in]
+    c5 = {}
+    for prec in ("fp64", "fp32", "bf16"):
+        m = measure_batch(pne, ctx, c5_in, objs, 8, prec, max(1, steps // 2))
+        res = m.pop("_res")
+        b = ctx.batch(objs[:8], K=8, precision=prec)
+        r8 = b.run()
+        b.close()
+        eps = []
+        for d in range(1, 9):
+            g = gold[str(d)]
+            o = np.asarray(g["values"])
+            v = r8[d - 1].open_values * math.exp(r8[d - 1].log_abs - g["log_scale"])
+            eps.append(float(np.linalg.norm(v - o) / np.linalg.norm(o)))
+        m["eps2_vs_oracle_d1_to_8"] = eps
+        c5[prec] = m
+        print(f"bench: 32x32 D=6 open, {prec}: {m['networks_per_s']} networks/s", file=sys.stderr, flush=True)
+    for x in objs:
+        x.close()
+    c5["speedup_fp32_over_fp64"] = round(c5["fp64"]["ms_per_step"] / c5["fp32"]["ms_per_step"], 3)
+    c5["speedup_bf16_over_fp64"] = round(c5["fp64"]["ms_per_step"] / c5["bf16"]["ms_per_step"], 3)
+    c5["workload"] = "32x32 D=6 U[0,1], open dim-2 legs at separation d = 1..8, x16 each (128 networks), K=8"
+    out["config5_open_32x32"] = c5
+    ctx.close()
+    return out
+
+
+def beyond_mall(pne, P, steps: int, precision: str, K: int) -> dict:
+    """The benchmark kernel on a batch whose concurrently resident tensors
+    exceed the 256 MB MALL: 512 networks of 18x18 U[0,1] at D = 4 (663 KB of
+    FP64 tensors each, 340 MB for the 512 blocks resident at once), so the
+    BP re-reads come from DRAM rather than the last-level cache."""
+    nets_in = [P.random_2d(18, 18, 4, "uniform01", seed=9000 + i) for i in range(512)]
+    ctx = pne.Context(0)
+    objs = [ctx.network(x) for x in nets_in]
+    m = measure_batch(pne, ctx, nets_in, objs, K, precision, steps)
+    m.pop("_res")
+    for x in objs:
+        x.close()
+    ctx.close()
+    m["workload"] = f"512 networks of 18x18 U[0,1] D=4 (seeds 9000+i), K={K}, {precision} terms"
+    m["resident_tensor_bytes"] = int(sum(x.nbytes() for x in nets_in))
+    return m
+
+
 def workloads_bench(pne, P, steps: int):
     """The other workloads at batch scale, one JSON line each: step time,
     networks/s, per-kernel device time (HIP events around every launch) with
@@ -443,7 +637,8 @@ def main():
     ap.add_argument("--nets", type=int, default=256, help="networks per bond dimension")
     ap.add_argument("--K", type=int, default=6)
     ap.add_argument("--check", type=int, default=2, help="networks per D checked against the oracle")
-    ap.add_argument("--cpu-sample", type=int, default=24, help="networks timed on the CPU oracle (0: skip)")
+    ap.add_argument("--cpu-sample", type=int, default=24,
+                    help="oracle networks per 8 cores in the CPU baseline (0: skip)")
     ap.add_argument("--fp64-steps", type=int, default=10, help="steps timed with FP64 terms (0: skip)")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel HIP events")
@@ -458,12 +653,22 @@ def main():
                     help="instead: only the infinite-lattice strip expansion at width L")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="before the workload, run plain device copies of MIB MiB (HBM counter calibration)")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the other configurations and the beyond-MALL batch in the default line")
     args = ap.parse_args()
 
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "multi-GPU sharding is a design note, not an implemented path.", file=sys.stderr)
         sys.exit(2)
+
+    # the CPU oracle baseline first: worker processes forked before anything
+    # touches the GPU
+    cpu = None
+    default_run = not (args.workloads or args.strips or args.rank or args.profile_run)
+    if default_run and args.cpu_sample > 0:
+        cpu = cpu_baseline(args.K, max(1, args.cpu_sample // 8), args.nets)
+        print(f"bench: cpu baseline {cpu['value']} networks/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
 
     import torch
 
@@ -656,28 +861,22 @@ def main():
         out["max_rel_err_log_vs_oracle"] = float(max(errs)) if errs else None
         out["accuracy_ok"] = bool(errs and max(errs) <= 1e-5)
 
-        if args.cpu_sample > 0:
-            try:
-                from threadpoolctl import threadpool_limits
-            except Exception:  # pragma: no cover
-                threadpool_limits = None
-            sample = [nets_in[i] for i in range(args.cpu_sample // 2)] + \
-                     [nets_in[args.nets + i] for i in range(args.cpu_sample - args.cpu_sample // 2)]
-            with (threadpool_limits(1) if threadpool_limits else contextlib.nullcontext()):
-                tc0 = time.perf_counter()
-                for n in sample:
-                    O.pne_contract(n, args.K)
-                tc1 = time.perf_counter()
-            out["cpu_baseline"] = {
-                "value": round(len(sample) / (tc1 - tc0), 4),
-                "unit": "networks/s",
-                "cores": 1,
-                "kind": "oracle",
-                "sample": f"{len(sample)} networks of this workload (half D=4, half D=3), FP64 oracle, "
-                          f"one thread, {tc1 - tc0:.1f}s; host nproc={os.cpu_count()}",
-            }
+        if cpu is not None:
+            out["cpu_baseline"] = cpu
+    if not args.profile_run and not args.no_extras:
+        del batch
+        for x in nets:
+            x.close()
+        del nets
+        try:
+            out["beyond_mall"] = beyond_mall(pne, P, max(3, args.steps // 4), args.precision, args.K)
+            print("bench: beyond-MALL batch done", file=sys.stderr, flush=True)
+            out["other_configs"] = other_configs(pne, P, max(3, args.steps // 4))
+            print("bench: other configurations done", file=sys.stderr, flush=True)
+        except Exception as e:  # report, keep the throughput line
+            out["other_configs_error"] = repr(e)
     if args.serving > 0 and not args.profile_run:
-        del batch, nets
+        batch = nets = None
         try:
             out["serving"] = serving_bench(pne, P, args.serving, int(args.serving_budget * 1e9), "bf16", args.K)
         except Exception as e:  # report, keep the throughput line

@@ -66,8 +66,22 @@ _DIRS = ("-x", "+x", "-y", "+y", "-z", "+z")
 def _lattice(shape):
     """Return (site_dirs, bonds) for an open-boundary hypercubic lattice.
 
-    ``site_dirs[s]`` maps a direction name to the site's leg slot.
+    ``site_dirs[s]`` maps a direction name to the site's leg slot.  Cached
+    per shape (callers must not modify the result).
     """
+    shape = tuple(int(x) for x in shape)
+    hit = _LATTICE_CACHE.get(shape)
+    if hit is None:
+        site_dirs, bonds = _lattice_uncached(shape)
+        bonds.setflags(write=False)  # shared by every network of this shape
+        hit = _LATTICE_CACHE[shape] = (site_dirs, bonds)
+    return hit
+
+
+_LATTICE_CACHE = {}
+
+
+def _lattice_uncached(shape):
     nd = len(shape)
     dims = list(shape)
     n = int(np.prod(dims))
@@ -164,16 +178,29 @@ def _ising_site(W: np.ndarray, rank: int) -> np.ndarray:
     return out
 
 
+def _ising_maker(W):
+    """Site tensors by rank, each built once (sites of equal rank share it)."""
+    made = {}
+
+    def make(s, r, o):
+        if r not in made:
+            made[r] = _ising_site(W, r)
+            made[r].setflags(write=False)  # shared by every site of rank r
+        return made[r]
+
+    return make
+
+
 def ising_2d(Lx: int, Ly: int, beta: float, J: float = 1.0) -> Network:
     W = _ising_w(beta, J)
-    net = _build((Lx, Ly), lambda s, r, o: _ising_site(W, r), name=f"ising2d_{Lx}x{Ly}_b{beta}")
+    net = _build((Lx, Ly), _ising_maker(W), name=f"ising2d_{Lx}x{Ly}_b{beta}")
     net.info.update(model="ising", beta=beta, J=J)
     return net
 
 
 def ising_3d(L: int, beta: float, J: float = 1.0) -> Network:
     W = _ising_w(beta, J)
-    net = _build((L, L, L), lambda s, r, o: _ising_site(W, r), name=f"ising3d_{L}_b{beta}")
+    net = _build((L, L, L), _ising_maker(W), name=f"ising3d_{L}_b{beta}")
     net.info.update(model="ising", beta=beta, J=J)
     return net
 
