@@ -387,14 +387,14 @@ def cpu_baseline(K: int, per_core: int, n_seeds: int) -> dict:
     }
 
 
-def measure_batch(pne, ctx, nets_in, nets, K: int, prec: str, steps: int) -> dict:
+def measure_batch(pne, ctx, nets_in, nets, K: int, prec: str, steps: int, **tile) -> dict:
     """Step time of one batch (whole path, results back each step), then a
     separate pass with HIP events around every launch for the per-kernel
     split and each kernel's algorithmic bytes over its device time."""
     import torch
 
     sb = {"fp64": 8, "fp32": 4, "bf16": 2}[prec]
-    b = ctx.batch(nets, K=K, precision=prec)
+    b = ctx.batch(nets, K=K, precision=prec, **tile)
     res = b.run_arrays()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -404,7 +404,7 @@ def measure_batch(pne, ctx, nets_in, nets, K: int, prec: str, steps: int) -> dic
     ms = (time.perf_counter() - t0) * 1e3 / steps
     paths = b.paths()
     b.close()
-    pb = ctx.batch(nets, K=K, precision=prec, profile=True)
+    pb = ctx.batch(nets, K=K, precision=prec, profile=True, **tile)
     pb.run_arrays()
     pb.kernel_times(reset=True)
     for _ in range(steps):
@@ -528,6 +528,15 @@ def beyond_mall(pne, P, steps: int, precision: str, K: int) -> dict:
     objs = [ctx.network(x) for x in nets_in]
     m = measure_batch(pne, ctx, nets_in, objs, K, precision, steps)
     m.pop("_res")
+    # the tuned tile shape (the 256-VGPR kernel leaves room in LDS for the
+    # in-block gauge of these larger networks)
+    choice = ctx.autotune(objs, K=K, precision=precision, trials=3)
+    tuned = measure_batch(pne, ctx, nets_in, objs, K, precision, steps, **{k: choice[k] for k in (
+        "small_sites", "tiles_in_flight", "reg_budget")})
+    tuned.pop("_res")
+    m["autotuned"] = {"choice": choice, "ms_per_step": tuned["ms_per_step"],
+                      "networks_per_s": tuned["networks_per_s"], "dominant_kernel": tuned["dominant_kernel"],
+                      "kernels": tuned["kernels"]}
     for x in objs:
         x.close()
     ctx.close()
@@ -864,6 +873,17 @@ def main():
         if cpu is not None:
             out["cpu_baseline"] = cpu
     if not args.profile_run and not args.no_extras:
+        # the autotuner on this batch: the persistent kernel's tile shapes
+        # timed against the default, the choice kept in a JSON cache
+        import tempfile
+
+        choice = ctx.autotune(nets, K=args.K, precision=args.precision, trials=3)
+        with tempfile.TemporaryDirectory() as td:
+            ctx.tune_cache_save(os.path.join(td, "tune.json"))
+            with open(os.path.join(td, "tune.json")) as fh:
+                entries = json.load(fh)["entries"]
+        ent = entries[0] if entries else {}
+        out["autotune"] = {"choice": choice, "tuned_ms": ent.get("ms"), "default_ms": ent.get("default_ms")}
         del batch
         for x in nets:
             x.close()

@@ -138,6 +138,20 @@ typedef struct {
                              term_err_est / max(1, |ln|Z||) exceeds it, or an open
                              one whose term_err_est exceeds it, is returned with
                              PNE_WARN_PRECISION (FP64 mode never warns)          */
+    /* Tile shape of the persistent BP kernel (execution only: results agree
+     * to rounding; see pne_autotune, which picks them by measurement). */
+    int32_t small_sites;     /* networks of at most this many sites run in
+                                two-wave blocks, the others in eight-wave ones
+                                (0: 64)                                         */
+    int32_t tiles_in_flight; /* tiles per wavefront step for the register shapes
+                                with all legs of dimension 2..4: 1 or 2 (0: by
+                                shape: 2 where a tile holds at most 4 register
+                                values per lane, else 1)                        */
+    int32_t reg_budget;      /* 0: 128 VGPRs per lane, two blocks per CU, 79 KB
+                                of LDS per block; 1: 256 VGPRs, one block per CU,
+                                155 KB of LDS (larger networks stay in the
+                                persistent kernel)                              */
+    int32_t reserved1;
 } pne_options;
 
 /* One network's result.  Closed network: Z = sign * exp(log_abs).  Open
@@ -307,18 +321,32 @@ pne_status pne_count_configurations(const pne_network_desc *desc, int32_t K, int
                                     const int32_t *part_begin, const int32_t *part_bond, int64_t *n_clusters,
                                     int64_t *n_configs);
 
-/* Autotune: for the batch these networks and options would form, time the
- * execution variants (gauge + slices inside the persistent BP block or in
- * their own launch; eager launches or graph replay), `trials` runs each after
- * one warm-up run, and return in *best the options with the fastest variant's
+/* Autotune (Sec. II.D: the terms are evaluated in parallel; this picks how):
+ * for the batch these networks and options would form, time the persistent
+ * kernel's tile shapes (small_sites 64 or 256, tiles_in_flight by shape, 1 or
+ * 2, reg_budget 0 or 1: twelve variants, eager launches), then graph replay of
+ * the best when every network runs in the persistent kernel; `trials` runs
+ * each after one warm-up run.  Variants that do not fit (LDS) are skipped.
+ * *best receives the options with the fastest variant's tile options and
  * flags.  The choice is cached in the context per batch signature (multiset
- * of lattices, K, precision, BP flags): later calls and batches created with
- * PNE_FLAG_AUTOTUNE reuse it without running anything.  The variants agree
- * to rounding (the two regauge forms order their sums differently; graph
- * replay is bitwise the eager sequence).  The runs use the context stream
- * and block. */
+ * of lattices, K, precision, mode, damping, BP flags): later calls and
+ * batches created with PNE_FLAG_AUTOTUNE reuse it without running anything.
+ * The variants agree to rounding (block size and the separate regauge order
+ * sums differently; graph replay is bitwise the eager sequence).  The runs
+ * use the context stream and block. */
 pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const pne_options *opt, int32_t trials,
                         pne_options *best);
+/* The context's tuning cache as a JSON file: {"pne_tune_cache": 1, "entries":
+ * [{"signature": "<16 hex digits>", "flags", "small_sites",
+ * "tiles_in_flight", "reg_budget", "ms", "default_ms"}, ...]} (ms: the chosen
+ * and the default variant's run time when tuned).  Save writes every entry
+ * (to path.tmp, then renamed); load adds or replaces entries and sets
+ * *n_loaded (may be NULL).  INVALID_ARG for an unreadable or malformed file
+ * (entries read before the error are kept).  Signatures hash lattice
+ * geometries and options, not devices: a cache is meant for the machine that
+ * wrote it. */
+pne_status pne_tune_cache_save(pne_ctx *ctx, const char *path);
+pne_status pne_tune_cache_load(pne_ctx *ctx, const char *path, int32_t *n_loaded);
 
 /* Per-kernel device time accumulated over profiled runs (PNE_FLAG_PROFILE),
  * measured with HIP events recorded on the batch's stream around each launch.

@@ -337,7 +337,7 @@ __host__ __device__ constexpr int dpp_tiles_in_flight(int D, int R) {
     return ipw(D, R - (R < 2 ? R : 2)) <= 4 ? 2 : 1;  // more register values per lane spill at two
 }
 
-template <int D, int R>
+template <int D, int R, int KNT>
 __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_off, int n_in_group, int chunk,
                                                        int mi, int mo, int scr, int *bad) {
     constexpr int P = D <= 2 ? 2 : 4;
@@ -349,7 +349,7 @@ __device__ __attribute__((noinline)) double ptiles_dpp(const PLayout L, int gl_o
     constexpr int NL = ipw(D, NLEG);
     constexpr int DT = ipw(D, T);
     constexpr int ND = R * D;
-    constexpr int kNT = dpp_tiles_in_flight(D, R);
+    constexpr int kNT = KNT;  // tiles in flight per wavefront step
     const int lane = threadIdx.x & 63;
     const int slot = lane / LS;
     const int tb = lane - slot * LS;
@@ -720,9 +720,12 @@ __device__ __attribute__((noinline)) void p_clusters(int class_begin, int n_clas
 }
 
 // NT threads per block: kPThreads for most networks, kPSmallThreads for
-// networks of at most kPSmallSites sites (more of them share a CU).
-template <typename S, int NT>
-__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(4, 8)))
+// networks of at most a batch-chosen number of sites (more of them share a
+// CU).  WPE: the fewest waves per SIMD the register allocation must allow;
+// 4 caps a lane at 128 VGPRs (two 512-thread blocks per CU), 2 at 256 (one
+// block per CU, no spills, twice the LDS per block).
+template <typename S, int NT, int WPE>
+__global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict__ groups,
                 const int *__restrict__ site_list, const SiteRec *__restrict__ sites, double *msg0, NetState *st,
                 double tol, int max_iter, S *__restrict__ slices, double *__restrict__ site_log,
@@ -802,31 +805,29 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
             cbase += nchunks;
             for (int c = c0; c < nchunks; c += NW) {
                 double tr = 0.0;
-                switch (gr.dc * 8 + gr.rank) {
-                    case 17: tr = ptiles_dpp<2, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 18: tr = ptiles_dpp<2, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 19: tr = ptiles_dpp<2, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 20: tr = ptiles_dpp<2, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 21: tr = ptiles_dpp<2, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 22: tr = ptiles_dpp<2, 6>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 25: tr = ptiles_dpp<3, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 26: tr = ptiles_dpp<3, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 27: tr = ptiles_dpp<3, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 28: tr = ptiles_dpp<3, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 29: tr = ptiles<3, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 33: tr = ptiles_dpp<4, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 34: tr = ptiles_dpp<4, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 35: tr = ptiles_dpp<4, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 36: tr = ptiles_dpp<4, 4>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 37: tr = ptiles<4, 5>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 41: tr = ptiles<5, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 42: tr = ptiles<5, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 43: tr = ptiles<5, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 49: tr = ptiles<6, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 50: tr = ptiles<6, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
-                    case 51: tr = ptiles<6, 3>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); break;
+                // DPP shapes: one or two tiles in flight (chosen per batch); the
+                // other shapes have one fixed tiling
+#define PNE_PT2(D_, R_)                                                                   \
+    case (D_ * 8 + R_) * 4 + 1:                                                           \
+        tr = ptiles_dpp<D_, R_, 1>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); \
+        break;                                                                            \
+    case (D_ * 8 + R_) * 4 + 2:                                                           \
+        tr = ptiles_dpp<D_, R_, 2>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot); \
+        break;
+#define PNE_PT1(D_, R_)                                                             \
+    case (D_ * 8 + R_) * 4 + tiles_in_flight(ipw(D_, R_ - ((6 / (D_ <= 2 ? 1 : (D_ <= 4 ? 2 : 3))) < R_ ? (6 / (D_ <= 2 ? 1 : (D_ <= 4 ? 2 : 3))) : R_))): \
+        tr = ptiles<D_, R_>(L, gr.list_off, gr.n_sites, c, mi, mo, scr, bad_slot);  \
+        break;
+                switch ((gr.dc * 8 + gr.rank) * 4 + gr.nt) {
+                    PNE_PT2(2, 1) PNE_PT2(2, 2) PNE_PT2(2, 3) PNE_PT2(2, 4) PNE_PT2(2, 5) PNE_PT2(2, 6)
+                    PNE_PT2(3, 1) PNE_PT2(3, 2) PNE_PT2(3, 3) PNE_PT2(3, 4)
+                    PNE_PT2(4, 1) PNE_PT2(4, 2) PNE_PT2(4, 3) PNE_PT2(4, 4)
+                    PNE_PT1(3, 5) PNE_PT1(4, 5) PNE_PT1(5, 1) PNE_PT1(5, 2) PNE_PT1(5, 3)
+                    PNE_PT1(6, 1) PNE_PT1(6, 2) PNE_PT1(6, 3)
                     default: break;
                 }
+#undef PNE_PT1
+#undef PNE_PT2
                 wres = fmax(wres, tr);
             }
         }
@@ -919,8 +920,8 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
 }  // namespace
 
 // doubles of dynamic LDS for a persistent block (see PLayout)
-size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers) {
-    const int waves = n_sites <= kPSmallSites ? kPSmallThreads / 64 : kPWaves;
+size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers, bool small) {
+    const int waves = small ? kPSmallThreads / 64 : kPWaves;
     return (size_t)n_buffers * msg_size + (size_t)n_sites + (size_t)(n_sites + 1) / 2 +
            (size_t)(n_sites * kMaxRank + 1) / 2 + 2 * (size_t)((n_sites + 1) / 2) + (size_t)n_sites +
            (size_t)waves * scratch_per_wave;
@@ -953,33 +954,44 @@ int bp_persistent_sites_per_tile(int dim, int rank) {
     return bp_reg_sites_per_tile(dim, rank);
 }
 
-int bp_persistent_scratch(int spw, int rank, int dim) {
-    return bp_persistent_tiles_in_flight(dim, rank) * spw * rank * dim;
+bool bp_persistent_tiles_tunable(int dim, int rank) { return dpp_shape(dim, rank); }
+
+int bp_persistent_scratch(int spw, int rank, int dim, int nt) {
+    return nt * spw * rank * dim;
 }
 
-template <int NT>
-void launch_fused_nt(const DeviceBatch &b, const FusedNet *fused, int n, size_t lds, double tol, int max_iter,
-                     hipStream_t s) {
+template <int NT, int WPE>
+void launch_fused_w(const DeviceBatch &b, const FusedNet *fused, int n, size_t lds, double tol, int max_iter,
+                    hipStream_t s) {
     switch (b.precision) {
         case 0:
-            hipLaunchKernelGGL((k_bp_persistent<double, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+            hipLaunchKernelGGL((k_bp_persistent<double, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
                                b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         case 1:
-            hipLaunchKernelGGL((k_bp_persistent<float, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+            hipLaunchKernelGGL((k_bp_persistent<float, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
                                b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         default:
-            hipLaunchKernelGGL((k_bp_persistent<uint16_t, NT>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
+            hipLaunchKernelGGL((k_bp_persistent<uint16_t, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
                                b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (uint16_t *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
     }
+}
+
+template <int NT>
+void launch_fused_nt(const DeviceBatch &b, const FusedNet *fused, int n, size_t lds, double tol, int max_iter,
+                     hipStream_t s) {
+    if (b.reg_budget)
+        launch_fused_w<NT, 2>(b, fused, n, lds, tol, max_iter, s);
+    else
+        launch_fused_w<NT, 4>(b, fused, n, lds, tol, max_iter, s);
 }
 
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {

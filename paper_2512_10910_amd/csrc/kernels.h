@@ -19,13 +19,14 @@ struct DeviceBatch {
                                         // D = 5, 6; rank 6 at D = 3)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel: the large ones,
-    int n_fused = 0;                    // then the n_fused_small of at most kPSmallSites sites
+    int n_fused = 0;                    // then the n_fused_small small ones (two-wave blocks)
     int n_fused_small = 0;
     size_t fused_lds_small = 0;
     const FusedGroup *fgroups = nullptr;
     const int *fsite_list = nullptr;
     size_t fused_lds = 0;
     int fused_regauge = 1;              // persistent blocks also build gauge + slices
+    int reg_budget = 0;                 // persistent kernel: 0 two blocks per CU (128 VGPRs), 1 one (256)
     const int *tile_sites = nullptr;
     const int *init_sites = nullptr;    // sites whose messages k_init resets (non-persistent networks)
     int n_init_sites = 0;
@@ -78,7 +79,7 @@ int bp_tile_threads();
 // sites per tile on the register path for uniform leg dimension D and rank R (0: LDS path)
 // Networks of at most this many sites run in persistent blocks of 128
 // threads (two waves) instead of 512.
-constexpr int kPSmallSites = 64;
+constexpr int kPSmallSites = 64;  // default threshold (pne_options.small_sites)
 int bp_reg_sites_per_tile(int D, int R);
 // sites per register tile of the per-launch sweep (0: LDS path); a superset
 // of the shapes bp_reg_sites_per_tile accepts
@@ -90,9 +91,11 @@ hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, h
 hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s);
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s);
 // doubles of dynamic LDS of a persistent block and its per-wave scratch
-size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers);
-int bp_persistent_scratch(int spw, int rank, int dim);
+size_t bp_persistent_lds_doubles(int msg_size, int n_sites, int scratch_per_wave, int n_buffers, bool small);
+int bp_persistent_scratch(int spw, int rank, int dim, int nt);
 int bp_persistent_tiles_in_flight(int dim, int rank);
+// shapes whose tiles in flight (1 or 2) a batch may choose
+bool bp_persistent_tiles_tunable(int dim, int rank);
 // shapes whose gauge and slices the persistent block builds, and the doubles
 // of per-wavefront scratch that needs
 bool bp_persistent_regauge_supported(int dim, int rank);

@@ -4,6 +4,8 @@
 #include <algorithm>
 #include <chrono>
 #include <cmath>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <deque>
 #include <functional>
@@ -62,7 +64,13 @@ struct pne_ctx {
     hipStream_t up_stream = nullptr;
     hipEvent_t up_done = nullptr;
     bool up_pending = false;
-    std::map<uint64_t, uint32_t> tuned;  // batch signature -> chosen flags (PNE_FLAG_AUTOTUNE)
+    // batch signature -> the variant pne_autotune chose (PNE_FLAG_AUTOTUNE)
+    struct Tuned {
+        uint32_t flags = 0;            // PNE_FLAG_GRAPH / PNE_FLAG_SEPARATE_REGAUGE
+        int32_t small_sites = 0, tiles_in_flight = 0, reg_budget = 0;
+        double ms = 0.0, default_ms = 0.0;  // best and default-variant run times when tuned
+    };
+    std::map<uint64_t, Tuned> tuned;
     std::unordered_map<const GeoPlan *, PlanTables> plan_tables;  // plans live as long as the context
 };
 
@@ -751,39 +759,155 @@ pne_status pne_autotune(pne_ctx *ctx, pne_network *const *nets, int32_t n, const
     if (!ctx || !nets || n <= 0 || !opt || !best) return fail(ctx, PNE_ERR_INVALID_ARG, "bad autotune arguments");
     const uint32_t keep = opt->flags & ~(PNE_FLAG_AUTOTUNE | PNE_FLAG_GRAPH | PNE_FLAG_SEPARATE_REGAUGE);
     const uint64_t sig = batch_signature(nets, n, opt);
-    *best = *opt;
+    auto apply = [&](const pne_ctx::Tuned &c) {
+        *best = *opt;
+        best->flags = keep | c.flags;
+        best->small_sites = c.small_sites;
+        best->tiles_in_flight = c.tiles_in_flight;
+        best->reg_budget = c.reg_budget;
+    };
     auto it = ctx->tuned.find(sig);
     if (it != ctx->tuned.end()) {
-        best->flags = keep | it->second;
+        apply(it->second);
         return PNE_OK;
     }
     if (trials < 1) trials = 1;
-    const uint32_t cands[4] = {0u, PNE_FLAG_SEPARATE_REGAUGE, PNE_FLAG_GRAPH,
-                               PNE_FLAG_GRAPH | PNE_FLAG_SEPARATE_REGAUGE};
-    double best_ms = 1e300;
-    uint32_t best_flags = 0;
-    for (uint32_t c : cands) {
+    // Candidates: the persistent kernel's tile shape (small-network block
+    // threshold, tiles in flight, register budget) with eager launches, then
+    // graph replay of the best of those.  The first candidate is the default.
+    std::vector<pne_ctx::Tuned> cands;
+    for (int rb : {0, 1})
+        for (int ss : {0, 256})
+            for (int nt : {0, 1, 2}) {
+                pne_ctx::Tuned c;
+                c.small_sites = ss;
+                c.tiles_in_flight = nt;
+                c.reg_budget = rb;
+                cands.push_back(c);
+            }
+    auto time_variant = [&](const pne_ctx::Tuned &c, double *ms_out, bool *graphable) -> pne_status {
         pne_options o = *opt;
-        o.flags = (keep & ~PNE_FLAG_PROFILE) | c;
+        o.flags = (keep & ~PNE_FLAG_PROFILE) | c.flags;
+        o.small_sites = c.small_sites;
+        o.tiles_in_flight = c.tiles_in_flight;
+        o.reg_budget = c.reg_budget;
         pne_batch *b = nullptr;
         pne_status st = pne::batch_create_on(ctx, nets, n, &o, ctx->stream, &b);
         if (st != PNE_OK) return st;
+        if (graphable) *graphable = b->db.n_tiles == 0;
         double ms = 1e300;
-        for (int t = 0; t <= trials && st >= 0; ++t) {  // the first run warms up
+        for (int tr = 0; tr <= trials && st >= 0; ++tr) {  // the first run warms up
             const auto t0 = std::chrono::steady_clock::now();
             st = pne_batch_run(b, nullptr);
             const double dt = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
-            if (t > 0) ms = std::min(ms, dt);
+            if (tr > 0) ms = std::min(ms, dt);
         }
         pne_batch_destroy(b);
-        if (st < 0) return st;
+        *ms_out = ms;
+        return st < 0 ? st : PNE_OK;
+    };
+    pne_ctx::Tuned bestc;
+    double best_ms = 1e300, default_ms = 0.0;
+    bool graphable = false;
+    for (size_t k = 0; k < cands.size(); ++k) {
+        double ms = 1e300;
+        pne_status st = time_variant(cands[k], &ms, k == 0 ? &graphable : nullptr);
+        if (st != PNE_OK) {
+            if (k == 0) return st;  // the default variant must run
+            continue;               // e.g. a variant whose LDS or register needs do not fit
+        }
+        if (k == 0) default_ms = ms;
         if (ms < best_ms) {
             best_ms = ms;
-            best_flags = c;
+            bestc = cands[k];
         }
     }
-    ctx->tuned[sig] = best_flags;
-    best->flags = keep | best_flags;
+    if (graphable) {
+        pne_ctx::Tuned g = bestc;
+        g.flags = PNE_FLAG_GRAPH;
+        double ms = 1e300;
+        if (time_variant(g, &ms, nullptr) == PNE_OK && ms < best_ms) {
+            best_ms = ms;
+            bestc = g;
+        }
+    }
+    bestc.ms = best_ms;
+    bestc.default_ms = default_ms;
+    ctx->tuned[sig] = bestc;
+    apply(bestc);
+    return PNE_OK;
+}
+
+pne_status pne_tune_cache_save(pne_ctx *ctx, const char *path) {
+    if (!ctx || !path) return fail(ctx, PNE_ERR_INVALID_ARG, "null argument");
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = std::fopen(tmp.c_str(), "w");
+    if (!f) return fail(ctx, PNE_ERR_INVALID_ARG, std::string("cannot write ") + tmp);
+    std::fprintf(f, "{\"pne_tune_cache\": 1, \"entries\": [");
+    bool first = true;
+    for (const auto &kv : ctx->tuned) {
+        const pne_ctx::Tuned &c = kv.second;
+        std::fprintf(f,
+                     "%s\n  {\"signature\": \"%016llx\", \"flags\": %u, \"small_sites\": %d, "
+                     "\"tiles_in_flight\": %d, \"reg_budget\": %d, \"ms\": %.6g, \"default_ms\": %.6g}",
+                     first ? "" : ",", (unsigned long long)kv.first, c.flags, c.small_sites, c.tiles_in_flight,
+                     c.reg_budget, c.ms, c.default_ms);
+        first = false;
+    }
+    std::fprintf(f, "\n]}\n");
+    const bool ok = std::fclose(f) == 0 && std::rename(tmp.c_str(), path) == 0;
+    return ok ? PNE_OK : fail(ctx, PNE_ERR_INVALID_ARG, std::string("cannot write ") + path);
+}
+
+pne_status pne_tune_cache_load(pne_ctx *ctx, const char *path, int32_t *n_loaded) {
+    if (!ctx || !path) return fail(ctx, PNE_ERR_INVALID_ARG, "null argument");
+    FILE *f = std::fopen(path, "r");
+    if (!f) return fail(ctx, PNE_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    std::string s;
+    char buf[4096];
+    size_t got;
+    while ((got = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, got);
+    std::fclose(f);
+    if (s.find("\"pne_tune_cache\"") == std::string::npos)
+        return fail(ctx, PNE_ERR_INVALID_ARG, "not a tuning cache file");
+    // every entry is one {...} object with the keys written by pne_tune_cache_save
+    auto field = [](const std::string &obj, const char *key, double *out) {
+        const std::string k = std::string("\"") + key + "\":";
+        const size_t p = obj.find(k);
+        if (p == std::string::npos) return false;
+        char *end = nullptr;
+        *out = std::strtod(obj.c_str() + p + k.size(), &end);
+        return end != obj.c_str() + p + k.size();
+    };
+    int32_t cnt = 0;
+    size_t pos = s.find('[');
+    while (pos != std::string::npos) {
+        const size_t a = s.find('{', pos), e = a == std::string::npos ? a : s.find('}', a);
+        if (a == std::string::npos || e == std::string::npos) break;
+        const std::string obj = s.substr(a, e - a + 1);
+        pos = e + 1;
+        const size_t sp = obj.find("\"signature\":");
+        if (sp == std::string::npos) return fail(ctx, PNE_ERR_INVALID_ARG, "tuning cache entry without a signature");
+        const size_t q = obj.find('"', sp + 12);
+        const uint64_t sig = std::strtoull(obj.c_str() + q + 1, nullptr, 16);
+        double v[6];
+        const char *keys[6] = {"flags", "small_sites", "tiles_in_flight", "reg_budget", "ms", "default_ms"};
+        for (int k = 0; k < 6; ++k)
+            if (!field(obj, keys[k], &v[k])) return fail(ctx, PNE_ERR_INVALID_ARG, "malformed tuning cache entry");
+        pne_ctx::Tuned c;
+        c.flags = (uint32_t)v[0] & (PNE_FLAG_GRAPH | PNE_FLAG_SEPARATE_REGAUGE);
+        c.small_sites = (int32_t)v[1];
+        c.tiles_in_flight = (int32_t)v[2];
+        c.reg_budget = (int32_t)v[3];
+        c.ms = v[4];
+        c.default_ms = v[5];
+        if (c.small_sites < 0 || c.tiles_in_flight < 0 || c.tiles_in_flight > 2 || c.reg_budget < 0 ||
+            c.reg_budget > 1)
+            return fail(ctx, PNE_ERR_INVALID_ARG, "tuning cache entry out of range");
+        ctx->tuned[sig] = c;
+        ++cnt;
+    }
+    if (n_loaded) *n_loaded = cnt;
     return PNE_OK;
 }
 
@@ -800,6 +924,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     if (!(opt->bp_damping >= 0.0 && opt->bp_damping < 1.0))
         return fail(ctx, PNE_ERR_INVALID_ARG, "bp_damping must be in [0, 1)");
     if (!(opt->err_bound >= 0.0)) return fail(ctx, PNE_ERR_INVALID_ARG, "err_bound must be >= 0");
+    if (opt->small_sites < 0 || opt->tiles_in_flight < 0 || opt->tiles_in_flight > 2 || opt->reg_budget < 0 ||
+        opt->reg_budget > 1)
+        return fail(ctx, PNE_ERR_INVALID_ARG, "bad tile options");
     if (fixed && (opt->flags & (PNE_FLAG_PROFILE | PNE_FLAG_GRAPH | PNE_FLAG_AUTOTUNE)))
         return fail(ctx, PNE_ERR_INVALID_ARG, "profiling, graph replay and autotuning allocate: not available here");
     for (int i = 0; i < n; ++i)
@@ -908,7 +1035,14 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<int> fsite_list;
     std::vector<BpTile> loop_tiles, wide_tiles;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
-    const size_t fused_budget = 79 * 1024 / 8;  // doubles of dynamic LDS per persistent block (two per CU)
+    // doubles of dynamic LDS per persistent block: two blocks per CU, or one
+    // with the 256-VGPR kernel
+    const size_t fused_budget = (opt->reg_budget ? 155 : 79) * 1024 / 8;
+    const int small_sites = opt->small_sites > 0 ? opt->small_sites : kPSmallSites;
+    auto tiles_for = [&](int dim, int rank) {
+        return (opt->tiles_in_flight > 0 && bp_persistent_tiles_tunable(dim, rank)) ? opt->tiles_in_flight
+                                                                                     : bp_persistent_tiles_in_flight(dim, rank);
+    };
     size_t bp_lds = 0;
     std::vector<char> net_rg_inline(n, 0);  // gauge + slices built by the persistent block
     std::vector<char> net_fused(n, 0);      // BP in a persistent block
@@ -978,7 +1112,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         for (auto &kv : groups) {
             const SiteRec &r0 = sites[kv.second[0]];
             const int spw = bp_persistent_sites_per_tile(r0.dim[0], r0.rank);
-            if (spw > 0) pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0]));
+            if (spw > 0)
+                pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0], tiles_for(r0.dim[0], r0.rank)));
         }
         // two-colouring of the site graph for the red-black schedule
         std::vector<int> colour(g.n_sites, -1);
@@ -1023,12 +1158,13 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         }
         // the in-block term sum needs 153 doubles of the waves' scratch (8 x 32, or 2 x 80 in the
         // two-wave blocks of small networks)
-        rg_scratch = std::max(rg_scratch, g.n_sites <= kPSmallSites ? 80 : 32);
-        if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2) <= fused_budget)
+        const bool small = g.n_sites <= small_sites;
+        rg_scratch = std::max(rg_scratch, small ? 80 : 32);
+        if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2, small) <= fused_budget)
             pscratch = rg_scratch;
         else
             rg_inline = false;
-        const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2);
+        const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2, small);
         // damped BP runs launch by launch (Jacobi, the damped mix in the per-launch normalisation)
         if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT) && opt->bp_damping == 0.0) {
             FusedNet f;
@@ -1052,7 +1188,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                     fg.dc = r0.dim[0];
                     fg.rank = r0.rank;
                     fg.spw = bp_persistent_sites_per_tile(fg.dc, fg.rank);
-                    fg.nt = bp_persistent_tiles_in_flight(fg.dc, fg.rank);
+                    fg.nt = tiles_for(fg.dc, fg.rank);
                     fg.color = c;
                     fg.list_off = (int)fsite_list.size() - f.list_begin;
                     for (int gs : kv.second)
@@ -1292,12 +1428,14 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         for (size_t k = 0; k < fused.size(); ++k) fused[k].prio = work[k] >= 2 * light ? 1 : 0;
     }
     // large networks first, then the small ones (their own launch, 128-thread blocks)
-    std::stable_partition(fused.begin(), fused.end(), [](const FusedNet &f) { return f.n_sites > kPSmallSites; });
+    std::stable_partition(fused.begin(), fused.end(),
+                          [small_sites](const FusedNet &f) { return f.n_sites > small_sites; });
     size_t lds_large = 0, lds_small = 0;
     int n_small = 0;
     for (const FusedNet &f : fused) {
-        const size_t need = bp_persistent_lds_doubles(f.msg_size, f.n_sites, f.scratch, f.colors == 2 ? 1 : 2) * 8;
-        if (f.n_sites <= kPSmallSites) {
+        const bool small = f.n_sites <= small_sites;
+        const size_t need = bp_persistent_lds_doubles(f.msg_size, f.n_sites, f.scratch, f.colors == 2 ? 1 : 2, small) * 8;
+        if (small) {
             lds_small = std::max(lds_small, need);
             ++n_small;
         } else {
@@ -1378,6 +1516,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.cluster_lds = cl_lds;
     db.precision = prec;
     db.damping = opt->bp_damping;
+    db.reg_budget = opt->reg_budget;
 #define AL(bytes, field, type) ap.buffer((bytes), &db.field)
     AL(sizeof(NetState) * n, state, NetState *);
     AL(sizeof(double) * msg, msg0, double *);

@@ -62,6 +62,10 @@ class Options(ctypes.Structure):
         ("reserved0", ctypes.c_int32),
         ("bp_damping", ctypes.c_double),
         ("err_bound", ctypes.c_double),
+        ("small_sites", ctypes.c_int32),
+        ("tiles_in_flight", ctypes.c_int32),
+        ("reg_budget", ctypes.c_int32),
+        ("reserved1", ctypes.c_int32),
     ]
 
 
@@ -226,6 +230,8 @@ _PROTOS = {
     "pne_batch_paths": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.c_int32]),
     "pne_autotune": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                     ctypes.POINTER(Options), ctypes.c_int32, ctypes.POINTER(Options)]),
+    "pne_tune_cache_save": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p]),
+    "pne_tune_cache_load": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_char_p, ctypes.POINTER(ctypes.c_int32)]),
     "pne_server_options_default": (ctypes.c_int, [ctypes.POINTER(ServerOptions)]),
     "pne_server_create": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerOptions),
                                          ctypes.POINTER(ctypes.c_void_p)]),
@@ -398,7 +404,8 @@ PATH_PERSISTENT, PATH_BLOCK_GAUGE, PATH_BLOCK_TERMS = 1, 2, 4
 
 
 def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
-             fused_regauge=True, graph=False, autotune=False, mode="loop", damping=0.0, err_bound=1e-5):
+             fused_regauge=True, graph=False, autotune=False, mode="loop", damping=0.0, err_bound=1e-5,
+             small_sites=0, tiles_in_flight=0, reg_budget=0):
     """profile: False, True (every kernel) or a list of KERNEL_NAMES to time."""
     lib = load_library()
     o = Options()
@@ -416,6 +423,9 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.mode = MODES[mode] if isinstance(mode, str) else int(mode)
     o.bp_damping = float(damping)
     o.err_bound = float(err_bound)
+    o.small_sites = int(small_sites)
+    o.tiles_in_flight = int(tiles_in_flight)
+    o.reg_budget = int(reg_budget)
     return o
 
 
@@ -458,26 +468,40 @@ class Context:
 
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
               profile=False, persistent=True, jacobi=False, fused_regauge=True, graph=False,
-              autotune=False, mode="loop", damping=0.0, err_bound=1e-5) -> "Batch":
+              autotune=False, mode="loop", damping=0.0, err_bound=1e-5, small_sites=0, tiles_in_flight=0,
+              reg_budget=0) -> "Batch":
         """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
         in the persistent kernel even on bipartite networks; fused_regauge=
         False: gauge + slices in their own launch; graph=True: replay a
         captured HIP graph; autotune=True: pick the variant by measurement
         (cached per batch signature in the context); mode="full": every
         configuration of degree <= K, dangling ones included; damping: BP
-        damping in [0, 1); err_bound: reduced-precision warning bound."""
+        damping in [0, 1); err_bound: reduced-precision warning bound;
+        small_sites, tiles_in_flight, reg_budget: the persistent kernel's tile
+        shape (see pne_options)."""
         return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi,
-                     fused_regauge, graph, autotune, mode, damping, err_bound)
+                     fused_regauge, graph, autotune, mode, damping, err_bound, small_sites, tiles_in_flight,
+                     reg_budget)
 
     def autotune(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, trials=3) -> dict:
-        """Time the execution variants for this batch; returns the chosen flags."""
+        """Time the tile-shape variants for this batch; returns the choice."""
         o = _options(K, precision, tol, max_iter, 0)
         best = Options()
         arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
         _check(self.lib, self.lib.pne_autotune(self.handle, arr, len(nets), ctypes.byref(o), int(trials),
                                                ctypes.byref(best)), self.handle)
         return {"graph": bool(best.flags & PNE_FLAG_GRAPH),
-                "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags)}
+                "fused_regauge": not bool(best.flags & PNE_FLAG_SEPARATE_REGAUGE), "flags": int(best.flags),
+                "small_sites": int(best.small_sites), "tiles_in_flight": int(best.tiles_in_flight),
+                "reg_budget": int(best.reg_budget)}
+
+    def tune_cache_save(self, path: str):
+        _check(self.lib, self.lib.pne_tune_cache_save(self.handle, os.fsencode(path)), self.handle)
+
+    def tune_cache_load(self, path: str) -> int:
+        n = ctypes.c_int32(0)
+        _check(self.lib, self.lib.pne_tune_cache_load(self.handle, os.fsencode(path), ctypes.byref(n)), self.handle)
+        return int(n.value)
 
     def rank_expand(self, nets, Lx: int, Ly: int, partitions, rank: int = 2, form: str = "combinatorial",
                     alpha: float = 0.8, ramp_sweeps: int = 10, max_sweeps: int = 2000, tol: float = 1e-12):
@@ -606,11 +630,11 @@ class Batch:
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
                  persistent=True, jacobi=False, fused_regauge=True, graph=False, autotune=False, mode="loop",
-                 damping=0.0, err_bound=1e-5):
+                 damping=0.0, err_bound=1e-5, small_sites=0, tiles_in_flight=0, reg_budget=0):
         self.ctx = ctx
         self.nets = list(nets)
         self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge,
-                            graph, autotune, mode, damping, err_bound)
+                            graph, autotune, mode, damping, err_bound, small_sites, tiles_in_flight, reg_budget)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),

@@ -58,6 +58,7 @@ int main(void) {
   P(pne_network_desc, site_rank) P(pne_network_desc, site_data)
   P(pne_options, bp_tol) P(pne_options, bp_max_iter) P(pne_options, flags)
   P(pne_options, mode) P(pne_options, bp_damping) P(pne_options, err_bound)
+  P(pne_options, small_sites) P(pne_options, tiles_in_flight) P(pne_options, reg_budget)
   P(pne_result, log_abs) P(pne_result, bp_iters) P(pne_result, bp_residual)
   P(pne_result, n_config_terms) P(pne_result, open_values) P(pne_result, open_capacity)
   P(pne_result, dangling_max) P(pne_result, term_err_est)

@@ -419,10 +419,16 @@ def test_graph_replays_equal_eager(ctx):
         np.testing.assert_array_equal(a[2].open_values, b[2].open_values)
 
 
-def test_autotune_picks_a_variant_and_keeps_results(ctx):
+def test_autotune_picks_a_variant_and_keeps_results(ctx, tmp_path):
+    """The tuner times the persistent kernel's tile shapes (block threshold,
+    tiles in flight, register budget) and graph replay; the choice is cached
+    in the context and in a JSON file, and every variant gives the same
+    results to rounding."""
+    import json
+
     nets = [ctx.network(P.random_2d(8, 8, 4, "uniform01", seed=80 + i)) for i in range(8)]
     choice = ctx.autotune(nets, K=6, precision="fp64", trials=2)
-    assert set(choice) == {"graph", "fused_regauge", "flags"}
+    assert set(choice) == {"graph", "fused_regauge", "flags", "small_sites", "tiles_in_flight", "reg_budget"}
     again = ctx.autotune(nets, K=6, precision="fp64", trials=2)  # cached
     assert again == choice
     tuned = ctx.batch(nets, K=6, precision="fp64", autotune=True).run_arrays()
@@ -431,6 +437,33 @@ def test_autotune_picks_a_variant_and_keeps_results(ctx):
     for i, n in enumerate([P.random_2d(8, 8, 4, "uniform01", seed=80 + i) for i in range(2)]):
         ref = O.pne_contract(n, 6)
         assert abs(tuned["log_abs"][i] - ref.log_abs) < 1e-10
+    # every tile variant, run directly, agrees with the default
+    for ss in (0, 256):
+        for nt in (0, 1, 2):
+            for rb in (0, 1):
+                v = ctx.batch(nets, K=6, precision="fp64", small_sites=ss, tiles_in_flight=nt,
+                              reg_budget=rb).run_arrays()
+                assert np.max(np.abs(v["log_abs"] - plain["log_abs"])) < 1e-12, (ss, nt, rb)
+                assert (v["status"] == 0).all()
+    # the JSON cache: saved, then loaded into a fresh context, gives the same choice
+    import paper_2512_10910_amd as pne
+
+    path = str(tmp_path / "tune.json")
+    ctx.tune_cache_save(path)
+    with open(path) as fh:
+        doc = json.load(fh)
+    assert doc["pne_tune_cache"] == 1 and len(doc["entries"]) >= 1
+    e = doc["entries"][0]
+    assert e["ms"] > 0 and e["default_ms"] >= e["ms"]
+    c2 = pne.Context(0)
+    assert c2.tune_cache_load(path) == len(doc["entries"])
+    n2 = [c2.network(P.random_2d(8, 8, 4, "uniform01", seed=80 + i)) for i in range(8)]
+    assert c2.autotune(n2, K=6, precision="fp64", trials=2) == choice
+    with open(path, "w") as fh:
+        fh.write("{not a cache}")
+    with pytest.raises(pne.PNEError):
+        c2.tune_cache_load(path)
+    c2.close()
 
 
 def test_two_outstanding_launches(ctx):
