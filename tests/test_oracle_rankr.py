@@ -95,3 +95,33 @@ def test_blocking_preserves_the_partition_function():
         lz = O.ising_bruteforce_logz(16, [(int(u), int(v)) for (u, _, v, _) in P.ising_2d(4, 4, beta).bonds], beta)
         s, lg = O.exact_log_contract(P.ising_blocked_lattice(4, 2, beta))
         assert s == 1 and abs(lg - lz) < 1e-12
+
+
+# ----------------------------------------------------------------------------
+# the paper's own setting (Sec. V.B): 12 x 12 Ising coarse-grained into 3 x 3
+# blocks of 4 x 4 spins, bond dimension chi = 16
+
+
+@pytest.mark.parametrize("beta", [0.5, 0.6, 0.8])
+def test_chi16_blocked_ising_rank2_within_the_papers_bound(beta):
+    """Below T_c (beta_c = 0.4407), rank-2 projectors on every bond (linear
+    form) reach epsilon < 1e-7 against the exact value, as Sec. V.B reports
+    for rank 2 at all temperatures; rank 1 on the four centre bonds misses
+    by more than 1% (two BP sectors).  The blocked network is exact (the
+    blocking contracts only inner bonds), so its exact contraction is the
+    144-spin partition function."""
+    net = P.ising_blocked_lattice(12, 4, beta)
+    assert all(d == 16 for t in net.tensors for d in t.shape)
+    wp = R.weight_passing(net)
+    assert wp[4]
+    s0, lg0 = _z0(net)
+    # the gauge change divides by singular values that fall far below the
+    # largest one deep below T_c, so the identity holds to a conditioning
+    # floor (8e-9 in ln Z at beta = 0.8) rather than to rounding
+    s, lg = R.gauged_value(net, wp)
+    assert s == s0 and abs(lg - lg0) < 5e-8
+    every = [[b] for b in range(net.n_bonds)]
+    s2, l2 = R.rank_expansion(net, every, 2, "linear", wp=wp)
+    assert s2 == s0 and abs(math.expm1(l2 - lg0)) < 1e-7
+    s1, l1 = R.rank_expansion(net, P.grid3_single_partitions(net), 1, "linear", wp=wp)
+    assert abs(math.expm1(l1 - lg0)) > 1e-2
