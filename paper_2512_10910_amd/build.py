@@ -10,7 +10,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libpne.so")
-SOURCES = ["bp.hip", "bp_persistent.hip", "kernels.hip", "strips.hip", "rankr.hip", "runtime.cpp", "geometry.cpp", "server.cpp", "noalloc.hip"]
+SOURCES = ["bp.hip", "bp_persistent.hip", "kernels.hip", "strips.hip", "rankr.hip", "runtime.cpp", "geometry.cpp", "server.cpp", "noalloc.hip", "rankr_large.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -14,6 +14,7 @@
 
 #include "gmem.h"
 #include "pne.h"
+#include "rankr.h"
 #include "runtime.h"
 
 namespace pne {
@@ -21,21 +22,10 @@ namespace {
 
 using dev::gld;
 
-constexpr int kRkChi = 4;        // bond dimension
-constexpr int kRkSites = 16;     // sites per network
-constexpr int kRkBonds = 32;
+constexpr int kRkChi = 4;        // bond dimension of the small-chi kernels
 constexpr int kRkSite = kRkChi * kRkChi * kRkChi * kRkChi;  // entries of one site tensor
 constexpr int kRkState = 1024;   // entries of the row-contraction state
 constexpr int kRkWp = 64;        // threads of the weight-passing block
-
-struct RkGeo {
-    int32_t n_sites, n_bonds, chi, Lx, Ly;
-    int32_t rank[kRkSites];
-    int32_t bu[kRkBonds], bul[kRkBonds], bv[kRkBonds], bvl[kRkBonds];
-    int32_t leg_bond[kRkSites][4];  // bond on each leg slot (-1: none)
-    int32_t dir_slot[kRkSites][4];  // slot of direction (-x, +x, -y, +y), -1 if absent
-    int32_t toff[kRkSites + 1];     // packed offsets of the site tensors (chi^rank each)
-};
 
 __device__ inline int tsize(int rank, int chi) {
     int n = 1;
@@ -69,6 +59,12 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
                     be += __shfl_xor(be, o, 64);
                     ga += __shfl_xor(ga, o, 64);
                 }
+                // one lane's sums for the whole wave: the butterfly's can differ
+                // in the last bit between lanes, enough to flip the rotation's
+                // sign on tied column norms
+                al = __shfl(al, 0, 64);
+                be = __shfl(be, 0, 64);
+                ga = __shfl(ga, 0, 64);
                 if (fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0) continue;
                 rotated = 1;
                 const double zeta = (be - al) / (2.0 * ga);
@@ -376,6 +372,8 @@ __global__ void __launch_bounds__(256) k_lattice_terms(const RkGeo *__restrict__
     }
 }
 
+}  // namespace
+
 // Per network: sum_t sign_t v_t exp(log_t - ref) in FP64, plus the
 // weight-passing log-scale.
 __global__ void k_rank_combine(const double *__restrict__ terms, const int8_t *__restrict__ sgn, int n_terms,
@@ -400,6 +398,8 @@ __global__ void k_rank_combine(const double *__restrict__ terms, const int8_t *_
     r.log_scale = log_all[net];
     res[net] = r;
 }
+
+namespace {
 
 // Gather the networks' site tensors into the padded layout [net][site][kRkSite].
 __global__ void k_rank_gather(const double *const *__restrict__ src, const int *__restrict__ sizes, int n_sites,
@@ -452,10 +452,15 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
     const int chi = dims.empty() ? 0 : dims[0];
     for (int d : dims)
         if (d != chi) return ctx_fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: bond dimensions differ");
-    if (chi < 1 || chi > kRkChi) return ctx_fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: bond dimension above 4");
+    // chi <= 4: the one-wave kernels below; chi 8 or 16: the MFMA path (rankr_large.hip)
+    const bool large = chi > kRkChi;
+    if (chi < 1 || (large && !rank_large_supported(chi, Lx, Ly)))
+        return ctx_fail(ctx, PNE_ERR_UNSUPPORTED,
+                        "unsupported: bond dimension above 4 needs chi in {8, 16}, Lx >= 2, chi^(Lx-1) a multiple "
+                        "of 16 and chi^(Lx+1) <= 65536");
     int ncol = 1;
     for (int x = 0; x <= Lx; ++x) ncol *= chi;
-    if (ncol > kRkState) return ctx_fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: chi^(Lx+1) above 1024");
+    if (!large && ncol > kRkState) return ctx_fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: chi^(Lx+1) above 1024");
     for (int i = 1; i < n; ++i)
         if (!same_geometry(nets[0], nets[i])) return ctx_fail(ctx, PNE_ERR_INVALID_ARG, "networks differ in geometry");
     const int nb = (int)bu.size();
@@ -537,6 +542,7 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
             ++n_terms;
         }
     }
+    if (large) return rank_expand_large(ctx, nets, n, geo, ops, sgn, n_terms, opt, results);
     hipStream_t s = ctx_stream(ctx);
     // device buffers in one allocation
     std::vector<const double *> src((size_t)n * n_sites);

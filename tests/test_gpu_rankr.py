@@ -105,3 +105,74 @@ def test_rank_errors(ctx):
     with pytest.raises(pne.PNEError) as e:
         ctx.rank_expand([big], 3, 3, [[0]])
     assert e.value.status == -2
+
+
+# ----------------------------------------------------------------------------
+# the paper's bond dimensions: chi = 16 (12 x 12 Ising in 3 x 3 blocks of
+# 4 x 4 spins, Sec. V.B) and chi = 8, on the MFMA term kernel
+
+
+def _every_bond(net):
+    return [[b] for b in range(net.n_bonds)]
+
+
+@pytest.mark.parametrize("make,label", [
+    (lambda b: P.ising_blocked_lattice(12, 4, b), "ising12_chi16"),
+    (lambda b: P.ising_blocked_lattice(9, 3, b), "ising9_chi8"),
+])
+@pytest.mark.parametrize("beta", [0.3, 0.5, 0.6, 0.8])
+def test_large_chi_rank_expansion_matches_oracle(ctx, make, label, beta):
+    raw = make(beta)
+    chi = raw.tensors[0].shape[0]
+    net = ctx.network(raw)
+    wp = R.weight_passing(raw)
+    s0, lg0 = O.exact_log_contract(raw)
+    # Each bond update is a change of gauge (Eq. (C3)): the gauged network's
+    # value is the exact one.  The oracle's drift from it is its own rounding
+    # (SVDs of cores whose singular values span the whole FP64 range at
+    # chi = 16), so the comparison allows for it; the GPU is held to the exact
+    # value at full rank.
+    drift = abs(R.gauged_value(raw, wp)[1] - lg0)
+    tol = 1e-8 + 2.0 * drift
+    full = ctx.rank_expand([net], 3, 3, [[0]], rank=chi, form="linear")
+    print(f"{label} beta={beta}: oracle gauge drift {drift:.2e}, gpu full rank err {abs(full['log_abs'][0] - lg0):.2e}")
+    assert full["status"][0] == 0 and full["sign"][0] == s0
+    assert abs(full["log_abs"][0] - lg0) <= 1e-9
+    for r, form, parts in ((2, "linear", _every_bond(raw)), (1, "linear", P.grid3_single_partitions(raw)),
+                           (2, "combinatorial", P.grid3_single_partitions(raw))):
+        out = ctx.rank_expand([net], 3, 3, parts, rank=r, form=form)
+        s, lg = R.rank_expansion(raw, parts, r, form, wp=wp)
+        d = abs(out["log_abs"][0] - lg)
+        print(f"{label} chi={chi} beta={beta} r={r} {form}: gpu {out['log_abs'][0]:.15f} oracle {lg:.15f} "
+              f"|d|={d:.2e} sweeps {out['sweeps'][0]}/{wp[3]} exact err {abs(lg - lg0):.2e}", flush=True)
+        assert out["status"][0] == 0 and out["sign"][0] == s
+        assert d <= tol, (d, tol)
+    # rank 2 on every bond: the paper's epsilon < 1e-7 below T_c
+    if beta >= 0.5:
+        out = ctx.rank_expand([net], 3, 3, _every_bond(raw), rank=2, form="linear")
+        assert abs(math.expm1(out["log_abs"][0] - lg0)) < 1e-7
+
+
+def test_large_chi_random_network_and_batch(ctx):
+    """chi = 8 random tensors (U[-1+bias, 1+bias], bias 1): a batch of four
+    networks, each against the oracle; rank chi gives the exact value."""
+    raws = [P.small_network(3, 3, "random", 8, seed=400 + i) for i in range(4)]
+    nets = [ctx.network(x) for x in raws]
+    parts = P.grid3_multi_partitions(raws[0])
+    out = ctx.rank_expand(nets, 3, 3, parts, rank=3, form="combinatorial")
+    for i, raw in enumerate(raws):
+        s, lg = R.rank_expansion(raw, parts, 3, "combinatorial")
+        assert out["status"][i] == 0 and out["sign"][i] == s
+        assert abs(out["log_abs"][i] - lg) <= 1e-8
+    full = ctx.rank_expand(nets[:1], 3, 3, parts, rank=8)
+    s0, lg0 = O.exact_log_contract(raws[0])
+    assert full["sign"][0] == s0 and abs(full["log_abs"][0] - lg0) < 1e-9
+
+
+def test_large_chi_envelope(ctx):
+    import paper_2512_10910_amd as pne
+
+    raw = P.small_network(3, 3, "random", 6, seed=1)  # chi 6: neither path
+    with pytest.raises(pne.PNEError) as e:
+        ctx.rank_expand([ctx.network(raw)], 3, 3, [[0]])
+    assert e.value.status == -2
