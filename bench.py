@@ -36,6 +36,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "PNE terms/s and networks/s at <=1e-5 rel err vs FP64 oracle; p50/p99 latency"
 HBM_PEAK_GBS = 8000.0
+FP64_MFMA_PEAK_TFLOPS = 78.6  # dense FP64 matrix-core peak
 
 
 def site_colours(net):
@@ -340,6 +341,67 @@ def rank_bench(pne, P, n: int = 4096):
     for x in nets:
         x.close()
     ctx.close()
+
+
+def rank_terms_flops(chi: int, Lx: int, Ly: int) -> int:
+    """Algorithmic FP64 flops of one term of the bond-dimension-8/16 path: the
+    lattice contracted row by row, site (x, y) absorbed as a dense GEMM of
+    chi^(Lx-1) other-column rows by its present incoming legs (-x, -y) by its
+    present outgoing legs (+x, +y), 2 flops per multiply-add."""
+    tot = 0
+    for y in range(Ly):
+        for x in range(Lx):
+            k = (chi if x > 0 else 1) * (chi if y > 0 else 1)
+            n = (chi if x < Lx - 1 else 1) * (chi if y < Ly - 1 else 1)
+            tot += 2 * chi ** (Lx - 1) * k * n
+    return tot
+
+
+def rank_large_bench(pne, P, n: int = 256, reps: int = 3) -> dict:
+    """Rank-r projectors at the paper's bond dimension (Sec. V.B): n 12x12
+    Ising lattices blocked into 3x3 sites of 4x4 spins (chi = 16), beta spread
+    over [0.5, 0.9] (below T_c), rank 2, the four single-index partitions of
+    the centre's bonds in the combinatorial form (Eq. (7), 15 terms): the
+    phase device times (HIP events), networks/s, the term kernel's FP64
+    matrix-core rate against its roofline, and sampled errors against the
+    exact contraction."""
+    import torch
+
+    import oracle as O
+
+    betas = np.linspace(0.5, 0.9, n)
+    raws = [P.ising_blocked_lattice(12, 4, float(b)) for b in betas]
+    ctx = pne.Context(0)
+    nets = [ctx.network(x) for x in raws]
+    parts = P.grid3_single_partitions(raws[0])
+    n_terms = 2 ** len(parts) - 1
+    ctx.rank_expand(nets[:4], 3, 3, parts, rank=2)
+    best = None
+    for _ in range(reps):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        out = ctx.rank_expand(nets, 3, 3, parts, rank=2, profile=True)
+        ms = (time.perf_counter() - t0) * 1e3
+        ph = ctx.rank_last_times()
+        if best is None or ms < best[0]:
+            best = (ms, ph, out)
+    ms, ph, out = best
+    samples = [0, n // 2, n - 1]
+    errs = [abs(float(out["log_abs"][i]) - O.exact_log_contract(raws[i])[1]) for i in samples]
+    flops = rank_terms_flops(16, 3, 3) * n_terms * n
+    tf = flops / (ph["terms"] * 1e-3) / 1e12 if ph["terms"] > 0 else 0.0
+    for x in nets:
+        x.close()
+    ctx.close()
+    return {"workload": "12x12 Ising in 3x3 blocks (chi=16), beta in [0.5, 0.9], rank-2 weight-passing projectors, "
+                        "four centre-bond partitions, Eq. (7) (15 terms), fp64",
+            "networks": n, "ms": round(ms, 2), "networks_per_s": round(n / (ms * 1e-3), 1),
+            "phase_ms": {k: round(v, 3) for k, v in ph.items()}, "mean_sweeps": float(out["sweeps"].mean()),
+            "status_min": int(out["status"].min()), "status_max": int(out["status"].max()),
+            "terms_roofline": {"bound": "mfma", "achieved": round(tf, 2), "peak": FP64_MFMA_PEAK_TFLOPS,
+                               "unit": "TFLOP/s", "frac": round(tf / FP64_MFMA_PEAK_TFLOPS, 4),
+                               "alg_flops_per_term": rank_terms_flops(16, 3, 3)},
+            "abs_err_lnZ_vs_exact_samples": errs}
 
 
 def _cpu_worker(job):
@@ -656,6 +718,8 @@ def main():
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
     ap.add_argument("--workloads", action="store_true",
                     help="instead: the other workloads at batch scale with per-kernel rooflines")
+    ap.add_argument("--rank-large", type=int, default=0, metavar="N",
+                    help="instead: only the chi = 16 rank-r workload (12x12 Ising, 3x3 blocks) on N lattices")
     ap.add_argument("--rank", type=int, default=0, metavar="N",
                     help="instead: only the rank-r weight-passing workload on N lattices")
     ap.add_argument("--strips", type=int, default=0, metavar="L",
@@ -674,7 +738,7 @@ def main():
     # the CPU oracle baseline first: worker processes forked before anything
     # touches the GPU
     cpu = None
-    default_run = not (args.workloads or args.strips or args.rank or args.profile_run)
+    default_run = not (args.workloads or args.strips or args.rank or args.rank_large or args.profile_run)
     if default_run and args.cpu_sample > 0:
         cpu = cpu_baseline(args.K, max(1, args.cpu_sample // 8), args.nets)
         print(f"bench: cpu baseline {cpu['value']} networks/s on {cpu['cores']} cores", file=sys.stderr, flush=True)
@@ -692,12 +756,16 @@ def main():
         workloads_bench(pne, P, max(1, min(args.steps, 5)))
         strips_bench(pne, P)
         rank_bench(pne, P)
+        print(json.dumps(rank_large_bench(pne, P)), flush=True)
         return
     if args.strips:
         strips_bench(pne, P, L=args.strips)
         return
     if args.rank:
         rank_bench(pne, P, n=args.rank)
+        return
+    if args.rank_large:
+        print(json.dumps(rank_large_bench(pne, P, n=args.rank_large)), flush=True)
         return
 
     if args.copy_calibration:
@@ -893,6 +961,8 @@ def main():
             print("bench: beyond-MALL batch done", file=sys.stderr, flush=True)
             out["other_configs"] = other_configs(pne, P, max(3, args.steps // 4))
             print("bench: other configurations done", file=sys.stderr, flush=True)
+            out["rank_chi16"] = rank_large_bench(pne, P, n=256, reps=2)
+            print("bench: chi = 16 rank-r workload done", file=sys.stderr, flush=True)
         except Exception as e:  # report, keep the throughput line
             out["other_configs_error"] = repr(e)
     if args.serving > 0 and not args.profile_run:

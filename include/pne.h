@@ -560,8 +560,11 @@ pne_status pne_strip_expand(pne_ctx *ctx, const double *A, int32_t chi, const pn
  *
  * Envelope: every network in the call has the same geometry, a closed
  * Lx x Ly lattice with sites numbered x + Lx y, bonds between lattice
- * neighbours only, one bond dimension chi <= 4, Lx Ly <= 16,
- * chi^(Lx+1) <= 1024, 1..16 partitions.  Networks are read in place (device
+ * neighbours only, one bond dimension chi, Lx Ly <= 16, 1..16 partitions;
+ * either chi <= 4 and chi^(Lx+1) <= 1024 (one wave per network), or
+ * chi in {8, 16}, Lx >= 2, chi^(Lx-1) a multiple of 16 and
+ * chi^(Lx+1) <= 65536 (a block per network for weight passing, the terms on
+ * the FP64 matrix cores); anything else is UNSUPPORTED.  Networks are read in place (device
  * copies made by pne_network_create).  Device memory is allocated and freed
  * by the call; it returns when done.  Per network: status (SINGULAR when a
  * singular value vanished; WARN_BP_NOT_CONVERGED when weight passing hit
@@ -574,7 +577,8 @@ typedef struct {
     int32_t ramp_sweeps; /* sweeps over which a ramps up to alpha (10)     */
     int32_t max_sweeps;  /* sweep cap (2000)                               */
     double tol;          /* largest weight change to stop (1e-12)          */
-    int32_t reserved[4];
+    int32_t profile;     /* != 0: time the phases (pne_rank_last_times) (0) */
+    int32_t reserved[3];
 } pne_rank_options;
 
 typedef struct {
@@ -593,6 +597,15 @@ pne_status pne_rank_options_default(pne_rank_options *opt);
 pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, int32_t n, int32_t Lx, int32_t Ly,
                            int32_t n_partitions, const int32_t *part_begin, const int32_t *part_bond,
                            const pne_rank_options *opt, pne_rank_result *results);
+
+/* Device time of each phase of the last pne_rank_expand call on this context
+ * that ran with opt->profile != 0, in milliseconds, from HIP events recorded
+ * on the context stream between the launches: ms[0] gathering the site
+ * tensors, ms[1] weight passing, ms[2] the dense site matrices (bond
+ * dimension 8 and 16 only, else 0), ms[3] the expansion's terms, ms[4] their
+ * signed sum.  Writes n <= 5 entries (INVALID_ARG otherwise); all zero when
+ * the last call was not profiled or failed. */
+pne_status pne_rank_last_times(pne_ctx *ctx, double *ms, int32_t n);
 
 #ifdef __cplusplus
 }

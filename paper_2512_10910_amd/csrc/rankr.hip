@@ -429,11 +429,18 @@ extern "C" pne_status pne_rank_options_default(pne_rank_options *opt) {
     return PNE_OK;
 }
 
+extern "C" pne_status pne_rank_last_times(pne_ctx *ctx, double *ms, int32_t n) {
+    if (!ctx || !ms || n < 0 || n > 5) return ctx_fail(ctx, PNE_ERR_INVALID_ARG, "need ctx, ms and 0 <= n <= 5");
+    for (int k = 0; k < n; ++k) ms[k] = ctx_rank_times(ctx)[k];
+    return PNE_OK;
+}
+
 extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, int32_t n, int32_t Lx, int32_t Ly,
                                       int32_t n_partitions, const int32_t *part_begin, const int32_t *part_bond,
                                       const pne_rank_options *opt, pne_rank_result *results) {
     if (!ctx || !nets || n < 1 || !opt || !results || !part_begin || (n_partitions > 0 && !part_bond))
         return ctx_fail(ctx, PNE_ERR_INVALID_ARG, "null or empty argument");
+    for (int k = 0; k < 5; ++k) ctx_rank_times(ctx)[k] = 0.0;
     if (Lx < 1 || Ly < 1 || Lx * Ly > kRkSites)
         return ctx_fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: lattice of more than 16 sites");
     if (n_partitions < 1 || n_partitions > 16)
@@ -542,7 +549,8 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
             ++n_terms;
         }
     }
-    if (large) return rank_expand_large(ctx, nets, n, geo, ops, sgn, n_terms, opt, results);
+    RankTimer timer(opt->profile != 0);
+    if (large) return rank_expand_large(ctx, nets, n, geo, ops, sgn, n_terms, opt, results, timer);
     hipStream_t s = ctx_stream(ctx);
     // device buffers in one allocation
     std::vector<const double *> src((size_t)n * n_sites);
@@ -584,9 +592,11 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
     RK_TRY(hipMemcpyAsync(B + oSizes, sizes.data(), sizes.size() * sizeof(int), hipMemcpyHostToDevice, s));
     RK_TRY(hipMemcpyAsync(B + oOps, ops.data(), ops.size(), hipMemcpyHostToDevice, s));
     RK_TRY(hipMemcpyAsync(B + oSgn, sgn.data(), sgn.size(), hipMemcpyHostToDevice, s));
+    timer.mark(s);
     hipLaunchKernelGGL(k_rank_gather, dim3(n), dim3(256), 0, s, reinterpret_cast<const double *const *>(B + oSrc),
                        reinterpret_cast<const int *>(B + oSizes), n_sites, reinterpret_cast<double *>(B + oT));
     RK_TRY(hipGetLastError());
+    timer.mark(s);
     {
         const size_t lds = (size_t)geo.toff[n_sites] * sizeof(double);
         auto *g = reinterpret_cast<const RkGeo *>(B + oGeo);
@@ -615,19 +625,24 @@ extern "C" pne_status pne_rank_expand(pne_ctx *ctx, pne_network *const *nets, in
         }
     }
     RK_TRY(hipGetLastError());
+    timer.mark(s);
+    timer.mark(s);  // no site-matrix phase at chi <= 4
     hipLaunchKernelGGL(k_lattice_terms, dim3((unsigned)n * n_terms), dim3(256), 0, s,
                        reinterpret_cast<const RkGeo *>(B + oGeo), reinterpret_cast<const double *>(B + oT),
                        reinterpret_cast<const double *>(B + oS), reinterpret_cast<const int8_t *>(B + oOps), n_terms,
                        opt->rank, reinterpret_cast<double *>(B + oTerms));
     RK_TRY(hipGetLastError());
+    timer.mark(s);
     hipLaunchKernelGGL(k_rank_combine, dim3((n + 63) / 64), dim3(64), 0, s, reinterpret_cast<const double *>(B + oTerms),
                        reinterpret_cast<const int8_t *>(B + oSgn), n_terms, n, reinterpret_cast<const double *>(B + oLog),
                        reinterpret_cast<pne_rank_result *>(B + oRes), reinterpret_cast<const int *>(B + oSw),
                        reinterpret_cast<const int *>(B + oSt));
     RK_TRY(hipGetLastError());
+    timer.mark(s);
     RK_TRY(hipMemcpyAsync(results, B + oRes, (size_t)n * sizeof(pne_rank_result), hipMemcpyDeviceToHost, s));
     RK_TRY(hipStreamSynchronize(s));
 #undef RK_TRY
+    timer.read(ctx_rank_times(ctx), 5);
     for (int i = 0; i < n; ++i) {
         if (results[i].status < 0 && st == PNE_OK) st = (pne_status)results[i].status;
         else if (results[i].status > 0 && st == PNE_OK) st = (pne_status)results[i].status;

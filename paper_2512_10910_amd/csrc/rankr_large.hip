@@ -541,16 +541,19 @@ template <int CHI>
 static void launch_large(hipStream_t s, int n, int n_sites, int n_items, int grid, const RkGeo *g, double *T,
                          int64_t net_stride, double *scr, int64_t scr_stride, double *Sw, double *Lg, int *Sp, int *St,
                          double *P, const int8_t *ops, int n_terms, int r, double *st, double *terms,
-                         const pne_rank_options *opt) {
+                         const pne_rank_options *opt, RankTimer &timer) {
     hipLaunchKernelGGL(k_wpl<CHI>, dim3(n), dim3(kLt), 0, s, g, T, net_stride, scr, scr_stride, Sw, Lg, Sp, St,
                        opt->alpha, opt->ramp_sweeps, opt->max_sweeps, opt->tol);
+    timer.mark(s);
     hipLaunchKernelGGL(k_pad_sites<CHI>, dim3((unsigned)n * n_sites), dim3(kLt), 0, s, g, T, net_stride, P);
+    timer.mark(s);
     hipLaunchKernelGGL(k_terms_mfma<CHI>, dim3(grid), dim3(kLt), 0, s, g, P, Sw, ops, n_terms, n_items, r, st, terms);
+    timer.mark(s);
 }
 
 pne_status rank_expand_large(pne_ctx *ctx, pne_network *const *nets, int32_t n, const RkGeo &geo,
                              const std::vector<int8_t> &ops, const std::vector<int8_t> &sgn, int n_terms,
-                             const pne_rank_options *opt, pne_rank_result *results) {
+                             const pne_rank_options *opt, pne_rank_result *results, RankTimer &timer) {
     const int chi = geo.chi, n_sites = geo.n_sites;
     const int64_t net_stride = ((int64_t)geo.toff[n_sites] + 31) & ~int64_t(31);
     const int64_t chi4 = (int64_t)chi * chi * chi * chi;
@@ -596,9 +599,11 @@ pne_status rank_expand_large(pne_ctx *ctx, pne_network *const *nets, int32_t n, 
     RKL_TRY(hipMemcpyAsync(B + oSgn, sgn.data(), sgn.size(), hipMemcpyHostToDevice, s));
     auto *g = reinterpret_cast<const RkGeo *>(B + oGeo);
     auto *T = reinterpret_cast<double *>(B + oT);
+    timer.mark(s);
     hipLaunchKernelGGL(k_gather_large, dim3(n), dim3(kLt), 0, s, reinterpret_cast<const double *const *>(B + oSrc), g,
                        net_stride, T);
     RKL_TRY(hipGetLastError());
+    timer.mark(s);
     auto *scr = reinterpret_cast<double *>(B + oScr);
     auto *Sw = reinterpret_cast<double *>(B + oS);
     auto *Lg = reinterpret_cast<double *>(B + oLog);
@@ -610,18 +615,20 @@ pne_status rank_expand_large(pne_ctx *ctx, pne_network *const *nets, int32_t n, 
     const auto *opd = reinterpret_cast<const int8_t *>(B + oOps);
     if (chi == 8)
         launch_large<8>(s, n, n_sites, n_items, grid, g, T, net_stride, scr, scr_stride, Sw, Lg, Sp, St, P, opd,
-                        n_terms, opt->rank, st, terms, opt);
+                        n_terms, opt->rank, st, terms, opt, timer);
     else
         launch_large<16>(s, n, n_sites, n_items, grid, g, T, net_stride, scr, scr_stride, Sw, Lg, Sp, St, P, opd,
-                         n_terms, opt->rank, st, terms, opt);
+                         n_terms, opt->rank, st, terms, opt, timer);
     RKL_TRY(hipGetLastError());
     hipLaunchKernelGGL(k_rank_combine, dim3((n + 63) / 64), dim3(64), 0, s, terms,
                        reinterpret_cast<const int8_t *>(B + oSgn), n_terms, n, Lg,
                        reinterpret_cast<pne_rank_result *>(B + oRes), Sp, St);
     RKL_TRY(hipGetLastError());
+    timer.mark(s);
     RKL_TRY(hipMemcpyAsync(results, B + oRes, (size_t)n * sizeof(pne_rank_result), hipMemcpyDeviceToHost, s));
     RKL_TRY(hipStreamSynchronize(s));
 #undef RKL_TRY
+    timer.read(ctx_rank_times(ctx), 5);
     pne_status stt = PNE_OK;
     for (int i = 0; i < n; ++i) {
         if (results[i].status < 0 && stt == PNE_OK) stt = (pne_status)results[i].status;

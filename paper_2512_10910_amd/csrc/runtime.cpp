@@ -17,6 +17,7 @@
 #include <vector>
 
 #include "geometry.h"
+#include "rankr.h"
 #include "runtime.h"
 #include "kernels.h"
 #include "pne.h"
@@ -55,6 +56,7 @@ struct pne_ctx {
     std::multimap<uint64_t, PlanEntry> cache;
     std::mutex mu;
     double wall_khz = 100000.0;  // device wall clock rate (ticks per ms)
+    double rank_ms[5] = {0.0, 0.0, 0.0, 0.0, 0.0};  // phases of the last profiled rank expansion
     void *staging = nullptr;     // pinned upload staging, reused by every batch creation
     size_t staging_bytes = 0;
     // Table uploads run on their own stream, so they never wait behind
@@ -616,6 +618,7 @@ bool pne::network_graph(pne_network *net, std::vector<int> *rank, std::vector<in
 const double *pne::network_site_ptr(pne_network *net, int site) { return net->dptr[site]; }
 bool pne::same_geometry(pne_network *a, pne_network *b) { return a->geo->same_as(*b->geo); }
 hipStream_t pne::ctx_stream(pne_ctx *ctx) { return ctx->stream; }
+double *pne::ctx_rank_times(pne_ctx *ctx) { return ctx->rank_ms; }
 int pne::ctx_device(pne_ctx *ctx) { return ctx->device; }
 pne_status pne::ctx_fail(pne_ctx *ctx, pne_status st, const std::string &msg) { return fail(ctx, st, msg); }
 

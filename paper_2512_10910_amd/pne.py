@@ -173,7 +173,8 @@ class RankOptions(ctypes.Structure):
         ("ramp_sweeps", ctypes.c_int32),
         ("max_sweeps", ctypes.c_int32),
         ("tol", ctypes.c_double),
-        ("reserved", ctypes.c_int32 * 4),
+        ("profile", ctypes.c_int32),
+        ("reserved", ctypes.c_int32 * 3),
     ]
 
 
@@ -204,6 +205,7 @@ _PROTOS = {
     "pne_rank_expand": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p), ctypes.c_int32,
                                        ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p,
                                        ctypes.POINTER(RankOptions), ctypes.POINTER(RankResult)]),
+    "pne_rank_last_times": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32]),
     "pne_strip_options_default": (ctypes.c_int, [ctypes.POINTER(StripOptions)]),
     "pne_strip_expand": (ctypes.c_int, [ctypes.c_void_p, _f64p, ctypes.c_int32, ctypes.POINTER(StripOptions),
                                         ctypes.POINTER(StripResult)]),
@@ -504,7 +506,8 @@ class Context:
         return int(n.value)
 
     def rank_expand(self, nets, Lx: int, Ly: int, partitions, rank: int = 2, form: str = "combinatorial",
-                    alpha: float = 0.8, ramp_sweeps: int = 10, max_sweeps: int = 2000, tol: float = 1e-12):
+                    alpha: float = 0.8, ramp_sweeps: int = 10, max_sweeps: int = 2000, tol: float = 1e-12,
+                    profile: bool = False):
         """Rank-r weight-passing projectors and the partitioned expansion on a
         batch of Lx x Ly lattice networks (Sec. V): per network (status,
         sweeps, sign, ln|Z|, log_scale) as a structured array."""
@@ -513,6 +516,7 @@ class Context:
         _check(self.lib, self.lib.pne_rank_options_default(ctypes.byref(opt)))
         opt.rank, opt.form = int(rank), {"combinatorial": 0, "linear": 1}[form]
         opt.alpha, opt.ramp_sweeps, opt.max_sweeps, opt.tol = float(alpha), int(ramp_sweeps), int(max_sweeps), float(tol)
+        opt.profile = 1 if profile else 0
         parts, begin, bonds = _partition_arrays(partitions)
         arr = (ctypes.c_void_p * len(nets))(*[n.handle.value for n in nets])
         res = (RankResult * len(nets))()
@@ -523,6 +527,12 @@ class Context:
         dt = np.dtype([("status", np.int32), ("sweeps", np.int32), ("sign", np.int32), ("pad", np.int32),
                        ("log_abs", np.float64), ("log_scale", np.float64)])
         return np.frombuffer(bytes(res), dtype=dt).copy()
+
+    def rank_last_times(self) -> dict:
+        """Phase device times (ms) of the last rank_expand(profile=True)."""
+        ms = np.zeros(5)
+        _check(self.lib, self.lib.pne_rank_last_times(self.handle, ms.ctypes.data_as(_f64p), 5), self.handle)
+        return dict(zip(("gather", "weight_passing", "site_matrices", "terms", "combine"), ms.tolist()))
 
     def strip_expand(self, A, L: int, two_d: bool = True, bp_tol: float = 1e-14, power_tol: float = 1e-13,
                      power_max_iter: int = 20000, check_every: int = 4, single_site_passes: bool = False) -> dict:

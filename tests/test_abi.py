@@ -209,6 +209,9 @@ def test_rank_and_partition_entry_points_reject_null_arguments(lib):
     begin = (ctypes.c_int32 * 2)(0, 1)
     bond = (ctypes.c_int32 * 1)(0)
     assert lib.pne_rank_expand(None, None, 1, 3, 3, 1, begin, bond, ctypes.byref(opt), res) == -1
+    assert opt.profile == 0
+    ms = (ctypes.c_double * 5)()
+    assert lib.pne_rank_last_times(None, ms, 5) == -1
     assert lib.pne_network_set_partitions(None, 1, begin, bond) == -1
     assert lib.pne_network_set_subpartitions(None, 1, 1, begin, bond) == -1
 
@@ -220,16 +223,18 @@ def test_rank_structs_match_header(tmp_path):
 #include <stddef.h>
 #include "pne.h"
 int main(void) {
-  printf("%zu %zu %zu %zu %zu\n", sizeof(pne_rank_options), sizeof(pne_rank_result),
-         offsetof(pne_rank_options, tol), offsetof(pne_rank_result, log_abs), offsetof(pne_rank_result, log_scale));
+  printf("%zu %zu %zu %zu %zu %zu\n", sizeof(pne_rank_options), sizeof(pne_rank_result),
+         offsetof(pne_rank_options, tol), offsetof(pne_rank_result, log_abs), offsetof(pne_rank_result, log_scale),
+         offsetof(pne_rank_options, profile));
   return 0;
 }
 ''')
     exe = tmp_path / "rank"
     subprocess.check_call(["gcc", "-I", os.path.join(ROOT, "include"), str(src), "-o", str(exe)])
-    a, b, c, d, e = (int(x) for x in subprocess.check_output([str(exe)]).split())
+    a, b, c, d, e, f = (int(x) for x in subprocess.check_output([str(exe)]).split())
     assert a == ctypes.sizeof(B.RankOptions) and b == ctypes.sizeof(B.RankResult)
     assert c == B.RankOptions.tol.offset and d == B.RankResult.log_abs.offset and e == B.RankResult.log_scale.offset
+    assert f == B.RankOptions.profile.offset
 
 
 @pytest.mark.parametrize("shape,K", [((3, 3), 12), ((3, 3), 5), ((2, 4), 10), ((3, 4), 17)])
