@@ -663,12 +663,19 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Three launches, each with the dynamic LDS its tiles need: a network's LDS
+// tiles (tens of KB for large mixed-dimension sites) would otherwise hold
+// every register tile of the sweep to a few blocks per CU.
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s) {
-    if (b.n_narrow_tiles > 0)
-        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s, b.sites,
-                           b.tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.damping);
+    if (b.n_reg_tiles > 0)
+        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, s, b.sites, b.tiles,
+                           b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.damping);
+    if (b.n_narrow_tiles > b.n_reg_tiles)
+        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, s,
+                           b.sites, b.tiles + b.n_reg_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
+                           b.damping);
     if (b.n_tiles > b.n_narrow_tiles)
-        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(b.n_tiles - b.n_narrow_tiles), dim3(kBpThreads), b.bp_lds, s,
+        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(b.n_tiles - b.n_narrow_tiles), dim3(kBpThreads), b.wide_lds, s,
                            b.sites, b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol,
                            max_iter, b.damping);
     return hipGetLastError();

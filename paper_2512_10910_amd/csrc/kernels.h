@@ -14,9 +14,10 @@ struct DeviceBatch {
     int n_sites = 0;
     const BpTile *tiles = nullptr;      // tiles swept by the per-sweep kernels
     int n_tiles = 0;
-    int n_narrow_tiles = 0;             // tiles[0, n_narrow_tiles): every shape but the wide ones;
-                                        // the rest: register tiles of the wide shapes (rank 4 at
-                                        // D = 5, 6; rank 6 at D = 3)
+    int n_reg_tiles = 0;                // tiles[0, n_reg_tiles): register tiles (dynamic LDS reg_lds);
+    int n_narrow_tiles = 0;             // then up to n_narrow_tiles the LDS tiles (bp_lds); the
+                                        // rest: register tiles of the wide shapes (rank 4 at
+                                        // D = 5, 6; rank 6 at D = 3; wide_lds)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel: the large ones,
     int n_fused = 0;                    // then the n_fused_small small ones (two-wave blocks)
@@ -32,7 +33,9 @@ struct DeviceBatch {
     int n_init_sites = 0;
     const int *init_nets = nullptr;     // networks whose state k_init resets (non-persistent networks)
     int n_init_nets = 0;
-    size_t bp_lds = 0;             // dynamic LDS of the sweep kernel
+    size_t bp_lds = 0;             // dynamic LDS of the sweep kernel's LDS tiles
+    size_t reg_lds = 0;            // ... of its register tiles (their raw outgoing messages)
+    size_t wide_lds = 0;           // ... of the wide-shape register tiles
     NetState *state = nullptr;
     int n_nets = 0;
     // buffers

@@ -1036,7 +1036,11 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<FusedNet> fused;
     std::vector<FusedGroup> fgroups;
     std::vector<int> fsite_list;
-    std::vector<BpTile> loop_tiles, wide_tiles;
+    // per-launch sweep tiles in three launches, each with its own dynamic LDS:
+    // register tiles, LDS tiles, register tiles of the wide shapes
+    std::vector<BpTile> reg_tiles, lds_tiles, wide_tiles;
+    std::vector<size_t> tile_need;  // dynamic LDS bytes of each entry of tiles
+    size_t reg_lds = 0, wide_lds = 0;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     // doubles of dynamic LDS per persistent block: two blocks per CU, or one
     // with the 256-VGPR kernel
@@ -1061,7 +1065,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         }
         const int tile_begin = (int)tiles.size();
         bool all_reg = g.n_open == 0;
-        size_t net_lds = 0;
         for (auto &kv : groups) {
             const SiteRec &r0 = sites[kv.second[0]];
             int nos = 0;
@@ -1099,8 +1102,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 for (int j = 0; j < t.n_sites; ++j) tile_sites.push_back(kv.second[k + j]);
                 const size_t need = t.reg ? (size_t)t.n_sites * nos * 8
                                           : bp_tile_lds_doubles(t.n_sites, r0.size, nos, last, maxd) * 8;
-                net_lds = std::max(net_lds, need);
                 tiles.push_back(t);
+                tile_need.push_back(need);
             }
         }
         // persistent path: every shape group on the register path, LDS fits
@@ -1205,10 +1208,18 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             net_fused[i] = 1;
         } else {
             for (size_t t = tile_begin; t < tiles.size(); ++t) {
-                const bool wide = tiles[t].reg && bp_reg_sites_per_tile(tiles[t].dc, tiles[t].rank) == 0;
-                (wide ? wide_tiles : loop_tiles).push_back(tiles[t]);
+                const BpTile &tt = tiles[t];
+                if (tt.reg && bp_reg_sites_per_tile(tt.dc, tt.rank) == 0) {
+                    wide_tiles.push_back(tt);
+                    wide_lds = std::max(wide_lds, tile_need[t]);
+                } else if (tt.reg) {
+                    reg_tiles.push_back(tt);
+                    reg_lds = std::max(reg_lds, tile_need[t]);
+                } else {
+                    lds_tiles.push_back(tt);
+                    bp_lds = std::max(bp_lds, tile_need[t]);
+                }
             }
-            bp_lds = std::max(bp_lds, net_lds);
         }
     }
 
@@ -1411,6 +1422,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     ArenaPlan ap;
 #define UP(vec, field) ap.upload(vec, &db.field)
     UP(sites, sites);
+    const int n_reg = (int)reg_tiles.size();
+    std::vector<BpTile> loop_tiles(std::move(reg_tiles));
+    loop_tiles.insert(loop_tiles.end(), lds_tiles.begin(), lds_tiles.end());
     const int n_narrow = (int)loop_tiles.size();
     loop_tiles.insert(loop_tiles.end(), wide_tiles.begin(), wide_tiles.end());
     UP(loop_tiles, tiles);
@@ -1508,6 +1522,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_sites = (int)sites.size();
     db.n_tiles = (int)loop_tiles.size();
     db.n_narrow_tiles = n_narrow;
+    db.n_reg_tiles = n_reg;
+    db.reg_lds = reg_lds;
+    db.wide_lds = wide_lds;
     db.n_fused = (int)fused.size();
     db.fused_lds = lds_large;
     db.fused_lds_small = lds_small;
