@@ -49,8 +49,18 @@ struct DeviceBatch {
     size_t regauge_lds = 0;
     const int *rg_tiles = nullptr;  // register-path tiles (indices into all_tiles) for the regauge
     int n_rg_tiles = 0;
-    const int *rg_sites = nullptr;  // sites regauged one per block (open or mixed-dimension sites)
-    int n_rg_sites = 0;
+    const int *rg_wide = nullptr;   // register tiles of one site whose shape holds 5..16 values
+    int n_rg_wide = 0;              // per lane (indices into all_tiles), regauged by k_regauge_wide,
+    static constexpr int kRgWideShapes = 4;  // grouped by shape (dim * 8 + rank)
+    int n_rg_wide_groups = 0;
+    int rg_wide_begin[kRgWideShapes + 1] = {};
+    int rg_wide_shape[kRgWideShapes] = {};
+    const int *rg_sites = nullptr;  // sites regauged one per block (open or mixed-dimension sites),
+    int n_rg_sites = 0;             // sorted by size and launched in groups, each with its own LDS
+    static constexpr int kRgGroups = 4;
+    int n_rg_groups = 0;
+    int rg_group_begin[kRgGroups + 1] = {};
+    size_t rg_group_lds[kRgGroups] = {};
     // clusters
     const ClassDesc *classes = nullptr;
     const StepDesc *steps = nullptr;
@@ -107,6 +117,17 @@ int bp_persistent_sites_per_tile(int dim, int rank);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 // shapes the register-path regauge handles (all legs of dimension dim)
 bool regauge_reg_supported(int dim, int rank);
+// dynamic LDS (doubles) of the per-site regauge of r: two tensor buffers and
+// a d x d transform per gauged slot
+inline size_t regauge_site_lds_doubles(const SiteRec &r) {
+    size_t n = 2 * (size_t)r.size;
+    for (int l = 0; l < r.rank; ++l)
+        if (!((r.open_mask >> l) & 1)) n += (size_t)r.dim[l] * (size_t)r.dim[l];
+    return n;
+}
+// shapes of the one-site register regauge (k_regauge_wide), and its sites per tile
+bool regauge_wide_supported(int dim, int rank);
+int regauge_wide_sites(int dim, int rank);
 // doubles of the per-wavefront LDS transform table of a register regauge tile
 int regauge_table_doubles(int dim, int rank);
 hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s);

@@ -29,8 +29,8 @@ constexpr int kClThreads = 256;
 constexpr int kCbThreads = 256;
 
 
-// Per site (one block): apply the gauge of every bond slot (mode products in
-// LDS), then divide by the vacuum factor z'_v = T'[0,...,0] (closed sites) or
+// Per site (one block): build the gauge of every bond slot, apply them (mode
+// products in LDS), then divide by the vacuum factor z'_v = T'[0,...,0] (closed sites) or
 // by the largest magnitude of the vacuum vector (sites with open legs), and
 // store the result in the slice precision.  ln|z'| and its sign are kept in
 // FP64; their sum over sites is ln|Z_BP|.
@@ -65,54 +65,73 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
                                                         double *__restrict__ site_log, int *__restrict__ site_sign,
                                                         double *__restrict__ vac, NetState *st) {
     const int gsite = rg_sites[blockIdx.x];
-    const SiteRec r = sites[gsite];
     extern __shared__ double lds[];
-    __shared__ double s_x[kMaxDim * kMaxDim];
     __shared__ double s_norm;
     __shared__ int s_ok;
+    // the site record and the slot transforms' offsets in LDS: indexed by
+    // slot at run time, they would otherwise live in scratch
+    __shared__ SiteRec s_rec;
+    __shared__ int xoff[kMaxRank];
     const int tid = threadIdx.x;
+    if (tid < (int)(sizeof(SiteRec) / 4))
+        reinterpret_cast<int *>(&s_rec)[tid] = gld(reinterpret_cast<const int *>(sites + gsite) + tid);
+    __syncthreads();
+    const SiteRec &r = s_rec;
+    if (tid == 0) {
+        int o = 0;
+        for (int l = 0; l < r.rank; ++l) {
+            xoff[l] = o;
+            if (!((r.open_mask >> l) & 1)) o += r.dim[l] * r.dim[l];
+        }
+    }
     const int size = r.size;
     double *b0 = lds;
     double *b1 = lds + size;
+    double *xt = lds + 2 * size;  // the slot transforms, d_l x d_l each (regauge_site_lds_doubles)
     for (int e = tid; e < size; e += kRgThreads) b0[e] = gld(r.t + e);
+    __syncthreads();  // xoff
+    // every slot's transform at once (one column per thread), so the message
+    // reads of all slots are in flight together with the tensor's
     const double *mb = st[r.net].parity ? msg1 : msg0;
-    for (int l = 0; l < r.rank; ++l) {
+    for (int it = tid; it < r.rank * kMaxDim; it += kRgThreads) {
+        const int l = it / kMaxDim, k = it - l * kMaxDim;
         const int d = r.dim[l];
-        if (!((r.open_mask >> l) & 1)) {
-            const bool vs = (r.vside_mask >> l) & 1;
-            const double *pin = mb + r.msg_off + r.moff[l];
-            const double *pout = mb + r.dst[l];
-            const double *pa = vs ? pout : pin;
-            const double *pc = vs ? pin : pout;
-            __syncthreads();
-            for (int k = tid; k < d; k += kRgThreads) {  // one column of X per thread
-                const LegGauge g = leg_gauge_setup(pa, pc, d);
-                if (k == 0 && !g.ok) atomicMin(&st[r.net].status, -4);
-                for (int i = 0; i < d; ++i) s_x[i * d + k] = leg_gauge_x(g, vs, i, k, pa[i], pc[i], pa[k], pc[k]);
-            }
-            __syncthreads();
-            const int sl = r.stride[l];
-            switch (d) {
-                case 2: mode_product_fibers<2>(b0, b1, s_x, size, sl); break;
-                case 3: mode_product_fibers<3>(b0, b1, s_x, size, sl); break;
-                case 4: mode_product_fibers<4>(b0, b1, s_x, size, sl); break;
-                case 5: mode_product_fibers<5>(b0, b1, s_x, size, sl); break;
-                case 6: mode_product_fibers<6>(b0, b1, s_x, size, sl); break;
-                default:
-                    for (int e = tid; e < size; e += kRgThreads) {
-                        const int k = (e / sl) % d;
-                        const int base = e - k * sl;
-                        double acc = 0.0;
-                        for (int i = 0; i < d; ++i) acc = fma(b0[base + i * sl], s_x[i * d + k], acc);
-                        b1[e] = acc;
-                    }
-            }
-            double *t = b0;
-            b0 = b1;
-            b1 = t;
-        }
+        if (k >= d || ((r.open_mask >> l) & 1)) continue;
+        const bool vs = (r.vside_mask >> l) & 1;
+        const double *pin = mb + r.msg_off + r.moff[l];
+        const double *pout = mb + r.dst[l];
+        const double *pa = vs ? pout : pin;
+        const double *pc = vs ? pin : pout;
+        const LegGauge g = leg_gauge_setup(pa, pc, d);
+        if (k == 0 && !g.ok) atomicMin(&st[r.net].status, -4);
+        for (int i = 0; i < d; ++i) xt[xoff[l] + i * d + k] = leg_gauge_x(g, vs, i, k, pa[i], pc[i], pa[k], pc[k]);
     }
     __syncthreads();
+    for (int l = 0; l < r.rank; ++l) {
+        const int d = r.dim[l];
+        if ((r.open_mask >> l) & 1) continue;
+        const double *s_x = xt + xoff[l];
+        const int sl = r.stride[l];
+        switch (d) {
+            case 2: mode_product_fibers<2>(b0, b1, s_x, size, sl); break;
+            case 3: mode_product_fibers<3>(b0, b1, s_x, size, sl); break;
+            case 4: mode_product_fibers<4>(b0, b1, s_x, size, sl); break;
+            case 5: mode_product_fibers<5>(b0, b1, s_x, size, sl); break;
+            case 6: mode_product_fibers<6>(b0, b1, s_x, size, sl); break;
+            default:
+                for (int e = tid; e < size; e += kRgThreads) {
+                    const int k = (e / sl) % d;
+                    const int base = e - k * sl;
+                    double acc = 0.0;
+                    for (int i = 0; i < d; ++i) acc = fma(b0[base + i * sl], s_x[i * d + k], acc);
+                    b1[e] = acc;
+                }
+        }
+        __syncthreads();
+        double *t = b0;
+        b0 = b1;
+        b1 = t;
+    }
     if (tid == 0) {
         double nv;
         int sg = 1;
@@ -180,6 +199,28 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
     auto site_of = [ts](int j) { return ts[j]; };
     regauge_reg_any<S, false>(tl.dc, tl.rank, tl.n_sites, tl.net, site_of, sites, msg, slices, site_log, site_sign,
                               &st[tl.net].status, s_xg);
+}
+
+// Register-path regauge of the shapes whose lead legs hold 5 to 16 values per
+// lane (rank 3 at D = 5, 6; rank 5 at D = 3, 4), one site per wavefront.  The
+// persistent kernel keeps to at most 4 values per lane for its registers;
+// these kernels run alone, one per shape (80-110 VGPRs).  Rank 4 at D = 5, 6
+// and rank 6 at D = 3 (25-36 values per lane) would need every register of
+// the SIMD lane and still spill, so they stay on the per-site LDS kernel.
+template <int D, int R, typename S>
+__global__ void __launch_bounds__(64) k_regauge_wide(const BpTile *__restrict__ tiles, const int *__restrict__ rg_wide,
+                                                     const SiteRec *__restrict__ sites,
+                                                     const int *__restrict__ tile_sites, const double *msg0,
+                                                     const double *msg1, S *__restrict__ slices,
+                                                     double *__restrict__ site_log, int *__restrict__ site_sign,
+                                                     NetState *st) {
+    const BpTile tl = tiles[rg_wide[blockIdx.x]];
+    __shared__ double s_xg[kRgXgMax];
+    const GlobalMsg msg{st[tl.net].parity ? msg1 : msg0};
+    const int *ts = tile_sites + tl.site_begin;
+    auto site_of = [ts](int j) { return ts[j]; };
+    regauge_reg<D, R, S, 1>(tl.n_sites, tl.net, site_of, sites, msg, slices, site_log, site_sign,
+                            &st[tl.net].status, s_xg);
 }
 
 // Logical block of a physical one so that consecutive logical blocks run on
@@ -592,14 +633,45 @@ bool regauge_reg_supported(int dim, int rank) {
     return rg_ipow(dim, rank - T) <= 4;
 }
 
+bool regauge_wide_supported(int dim, int rank) {
+    switch (dim * 8 + rank) {
+        case 3 * 8 + 5: case 4 * 8 + 5: case 5 * 8 + 3: case 6 * 8 + 3:
+            return true;
+        default:
+            return false;
+    }
+}
+
+int regauge_wide_sites(int dim, int rank) { return regauge_wide_supported(dim, rank) ? regauge_sites_per_tile(dim, rank) : 0; }
+
 template <typename S>
 static void launch_regauge_t(const DeviceBatch &b, hipStream_t s) {
     if (b.n_rg_tiles)
         hipLaunchKernelGGL(k_regauge_tiles<S>, dim3(b.n_rg_tiles), dim3(64), 0, s, b.all_tiles, b.rg_tiles, b.sites,
                            b.tile_sites, b.msg0, b.msg1, (S *)b.slices, b.site_log, b.site_sign, b.state);
-    if (b.n_rg_sites)
-        hipLaunchKernelGGL(k_regauge<S>, dim3(b.n_rg_sites), dim3(kRgThreads), b.regauge_lds, s, b.sites, b.rg_sites,
-                           b.msg0, b.msg1, (S *)b.slices, b.site_log, b.site_sign, b.vac, b.state);
+    // the wide shapes, one launch per shape (rg_wide is grouped by shape)
+    for (int g = 0; g < b.n_rg_wide_groups; ++g) {
+        const int cnt = b.rg_wide_begin[g + 1] - b.rg_wide_begin[g];
+        const int *idx = b.rg_wide + b.rg_wide_begin[g];
+#define PNE_RGW(D_, R_)                                                                                       \
+    case D_ * 8 + R_:                                                                                         \
+        hipLaunchKernelGGL((k_regauge_wide<D_, R_, S>), dim3(cnt), dim3(64), 0, s, b.all_tiles, idx, b.sites,  \
+                           b.tile_sites, b.msg0, b.msg1, (S *)b.slices, b.site_log, b.site_sign, b.state);      \
+        break;
+        switch (b.rg_wide_shape[g]) {
+            PNE_RGW(3, 5) PNE_RGW(4, 5) PNE_RGW(5, 3) PNE_RGW(6, 3)
+            default: break;
+        }
+#undef PNE_RGW
+    }
+    // one launch per size group: the dynamic LDS is twice the group's largest site
+    for (int g = 0; g < b.n_rg_groups; ++g) {
+        const int cnt = b.rg_group_begin[g + 1] - b.rg_group_begin[g];
+        if (cnt > 0)
+            hipLaunchKernelGGL(k_regauge<S>, dim3(cnt), dim3(kRgThreads), b.rg_group_lds[g], s, b.sites,
+                               b.rg_sites + b.rg_group_begin[g], b.msg0, b.msg1, (S *)b.slices, b.site_log,
+                               b.site_sign, b.vac, b.state);
+    }
 }
 
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s) {

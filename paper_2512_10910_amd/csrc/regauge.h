@@ -223,23 +223,26 @@ __device__ inline void regauge_reg(int n_sites, int net, const SiteOf &site_of, 
         if (k * SPT >= n_sites) break;
         const int j = k * SPT + slot;
         const double *X0 = xs + (j < n_sites ? j : 0) * R * D * D;
-        // register (lead) legs
+        // register (lead) legs: fiber by fiber (the D values along the leg),
+        // so only one fiber is held twice
 #pragma unroll
         for (int kl = 0; kl < NLEG; ++kl) {
             const double *X = X0 + kl * D * D;
-            double w[NL];
+            const int stride = rg_ipow(D, NLEG - 1 - kl);
 #pragma unroll
-            for (int q = 0; q < NL; ++q) {
-                const int stride = rg_ipow(D, NLEG - 1 - kl);
-                const int dk = (q / stride) % D;
-                const int q0 = q - dk * stride;
-                double acc = 0.0;
+            for (int f = 0; f < NL / D; ++f) {
+                const int q0 = (f / stride) * D * stride + f % stride;
+                double fib[D];
 #pragma unroll
-                for (int i = 0; i < D; ++i) acc = fma(v[k][q0 + i * stride], X[i * D + dk], acc);
-                w[q] = acc;
+                for (int i = 0; i < D; ++i) fib[i] = v[k][q0 + i * stride];
+#pragma unroll
+                for (int dk = 0; dk < D; ++dk) {
+                    double acc = 0.0;
+#pragma unroll
+                    for (int i = 0; i < D; ++i) acc = fma(fib[i], X[i * D + dk], acc);
+                    v[k][q0 + dk * stride] = acc;
+                }
             }
-#pragma unroll
-            for (int q = 0; q < NL; ++q) v[k][q] = w[q];
         }
         // lane (trailing) legs
 #pragma unroll

@@ -456,7 +456,7 @@ hipError_t timed(pne_batch *b, int kid, F &&fn) {
     const DeviceBatch &db = b->db;
     const bool work = kid == KID_INIT ? (db.n_init_sites > 0 || db.n_init_nets > 0)
                     : kid == KID_FUSED ? db.n_fused > 0
-                    : kid == KID_REGAUGE ? (db.n_rg_tiles > 0 || db.n_rg_sites > 0)
+                    : kid == KID_REGAUGE ? (db.n_rg_tiles > 0 || db.n_rg_wide > 0 || db.n_rg_sites > 0)
                     : kid == KID_CLUSTERS ? db.n_cblocks > 0
                     : kid == KID_COMBINE ? db.n_combine > 0
                     : true;
@@ -968,7 +968,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<SiteRec> sites;
     std::vector<int> net_of_site;
     int64_t msg = 0, sl = 0, vac = 0;
-    size_t max_size = 1;
     b->site_base.resize(n);
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
@@ -1003,7 +1002,6 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 r.vac_off = (int)vac;
                 vac += nopen;
             }
-            max_size = std::max(max_size, (size_t)size);
             msg += mo;
             sl += size;
             sites.push_back(r);
@@ -1415,7 +1413,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     }
 
     // device allocation
-    size_t regauge_lds = 2 * max_size * 8;
+    size_t regauge_lds = 0;
+    for (const SiteRec &r : sites) regauge_lds = std::max(regauge_lds, regauge_site_lds_doubles(r) * 8);
     if (regauge_lds > 150 * 1024) return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: site tensor too large for LDS");
     pne_status st;
     DeviceBatch &db = b->db;
@@ -1468,20 +1467,58 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(fgroups, fgroups);
     UP(fsite_list, fsite_list);
     // regauge work: register tiles without open legs, other sites one per block
-    std::vector<int> rg_tiles, rg_sites;
+    std::vector<int> rg_tiles, rg_wide, rg_sites;
     for (size_t t = 0; t < tiles.size(); ++t) {
         if (net_rg_inline[tiles[t].net]) continue;
         bool open = false;
         for (int j = 0; j < tiles[t].n_sites; ++j) open = open || sites[tile_sites[tiles[t].site_begin + j]].open_mask;
         if (tiles[t].reg && !open && regauge_reg_supported(tiles[t].dc, tiles[t].rank)) {
             rg_tiles.push_back((int)t);
+        } else if (tiles[t].reg && !open && tiles[t].n_sites <= regauge_wide_sites(tiles[t].dc, tiles[t].rank)) {
+            rg_wide.push_back((int)t);
         } else {
             for (int j = 0; j < tiles[t].n_sites; ++j) rg_sites.push_back(tile_sites[tiles[t].site_begin + j]);
         }
     }
+    // the wide-shape regauge, one launch per shape (regauge_wide_supported lists
+    // kRgWideShapes shapes, so the groups fit)
+    std::stable_sort(rg_wide.begin(), rg_wide.end(), [&](int x, int y) {
+        return tiles[x].dc * 8 + tiles[x].rank < tiles[y].dc * 8 + tiles[y].rank;
+    });
+    db.n_rg_wide_groups = 0;
+    for (size_t g0 = 0; g0 < rg_wide.size();) {
+        const int key = tiles[rg_wide[g0]].dc * 8 + tiles[rg_wide[g0]].rank;
+        size_t g1 = g0;
+        while (g1 < rg_wide.size() && tiles[rg_wide[g1]].dc * 8 + tiles[rg_wide[g1]].rank == key) ++g1;
+        db.rg_wide_shape[db.n_rg_wide_groups] = key;
+        db.rg_wide_begin[db.n_rg_wide_groups++] = (int)g0;
+        g0 = g1;
+    }
+    db.rg_wide_begin[db.n_rg_wide_groups] = (int)rg_wide.size();
+    // the per-site regauge in size groups (each up to twice its smallest
+    // site; the last takes the rest), launched with their own LDS
+    std::stable_sort(rg_sites.begin(), rg_sites.end(),
+                     [&](int x, int y) { return regauge_site_lds_doubles(sites[x]) < regauge_site_lds_doubles(sites[y]); });
+    db.n_rg_groups = 0;
+    for (size_t g0 = 0; g0 < rg_sites.size();) {
+        const int gi = db.n_rg_groups++;
+        const size_t lo = regauge_site_lds_doubles(sites[rg_sites[g0]]);
+        size_t g1 = g0, hi = lo;
+        while (g1 < rg_sites.size() &&
+               (gi == DeviceBatch::kRgGroups - 1 || regauge_site_lds_doubles(sites[rg_sites[g1]]) <= 2 * lo)) {
+            hi = std::max(hi, regauge_site_lds_doubles(sites[rg_sites[g1]]));
+            ++g1;
+        }
+        db.rg_group_begin[gi] = (int)g0;
+        db.rg_group_lds[gi] = hi * 8;
+        g0 = g1;
+    }
+    db.rg_group_begin[db.n_rg_groups] = (int)rg_sites.size();
     UP(rg_tiles, rg_tiles);
+    UP(rg_wide, rg_wide);
     UP(rg_sites, rg_sites);
     db.n_rg_tiles = (int)rg_tiles.size();
+    db.n_rg_wide = (int)rg_wide.size();
     db.n_rg_sites = (int)rg_sites.size();
     UP(tile_sites, tile_sites);
     // k_init resets the messages of networks swept launch by launch only
