@@ -117,10 +117,17 @@ int bp_persistent_sites_per_tile(int dim, int rank);
 hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s);
 // shapes the register-path regauge handles (all legs of dimension dim)
 bool regauge_reg_supported(int dim, int rank);
-// dynamic LDS (doubles) of the per-site regauge of r: two tensor buffers and
+// tensor buffers of the per-site regauge of r: one when every gauged leg has
+// dimension <= 6 (fiber-wise products in place), else two
+__host__ __device__ inline int regauge_site_buffers(const SiteRec &r) {
+    for (int l = 0; l < r.rank; ++l)
+        if (!((r.open_mask >> l) & 1) && r.dim[l] > 6) return 2;
+    return 1;
+}
+// dynamic LDS (doubles) of the per-site regauge of r: its tensor buffers and
 // a d x d transform per gauged slot
 inline size_t regauge_site_lds_doubles(const SiteRec &r) {
-    size_t n = 2 * (size_t)r.size;
+    size_t n = (size_t)regauge_site_buffers(r) * (size_t)r.size;
     for (int l = 0; l < r.rank; ++l)
         if (!((r.open_mask >> l) & 1)) n += (size_t)r.dim[l] * (size_t)r.dim[l];
     return n;

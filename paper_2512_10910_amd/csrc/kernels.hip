@@ -37,7 +37,7 @@ constexpr int kCbThreads = 256;
 // One mode product of the staged site tensor along a leg of dimension DD and
 // stride sl: each thread takes whole fibers (the DD entries along the leg),
 // reads them once and writes the DD outputs, with the same summation order
-// as the per-entry form below.
+// as the per-entry form below.  Fibers are disjoint, so b1 may be b0.
 template <int DD>
 __device__ inline void mode_product_fibers(const double *b0, double *b1, const double *s_x, int size, int sl) {
     const int nf = size / DD;
@@ -85,9 +85,12 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
         }
     }
     const int size = r.size;
+    // legs of dimension <= 6 take the fiber-wise product, in place; larger
+    // ones the per-entry form, which needs a second buffer
+    const int nbuf = regauge_site_buffers(r);
     double *b0 = lds;
-    double *b1 = lds + size;
-    double *xt = lds + 2 * size;  // the slot transforms, d_l x d_l each (regauge_site_lds_doubles)
+    double *b1 = lds + (nbuf - 1) * size;
+    double *xt = lds + nbuf * size;  // the slot transforms, d_l x d_l each (regauge_site_lds_doubles)
     for (int e = tid; e < size; e += kRgThreads) b0[e] = gld(r.t + e);
     __syncthreads();  // xoff
     // every slot's transform at once (one column per thread), so the message
