@@ -665,20 +665,36 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
 
 // Three launches, each with the dynamic LDS its tiles need: a network's LDS
 // tiles (tens of KB for large mixed-dimension sites) would otherwise hold
-// every register tile of the sweep to a few blocks per CU.
+// every register tile of the sweep to a few blocks per CU.  Where the batch
+// has a side stream and wide tiles, the register and LDS tiles of the other
+// shapes run on the side stream, beside the wide launch.
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s) {
+    const int n_wide = b.n_tiles - b.n_narrow_tiles;
+    const bool split = b.side != nullptr && n_wide > 0 && b.n_narrow_tiles > 0;
+    hipError_t e = hipSuccess;
+    hipStream_t ns = s;
+    if (split) {
+        if ((e = hipEventRecord(b.fork, s)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(b.side, b.fork, 0)) != hipSuccess) return e;
+        ns = b.side;
+    }
     if (b.n_reg_tiles > 0)
-        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, s, b.sites, b.tiles,
+        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, ns, b.sites, b.tiles,
                            b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.damping);
     if (b.n_narrow_tiles > b.n_reg_tiles)
-        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, s,
+        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, ns,
                            b.sites, b.tiles + b.n_reg_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
                            b.damping);
-    if (b.n_tiles > b.n_narrow_tiles)
-        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(b.n_tiles - b.n_narrow_tiles), dim3(kBpThreads), b.wide_lds, s,
-                           b.sites, b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol,
-                           max_iter, b.damping);
-    return hipGetLastError();
+    if (n_wide > 0)
+        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(n_wide), dim3(kBpThreads), b.wide_lds, s, b.sites,
+                           b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
+                           b.damping);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (split) {
+        if ((e = hipEventRecord(b.join, b.side)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(s, b.join, 0)) != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t launch_close(const DeviceBatch &b, int k_last, double tol, hipStream_t s) {

@@ -36,6 +36,11 @@ struct DeviceBatch {
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel's LDS tiles
     size_t reg_lds = 0;            // ... of its register tiles (their raw outgoing messages)
     size_t wide_lds = 0;           // ... of the wide-shape register tiles
+    // Where a sweep has wide tiles and others, the others (few, or short) run
+    // on the context's side stream beside the wide launch: fork and join
+    // events of the batch (null for a batch that must not create them).
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     NetState *state = nullptr;
     int n_nets = 0;
     // buffers

@@ -64,6 +64,7 @@ struct pne_ctx {
     // up_done instead, and the staging buffer is rewritten only once the
     // previous upload has completed.
     hipStream_t up_stream = nullptr;
+    hipStream_t side_stream = nullptr;  // a batch's short BP launches, beside its wide-tile launch
     hipEvent_t up_done = nullptr;
     bool up_pending = false;
     // batch signature -> the variant pne_autotune chose (PNE_FLAG_AUTOTUNE)
@@ -513,6 +514,11 @@ void free_batch(pne_batch *b) {
         if (e) (void)hipEventDestroy(e);
         e = nullptr;
     }
+    for (hipEvent_t *e : {&b->db.fork, &b->db.join}) {
+        if (*e) (void)hipEventDestroy(*e);
+        *e = nullptr;
+    }
+    b->db.side = nullptr;
     if (b->graph_exec) (void)hipGraphExecDestroy(b->graph_exec);
     b->graph_exec = nullptr;
     if (b->graph) (void)hipGraphDestroy(b->graph);
@@ -573,7 +579,9 @@ pne_status pne_ctx_create(int device, size_t budget, void *stream, pne_ctx **out
         c->own_stream = true;
     }
     if (hipStreamCreateWithFlags(&c->up_stream, hipStreamNonBlocking) != hipSuccess ||
+        hipStreamCreateWithFlags(&c->side_stream, hipStreamNonBlocking) != hipSuccess ||
         hipEventCreateWithFlags(&c->up_done, hipEventDisableTiming) != hipSuccess) {
+        if (c->side_stream) (void)hipStreamDestroy(c->side_stream);
         if (c->up_stream) (void)hipStreamDestroy(c->up_stream);
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
@@ -589,6 +597,10 @@ pne_status pne_ctx_destroy(pne_ctx *ctx) {
     if (ctx->own_stream) (void)hipStreamDestroy(ctx->stream);
     if (ctx->up_done) (void)hipEventDestroy(ctx->up_done);
     if (ctx->up_stream) (void)hipStreamDestroy(ctx->up_stream);
+    if (ctx->side_stream) {
+        (void)hipStreamSynchronize(ctx->side_stream);
+        (void)hipStreamDestroy(ctx->side_stream);
+    }
     if (ctx->staging) (void)hipHostFree(ctx->staging);
     for (auto &kv : ctx->plan_tables) (void)hipFree(kv.second.dev);
     delete ctx;
@@ -1625,6 +1637,15 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             free_batch(b.get());
             return fail(ctx, PNE_ERR_DEVICE, "event creation failed");
         }
+    }
+    // sweeps with wide and other tiles run the others on the side stream
+    if (!fixed && b->db.n_narrow_tiles > 0 && b->db.n_tiles > b->db.n_narrow_tiles) {
+        if (hipEventCreateWithFlags(&b->db.fork, hipEventDisableTiming) != hipSuccess ||
+            hipEventCreateWithFlags(&b->db.join, hipEventDisableTiming) != hipSuccess) {
+            free_batch(b.get());
+            return fail(ctx, PNE_ERR_DEVICE, "event creation failed");
+        }
+        b->db.side = ctx->side_stream;
     }
     b->h_state_pinned = b->h_state_slot[0];
     b->h_results_pinned = b->h_results_slot[0];
