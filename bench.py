@@ -9,9 +9,10 @@ uniform messages, gauge, slices, clusters, sum) every step.  Tensors are
 resident in device memory before timing; the batch's geometry plan and
 device tables are prepared once (they depend only on the lattice).
 
-Then (unless --serving 0) the serving loop: the serving requests with
-Poisson arrivals at 0.7 x the measured saturated capacity, reporting p50/p99
-latency and networks/s under "serving".
+Then (unless --serving 0) the serving loop on the serving requests: the
+saturated capacity, Poisson arrivals at 0.3, 0.5, 0.7 and 0.9 x that capacity
+(p50/p99 latency and networks/s, the 0.7 point reported at the top of
+"serving"), and a sample of served results against their FP64 form.
 
 Prints one JSON line.  Kernel durations come from HIP events the library
 records on its own stream around each launch during the timed steps.
@@ -162,17 +163,20 @@ def measured_traffic(kernel: str):
     return int(float(v)) if v else None
 
 
-def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth: int = 2):
+def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth: int = 2,
+                  rates=(0.3, 0.5, 0.7, 0.9), n_check: int = 32):
     """Serving requests i = 0..n_req-1 (seed 40000+i): saturated capacity
-    (all submitted at once), then Poisson arrivals (seed 4) at 0.7 x capacity;
-    latency is submit -> result ready, measured by the server."""
+    (all submitted at once), then Poisson arrivals (seed 4) at a sweep of
+    fractions of that capacity (0.7 is the reported point); latency is
+    submit -> result ready, measured by the server.  A sample of n_check
+    served results is compared with the same requests run in FP64."""
     nets = [P.config4_request(i) for i in range(n_req)]
     # requests are marshalled by the client before they arrive (descriptor
     # arrays, one contiguous tensor buffer each); the server copies them at submit
     reqs = [pne.Server.prepare(n, K=K, precision=precision) for n in nets]
     ctx = pne.Context(0)
 
-    def drain(sv, tickets, deadline=300.0):
+    def drain(sv, tickets, keep=None, deadline=300.0):
         left = set(tickets)
         t0 = time.perf_counter()
         while left:
@@ -181,6 +185,8 @@ def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth
                     r = sv.poll(t)
                     if r.status < 0:
                         raise RuntimeError(f"request failed with status {r.status}")
+                    if keep is not None and t in keep:
+                        keep[t] = r
                     left.discard(t)
             if time.perf_counter() - t0 > deadline:
                 raise RuntimeError("serving run did not finish")
@@ -199,23 +205,46 @@ def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth
     sv.close()
     sv = pne.Server(ctx, mem_budget=budget, pipeline_depth=depth, completion_queue=True)
     t0 = time.perf_counter()
-    drain(sv, [sv.submit(r) for r in reqs])
+    tickets = [sv.submit(r) for r in reqs]
+    check_idx = list(range(0, n_req, max(1, n_req // n_check)))[:n_check]
+    kept = {tickets[i]: None for i in check_idx}
+    drain(sv, tickets, kept)
     cap = n_req / (time.perf_counter() - t0)
     sat = sv.stats()
     sv.close()
-    rate = 0.7 * cap
-    arrivals = P.config4_arrivals(n_req, rate)
-    sv = pne.Server(ctx, mem_budget=budget, pipeline_depth=depth, completion_queue=True)
-    tickets = []
-    t0 = time.perf_counter()
-    for i, r in enumerate(reqs):
-        while time.perf_counter() - t0 < arrivals[i]:
-            pass
-        tickets.append(sv.submit(r))
-    drain(sv, tickets)
-    st = sv.stats()
-    sv.close()
+    # accuracy of the served results against the FP64 form of the same requests
+    errs, warned = [], 0
+    ref_nets = [ctx.network(nets[i]) for i in check_idx]
+    ref = ctx.batch(ref_nets, K=K, precision="fp64").run_arrays()
+    for j, i in enumerate(check_idx):
+        r = kept[tickets[i]]
+        warned += int(r.status == 2)
+        errs.append(abs(r.log_abs - float(ref["log_abs"][j])) / max(1.0, abs(float(ref["log_abs"][j]))))
+    for x in ref_nets:
+        x.close()
+    sweep = []
+    for frac in rates:
+        rate = frac * cap
+        arrivals = P.config4_arrivals(n_req, rate)
+        sv = pne.Server(ctx, mem_budget=budget, pipeline_depth=depth, completion_queue=True)
+        tickets = []
+        t0 = time.perf_counter()
+        for i, r in enumerate(reqs):
+            while time.perf_counter() - t0 < arrivals[i]:
+                pass
+            tickets.append(sv.submit(r))
+        drain(sv, tickets)
+        st = sv.stats()
+        sv.close()
+        sweep.append({"fraction_of_capacity": frac, "rate_per_s": round(rate, 1),
+                      "networks_per_s": round(st["networks_per_s"], 1),
+                      "latency_p50_ms": round(st["latency_p50_ms"], 3),
+                      "latency_p99_ms": round(st["latency_p99_ms"], 3),
+                      "latency_mean_ms": round(st["latency_mean_ms"], 3), "batches": st["batches"]})
+        print(f"bench: serving at {frac:.1f} x capacity: p50 {st['latency_p50_ms']:.2f} ms, "
+              f"p99 {st['latency_p99_ms']:.2f} ms", file=sys.stderr, flush=True)
     ctx.close()
+    at07 = next((x for x in sweep if abs(x["fraction_of_capacity"] - 0.7) < 1e-9), sweep[-1])
     return {
         "workload": f"{n_req} serving requests (seed 40000+i: 2D L~U{{4..32}} or 3D L~U{{4..8}}, D~U{{2,3,4}}, "
                     f"U[0,1] or N(1,0.3)), K={K}, {precision} terms, device budget {budget / 1e9:.1f} GB",
@@ -224,12 +253,16 @@ def serving_bench(pne, P, n_req: int, budget: int, precision: str, K: int, depth
         "saturated_host_prep_s": round(sat["prep_s"], 3),
         "saturated_wait_s": round(sat["wait_s"], 3),
         "saturated_prep_split_s": {k: round(sat[k + "_s"], 3) for k in ("upload", "networks", "batch", "launch")},
-        "rate_per_s": round(rate, 1),
-        "networks_per_s": round(st["networks_per_s"], 1),
-        "latency_p50_ms": round(st["latency_p50_ms"], 3),
-        "latency_p99_ms": round(st["latency_p99_ms"], 3),
-        "latency_mean_ms": round(st["latency_mean_ms"], 3),
-        "batches": st["batches"],
+        "rate_per_s": at07["rate_per_s"],
+        "networks_per_s": at07["networks_per_s"],
+        "latency_p50_ms": at07["latency_p50_ms"],
+        "latency_p99_ms": at07["latency_p99_ms"],
+        "latency_mean_ms": at07["latency_mean_ms"],
+        "batches": at07["batches"],
+        "rate_sweep": sweep,
+        "sampled_max_rel_err_log_vs_fp64_form": max(errs) if errs else None,
+        "sampled_requests": len(errs),
+        "sampled_precision_warnings": warned,
     }
 
 
@@ -713,8 +746,8 @@ def main():
     ap.add_argument("--fp64-steps", type=int, default=10, help="steps timed with FP64 terms (0: skip)")
     ap.add_argument("--profile-run", action="store_true", help="short run for rocprofv3 (no checks)")
     ap.add_argument("--no-events", action="store_true", help="time without per-kernel HIP events")
-    ap.add_argument("--serving", type=int, default=1024, metavar="N",
-                    help="also run the serving loop on N requests (Poisson arrivals at 0.7 x capacity); 0: skip")
+    ap.add_argument("--serving", type=int, default=4096, metavar="N",
+                    help="also run the serving loop on N requests (capacity, then a sweep of Poisson arrival rates); 0: skip")
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
     ap.add_argument("--workloads", action="store_true",
                     help="instead: the other workloads at batch scale with per-kernel rooflines")
