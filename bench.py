@@ -376,6 +376,27 @@ def rank_bench(pne, P, n: int = 4096):
     ctx.close()
 
 
+def measured_copy_gbps(torch, mib: int = 1024, reps: int = 5) -> float:
+    """Achieved HBM bandwidth of a plain device copy of `mib` MiB (bytes read
+    plus bytes written over the copy's time, HIP events on torch's stream):
+    the practical ceiling beside the published 8 TB/s."""
+    n = mib * (1 << 20) // 4
+    src = torch.ones(n, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    torch.cuda.synchronize()
+    return 2 * mib * (1 << 20) / (ms * 1e-3) / 1e9
+
+
 def rank_terms_flops(chi: int, Lx: int, Ly: int) -> int:
     """Algorithmic FP64 flops of one term of the bond-dimension-8/16 path: the
     lattice contracted row by row, site (x, y) absorbed as a dense GEMM of
@@ -932,6 +953,12 @@ def main():
         "roofline": roofline,
     }
 
+    if not args.profile_run:
+        bw = measured_copy_gbps(torch)
+        roofline["measured_copy_GBps"] = round(bw, 1)
+        if roofline.get("achieved"):
+            roofline["frac_of_measured_copy"] = round(roofline["achieved"] / bw, 4)
+
     if args.fp64_steps > 0 and not args.profile_run and args.precision != "fp64":
         # the same batch with FP64 term contractions (slices, clusters and
         # sums all FP64), timed the same way: the plain FP64 form
@@ -954,6 +981,29 @@ def main():
             "speedup_of_reduced_precision": round(fms / ms_step, 3),
             "max_rel_err_log_vs_fp64_form": float(d.max()),
             "signs_equal": bool((results["sign"] == r64["sign"]).all()),
+        }
+        # the other reduced precision on the same batch, against the FP64 form
+        other = "bf16" if args.precision == "fp32" else "fp32"
+        ob = ctx.batch(nets, K=args.K, precision=other)
+        for _ in range(args.warmup):
+            ob.run_arrays()
+        torch.cuda.synchronize()
+        o0 = time.perf_counter()
+        for _ in range(args.fp64_steps):
+            ro = ob.run_arrays()
+        torch.cuda.synchronize()
+        o1 = time.perf_counter()
+        ob.close()
+        oms = (o1 - o0) * 1e3 / args.fp64_steps
+        do = np.abs(ro["log_abs"] - r64["log_abs"]) / np.maximum(1.0, np.abs(r64["log_abs"]))
+        st_o = {int(k): int(v) for k, v in zip(*np.unique(ro["status"], return_counts=True))}
+        out[f"{other}_form"] = {
+            "networks_per_s": round(n_nets / (oms * 1e-3), 1),
+            "ms_per_step": round(oms, 4),
+            "steps": args.fp64_steps,
+            "speedup_over_fp64_form": round(fms / oms, 3),
+            "max_rel_err_log_vs_fp64_form": float(do.max()),
+            "status_counts": st_o,
         }
 
     if not args.profile_run:

@@ -49,7 +49,8 @@ typedef enum {
     PNE_ERR_OUT_OF_MEMORY = -3,    /* device allocation failed or budget exceeded */
     PNE_ERR_SINGULAR = -4,         /* a bond overlap a.c ~ 0 or a vacuum factor == 0 */
     PNE_ERR_DEVICE = -5,           /* HIP runtime error or no usable device */
-    PNE_ERR_NOT_READY = -6         /* pne_poll: request still running */
+    PNE_ERR_NOT_READY = -6,        /* pne_poll: request still running */
+    PNE_ERR_CANCELLED = -7         /* pne_poll: the request was cancelled (pne_cancel) */
 } pne_status;
 
 /* pne_options.flags bits */
@@ -450,6 +451,13 @@ pne_status pne_submit(pne_server *server, const pne_network_desc *desc, const pn
  * ticket; with too small an open buffer it returns INVALID_ARG and keeps the
  * result for another poll. */
 pne_status pne_poll(pne_server *server, uint64_t ticket, pne_result *result);
+/* Cancels a request that is still queued (not yet admitted into a batch): it
+ * leaves the queue and finishes at once with PNE_ERR_CANCELLED, which
+ * pne_poll then returns (and pne_server_completed lists it; the statistics
+ * count it as failed, outside the latencies).  PNE_ERR_NOT_READY when the
+ * request is already admitted (it completes normally), INVALID_ARG for an
+ * unknown or finished ticket. */
+pne_status pne_cancel(pne_server *server, uint64_t ticket);
 pne_status pne_server_get_stats(pne_server *server, pne_server_stats *out);
 /* With completion_queue set: moves up to `capacity` tickets of finished
  * requests (success or failure), oldest first, into tickets[] and sets *n to

@@ -27,4 +27,6 @@ from .pne import (  # noqa: F401
     PNE_OK,
     PNE_WARN_BP_NOT_CONVERGED,
     PNE_WARN_PRECISION,
+    PNE_ERR_NOT_READY,
+    PNE_ERR_CANCELLED,
 )

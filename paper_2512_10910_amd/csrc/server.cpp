@@ -571,6 +571,30 @@ pne_status pne_poll(pne_server *sv, uint64_t ticket, pne_result *res) {
     return st;
 }
 
+pne_status pne_cancel(pne_server *sv, uint64_t ticket) {
+    if (!sv) return PNE_ERR_INVALID_ARG;
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        auto it = sv->all.find(ticket);
+        if (it == sv->all.end() || it->second->done) return PNE_ERR_INVALID_ARG;
+        Request *r = it->second.get();
+        auto q = std::find(sv->pending.begin(), sv->pending.end(), r);
+        if (q == sv->pending.end()) return PNE_ERR_NOT_READY;  // admitted: it runs to completion
+        sv->pending.erase(q);
+        r->res = pne_result{};
+        r->res.status = PNE_ERR_CANCELLED;
+        r->done = true;
+        r->t_done = Clock::now();
+        ++sv->failed;
+        ++sv->completed;
+        if (sv->so.completion_queue) sv->done_q.push_back(r->ticket);
+        r->data.clear();
+        r->data.shrink_to_fit();
+    }
+    sv->cv.notify_all();  // the queue's head may have changed (memory admission)
+    return PNE_OK;
+}
+
 pne_status pne_server_get_stats(pne_server *sv, pne_server_stats *out) {
     if (!sv || !out) return PNE_ERR_INVALID_ARG;
     std::lock_guard<std::mutex> lk(sv->mu);

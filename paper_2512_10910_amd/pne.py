@@ -27,6 +27,7 @@ PNE_ERR_OUT_OF_MEMORY = -3
 PNE_ERR_SINGULAR = -4
 PNE_ERR_DEVICE = -5
 PNE_ERR_NOT_READY = -6
+PNE_ERR_CANCELLED = -7
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 MODES = {"loop": 0, "full": 1, "cumulant": 2}
@@ -241,6 +242,7 @@ _PROTOS = {
     "pne_submit": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(NetworkDesc), ctypes.POINTER(Options),
                                   ctypes.POINTER(ctypes.c_uint64)]),
     "pne_poll": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64, ctypes.POINTER(ResultStruct)]),
+    "pne_cancel": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_uint64]),
     "pne_server_get_stats": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ServerStats)]),
     "pne_server_completed": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_uint64), ctypes.c_int32,
                                             ctypes.POINTER(ctypes.c_int32)]),
@@ -858,6 +860,15 @@ class Server:
         ov = buf[: r.n_open_values].copy().reshape(shape) if (m and r.n_open_values) else None
         return Result(r.status, r.sign, r.log_abs, r.log_abs_bp, r.bp_iters, r.bp_residual, r.n_cluster_terms,
                       r.n_config_terms, ov, r.dangling_max, r.term_err_est)
+
+    def cancel(self, ticket: int) -> bool:
+        """Cancel a queued request: True when it left the queue (its poll then
+        reports PNE_ERR_CANCELLED), False when it is already running."""
+        st = self.lib.pne_cancel(self.handle, ctypes.c_uint64(ticket))
+        if st == PNE_ERR_NOT_READY:
+            return False
+        _check(self.lib, st)
+        return True
 
     def stats(self) -> dict:
         st = ServerStats()

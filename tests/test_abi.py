@@ -212,6 +212,7 @@ def test_rank_and_partition_entry_points_reject_null_arguments(lib):
     assert opt.profile == 0
     ms = (ctypes.c_double * 5)()
     assert lib.pne_rank_last_times(None, ms, 5) == -1
+    assert lib.pne_cancel(None, ctypes.c_uint64(1)) == -1
     assert lib.pne_network_set_partitions(None, 1, begin, bond) == -1
     assert lib.pne_network_set_subpartitions(None, 1, 1, begin, bond) == -1
 

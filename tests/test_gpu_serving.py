@@ -126,3 +126,36 @@ def test_completion_queue_with_prepared_requests(pne):
         assert r.status == a.status and r.log_abs == a.log_abs
     sv.close()
     ctx.close()
+
+
+def test_cancel_queued_requests(pne):
+    """Requests still queued when cancelled finish with PNE_ERR_CANCELLED;
+    the others complete as if alone."""
+    nets = [P.config4_request(i) for i in SMALL_REQUESTS[:12]]
+    alone = _alone(pne, nets, 6, "fp32")
+    ctx = pne.Context(0)
+    # one request per batch, one batch in flight: the tail waits in the queue
+    sv = pne.Server(ctx, max_batch=1, pipeline_depth=1, completion_queue=True)
+    reqs = [pne.Server.prepare(n, K=6, precision="fp32") for n in nets]
+    tickets = [sv.submit(r) for r in reqs]
+    cancelled = {t for t in tickets[6:] if sv.cancel(t)}
+    assert cancelled, "no request was still queued"
+    seen = []
+    t0 = time.time()
+    while len(seen) < len(tickets):
+        seen += sv.completed()
+        assert time.time() - t0 < 120, "server did not finish"
+        time.sleep(0.001)
+    assert sorted(seen) == sorted(tickets)
+    for t, a in zip(tickets, alone):
+        r = sv.poll(t)
+        if t in cancelled:
+            assert r.status == pne.PNE_ERR_CANCELLED
+        else:
+            assert r.status == a.status and r.log_abs == a.log_abs
+    with pytest.raises(pne.PNEError):
+        sv.cancel(tickets[0])  # finished and polled: unknown ticket
+    st = sv.stats()
+    assert st["failed"] == len(cancelled) and st["completed"] == len(tickets)
+    sv.close()
+    ctx.close()
