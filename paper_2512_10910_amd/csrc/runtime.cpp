@@ -1704,6 +1704,12 @@ pne_status pne_batch_launch(pne_batch *b) {
     const int n = db.n_nets;
     int sweep = 0;
     int chunk = b->opt.bp_check_every > 0 ? b->opt.bp_check_every : b->first_chunk;
+    // residual of each running network at the previous check: with the
+    // current one it gives the network's geometric rate, and from that the
+    // sweeps it still needs, so the next chunk ends near the last network's
+    // convergence instead of a fixed doubling past it
+    std::vector<double> prev_r(db.n_tiles > 0 ? n : 0, -1.0);
+    int prev_last = -1;
     while (db.n_tiles > 0 && sweep < max_iter) {
         const int kk = std::min(chunk, max_iter - sweep);
         for (int j = 0; j < kk; ++j, ++sweep)
@@ -1712,7 +1718,8 @@ pne_status pne_batch_launch(pne_batch *b) {
         HIP_TRY(ctx, hipStreamSynchronize(s));
         const int last = sweep - 1;
         bool all_done = true;
-        for (int i = 0; i < n && all_done; ++i) {
+        int need = 0;  // largest predicted remaining sweeps (0: no running network has a rate yet)
+        for (int i = 0; i < n; ++i) {
             const NetState &st = b->h_state_pinned[i];
             if (st.stop >= 0 || st.status < 0) continue;
             const double r = [&] {
@@ -1720,10 +1727,19 @@ pne_status pne_batch_launch(pne_batch *b) {
                 std::memcpy(&d, &st.res_acc[last % 3], sizeof d);
                 return d;
             }();
-            if (!(r <= tol)) all_done = false;
+            if (r <= tol) continue;
+            all_done = false;
+            if (prev_last >= 0 && prev_r[i] > 0.0 && r > 0.0 && r < prev_r[i]) {
+                const double lq = std::log(r / prev_r[i]) / (double)(last - prev_last);  // log rate per sweep
+                const double left = std::log(tol / r) / lq;
+                if (std::isfinite(left)) need = std::max(need, (int)std::ceil(left));
+            }
+            prev_r[i] = r;
         }
+        prev_last = last;
         if (all_done) break;
-        if (b->opt.bp_check_every <= 0) chunk = std::min(chunk * 2, 16);
+        if (b->opt.bp_check_every <= 0)
+            chunk = need > 0 ? std::min(need + 1, 32) : std::min(chunk * 2, 16);
     }
     // the close kernel finishes per-launch networks only (persistent blocks
     // record their own final state)
