@@ -673,30 +673,33 @@ def workloads_bench(pne, P, steps: int):
 
     cases = [
         ("4x4 Ising, beta_i = 0.44(1 + 0.01 u_i), K=4, fp64",
-         lambda: [P.ising_2d(4, 4, float(b)) for b in P.config1_betas(65536)], 4, "fp64", True),
+         lambda: [P.ising_2d(4, 4, float(b)) for b in P.config1_betas(65536)], 4, "fp64", True, None, 500),
         ("6x6x6 Ising, beta in {0.18, 0.2217, 0.26} x 1365 each, K=6, fp32",
-         lambda: [P.config3_ising_network(b) for b in (0.18, 0.2217, 0.26) for _ in range(1365)], 6, "fp32", True),
+         lambda: [P.config3_ising_network(b) for b in (0.18, 0.2217, 0.26) for _ in range(1365)], 6, "fp32", True,
+         None, 500),
+        # a random gauge makes the uniform start a generic one: BP then also
+        # has to damp the slow non-singlet modes (about 0.95 per step), and
+        # the copies take 500-750 red-black steps to reach 1e-13
         ("12x12 AKLT double layer, random bond gauge per copy (seed 3000+i), K=8, fp32",
-         lambda: [P.config3_aklt_network(gauge_seed=3000 + i) for i in range(4096)], 8, "fp32", True),
+         lambda: [P.config3_aklt_network(gauge_seed=3000 + i) for i in range(4096)], 8, "fp32", True, None, 1500),
         ("32x32 D=6 U[0,1], two open dim-2 legs d = 1..8 apart, x16 each, K=8, fp32",
-         lambda: [P.config5_network(d) for d in range(1, 9)] * 16, 8, "fp32", False),
+         lambda: [P.config5_network(d) for d in range(1, 9)] * 16, 8, "fp32", False, None, 500),
     ]
     # user partitions (Eqs. (4), (7)): complete expansion over the partitions
     parted = [
         ("3x3 U[0,2] D=4 (seed 50000+i), six multi-index partitions, Eq. (7) complete (K=12), fp64",
          lambda: [P.small_network(3, 3, "random", 4, seed=50000 + i) for i in range(8192)], 12, "fp64", True,
-         P.grid3_multi_partitions),
+         P.grid3_multi_partitions, 500),
         ("3x2 double loop U[0,2] D=6 (seed 60000+i), three vertical partitions, Eq. (4) complete (K=7), fp64",
          lambda: [P.small_network(3, 2, "random", 6, seed=60000 + i) for i in range(16384)], 7, "fp64", True,
-         P.double_loop_partitions),
+         P.double_loop_partitions, 500),
         ("3x4 U[0,2] D=4 (seed 70000+i), five lines with the two 3x3 principal terms refined by six partitions "
          "(recursive, Sec. IV.A), complete (K=17), fp64",
          lambda: [P.small_network(3, 4, "random", 4, seed=70000 + i) for i in range(8192)], 17, "fp64", True,
-         P.grid3x4_recursive_partitions),
+         P.grid3x4_recursive_partitions, 500),
     ]
     sb = {"fp64": 8, "fp32": 4, "bf16": 2}
-    for label, make, K, prec, check, *rest in [c + (None,) for c in cases] + parted:
-        parts_of = rest[0]
+    for label, make, K, prec, check, parts_of, max_iter in cases + parted:
         nets_in = make()
         ctx = pne.Context(0)
         nets = [ctx.network(n) for n in nets_in]
@@ -707,7 +710,7 @@ def workloads_bench(pne, P, steps: int):
                 n.set_partitions(parts)
                 for sx, inner in subs.items():
                     n.set_subpartitions(sx, inner)
-        b = ctx.batch(nets, K=K, precision=prec, profile=True)
+        b = ctx.batch(nets, K=K, precision=prec, max_iter=max_iter, profile=True)
         b.run_arrays()
         b.kernel_times(reset=True)
         torch.cuda.synchronize()
@@ -733,7 +736,8 @@ def workloads_bench(pne, P, steps: int):
             kernels[k] = d
         out = {"workload": label, "networks": len(nets), "ms_per_step": round(ms, 4),
                "networks_per_s": round(len(nets) / (ms * 1e-3), 1), "precision": prec, "K": K,
-               "bp_iters_mean": float(np.mean(iters)), "status_min": int(res["status"].min()),
+               "bp_iters_mean": float(np.mean(iters)), "bp_iters_max": max(iters), "bp_max_iter": max_iter,
+               "status_min": int(res["status"].min()), "status_max": int(res["status"].max()),
                "cluster_terms_per_step": nclu, "kernels": kernels}
         if check and parts_of is not None:
             from oracle import partitioned as PT
@@ -743,7 +747,7 @@ def workloads_bench(pne, P, steps: int):
             _, lg = PT.recursive_pne(nets_in[0], parts, subs)
             out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - lg) / max(1.0, abs(lg))
         elif check:
-            ref = O.pne_contract(nets_in[0], K)
+            ref = O.pne_contract(nets_in[0], K, max_iter=3 * max_iter)
             out["rel_err_log_vs_oracle_sample0"] = abs(float(res["log_abs"][0]) - ref.log_abs) / max(
                 1.0, abs(ref.log_abs))
         print(json.dumps(out), flush=True)

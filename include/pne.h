@@ -121,14 +121,22 @@ typedef struct {
     int32_t max_excited;  /* K: largest retained configuration degree (>= 0)   */
     int32_t precision;    /* pne_precision                                       */
     double bp_tol;        /* stop when the largest sign-insensitive inf-norm
-                             message change of a sweep is <= bp_tol (1e-13)      */
+                             message change of a sweep is <= bp_tol (1e-13)
+                             (red-black schedule: of the last two steps), or
+                             at the rounding floor (bp_stall_steps)            */
     int32_t bp_max_iter;  /* sweep cap (500)                                     */
     int32_t bp_check_every; /* sweeps between host convergence checks (0: auto) */
     uint32_t flags;       /* PNE_FLAG_* bits (0: defaults)                       */
     int32_t profile_kernels; /* with PNE_FLAG_PROFILE: bit k times kernel index k of
                                 pne_batch_kernel_times only; 0 times every kernel  */
     int32_t mode;         /* pne_mode (PNE_MODE_LOOP)                            */
-    int32_t reserved0;
+    int32_t bp_stall_steps; /* rounding-floor stop: BP also ends, as converged,
+                             when its smallest residual so far is <= 100 *
+                             bp_tol and no sweep has lowered it for this many
+                             sweeps (0: 50; < 0: never).  The residual then sits
+                             at the rounding floor of the messages, which a
+                             badly conditioned bond gauge can raise above
+                             bp_tol; bp_residual reports the value reached.    */
     double bp_damping;    /* 0 <= lambda < 1 (0): every stored message is the
                              normalised, sign-fixed mix (1-lambda) m_new +
                              lambda m_old of the normalised update and the same

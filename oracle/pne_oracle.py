@@ -75,7 +75,7 @@ def _contract_except(t, msgs, keep):
     return out
 
 
-def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0):
+def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0, stall=50):
     """Jacobi BP from uniform messages.
 
     Every directed message starts at 1/sqrt(d).  A sweep recomputes every
@@ -83,6 +83,12 @@ def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0):
     to unit 2-norm and flips its sign so that its entries sum to >= 0.  The
     residual is the largest sign-insensitive infinity-norm change over all
     messages; sweeps stop once it is <= tol or after max_iter sweeps.
+
+    Rounding floor (not part of the paper's method): with stall > 0, sweeps
+    also stop, as converged, once `stall` sweeps in a row have not lowered
+    the smallest residual so far and that residual is <= 100 * tol.  A
+    residual that no longer decreases has reached the rounding noise of the
+    messages, which an ill-conditioned bond gauge can lift above tol.
 
     Damping (not part of the paper's method; 0 by default): with
     0 <= damping < 1 the stored message is the mix
@@ -100,6 +106,7 @@ def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0):
     inc = [[np.full(d, 1.0 / math.sqrt(d)) for d in t.shape] for t in T]
     residual = math.inf
     iters = 0
+    best, best_at = math.inf, 0
     for it in range(1, max_iter + 1):
         new = [[None] * t.ndim for t in T]
         for s, t in enumerate(T):
@@ -130,6 +137,10 @@ def bp_messages(net, tol=1e-13, max_iter=500, damping=0.0):
         inc = new
         iters = it
         if residual <= tol:
+            return inc, iters, residual, True
+        if residual < best:
+            best, best_at = residual, it
+        elif stall > 0 and best <= 100.0 * tol and it - best_at >= stall:
             return inc, iters, residual, True
     return inc, iters, residual, False
 
@@ -370,7 +381,7 @@ class OracleResult:
     inc: list | None = None
 
 
-def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop", damping=0.0):
+def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop", damping=0.0, stall=50):
     """Loop-truncated PNE of a closed or open network.
 
     Closed network: returns (sign, ln|Z|).  Open network: Out = open_values *
@@ -388,7 +399,7 @@ def pne_contract(net, K, tol=1e-13, max_iter=500, keep_details=False, mode="loop
         raise ValueError("mode must be 'loop', 'full' or 'cumulant'")
     if mode != "loop" and net.n_open:
         raise ValueError(f"{mode} mode is for closed networks")
-    inc, iters, residual, converged = bp_messages(net, tol, max_iter, damping)
+    inc, iters, residual, converged = bp_messages(net, tol, max_iter, damping, stall)
     proj = projectors(net, inc)
     z = vacuum(net, inc)
     open_site = _open_slots(net)

@@ -43,6 +43,8 @@ __global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict_
         s.parity = 0;
         s.status = 0;
         s.res_acc[0] = s.res_acc[1] = s.res_acc[2] = 0ull;
+        s.best[0] = s.best[1] = INFINITY;
+        s.best_at[0] = s.best_at[1] = -1;
         s.residual = 0.0;
         s.log_bp = 0.0;
         s.sign_bp = 1;
@@ -63,22 +65,42 @@ __global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict_
 // Stop test for sweep k of a network: true when the network stopped before
 // sweep k.  Every tile of the network reaches the same answer, because it
 // depends only on values completed by earlier launches (the residual of sweep
-// k-1 and the error status).  The network's first tile records the stop.
-__device__ bool network_stopped(NetState *ns, int k, double tol, int max_iter, bool writer) {
+// k-1, the error status and the smallest-residual record in slot k&1).  The
+// network's first tile records the stop, or else the record updated with
+// sweep k-1 in the other slot.  A network also stops, as converged, at its
+// rounding floor: no new smallest residual for `stall` sweeps, that residual
+// at most `floor_tol`.
+__device__ bool network_stopped(NetState *ns, int k, double tol, int max_iter, int stall, double floor_tol,
+                                bool writer) {
     if (ns->stop >= 0) return true;
     if (k == 0) return false;
     const double r = __longlong_as_double((long long)ns->res_acc[(k - 1) % 3]);
     const int status = ns->status;
     const bool conv = status >= 0 && r <= tol;
-    if (status < 0 || conv || k >= max_iter) {
+    double best = ns->best[k & 1];
+    int best_at = ns->best_at[k & 1];
+    bool floor = false;
+    if (!conv) {
+        if (r < best) {
+            best = r;
+            best_at = k - 1;
+        } else {
+            floor = status >= 0 && stall > 0 && best <= floor_tol && (k - 1) - best_at >= stall;
+        }
+    }
+    if (status < 0 || conv || floor || k >= max_iter) {
         if (writer) {
             ns->stop = k - 1;
             ns->iters = k;
             ns->parity = k & 1;
             ns->residual = r;
-            ns->converged = conv ? 1 : 0;
+            ns->converged = (conv || floor) ? 1 : 0;
         }
         return true;
+    }
+    if (writer) {
+        ns->best[(k - 1) & 1] = best;
+        ns->best_at[(k - 1) & 1] = best_at;
     }
     return false;
 }
@@ -549,14 +571,15 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
                                                          const BpTile *__restrict__ tiles,
                                                          const int *__restrict__ tile_sites,
                                                          double *msg0, double *msg1, NetState *st, int sweep,
-                                                         double tol, int max_iter, double damp) {
+                                                         double tol, int max_iter, int stall,
+                                                         double floor_tol, double damp) {
     const BpTile tl = tiles[blockIdx.x];
     NetState *ns = st + tl.net;
     extern __shared__ double lds[];
     __shared__ int s_skip;
     __shared__ TileShared sh;
     if (threadIdx.x == 0) {
-        s_skip = network_stopped(ns, sweep, tol, max_iter, tl.first != 0);
+        s_skip = network_stopped(ns, sweep, tol, max_iter, stall, floor_tol, tl.first != 0);
         // slot (sweep+1)%3 was last read at the start of sweep-1: clear it for sweep+1
         if (!s_skip && tl.first) ns->res_acc[(sweep + 1) % 3] = 0ull;
     }
@@ -680,15 +703,15 @@ hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, h
     }
     if (b.n_reg_tiles > 0)
         hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, ns, b.sites, b.tiles,
-                           b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.damping);
+                           b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.bp_stall, b.bp_floor, b.damping);
     if (b.n_narrow_tiles > b.n_reg_tiles)
         hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, ns,
                            b.sites, b.tiles + b.n_reg_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
-                           b.damping);
+                           b.bp_stall, b.bp_floor, b.damping);
     if (n_wide > 0)
         hipLaunchKernelGGL(k_bp_sweep<true>, dim3(n_wide), dim3(kBpThreads), b.wide_lds, s, b.sites,
                            b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
-                           b.damping);
+                           b.bp_stall, b.bp_floor, b.damping);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (split) {
         if ((e = hipEventRecord(b.join, b.side)) != hipSuccess) return e;

@@ -724,11 +724,21 @@ __device__ __attribute__((noinline)) void p_clusters(int class_begin, int n_clas
 // CU).  WPE: the fewest waves per SIMD the register allocation must allow;
 // 4 caps a lane at 128 VGPRs (two 512-thread blocks per CU), 2 at 256 (one
 // block per CU, no spills, twice the LDS per block).
+// A double that every lane of the wave holds, read from the first lane, so
+// that the compiler can keep it (and what is derived from it) in SGPRs.
+__device__ __forceinline__ double uniform_double(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readfirstlane((int)(b & 0xffffffffll));
+    const int hi = __builtin_amdgcn_readfirstlane((int)(b >> 32));
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
 template <typename S, int NT, int WPE>
 __global__ void __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(WPE, 8)))
 k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict__ groups,
                 const int *__restrict__ site_list, const SiteRec *__restrict__ sites, double *msg0, NetState *st,
-                double tol, int max_iter, S *__restrict__ slices, double *__restrict__ site_log,
+                double tol, int max_iter, int stall, double floor_tol, S *__restrict__ slices,
+                double *__restrict__ site_log,
                 int *__restrict__ site_sign, int rg_enabled, const ClassDesc *__restrict__ classes,
                 double *__restrict__ w,
                 const CombineRec *__restrict__ crecs, const GeoRec *__restrict__ geos,
@@ -784,6 +794,10 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
     __syncthreads();
     int sweep = 0;
     double r = 0.0, r_prev = 0.0;
+    // smallest residual so far (red-black: of the last two steps) and the
+    // step that reached it, for the rounding-floor stop
+    double r_best = INFINITY;
+    int best_at = -1;
     bool conv = false;
     for (sweep = 0; sweep < max_iter; ++sweep) {
         // Jacobi: read buffer sweep&1, write the other.  Red-black: sites of
@@ -844,6 +858,15 @@ k_bp_persistent(const FusedNet *__restrict__ fnets, const FusedGroup *__restrict
         if (*bad_slot) break;
         // red-black: both colours' latest updates must be within tol
         if (r <= tol && (!rb || (sweep > 0 && r_prev <= tol))) {
+            conv = true;
+            break;
+        }
+        // the same value in every lane: keep the record in scalar registers
+        const double rr = uniform_double(rb ? fmax(r, r_prev) : r);
+        if (rr < r_best) {
+            r_best = rr;
+            best_at = sweep;
+        } else if (stall > 0 && r_best <= floor_tol && sweep - best_at >= stall) {
             conv = true;
             break;
         }
@@ -966,19 +989,19 @@ void launch_fused_w(const DeviceBatch &b, const FusedNet *fused, int n, size_t l
     switch (b.precision) {
         case 0:
             hipLaunchKernelGGL((k_bp_persistent<double, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
-                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (double *)b.slices,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, b.bp_stall, b.bp_floor, (double *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         case 1:
             hipLaunchKernelGGL((k_bp_persistent<float, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
-                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (float *)b.slices,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, b.bp_stall, b.bp_floor, (float *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;
         default:
             hipLaunchKernelGGL((k_bp_persistent<uint16_t, NT, WPE>), dim3(n), dim3(NT), lds, s, fused, b.fgroups,
-                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, (uint16_t *)b.slices,
+                               b.fsite_list, b.sites, b.msg0, b.state, tol, max_iter, b.bp_stall, b.bp_floor, (uint16_t *)b.slices,
                                b.site_log, b.site_sign, b.fused_regauge, b.classes, b.w, b.crec, b.geos,
                                b.buckets, b.pair_a, b.pair_b, b.pair_cats, b.results);
             break;

@@ -48,6 +48,8 @@ struct DeviceBatch {
     void *slices = nullptr;
     int precision = 0;
     double damping = 0.0;          // BP damping of the per-launch sweeps
+    int bp_stall = 50;             // rounding-floor stop: sweeps without a new smallest residual (0: never)
+    double bp_floor = 0.0;         // ... once that residual is at most this (100 * tol)
     double *site_log = nullptr;
     int *site_sign = nullptr;
     double *vac = nullptr;

@@ -85,6 +85,11 @@ struct NetState {
     int32_t parity;     // buffer holding the final messages
     int32_t status;     // 0 ok, else a negative pne_status
     unsigned long long res_acc[3];  // per-sweep residual maxima (bits of doubles >= 0)
+    // smallest residual so far and the sweep that reached it, double-buffered
+    // for the per-launch sweeps: the test of sweep k reads slot k&1 and its
+    // first tile writes the update with sweep k-1's residual to the other slot
+    double best[2];
+    int32_t best_at[2];
     double residual;    // residual of the last sweep
     double log_bp;
     int32_t sign_bp;

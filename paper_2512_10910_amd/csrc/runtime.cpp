@@ -1585,6 +1585,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.cluster_lds = cl_lds;
     db.precision = prec;
     db.damping = opt->bp_damping;
+    db.bp_stall = opt->bp_stall_steps == 0 ? 50 : std::max(0, opt->bp_stall_steps);
+    db.bp_floor = 100.0 * opt->bp_tol;
     db.reg_budget = opt->reg_budget;
 #define AL(bytes, field, type) ap.buffer((bytes), &db.field)
     AL(sizeof(NetState) * n, state, NetState *);

@@ -60,7 +60,7 @@ class Options(ctypes.Structure):
         ("flags", ctypes.c_uint32),
         ("profile_kernels", ctypes.c_int32),
         ("mode", ctypes.c_int32),
-        ("reserved0", ctypes.c_int32),
+        ("bp_stall_steps", ctypes.c_int32),
         ("bp_damping", ctypes.c_double),
         ("err_bound", ctypes.c_double),
         ("small_sites", ctypes.c_int32),
@@ -409,7 +409,7 @@ PATH_PERSISTENT, PATH_BLOCK_GAUGE, PATH_BLOCK_TERMS = 1, 2, 4
 
 def _options(K, precision, tol, max_iter, check_every, profile=False, persistent=True, jacobi=False,
              fused_regauge=True, graph=False, autotune=False, mode="loop", damping=0.0, err_bound=1e-5,
-             small_sites=0, tiles_in_flight=0, reg_budget=0):
+             small_sites=0, tiles_in_flight=0, reg_budget=0, stall_steps=0):
     """profile: False, True (every kernel) or a list of KERNEL_NAMES to time."""
     lib = load_library()
     o = Options()
@@ -430,6 +430,7 @@ def _options(K, precision, tol, max_iter, check_every, profile=False, persistent
     o.small_sites = int(small_sites)
     o.tiles_in_flight = int(tiles_in_flight)
     o.reg_budget = int(reg_budget)
+    o.bp_stall_steps = int(stall_steps)
     return o
 
 
@@ -473,7 +474,7 @@ class Context:
     def batch(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, check_every=0,
               profile=False, persistent=True, jacobi=False, fused_regauge=True, graph=False,
               autotune=False, mode="loop", damping=0.0, err_bound=1e-5, small_sites=0, tiles_in_flight=0,
-              reg_budget=0) -> "Batch":
+              reg_budget=0, stall_steps=0) -> "Batch":
         """persistent=False: BP launch by launch; jacobi=True: Jacobi sweeps
         in the persistent kernel even on bipartite networks; fused_regauge=
         False: gauge + slices in their own launch; graph=True: replay a
@@ -482,10 +483,11 @@ class Context:
         configuration of degree <= K, dangling ones included; damping: BP
         damping in [0, 1); err_bound: reduced-precision warning bound;
         small_sites, tiles_in_flight, reg_budget: the persistent kernel's tile
-        shape (see pne_options)."""
+        shape (see pne_options); stall_steps: BP's rounding-floor stop (0:
+        50 sweeps, < 0: off)."""
         return Batch(self, nets, K, precision, tol, max_iter, check_every, profile, persistent, jacobi,
                      fused_regauge, graph, autotune, mode, damping, err_bound, small_sites, tiles_in_flight,
-                     reg_budget)
+                     reg_budget, stall_steps)
 
     def autotune(self, nets, K=4, precision="fp64", tol=1e-13, max_iter=500, trials=3) -> dict:
         """Time the tile-shape variants for this batch; returns the choice."""
@@ -642,11 +644,12 @@ class Batch:
 
     def __init__(self, ctx: Context, nets, K, precision, tol, max_iter, check_every, profile=False,
                  persistent=True, jacobi=False, fused_regauge=True, graph=False, autotune=False, mode="loop",
-                 damping=0.0, err_bound=1e-5, small_sites=0, tiles_in_flight=0, reg_budget=0):
+                 damping=0.0, err_bound=1e-5, small_sites=0, tiles_in_flight=0, reg_budget=0, stall_steps=0):
         self.ctx = ctx
         self.nets = list(nets)
         self.opt = _options(K, precision, tol, max_iter, check_every, profile, persistent, jacobi, fused_regauge,
-                            graph, autotune, mode, damping, err_bound, small_sites, tiles_in_flight, reg_budget)
+                            graph, autotune, mode, damping, err_bound, small_sites, tiles_in_flight, reg_budget,
+                            stall_steps)
         arr = (ctypes.c_void_p * len(self.nets))(*[n.handle.value for n in self.nets])
         h = ctypes.c_void_p()
         _check(ctx.lib, ctx.lib.pne_batch_create(ctx.handle, arr, len(self.nets), ctypes.byref(self.opt),

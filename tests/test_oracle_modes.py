@@ -260,3 +260,23 @@ def test_cumulant_planted_mistake_is_caught(monkeypatch):
     good = O.pne_contract(net, 8, mode="cumulant").log_abs
     monkeypatch.setattr(PO, "cumulant_sum", no_self)
     assert abs(O.pne_contract(net, 8, mode="cumulant").log_abs - good) > 1e-6
+
+
+def test_bp_rounding_floor_stop():
+    """The rounding-floor stop of BP: with tol (1e-17) below the FP64 noise of
+    the messages, plain sweeps never reach tol; the floor stop ends them as
+    converged once 50 sweeps have not lowered the smallest residual, at the
+    messages a normal 1e-13 run reaches.  Above 100 * tol the floor does not
+    count, and on a run that reaches tol the stop never fires."""
+    net = P.apply_random_gauge(P.small_network(3, 3, "random", 3, seed=1), 11, scale=1.0)
+    inc0, it0, _, c0 = O.bp_messages(net, tol=1e-13)
+    assert c0 and O.bp_messages(net, tol=1e-13, stall=0)[1] == it0
+    inc, it, r, c = O.bp_messages(net, tol=1e-17, max_iter=400)
+    assert c and it0 < it < 400 and r < 1e-13
+    for a, b in zip(inc, inc0):
+        for x, y in zip(a, b):
+            assert np.max(np.abs(x - y)) < 1e-12
+    _, it, _, c = O.bp_messages(net, tol=1e-17, max_iter=400, stall=0)
+    assert not c and it == 400
+    _, it, _, c = O.bp_messages(net, tol=1e-20, max_iter=400)
+    assert not c and it == 400

@@ -55,7 +55,7 @@ def _singles_only(clusters, sizes, vsets, K):
     return [c for c in _ORIG["enumerate_collections"](clusters, sizes, vsets, K) if len(c) == 1]
 
 
-def _one_sweep(net, tol=1e-13, max_iter=500, damping=0.0):
+def _one_sweep(net, tol=1e-13, max_iter=500, damping=0.0, stall=50):
     return _ORIG["bp_messages"](net, tol, 2)
 
 
