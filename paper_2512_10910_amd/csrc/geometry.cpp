@@ -513,8 +513,46 @@ std::vector<int> elimination_order(const LocalCluster &lc) {
     return best;
 }
 
+// Entry tables of one step (StepEnt): output entries o, then summed entries
+// t, each in mixed radix with the last label fastest.  None (ent = -1) when
+// a label has more than 16 values or the plan's tables would grow past
+// kMaxStepEnts.
+constexpr size_t kMaxStepEnts = size_t(1) << 22;
+
+void step_entries(StepDesc *sd, std::vector<StepEnt> *ents) {
+    sd->ent = -1;
+    for (int k = 0; k < sd->n_ol; ++k)
+        if (sd->out_dim[k] > 16) return;
+    for (int k = 0; k < sd->n_sl; ++k)
+        if (sd->sum_dim[k] > 16) return;
+    if (ents->size() + (size_t)sd->n_out + (size_t)sd->n_sum > kMaxStepEnts) return;
+    sd->ent = (int)ents->size();
+    for (int o = 0; o < sd->n_out; ++o) {
+        StepEnt e{0, 0u};
+        int rem = o;
+        for (int k = sd->n_ol - 1; k >= 0; --k) {
+            const int dg = rem % sd->out_dim[k];
+            rem /= sd->out_dim[k];
+            e.f += dg * sd->out_fs[k];
+            if (sd->out_xl[k] >= 0) e.xdig |= (uint32_t)dg << (4 * sd->out_xl[k]);
+        }
+        ents->push_back(e);
+    }
+    for (int t = 0; t < sd->n_sum; ++t) {
+        StepEnt e{0, 0u};
+        int rem = t;
+        for (int k = sd->n_sl - 1; k >= 0; --k) {
+            const int dg = rem % sd->sum_dim[k];
+            rem /= sd->sum_dim[k];
+            e.f += dg * sd->sum_fs[k];
+            e.xdig |= (uint32_t)dg << (4 * sd->sum_xl[k]);
+        }
+        ents->push_back(e);
+    }
+}
+
 bool build_steps(const LocalCluster &lc, const std::vector<int> &order, std::vector<StepDesc> *steps,
-                 size_t *max_f, int *out_size, std::string *err) {
+                 std::vector<StepEnt> *ents, size_t *max_f, int *out_size, std::string *err) {
     std::vector<int> F;  // labels of the running frontier, C order
     *max_f = 1;
     for (size_t si = 0; si < order.size(); ++si) {
@@ -612,6 +650,7 @@ bool build_steps(const LocalCluster &lc, const std::vector<int> &order, std::vec
         sd.n_out = (int)nout;
         sd.n_sum = (int)nsum;
         *max_f = std::max(*max_f, nout);
+        step_entries(&sd, ents);
         steps->push_back(sd);
         F = outl;
     }
@@ -742,8 +781,17 @@ std::shared_ptr<GeoPlan> build_plan(const Geometry &g, int K, std::string *err, 
             cd.step_begin = (int)plan->steps.size();
             size_t mf = 1;
             int osz = 1;
-            if (!build_steps(lc, order, &plan->steps, &mf, &osz, err)) return nullptr;
+            if (!build_steps(lc, order, &plan->steps, &plan->step_ents, &mf, &osz, err)) return nullptr;
             cd.n_steps = (int)plan->steps.size() - cd.step_begin;
+            cd.max_sum = 0;
+            for (int st = 0; st < cd.n_steps; ++st) {
+                const StepDesc &sd = plan->steps[cd.step_begin + st];
+                if (sd.ent < 0) {
+                    cd.max_sum = 0;
+                    break;
+                }
+                cd.max_sum = std::max(cd.max_sum, sd.n_sum);
+            }
             cd.n_verts = (int)lc.verts.size();
             cd.max_f = (int)mf;
             int gsz = 1;

@@ -78,6 +78,7 @@ struct GeoPlan {
 
     std::vector<ClassDesc> classes;
     std::vector<StepDesc> steps;
+    std::vector<StepEnt> step_ents;  // per step with tables: n_out + n_sum entries
     std::vector<std::vector<int>> inst_cluster;    // per class
     std::vector<std::vector<int>> inst_site;       // per class: n_inst * n_verts (local site ids)
     std::vector<std::vector<uint32_t>> inst_slots; // per class: n_inst * n_verts packed slots

@@ -71,6 +71,7 @@ struct DeviceBatch {
     // clusters
     const ClassDesc *classes = nullptr;
     const StepDesc *steps = nullptr;
+    const StepEnt *step_ents = nullptr;
     const ClusterBlock *cblocks = nullptr;
     int n_cblocks = 0;
     const PlanNet *pnets = nullptr;       // per plan: its networks' slice and weight bases

@@ -234,16 +234,37 @@ __device__ inline int xcd_block(int p, int nb) {
     return x * q + min(x, r) + (p >> 3);
 }
 
+// Slice offset of a StepEnt's digits (4 bits per slice leg) under an
+// instance's leg strides.
+__device__ __forceinline__ int ent_offset(uint32_t xdig, const int (&xs)[kMaxLab]) {
+    int x = 0;
+#pragma unroll
+    for (int m = 0; m < kMaxLab; ++m) x += (int)((xdig >> (4 * m)) & 15u) * xs[m];
+    return x;
+}
+
+// Orders the LDS accesses of the lanes of one wavefront (an instance's lanes
+// never span two wavefronts: the group size divides 64).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Cluster contraction by a per-class plan: the frontier tensor F absorbs one
 // excited slice per step (F_next[out] = sum_shared F[.] X[.]).  A class runs
 // `group` lanes per instance; every step is uniform across the block.  An
 // instance's step records (slice offset from its network's slice base, leg
 // strides) come from the plan's instance table; classes whose frontier has
 // one entry throughout are a plain product of one slice element per vertex,
-// one instance per thread.
+// one instance per thread.  Classes with entry tables (max_sum > 0) read
+// each output's and each summed entry's F offset and slice digits from
+// them; the instance's lanes first turn the summed entries into (F, slice)
+// offset pairs in LDS, then each lane sums its outputs over them, in the
+// same order as the index walk of the other classes.
 template <typename S>
 __global__ void __launch_bounds__(kClThreads) k_clusters(
-    const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps,
+    const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps, const StepEnt *__restrict__ ents,
     const ClusterBlock *__restrict__ blocks, const PlanNet *__restrict__ pnets, const S *__restrict__ slices,
     double *__restrict__ w) {
     using A = typename SliceIO<S>::acc;
@@ -297,6 +318,48 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
     A *G = F + cd.max_f;
     if (lane == 0) F[0] = A(1);
     __syncthreads();
+    if (cd.max_sum > 0) {
+        int2 *SO = reinterpret_cast<int2 *>(reinterpret_cast<A *>(lds_raw) + (size_t)(kClThreads / g) * 2 * cd.max_f) +
+                   (size_t)slot * cd.max_sum;
+        for (int st = 0; st < cd.n_steps; ++st) {
+            const StepDesc &sd = s_steps[st];
+            const StepEnt *E = ents + sd.ent;
+            int xs[kMaxLab];
+            int64_t xbase = 0;
+            if (valid) {
+                xbase = pn.slice_base + gld(&rec[st].xoff);
+#pragma unroll
+                for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
+                for (int t = lane; t < sd.n_sum; t += g) {
+                    const StepEnt e = E[sd.n_out + t];
+                    SO[t] = make_int2(e.f, ent_offset(e.xdig, xs));
+                }
+            }
+            wave_sync();
+            if (valid) {
+                for (int o = lane; o < sd.n_out; o += g) {
+                    const StepEnt e = E[o];
+                    const A *Fo = F + e.f;
+                    const S *Xo = slices + xbase + ent_offset(e.xdig, xs);
+                    A acc = A(0);
+                    for (int t = 0; t < sd.n_sum; ++t) {
+                        const int2 q = SO[t];
+                        acc += Fo[q.x] * SliceIO<S>::load(Xo, q.y);
+                    }
+                    G[o] = acc;
+                }
+            }
+            wave_sync();
+            A *tmp = F;
+            F = G;
+            G = tmp;
+        }
+        if (valid) {
+            const int64_t wo = pn.w_base + gld(cd.iw + k);
+            for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
+        }
+        return;
+    }
     for (int st = 0; st < cd.n_steps; ++st) {
         const StepDesc &sd = s_steps[st];
         if (valid) {
@@ -352,7 +415,13 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                 G[o] = acc;
             }
         }
-        __syncthreads();
+        // an instance's lanes lie in one wavefront (g divides 64), and F and
+        // G are its own: a wavefront-scope fence orders the step's LDS
+        // writes before the next step's reads, and the waves of the block
+        // run their steps independently
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
         A *t = F;
         F = G;
         G = t;
@@ -691,17 +760,17 @@ hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
     switch (b.precision) {
         case 0:
             hipLaunchKernelGGL(k_clusters<double>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.pnets,
+                               b.steps, b.step_ents, b.cblocks, b.pnets,
                                (const double *)b.slices, b.w);
             break;
         case 1:
             hipLaunchKernelGGL(k_clusters<float>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.cblocks, b.pnets,
+                               b.steps, b.step_ents, b.cblocks, b.pnets,
                                (const float *)b.slices, b.w);
             break;
         default:
             hipLaunchKernelGGL(k_clusters<uint16_t>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s,
-                               b.classes, b.steps, b.cblocks, b.pnets,
+                               b.classes, b.steps, b.step_ents, b.cblocks, b.pnets,
                                (const uint16_t *)b.slices, b.w);
             break;
     }

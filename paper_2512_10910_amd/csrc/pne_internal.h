@@ -115,6 +115,18 @@ struct StepDesc {
     int32_t sum_fs[kMaxLab];
     int32_t sum_xl[kMaxLab];
     int32_t x_excited[kMaxLab];  // 1 when the slice leg is an excited bond leg
+    int32_t ent;         // first StepEnt of the step (n_out output entries, then n_sum
+                         // summed entries), or -1 when the class has no entry tables
+};
+
+// Precomputed index of one output entry or one summed entry of a step, in
+// the order the contraction visits them (last label fastest): f is its
+// offset in F (for an output entry, F's part of it), xdig the slice index
+// digit of each slice leg m in bits 4m..4m+3.  An instance's slice offset is
+// the sum of digit x stride over its slice legs.
+struct StepEnt {
+    int32_t f;
+    uint32_t xdig;
 };
 
 // A class of clusters with the same contraction plan.
@@ -136,7 +148,7 @@ struct ClassDesc {
     int32_t scalar;      // 1: frontier of one entry throughout (every leg of dimension 1)
     int32_t loop_e;      // > 0: a simple cycle of legs of dimension loop_e, evaluated as the
                          // trace of a matrix product (records in cycle order)
-    int32_t pad;
+    int32_t max_sum;     // > 0: every step has StepEnt tables; the largest summed space
 };
 
 // One step of one instance: where the absorbed slice's block starts (element

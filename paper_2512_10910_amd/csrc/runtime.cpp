@@ -1236,6 +1236,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     // cluster tables: classes shared per distinct plan, instances per class
     std::vector<ClassDesc> classes;
     std::vector<StepDesc> steps;
+    std::vector<StepEnt> step_ents;
     std::vector<ClusterBlock> cblocks;
     std::vector<PlanNet> pnets;
     std::vector<CombineRec> crec(n);
@@ -1260,11 +1261,20 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             for (const ClassDesc &cd0 : p->classes) {
                 ClassDesc cd = cd0;
                 cd.step_begin += (int)steps.size();
-                classes.push_back(cd);
                 const size_t asz = prec == PNE_FP64 ? 8 : 4;
-                cl_lds = std::max(cl_lds, (size_t)(256 / cd.group) * 2 * (size_t)cd.max_f * asz);
+                // per instance slot: F and G, then the step's summed-entry offsets
+                const size_t slots = (size_t)(256 / cd.group);
+                const size_t fg = slots * 2 * (size_t)cd.max_f * asz;
+                if (fg + slots * (size_t)cd.max_sum * sizeof(StepEnt) > 64 * 1024) cd.max_sum = 0;
+                classes.push_back(cd);
+                cl_lds = std::max(cl_lds, fg + slots * (size_t)cd.max_sum * sizeof(StepEnt));
             }
-            steps.insert(steps.end(), p->steps.begin(), p->steps.end());
+            const int ent_base = (int)step_ents.size();
+            for (StepDesc sd : p->steps) {
+                if (sd.ent >= 0) sd.ent += ent_base;
+                steps.push_back(sd);
+            }
+            step_ents.insert(step_ents.end(), p->step_ents.begin(), p->step_ents.end());
             GeoRec gr;
             std::memset(&gr, 0, sizeof gr);
             gr.K = K;
@@ -1547,6 +1557,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_init_nets = (int)init_nets.size();
     UP(classes, classes);
     UP(steps, steps);
+    UP(step_ents, step_ents);
     UP(cblocks, cblocks);
     UP(pnets, pnets);
     UP(crec, crec);
