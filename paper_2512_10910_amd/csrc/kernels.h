@@ -74,6 +74,8 @@ struct DeviceBatch {
     const StepEnt *step_ents = nullptr;
     const ClusterBlock *cblocks = nullptr;
     int n_cblocks = 0;
+    static constexpr int kClKinds = 6;    // block ranges: frontier plans, cycles of leg
+    int cl_kind_begin[kClKinds + 1] = {}; // dimension 2..5, scalar products
     const PlanNet *pnets = nullptr;       // per plan: its networks' slice and weight bases
     size_t cluster_lds = 0;
     double *w = nullptr;

@@ -261,8 +261,11 @@ __device__ __forceinline__ void wave_sync() {
 // each output's and each summed entry's F offset and slice digits from
 // them; the instance's lanes first turn the summed entries into (F, slice)
 // offset pairs in LDS, then each lane sums its outputs over them, in the
-// same order as the index walk of the other classes.
-template <typename S>
+// same order as the index walk of the other classes.  KIND selects the
+// blocks' path (0 frontier plans, 1-4 cycles of leg dimension KIND + 1, 5
+// scalar products): each path is its own launch, so one path's registers
+// (a dimension-5 cycle's matrices) do not lower the occupancy of another.
+template <typename S, int KIND>
 __global__ void __launch_bounds__(kClThreads) k_clusters(
     const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps, const StepEnt *__restrict__ ents,
     const ClusterBlock *__restrict__ blocks, const PlanNet *__restrict__ pnets, const S *__restrict__ slices,
@@ -271,24 +274,17 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
     const ClusterBlock blk = blocks[xcd_block(blockIdx.x, gridDim.x)];
     const ClassDesc cd = classes[blk.cls];
     const int tid = threadIdx.x;
-    if (cd.loop_e) {
+    if constexpr (KIND >= 1 && KIND <= 4) {
         if (tid >= blk.count) return;
         const int f = blk.flat_begin + tid;
         const int net = f / cd.n_inst;
         const int k = f - net * cd.n_inst;
         const PlanNet pn = pnets[cd.pnet_begin + net];
         const InstStep *rec = cd.tab + (int64_t)k * cd.n_verts;
-        A v = A(0);
-        switch (cd.loop_e) {
-            case 2: v = loop_trace<2, S>(rec, cd.n_verts, slices, pn.slice_base); break;
-            case 3: v = loop_trace<3, S>(rec, cd.n_verts, slices, pn.slice_base); break;
-            case 4: v = loop_trace<4, S>(rec, cd.n_verts, slices, pn.slice_base); break;
-            default: v = loop_trace<5, S>(rec, cd.n_verts, slices, pn.slice_base); break;
-        }
+        const A v = loop_trace<KIND + 1, S>(rec, cd.n_verts, slices, pn.slice_base);
         w[pn.w_base + gld(cd.iw + k)] = (double)v;
         return;
-    }
-    if (cd.scalar) {
+    } else if constexpr (KIND == 5) {
         if (tid >= blk.count) return;
         const int f = blk.flat_begin + tid;
         const int net = f / cd.n_inst;
@@ -299,136 +295,135 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, pn.slice_base + gld(&rec[st].xoff));
         w[pn.w_base + gld(cd.iw + k)] = (double)prod;
         return;
-    }
-    extern __shared__ double lds_raw[];
-    __shared__ StepDesc s_steps[kMaxVerts];
-    for (int i = tid; i < cd.n_steps * (int)(sizeof(StepDesc) / 4); i += kClThreads)
-        reinterpret_cast<int32_t *>(s_steps)[i] =
-            reinterpret_cast<const int32_t *>(steps + cd.step_begin)[i];
-    const int g = cd.group;
-    const int lane = tid & (g - 1);
-    const int slot = tid / g;
-    const bool valid = slot < blk.count;
-    const int f = blk.flat_begin + (valid ? slot : 0);
-    const int net = f / cd.n_inst;
-    const int k = f - net * cd.n_inst;
-    const PlanNet pn = pnets[cd.pnet_begin + net];
-    const InstStep *rec = cd.tab + (int64_t)k * cd.n_steps;
-    A *F = reinterpret_cast<A *>(lds_raw) + (size_t)slot * 2 * cd.max_f;
-    A *G = F + cd.max_f;
-    if (lane == 0) F[0] = A(1);
-    __syncthreads();
-    if (cd.max_sum > 0) {
-        int2 *SO = reinterpret_cast<int2 *>(reinterpret_cast<A *>(lds_raw) + (size_t)(kClThreads / g) * 2 * cd.max_f) +
-                   (size_t)slot * cd.max_sum;
+    } else {
+        extern __shared__ double lds_raw[];
+        __shared__ StepDesc s_steps[kMaxVerts];
+        for (int i = tid; i < cd.n_steps * (int)(sizeof(StepDesc) / 4); i += kClThreads)
+            reinterpret_cast<int32_t *>(s_steps)[i] =
+                reinterpret_cast<const int32_t *>(steps + cd.step_begin)[i];
+        const int g = cd.group;
+        const int lane = tid & (g - 1);
+        const int slot = tid / g;
+        const bool valid = slot < blk.count;
+        const int f = blk.flat_begin + (valid ? slot : 0);
+        const int net = f / cd.n_inst;
+        const int k = f - net * cd.n_inst;
+        const PlanNet pn = pnets[cd.pnet_begin + net];
+        const InstStep *rec = cd.tab + (int64_t)k * cd.n_steps;
+        A *F = reinterpret_cast<A *>(lds_raw) + (size_t)slot * 2 * cd.max_f;
+        A *G = F + cd.max_f;
+        if (lane == 0) F[0] = A(1);
+        __syncthreads();
+        if (cd.max_sum > 0) {
+            int2 *SO = reinterpret_cast<int2 *>(reinterpret_cast<A *>(lds_raw) + (size_t)(kClThreads / g) * 2 * cd.max_f) +
+                       (size_t)slot * cd.max_sum;
+            for (int st = 0; st < cd.n_steps; ++st) {
+                const StepDesc &sd = s_steps[st];
+                const StepEnt *E = ents + sd.ent;
+                int xs[kMaxLab];
+                int64_t xbase = 0;
+                if (valid) {
+                    xbase = pn.slice_base + gld(&rec[st].xoff);
+    #pragma unroll
+                    for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
+                    for (int t = lane; t < sd.n_sum; t += g) {
+                        const StepEnt e = E[sd.n_out + t];
+                        SO[t] = make_int2(e.f, ent_offset(e.xdig, xs));
+                    }
+                }
+                wave_sync();
+                if (valid) {
+                    for (int o = lane; o < sd.n_out; o += g) {
+                        const StepEnt e = E[o];
+                        const A *Fo = F + e.f;
+                        const S *Xo = slices + xbase + ent_offset(e.xdig, xs);
+                        A acc = A(0);
+                        for (int t = 0; t < sd.n_sum; ++t) {
+                            const int2 q = SO[t];
+                            acc += Fo[q.x] * SliceIO<S>::load(Xo, q.y);
+                        }
+                        G[o] = acc;
+                    }
+                }
+                wave_sync();
+                A *tmp = F;
+                F = G;
+                G = tmp;
+            }
+            if (valid) {
+                const int64_t wo = pn.w_base + gld(cd.iw + k);
+                for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
+            }
+            return;
+        }
         for (int st = 0; st < cd.n_steps; ++st) {
             const StepDesc &sd = s_steps[st];
-            const StepEnt *E = ents + sd.ent;
-            int xs[kMaxLab];
-            int64_t xbase = 0;
             if (valid) {
-                xbase = pn.slice_base + gld(&rec[st].xoff);
-#pragma unroll
+                const int64_t xbase = pn.slice_base + gld(&rec[st].xoff);
+                int xs[kMaxLab];
+    #pragma unroll
                 for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
-                for (int t = lane; t < sd.n_sum; t += g) {
-                    const StepEnt e = E[sd.n_out + t];
-                    SO[t] = make_int2(e.f, ent_offset(e.xdig, xs));
-                }
-            }
-            wave_sync();
-            if (valid) {
                 for (int o = lane; o < sd.n_out; o += g) {
-                    const StepEnt e = E[o];
-                    const A *Fo = F + e.f;
-                    const S *Xo = slices + xbase + ent_offset(e.xdig, xs);
+                    int rem = o, fb = 0, xb = 0;
+                    for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
+                        const int dd = sd.out_dim[kk];
+                        const int dg = rem % dd;
+                        rem /= dd;
+                        fb += dg * sd.out_fs[kk];
+                        const int xl = sd.out_xl[kk];
+                        if (xl >= 0) {
+    #pragma unroll
+                            for (int m = 0; m < kMaxLab; ++m)
+                                if (m == xl) xb += dg * xs[m];
+                        }
+                    }
+                    int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
+    #pragma unroll
+                    for (int kk = 0; kk < kMaxLab; ++kk) {
+                        sdg[kk] = 0;
+                        sfs[kk] = 0;
+                        sxs[kk] = 0;
+                        if (kk < sd.n_sl) {
+                            sfs[kk] = sd.sum_fs[kk];
+    #pragma unroll
+                            for (int m = 0; m < kMaxLab; ++m)
+                                if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
+                        }
+                    }
                     A acc = A(0);
+                    int fo = fb;
+                    int64_t xo = xbase + xb;
                     for (int t = 0; t < sd.n_sum; ++t) {
-                        const int2 q = SO[t];
-                        acc += Fo[q.x] * SliceIO<S>::load(Xo, q.y);
+                        acc += F[fo] * SliceIO<S>::load(slices, xo);
+    #pragma unroll
+                        for (int kk = kMaxLab - 1; kk >= 0; --kk) {
+                            if (kk >= sd.n_sl) continue;
+                            if (++sdg[kk] < sd.sum_dim[kk]) {
+                                fo += sfs[kk];
+                                xo += sxs[kk];
+                                break;
+                            }
+                            fo -= (sd.sum_dim[kk] - 1) * sfs[kk];
+                            xo -= (int64_t)(sd.sum_dim[kk] - 1) * sxs[kk];
+                            sdg[kk] = 0;
+                        }
                     }
                     G[o] = acc;
                 }
             }
+            // an instance's lanes lie in one wavefront (g divides 64), and F and
+            // G are its own: a wavefront-scope fence orders the step's LDS
+            // writes before the next step's reads, and the waves of the block
+            // run their steps independently
             wave_sync();
-            A *tmp = F;
+            A *t = F;
             F = G;
-            G = tmp;
+            G = t;
         }
         if (valid) {
             const int64_t wo = pn.w_base + gld(cd.iw + k);
             for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
         }
-        return;
-    }
-    for (int st = 0; st < cd.n_steps; ++st) {
-        const StepDesc &sd = s_steps[st];
-        if (valid) {
-            const int64_t xbase = pn.slice_base + gld(&rec[st].xoff);
-            int xs[kMaxLab];
-#pragma unroll
-            for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
-            for (int o = lane; o < sd.n_out; o += g) {
-                int rem = o, fb = 0, xb = 0;
-                for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
-                    const int dd = sd.out_dim[kk];
-                    const int dg = rem % dd;
-                    rem /= dd;
-                    fb += dg * sd.out_fs[kk];
-                    const int xl = sd.out_xl[kk];
-                    if (xl >= 0) {
-#pragma unroll
-                        for (int m = 0; m < kMaxLab; ++m)
-                            if (m == xl) xb += dg * xs[m];
-                    }
-                }
-                int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
-#pragma unroll
-                for (int kk = 0; kk < kMaxLab; ++kk) {
-                    sdg[kk] = 0;
-                    sfs[kk] = 0;
-                    sxs[kk] = 0;
-                    if (kk < sd.n_sl) {
-                        sfs[kk] = sd.sum_fs[kk];
-#pragma unroll
-                        for (int m = 0; m < kMaxLab; ++m)
-                            if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
-                    }
-                }
-                A acc = A(0);
-                int fo = fb;
-                int64_t xo = xbase + xb;
-                for (int t = 0; t < sd.n_sum; ++t) {
-                    acc += F[fo] * SliceIO<S>::load(slices, xo);
-#pragma unroll
-                    for (int kk = kMaxLab - 1; kk >= 0; --kk) {
-                        if (kk >= sd.n_sl) continue;
-                        if (++sdg[kk] < sd.sum_dim[kk]) {
-                            fo += sfs[kk];
-                            xo += sxs[kk];
-                            break;
-                        }
-                        fo -= (sd.sum_dim[kk] - 1) * sfs[kk];
-                        xo -= (int64_t)(sd.sum_dim[kk] - 1) * sxs[kk];
-                        sdg[kk] = 0;
-                    }
-                }
-                G[o] = acc;
-            }
-        }
-        // an instance's lanes lie in one wavefront (g divides 64), and F and
-        // G are its own: a wavefront-scope fence orders the step's LDS
-        // writes before the next step's reads, and the waves of the block
-        // run their steps independently
-        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-        A *t = F;
-        F = G;
-        G = t;
-    }
-    if (valid) {
-        const int64_t wo = pn.w_base + gld(cd.iw + k);
-        for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
     }
 }
 
@@ -755,24 +750,31 @@ hipError_t launch_regauge(const DeviceBatch &b, hipStream_t s) {
     return hipGetLastError();
 }
 
+template <typename S, int KIND>
+void launch_clusters_kind(const DeviceBatch &b, hipStream_t s) {
+    const int b0 = b.cl_kind_begin[KIND], n = b.cl_kind_begin[KIND + 1] - b0;
+    if (n > 0)
+        hipLaunchKernelGGL((k_clusters<S, KIND>), dim3(n), dim3(kClThreads), KIND == 0 ? b.cluster_lds : 0, s,
+                           b.classes, b.steps, b.step_ents, b.cblocks + b0, b.pnets, (const S *)b.slices, b.w);
+}
+
+template <typename S>
+void launch_clusters_t(const DeviceBatch &b, hipStream_t s) {
+    static_assert(DeviceBatch::kClKinds == 6, "cluster block kinds");
+    launch_clusters_kind<S, 0>(b, s);
+    launch_clusters_kind<S, 1>(b, s);
+    launch_clusters_kind<S, 2>(b, s);
+    launch_clusters_kind<S, 3>(b, s);
+    launch_clusters_kind<S, 4>(b, s);
+    launch_clusters_kind<S, 5>(b, s);
+}
+
 hipError_t launch_clusters(const DeviceBatch &b, hipStream_t s) {
     if (!b.n_cblocks) return hipSuccess;
     switch (b.precision) {
-        case 0:
-            hipLaunchKernelGGL(k_clusters<double>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.step_ents, b.cblocks, b.pnets,
-                               (const double *)b.slices, b.w);
-            break;
-        case 1:
-            hipLaunchKernelGGL(k_clusters<float>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s, b.classes,
-                               b.steps, b.step_ents, b.cblocks, b.pnets,
-                               (const float *)b.slices, b.w);
-            break;
-        default:
-            hipLaunchKernelGGL(k_clusters<uint16_t>, dim3(b.n_cblocks), dim3(kClThreads), b.cluster_lds, s,
-                               b.classes, b.steps, b.step_ents, b.cblocks, b.pnets,
-                               (const uint16_t *)b.slices, b.w);
-            break;
+        case 0: launch_clusters_t<double>(b, s); break;
+        case 1: launch_clusters_t<float>(b, s); break;
+        default: launch_clusters_t<uint16_t>(b, s); break;
     }
     return hipGetLastError();
 }

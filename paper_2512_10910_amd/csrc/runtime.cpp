@@ -1558,6 +1558,26 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(classes, classes);
     UP(steps, steps);
     UP(step_ents, step_ents);
+    // blocks by kernel path (frontier plans; cycles of leg dimension 2, 3, 4,
+    // 5; scalar products), each launched with the registers of its own
+    // path; order kept within a path
+    constexpr int kClKinds = DeviceBatch::kClKinds;
+    int cl_kind_begin[kClKinds + 1] = {};
+    {
+        auto kind = [&](const ClusterBlock &cb) {
+            const ClassDesc &cd = classes[cb.cls];
+            return cd.scalar ? kClKinds - 1 : (cd.loop_e ? cd.loop_e - 1 : 0);
+        };
+        std::vector<ClusterBlock> sorted;
+        sorted.reserve(cblocks.size());
+        for (int k = 0; k < kClKinds; ++k) {
+            cl_kind_begin[k] = (int)sorted.size();
+            for (const ClusterBlock &cb : cblocks)
+                if (kind(cb) == k) sorted.push_back(cb);
+        }
+        cl_kind_begin[kClKinds] = (int)sorted.size();
+        cblocks.swap(sorted);
+    }
     UP(cblocks, cblocks);
     UP(pnets, pnets);
     UP(crec, crec);
@@ -1591,6 +1611,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_fused_small = n_small;
     db.n_nets = n;
     db.n_cblocks = (int)cblocks.size();
+    for (int k = 0; k <= kClKinds; ++k) db.cl_kind_begin[k] = cl_kind_begin[k];
     db.bp_lds = bp_lds;
     db.regauge_lds = regauge_lds;
     db.cluster_lds = cl_lds;
