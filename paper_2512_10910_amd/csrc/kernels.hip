@@ -235,12 +235,28 @@ __device__ inline int xcd_block(int p, int nb) {
 }
 
 // Slice offset of a StepEnt's digits (4 bits per slice leg) under an
-// instance's leg strides.
+// instance's leg strides (below 2^24: the plan tables check it).
 __device__ __forceinline__ int ent_offset(uint32_t xdig, const int (&xs)[kMaxLab]) {
-    int x = 0;
+    unsigned x = 0;
 #pragma unroll
-    for (int m = 0; m < kMaxLab; ++m) x += (int)((xdig >> (4 * m)) & 15u) * xs[m];
-    return x;
+    for (int m = 0; m < kMaxLab; ++m) x += __umul24((xdig >> (4 * m)) & 15u, (unsigned)xs[m]);
+    return (int)x;
+}
+
+// acc + sum over N consecutive summed entries q of Fo[q.x] * Xo[q.y], in
+// order, with all N loads issued before the first product.
+template <int N, typename A, typename S>
+__device__ __forceinline__ A sum_entries(A acc, const int2 *q, const A *Fo, const S *Xo) {
+    A fv[N], xv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        const int2 e = q[i];
+        xv[i] = SliceIO<S>::load(Xo, e.y);
+        fv[i] = Fo[e.x];
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) acc += fv[i] * xv[i];
+    return acc;
 }
 
 // Orders the LDS accesses of the lanes of one wavefront (an instance's lanes
@@ -323,9 +339,13 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                 int xs[kMaxLab];
                 int64_t xbase = 0;
                 if (valid) {
-                    xbase = pn.slice_base + gld(&rec[st].xoff);
-    #pragma unroll
-                    for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
+                    // the record in three 16-byte loads (strides past n_xl are 0)
+                    static_assert(sizeof(InstStep) == 48 && kMaxLab == 8, "InstStep layout");
+                    const int4 *r4 = reinterpret_cast<const int4 *>(rec + st);
+                    const int4 ra = r4[0], rb = r4[1], rc = r4[2];
+                    xbase = pn.slice_base + ra.x;
+                    xs[0] = ra.y, xs[1] = ra.z, xs[2] = ra.w, xs[3] = rb.x;
+                    xs[4] = rb.y, xs[5] = rb.z, xs[6] = rb.w, xs[7] = rc.x;
                     for (int t = lane; t < sd.n_sum; t += g) {
                         const StepEnt e = E[sd.n_out + t];
                         SO[t] = make_int2(e.f, ent_offset(e.xdig, xs));
@@ -337,11 +357,17 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                         const StepEnt e = E[o];
                         const A *Fo = F + e.f;
                         const S *Xo = slices + xbase + ent_offset(e.xdig, xs);
+                        // summed entries four, then two, then one at a time:
+                        // a group's loads issue together, the products still
+                        // accumulate in order
                         A acc = A(0);
-                        for (int t = 0; t < sd.n_sum; ++t) {
-                            const int2 q = SO[t];
-                            acc += Fo[q.x] * SliceIO<S>::load(Xo, q.y);
+                        int t = 0;
+                        for (; t + 4 <= sd.n_sum; t += 4) acc = sum_entries<4>(acc, SO + t, Fo, Xo);
+                        if (t + 2 <= sd.n_sum) {
+                            acc = sum_entries<2>(acc, SO + t, Fo, Xo);
+                            t += 2;
                         }
+                        if (t < sd.n_sum) acc = sum_entries<1>(acc, SO + t, Fo, Xo);
                         G[o] = acc;
                     }
                 }
@@ -361,7 +387,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
             if (valid) {
                 const int64_t xbase = pn.slice_base + gld(&rec[st].xoff);
                 int xs[kMaxLab];
-    #pragma unroll
+#pragma unroll
                 for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
                 for (int o = lane; o < sd.n_out; o += g) {
                     int rem = o, fb = 0, xb = 0;
@@ -372,20 +398,20 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                         fb += dg * sd.out_fs[kk];
                         const int xl = sd.out_xl[kk];
                         if (xl >= 0) {
-    #pragma unroll
+#pragma unroll
                             for (int m = 0; m < kMaxLab; ++m)
                                 if (m == xl) xb += dg * xs[m];
                         }
                     }
                     int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
-    #pragma unroll
+#pragma unroll
                     for (int kk = 0; kk < kMaxLab; ++kk) {
                         sdg[kk] = 0;
                         sfs[kk] = 0;
                         sxs[kk] = 0;
                         if (kk < sd.n_sl) {
                             sfs[kk] = sd.sum_fs[kk];
-    #pragma unroll
+#pragma unroll
                             for (int m = 0; m < kMaxLab; ++m)
                                 if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
                         }
@@ -395,7 +421,7 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                     int64_t xo = xbase + xb;
                     for (int t = 0; t < sd.n_sum; ++t) {
                         acc += F[fo] * SliceIO<S>::load(slices, xo);
-    #pragma unroll
+#pragma unroll
                         for (int kk = kMaxLab - 1; kk >= 0; --kk) {
                             if (kk >= sd.n_sl) continue;
                             if (++sdg[kk] < sd.sum_dim[kk]) {

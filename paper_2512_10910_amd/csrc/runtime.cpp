@@ -41,6 +41,7 @@ struct PlanTables {
         const InstStep *tab;
         const int32_t *iw;
         int32_t n_inst, scalar, loop_e;
+        int32_t wide_stride;  // a slice stride >= 2^24 (the entry-table path multiplies in 24 bits)
     };
     std::vector<Cls> cls;  // per class of the plan
 };
@@ -222,6 +223,7 @@ void plan_tables_host(const GeoPlan *p, const Geometry &g, PlanTablesHost *h) {
         tab_off[c] = tab.size();
         iw_off[c] = iw.size();
         pc.n_inst = (int)p->inst_cluster[c].size();
+        pc.wide_stride = 0;
         pc.scalar = (cd.max_f == 1 && cd.out_size == 1) ? 1 : 0;
         const std::vector<int> &cyc = p->loop_order[c];
         pc.loop_e = 0;
@@ -255,6 +257,7 @@ void plan_tables_host(const GeoPlan *p, const Geometry &g, PlanTablesHost *h) {
                 for (int m = 0; m < sd.n_xl; ++m) {
                     const int64_t sm = stride_of(site, (int)((slots >> (4 * m)) & 15u));
                     r.xs[m] = (int32_t)sm;
+                    if (sm >= (int64_t(1) << 24)) pc.wide_stride = 1;
                     if (sd.x_excited[m]) xo += sm;  // excited indices start at 1
                 }
                 r.xoff = (int32_t)xo;
@@ -1402,6 +1405,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 cd.n_pnets = (int)pn.size();
                 cd.scalar = pc.scalar;
                 cd.loop_e = pc.loop_e;
+                if (pc.wide_stride) cd.max_sum = 0;
             }
             // blocks: networks in order, classes interleaved
             std::vector<int> pend_begin(ncls, 0), pend_count(ncls, 0);
