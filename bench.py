@@ -661,7 +661,7 @@ def beyond_mall(pne, P, steps: int, precision: str, K: int) -> dict:
     return m
 
 
-def workloads_bench(pne, P, steps: int):
+def workloads_bench(pne, P, steps: int, only: str = ""):
     """The other workloads at batch scale, one JSON line each: step time,
     networks/s, per-kernel device time (HIP events around every launch) with
     its algorithmic HBM bytes and roofline fraction, and a sampled check
@@ -700,6 +700,8 @@ def workloads_bench(pne, P, steps: int):
     ]
     sb = {"fp64": 8, "fp32": 4, "bf16": 2}
     for label, make, K, prec, check, parts_of, max_iter in cases + parted:
+        if only and only not in label:
+            continue
         nets_in = make()
         ctx = pne.Context(0)
         nets = [ctx.network(n) for n in nets_in]
@@ -776,6 +778,8 @@ def main():
     ap.add_argument("--serving-budget", type=float, default=2.0, help="serving device budget, GB")
     ap.add_argument("--workloads", action="store_true",
                     help="instead: the other workloads at batch scale with per-kernel rooflines")
+    ap.add_argument("--workload-filter", default="", metavar="TEXT",
+                    help="with --workloads: only the batch workloads whose label contains TEXT")
     ap.add_argument("--rank-large", type=int, default=0, metavar="N",
                     help="instead: only the chi = 16 rank-r workload (12x12 Ising, 3x3 blocks) on N lattices")
     ap.add_argument("--rank", type=int, default=0, metavar="N",
@@ -811,7 +815,9 @@ def main():
         sys.exit(1)
 
     if args.workloads:
-        workloads_bench(pne, P, max(1, min(args.steps, 5)))
+        workloads_bench(pne, P, max(1, min(args.steps, 5)), args.workload_filter)
+        if args.workload_filter:
+            return
         strips_bench(pne, P)
         rank_bench(pne, P)
         print(json.dumps(rank_large_bench(pne, P)), flush=True)
