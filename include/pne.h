@@ -50,7 +50,11 @@ typedef enum {
     PNE_ERR_SINGULAR = -4,         /* a bond overlap a.c ~ 0 or a vacuum factor == 0 */
     PNE_ERR_DEVICE = -5,           /* HIP runtime error or no usable device */
     PNE_ERR_NOT_READY = -6,        /* pne_poll: request still running */
-    PNE_ERR_CANCELLED = -7         /* pne_poll: the request was cancelled (pne_cancel) */
+    PNE_ERR_CANCELLED = -7,        /* pne_poll: the request was cancelled (pne_cancel) */
+    PNE_ERR_CHECK = -8             /* checked build (libpne_checked.so) only: a cluster
+                                      kernel index left its table, frontier or slice
+                                      buffer; the access was suppressed and the
+                                      network's result is invalid (a library bug)   */
 } pne_status;
 
 /* pne_options.flags bits */

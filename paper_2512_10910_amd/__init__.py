@@ -29,4 +29,5 @@ from .pne import (  # noqa: F401
     PNE_WARN_PRECISION,
     PNE_ERR_NOT_READY,
     PNE_ERR_CANCELLED,
+    PNE_ERR_CHECK,
 )

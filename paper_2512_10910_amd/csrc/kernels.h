@@ -79,6 +79,9 @@ struct DeviceBatch {
     const PlanNet *pnets = nullptr;       // per plan: its networks' slice and weight bases
     size_t cluster_lds = 0;
     double *w = nullptr;
+    int64_t n_slice_elems = 0;  // extents the checked build tests cluster indices against
+    int64_t n_w = 0;
+    int n_step_ents = 0;
     // combine
     const CombineRec *crec = nullptr;
     const int *combine_nets = nullptr;   // networks summed by the combine launch

@@ -15,6 +15,7 @@
 #include <cstdint>
 
 #include "kernels.h"
+#include "pne.h"
 #include "regauge.h"
 #include "terms.h"
 
@@ -243,16 +244,34 @@ __device__ __forceinline__ int ent_offset(uint32_t xdig, const int (&xs)[kMaxLab
     return (int)x;
 }
 
-// acc + sum over N consecutive summed entries q of Fo[q.x] * Xo[q.y], in
-// order, with all N loads issued before the first product.
+// Index check of the checked build (PNE_CHECKED): an index outside [0, n)
+// is noted in bad and replaced by 0, so the access stays inside its buffer
+// and the network reports PNE_ERR_CHECK.  Without PNE_CHECKED it is the
+// index itself.
+__device__ __forceinline__ int64_t chk(int64_t i, int64_t n, bool &bad) {
+#ifdef PNE_CHECKED
+    const bool ok = i >= 0 && i < n;
+    bad = bad || !ok;
+    return ok ? i : 0;
+#else
+    (void)n;
+    (void)bad;
+    return i;
+#endif
+}
+
+// acc + sum over N consecutive summed entries q of F[fb + q.x] *
+// slices[xb + q.y], in order, with all N loads issued before the first
+// product.
 template <int N, typename A, typename S>
-__device__ __forceinline__ A sum_entries(A acc, const int2 *q, const A *Fo, const S *Xo) {
+__device__ __forceinline__ A sum_entries(A acc, const int2 *q, const A *F, int fb, int max_f, const S *slices,
+                                         int64_t xb, int64_t n_slices, bool &bad) {
     A fv[N], xv[N];
 #pragma unroll
     for (int i = 0; i < N; ++i) {
         const int2 e = q[i];
-        xv[i] = SliceIO<S>::load(Xo, e.y);
-        fv[i] = Fo[e.x];
+        xv[i] = SliceIO<S>::load(slices, chk(xb + e.y, n_slices, bad));
+        fv[i] = F[chk(fb + e.x, max_f, bad)];
     }
 #pragma unroll
     for (int i = 0; i < N; ++i) acc += fv[i] * xv[i];
@@ -281,15 +300,18 @@ __device__ __forceinline__ void wave_sync() {
 // blocks' path (0 frontier plans, 1-4 cycles of leg dimension KIND + 1, 5
 // scalar products): each path is its own launch, so one path's registers
 // (a dimension-5 cycle's matrices) do not lower the occupancy of another.
+// n_slices, n_w and n_ents are the extents the checked build tests indices
+// against; st receives its PNE_ERR_CHECK.
 template <typename S, int KIND>
 __global__ void __launch_bounds__(kClThreads) k_clusters(
     const ClassDesc *__restrict__ classes, const StepDesc *__restrict__ steps, const StepEnt *__restrict__ ents,
     const ClusterBlock *__restrict__ blocks, const PlanNet *__restrict__ pnets, const S *__restrict__ slices,
-    double *__restrict__ w) {
+    double *__restrict__ w, int64_t n_slices, int64_t n_w, int n_ents, NetState *st) {
     using A = typename SliceIO<S>::acc;
     const ClusterBlock blk = blocks[xcd_block(blockIdx.x, gridDim.x)];
     const ClassDesc cd = classes[blk.cls];
     const int tid = threadIdx.x;
+    bool bad = false;
     if constexpr (KIND >= 1 && KIND <= 4) {
         if (tid >= blk.count) return;
         const int f = blk.flat_begin + tid;
@@ -297,8 +319,20 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         const int k = f - net * cd.n_inst;
         const PlanNet pn = pnets[cd.pnet_begin + net];
         const InstStep *rec = cd.tab + (int64_t)k * cd.n_verts;
+#ifdef PNE_CHECKED
+        // every element the cycle reads: offsets xoff + a x0 + b x1, a, b < E
+        for (int j = 0; j < cd.n_verts; ++j) {
+            const int64_t lo = pn.slice_base + gld(&rec[j].xoff);
+            const int64_t hi = lo + (int64_t)KIND * ((int64_t)gld(&rec[j].xs[0]) + gld(&rec[j].xs[1]));
+            chk(lo, n_slices, bad);
+            chk(hi, n_slices, bad);
+        }
+        const A v = bad ? A(0) : loop_trace<KIND + 1, S>(rec, cd.n_verts, slices, pn.slice_base);
+#else
         const A v = loop_trace<KIND + 1, S>(rec, cd.n_verts, slices, pn.slice_base);
-        w[pn.w_base + gld(cd.iw + k)] = (double)v;
+#endif
+        w[chk(pn.w_base + gld(cd.iw + k), n_w, bad)] = (double)v;
+        if (bad) atomicMin(&st[pn.net].status, PNE_ERR_CHECK);
         return;
     } else if constexpr (KIND == 5) {
         if (tid >= blk.count) return;
@@ -308,8 +342,10 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         const PlanNet pn = pnets[cd.pnet_begin + net];
         const InstStep *rec = cd.tab + (int64_t)k * cd.n_steps;
         A prod = A(1);
-        for (int st = 0; st < cd.n_steps; ++st) prod *= SliceIO<S>::load(slices, pn.slice_base + gld(&rec[st].xoff));
-        w[pn.w_base + gld(cd.iw + k)] = (double)prod;
+        for (int st2 = 0; st2 < cd.n_steps; ++st2)
+            prod *= SliceIO<S>::load(slices, chk(pn.slice_base + gld(&rec[st2].xoff), n_slices, bad));
+        w[chk(pn.w_base + gld(cd.iw + k), n_w, bad)] = (double)prod;
+        if (bad) atomicMin(&st[pn.net].status, PNE_ERR_CHECK);
         return;
     } else {
         extern __shared__ double lds_raw[];
@@ -333,42 +369,41 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
         if (cd.max_sum > 0) {
             int2 *SO = reinterpret_cast<int2 *>(reinterpret_cast<A *>(lds_raw) + (size_t)(kClThreads / g) * 2 * cd.max_f) +
                        (size_t)slot * cd.max_sum;
-            for (int st = 0; st < cd.n_steps; ++st) {
-                const StepDesc &sd = s_steps[st];
-                const StepEnt *E = ents + sd.ent;
+            for (int st2 = 0; st2 < cd.n_steps; ++st2) {
+                const StepDesc &sd = s_steps[st2];
                 int xs[kMaxLab];
                 int64_t xbase = 0;
                 if (valid) {
                     // the record in three 16-byte loads (strides past n_xl are 0)
                     static_assert(sizeof(InstStep) == 48 && kMaxLab == 8, "InstStep layout");
-                    const int4 *r4 = reinterpret_cast<const int4 *>(rec + st);
+                    const int4 *r4 = reinterpret_cast<const int4 *>(rec + st2);
                     const int4 ra = r4[0], rb = r4[1], rc = r4[2];
                     xbase = pn.slice_base + ra.x;
                     xs[0] = ra.y, xs[1] = ra.z, xs[2] = ra.w, xs[3] = rb.x;
                     xs[4] = rb.y, xs[5] = rb.z, xs[6] = rb.w, xs[7] = rc.x;
                     for (int t = lane; t < sd.n_sum; t += g) {
-                        const StepEnt e = E[sd.n_out + t];
-                        SO[t] = make_int2(e.f, ent_offset(e.xdig, xs));
+                        const StepEnt e = ents[chk(sd.ent + sd.n_out + t, n_ents, bad)];
+                        SO[chk(t, cd.max_sum, bad)] = make_int2(e.f, ent_offset(e.xdig, xs));
                     }
                 }
                 wave_sync();
                 if (valid) {
                     for (int o = lane; o < sd.n_out; o += g) {
-                        const StepEnt e = E[o];
-                        const A *Fo = F + e.f;
-                        const S *Xo = slices + xbase + ent_offset(e.xdig, xs);
+                        const StepEnt e = ents[chk(sd.ent + o, n_ents, bad)];
+                        const int64_t xb = xbase + ent_offset(e.xdig, xs);
                         // summed entries four, then two, then one at a time:
                         // a group's loads issue together, the products still
                         // accumulate in order
                         A acc = A(0);
                         int t = 0;
-                        for (; t + 4 <= sd.n_sum; t += 4) acc = sum_entries<4>(acc, SO + t, Fo, Xo);
+                        for (; t + 4 <= sd.n_sum; t += 4)
+                            acc = sum_entries<4>(acc, SO + t, F, e.f, cd.max_f, slices, xb, n_slices, bad);
                         if (t + 2 <= sd.n_sum) {
-                            acc = sum_entries<2>(acc, SO + t, Fo, Xo);
+                            acc = sum_entries<2>(acc, SO + t, F, e.f, cd.max_f, slices, xb, n_slices, bad);
                             t += 2;
                         }
-                        if (t < sd.n_sum) acc = sum_entries<1>(acc, SO + t, Fo, Xo);
-                        G[o] = acc;
+                        if (t < sd.n_sum) acc = sum_entries<1>(acc, SO + t, F, e.f, cd.max_f, slices, xb, n_slices, bad);
+                        G[chk(o, cd.max_f, bad)] = acc;
                     }
                 }
                 wave_sync();
@@ -376,79 +411,76 @@ __global__ void __launch_bounds__(kClThreads) k_clusters(
                 F = G;
                 G = tmp;
             }
-            if (valid) {
-                const int64_t wo = pn.w_base + gld(cd.iw + k);
-                for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
-            }
-            return;
-        }
-        for (int st = 0; st < cd.n_steps; ++st) {
-            const StepDesc &sd = s_steps[st];
-            if (valid) {
-                const int64_t xbase = pn.slice_base + gld(&rec[st].xoff);
-                int xs[kMaxLab];
+        } else {
+            for (int st2 = 0; st2 < cd.n_steps; ++st2) {
+                const StepDesc &sd = s_steps[st2];
+                if (valid) {
+                    const int64_t xbase = pn.slice_base + gld(&rec[st2].xoff);
+                    int xs[kMaxLab];
 #pragma unroll
-                for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st].xs[m]) : 0;
-                for (int o = lane; o < sd.n_out; o += g) {
-                    int rem = o, fb = 0, xb = 0;
-                    for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
-                        const int dd = sd.out_dim[kk];
-                        const int dg = rem % dd;
-                        rem /= dd;
-                        fb += dg * sd.out_fs[kk];
-                        const int xl = sd.out_xl[kk];
-                        if (xl >= 0) {
+                    for (int m = 0; m < kMaxLab; ++m) xs[m] = m < sd.n_xl ? gld(&rec[st2].xs[m]) : 0;
+                    for (int o = lane; o < sd.n_out; o += g) {
+                        int rem = o, fb = 0, xb = 0;
+                        for (int kk = sd.n_ol - 1; kk >= 0; --kk) {
+                            const int dd = sd.out_dim[kk];
+                            const int dg = rem % dd;
+                            rem /= dd;
+                            fb += dg * sd.out_fs[kk];
+                            const int xl = sd.out_xl[kk];
+                            if (xl >= 0) {
 #pragma unroll
-                            for (int m = 0; m < kMaxLab; ++m)
-                                if (m == xl) xb += dg * xs[m];
-                        }
-                    }
-                    int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
-#pragma unroll
-                    for (int kk = 0; kk < kMaxLab; ++kk) {
-                        sdg[kk] = 0;
-                        sfs[kk] = 0;
-                        sxs[kk] = 0;
-                        if (kk < sd.n_sl) {
-                            sfs[kk] = sd.sum_fs[kk];
-#pragma unroll
-                            for (int m = 0; m < kMaxLab; ++m)
-                                if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
-                        }
-                    }
-                    A acc = A(0);
-                    int fo = fb;
-                    int64_t xo = xbase + xb;
-                    for (int t = 0; t < sd.n_sum; ++t) {
-                        acc += F[fo] * SliceIO<S>::load(slices, xo);
-#pragma unroll
-                        for (int kk = kMaxLab - 1; kk >= 0; --kk) {
-                            if (kk >= sd.n_sl) continue;
-                            if (++sdg[kk] < sd.sum_dim[kk]) {
-                                fo += sfs[kk];
-                                xo += sxs[kk];
-                                break;
+                                for (int m = 0; m < kMaxLab; ++m)
+                                    if (m == xl) xb += dg * xs[m];
                             }
-                            fo -= (sd.sum_dim[kk] - 1) * sfs[kk];
-                            xo -= (int64_t)(sd.sum_dim[kk] - 1) * sxs[kk];
-                            sdg[kk] = 0;
                         }
+                        int sfs[kMaxLab], sxs[kMaxLab], sdg[kMaxLab];
+#pragma unroll
+                        for (int kk = 0; kk < kMaxLab; ++kk) {
+                            sdg[kk] = 0;
+                            sfs[kk] = 0;
+                            sxs[kk] = 0;
+                            if (kk < sd.n_sl) {
+                                sfs[kk] = sd.sum_fs[kk];
+#pragma unroll
+                                for (int m = 0; m < kMaxLab; ++m)
+                                    if (m == sd.sum_xl[kk]) sxs[kk] = xs[m];
+                            }
+                        }
+                        A acc = A(0);
+                        int fo = fb;
+                        int64_t xo = xbase + xb;
+                        for (int t = 0; t < sd.n_sum; ++t) {
+                            acc += F[chk(fo, cd.max_f, bad)] * SliceIO<S>::load(slices, chk(xo, n_slices, bad));
+#pragma unroll
+                            for (int kk = kMaxLab - 1; kk >= 0; --kk) {
+                                if (kk >= sd.n_sl) continue;
+                                if (++sdg[kk] < sd.sum_dim[kk]) {
+                                    fo += sfs[kk];
+                                    xo += sxs[kk];
+                                    break;
+                                }
+                                fo -= (sd.sum_dim[kk] - 1) * sfs[kk];
+                                xo -= (int64_t)(sd.sum_dim[kk] - 1) * sxs[kk];
+                                sdg[kk] = 0;
+                            }
+                        }
+                        G[chk(o, cd.max_f, bad)] = acc;
                     }
-                    G[o] = acc;
                 }
+                // an instance's lanes lie in one wavefront (g divides 64), and F and
+                // G are its own: a wavefront-scope fence orders the step's LDS
+                // writes before the next step's reads, and the waves of the block
+                // run their steps independently
+                wave_sync();
+                A *t = F;
+                F = G;
+                G = t;
             }
-            // an instance's lanes lie in one wavefront (g divides 64), and F and
-            // G are its own: a wavefront-scope fence orders the step's LDS
-            // writes before the next step's reads, and the waves of the block
-            // run their steps independently
-            wave_sync();
-            A *t = F;
-            F = G;
-            G = t;
         }
         if (valid) {
             const int64_t wo = pn.w_base + gld(cd.iw + k);
-            for (int o = lane; o < cd.out_size; o += g) w[wo + o] = (double)F[o];
+            for (int o = lane; o < cd.out_size; o += g) w[chk(wo + o, n_w, bad)] = (double)F[chk(o, cd.max_f, bad)];
+            if (bad) atomicMin(&st[pn.net].status, PNE_ERR_CHECK);
         }
     }
 }
@@ -781,7 +813,8 @@ void launch_clusters_kind(const DeviceBatch &b, hipStream_t s) {
     const int b0 = b.cl_kind_begin[KIND], n = b.cl_kind_begin[KIND + 1] - b0;
     if (n > 0)
         hipLaunchKernelGGL((k_clusters<S, KIND>), dim3(n), dim3(kClThreads), KIND == 0 ? b.cluster_lds : 0, s,
-                           b.classes, b.steps, b.step_ents, b.cblocks + b0, b.pnets, (const S *)b.slices, b.w);
+                           b.classes, b.steps, b.step_ents, b.cblocks + b0, b.pnets, (const S *)b.slices, b.w,
+                           b.n_slice_elems, b.n_w, b.n_step_ents, b.state);
 }
 
 template <typename S>

@@ -166,6 +166,8 @@ struct InstStep {
 struct PlanNet {
     int64_t slice_base;  // element offset of the network's first slice
     int64_t w_base;      // offset of the network's first cluster weight
+    int32_t net;         // the network's index in the batch
+    int32_t pad;
 };
 
 // A block of cluster work: `count` consecutive instances of one class.

@@ -1394,7 +1394,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 }
             }
             const int pnet_begin = (int)pnets.size();
-            for (int i : pn) pnets.push_back(PlanNet{sites[b->site_base[i]].slice_off, b->w_base[i]});
+            for (int i : pn) pnets.push_back(PlanNet{sites[b->site_base[i]].slice_off, b->w_base[i], i, 0});
             for (int c = 0; c < ncls; ++c) {
                 ClassDesc &cd = classes[c0 + c];
                 const PlanTables::Cls &pc = pt->cls[c];
@@ -1562,6 +1562,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     UP(classes, classes);
     UP(steps, steps);
     UP(step_ents, step_ents);
+    db.n_step_ents = (int)step_ents.size();
     // blocks by kernel path (frontier plans; cycles of leg dimension 2, 3, 4,
     // 5; scalar products), each launched with the registers of its own
     // path; order kept within a path
@@ -1629,6 +1630,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     AL(sizeof(double) * msg, msg0, double *);
     AL(sizeof(double) * msg, msg1, double *);
     AL(esz * std::max<int64_t>(sl, 1), slices, void *);
+    db.n_slice_elems = sl;
+    db.n_w = wtot;
     AL(sizeof(double) * sites.size(), site_log, double *);
     AL(sizeof(int) * sites.size(), site_sign, int *);
     AL(sizeof(double) * std::max<int64_t>(vac, 1), vac, double *);

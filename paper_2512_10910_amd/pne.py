@@ -16,7 +16,9 @@ from dataclasses import dataclass, field
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libpne.so")
+# PNE_CHECKED=1 in the environment selects the checked build (cluster
+# kernel index checks compiled in, PNE_ERR_CHECK on a failed check)
+LIB_PATH = os.path.join(_HERE, "libpne_checked.so" if os.environ.get("PNE_CHECKED") == "1" else "libpne.so")
 
 PNE_OK = 0
 PNE_WARN_BP_NOT_CONVERGED = 1
@@ -28,6 +30,7 @@ PNE_ERR_SINGULAR = -4
 PNE_ERR_DEVICE = -5
 PNE_ERR_NOT_READY = -6
 PNE_ERR_CANCELLED = -7
+PNE_ERR_CHECK = -8
 
 PRECISIONS = {"fp64": 0, "fp32": 1, "bf16": 2}
 MODES = {"loop": 0, "full": 1, "cumulant": 2}

@@ -46,6 +46,18 @@ def test_every_declared_symbol_is_exported(lib):
     assert set(names) <= set(B._PROTOS), set(names) - set(B._PROTOS)
 
 
+def test_checked_build_exports_the_same_symbols(lib):
+    """libpne_checked.so (cluster index checks compiled in) is built beside
+    libpne.so and exports every declared entry point too."""
+    from paper_2512_10910_amd import build
+
+    assert os.path.exists(build.LIB_CHECKED)
+    chk = ctypes.CDLL(build.LIB_CHECKED)
+    for n in _declared_functions():
+        assert hasattr(chk, n), n
+    assert B.PNE_ERR_CHECK == -8 and "PNE_ERR_CHECK = -8" in open(HEADER).read()
+
+
 def test_struct_layout_matches_header(tmp_path):
     src = tmp_path / "layout.c"
     src.write_text(r'''
