@@ -24,9 +24,17 @@
 
 using namespace pne;
 
+struct SiteLayout {
+    std::vector<std::pair<std::vector<int>, std::vector<int>>> groups;  // leg dims -> sites, in dims order
+    std::vector<int> colour;     // two-colouring of the site graph (meaningful when bipartite)
+    bool bipartite = false;
+    std::vector<int> slot_site;  // site of each global slot
+};
+
 struct PlanEntry {
     std::shared_ptr<Geometry> geo;
     std::map<int, std::shared_ptr<GeoPlan>> plans;  // by K, with bit 8 set for the complete-expansion mode
+    std::shared_ptr<const SiteLayout> layout;       // built on first use
 };
 
 // Device instance tables of one plan, built and uploaded once per context:
@@ -162,8 +170,50 @@ pne_status hip_fail(pne_ctx *ctx, hipError_t e, const char *what) {
         if (e_ != hipSuccess) return hip_fail(ctx, e_, #expr); \
     } while (0)
 
+// Site layout of a geometry for the BP tables, built once per cached
+// geometry: sites grouped by their leg-dimension tuple (tuple order), the
+// two-colouring of the site graph, and each slot's site.
+SiteLayout build_site_layout(const Geometry &g) {
+    SiteLayout L;
+    std::map<std::vector<int>, std::vector<int>> groups;
+    for (int s = 0; s < g.n_sites; ++s)
+        groups[std::vector<int>(g.dim.begin() + g.slot_base[s], g.dim.begin() + g.slot_base[s + 1])].push_back(s);
+    L.groups.assign(groups.begin(), groups.end());
+    L.slot_site.resize(g.slot_base[g.n_sites]);
+    for (int s = 0; s < g.n_sites; ++s)
+        for (int k = g.slot_base[s]; k < g.slot_base[s + 1]; ++k) L.slot_site[k] = s;
+    L.colour.assign(g.n_sites, -1);
+    bool bip = g.n_sites > 1;
+    std::vector<std::vector<int>> adj(g.n_sites);
+    for (int bb = 0; bb < g.n_bonds; ++bb) {
+        adj[g.bu[bb]].push_back(g.bv[bb]);
+        adj[g.bv[bb]].push_back(g.bu[bb]);
+    }
+    std::vector<int> queue;
+    for (int s0 = 0; s0 < g.n_sites && bip; ++s0) {
+        if (L.colour[s0] >= 0) continue;
+        L.colour[s0] = 0;
+        queue.assign(1, s0);
+        for (size_t h = 0; h < queue.size() && bip; ++h) {
+            const int u = queue[h];
+            for (int v : adj[u]) {
+                if (L.colour[v] < 0) {
+                    L.colour[v] = 1 - L.colour[u];
+                    queue.push_back(v);
+                } else if (L.colour[v] == L.colour[u]) {
+                    bip = false;
+                    break;
+                }
+            }
+        }
+    }
+    L.bipartite = bip;
+    return L;
+}
+
 std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> &g, int K, bool full,
-                                  std::string *err, std::shared_ptr<Geometry> *canon) {
+                                  std::string *err, std::shared_ptr<Geometry> *canon,
+                                  std::shared_ptr<const SiteLayout> *layout) {
     std::lock_guard<std::mutex> lk(ctx->mu);
     auto range = ctx->cache.equal_range(g->hash);
     PlanEntry *pe = nullptr;
@@ -177,6 +227,10 @@ std::shared_ptr<GeoPlan> get_plan(pne_ctx *ctx, const std::shared_ptr<Geometry> 
         pe = &it->second;
     }
     if (canon) *canon = pe->geo;
+    if (layout) {
+        if (!pe->layout) pe->layout = std::make_shared<const SiteLayout>(build_site_layout(*pe->geo));
+        *layout = pe->layout;
+    }
     const int key = K | (full ? 1 << 8 : 0);  // K <= 32
     auto f = pe->plans.find(key);
     if (f != pe->plans.end()) return f->second;
@@ -960,11 +1014,14 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     const int prec = opt->precision;
     const size_t esz = prec == PNE_FP64 ? 8 : prec == PNE_FP32 ? 4 : 2;
 
-    // plans
+    // plans, and each geometry's site layout
+    std::vector<std::shared_ptr<const SiteLayout>> layouts;
+    layouts.reserve(n);
     for (int i = 0; i < n; ++i) {
         std::string err;
         std::shared_ptr<Geometry> canon;
-        auto p = get_plan(ctx, nets[i]->geo, K, opt->mode == PNE_MODE_FULL, &err, &canon);
+        std::shared_ptr<const SiteLayout> lay;
+        auto p = get_plan(ctx, nets[i]->geo, K, opt->mode == PNE_MODE_FULL, &err, &canon, &lay);
         if (!p) {
             bool unsup = err.rfind("unsupported", 0) == 0;
             return fail(ctx, unsup ? PNE_ERR_UNSUPPORTED : PNE_ERR_INVALID_ARG, err);
@@ -977,11 +1034,18 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 return fail(ctx, PNE_ERR_UNSUPPORTED, "unsupported: the second-order cumulant form needs K < 3 x the smallest cluster");
         }
         b->plans.push_back(p);
+        layouts.push_back(std::move(lay));
     }
 
     // sites, messages, transforms, slices
     std::vector<SiteRec> sites;
     std::vector<int> net_of_site;
+    {
+        size_t total_sites = 0;
+        for (int i = 0; i < n; ++i) total_sites += (size_t)nets[i]->geo->n_sites;
+        sites.reserve(total_sites);
+        net_of_site.reserve(total_sites);
+    }
     int64_t msg = 0, sl = 0, vac = 0;
     b->site_base.resize(n);
     for (int i = 0; i < n; ++i) {
@@ -1031,9 +1095,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         for (int s = 0; s < g.n_sites; ++s) {
             SiteRec &r = sites[base + s];
             for (int l = 0; l < r.rank; ++l) {
-                int p = g.partner[g.slot(s, l)];
-                int ps = (int)(std::upper_bound(g.slot_base.begin(), g.slot_base.end(), p) - g.slot_base.begin()) - 1;
-                int pl = p - g.slot_base[ps];
+                const int p = g.partner[g.slot(s, l)];
+                const int ps = layouts[i]->slot_site[p];
+                const int pl = p - g.slot_base[ps];
                 r.dst[l] = sites[base + ps].msg_off + sites[base + ps].moff[pl];
             }
         }
@@ -1070,16 +1134,12 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     for (int i = 0; i < n; ++i) {
         const Geometry &g = *nets[i]->geo;
         int base = b->site_base[i];
-        std::map<std::vector<int>, std::vector<int>> groups;
+        const SiteLayout &lay = *layouts[i];
         bool first_tile_of_net = true;
-        for (int s = 0; s < g.n_sites; ++s) {
-            std::vector<int> key(g.dim.begin() + g.slot_base[s], g.dim.begin() + g.slot_base[s + 1]);
-            groups[key].push_back(base + s);
-        }
         const int tile_begin = (int)tiles.size();
         bool all_reg = g.n_open == 0;
-        for (auto &kv : groups) {
-            const SiteRec &r0 = sites[kv.second[0]];
+        for (auto &kv : lay.groups) {
+            const SiteRec &r0 = sites[base + kv.second[0]];
             int nos = 0;
             for (int l = 0; l < r0.rank; ++l) nos += r0.dim[l];
             const int last = r0.dim[r0.rank - 1];
@@ -1112,7 +1172,7 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                 t.dc = dc;
                 t.reg = reg_spt > 0 ? 1 : 0;
                 first_tile_of_net = false;
-                for (int j = 0; j < t.n_sites; ++j) tile_sites.push_back(kv.second[k + j]);
+                for (int j = 0; j < t.n_sites; ++j) tile_sites.push_back(base + kv.second[k + j]);
                 const size_t need = t.reg ? (size_t)t.n_sites * nos * 8
                                           : bp_tile_lds_doubles(t.n_sites, r0.size, nos, last, maxd) * 8;
                 tiles.push_back(t);
@@ -1128,47 +1188,22 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         }
         const int msg_size = (int)(msg_hi - msg_lo);
         int pscratch = 0;
-        for (auto &kv : groups) {
-            const SiteRec &r0 = sites[kv.second[0]];
+        for (auto &kv : lay.groups) {
+            const SiteRec &r0 = sites[base + kv.second[0]];
             const int spw = bp_persistent_sites_per_tile(r0.dim[0], r0.rank);
             if (spw > 0)
                 pscratch = std::max(pscratch, bp_persistent_scratch(spw, r0.rank, r0.dim[0], tiles_for(r0.dim[0], r0.rank)));
         }
         // two-colouring of the site graph for the red-black schedule
-        std::vector<int> colour(g.n_sites, -1);
-        bool bip = !(opt->flags & PNE_FLAG_BP_JACOBI) && g.n_sites > 1;
-        if (bip) {
-            std::vector<std::vector<int>> adj(g.n_sites);
-            for (int bb = 0; bb < g.n_bonds; ++bb) {
-                adj[g.bu[bb]].push_back(g.bv[bb]);
-                adj[g.bv[bb]].push_back(g.bu[bb]);
-            }
-            std::vector<int> queue;
-            for (int s0 = 0; s0 < g.n_sites && bip; ++s0) {
-                if (colour[s0] >= 0) continue;
-                colour[s0] = 0;
-                queue.assign(1, s0);
-                for (size_t h = 0; h < queue.size() && bip; ++h) {
-                    const int u = queue[h];
-                    for (int v : adj[u]) {
-                        if (colour[v] < 0) {
-                            colour[v] = 1 - colour[u];
-                            queue.push_back(v);
-                        } else if (colour[v] == colour[u]) {
-                            bip = false;
-                            break;
-                        }
-                    }
-                }
-            }
-        }
+        const std::vector<int> &colour = lay.colour;
+        const bool bip = !(opt->flags & PNE_FLAG_BP_JACOBI) && lay.bipartite;
         // gauge + slices inside the persistent block when every shape has a
         // register-path regauge; its per-wave transform table shares the scratch
         // (dropped again when the larger scratch would not fit the LDS budget)
         bool rg_inline = !(opt->flags & PNE_FLAG_SEPARATE_REGAUGE);
         int rg_scratch = pscratch;
-        for (auto &kv : groups) {
-            const SiteRec &r0 = sites[kv.second[0]];
+        for (auto &kv : lay.groups) {
+            const SiteRec &r0 = sites[base + kv.second[0]];
             if (!bp_persistent_regauge_supported(r0.dim[0], r0.rank)) {
                 rg_inline = false;
                 break;
@@ -1200,8 +1235,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
             f.rg_inline = rg_inline ? 1 : 0;
             net_rg_inline[i] = rg_inline ? 1 : 0;
             for (int c = 0; c < f.colors; ++c)
-                for (auto &kv : groups) {
-                    const SiteRec &r0 = sites[kv.second[0]];
+                for (auto &kv : lay.groups) {
+                    const SiteRec &r0 = sites[base + kv.second[0]];
                     FusedGroup fg;
                     std::memset(&fg, 0, sizeof fg);
                     fg.dc = r0.dim[0];
@@ -1210,8 +1245,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
                     fg.nt = tiles_for(fg.dc, fg.rank);
                     fg.color = c;
                     fg.list_off = (int)fsite_list.size() - f.list_begin;
-                    for (int gs : kv.second)
-                        if (!bip || colour[gs - base] == c) fsite_list.push_back(gs - base);
+                    for (int ls : kv.second)
+                        if (!bip || colour[ls] == c) fsite_list.push_back(ls);
                     fg.n_sites = (int)fsite_list.size() - f.list_begin - fg.list_off;
                     if (fg.n_sites > 0) fgroups.push_back(fg);
                 }
