@@ -2,17 +2,19 @@
 //
 // Clients submit networks from any thread (pne_submit copies the descriptor
 // and the host tensors) and collect results with pne_poll (or learn which
-// tickets finished from pne_server_completed).  Two threads own the context:
-// the worker admits pending requests in arrival order while their estimated
-// device bytes fit the memory budget, groups requests with identical options
-// into one batch (plans are cached per lattice, so a batch of mixed lattices
-// shares nothing but the launches), and keeps up to `pipeline_depth` batches
-// in flight on separate streams, so the host work of the next batch
-// (validation, uploads, tables) overlaps the device work of the current one;
-// the completion thread hands a batch's results out as soon as the device
-// has finished it.  A batch's networks stay resident from admission until its
-// results are copied back.  Each network's result does not depend on which
-// other networks share its batch.
+// tickets finished from pne_server_completed).  Three threads own the
+// context: the worker admits pending requests in arrival order while their
+// estimated device bytes fit the memory budget, groups requests with
+// identical options into one batch (plans are cached per lattice, so a batch
+// of mixed lattices shares nothing but the launches), and keeps up to
+// `pipeline_depth` batches being launched or in flight on separate streams,
+// so the host work of the next batch (validation, uploads, tables) overlaps
+// the device work of the current one; the launcher launches prepared batches
+// in order (a batch whose networks sweep BP launch by launch waits on the
+// device between sweep chunks); the completion thread hands a batch's
+// results out as soon as the device has finished it.  A batch's networks
+// stay resident from admission until its results are copied back.  Each
+// network's result does not depend on which other networks share its batch.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -99,8 +101,16 @@ struct pne_server {
     bool stop = false;        // no more submissions: finish what is queued, then end the worker
     bool stop_done = false;   // the worker has ended: end the completion thread
     size_t in_use = 0;
-    std::thread worker;       // admission, preparation and launch
+    std::thread worker;       // admission and preparation
+    std::thread launcher;     // launches prepared batches in order
     std::thread completer;    // waits for launched batches and hands out their results
+    // A batch with networks swept launch by launch waits on the device
+    // between its sweep chunks inside pne_batch_launch; launching on a thread
+    // of its own lets the worker prepare the next batch meanwhile.
+    std::condition_variable cv_launch;  // wakes the launcher
+    std::deque<InFlight> to_launch;     // prepared, oldest first (the worker appends, the launcher pops)
+    int launching = 0;                  // batches prepared and not yet in flight
+    bool stop_launch = false;           // the worker has ended: end the launcher
     std::condition_variable cv_done;   // wakes the completion thread
     std::deque<InFlight> inflight;     // launched, oldest first (the worker appends, the completer pops)
     std::vector<InFlight> graveyard;   // finished; freed while nothing is in flight (frees synchronise)
@@ -113,7 +123,7 @@ struct pne_server {
     std::vector<double> latencies;  // seconds, completed requests
     int64_t submitted = 0, completed = 0, failed = 0, batches = 0;
     double busy_s = 0.0;
-    double prep_s = 0.0;  // worker time creating networks and batches and launching
+    double prep_s = 0.0;  // time creating networks and batches (worker) and launching (launcher)
     void *staging = nullptr;  // pinned upload staging of the worker
     size_t staging_bytes = 0;
     // tensor uploads run on their own stream (never behind a batch's
@@ -190,10 +200,10 @@ void release(pne_server *sv, InFlight &f) {
     sv->in_use -= std::min(sv->in_use, f.bytes);
 }
 
-// Upload the requests' tensors, create their networks and one batch on
-// stream s, and launch it.  Requests that fail are finished here; false when
-// nothing was launched (f then holds whatever must be released).
-bool prepare_and_launch(pne_server *sv, const std::vector<Request *> &take, hipStream_t s, InFlight &f) {
+// Upload the requests' tensors and create their networks and one batch on
+// stream s.  Requests that fail are finished here; false when no batch was
+// made (f then holds whatever must be released).
+bool prepare_batch(pne_server *sv, const std::vector<Request *> &take, hipStream_t s, InFlight &f) {
     const Clock::time_point tp0 = Clock::now();
     for (Request *r : take) f.bytes += r->est_bytes;
     // every request's tensors in one device allocation, uploaded by one copy
@@ -262,26 +272,60 @@ bool prepare_and_launch(pne_server *sv, const std::vector<Request *> &take, hipS
     if (f.nets.empty()) return false;
     pne_status st = pne::batch_create_on(sv->ctx, f.nets.data(), (int32_t)f.nets.size(), &ok[0]->opt, s, &f.batch);
     const Clock::time_point tp3 = Clock::now();
-    if (st == PNE_OK) st = pne_batch_launch(f.batch);
+    std::lock_guard<std::mutex> lk(sv->mu);
     if (st != PNE_OK) {
-        std::lock_guard<std::mutex> lk(sv->mu);
         for (Request *r : ok) fail_request(sv, r, st);
         return false;
     }
-    f.t_launch = Clock::now();
-    std::lock_guard<std::mutex> lk(sv->mu);
-    sv->prep_s += seconds_since(tp0, f.t_launch);
+    sv->prep_s += seconds_since(tp0, tp3);
     sv->upload_s += seconds_since(tp0, tp1);
     sv->networks_s += seconds_since(tp1, tp2);
     sv->batch_s += seconds_since(tp2, tp3);
-    sv->launch_s += seconds_since(tp3, f.t_launch);
     return true;
+}
+
+// Launch: takes prepared batches in order and launches them; a launched
+// batch goes to the completion thread, a failed one to the graveyard.  At
+// most pipeline_depth (<= 2) batches are being launched or in flight, on the
+// server's two streams.
+void launcher_main(pne_server *sv) {
+    for (;;) {
+        InFlight f;
+        {
+            std::unique_lock<std::mutex> lk(sv->mu);
+            sv->cv_launch.wait(lk, [&] { return sv->stop_launch || !sv->to_launch.empty(); });
+            if (sv->to_launch.empty()) break;  // stop_launch
+            f = std::move(sv->to_launch.front());
+            sv->to_launch.pop_front();
+        }
+        const Clock::time_point tl0 = Clock::now();
+        const pne_status st = pne_batch_launch(f.batch);
+        const Clock::time_point tl1 = Clock::now();
+        {
+            std::lock_guard<std::mutex> lk(sv->mu);
+            sv->prep_s += seconds_since(tl0, tl1);
+            sv->launch_s += seconds_since(tl0, tl1);
+            --sv->launching;
+            if (st != PNE_OK) {
+                for (Request *r : f.reqs) fail_request(sv, r, st);
+                sv->graveyard.push_back(std::move(f));
+            } else {
+                f.t_launch = tl1;
+                if (sv->inflight.empty()) sv->busy_since = f.t_launch;
+                sv->inflight.push_back(std::move(f));
+                ++sv->batches;
+            }
+        }
+        sv->cv_done.notify_all();
+        sv->cv.notify_all();
+    }
 }
 
 // Admission and preparation: takes pending requests in arrival order while
 // their estimated bytes fit the budget and fewer than pipeline_depth
-// batches are in flight, prepares and launches them, and frees finished
-// batches whenever nothing is in flight.
+// batches are being launched or in flight, prepares them and hands them to
+// the launcher, and frees finished batches whenever nothing is being
+// launched or in flight.
 constexpr int kGraveyardMax = 8;
 
 void worker_main(pne_server *sv) {
@@ -297,14 +341,14 @@ void worker_main(pne_server *sv) {
             for (;;) {
                 // finished batches are freed while nothing is in flight (a free
                 // synchronises the device), or once kGraveyardMax pile up
+                auto idle = [&] { return sv->inflight.empty() && sv->launching == 0; };
                 auto release_now = [&] {
-                    return !sv->graveyard.empty() &&
-                           (sv->inflight.empty() || (int)sv->graveyard.size() >= kGraveyardMax);
+                    return !sv->graveyard.empty() && (idle() || (int)sv->graveyard.size() >= kGraveyardMax);
                 };
+                const auto active = [&] { return (int)sv->inflight.size() + sv->launching; };
                 sv->cv.wait(lk, [&] {
-                    return (!blocked && (int)sv->inflight.size() < depth && !sv->pending.empty()) ||
-                           release_now() || (sv->stop && sv->pending.empty() && sv->inflight.empty()) ||
-                           sv->finished_batches != seen;
+                    return (!blocked && active() < depth && !sv->pending.empty()) || release_now() ||
+                           (sv->stop && sv->pending.empty() && idle()) || sv->finished_batches != seen;
                 });
                 if (sv->finished_batches != seen) blocked = false;
                 seen = sv->finished_batches;
@@ -312,16 +356,15 @@ void worker_main(pne_server *sv) {
                     dead.swap(sv->graveyard);
                     break;
                 }
-                if (sv->stop && sv->pending.empty() && sv->inflight.empty()) break;
-                if ((int)sv->inflight.size() >= depth || sv->pending.empty()) continue;
+                if (sv->stop && sv->pending.empty() && idle()) break;
+                if (active() >= depth || sv->pending.empty()) continue;
                 const pne_options head = sv->pending.front()->opt;
                 size_t bytes = 0;
                 for (auto it = sv->pending.begin(); it != sv->pending.end() && (int)take.size() < sv->so.max_batch;) {
                     Request *r = *it;
                     const bool fits =
                         sv->so.mem_budget == 0 || sv->in_use + bytes + r->est_bytes <= sv->so.mem_budget;
-                    if (same_options(r->opt, head) &&
-                        (fits || (sv->inflight.empty() && take.empty() && sv->in_use == 0))) {
+                    if (same_options(r->opt, head) && (fits || (idle() && take.empty() && sv->in_use == 0))) {
                         take.push_back(r);
                         bytes += r->est_bytes;
                         it = sv->pending.erase(it);
@@ -345,18 +388,17 @@ void worker_main(pne_server *sv) {
         }
         InFlight f;
         hipStream_t s = sv->streams[launch_count % 2];
-        if (!prepare_and_launch(sv, take, s, f)) {
+        if (!prepare_batch(sv, take, s, f)) {
             release(sv, f);
             continue;
         }
         ++launch_count;
         {
             std::lock_guard<std::mutex> lk(sv->mu);
-            if (sv->inflight.empty()) sv->busy_since = f.t_launch;
-            sv->inflight.push_back(std::move(f));
-            ++sv->batches;
+            sv->to_launch.push_back(std::move(f));
+            ++sv->launching;
         }
-        sv->cv_done.notify_all();
+        sv->cv_launch.notify_all();
     }
     if (sv->up_stream) (void)hipStreamSynchronize(sv->up_stream);
     if (sv->staging) (void)hipHostFree(sv->staging);
@@ -445,6 +487,10 @@ pne_status pne_server_create(pne_ctx *ctx, const pne_server_options *opt, pne_se
         (void)hipSetDevice(dev);
         worker_main(p);
     });
+    p->launcher = std::thread([p, dev] {
+        (void)hipSetDevice(dev);
+        launcher_main(p);
+    });
     p->completer = std::thread([p, dev] {
         (void)hipSetDevice(dev);
         completer_main(p);
@@ -461,6 +507,12 @@ pne_status pne_server_destroy(pne_server *sv) {
     }
     sv->cv.notify_all();
     if (sv->worker.joinable()) sv->worker.join();  // every request finished, every batch freed
+    {
+        std::lock_guard<std::mutex> lk(sv->mu);
+        sv->stop_launch = true;
+    }
+    sv->cv_launch.notify_all();
+    if (sv->launcher.joinable()) sv->launcher.join();
     {
         std::lock_guard<std::mutex> lk(sv->mu);
         sv->stop_done = true;
