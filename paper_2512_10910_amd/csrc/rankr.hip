@@ -34,7 +34,8 @@ __device__ inline int tsize(int rank, int chi) {
 }
 
 // One-sided Jacobi SVD of the m x n matrix held column-major in a (column j
-// at a[j * m ..]), n <= 4, by one wave of 64 lanes.  On return the columns
+// at a[j * m ..]), n <= 4, by one wave of 64 lanes (at n = 4 two disjoint
+// column pairs rotate at once, one per half-wave).  On return the columns
 // are U S (orthogonal, norms s), V holds the accumulated rotations (n x n,
 // V[i * n + j]), and s the column norms; columns, s and V are sorted by
 // decreasing s.  Rotations stop when every pair is orthogonal to 1e-15
@@ -45,6 +46,50 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
         int rotated = 0;
+        if (n == 4) {
+            // the six pairs in three rounds of two disjoint pairs, one pair
+            // per half-wave: (0,1)(2,3), (0,2)(1,3), (0,3)(1,2)
+            const int half = lane >> 5, hl = lane & 31;
+            for (int round = 0; round < 3; ++round) {
+                const int p = half == 0 ? 0 : (round == 0 ? 2 : 1);
+                const int q = half == 0 ? round + 1 : (round == 2 ? 2 : 3);
+                double al = 0.0, be = 0.0, ga = 0.0;
+                for (int i = hl; i < m; i += 32) {
+                    const double x = a[p * m + i], y = a[q * m + i];
+                    al = fma(x, x, al);
+                    be = fma(y, y, be);
+                    ga = fma(x, y, ga);
+                }
+                for (int o = 16; o > 0; o >>= 1) {
+                    al += __shfl_xor(al, o, 64);
+                    be += __shfl_xor(be, o, 64);
+                    ga += __shfl_xor(ga, o, 64);
+                }
+                // the half's first lane's sums for all its lanes (see below)
+                al = __shfl(al, half << 5, 64);
+                be = __shfl(be, half << 5, 64);
+                ga = __shfl(ga, half << 5, 64);
+                if (!(fabs(ga) <= 1e-15 * sqrt(al * be) || ga == 0.0)) {
+                    rotated = 1;
+                    const double zeta = (be - al) / (2.0 * ga);
+                    const double t = (zeta >= 0.0 ? 1.0 : -1.0) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
+                    const double c = 1.0 / sqrt(1.0 + t * t), sn = c * t;
+                    for (int i = hl; i < m; i += 32) {
+                        const double x = a[p * m + i], y = a[q * m + i];
+                        a[p * m + i] = c * x - sn * y;
+                        a[q * m + i] = sn * x + c * y;
+                    }
+                    if (hl < n) {
+                        const double x = V[hl * n + p], y = V[hl * n + q];
+                        V[hl * n + p] = c * x - sn * y;
+                        V[hl * n + q] = sn * x + c * y;
+                    }
+                }
+                __syncthreads();
+            }
+            if (!__any(rotated)) break;
+            continue;
+        }
         for (int p = 0; p < n - 1; ++p)
             for (int q = p + 1; q < n; ++q) {
                 double al = 0.0, be = 0.0, ga = 0.0;
