@@ -240,6 +240,20 @@ def test_open_network_one_site_and_far_pair(ctx):
     _check_open(r, O.pne_contract(net, 8), 1e-10)
 
 
+def test_cluster_kernel_paths_against_oracle(ctx):
+    """The cluster kernel's paths against the oracle, launch by launch:
+    frontier plans whose open label has 16 values (the largest leg
+    dimension, the top of an entry table's 4-bit digit), and cycles of every
+    leg dimension 2-5 (bond dimensions 3-6)."""
+    net = P.random_2d(3, 3, 3, "uniform01", seed=36, open_sites={4: 16})
+    r, _, _ = _run(ctx, net, 6, persistent=False)
+    _check_open(r, O.pne_contract(net, 6), 1e-10)
+    for D in (3, 4, 5, 6):
+        net = P.random_2d(3, 3, D, "uniform01", seed=37 + D)
+        r, _, _ = _run(ctx, net, 8, persistent=False)
+        _check_closed(r, O.pne_contract(net, 8), 1e-10)
+
+
 def test_batch_results_equal_alone(ctx):
     nets_in = [P.random_2d(4, 4, 3, "uniform01", seed=40), P.random_3d(3, 2, "normal", seed=41),
                P.config1_network(), P.random_2d(6, 5, 2, "uniform01", seed=42)]
