@@ -1018,10 +1018,14 @@ void launch_fused_nt(const DeviceBatch &b, const FusedNet *fused, int n, size_t 
 }
 
 hipError_t launch_fused(const DeviceBatch &b, double tol, int max_iter, hipStream_t s) {
-    const int n_large = b.n_fused - b.n_fused_small;
+    const int n_large = b.n_fused - b.n_fused_small - b.n_fused_big;
     if (n_large > 0) launch_fused_nt<kPThreads>(b, b.fused, n_large, b.fused_lds, tol, max_iter, s);
     if (b.n_fused_small > 0)
         launch_fused_nt<kPSmallThreads>(b, b.fused + n_large, b.n_fused_small, b.fused_lds_small, tol, max_iter, s);
+    // networks whose LDS only the one-block-per-CU kernel has
+    if (b.n_fused_big > 0)
+        launch_fused_w<kPThreads, 2>(b, b.fused + n_large + b.n_fused_small, b.n_fused_big, b.fused_lds_big, tol,
+                                     max_iter, s);
     return hipGetLastError();
 }
 

@@ -20,9 +20,11 @@ struct DeviceBatch {
                                         // D = 5, 6; rank 6 at D = 3; wide_lds)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel: the large ones,
-    int n_fused = 0;                    // then the n_fused_small small ones (two-wave blocks)
-    int n_fused_small = 0;
+    int n_fused = 0;                    // then the n_fused_small small ones (two-wave blocks), then
+    int n_fused_small = 0;              // the n_fused_big ones whose LDS needs the 256-VGPR kernel
     size_t fused_lds_small = 0;
+    int n_fused_big = 0;
+    size_t fused_lds_big = 0;
     const FusedGroup *fgroups = nullptr;
     const int *fsite_list = nullptr;
     size_t fused_lds = 0;

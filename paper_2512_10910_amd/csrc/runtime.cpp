@@ -1122,6 +1122,10 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     // doubles of dynamic LDS per persistent block: two blocks per CU, or one
     // with the 256-VGPR kernel
     const size_t fused_budget = (opt->reg_budget ? 155 : 79) * 1024 / 8;
+    // networks over that budget but within the 256-VGPR kernel's run in it,
+    // one block per CU, in a launch of their own
+    const size_t big_budget = 155 * 1024 / 8;
+    std::vector<char> fused_big;  // per fused entry
     const int small_sites = opt->small_sites > 0 ? opt->small_sites : kPSmallSites;
     auto tiles_for = [&](int dim, int rank) {
         return (opt->tiles_in_flight > 0 && bp_persistent_tiles_tunable(dim, rank)) ? opt->tiles_in_flight
@@ -1214,13 +1218,20 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         // two-wave blocks of small networks)
         const bool small = g.n_sites <= small_sites;
         rg_scratch = std::max(rg_scratch, small ? 80 : 32);
-        if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2, small) <= fused_budget)
+        // the budget of the network's launch: the batch's, or the 256-VGPR
+        // kernel's for a large network that does not fit the batch's
+        size_t budget = fused_budget;
+        if (!small && fused_budget < big_budget &&
+            bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2, small) > fused_budget)
+            budget = big_budget;
+        if (rg_inline && bp_persistent_lds_doubles(msg_size, g.n_sites, rg_scratch, bip ? 1 : 2, small) <= budget)
             pscratch = rg_scratch;
         else
             rg_inline = false;
         const size_t pneed = bp_persistent_lds_doubles(msg_size, g.n_sites, pscratch, bip ? 1 : 2, small);
         // damped BP runs launch by launch (Jacobi, the damped mix in the per-launch normalisation)
-        if (all_reg && pneed <= fused_budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT) && opt->bp_damping == 0.0) {
+        if (all_reg && pneed <= budget && !(opt->flags & PNE_FLAG_NO_PERSISTENT) && opt->bp_damping == 0.0) {
+            fused_big.push_back(pneed > fused_budget ? 1 : 0);
             FusedNet f;
             std::memset(&f, 0, sizeof f);
             f.net = i;
@@ -1504,15 +1515,32 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         const int64_t light = sorted_work[sorted_work.size() / 4];  // lower quartile
         for (size_t k = 0; k < fused.size(); ++k) fused[k].prio = work[k] >= 2 * light ? 1 : 0;
     }
-    // large networks first, then the small ones (their own launch, 128-thread blocks)
-    std::stable_partition(fused.begin(), fused.end(),
-                          [small_sites](const FusedNet &f) { return f.n_sites > small_sites; });
-    size_t lds_large = 0, lds_small = 0;
-    int n_small = 0;
-    for (const FusedNet &f : fused) {
+    // large networks first, then the small ones (their own launch, 128-thread
+    // blocks), then the big ones (their own launch, the 256-VGPR kernel)
+    {
+        std::vector<int> order(fused.size());
+        for (size_t k = 0; k < fused.size(); ++k) order[k] = (int)k;
+        auto cls = [&](int k) { return fused_big[k] ? 2 : (fused[k].n_sites <= small_sites ? 1 : 0); };
+        std::stable_sort(order.begin(), order.end(), [&](int x, int y) { return cls(x) < cls(y); });
+        std::vector<FusedNet> sorted;
+        std::vector<char> big_sorted;
+        for (int k : order) {
+            sorted.push_back(fused[k]);
+            big_sorted.push_back(fused_big[k]);
+        }
+        fused.swap(sorted);
+        fused_big.swap(big_sorted);
+    }
+    size_t lds_large = 0, lds_small = 0, lds_big = 0;
+    int n_small = 0, n_big = 0;
+    for (size_t k = 0; k < fused.size(); ++k) {
+        const FusedNet &f = fused[k];
         const bool small = f.n_sites <= small_sites;
         const size_t need = bp_persistent_lds_doubles(f.msg_size, f.n_sites, f.scratch, f.colors == 2 ? 1 : 2, small) * 8;
-        if (small) {
+        if (fused_big[k]) {
+            lds_big = std::max(lds_big, need);
+            ++n_big;
+        } else if (small) {
             lds_small = std::max(lds_small, need);
             ++n_small;
         } else {
@@ -1649,6 +1677,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.fused_lds = lds_large;
     db.fused_lds_small = lds_small;
     db.n_fused_small = n_small;
+    db.fused_lds_big = lds_big;
+    db.n_fused_big = n_big;
     db.n_nets = n;
     db.n_cblocks = (int)cblocks.size();
     for (int k = 0; k <= kClKinds; ++k) db.cl_kind_begin[k] = cl_kind_begin[k];

@@ -254,6 +254,29 @@ def test_cluster_kernel_paths_against_oracle(ctx):
         _check_closed(r, O.pne_contract(net, 8), 1e-10)
 
 
+def test_large_networks_in_the_big_lds_persistent_launch(ctx):
+    """Closed networks whose persistent block needs more LDS than the
+    two-blocks-per-CU kernel has (24 x 24 at D = 4, 30 x 30 at D = 3) run
+    in the one-block-per-CU kernel's launch, batched with networks that fit
+    the ordinary launch; each agrees with the oracle and with the result it
+    gets alone."""
+    import paper_2512_10910_amd as pne
+
+    raws = [P.random_2d(24, 24, 4, "uniform01", seed=524), P.random_2d(8, 8, 4, "uniform01", seed=525),
+            P.random_2d(30, 30, 3, "uniform01", seed=530), P.random_2d(3, 3, 3, "uniform01", seed=531)]
+    nets = [ctx.network(x) for x in raws]
+    b = ctx.batch(nets, K=4)
+    paths = b.paths()
+    assert all(int(p) & pne.PATH_PERSISTENT for p in paths), paths
+    res = b.run()
+    for i, raw in enumerate(raws):
+        ref = O.pne_contract(raw, 4)
+        assert res[i].status == 0 and res[i].sign == ref.sign
+        assert abs(res[i].log_abs - ref.log_abs) <= 1e-12 * max(1.0, abs(ref.log_abs)), (i, res[i].log_abs, ref.log_abs)
+        alone = ctx.batch([nets[i]], K=4).run()[0]
+        assert alone.log_abs == res[i].log_abs and alone.sign == res[i].sign
+
+
 def test_batch_results_equal_alone(ctx):
     nets_in = [P.random_2d(4, 4, 3, "uniform01", seed=40), P.random_3d(3, 2, "normal", seed=41),
                P.config1_network(), P.random_2d(6, 5, 2, "uniform01", seed=42)]
