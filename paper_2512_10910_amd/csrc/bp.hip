@@ -10,6 +10,7 @@
 
 #include <cstdint>
 
+#include "dpp.h"
 #include "gmem.h"
 #include "kernels.h"
 
@@ -356,6 +357,20 @@ __device__ inline void tile_sync() {
     }
 }
 
+// Sum over trailing digit m2 of a register tile's lane field (B lane bits
+// per digit, the last digit in the lowest bits).
+template <int B, int T>
+__device__ inline double trailing_digit_sum(double v, int m2) {
+    if (m2 == T - 1) return dpp::bits_sum<0, B>(v);
+    if constexpr (T >= 2)
+        if (m2 == T - 2) return dpp::bits_sum<B, B>(v);
+    if constexpr (T >= 3)
+        if (m2 == T - 3) return dpp::bits_sum<2 * B, B>(v);
+#pragma unroll
+    for (int bit = 0; bit < B; ++bit) v += __shfl_xor(v, 1 << (B * (T - 1 - m2) + bit), 64);
+    return v;
+}
+
 // Processes one register-path tile.  Message offsets in the site table are
 // absolute; `min`/`mout` point at message storage for offset `msg_base`
 // (global buffers with msg_base = 0, or a network's LDS copy).  Returns the
@@ -451,8 +466,7 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
 #pragma unroll
             for (int m2 = 0; m2 < T; ++m2) {
                 if (m2 == m) continue;
-#pragma unroll
-                for (int bit = 0; bit < B; ++bit) pm += __shfl_xor(pm, 1 << (B * (T - 1 - m2) + bit), 64);
+                pm = trailing_digit_sum<B, T>(pm, m2);
             }
             bool owner = act[row];
 #pragma unroll
@@ -480,8 +494,12 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
                         sv = fma(tv[row][L], w, sv);
                     }
                     sv *= q;
+                    if constexpr (B * T == 6) {
+                        sv = dpp::wave_sum(sv);  // every lane bit: the row by DPP, then the rows
+                    } else {
 #pragma unroll
-                    for (int bit = 0; bit < B * T; ++bit) sv += __shfl_xor(sv, 1 << bit, 64);
+                        for (int bit = 0; bit < B * T; ++bit) sv += __shfl_xor(sv, 1 << bit, 64);
+                    }
                     if (tb == 0 && site < nsit) out[site * (R * D) + k * D + i] = sv;
                 }
             }

@@ -12,6 +12,7 @@
 #include <string>
 #include <vector>
 
+#include "dpp.h"
 #include "gmem.h"
 #include "pne.h"
 #include "rankr.h"
@@ -31,34 +32,6 @@ __device__ inline int tsize(int rank, int chi) {
     int n = 1;
     for (int l = 0; l < rank; ++l) n *= chi;
     return n;
-}
-
-// A lane's partner lane ^ MASK within its 16-lane row (MASK 15, 7, 3, 1:
-// row_mirror, row_half_mirror, quad_perm [3,2,1,0], quad_perm [1,0,3,2]),
-// read by data-parallel-primitive moves on the VALU.
-template <int MASK>
-__device__ inline double row_partner(double v) {
-    constexpr int ctrl = MASK == 15 ? 0x140 : (MASK == 7 ? 0x141 : (MASK == 3 ? 0x1B : 0xB1));
-    const int lo = __builtin_amdgcn_mov_dpp(__double2loint(v), ctrl, 0xF, 0xF, true);
-    const int hi = __builtin_amdgcn_mov_dpp(__double2hiint(v), ctrl, 0xF, 0xF, true);
-    return __hiloint2double(hi, lo);
-}
-
-// Sum over the lane's 16-lane row (a butterfly over the four lane bits).
-__device__ inline double row_sum(double v) {
-    v += row_partner<15>(v);
-    v += row_partner<7>(v);
-    v += row_partner<3>(v);
-    v += row_partner<1>(v);
-    return v;
-}
-
-// Sum over the wavefront: the row butterfly, then across the four rows.
-__device__ inline double wave_sum(double v) {
-    v = row_sum(v);
-    v += __shfl_xor(v, 16, 64);
-    v += __shfl_xor(v, 32, 64);
-    return v;
 }
 
 // One-sided Jacobi SVD of the m x n matrix held column-major in a (column j
@@ -90,9 +63,9 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
                 }
                 // a 16-lane row butterfly on the VALU (DPP), then across the
                 // half-wave's two rows
-                al = row_sum(al);
-                be = row_sum(be);
-                ga = row_sum(ga);
+                al = dpp::row_sum(al);
+                be = dpp::row_sum(be);
+                ga = dpp::row_sum(ga);
                 al += __shfl_xor(al, 16, 64);
                 be += __shfl_xor(be, 16, 64);
                 ga += __shfl_xor(ga, 16, 64);
@@ -130,9 +103,9 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
                     be = fma(y, y, be);
                     ga = fma(x, y, ga);
                 }
-                al = wave_sum(al);
-                be = wave_sum(be);
-                ga = wave_sum(ga);
+                al = dpp::wave_sum(al);
+                be = dpp::wave_sum(be);
+                ga = dpp::wave_sum(ga);
                 // one lane's sums for the whole wave: the butterfly's can differ
                 // in the last bit between lanes, enough to flip the rotation's
                 // sign on tied column norms
@@ -161,7 +134,7 @@ __device__ void jacobi_svd(double *a, int m, int n, double *V, double *s) {
     for (int j = 0; j < n; ++j) {
         double nn = 0.0;
         for (int i = lane; i < m; i += kRkWp) nn = fma(a[j * m + i], a[j * m + i], nn);
-        nn = wave_sum(nn);
+        nn = dpp::wave_sum(nn);
         if (lane == 0) s[j] = sqrt(nn);
     }
     __syncthreads();
