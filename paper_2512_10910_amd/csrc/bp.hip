@@ -575,16 +575,22 @@ __host__ __device__ constexpr int reg_sites_per_tile(int D, int R, int max_lead 
 __host__ __device__ constexpr bool wide_shape(int D, int R) {
     return (R == 4 && (D == 5 || D == 6)) || (R == 6 && D == 3);
 }
+// Rank-6 sites at D = 4 (the interior of 3D lattices, 4096 entries): three
+// legs index the 64 lanes and the other three 64 values per lane, one site
+// per wavefront, in a kernel instance of their own (its registers would hold
+// every other tile to one wavefront per SIMD).
+__host__ __device__ constexpr bool xwide_shape(int D, int R) { return R == 6 && D == 4; }
 
 // One Jacobi sweep: sweep reads message buffer sweep&1 and writes the other.
 // Tiles of networks that stopped exit at once; the per-network bookkeeping of
 // the previous sweep is folded into the stop test, so one launch is one sweep
 // and no block waits for, or fences against, any other block.
 //
-// WIDE: the kernel for register tiles of the wide shapes (wide_shape), kept
-// apart so that their registers do not lower the occupancy of every other
-// tile.
-template <bool WIDE>
+// WIDE: 0 the register and LDS tiles; 1 the register tiles of the wide
+// shapes (wide_shape), 2 those of the extra-wide shape (xwide_shape), each
+// kept apart so that their registers do not lower the occupancy of the
+// other tiles.
+template <int WIDE>
 __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restrict__ sites,
                                                          const BpTile *__restrict__ tiles,
                                                          const int *__restrict__ tile_sites,
@@ -605,14 +611,21 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
     if (s_skip) return;
     const double *min = (sweep & 1) ? msg1 : msg0;
     double *mout = (sweep & 1) ? msg0 : msg1;
-    if (WIDE) {
+    if constexpr (WIDE != 0) {
         if (threadIdx.x == 0) sh.bad = 0;
         double res = 0.0;
-        switch (tl.dc * 8 + tl.rank) {
-            case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            default: sh.bad = 1; break;  // not a wide shape: never scheduled here
+        if constexpr (WIDE == 2) {
+            if (tl.dc == 4 && tl.rank == 6)
+                res = sweep_reg<4, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp);
+            else
+                sh.bad = 1;  // not the extra-wide shape: never scheduled here
+        } else {
+            switch (tl.dc * 8 + tl.rank) {
+                case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                default: sh.bad = 1; break;  // not a wide shape: never scheduled here
+            }
         }
         if (threadIdx.x == 0) {
             atomicMax(&ns->res_acc[sweep % 3], (unsigned long long)__double_as_longlong(res));
@@ -687,8 +700,10 @@ int bp_tile_threads() { return kBpThreads; }
 
 int bp_reg_sites_per_tile(int D, int R) { return reg_sites_per_tile(D, R); }
 int bp_sweep_reg_sites_per_tile(int D, int R) {
+    if (xwide_shape(D, R)) return reg_sites_per_tile(D, R, 64);
     return wide_shape(D, R) ? reg_sites_per_tile(D, R, 36) : reg_sites_per_tile(D, R);
 }
+bool bp_sweep_xwide(int D, int R) { return xwide_shape(D, R); }
 
 size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int max_dim) {
     size_t red = (size_t)n_sites * (size_t)max_dim;
@@ -710,8 +725,9 @@ hipError_t launch_init(const DeviceBatch &b, hipStream_t s) {
 // has a side stream and wide tiles, the register and LDS tiles of the other
 // shapes run on the side stream, beside the wide launch.
 hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, hipStream_t s) {
-    const int n_wide = b.n_tiles - b.n_narrow_tiles;
-    const bool split = b.side != nullptr && n_wide > 0 && b.n_narrow_tiles > 0;
+    const int n_wide = b.n_wide_end - b.n_narrow_tiles;
+    const int n_xwide = b.n_tiles - b.n_wide_end;
+    const bool split = b.side != nullptr && n_wide + n_xwide > 0 && b.n_narrow_tiles > 0;
     hipError_t e = hipSuccess;
     hipStream_t ns = s;
     if (split) {
@@ -720,15 +736,19 @@ hipError_t launch_sweep(const DeviceBatch &b, int k, double tol, int max_iter, h
         ns = b.side;
     }
     if (b.n_reg_tiles > 0)
-        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, ns, b.sites, b.tiles,
+        hipLaunchKernelGGL(k_bp_sweep<0>, dim3(b.n_reg_tiles), dim3(kBpThreads), b.reg_lds, ns, b.sites, b.tiles,
                            b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter, b.bp_stall, b.bp_floor, b.damping);
     if (b.n_narrow_tiles > b.n_reg_tiles)
-        hipLaunchKernelGGL(k_bp_sweep<false>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, ns,
+        hipLaunchKernelGGL(k_bp_sweep<0>, dim3(b.n_narrow_tiles - b.n_reg_tiles), dim3(kBpThreads), b.bp_lds, ns,
                            b.sites, b.tiles + b.n_reg_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
                            b.bp_stall, b.bp_floor, b.damping);
     if (n_wide > 0)
-        hipLaunchKernelGGL(k_bp_sweep<true>, dim3(n_wide), dim3(kBpThreads), b.wide_lds, s, b.sites,
+        hipLaunchKernelGGL(k_bp_sweep<1>, dim3(n_wide), dim3(kBpThreads), b.wide_lds, s, b.sites,
                            b.tiles + b.n_narrow_tiles, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
+                           b.bp_stall, b.bp_floor, b.damping);
+    if (n_xwide > 0)
+        hipLaunchKernelGGL(k_bp_sweep<2>, dim3(n_xwide), dim3(kBpThreads), b.xwide_lds, s, b.sites,
+                           b.tiles + b.n_wide_end, b.tile_sites, b.msg0, b.msg1, b.state, k, tol, max_iter,
                            b.bp_stall, b.bp_floor, b.damping);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (split) {

@@ -15,9 +15,10 @@ struct DeviceBatch {
     const BpTile *tiles = nullptr;      // tiles swept by the per-sweep kernels
     int n_tiles = 0;
     int n_reg_tiles = 0;                // tiles[0, n_reg_tiles): register tiles (dynamic LDS reg_lds);
-    int n_narrow_tiles = 0;             // then up to n_narrow_tiles the LDS tiles (bp_lds); the
-                                        // rest: register tiles of the wide shapes (rank 4 at
-                                        // D = 5, 6; rank 6 at D = 3; wide_lds)
+    int n_narrow_tiles = 0;             // then up to n_narrow_tiles the LDS tiles (bp_lds); then up
+                                        // to n_wide_end register tiles of the wide shapes (rank 4 at
+                                        // D = 5, 6; rank 6 at D = 3; wide_lds); the rest: rank 6 at
+                                        // D = 4 (xwide_lds)
     const BpTile *all_tiles = nullptr;  // every tile (the fused kernel indexes it)
     const FusedNet *fused = nullptr;    // networks run by the persistent BP kernel: the large ones,
     int n_fused = 0;                    // then the n_fused_small small ones (two-wave blocks), then
@@ -38,6 +39,8 @@ struct DeviceBatch {
     size_t bp_lds = 0;             // dynamic LDS of the sweep kernel's LDS tiles
     size_t reg_lds = 0;            // ... of its register tiles (their raw outgoing messages)
     size_t wide_lds = 0;           // ... of the wide-shape register tiles
+    size_t xwide_lds = 0;          // ... of the extra-wide (rank 6, D = 4) register tiles
+    int n_wide_end = 0;            // tiles[n_wide_end, n_tiles): the extra-wide tiles
     // Where a sweep has wide tiles and others, the others (few, or short) run
     // on the context's side stream beside the wide launch: fork and join
     // events of the batch (null for a batch that must not create them).
@@ -112,6 +115,7 @@ int bp_reg_sites_per_tile(int D, int R);
 // sites per register tile of the per-launch sweep (0: LDS path); a superset
 // of the shapes bp_reg_sites_per_tile accepts
 int bp_sweep_reg_sites_per_tile(int D, int R);
+bool bp_sweep_xwide(int D, int R);
 size_t bp_tile_lds_doubles(int n_sites, int size, int n_os, int last_dim, int max_dim);
 
 hipError_t launch_init(const DeviceBatch &b, hipStream_t s);

@@ -1115,9 +1115,9 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     std::vector<int> fsite_list;
     // per-launch sweep tiles in three launches, each with its own dynamic LDS:
     // register tiles, LDS tiles, register tiles of the wide shapes
-    std::vector<BpTile> reg_tiles, lds_tiles, wide_tiles;
+    std::vector<BpTile> reg_tiles, lds_tiles, wide_tiles, xwide_tiles;
     std::vector<size_t> tile_need;  // dynamic LDS bytes of each entry of tiles
-    size_t reg_lds = 0, wide_lds = 0;
+    size_t reg_lds = 0, wide_lds = 0, xwide_lds = 0;
     const size_t bp_budget = 16 * 1024 / 8;  // doubles of dynamic LDS per tile (several waves per CU)
     // doubles of dynamic LDS per persistent block: two blocks per CU, or one
     // with the 256-VGPR kernel
@@ -1268,7 +1268,10 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
         } else {
             for (size_t t = tile_begin; t < tiles.size(); ++t) {
                 const BpTile &tt = tiles[t];
-                if (tt.reg && bp_reg_sites_per_tile(tt.dc, tt.rank) == 0) {
+                if (tt.reg && bp_sweep_xwide(tt.dc, tt.rank)) {
+                    xwide_tiles.push_back(tt);
+                    xwide_lds = std::max(xwide_lds, tile_need[t]);
+                } else if (tt.reg && bp_reg_sites_per_tile(tt.dc, tt.rank) == 0) {
                     wide_tiles.push_back(tt);
                     wide_lds = std::max(wide_lds, tile_need[t]);
                 } else if (tt.reg) {
@@ -1498,6 +1501,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     loop_tiles.insert(loop_tiles.end(), lds_tiles.begin(), lds_tiles.end());
     const int n_narrow = (int)loop_tiles.size();
     loop_tiles.insert(loop_tiles.end(), wide_tiles.begin(), wide_tiles.end());
+    const int n_wide_end = (int)loop_tiles.size();
+    loop_tiles.insert(loop_tiles.end(), xwide_tiles.begin(), xwide_tiles.end());
     UP(loop_tiles, tiles);
     UP(tiles, all_tiles);
     // Wave priority by work per BP step (tensor entries): where blocks of light
@@ -1673,6 +1678,8 @@ pne_status pne::batch_create_on(pne_ctx *ctx, pne_network *const *nets, int32_t 
     db.n_reg_tiles = n_reg;
     db.reg_lds = reg_lds;
     db.wide_lds = wide_lds;
+    db.xwide_lds = xwide_lds;
+    db.n_wide_end = n_wide_end;
     db.n_fused = (int)fused.size();
     db.fused_lds = lds_large;
     db.fused_lds_small = lds_small;
