@@ -209,8 +209,10 @@ __global__ void __launch_bounds__(64) k_regauge_tiles(const BpTile *__restrict__
 // lane (rank 3 at D = 5, 6; rank 5 at D = 3, 4), one site per wavefront.  The
 // persistent kernel keeps to at most 4 values per lane for its registers;
 // these kernels run alone, one per shape (80-110 VGPRs).  Rank 4 at D = 5, 6
-// and rank 6 at D = 3 (25-36 values per lane) would need every register of
-// the SIMD lane and still spill, so they stay on the per-site LDS kernel.
+// and rank 6 at D = 3 (25-36 values per lane) stay on the per-site LDS
+// kernel: in this form rank 4 at D = 6 takes 256 VGPRs and 186 AGPRs (one
+// wave per SIMD) and was slower than the LDS kernel on 32x32 D = 6 networks
+// (1.89 against 1.44 ms for 131k sites); capped at two waves it spills.
 template <int D, int R, typename S>
 __global__ void __launch_bounds__(64) k_regauge_wide(const BpTile *__restrict__ tiles, const int *__restrict__ rg_wide,
                                                      const SiteRec *__restrict__ sites,
