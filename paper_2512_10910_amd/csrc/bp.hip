@@ -73,37 +73,37 @@ __global__ void k_init(const SiteRec *__restrict__ sites, const int *__restrict_
 // at most `floor_tol`.
 __device__ bool network_stopped(NetState *ns, int k, double tol, int max_iter, int stall, double floor_tol,
                                 bool writer) {
-    if (ns->stop >= 0) return true;
-    if (k == 0) return false;
-    const double r = __longlong_as_double((long long)ns->res_acc[(k - 1) % 3]);
+    // every input is loaded, and every test evaluated, before the first
+    // branch, so the loads share one round trip to memory; (k + 2) % 3 is
+    // sweep k-1's residual slot, and an unused in-bounds slot at k = 0
+    const int stop = ns->stop;
+    const double r = __longlong_as_double((long long)ns->res_acc[(k + 2) % 3]);
     const int status = ns->status;
+    const double best_in = ns->best[k & 1];
+    const int best_at_in = ns->best_at[k & 1];
     const bool conv = status >= 0 && r <= tol;
-    double best = ns->best[k & 1];
-    int best_at = ns->best_at[k & 1];
-    bool floor = false;
-    if (!conv) {
-        if (r < best) {
-            best = r;
-            best_at = k - 1;
-        } else {
-            floor = status >= 0 && stall > 0 && best <= floor_tol && (k - 1) - best_at >= stall;
-        }
-    }
-    if (status < 0 || conv || floor || k >= max_iter) {
-        if (writer) {
+    const bool better = !conv && r < best_in;
+    const double best = better ? r : best_in;
+    const int best_at = better ? k - 1 : best_at_in;
+    const bool floor = !conv && !better && status >= 0 && stall > 0 && best_in <= floor_tol &&
+                       (k - 1) - best_at_in >= stall;
+    // the exits are combined without branches, so that no load is sunk
+    // behind the first test
+    const bool running = (stop < 0) & (k != 0);
+    const bool end = (status < 0) | conv | floor | (k >= max_iter);
+    if (writer & running) {
+        if (end) {
             ns->stop = k - 1;
             ns->iters = k;
             ns->parity = k & 1;
             ns->residual = r;
             ns->converged = (conv || floor) ? 1 : 0;
+        } else {
+            ns->best[(k - 1) & 1] = best;
+            ns->best_at[(k - 1) & 1] = best_at;
         }
-        return true;
     }
-    if (writer) {
-        ns->best[(k - 1) & 1] = best;
-        ns->best_at[(k - 1) & 1] = best_at;
-    }
-    return false;
+    return (stop >= 0) | (running & end);
 }
 
 // One tile of one sweep.  DC > 0: every leg has dimension DC (constant index
@@ -377,8 +377,8 @@ __device__ inline double trailing_digit_sum(double v, int m2) {
 // tile's residual (valid in every lane); sets *bad on a zero message.
 template <int D, int R, bool WAVE, class SH, int ROWS = 0>
 __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites, const int *__restrict__ tile_sites,
-                            const double *min, double *mout, int msg_base, double *lds, SH &sh, int *bad,
-                            double damp) {
+                            int my_site, const double *min, double *mout, int msg_base, double *lds, SH &sh,
+                            int *bad, double damp) {
     constexpr int P = RegShape<D>::P;
     constexpr int B = RegShape<D>::B;
     constexpr int T = reg_trailing(D, R);
@@ -391,7 +391,7 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
     const int lane = threadIdx.x & 63;
     const int nsit = tl.n_sites;
     for (int j = lane; j < nsit; j += kBpThreads) {
-        const SiteRec &r = sites[tile_sites[tl.site_begin + j]];
+        const SiteRec &r = sites[j == lane ? my_site : tile_sites[tl.site_begin + j]];
         sh.t[j] = r.t;
         sh.msg[j] = r.msg_off - msg_base;
 #pragma unroll
@@ -602,6 +602,9 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
     extern __shared__ double lds[];
     __shared__ int s_skip;
     __shared__ TileShared sh;
+    // this lane's site of a register tile (clamped in bounds), loaded beside
+    // the stop test's inputs rather than after them
+    const int my_site = tile_sites[tl.site_begin + min((int)threadIdx.x, tl.n_sites - 1)];
     if (threadIdx.x == 0) {
         s_skip = network_stopped(ns, sweep, tol, max_iter, stall, floor_tol, tl.first != 0);
         // slot (sweep+1)%3 was last read at the start of sweep-1: clear it for sweep+1
@@ -616,14 +619,14 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
         double res = 0.0;
         if constexpr (WIDE == 2) {
             if (tl.dc == 4 && tl.rank == 6)
-                res = sweep_reg<4, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp);
+                res = sweep_reg<4, 6, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp);
             else
                 sh.bad = 1;  // not the extra-wide shape: never scheduled here
         } else {
             switch (tl.dc * 8 + tl.rank) {
-                case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-                case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-                case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                case 30: res = sweep_reg<3, 6, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                case 44: res = sweep_reg<5, 4, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+                case 52: res = sweep_reg<6, 4, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
                 default: sh.bad = 1; break;  // not a wide shape: never scheduled here
             }
         }
@@ -637,28 +640,28 @@ __global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restri
         double res = -1.0;
         if (threadIdx.x == 0) sh.bad = 0;
         switch (tl.dc * 8 + tl.rank) {
-            case 17: res = sweep_reg<2, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 18: res = sweep_reg<2, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 19: res = sweep_reg<2, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 20: res = sweep_reg<2, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 21: res = sweep_reg<2, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 22: res = sweep_reg<2, 6, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 25: res = sweep_reg<3, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 26: res = sweep_reg<3, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 27: res = sweep_reg<3, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 28: res = sweep_reg<3, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 29: res = sweep_reg<3, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 33: res = sweep_reg<4, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 34: res = sweep_reg<4, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 35: res = sweep_reg<4, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 36: res = sweep_reg<4, 4, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 37: res = sweep_reg<4, 5, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 41: res = sweep_reg<5, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 42: res = sweep_reg<5, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 43: res = sweep_reg<5, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 49: res = sweep_reg<6, 1, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 50: res = sweep_reg<6, 2, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
-            case 51: res = sweep_reg<6, 3, false>(tl, sites, tile_sites, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 17: res = sweep_reg<2, 1, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 18: res = sweep_reg<2, 2, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 19: res = sweep_reg<2, 3, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 20: res = sweep_reg<2, 4, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 21: res = sweep_reg<2, 5, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 22: res = sweep_reg<2, 6, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 25: res = sweep_reg<3, 1, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 26: res = sweep_reg<3, 2, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 27: res = sweep_reg<3, 3, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 28: res = sweep_reg<3, 4, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 29: res = sweep_reg<3, 5, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 33: res = sweep_reg<4, 1, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 34: res = sweep_reg<4, 2, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 35: res = sweep_reg<4, 3, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 36: res = sweep_reg<4, 4, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 37: res = sweep_reg<4, 5, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 41: res = sweep_reg<5, 1, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 42: res = sweep_reg<5, 2, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 43: res = sweep_reg<5, 3, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 49: res = sweep_reg<6, 1, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 50: res = sweep_reg<6, 2, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
+            case 51: res = sweep_reg<6, 3, false>(tl, sites, tile_sites, my_site, min, mout, 0, lds, sh, &sh.bad, damp); break;
             default: break;
         }
         if (res >= 0.0) {
