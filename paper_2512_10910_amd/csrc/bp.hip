@@ -447,15 +447,22 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
 #pragma unroll
     for (int row = 0; row < NS; ++row) {
         const int site = row * SPW + slot;
-        // lead-contracted value
-        double A = 0.0;
+        // lead-contracted value (more than 16 values per lane: four
+        // interleaved partial sums, so the FMA chain is a quarter as long)
+        constexpr int NA = NL > 16 ? 4 : 1;
+        double Ap[NA];
+#pragma unroll
+        for (int a = 0; a < NA; ++a) Ap[a] = 0.0;
 #pragma unroll
         for (int L = 0; L < NL; ++L) {
             double w = 1.0;
 #pragma unroll
             for (int k = 0; k < NLEG; ++k) w *= ml[row][k][(L / ipow(D, NLEG - 1 - k)) % D];
-            A = fma(tv[row][L], w, A);
+            Ap[L % NA] = fma(tv[row][L], w, Ap[L % NA]);
         }
+        double A = Ap[0];
+#pragma unroll
+        for (int a = 1; a < NA; ++a) A += Ap[a];
         // trailing legs
 #pragma unroll
         for (int m = 0; m < T; ++m) {
@@ -475,7 +482,33 @@ __device__ double sweep_reg(const BpTile &tl, const SiteRec *__restrict__ sites,
             if (owner) out[site * (R * D) + (NLEG + m) * D + dig[m]] = pm;
         }
         // lead legs
-        if (NLEG > 0) {
+        if constexpr (NLEG > 0 && B * T == 6 && NLEG * D <= 16 && NL <= 36) {
+            // one site per wavefront: the NLEG * D sums over all 64 lanes
+            // at once, by recursive halving (lane i of the first row ends
+            // with output i = k * D + j of lead leg k)
+            double q = act[row] ? 1.0 : 0.0;
+#pragma unroll
+            for (int m = 0; m < T; ++m) q *= mt[row][m];
+            auto lead = [&](int o) {
+                const int k = o / D, i = o % D;
+                double acc = 0.0;
+#pragma unroll
+                for (int L = 0; L < NL; ++L) {
+                    if ((L / ipow(D, NLEG - 1 - k)) % D != i) continue;
+                    double w = 1.0;
+#pragma unroll
+                    for (int k2 = 0; k2 < NLEG; ++k2)
+                        if (k2 != k) w *= ml[row][k2][(L / ipow(D, NLEG - 1 - k2)) % D];
+                    acc = fma(tv[row][L], w, acc);
+                }
+                return acc * q;
+            };
+            double sv[NLEG * D];
+#pragma unroll
+            for (int o = 0; o < NLEG * D; ++o) sv[o] = lead(o);
+            const double tot = dpp::wave_sums16<NLEG * D>(sv, lane);
+            if (lane < NLEG * D && site < nsit) out[site * (R * D) + lane] = tot;
+        } else if (NLEG > 0) {
             double q = act[row] ? 1.0 : 0.0;
 #pragma unroll
             for (int m = 0; m < T; ++m) q *= mt[row][m];
@@ -591,7 +624,8 @@ __host__ __device__ constexpr bool xwide_shape(int D, int R) { return R == 6 && 
 // kept apart so that their registers do not lower the occupancy of the
 // other tiles.
 template <int WIDE>
-__global__ void __launch_bounds__(kBpThreads) k_bp_sweep(const SiteRec *__restrict__ sites,
+__global__ void __launch_bounds__(kBpThreads) __attribute__((amdgpu_waves_per_eu(WIDE == 1 ? 4 : 1)))
+k_bp_sweep(const SiteRec *__restrict__ sites,
                                                          const BpTile *__restrict__ tiles,
                                                          const int *__restrict__ tile_sites,
                                                          double *msg0, double *msg1, NetState *st, int sweep,

@@ -69,6 +69,36 @@ __device__ inline double row_sum(double v) {
     return v;
 }
 
+// Pair stage of a recursive halving over one lane bit: the lane keeps value
+// `lo` or `hi` as its bit is 0 or 1 and adds the partner's copy of it; the
+// partner (opposite bit, same index set) receives the other one.
+template <int MASK>
+__device__ inline double halve(double lo, double hi, bool bit) {
+    const double keep = bit ? hi : lo;
+    return keep + row_partner<MASK>(bit ? lo : hi);
+}
+
+// Joint sums of N <= 16 values per lane over the wavefront by recursive
+// halving inside each row (lane bits 3, 2, 1, 0 with the partners lane ^ 15,
+// ^ 7, ^ 3, ^ 1, each of which keeps the higher bits), then across the four
+// rows.  Lane l ends with the wavefront's sum of value l & 15 (0 where
+// l & 15 >= N): 15 DPP moves and two shuffles in place of N wave_sum calls.
+template <int N>
+__device__ inline double wave_sums16(const double (&v)[N], int lane) {
+    static_assert(N >= 1 && N <= 16, "at most 16 values");
+    double a[8], b[4], c[2];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) a[j] = j < N ? halve<15>(v[j], j + 8 < N ? v[j + 8] : 0.0, lane & 8) : 0.0;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) b[j] = j < N ? halve<7>(a[j], a[j + 4], lane & 4) : 0.0;
+#pragma unroll
+    for (int j = 0; j < 2; ++j) c[j] = j < N ? halve<3>(b[j], b[j + 2], lane & 2) : 0.0;
+    double d = halve<1>(c[0], c[1], lane & 1);
+    d += __shfl_xor(d, 16, 64);
+    d += __shfl_xor(d, 32, 64);
+    return d;
+}
+
 // Sum over the wavefront: the row butterfly, then across the four rows.
 __device__ inline double wave_sum(double v) {
     v = row_sum(v);
