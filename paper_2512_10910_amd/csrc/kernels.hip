@@ -58,8 +58,35 @@ __device__ inline void mode_product_fibers(const double *b0, double *b1, const d
     }
 }
 
+// One column k of a slot transform X (d x d, row-major) for a leg of
+// dimension DD: the two messages are read into registers with every load in
+// flight at once, then the gauge is built from them (the same arithmetic as
+// the loop over a runtime dimension, which waits on each message load in
+// turn).
+template <int DD>
+__device__ inline void slot_column(const double *pa, const double *pc, bool vs, int k, double *X, int *status) {
+    double a[DD], c[DD];
+#pragma unroll
+    for (int i = 0; i < DD; ++i) {
+        a[i] = pa[i];
+        c[i] = pc[i];
+    }
+    const LegGauge g = leg_gauge_setup(a, c, DD);
+    if (k == 0 && !g.ok) atomicMin(status, -4);
+    double ak = a[0], ck = c[0];
+#pragma unroll
+    for (int i = 1; i < DD; ++i)
+        if (k == i) {
+            ak = a[i];
+            ck = c[i];
+        }
+#pragma unroll
+    for (int i = 0; i < DD; ++i) X[i * DD + k] = leg_gauge_x(g, vs, i, k, a[i], c[i], ak, ck);
+}
+
 template <typename S>
-__global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restrict__ sites,
+__global__ void __launch_bounds__(kRgThreads)
+k_regauge(const SiteRec *__restrict__ sites,
                                                         const int *__restrict__ rg_sites,
                                                         const double *msg0, const double *msg1,
                                                         S *__restrict__ slices,
@@ -92,24 +119,49 @@ __global__ void __launch_bounds__(kRgThreads) k_regauge(const SiteRec *__restric
     double *b0 = lds;
     double *b1 = lds + (nbuf - 1) * size;
     double *xt = lds + nbuf * size;  // the slot transforms, d_l x d_l each (regauge_site_lds_doubles)
-    for (int e = tid; e < size; e += kRgThreads) b0[e] = gld(r.t + e);
-    __syncthreads();  // xoff
-    // every slot's transform at once (one column per thread), so the message
-    // reads of all slots are in flight together with the tensor's
     const double *mb = st[r.net].parity ? msg1 : msg0;
+    // the tensor's first 12 * kRgThreads entries go to registers first (one
+    // load round for sites of up to 1536 entries) ...
+    double tv[12];
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+        const int e = tid + u * kRgThreads;
+        tv[u] = e < size ? gld(r.t + e) : 0.0;
+    }
+    // ... while every slot's transform is built (one column per thread), so
+    // the message loads are in flight together with the tensor's
     for (int it = tid; it < r.rank * kMaxDim; it += kRgThreads) {
         const int l = it / kMaxDim, k = it - l * kMaxDim;
         const int d = r.dim[l];
         if (k >= d || ((r.open_mask >> l) & 1)) continue;
+        int xo = 0;  // this slot's transform offset (thread 0 tabulates them for later)
+        for (int l2 = 0; l2 < l; ++l2)
+            if (!((r.open_mask >> l2) & 1)) xo += r.dim[l2] * r.dim[l2];
         const bool vs = (r.vside_mask >> l) & 1;
         const double *pin = mb + r.msg_off + r.moff[l];
         const double *pout = mb + r.dst[l];
         const double *pa = vs ? pout : pin;
         const double *pc = vs ? pin : pout;
-        const LegGauge g = leg_gauge_setup(pa, pc, d);
-        if (k == 0 && !g.ok) atomicMin(&st[r.net].status, -4);
-        for (int i = 0; i < d; ++i) xt[xoff[l] + i * d + k] = leg_gauge_x(g, vs, i, k, pa[i], pc[i], pa[k], pc[k]);
+        double *X = xt + xo;
+        switch (d) {
+            case 2: slot_column<2>(pa, pc, vs, k, X, &st[r.net].status); break;
+            case 3: slot_column<3>(pa, pc, vs, k, X, &st[r.net].status); break;
+            case 4: slot_column<4>(pa, pc, vs, k, X, &st[r.net].status); break;
+            case 5: slot_column<5>(pa, pc, vs, k, X, &st[r.net].status); break;
+            case 6: slot_column<6>(pa, pc, vs, k, X, &st[r.net].status); break;
+            default: {
+                const LegGauge g = leg_gauge_setup(pa, pc, d);
+                if (k == 0 && !g.ok) atomicMin(&st[r.net].status, -4);
+                for (int i = 0; i < d; ++i) X[i * d + k] = leg_gauge_x(g, vs, i, k, pa[i], pc[i], pa[k], pc[k]);
+            }
+        }
     }
+#pragma unroll
+    for (int u = 0; u < 12; ++u) {
+        const int e = tid + u * kRgThreads;
+        if (e < size) b0[e] = tv[u];
+    }
+    for (int e = tid + 12 * kRgThreads; e < size; e += kRgThreads) b0[e] = gld(r.t + e);
     __syncthreads();
     for (int l = 0; l < r.rank; ++l) {
         const int d = r.dim[l];
