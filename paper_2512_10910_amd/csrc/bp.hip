@@ -166,9 +166,21 @@ __device__ void sweep_tile(const BpTile &tl, const SiteRec *__restrict__ sites, 
     double *red = nxt + nsit * rows0;  // reduction partials          >= 64
     const float inv_size = 1.0f / (float)size;
     const float inv_nos = 1.0f / (float)nos;
-    for (int e = tid; e < nsit * size; e += kBpThreads) {
-        const int j = fdiv(e, inv_size);
-        part[e] = dev::gld(s_t[j] + (e - j * size));
+    // the tiles' tensors, eight loads per lane in flight at a time
+    for (int e0 = tid; e0 < nsit * size; e0 += 8 * kBpThreads) {
+        double v[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int eu = e0 + u * kBpThreads;
+            const int e = eu < nsit * size ? eu : nsit * size - 1;  // clamped in bounds
+            const int j = fdiv(e, inv_size);
+            v[u] = dev::gld(s_t[j] + (e - j * size));
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const int e = e0 + u * kBpThreads;
+            if (e < nsit * size) part[e] = v[u];
+        }
     }
     for (int e = tid; e < nsit * nos; e += kBpThreads) {
         const int j = fdiv(e, inv_nos);
